@@ -1,0 +1,115 @@
+"""Dense-matrix evaluation of the multilevel approximation (test infrastructure).
+
+The paper (Section 3) approximates the reciprocal distance by nested grid
+interpolation,
+
+    1/r  ~  g* + I^0(g^0 + I^1(g^1 + ... + I^{l-2}(g^{l-2} + I^{l-1} g^{l-1})...)),
+
+with I^k g(r_i, r_j) = sum_mu sum_nu phi^k_mu(r_i) g(r^k_mu, r^k_nu) phi^k_nu(r_j).
+This module writes that formula out as explicit matrices on tiny inputs:
+Phi0[i, mu] = phi^0_mu(r_i), R_k[mu, nu] = phi^{k+1}_mu(r^k_nu) and
+G_k[mu, nu] = g^k(r^k_mu, r^k_nu), so that the long-range potential is
+Phi0 (G_0 + R_0^T (G_1 + R_1^T (...) R_1) R_0) Phi0^T q. The grids are padded
+well beyond the nodes any atom can reach, so agreement with the fast oracle
+also shows that its truncated grids lose no term.
+
+It is NumPy only and shares no code with the C oracle; its smoothing function
+and basis are written in the expanded polynomial form rather than the
+Hermite-basis form the C file uses.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def gamma(rho):
+    rho = np.asarray(rho, dtype=np.float64)
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        inner = 1.875 - 1.25 * rho ** 2 + 0.375 * rho ** 4
+        outer = 1.0 / rho
+    return np.where(rho >= 1.0, outer, inner)
+
+
+def Phi(t):
+    s = np.abs(np.asarray(t, dtype=np.float64))
+    near = (1.0 - s) * (1.0 + s - 1.5 * s * s)
+    far = -0.5 * (s - 1.0) * (2.0 - s) ** 2
+    return np.where(s <= 1.0, near, np.where(s < 2.0, far, 0.0))
+
+
+def g_level(r, a, k, l):
+    ak = a * 2.0 ** k
+    if k == l - 1:
+        return gamma(r / ak) / ak
+    return gamma(r / ak) / ak - gamma(r / (2 * ak)) / (2 * ak)
+
+
+def g_star(r, a):
+    with np.errstate(divide="ignore"):
+        return np.where(r < a, 1.0 / r - gamma(r / a) / a, 0.0)
+
+
+def _nodes(lo, h, k, lo_idx, hi_idx):
+    """Positions of the level-k nodes with integer indices in [lo_idx, hi_idx] per axis."""
+    axes = [lo[d] + (2.0 ** k) * h * np.arange(lo_idx[d], hi_idx[d] + 1) for d in range(3)]
+    zz, yy, xx = np.meshgrid(axes[2], axes[1], axes[0], indexing="ij")
+    return np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
+
+
+def _basis(points, nodes, spacing):
+    """Matrix B[p, mu] = prod_d Phi((x_p,d - x_mu,d) / spacing)."""
+    w = np.ones((points.shape[0], nodes.shape[0]))
+    for d in range(3):
+        w *= Phi((points[:, d][:, None] - nodes[:, d][None, :]) / spacing)
+    return w
+
+
+def _pair_dist(x):
+    diff = x[:, None, :] - x[None, :, :]
+    return np.sqrt((diff ** 2).sum(axis=-1))
+
+
+def long_range_matrix(xyz, a, h, lo, hi, levels, pad=2):
+    """The N x N matrix of the nested grid approximation of g_a = g^0 + ... + g^{l-1}."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    lo = np.asarray(lo, dtype=np.float64)
+    hi = np.asarray(hi, dtype=np.float64)
+    n_lo = np.full(3, -2 - pad)
+    n_hi = np.floor((hi - lo) / h).astype(int) + 3 + pad
+    ranges = []
+    for k in range(levels):
+        ranges.append((n_lo.copy(), n_hi.copy()))
+        n_lo = np.floor((n_lo - 3) / 2.0).astype(int) - pad
+        n_hi = np.ceil((n_hi + 3) / 2.0).astype(int) + pad
+    nodes = [_nodes(lo, h, k, *ranges[k]) for k in range(levels)]
+    Gs = [g_level(_pair_dist(nodes[k]), a, k, levels) for k in range(levels)]
+    K = Gs[levels - 1]
+    for k in range(levels - 2, -1, -1):
+        R = _basis(nodes[k], nodes[k + 1], (2.0 ** (k + 1)) * h).T   # R[mu_coarse, nu_fine]
+        K = Gs[k] + R.T @ K @ R
+    P0 = _basis(xyz, nodes[0], h)
+    return P0 @ K @ P0.T
+
+
+def energy_potential(xyz, q, a, h, lo, hi, levels, ke=1.0, pad=2):
+    """Energy and per-atom potentials of the multilevel approximation, dense."""
+    xyz = np.asarray(xyz, dtype=np.float64)
+    q = np.asarray(q, dtype=np.float64)
+    M = long_range_matrix(xyz, a, h, lo, hi, levels, pad)
+    r = _pair_dist(xyz)
+    np.fill_diagonal(r, np.inf)
+    S = g_star(r, a)
+    np.fill_diagonal(S, 0.0)
+    u_short = S @ q
+    u_long = M @ q
+    phi = ke * (u_short + u_long - q * float(gamma(0.0)) / a)
+    return 0.5 * float(q @ phi), phi, u_short, u_long
+
+
+def literal_pair_sum(ri, rj, a, h, lo, hi, levels, pad=2):
+    """The nested approximation of 1/|ri - rj| for one pair, as a single number."""
+    M = long_range_matrix(np.stack([ri, rj]), a, h, lo, hi, levels, pad)
+    r = math.dist(ri, rj)
+    return float(g_star(np.array(r), a)) + M[0, 1]

@@ -1,0 +1,168 @@
+"""ctypes bindings of the C oracle (test infrastructure only)."""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import threading
+
+import numpy as np
+
+from . import build as _build
+
+MAXLEV = 16
+_lock = threading.Lock()
+_lib = None
+
+_dp = C.POINTER(C.c_double)
+
+
+class _Params(C.Structure):
+    _fields_ = [("a", C.c_double), ("h", C.c_double), ("levels", C.c_int),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("ke", C.c_double)]
+
+
+class _Stages(C.Structure):
+    _fields_ = [("u_short", _dp), ("f_short", _dp),
+                ("q_grid", _dp * MAXLEV), ("ucut_grid", _dp * MAXLEV), ("u_grid", _dp * MAXLEV),
+                ("u_long", _dp), ("g_long", _dp)]
+
+
+@dataclasses.dataclass
+class OracleParams:
+    a: float
+    h: float
+    lo: tuple
+    hi: tuple
+    levels: int = 0
+    ke: float = 138.935458
+
+    def c(self) -> _Params:
+        p = _Params()
+        p.a, p.h, p.levels, p.ke = float(self.a), float(self.h), int(self.levels), float(self.ke)
+        for d in range(3):
+            p.lo[d] = float(self.lo[d])
+            p.hi[d] = float(self.hi[d])
+        return p
+
+    @classmethod
+    def of(cls, w, ke: float = 138.935458) -> "OracleParams":
+        return cls(w.a, w.h, tuple(w.lo), tuple(w.hi), w.levels, ke)
+
+
+def lib():
+    global _lib
+    with _lock:
+        if _lib is None:
+            path = _build.compile_oracle(force=False)
+            L = C.CDLL(path)
+            for name in ("orc_gamma", "orc_dgamma", "orc_Phi", "orc_dPhi"):
+                getattr(L, name).restype = C.c_double
+                getattr(L, name).argtypes = [C.c_double]
+            L.orc_gstar.restype = C.c_double
+            L.orc_gstar.argtypes = [C.c_double, C.c_double]
+            L.orc_glevel.restype = C.c_double
+            L.orc_glevel.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int]
+            L.orc_levels.restype = C.c_int
+            L.orc_levels.argtypes = [C.POINTER(_Params)]
+            L.orc_grid_shape.restype = C.c_int
+            L.orc_grid_shape.argtypes = [C.POINTER(_Params), C.c_int, C.c_int * 3, C.c_int * 3]
+            L.orc_msm.restype = C.c_int
+            L.orc_msm.argtypes = [C.POINTER(_Params), C.c_int64, _dp, _dp, _dp, _dp, _dp,
+                                  C.POINTER(_Stages)]
+            L.orc_coulomb.restype = C.c_int
+            L.orc_coulomb.argtypes = [C.c_int64, _dp, _dp, C.c_double, _dp, _dp, _dp]
+            _lib = L
+        return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(_dp)
+
+
+def _vec(f):
+    def g(x):
+        if np.isscalar(x):
+            return f(float(x))
+        return np.array([f(float(v)) for v in np.ravel(x)]).reshape(np.shape(x))
+    return g
+
+
+gamma = _vec(lambda x: lib().orc_gamma(x))
+dgamma = _vec(lambda x: lib().orc_dgamma(x))
+Phi = _vec(lambda x: lib().orc_Phi(x))
+dPhi = _vec(lambda x: lib().orc_dPhi(x))
+
+
+def gstar(r, a):
+    return _vec(lambda x: lib().orc_gstar(x, float(a)))(r)
+
+
+def glevel(r, a, k, l):
+    return _vec(lambda x: lib().orc_glevel(x, float(a), int(k), int(l)))(r)
+
+
+def levels(p: OracleParams) -> int:
+    cp = p.c()
+    return lib().orc_levels(C.byref(cp))
+
+
+def grid_shape(p: OracleParams, level: int):
+    cp = p.c()
+    org = (C.c_int * 3)()
+    dim = (C.c_int * 3)()
+    if lib().orc_grid_shape(C.byref(cp), level, org, dim) != 0:
+        raise ValueError("bad level")
+    return tuple(org), tuple(dim)
+
+
+def msm(p: OracleParams, xyz, q, stages: bool = False):
+    """Energy, forces (n,3) and potentials (n,) of the MSM approximation; with
+    ``stages`` also a dict of the intermediate results of every step."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+    n = xyz.shape[0]
+    e = np.zeros(1)
+    f = np.zeros((n, 3))
+    pot = np.zeros(n)
+    cp = p.c()
+    st = None
+    out = {}
+    if stages:
+        l = levels(p)
+        st = _Stages()
+        out["u_short"] = np.zeros(n)
+        out["f_short"] = np.zeros((n, 3))
+        out["u_long"] = np.zeros(n)
+        out["g_long"] = np.zeros((n, 3))
+        st.u_short, st.f_short = _ptr(out["u_short"]), _ptr(out["f_short"])
+        st.u_long, st.g_long = _ptr(out["u_long"]), _ptr(out["g_long"])
+        for key in ("q_grid", "ucut_grid", "u_grid"):
+            out[key] = []
+        for k in range(l):
+            _, dim = grid_shape(p, k)
+            shape = (dim[2], dim[1], dim[0])
+            for key in ("q_grid", "ucut_grid", "u_grid"):
+                arr = np.zeros(shape)
+                out[key].append(arr)
+                getattr(st, key)[k] = _ptr(arr)
+    rc = lib().orc_msm(C.byref(cp), n, _ptr(xyz), _ptr(q), _ptr(e), _ptr(f), _ptr(pot),
+                       C.byref(st) if st is not None else None)
+    if rc != 0:
+        raise RuntimeError(f"oracle msm failed with code {rc}")
+    if stages:
+        return float(e[0]), f, pot, out
+    return float(e[0]), f, pot
+
+
+def coulomb(xyz, q, ke: float = 138.935458):
+    """Exact Coulomb energy, forces and potentials by the direct pair sum."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+    n = xyz.shape[0]
+    e = np.zeros(1)
+    f = np.zeros((n, 3))
+    pot = np.zeros(n)
+    rc = lib().orc_coulomb(n, _ptr(xyz), _ptr(q), float(ke), _ptr(e), _ptr(f), _ptr(pot))
+    if rc != 0:
+        raise RuntimeError(f"oracle coulomb failed with code {rc}")
+    return float(e[0]), f, pot

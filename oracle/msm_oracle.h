@@ -1,0 +1,59 @@
+/*
+ * FP64 CPU oracle for the multilevel summation method (MSM) and the
+ * velocity-Verlet / parareal integration that uses it.
+ *
+ * TEST INFRASTRUCTURE ONLY. Only the test suite, the package smoke check and
+ * the CPU-baseline leg of the benchmark may load or call this library. It
+ * shares no code, header, table or constant generator with the HIP library;
+ * it is written to be read against the paper, not to be fast.
+ *
+ * Units: nm, e, kJ/mol (with ke = 1/(4 pi eps0) = 138.935458 kJ mol^-1 nm e^-2),
+ * or ke = 1 for unit tests. Arrays are row-major; positions are (n, 3).
+ * Return codes: 0 ok, -1 bad argument, -2 atom outside the domain,
+ * -3 non-finite input.
+ */
+#ifndef MSM_ORACLE_H
+#define MSM_ORACLE_H
+#include <stdint.h>
+
+#define ORC_MAXLEV 16
+
+typedef struct {
+    double a;          /* short-range cutoff */
+    double h;          /* finest grid spacing */
+    int levels;        /* number of grids l; 0 = choose from the domain */
+    double lo[3];      /* domain lower corner (grid origin of every level) */
+    double hi[3];      /* domain upper corner */
+    double ke;         /* Coulomb constant */
+} orc_params;
+
+/* Optional per-stage outputs; any pointer may be NULL. Grid arrays are
+ * x-fastest over the level's node range (see orc_grid_shape). */
+typedef struct {
+    double *u_short;               /* n: sum_j g*(r_ij) q_j */
+    double *f_short;               /* n*3: -sum_j q_j (dg^*(r)/dr) (r_i - r_j) / r_ij */
+    double *q_grid[ORC_MAXLEV];    /* grid charges q^k */
+    double *ucut_grid[ORC_MAXLEV]; /* lattice-cutoff potentials u^{k,cutoff} (top: u^{l-1}) */
+    double *u_grid[ORC_MAXLEV];    /* prolongated potentials u^k */
+    double *u_long;                /* n: sum_mu phi_mu(r_i) u^0_mu */
+    double *g_long;                /* n*3: sum_mu grad phi_mu(r_i) u^0_mu */
+} orc_stages;
+
+double orc_gamma(double rho);
+double orc_dgamma(double rho);
+double orc_Phi(double t);
+double orc_dPhi(double t);
+double orc_gstar(double r, double a);
+double orc_dgstar(double r, double a);
+double orc_glevel(double r, double a, int k, int l);
+
+int orc_levels(const orc_params *p);
+int orc_grid_shape(const orc_params *p, int level, int org[3], int dim[3]);
+
+int orc_msm(const orc_params *p, int64_t n, const double *xyz, const double *q,
+            double *energy, double *forces, double *pot, orc_stages *st);
+
+int orc_coulomb(int64_t n, const double *xyz, const double *q, double ke,
+                double *energy, double *forces, double *pot);
+
+#endif

@@ -1,0 +1,356 @@
+"""Pins of the FP64 oracle against facts that do not come from the oracle itself.
+
+Each test checks a fact that the paper (Section 3 unless stated) or plain
+mathematics fixes: closed forms, smoothness conditions, the telescoping of the
+kernel splitting, moment preservation, an independent dense evaluation of the
+nested interpolation formula, brute-force Coulomb within the method's stated
+error bound, finite differences, Newton's third law and grid symmetries. A
+plausible mistake in the oracle (a dropped term, a wrong sign, index or
+transposition) fails at least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import dense
+from workloads import uniform_pm, water_box
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def fd(f, x, eps=1e-5):
+    return (f(x + eps) - f(x - eps)) / (2 * eps)
+
+
+def fd2(f, x, eps=1e-4):
+    return (f(x + eps) - 2 * f(x) + f(x - eps)) / eps ** 2
+
+
+# --------------------------------------------------------------------------
+# smoothing function gamma (Section 3): even quartic inside, 1/rho outside,
+# joined with C2 continuity.
+# --------------------------------------------------------------------------
+def test_gamma_is_reciprocal_beyond_one(orc):
+    for rho in [1.0, 1.3, 2.0, 7.5]:
+        assert orc.gamma(rho) == pytest.approx(1.0 / rho, rel=1e-15)
+
+
+def test_gamma_is_even_quartic_inside(orc):
+    # A polynomial in rho^2 of degree 2 is fixed by three samples; every other
+    # sample on [0, 1) must lie on it.
+    s = np.array([0.0, 0.4, 0.8])
+    coef = np.polyfit(s ** 2, orc.gamma(s), 2)
+    for rho in np.linspace(0.05, 0.99, 17):
+        assert orc.gamma(rho) == pytest.approx(np.polyval(coef, rho ** 2), abs=1e-13)
+
+
+def test_gamma_c2_join(orc):
+    g = lambda x: orc.gamma(x)  # noqa: E731
+    left = lambda x: np.polyval(np.polyfit(np.array([0.0, 0.4, 0.8]) ** 2, orc.gamma(np.array([0.0, 0.4, 0.8])), 2), x ** 2)  # noqa: E731
+    # value, slope and curvature of the inner polynomial at rho = 1 match 1/rho
+    assert left(1.0) == pytest.approx(1.0, abs=1e-12)
+    assert fd(left, 1.0) == pytest.approx(-1.0, abs=1e-8)
+    assert fd2(left, 1.0) == pytest.approx(2.0, abs=1e-5)
+    # and the function itself is C1 across the join
+    assert fd(g, 1.0, 1e-6) == pytest.approx(-1.0, abs=1e-6)
+    assert orc.dgamma(1.0 - 1e-12) == pytest.approx(orc.dgamma(1.0 + 1e-12), abs=1e-10)
+
+
+def test_dgamma_matches_finite_difference(orc):
+    for rho in [0.1, 0.5, 0.93, 1.2, 3.0]:
+        assert orc.dgamma(rho) == pytest.approx(fd(orc.gamma, rho), rel=1e-7, abs=1e-9)
+
+
+# --------------------------------------------------------------------------
+# nodal basis Phi (Section 3; cubic numerical Hermite, p = 3)
+# --------------------------------------------------------------------------
+def test_phi_interpolates_and_has_support_four(orc):
+    for n in range(-4, 5):
+        assert orc.Phi(float(n)) == (1.0 if n == 0 else 0.0)
+    for t in [-3.5, -2.0, -2.7, 2.0, 2.01, 3.9]:
+        assert orc.Phi(t) == 0.0
+
+
+def test_phi_reproduces_quadratics(orc):
+    rng = np.random.default_rng(0)
+    for t in rng.uniform(-3, 3, 25):
+        ns = np.arange(math.floor(t) - 3, math.floor(t) + 4)
+        w = orc.Phi(t - ns)
+        assert w.sum() == pytest.approx(1.0, abs=1e-14)
+        assert (w * ns).sum() == pytest.approx(t, abs=1e-13)
+        assert (w * ns ** 2).sum() == pytest.approx(t * t, abs=1e-12)
+        # it is not cubic-exact: the numerical Hermite slopes are second order
+    t = 0.3
+    ns = np.arange(-3, 4)
+    assert abs((orc.Phi(t - ns) * ns ** 3).sum() - t ** 3) > 1e-3
+
+
+def test_phi_is_c1_piecewise_cubic(orc):
+    # C1 at the knots
+    for knot in [-2.0, -1.0, 0.0, 1.0, 2.0]:
+        assert orc.dPhi(knot - 1e-9) == pytest.approx(orc.dPhi(knot + 1e-9), abs=1e-7)
+    # slopes at the nodes are the central differences of the cardinal data
+    assert orc.dPhi(0.0) == pytest.approx(0.0, abs=1e-15)
+    assert orc.dPhi(1.0) == pytest.approx(-0.5, abs=1e-12)
+    assert orc.dPhi(-1.0) == pytest.approx(0.5, abs=1e-12)
+    # cubic on each unit interval: fourth differences vanish
+    for left in [-2.0, -1.0, 0.0, 1.0]:
+        xs = left + np.linspace(0.1, 0.9, 5)
+        assert abs(np.diff(orc.Phi(xs), 4)[0]) < 1e-13
+    for t in [-1.7, -0.4, 0.25, 1.5]:
+        assert orc.dPhi(t) == pytest.approx(fd(orc.Phi, t), abs=1e-8)
+
+
+def test_restriction_weights(orc):
+    # a fine node at half-integer coarse offset d/2 weighs Phi(d/2)
+    w = orc.Phi(np.arange(-3, 4) / 2.0)
+    np.testing.assert_allclose(w, [-1 / 16, 0, 9 / 16, 1, 9 / 16, 0, -1 / 16], atol=1e-15)
+
+
+# --------------------------------------------------------------------------
+# kernel splitting (Section 3): 1/r = g* + g^0 + ... + g^{l-1}, telescoping
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("l", [1, 2, 3, 5])
+def test_splitting_telescopes_to_reciprocal(orc, l):
+    a = 1.2
+    for r in [0.05, 0.3, 1.1, 1.2, 2.0, 3.7, 9.0, 30.0]:
+        total = orc.gstar(r, a) + sum(orc.glevel(r, a, k, l) for k in range(l))
+        assert total == pytest.approx(1.0 / r, rel=1e-13)
+
+
+def test_splitting_supports(orc):
+    a, l = 1.2, 4
+    for r in [a, 1.5 * a, 3 * a]:
+        assert orc.gstar(r, a) == pytest.approx(0.0, abs=1e-15)
+    for k in range(l - 1):
+        for r in [2 ** (k + 1) * a, 2 ** (k + 1) * a * 1.3]:
+            assert orc.glevel(r, a, k, l) == pytest.approx(0.0, abs=1e-15)
+        assert abs(orc.glevel(0.5 * 2 ** (k + 1) * a, a, k, l)) > 1e-3
+    # beyond the cutoff the level kernels alone give 1/r (the short part is zero)
+    for r in [1.25, 2.5, 6.0]:
+        assert sum(orc.glevel(r, a, k, l) for k in range(l)) == pytest.approx(1.0 / r, rel=1e-13)
+
+
+# --------------------------------------------------------------------------
+# grids and the whole long-range chain against the dense nested formula
+# --------------------------------------------------------------------------
+def _tiny(seed=7, n=12, side=1.5):
+    rng = np.random.default_rng(seed)
+    return rng.uniform(0, side, (n, 3)), rng.standard_normal(n), np.zeros(3), np.full(3, side)
+
+
+@pytest.mark.parametrize("a,h,l", [(0.5, 0.25, 3), (0.6, 0.25, 2), (0.45, 0.3, 1)])
+def test_fast_oracle_equals_dense_nested_formula(orc, a, h, l):
+    xyz, q, lo, hi = _tiny()
+    p = orc.OracleParams(a, h, tuple(lo), tuple(hi), l, 1.0)
+    e, f, pot, st = orc.msm(p, xyz, q, stages=True)
+    ed, phid, us, ul = dense.energy_potential(xyz, q, a, h, lo, hi, l, pad=1)
+    assert e == pytest.approx(ed, rel=1e-13)
+    np.testing.assert_allclose(st["u_long"], ul, rtol=0, atol=1e-13 * np.abs(ul).max())
+    np.testing.assert_allclose(st["u_short"], us, rtol=0, atol=1e-13 * np.abs(us).max())
+    np.testing.assert_allclose(pot, phid, rtol=0, atol=1e-13 * np.abs(phid).max())
+
+
+def test_literal_pair_formula_matches_oracle_pair_energy(orc):
+    # two unit charges: U = (g* + I(g_a))(r_12) + the grid self-energy residual of each
+    # charge, 1/2 (I(g_a)(r_i, r_i) - gamma(0)/a), which the self term does not cancel exactly
+    ri, rj = np.array([0.31, 0.52, 0.77]), np.array([0.95, 0.40, 0.28])
+    lo, hi, a, h, l = np.zeros(3), np.full(3, 1.25), 0.5, 0.25, 2
+    M = dense.long_range_matrix(np.stack([ri, rj]), a, h, lo, hi, l, pad=1)
+    approx = float(dense.g_star(np.array(np.linalg.norm(ri - rj)), a)) + M[0, 1]
+    self_res = 0.5 * (M[0, 0] + M[1, 1]) - float(dense.gamma(0.0)) / a
+    p = orc.OracleParams(a, h, tuple(lo), tuple(hi), l, 1.0)
+    e, _, _ = orc.msm(p, np.stack([ri, rj]), np.array([1.0, 1.0]))
+    assert e == pytest.approx(approx + self_res, rel=1e-12)
+    assert approx == pytest.approx(1.0 / np.linalg.norm(ri - rj), rel=0.02)
+    assert abs(self_res) < 0.05 * float(dense.gamma(0.0)) / a
+
+
+def test_grid_ranges_rule(orc):
+    p = orc.OracleParams(1.2, 0.25, (0, 0, 0), (4, 4, 4), 0, 1.0)
+    assert orc.levels(p) == 3     # the paper's three-grid example
+    assert orc.grid_shape(p, 0) == ((-1, -1, -1), (20, 20, 20))
+    assert orc.grid_shape(p, 1) == ((-2, -2, -2), (13, 13, 13))
+    assert orc.grid_shape(p, 2) == ((-2, -2, -2), (9, 9, 9))
+
+
+def test_grid_moments_preserved(orc):
+    w = uniform_pm(300, 3.0, seed=3)
+    p = orc.OracleParams(0.9, 0.25, tuple(w.lo), tuple(w.hi), 3, 1.0)
+    q = np.random.default_rng(1).standard_normal(w.n)
+    _, _, _, st = orc.msm(p, w.xyz, q, stages=True)
+    m0 = q.sum()
+    m1 = (q[:, None] * w.xyz).sum(0)
+    m2 = (q[:, None, None] * w.xyz[:, :, None] * w.xyz[:, None, :]).sum(0)
+    for k, grid in enumerate(st["q_grid"]):
+        org, dim = orc.grid_shape(p, k)
+        hk = 0.25 * 2 ** k
+        ax = [w.lo[d] + hk * (org[d] + np.arange(dim[d])) for d in range(3)]
+        Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+        pos = np.stack([X, Y, Z], -1).reshape(-1, 3)
+        g = grid.reshape(-1)
+        assert g.sum() == pytest.approx(m0, abs=1e-11)
+        np.testing.assert_allclose((g[:, None] * pos).sum(0), m1, atol=1e-10)
+        np.testing.assert_allclose((g[:, None, None] * pos[:, :, None] * pos[:, None, :]).sum(0), m2, atol=1e-9)
+
+
+def test_atoms_on_nodes(orc):
+    # atoms exactly on level-0 nodes put their charge on that node only, and
+    # read back exactly that node's potential
+    lo, h = np.zeros(3), 0.25
+    idx = np.array([[2, 3, 4], [5, 5, 1], [7, 2, 6], [3, 8, 8]])
+    xyz = lo + h * idx
+    q = np.array([1.0, -2.0, 0.5, 0.75])
+    p = orc.OracleParams(0.6, h, (0, 0, 0), (2.25, 2.25, 2.25), 2, 1.0)
+    _, _, _, st = orc.msm(p, xyz, q, stages=True)
+    org, dim = orc.grid_shape(p, 0)
+    g = st["q_grid"][0]
+    expect = np.zeros_like(g)
+    for (ix, iy, iz), qi in zip(idx, q):
+        expect[iz - org[2], iy - org[1], ix - org[0]] += qi
+    np.testing.assert_allclose(g, expect, atol=1e-15)
+    u0 = st["u_grid"][0]
+    for i, (ix, iy, iz) in enumerate(idx):
+        assert st["u_long"][i] == pytest.approx(u0[iz - org[2], iy - org[1], ix - org[0]], abs=1e-13)
+
+
+# --------------------------------------------------------------------------
+# accuracy against brute-force Coulomb (Section 3: under 1 % relative error
+# in potential for a C2 Taylor smoothing with a cubic Hermite basis)
+# --------------------------------------------------------------------------
+def _rel_rms(x, ref):
+    return float(np.sqrt(((x - ref) ** 2).sum() / (ref ** 2).sum()))
+
+
+def test_msm_within_stated_error_of_bruteforce(orc):
+    w = uniform_pm(2000, 4.0, seed=1)
+    p = orc.OracleParams.of(w)
+    e, f, pot = orc.msm(p, w.xyz, w.q)
+    e0, f0, p0 = orc.coulomb(w.xyz, w.q)
+    assert _rel_rms(pot, p0) < 0.01
+    assert _rel_rms(f, f0) < 0.01
+    assert abs(e - e0) / abs(e0) < 0.01
+    # a shorter cutoff at the same spacing is less accurate
+    p2 = orc.OracleParams(0.8, w.h, tuple(w.lo), tuple(w.hi), 0, p.ke)
+    _, f2, pot2 = orc.msm(p2, w.xyz, w.q)
+    assert _rel_rms(f2, f0) > _rel_rms(f, f0)
+    assert _rel_rms(pot2, p0) > _rel_rms(pot, p0)
+
+
+def test_water_within_stated_error_of_bruteforce(orc):
+    w = water_box(600, (13, 13, 13), (4.0, 4.0, 4.0), seed=11)
+    p = orc.OracleParams.of(w)
+    e, f, pot = orc.msm(p, w.xyz, w.q)
+    e0, f0, p0 = orc.coulomb(w.xyz, w.q)
+    assert _rel_rms(f, f0) < 0.01
+    assert abs(e - e0) / abs(e0) < 0.01
+
+
+def test_bruteforce_closed_forms(orc):
+    # two charges
+    e, f, pot = orc.coulomb(np.array([[0, 0, 0], [0.3, 0.4, 0.0]]), np.array([2.0, -1.5]), ke=1.0)
+    assert e == pytest.approx(2.0 * -1.5 / 0.5, rel=1e-15)
+    # F_0 = -dU/dr_0 = q0 q1 (r_0 - r_1) / r^3
+    np.testing.assert_allclose(f[0], 2.0 * -1.5 * np.array([-0.3, -0.4, 0.0]) / 0.5 ** 3, rtol=1e-14)
+    np.testing.assert_allclose(f[0], -f[1], rtol=1e-14)
+    # eight unit charges on the corners of a unit cube:
+    # 12 edges (r=1), 12 face diagonals (sqrt 2), 4 body diagonals (sqrt 3)
+    c = np.array([[i, j, k] for i in (0, 1) for j in (0, 1) for k in (0, 1)], dtype=float)
+    e, f, _ = orc.coulomb(c, np.ones(8), ke=1.0)
+    assert e == pytest.approx(12 + 12 / math.sqrt(2) + 4 / math.sqrt(3), rel=1e-14)
+    np.testing.assert_allclose(f.sum(0), 0, atol=1e-13)
+
+
+# --------------------------------------------------------------------------
+# gradients (Section 2: F = -dU/dr), Newton's third law, symmetries
+# --------------------------------------------------------------------------
+def test_forces_are_minus_energy_gradient(orc):
+    w = uniform_pm(200, 2.5, seed=5)
+    p = orc.OracleParams(0.8, 0.25, tuple(w.lo), tuple(w.hi), 0, 1.0)
+    _, f, pot = orc.msm(p, w.xyz, w.q)
+    delta = 1e-4
+    for i in [0, 17, 123]:
+        for d in range(3):
+            xp = w.xyz.copy()
+            xm = w.xyz.copy()
+            xp[i, d] += delta
+            xm[i, d] -= delta
+            ep = orc.msm(p, xp, w.q)[0]
+            em = orc.msm(p, xm, w.q)[0]
+            g = (ep - em) / (2 * delta)
+            assert -g == pytest.approx(f[i, d], rel=2e-6, abs=1e-6 * np.abs(f).max())
+    # U is quadratic in the charges: the central difference is exact
+    for i in [3, 99]:
+        qp = w.q.copy()
+        qm = w.q.copy()
+        qp[i] += 0.1
+        qm[i] -= 0.1
+        g = (orc.msm(p, w.xyz, qp)[0] - orc.msm(p, w.xyz, qm)[0]) / 0.2
+        assert g == pytest.approx(pot[i], rel=1e-11)
+
+
+def test_short_range_newton_third_law(orc):
+    w = water_box(300, (10, 10, 10), (3.0, 3.0, 3.0), seed=4)
+    p = orc.OracleParams.of(w, ke=1.0)
+    _, _, _, st = orc.msm(p, w.xyz, w.q, stages=True)
+    fs = w.q[:, None] * st["f_short"]
+    assert np.abs(fs.sum(0)).max() < 1e-10 * np.abs(fs).max()
+
+
+def test_translation_by_grid_steps_and_axis_symmetries(orc):
+    rng = np.random.default_rng(9)
+    xyz = rng.uniform(0.6, 2.4, (60, 3))
+    q = rng.standard_normal(60)
+    h = 0.25
+    p = orc.OracleParams(0.7, h, (0, 0, 0), (3.5, 3.5, 3.5), 3, 1.0)
+    e, f, pot = orc.msm(p, xyz, q)
+    # shift by whole multiples of the coarsest spacing (4h for three grids)
+    sh = np.array([4 * h, 0.0, 4 * h])
+    e2, f2, _ = orc.msm(p, xyz + sh, q)
+    assert e2 == pytest.approx(e, rel=1e-12)
+    np.testing.assert_allclose(f2, f, atol=1e-11 * np.abs(f).max())
+    # permute axes
+    perm = [2, 0, 1]
+    e3, f3, _ = orc.msm(p, xyz[:, perm], q)
+    assert e3 == pytest.approx(e, rel=1e-12)
+    np.testing.assert_allclose(f3, f[:, perm], atol=1e-11 * np.abs(f).max())
+    # reflect x through a coarse node at 3.0 (a multiple of 4h): x -> 3 - x keeps the atoms inside
+    xr = xyz.copy()
+    xr[:, 0] = 3.0 - xr[:, 0]
+    e4, f4, _ = orc.msm(p, xr, q)
+    assert e4 == pytest.approx(e, rel=1e-12)
+    fr = f.copy()
+    fr[:, 0] *= -1
+    np.testing.assert_allclose(f4, fr, atol=1e-11 * np.abs(f).max())
+    # a half-spacing shift is not a grid symmetry: the approximation changes a little
+    e5, _, _ = orc.msm(p, xyz + np.array([h / 2, 0, 0]), q)
+    assert e5 != pytest.approx(e, rel=1e-12)
+    assert e5 == pytest.approx(e, rel=1e-2)
+
+
+def test_forces_continuous_across_cutoff_and_grid_planes(orc):
+    # Section 3: the method gives continuous forces. Move one charge along x and
+    # compare the force just left and right of a grid plane (x = 1.25, on the
+    # level-0 lattice) and of the cutoff sphere of a second charge (x = 1.3).
+    p = orc.OracleParams(0.6, 0.25, (0, 0, 0), (2.5, 2.5, 2.5), 2, 1.0)
+    fixed = np.array([0.7, 1.1, 1.3])
+
+    def force(x):
+        return orc.msm(p, np.stack([fixed, [x, 1.1, 1.3]]), np.array([1.0, -1.0]))[1][1]
+
+    scale = np.abs(force(1.2)).max()
+    eps = 1e-9
+    for xc in (1.25, 1.3):
+        jump = np.abs(force(xc + eps) - force(xc - eps)).max()
+        assert jump < 1e-6 * scale
+    # the finite-difference step used here does resolve a real change in force
+    assert np.abs(force(1.3 + 1e-3) - force(1.3 - 1e-3)).max() > 1e3 * 1e-6 * scale
+
+
+def test_oracle_rejects_bad_inputs(orc):
+    p = orc.OracleParams(0.6, 0.25, (0, 0, 0), (1, 1, 1), 0, 1.0)
+    with pytest.raises(RuntimeError, match="-2"):
+        orc.msm(p, np.array([[0.5, 0.5, 1.2]]), np.array([1.0]))
+    with pytest.raises(RuntimeError, match="-3"):
+        orc.msm(p, np.array([[0.5, np.nan, 0.5]]), np.array([1.0]))
