@@ -1,0 +1,134 @@
+/*
+ * msmx: multilevel summation electrostatics and parareal velocity Verlet on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libmsmx.so. Method: J. Pazurikova and L. Matyska, "Parallel-in-time
+ * method for calculation of long-range electrostatic interactions"
+ * (arXiv:1309.1889). Section 2 states the problem (charges q_i, positions r_i,
+ * velocities v_i in; potential energy U and forces F_i = -dU/dr_i out),
+ * Section 3 the multilevel summation method (MSM) that evaluates U, and
+ * Section 4 the parareal iteration that uses a fine and a coarse propagator.
+ *
+ * Conventions
+ *  - Units: nm, e, amu, ps, kJ/mol; coulomb_k = 1/(4 pi eps0) = 138.935458
+ *    kJ mol^-1 nm e^-2 (or 1.0 for unit tests).
+ *  - Every pointer whose name ends in _dev is a device pointer (HBM of the
+ *    context's GPU) owned by the caller; _host pointers are host memory owned
+ *    by the caller. The library owns its workspace, allocated in msm_setup and
+ *    freed in msm_destroy; the evaluation and integration calls allocate no
+ *    memory.
+ *  - Calls are asynchronous on the stream given at setup: they return once
+ *    the work is enqueued. Results are valid after the stream synchronises.
+ *    Conditions only the device can see (an atom outside the domain, a
+ *    non-finite value) set a status word that msm_get_status reads.
+ *  - Precision: MSM_FP64 runs every step in double. MSM_FP32 runs pair, grid
+ *    and stencil arithmetic in float and keeps the energy reduction (and the
+ *    parareal correction) in double. Positions/charges, forces and potentials
+ *    are float or double accordingly.
+ *  - Return value: MSM_OK (0), MSM_NOT_CONVERGED (1) or a negative MSM_ERR_*.
+ *  - A context is used by one host thread at a time.
+ */
+#ifndef MSMX_MSM_H
+#define MSMX_MSM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    MSM_OK = 0,
+    MSM_NOT_CONVERGED = 1,      /* parareal stopped at kmax above tolerance */
+    MSM_ERR_ARG = -1,           /* invalid argument */
+    MSM_ERR_DOMAIN = -2,        /* an atom lies outside its system's domain */
+    MSM_ERR_NONFINITE = -3,     /* a position or charge is NaN or infinite */
+    MSM_ERR_CAPACITY = -4,      /* more atoms/systems or a larger domain than set up for */
+    MSM_ERR_HIP = -5,           /* a HIP runtime call failed */
+    MSM_ERR_UNSUPPORTED = -6    /* parameters outside what the kernels are built for */
+};
+
+enum { MSM_FP64 = 0, MSM_FP32 = 1 };
+
+typedef struct msm_ctx msm_ctx;   /* opaque; owned by the library */
+
+/* Method parameters (Section 3): cutoff a, finest spacing h, number of grids
+ * l, and the domain. The smoothing function is the C2 even Taylor polynomial
+ * of Section 3 and the nodal basis the C1 cubic numerical Hermite interpolant
+ * (p = 3), the pair the paper selects for accuracy and cost. */
+typedef struct {
+    double a;              /* short-range cutoff (nm), > 0 */
+    double h;              /* finest grid spacing (nm), > 0; a/h <= 6 */
+    int levels;            /* number of grids l; 0 = smallest l with the coarsest
+                              grid spanning at most 4 spacings per axis */
+    int precision;         /* MSM_FP64 or MSM_FP32 */
+    double lo[3], hi[3];   /* non-periodic domain; its extent bounds every system's */
+    double coulomb_k;      /* prefactor of the potential */
+    int64_t max_atoms;     /* capacity: atoms summed over a batch */
+    int max_systems;       /* capacity: systems per batch */
+} msm_params;
+
+/* Create a context: validates the parameters, builds the stencil weights and
+ * allocates the workspace for max_atoms atoms in up to max_systems systems
+ * whose domains are no larger than [lo, hi]. stream is a hipStream_t (NULL:
+ * the null stream). On success *out owns the context. */
+int msm_setup(const msm_params *params, void *stream, msm_ctx **out);
+
+/* Release the context and its workspace (synchronises its stream). NULL is a no-op. */
+void msm_destroy(msm_ctx *ctx);
+
+/* Change the stream later calls are enqueued on. */
+int msm_set_stream(msm_ctx *ctx, void *stream);
+
+/* Energy, forces and per-atom potentials of nsys independent systems
+ * (Section 3: short-range part, anterpolation, restriction, lattice cutoff,
+ * top level, prolongation, interpolation, and the combination
+ * U_i = k (u_i^short + u_i^long); Section 2: F_i = -dU/dr_i).
+ *
+ *  offsets_host   nsys+1 increasing int64; system s owns atoms
+ *                 [offsets[s], offsets[s+1]) of the arrays below;
+ *                 offsets[0] = 0 and offsets[nsys] <= max_atoms.
+ *  domains_host   NULL (every system uses the context's domain) or nsys*6
+ *                 doubles lo_x lo_y lo_z hi_x hi_y hi_z, each extent no
+ *                 larger than the context's.
+ *  xyzq_dev       N x 4 (x, y, z, q), float or double per the precision.
+ *  energy_dev     nsys doubles: U = 1/2 sum_i q_i phi_i per system, where phi_i
+ *                 excludes the atom's own charge (the smooth self term
+ *                 q_i gamma(0)/a is removed). May be NULL.
+ *  forces_dev     N x 3, F_i = -dU/dr_i. May be NULL.
+ *  potentials_dev N, phi_i = dU/dq_i. May be NULL.
+ * Outputs are in the caller's atom order. Results for a system with an atom
+ * outside its domain or a non-finite input are undefined; the status word
+ * reports it. Two atoms at the same position are not allowed. */
+int msm_energy_forces(msm_ctx *ctx, int nsys, const int64_t *offsets_host,
+                      const double *domains_host, const void *xyzq_dev,
+                      double *energy_dev, void *forces_dev, void *potentials_dev);
+
+/* Synchronise the stream, return and clear the device status word:
+ * MSM_OK, MSM_ERR_DOMAIN or MSM_ERR_NONFINITE (the first seen), or MSM_ERR_HIP. */
+int msm_get_status(msm_ctx *ctx);
+
+/* Text for a status code. */
+const char *msm_status_string(int code);
+
+/* Grid geometry of one system (context domain when domain_host is NULL):
+ * returns the number of grids and fills, per level k < 16, the first node
+ * index org[3k..3k+2] and node counts dim[3k..3k+2]. Level k node (i, j, l)
+ * sits at lo + 2^k h (i, j, l). */
+int msm_grid_shape(const msm_ctx *ctx, const double *domain_host, int *org, int *dim);
+
+/* Copy intermediate results of the last msm_energy_forces call for system
+ * `sys` into caller device buffers (any may be NULL), converted to double:
+ * u_short (N_s), f_short (N_s x 3, the bracket of the short-range force
+ * before the factor k q_i), per-level grids q^k and u^k (prolongated; the
+ * lattice-cutoff part for `ucut`) in x-fastest order of msm_grid_shape.
+ * Grid pointers are arrays of `levels` device pointers in host memory.
+ * Atom arrays are in the caller's order. For tests. */
+int msm_debug_stages(msm_ctx *ctx, int sys, double *u_short_dev, double *f_short_dev,
+                     double *const *q_grid_dev, double *const *ucut_grid_dev,
+                     double *const *u_grid_dev);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,214 @@
+"""ctypes binding of libmsmx.so; argument marshalling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+MSM_FP64 = 0
+MSM_FP32 = 1
+MAXLEV = 16
+
+_lock = threading.Lock()
+_lib = None
+
+
+class MsmError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {status_string(code)} ({code})" if what else f"{status_string(code)} ({code})")
+
+
+class _Params(C.Structure):
+    _fields_ = [("a", C.c_double), ("h", C.c_double), ("levels", C.c_int), ("precision", C.c_int),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("coulomb_k", C.c_double),
+                ("max_atoms", C.c_int64), ("max_systems", C.c_int)]
+
+
+def lib_path() -> str:
+    return os.path.join(HERE, "libmsmx.so")
+
+
+def lib():
+    """Load libmsmx.so; raises if it is not built (there is no fallback)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        path = lib_path()
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is not built; run `python -m paper_1309_1889_amd.build`")
+        L = C.CDLL(path)
+        vp = C.c_void_p
+        L.msm_setup.argtypes = [C.POINTER(_Params), vp, C.POINTER(vp)]
+        L.msm_setup.restype = C.c_int
+        L.msm_destroy.argtypes = [vp]
+        L.msm_destroy.restype = None
+        L.msm_set_stream.argtypes = [vp, vp]
+        L.msm_set_stream.restype = C.c_int
+        L.msm_energy_forces.argtypes = [vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double), vp, vp, vp, vp]
+        L.msm_energy_forces.restype = C.c_int
+        L.msm_get_status.argtypes = [vp]
+        L.msm_get_status.restype = C.c_int
+        L.msm_status_string.argtypes = [C.c_int]
+        L.msm_status_string.restype = C.c_char_p
+        L.msm_grid_shape.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.msm_grid_shape.restype = C.c_int
+        L.msm_debug_stages.argtypes = [vp, C.c_int, vp, vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]
+        L.msm_debug_stages.restype = C.c_int
+        _lib = L
+        return L
+
+
+def status_string(code: int) -> str:
+    try:
+        return lib().msm_status_string(int(code)).decode()
+    except ImportError:
+        return "status %d" % code
+
+
+def _check(code: int, what: str):
+    if code < 0:
+        raise MsmError(code, what)
+    return code
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(int(stream.cuda_stream))
+
+
+class MsmContext:
+    """A configured MSM evaluator with its workspace on one GPU.
+
+    a, h: cutoff and finest grid spacing (nm); lo, hi: domain corners;
+    levels: number of grids (0 = from the domain); precision: "fp32" or
+    "fp64"; ke: Coulomb prefactor; max_atoms / max_systems: batch capacity.
+    """
+
+    def __init__(self, a, h, lo, hi, *, levels=0, precision="fp32", ke=138.935458,
+                 max_atoms=1 << 20, max_systems=1, stream=None):
+        import torch
+        self.precision = precision
+        self.dtype = torch.float32 if precision == "fp32" else torch.float64
+        p = _Params()
+        p.a, p.h, p.levels = float(a), float(h), int(levels)
+        p.precision = MSM_FP32 if precision == "fp32" else MSM_FP64
+        for d in range(3):
+            p.lo[d] = float(lo[d])
+            p.hi[d] = float(hi[d])
+        p.coulomb_k = float(ke)
+        p.max_atoms = int(max_atoms)
+        p.max_systems = int(max_systems)
+        self.params = p
+        self.a, self.h, self.ke = float(a), float(h), float(ke)
+        self.lo = tuple(float(v) for v in lo)
+        self.hi = tuple(float(v) for v in hi)
+        self.max_atoms, self.max_systems = int(max_atoms), int(max_systems)
+        handle = C.c_void_p()
+        _check(lib().msm_setup(C.byref(p), _stream_handle(stream), C.byref(handle)), "msm_setup")
+        self._h = handle
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().msm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        _check(lib().msm_set_stream(self._h, _stream_handle(stream)), "msm_set_stream")
+
+    def status(self) -> int:
+        return lib().msm_get_status(self._h)
+
+    def check(self):
+        code = self.status()
+        if code != 0:
+            raise MsmError(code, "device status")
+
+    def grid_shape(self, domain=None):
+        org = (C.c_int * (3 * MAXLEV))()
+        dim = (C.c_int * (3 * MAXLEV))()
+        dom = None
+        if domain is not None:
+            dom = (C.c_double * 6)(*[float(v) for v in domain])
+        n = _check(lib().msm_grid_shape(self._h, dom, org, dim), "msm_grid_shape")
+        return [(tuple(org[3 * k:3 * k + 3]), tuple(dim[3 * k:3 * k + 3])) for k in range(n)]
+
+    # ------------------------------------------------------------------
+    def energy_forces(self, xyzq, offsets=None, domains=None, *, energy=None, forces=None, potentials=None,
+                      want=("energy", "forces", "potentials")):
+        """Evaluate nsys systems packed in ``xyzq`` (N x 4, contiguous, on the
+        context's GPU, in its precision). ``offsets`` (nsys+1 ints) splits the
+        atoms into systems (default: one system); ``domains`` (nsys x 6) gives
+        per-system domains. Output tensors are allocated unless passed in.
+        Returns (energy[nsys] float64, forces[N,3], potentials[N])."""
+        import torch
+        if xyzq.dtype != self.dtype or not xyzq.is_cuda or not xyzq.is_contiguous() or xyzq.dim() != 2 \
+                or xyzq.shape[1] != 4:
+            raise ValueError("xyzq must be a contiguous (N, 4) device tensor of the context's precision")
+        n = xyzq.shape[0]
+        if offsets is None:
+            offsets = [0, n]
+        offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        nsys = len(offs) - 1
+        if offs[-1] != n:
+            raise ValueError("offsets must end at the number of atoms")
+        dev = xyzq.device
+        if energy is None and "energy" in want:
+            energy = torch.empty(nsys, dtype=torch.float64, device=dev)
+        if forces is None and "forces" in want:
+            forces = torch.empty((n, 3), dtype=self.dtype, device=dev)
+        if potentials is None and "potentials" in want:
+            potentials = torch.empty(n, dtype=self.dtype, device=dev)
+        dom_p = None
+        if domains is not None:
+            dom = np.ascontiguousarray(np.asarray(domains, dtype=np.float64).reshape(nsys, 6))
+            dom_p = dom.ctypes.data_as(C.POINTER(C.c_double))
+        ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+        rc = lib().msm_energy_forces(self._h, nsys, offs.ctypes.data_as(C.POINTER(C.c_int64)), dom_p,
+                                     ptr(xyzq), ptr(energy), ptr(forces), ptr(potentials))
+        _check(rc, "msm_energy_forces")
+        return energy, forces, potentials
+
+    def debug_stages(self, sys=0, domain=None):
+        """Intermediate results of the last evaluation of system ``sys``
+        (float64 device tensors, caller atom order)."""
+        import torch
+        shapes = self.grid_shape(domain)
+        dev = torch.device("cuda", torch.cuda.current_device())
+        # number of atoms of that system is not stored here; the caller slices
+        out = {"q_grid": [], "ucut_grid": [], "u_grid": []}
+        ptrs = {}
+        for key in out:
+            arr = (C.c_void_p * len(shapes))()
+            for k, (_, dim) in enumerate(shapes):
+                t = torch.zeros((dim[2], dim[1], dim[0]), dtype=torch.float64, device=dev)
+                out[key].append(t)
+                arr[k] = t.data_ptr()
+            ptrs[key] = arr
+        return out, ptrs
+
+    def stages(self, n_sys_atoms, sys=0, domain=None):
+        import torch
+        out, ptrs = self.debug_stages(sys, domain)
+        dev = out["q_grid"][0].device
+        us = torch.zeros(n_sys_atoms, dtype=torch.float64, device=dev)
+        fs = torch.zeros((n_sys_atoms, 3), dtype=torch.float64, device=dev)
+        _check(lib().msm_debug_stages(self._h, sys, C.c_void_p(us.data_ptr()), C.c_void_p(fs.data_ptr()),
+                                      ptrs["q_grid"], ptrs["ucut_grid"], ptrs["u_grid"]), "msm_debug_stages")
+        torch.cuda.synchronize()
+        out["u_short"] = us
+        out["f_short"] = fs
+        return out

@@ -1,0 +1,213 @@
+// Binning of atoms into cells of edge h (the cells that the short-range pair
+// search and the gather forms of anterpolation and interpolation walk), as a
+// counting sort: histogram, exclusive scan, scatter. Cells are ranked
+// brick-major (4x4x4 cells per brick) so that 64 consecutive sorted atoms form
+// a compact group, while the cells of one brick row along x stay contiguous.
+// A final per-cell sort by input index makes the order independent of the
+// arrival order of the histogram atomics, so every evaluation is bitwise
+// reproducible.
+#include "launch.h"
+
+namespace msmx {
+
+namespace {
+
+constexpr int kScanThreads = 256;
+constexpr int kScanItems = 16;
+constexpr int kScanBlock = kScanThreads * kScanItems;
+
+__global__ void k_fill_i32(int *p, int64_t n, int v)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+template <typename T> __global__ void k_fill_t(T *p, int64_t n, T v)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+template <typename T>
+__global__ void k_bin_count(DevPlan p, const vec4_t<T> *__restrict__ xyzq, int *__restrict__ cell_of,
+                            int *__restrict__ slot_of, int *__restrict__ counts, int *__restrict__ status)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= p.natoms) return;
+    int s = find_segment(p.atom_prefix, p.nsys, i);
+    const SysPlan &P = p.sys[s];
+    vec4_t<T> a = xyzq[i];
+    T pos[3] = {a.x, a.y, a.z};
+    int c[3];
+    int bad = 0;
+    for (int d = 0; d < 3; d++) {
+        T t = (pos[d] - T(P.lo[d])) * T(P.inv_h);
+        // an atom may sit on the boundary; a rounding overshoot of a fraction
+        // of a cell is tolerated and binned into the edge cell
+        if (!(t >= T(-1e-4) && t <= T(P.tmax[d] + 1e-4))) bad |= isfinite(t) ? kStatusDomain : kStatusNonFinite;
+        int ci = (t >= T(0)) ? (int)floor(t) : 0;
+        if (!(t >= T(0))) ci = 0;
+        if (ci > P.nc[d] - 1) ci = P.nc[d] - 1;
+        c[d] = ci;
+    }
+    if (!isfinite(a.w)) bad |= kStatusNonFinite;
+    if (bad) atomicOr(status, bad);
+    int cell = (int)(P.cell0 + cell_rank(P, c[0], c[1], c[2]));
+    cell_of[i] = cell;
+    slot_of[i] = atomicAdd(&counts[cell], 1);
+}
+
+// exclusive scan of int counts, three passes
+__global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int *__restrict__ in, int64_t n,
+                                                               int *__restrict__ bsum)
+{
+    __shared__ int red[kScanThreads];
+    int64_t base = blockIdx.x * (int64_t)kScanBlock;
+    int acc = 0;
+    for (int j = 0; j < kScanItems; j++) {
+        int64_t idx = base + (int64_t)j * kScanThreads + threadIdx.x;
+        if (idx < n) acc += in[idx];
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = kScanThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+
+// in-block exclusive scan of one value per thread; returns the block total
+__device__ inline int block_exclusive_scan(int v, int *sh, int &total)
+{
+    int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
+        int add = (tid >= off) ? sh[tid - off] : 0;
+        __syncthreads();
+        sh[tid] += add;
+        __syncthreads();
+    }
+    int incl = sh[tid];
+    total = sh[blockDim.x - 1];
+    __syncthreads();
+    return incl - v;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_blocksums(int *__restrict__ bsum, int nb)
+{
+    __shared__ int sh[1024];
+    int carry = 0;
+    for (int base = 0; base < nb; base += 1024) {
+        int idx = base + threadIdx.x;
+        int v = idx < nb ? bsum[idx] : 0;
+        int total;
+        int ex = block_exclusive_scan(v, sh, total);
+        if (idx < nb) bsum[idx] = ex + carry;
+        carry += total;
+    }
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(int *__restrict__ data, int64_t n,
+                                                              const int *__restrict__ bsum)
+{
+    __shared__ int sh[kScanThreads];
+    int64_t base = blockIdx.x * (int64_t)kScanBlock + (int64_t)threadIdx.x * kScanItems;
+    int v[kScanItems];
+    int acc = 0;
+    for (int j = 0; j < kScanItems; j++) {
+        int64_t idx = base + j;
+        v[j] = idx < n ? data[idx] : 0;
+        acc += v[j];
+    }
+    int total;
+    int ex = block_exclusive_scan(acc, sh, total) + bsum[blockIdx.x];
+    for (int j = 0; j < kScanItems; j++) {
+        int64_t idx = base + j;
+        if (idx < n) data[idx] = ex;
+        ex += v[j];
+    }
+}
+
+__global__ void k_scatter(int64_t n, const int *__restrict__ cell_of, const int *__restrict__ slot_of,
+                          const int *__restrict__ start, int *__restrict__ order)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    order[start[cell_of[i]] + slot_of[i]] = (int)i;
+}
+
+template <typename T>
+__global__ void k_cell_sort(int64_t ncells, const int *__restrict__ start, int *__restrict__ order,
+                            const vec4_t<T> *__restrict__ xyzq, vec4_t<T> *__restrict__ sxyzq)
+{
+    int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    int b = start[c], e = start[c + 1];
+    for (int i = b + 1; i < e; i++) {
+        int v = order[i];
+        int j = i - 1;
+        while (j >= b && order[j] > v) {
+            order[j + 1] = order[j];
+            j--;
+        }
+        order[j + 1] = v;
+    }
+    for (int i = b; i < e; i++) sxyzq[i] = xyzq[order[i]];
+}
+
+inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+}  // namespace
+
+hipError_t fill_i32(hipStream_t s, int *p, int64_t n, int v)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+template <typename T> hipError_t fill_t(hipStream_t s, T *p, int64_t n, T v)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_t<T>, dim3(nblocks(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+template hipError_t fill_t<float>(hipStream_t, float *, int64_t, float);
+template hipError_t fill_t<double>(hipStream_t, double *, int64_t, double);
+
+// Exclusive scan in place over n ints (n + 1 entries are rewritten when the
+// caller appends a zero count: entry n then holds the total).
+int scan_cells(hipStream_t s, int *data, int64_t n, int *block_sums)
+{
+    int64_t nb = (n + kScanBlock - 1) / kScanBlock;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, block_sums);
+    hipLaunchKernelGGL(k_scan_blocksums, dim3(1), dim3(1024), 0, s, block_sums, (int)nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, block_sums);
+    return (int)hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::bin(hipStream_t s, const DevPlan &p, const Work<T> &w, const vec4_t<T> *xyzq)
+{
+    hipError_t e = fill_i32(s, w.cell_start, p.ncells + 1, 0);
+    if (e != hipSuccess) return e;
+    if (p.natoms > 0)
+        hipLaunchKernelGGL(k_bin_count<T>, dim3(nblocks(p.natoms, 256)), dim3(256), 0, s, p, xyzq, w.cell_of,
+                           w.slot_of, w.cell_start, w.status);
+    scan_cells(s, w.cell_start, p.ncells + 1, w.scan_blocks);
+    if (p.natoms > 0) {
+        hipLaunchKernelGGL(k_scatter, dim3(nblocks(p.natoms, 256)), dim3(256), 0, s, p.natoms, w.cell_of,
+                           w.slot_of, w.cell_start, w.order);
+        hipLaunchKernelGGL(k_cell_sort<T>, dim3(nblocks(p.ncells, 256)), dim3(256), 0, s, p.ncells,
+                           w.cell_start, w.order, xyzq, w.sxyzq);
+    }
+    return hipGetLastError();
+}
+
+template struct Launch<float>;
+template struct Launch<double>;
+
+}  // namespace msmx

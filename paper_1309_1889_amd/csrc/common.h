@@ -1,0 +1,120 @@
+// Shared definitions of the HIP library: per-system plan, workspace layout,
+// device helpers for the smoothing function and nodal basis.
+//
+// Grid geometry (a reading of Section 3, which leaves it open): every level of
+// a system shares the domain's lower corner as origin; level-k node (i, j, l)
+// sits at lo + 2^k h (i, j, l). Atoms are binned into cells of edge h, cell c
+// holding t = (x - lo)/h in [c, c+1), so an atom in cell c touches level-0
+// nodes c-1 .. c+2. Level 0 spans node indices [-1, nc+1] with nc =
+// floor(L/h) + 1 cells; level k+1 spans [ceil((i0-3)/2), floor((i1+3)/2)] of
+// level k's [i0, i1], the nodes that restriction can reach. With these ranges
+// no term of the nested sums is dropped.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace msmx {
+
+constexpr int kMaxLevels = 16;
+constexpr int kBrick = 4;            // cells per brick edge; atoms are sorted brick-major
+constexpr int kBrickCells = kBrick * kBrick * kBrick;
+constexpr int kWave = 64;            // CDNA wavefront
+constexpr int kMaxReach = 12;        // largest stencil reach ceil(2a/h) - 1 built for
+constexpr int kGridPad = kMaxReach;  // zero halo around every charge grid
+
+enum StatusBits : int { kStatusDomain = 1, kStatusNonFinite = 2 };
+
+template <typename T> struct Vec4;
+template <> struct Vec4<float> { using type = float4; };
+template <> struct Vec4<double> { using type = double4; };
+template <typename T> using vec4_t = typename Vec4<T>::type;
+
+// One system of a batch, as the kernels see it.
+struct SysPlan {
+    int64_t atom0;           // first atom in the batch arrays
+    int64_t natoms;
+    double lo[3];            // domain lower corner (grid origin)
+    double inv_h;            // 1/h
+    double tmax[3];          // (hi - lo)/h: largest valid t per axis
+    int nc[3];               // cells per axis (floor(L/h) + 1)
+    int nb[3];               // bricks per axis (nc rounded up to kBrick)
+    int64_t cell0;           // first cell (brick-major) in the batch cell arrays
+    int64_t ncells;          // nb[0]*nb[1]*nb[2]*kBrickCells
+    int nlev;                // number of grids l
+    int gorg[kMaxLevels][3]; // first node index per level
+    int gdim[kMaxLevels][3]; // node count per level
+    int64_t qoff[kMaxLevels];// offset of the padded charge grid (pad kGridPad each side,
+                             // and kGridPad + kStencilZ extra on the high z side)
+    int64_t uoff[kMaxLevels];// offset of the unpadded potential grids
+    int64_t group0;          // first 64-atom pair group
+    int64_t ngroups;
+};
+
+constexpr int kStencilZ = 8;         // z outputs per thread in the stencil kernel
+
+__host__ __device__ inline int padded_x(int d) { return d + 2 * kGridPad; }
+__host__ __device__ inline int padded_z(int d) { return d + 2 * kGridPad + kStencilZ; }
+
+// Brick-major rank of cell (cx, cy, cz) within its system.
+__host__ __device__ inline int64_t cell_rank(const SysPlan &p, int cx, int cy, int cz)
+{
+    int bx = cx / kBrick, by = cy / kBrick, bz = cz / kBrick;
+    int ix = cx % kBrick, iy = cy % kBrick, iz = cz % kBrick;
+    int64_t brick = ((int64_t)bz * p.nb[1] + by) * p.nb[0] + bx;
+    return brick * kBrickCells + (iz * kBrick + iy) * kBrick + ix;
+}
+
+// Find s with prefix[s] <= g < prefix[s+1]; prefix has n+1 increasing entries.
+__device__ inline int find_segment(const int64_t *prefix, int n, int64_t g)
+{
+    int lo = 0, hi = n;   // invariant: prefix[lo] <= g < prefix[hi]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (prefix[mid] <= g) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+// ---- Section 3: smoothing function gamma (C2, even quartic inside rho < 1) ----
+template <typename T> __host__ __device__ inline T gamma_s(T rho)
+{
+    if (rho >= T(1)) return T(1) / rho;
+    T r2 = rho * rho;
+    return T(1.875) + r2 * (T(-1.25) + r2 * T(0.375));
+}
+
+// ---- Section 3: nodal basis Phi, the C1 cubic numerical Hermite interpolant
+// (p = 3): 1 - 5/2 s^2 + 3/2 s^3 on |t| <= 1, -1/2 (s-1)(2-s)^2 on 1 < |t| < 2.
+template <typename T> __device__ inline T basis(T t)
+{
+    T s = fabs(t);
+    T inner = T(1) + s * s * (T(-2.5) + T(1.5) * s);
+    T u = T(2) - s;
+    T outer = T(-0.5) * (s - T(1)) * u * u;
+    return s <= T(1) ? inner : (s < T(2) ? outer : T(0));
+}
+
+template <typename T> __device__ inline T dbasis(T t)
+{
+    T s = fabs(t);
+    T inner = s * (T(-5) + T(4.5) * s);
+    T u = T(2) - s;
+    T outer = T(-0.5) * u * (T(4) - T(3) * s);
+    T v = s <= T(1) ? inner : (s < T(2) ? outer : T(0));
+    return t < T(0) ? -v : v;
+}
+
+// Reciprocal square root: the hardware estimate for float; for double the
+// estimate refined by two Newton-Raphson steps y <- y (3 - x y^2) / 2.
+__device__ inline float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ inline double rsqrt_t(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    double hx = 0.5 * x;
+    y = fma(y, fma(-hx * y, y, 0.5), y);
+    y = fma(y, fma(-hx * y, y, 0.5), y);
+    return y;
+}
+
+}  // namespace msmx

@@ -1,0 +1,513 @@
+// Host side of libmsmx: context, per-call plan of a batch of systems,
+// workspace carving, and the launch sequence of one multilevel summation
+// evaluation. Implements the msm_* entry points of include/msm.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/msm.h"
+#include "engine.h"
+#include "launch.h"
+
+using namespace msmx;
+
+namespace {
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+int64_t floordiv2(int64_t v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }
+int64_t ceildiv2(int64_t v) { return -floordiv2(-v); }
+
+// Number of grids (a reading of Section 3): the smallest l for which the
+// coarsest spacing 2^(l-1) h spans the domain in at most 4 steps on every axis.
+int auto_levels(double h, const double *len)
+{
+    for (int l = 1; l <= kMaxLevels; l++) {
+        bool ok = true;
+        for (int d = 0; d < 3; d++)
+            if (std::ceil(len[d] / std::ldexp(h, l - 1)) > 4.0) ok = false;
+        if (ok) return l;
+    }
+    return kMaxLevels;
+}
+
+struct Geometry {
+    int nlev;
+    int nc[3];
+    int gorg[kMaxLevels][3];
+    int gdim[kMaxLevels][3];
+};
+
+int geometry(const msm_params &prm, const double *lo, const double *hi, Geometry &g)
+{
+    double len[3];
+    for (int d = 0; d < 3; d++) {
+        len[d] = hi[d] - lo[d];
+        if (!(len[d] > 0) || !std::isfinite(len[d])) return MSM_ERR_ARG;
+        double ncd = std::floor(len[d] / prm.h) + 1.0;
+        if (ncd > 1 << 20) return MSM_ERR_CAPACITY;
+        g.nc[d] = (int)ncd;
+    }
+    g.nlev = prm.levels > 0 ? prm.levels : auto_levels(prm.h, len);
+    if (g.nlev < 1 || g.nlev > kMaxLevels) return MSM_ERR_UNSUPPORTED;
+    for (int d = 0; d < 3; d++) {
+        int64_t i0 = -1, i1 = g.nc[d] + 1;
+        for (int k = 0; k < g.nlev; k++) {
+            g.gorg[k][d] = (int)i0;
+            g.gdim[k][d] = (int)(i1 - i0 + 1);
+            i0 = ceildiv2(i0 - 3);
+            i1 = floordiv2(i1 + 3);
+        }
+    }
+    return MSM_OK;
+}
+
+struct Sizes {
+    int64_t cells, q, u;
+};
+
+Sizes sizes_of(const Geometry &g)
+{
+    Sizes s{};
+    int64_t nb = 1;
+    for (int d = 0; d < 3; d++) nb *= (g.nc[d] + kBrick - 1) / kBrick;
+    s.cells = nb * kBrickCells;
+    for (int k = 0; k < g.nlev; k++) {
+        s.q += round_up((int64_t)padded_x(g.gdim[k][0]) * padded_x(g.gdim[k][1]) * padded_z(g.gdim[k][2]), 64);
+        s.u += round_up((int64_t)g.gdim[k][0] * g.gdim[k][1] * g.gdim[k][2], 64);
+    }
+    return s;
+}
+
+template <typename T> size_t vec_bytes() { return sizeof(vec4_t<T>); }
+
+}  // namespace
+
+struct msm_ctx {
+    msm_params prm;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    MethodConst mc{};
+    int d2max = 0;
+    Geometry ctx_geom{};
+    // capacities
+    int64_t cap_cells = 0, cap_q = 0, cap_u = 0, cap_iblk = 0;
+    // device memory
+    char *wbuf = nullptr;
+    size_t wbytes = 0;
+    void *weights = nullptr;     // stencil table W[o], precision T
+    char *plan_dev = nullptr;    // tables of the current batch
+    char *plan_host = nullptr;   // pinned staging copy
+    size_t plan_cap = 0;
+    DevPlan dp{};
+    bool plan_valid = false;
+    std::vector<int64_t> last_offsets;
+    std::vector<double> last_domains;
+    std::vector<SysPlan> host_sys;
+    Work<float> wf{};
+    Work<double> wd{};
+};
+
+namespace {
+
+int hip_status(hipError_t e) { return e == hipSuccess ? MSM_OK : MSM_ERR_HIP; }
+
+template <typename T> void carve(msm_ctx *c, Work<T> &w, char *base, size_t *used, bool commit)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *p = base ? base + off : nullptr;
+        off += (bytes + 255) / 256 * 256;
+        return p;
+    };
+    const int64_t na = std::max<int64_t>(c->prm.max_atoms, 1);
+    w.cell_of = (int *)take(sizeof(int) * na);
+    w.slot_of = (int *)take(sizeof(int) * na);
+    w.cell_start = (int *)take(sizeof(int) * (c->cap_cells + 1));
+    w.scan_blocks = (int *)take(sizeof(int) * ((c->cap_cells + 1) / 4096 + 2));
+    w.order = (int *)take(sizeof(int) * na);
+    w.sxyzq = (vec4_t<T> *)take(vec_bytes<T>() * na);
+    w.shrt = (vec4_t<T> *)take(vec_bytes<T>() * na);
+    w.qgrid = (T *)take(sizeof(T) * c->cap_q);
+    w.ucut = (T *)take(sizeof(T) * c->cap_u);
+    w.ugrid = (T *)take(sizeof(T) * c->cap_u);
+    w.eparts = (double *)take(sizeof(double) * c->cap_iblk);
+    w.status = (int *)take(sizeof(int) * 64);
+    *used = off;
+    (void)commit;
+}
+
+// Build the device tables of a batch; returns MSM_OK or an error.
+int build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double *domains)
+{
+    if (c->plan_valid && (int)c->last_offsets.size() == nsys + 1 &&
+        std::equal(offsets, offsets + nsys + 1, c->last_offsets.begin())) {
+        bool same = domains ? (c->last_domains.size() == (size_t)nsys * 6 &&
+                               std::equal(domains, domains + nsys * 6, c->last_domains.begin()))
+                            : c->last_domains.empty();
+        if (same) return MSM_OK;
+    }
+    if (offsets[0] != 0) return MSM_ERR_ARG;
+    for (int s = 0; s < nsys; s++)
+        if (offsets[s + 1] < offsets[s]) return MSM_ERR_ARG;
+    if (offsets[nsys] > c->prm.max_atoms) return MSM_ERR_CAPACITY;
+
+    std::vector<SysPlan> sys(nsys);
+    const int W = nsys + 1;
+    std::vector<int64_t> atom_p(W), group_p(W), cell_p(W), iblk_p(W), top_p(W);
+    std::vector<int64_t> node_p((size_t)kMaxLevels * W), sten_p((size_t)kMaxLevels * W);
+    int64_t cells = 0, q = 0, u = 0, groups = 0, iblk = 0, top = 0;
+    int64_t nodes[kMaxLevels] = {0}, sten[kMaxLevels] = {0};
+    int maxlev = 1;
+    for (int s = 0; s < nsys; s++) {
+        const double *lo = domains ? domains + 6 * s : c->prm.lo;
+        const double *hi = domains ? domains + 6 * s + 3 : c->prm.hi;
+        for (int d = 0; d < 3; d++)
+            if (!(hi[d] - lo[d] <= c->prm.hi[d] - c->prm.lo[d] + 1e-12 * std::fabs(c->prm.hi[d] - c->prm.lo[d])))
+                return MSM_ERR_CAPACITY;
+        Geometry g;
+        int rc = geometry(c->prm, lo, hi, g);
+        if (rc) return rc;
+        SysPlan &P = sys[s];
+        std::memset(&P, 0, sizeof(P));
+        P.atom0 = offsets[s];
+        P.natoms = offsets[s + 1] - offsets[s];
+        P.inv_h = 1.0 / c->prm.h;
+        for (int d = 0; d < 3; d++) {
+            P.lo[d] = lo[d];
+            P.tmax[d] = (hi[d] - lo[d]) / c->prm.h;
+            P.nc[d] = g.nc[d];
+            P.nb[d] = (g.nc[d] + kBrick - 1) / kBrick;
+        }
+        P.nlev = g.nlev;
+        maxlev = std::max(maxlev, g.nlev);
+        std::memcpy(P.gorg, g.gorg, sizeof(P.gorg));
+        std::memcpy(P.gdim, g.gdim, sizeof(P.gdim));
+        P.cell0 = cells;
+        P.ncells = (int64_t)P.nb[0] * P.nb[1] * P.nb[2] * kBrickCells;
+        P.group0 = groups;
+        P.ngroups = (P.natoms + kWave - 1) / kWave;
+        atom_p[s] = P.atom0;
+        group_p[s] = groups;
+        cell_p[s] = cells;
+        iblk_p[s] = iblk;
+        top_p[s] = top;
+        for (int k = 0; k < kMaxLevels; k++) {
+            node_p[(size_t)k * W + s] = nodes[k];
+            sten_p[(size_t)k * W + s] = sten[k];
+        }
+        for (int k = 0; k < g.nlev; k++) {
+            P.qoff[k] = q;
+            P.uoff[k] = u;
+            const int64_t n = (int64_t)g.gdim[k][0] * g.gdim[k][1] * g.gdim[k][2];
+            q += round_up((int64_t)padded_x(g.gdim[k][0]) * padded_x(g.gdim[k][1]) * padded_z(g.gdim[k][2]), 64);
+            u += round_up(n, 64);
+            nodes[k] += n;
+            if (k < g.nlev - 1)
+                sten[k] += (int64_t)g.gdim[k][0] * g.gdim[k][1] * ((g.gdim[k][2] + kStencilZ - 1) / kStencilZ);
+        }
+        const int kt = g.nlev - 1;
+        top += (int64_t)g.gdim[kt][0] * g.gdim[kt][1] * g.gdim[kt][2];
+        cells += P.ncells;
+        groups += P.ngroups;
+        iblk += (P.natoms + 255) / 256;
+    }
+    atom_p[nsys] = offsets[nsys];
+    group_p[nsys] = groups;
+    cell_p[nsys] = cells;
+    iblk_p[nsys] = iblk;
+    top_p[nsys] = top;
+    for (int k = 0; k < kMaxLevels; k++) {
+        node_p[(size_t)k * W + nsys] = nodes[k];
+        sten_p[(size_t)k * W + nsys] = sten[k];
+    }
+    if (cells > c->cap_cells || q > c->cap_q || u > c->cap_u || iblk > c->cap_iblk) return MSM_ERR_CAPACITY;
+    if (cells >= (int64_t)1 << 31) return MSM_ERR_CAPACITY;
+
+    // pack the tables into one blob
+    size_t off = 0;
+    auto place = [&](size_t bytes) {
+        size_t o = off;
+        off += (bytes + 255) / 256 * 256;
+        return o;
+    };
+    const size_t o_sys = place(sizeof(SysPlan) * nsys);
+    const size_t o_atom = place(sizeof(int64_t) * W), o_group = place(sizeof(int64_t) * W);
+    const size_t o_cell = place(sizeof(int64_t) * W), o_iblk = place(sizeof(int64_t) * W);
+    const size_t o_top = place(sizeof(int64_t) * W);
+    const size_t o_node = place(sizeof(int64_t) * kMaxLevels * W), o_sten = place(sizeof(int64_t) * kMaxLevels * W);
+    // the staging buffer may still feed an earlier copy
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
+    if (off > c->plan_cap) {
+        if (c->plan_dev) (void)hipFree(c->plan_dev);
+        if (c->plan_host) (void)hipHostFree(c->plan_host);
+        c->plan_dev = nullptr;
+        c->plan_host = nullptr;
+        c->plan_cap = 0;
+        if (hipMalloc((void **)&c->plan_dev, off) != hipSuccess) return MSM_ERR_HIP;
+        if (hipHostMalloc((void **)&c->plan_host, off, hipHostMallocDefault) != hipSuccess) return MSM_ERR_HIP;
+        c->plan_cap = off;
+    }
+    char *h = c->plan_host;
+    std::memcpy(h + o_sys, sys.data(), sizeof(SysPlan) * nsys);
+    std::memcpy(h + o_atom, atom_p.data(), sizeof(int64_t) * W);
+    std::memcpy(h + o_group, group_p.data(), sizeof(int64_t) * W);
+    std::memcpy(h + o_cell, cell_p.data(), sizeof(int64_t) * W);
+    std::memcpy(h + o_iblk, iblk_p.data(), sizeof(int64_t) * W);
+    std::memcpy(h + o_top, top_p.data(), sizeof(int64_t) * W);
+    std::memcpy(h + o_node, node_p.data(), sizeof(int64_t) * kMaxLevels * W);
+    std::memcpy(h + o_sten, sten_p.data(), sizeof(int64_t) * kMaxLevels * W);
+    if (hipMemcpyAsync(c->plan_dev, h, off, hipMemcpyHostToDevice, c->stream) != hipSuccess) return MSM_ERR_HIP;
+
+    DevPlan &dp = c->dp;
+    char *d = c->plan_dev;
+    dp.sys = (const SysPlan *)(d + o_sys);
+    dp.nsys = nsys;
+    dp.atom_prefix = (const int64_t *)(d + o_atom);
+    dp.group_prefix = (const int64_t *)(d + o_group);
+    dp.cell_prefix = (const int64_t *)(d + o_cell);
+    dp.iblk_prefix = (const int64_t *)(d + o_iblk);
+    dp.top_prefix = (const int64_t *)(d + o_top);
+    dp.node_prefix = (const int64_t *)(d + o_node);
+    dp.sten_prefix = (const int64_t *)(d + o_sten);
+    dp.natoms = offsets[nsys];
+    dp.ngroups = groups;
+    dp.ncells = cells;
+    dp.niblk = iblk;
+    dp.ntop = top;
+    for (int k = 0; k < kMaxLevels; k++) {
+        dp.nnodes[k] = nodes[k];
+        dp.nsten[k] = sten[k];
+    }
+    dp.maxlev = maxlev;
+    c->host_sys = sys;
+    c->last_offsets.assign(offsets, offsets + nsys + 1);
+    if (domains) c->last_domains.assign(domains, domains + nsys * 6);
+    else c->last_domains.clear();
+    c->plan_valid = true;
+    return MSM_OK;
+}
+
+template <typename T> Work<T> &work(msm_ctx *c);
+template <> Work<float> &work<float>(msm_ctx *c) { return c->wf; }
+template <> Work<double> &work<double>(msm_ctx *c) { return c->wd; }
+
+template <typename T>
+int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *pots)
+{
+    using L = Launch<T>;
+    const DevPlan &p = c->dp;
+    Work<T> &w = work<T>(c);
+    hipStream_t s = c->stream;
+    hipError_t e;
+    if ((e = L::bin(s, p, w, (const vec4_t<T> *)xyzq)) != hipSuccess) return MSM_ERR_HIP;
+    if ((e = L::pair(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
+    if ((e = L::anterp(s, p, w)) != hipSuccess) return MSM_ERR_HIP;
+    for (int k = 0; k + 1 < p.maxlev; k++)
+        if ((e = L::restrict_level(s, p, w, k)) != hipSuccess) return MSM_ERR_HIP;
+    for (int k = 0; k + 1 < p.maxlev; k++)
+        if ((e = L::stencil_level(s, p, w, (const T *)c->weights, c->mc.reach, c->d2max, k)) != hipSuccess) return MSM_ERR_HIP;
+    if ((e = L::top_level(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
+    for (int k = p.maxlev - 2; k >= 0; k--)
+        if ((e = L::prolong_level(s, p, w, k)) != hipSuccess) return MSM_ERR_HIP;
+    if ((e = L::interp(s, p, w, c->mc, (T *)forces, (T *)pots)) != hipSuccess) return MSM_ERR_HIP;
+    if ((e = L::energy(s, p, w, energy)) != hipSuccess) return MSM_ERR_HIP;
+    return MSM_OK;
+}
+
+// W[o] = g^0(h |o|) = gamma(h|o|/a)/a - gamma(h|o|/(2a))/(2a) for |o|^2 <= d2max
+// (zero beyond: g^0 vanishes for r >= 2a), laid out [(oy+R)(2R+1) + ox+R](2R+1) + oz+R.
+template <typename T> std::vector<T> stencil_table(double a, double h, int R, int d2max)
+{
+    const int D = 2 * R + 1;
+    std::vector<T> w((size_t)D * D * D, T(0));
+    for (int oy = -R; oy <= R; oy++)
+        for (int ox = -R; ox <= R; ox++)
+            for (int oz = -R; oz <= R; oz++) {
+                const int d2 = ox * ox + oy * oy + oz * oz;
+                if (d2 > d2max) continue;
+                const double r = h * std::sqrt((double)d2);
+                const double g0 = gamma_s(r / a) / a - gamma_s(r / (2 * a)) / (2 * a);
+                w[((size_t)(oy + R) * D + (ox + R)) * D + (oz + R)] = T(g0);
+            }
+    return w;
+}
+
+}  // namespace
+
+int msmx_ctx_precision(const msm_ctx *c) { return c->prm.precision; }
+hipStream_t msmx_ctx_stream(const msm_ctx *c) { return c->stream; }
+
+extern "C" {
+
+const char *msm_status_string(int code)
+{
+    switch (code) {
+    case MSM_OK: return "ok";
+    case MSM_NOT_CONVERGED: return "parareal did not converge within kmax iterations";
+    case MSM_ERR_ARG: return "invalid argument";
+    case MSM_ERR_DOMAIN: return "an atom lies outside its domain";
+    case MSM_ERR_NONFINITE: return "non-finite position or charge";
+    case MSM_ERR_CAPACITY: return "capacity of the context exceeded";
+    case MSM_ERR_HIP: return "HIP runtime error";
+    case MSM_ERR_UNSUPPORTED: return "parameters outside the supported range";
+    default: return "unknown status";
+    }
+}
+
+int msm_setup(const msm_params *prm, void *stream, msm_ctx **out)
+{
+    if (!prm || !out) return MSM_ERR_ARG;
+    *out = nullptr;
+    if (!(prm->a > 0) || !(prm->h > 0) || !std::isfinite(prm->a) || !std::isfinite(prm->h)) return MSM_ERR_ARG;
+    if (prm->precision != MSM_FP32 && prm->precision != MSM_FP64) return MSM_ERR_ARG;
+    if (prm->max_atoms < 0 || prm->max_atoms >= ((int64_t)1 << 31) || prm->max_systems < 1) return MSM_ERR_ARG;
+    if (prm->levels < 0 || prm->levels > kMaxLevels) return MSM_ERR_ARG;
+    if (!std::isfinite(prm->coulomb_k)) return MSM_ERR_ARG;
+    const double ratio = 2.0 * prm->a / prm->h;
+    const int reach = (int)std::ceil(ratio) - 1;       // largest integer below 2a/h
+    if (reach < 1 || reach > kMaxReach - 1) return MSM_ERR_UNSUPPORTED;
+
+    msm_ctx *c = new (std::nothrow) msm_ctx();
+    if (!c) return MSM_ERR_ARG;
+    c->prm = *prm;
+    c->stream = (hipStream_t)stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        return MSM_ERR_HIP;
+    }
+    c->mc.a = prm->a;
+    c->mc.h = prm->h;
+    c->mc.ke = prm->coulomb_k;
+    c->mc.reach = reach;
+    c->d2max = (int)std::ceil(ratio * ratio) - 1;      // largest integer below (2a/h)^2
+    int rc = geometry(*prm, prm->lo, prm->hi, c->ctx_geom);
+    if (rc) {
+        delete c;
+        return rc;
+    }
+    const Sizes sz = sizes_of(c->ctx_geom);
+    const int64_t ns = prm->max_systems;
+    c->cap_cells = sz.cells * ns;
+    c->cap_q = sz.q * ns;
+    c->cap_u = sz.u * ns;
+    c->cap_iblk = (prm->max_atoms + 255) / 256 + ns;
+    if (c->cap_cells >= ((int64_t)1 << 31)) {
+        delete c;
+        return MSM_ERR_CAPACITY;
+    }
+    size_t bytes = 0;
+    if (prm->precision == MSM_FP32) carve<float>(c, c->wf, nullptr, &bytes, false);
+    else carve<double>(c, c->wd, nullptr, &bytes, false);
+    if (hipMalloc((void **)&c->wbuf, bytes) != hipSuccess) {
+        delete c;
+        return MSM_ERR_HIP;
+    }
+    c->wbytes = bytes;
+    if (prm->precision == MSM_FP32) carve<float>(c, c->wf, c->wbuf, &bytes, true);
+    else carve<double>(c, c->wd, c->wbuf, &bytes, true);
+
+    // zero everything once: the halos of the charge grids are never written
+    if (hipMemsetAsync(c->wbuf, 0, c->wbytes, c->stream) != hipSuccess) {
+        msm_destroy(c);
+        return MSM_ERR_HIP;
+    }
+    if (prm->precision == MSM_FP32) {
+        auto w = stencil_table<float>(prm->a, prm->h, reach, c->d2max);
+        if (hipMalloc(&c->weights, w.size() * sizeof(float)) != hipSuccess ||
+            hipMemcpy(c->weights, w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+            msm_destroy(c);
+            return MSM_ERR_HIP;
+        }
+    } else {
+        auto w = stencil_table<double>(prm->a, prm->h, reach, c->d2max);
+        if (hipMalloc(&c->weights, w.size() * sizeof(double)) != hipSuccess ||
+            hipMemcpy(c->weights, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
+            msm_destroy(c);
+            return MSM_ERR_HIP;
+        }
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+        msm_destroy(c);
+        return MSM_ERR_HIP;
+    }
+    *out = c;
+    return MSM_OK;
+}
+
+void msm_destroy(msm_ctx *c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    if (c->wbuf) (void)hipFree(c->wbuf);
+    if (c->weights) (void)hipFree(c->weights);
+    if (c->plan_dev) (void)hipFree(c->plan_dev);
+    if (c->plan_host) (void)hipHostFree(c->plan_host);
+    delete c;
+}
+
+int msm_set_stream(msm_ctx *c, void *stream)
+{
+    if (!c) return MSM_ERR_ARG;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
+    c->stream = (hipStream_t)stream;
+    return MSM_OK;
+}
+
+int msm_energy_forces(msm_ctx *c, int nsys, const int64_t *offsets, const double *domains, const void *xyzq,
+                      double *energy, void *forces, void *pots)
+{
+    if (!c || nsys < 1 || !offsets) return MSM_ERR_ARG;
+    if (nsys > c->prm.max_systems) return MSM_ERR_CAPACITY;
+    if (offsets[nsys] > 0 && !xyzq) return MSM_ERR_ARG;
+    int rc = build_plan(c, nsys, offsets, domains);
+    if (rc) return rc;
+    if (c->prm.precision == MSM_FP32) return evaluate<float>(c, xyzq, energy, forces, pots);
+    return evaluate<double>(c, xyzq, energy, forces, pots);
+}
+
+int msm_get_status(msm_ctx *c)
+{
+    if (!c) return MSM_ERR_ARG;
+    int *st = c->prm.precision == MSM_FP32 ? c->wf.status : c->wd.status;
+    int v = 0;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
+    if (hipMemcpy(&v, st, sizeof(int), hipMemcpyDeviceToHost) != hipSuccess) return MSM_ERR_HIP;
+    if (v) {
+        if (fill_i32(c->stream, st, 1, 0) != hipSuccess) return MSM_ERR_HIP;
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
+    }
+    if (v & kStatusNonFinite) return MSM_ERR_NONFINITE;
+    if (v & kStatusDomain) return MSM_ERR_DOMAIN;
+    return MSM_OK;
+}
+
+int msm_grid_shape(const msm_ctx *c, const double *domain, int *org, int *dim)
+{
+    if (!c || !org || !dim) return MSM_ERR_ARG;
+    Geometry g;
+    int rc = geometry(c->prm, domain ? domain : c->prm.lo, domain ? domain + 3 : c->prm.hi, g);
+    if (rc) return rc;
+    for (int k = 0; k < g.nlev; k++)
+        for (int d = 0; d < 3; d++) {
+            org[3 * k + d] = g.gorg[k][d];
+            dim[3 * k + d] = g.gdim[k][d];
+        }
+    return g.nlev;
+}
+
+int msm_debug_stages(msm_ctx *c, int sys, double *u_short, double *f_short, double *const *qg,
+                     double *const *ucut, double *const *ug)
+{
+    if (!c || !c->plan_valid || sys < 0 || sys >= c->dp.nsys) return MSM_ERR_ARG;
+    hipError_t e = c->prm.precision == MSM_FP32
+                       ? Launch<float>::stage_copy(c->stream, c->dp, c->wf, sys, u_short, f_short, qg, ucut, ug)
+                       : Launch<double>::stage_copy(c->stream, c->dp, c->wd, sys, u_short, f_short, qg, ucut, ug);
+    return hip_status(e);
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+// Host-side launchers of the HIP kernels (one translation unit per kernel
+// family); every launcher enqueues on the given stream and returns the launch
+// status.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace msmx {
+
+// Read-only tables of one evaluation, resident in device memory.
+struct DevPlan {
+    const SysPlan *sys;          // nsys plans
+    int nsys;
+    const int64_t *atom_prefix;  // nsys+1: atom offsets
+    const int64_t *group_prefix; // nsys+1: 64-atom pair groups
+    const int64_t *cell_prefix;  // nsys+1: brick-major cells
+    const int64_t *node_prefix;  // kMaxLevels x (nsys+1): level-k nodes per system
+    const int64_t *iblk_prefix;  // nsys+1: interpolation blocks per system
+    const int64_t *sten_prefix;  // kMaxLevels x (nsys+1): stencil threads (columns x z-blocks)
+    const int64_t *top_prefix;   // nsys+1: top-level nodes per system
+    int64_t natoms, ngroups, ncells, niblk, ntop;
+    int64_t nnodes[kMaxLevels];  // level-k nodes over the batch
+    int64_t nsten[kMaxLevels];   // level-k stencil threads over the batch
+    int maxlev;                  // largest level count in the batch
+};
+
+// Scratch arrays owned by the context.
+template <typename T> struct Work {
+    int *cell_of;        // per input atom: brick-major cell (batch-global)
+    int *slot_of;        // per input atom: arrival slot within its cell
+    int *cell_start;     // ncells + 1: exclusive scan of cell counts
+    int *scan_blocks;    // block sums of the scan
+    int *order;          // sorted position -> input atom
+    vec4_t<T> *sxyzq;    // atoms in sorted order
+    vec4_t<T> *shrt;     // sorted order: (bracket of F^short, u^short)
+    T *qgrid;            // padded charge grids, all levels and systems
+    T *ucut;             // lattice-cutoff potentials (top level: u^{l-1})
+    T *ugrid;            // prolongated potentials u^k
+    double *eparts;      // per interpolation block: sum q_i phi_i
+    int *status;         // device status word
+};
+
+struct MethodConst {
+    double a, h, ke;
+    int reach;                 // stencil reach R: largest integer with R < 2a/h
+};
+
+int scan_cells(hipStream_t s, int *counts_to_start, int64_t n, int *block_sums);
+
+template <typename T> struct Launch {
+    static hipError_t bin(hipStream_t s, const DevPlan &p, const Work<T> &w, const vec4_t<T> *xyzq);
+    static hipError_t pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m);
+    static hipError_t anterp(hipStream_t s, const DevPlan &p, const Work<T> &w);
+    static hipError_t restrict_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k);
+    static hipError_t stencil_level(hipStream_t s, const DevPlan &p, const Work<T> &w,
+                                    const T *weights, int reach, int r2max, int k);
+    static hipError_t top_level(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m);
+    static hipError_t prolong_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k);
+    static hipError_t interp(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m,
+                             T *forces, T *potentials);
+    static hipError_t energy(hipStream_t s, const DevPlan &p, const Work<T> &w, double *energy);
+    static hipError_t stage_copy(hipStream_t s, const DevPlan &p, const Work<T> &w, int sys,
+                                 double *u_short, double *f_short, double *const *qg,
+                                 double *const *ucut, double *const *ug);
+};
+
+hipError_t fill_i32(hipStream_t s, int *p, int64_t n, int v);
+template <typename T> hipError_t fill_t(hipStream_t s, T *p, int64_t n, T v);
+
+}  // namespace msmx

@@ -1,0 +1,619 @@
+// HIP kernels of one multilevel summation evaluation (Section 3), templated
+// on the arithmetic type T (float or double). Every kernel works on all
+// systems of a batch in one launch; a thread or wave finds its system by a
+// binary search of a prefix table.
+#include "launch.h"
+
+namespace msmx {
+
+namespace {
+
+inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// Broadcast lane 0's value to the whole wave as a scalar (the value must
+// already be uniform); lets the compiler keep loop bounds and the j-atom
+// loads of the pair kernel in scalar registers.
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ inline double uni(double v)
+{
+    int64_t b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+    int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+
+template <typename T> __device__ inline T wave_min(T v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+template <typename T> __device__ inline T wave_max(T v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+template <typename T> __device__ inline int cell_floor(T t, int nc)
+{
+    // floor, clamped to the cell range; NaN maps to 0
+    if (!(t >= T(0))) return 0;
+    int c = (int)floor(t);
+    return c > nc - 1 ? nc - 1 : c;
+}
+
+// ---------------------------------------------------------------------------
+// Short-range part (Section 3): u_i^short = sum_{j != i, r < a} g*(r_ij) q_j with
+// g*(r) = 1/r - gamma(r/a)/a, and the force bracket
+// b_i = sum_j q_j (-dg*/dr / r)(r_i - r_j) = sum_j q_j (1/r^3 - (5/2 - 3/2 rho^2)/a^3)(r_i - r_j),
+// so that F_i^short = k q_i b_i.
+//
+// One wave owns 64 consecutive sorted atoms (a compact group, one per lane).
+// It walks the cell rows that intersect the group's bounding box grown by a,
+// each row clipped to the chord the cutoff sphere leaves it, and streams the
+// candidate j atoms as wave-uniform scalars: each lane tests its own pair.
+// Every pair is evaluated from both sides, so no atomics are needed and the
+// summation order is fixed.
+// ---------------------------------------------------------------------------
+template <typename T> struct PairK {
+    T a2;            // a^2
+    T reach;         // a plus a rounding margin, for the row search
+    T inv_a2;        // 1/a^2
+    T c0, c1, c2;    // gamma(rho)/a = c0 + c1 rho^2 + c2 rho^4
+    T d0, d1;        // -gamma'(rho)/(a^2 rho) / a ... = d0 + d1 rho^2 (force bracket term)
+};
+
+template <typename T>
+__global__ __launch_bounds__(64) void k_pair(DevPlan p, const vec4_t<T> *__restrict__ sx,
+                                             const int *__restrict__ cstart, vec4_t<T> *__restrict__ out,
+                                             PairK<T> k)
+{
+    const int64_t g = blockIdx.x;
+    const int s = find_segment(p.group_prefix, p.nsys, g);
+    const SysPlan &P = p.sys[s];
+    const int64_t first = P.atom0 + (g - p.group_prefix[s]) * kWave;
+    const int64_t end = P.atom0 + P.natoms;
+    const int lane = threadIdx.x;
+    const int64_t i = first + lane;
+    const bool valid = i < end;
+    const vec4_t<T> ai = sx[valid ? i : first];
+
+    const T bminx = uni(wave_min(ai.x)), bmaxx = uni(wave_max(ai.x));
+    const T bminy = uni(wave_min(ai.y)), bmaxy = uni(wave_max(ai.y));
+    const T bminz = uni(wave_min(ai.z)), bmaxz = uni(wave_max(ai.z));
+    const T lox = T(P.lo[0]), loy = T(P.lo[1]), loz = T(P.lo[2]);
+    const T inv_h = T(P.inv_h), h = T(1.0 / P.inv_h);
+    const int ncx = P.nc[0], ncy = P.nc[1], ncz = P.nc[2];
+    const T reach = k.reach, reach2 = k.reach * k.reach;
+
+    const int cy0 = clampi((int)floor((bminy - loy - reach) * inv_h), 0, ncy - 1);
+    const int cy1 = clampi((int)floor((bmaxy - loy + reach) * inv_h), 0, ncy - 1);
+    const int cz0 = clampi((int)floor((bminz - loz - reach) * inv_h), 0, ncz - 1);
+    const int cz1 = clampi((int)floor((bmaxz - loz + reach) * inv_h), 0, ncz - 1);
+
+    T fx = 0, fy = 0, fz = 0, u = 0;
+    for (int cz = cz0; cz <= cz1; ++cz) {
+        const T z0 = loz + T(cz) * h;
+        const T dz = fmax(T(0), fmax(z0 - bmaxz, bminz - (z0 + h)));
+        for (int cy = cy0; cy <= cy1; ++cy) {
+            const T y0 = loy + T(cy) * h;
+            const T dy = fmax(T(0), fmax(y0 - bmaxy, bminy - (y0 + h)));
+            const T rem = reach2 - dy * dy - dz * dz;
+            if (rem <= T(0)) continue;
+            const T wdt = sqrt(rem);
+            const int cx0 = clampi((int)floor((bminx - lox - wdt) * inv_h), 0, ncx - 1);
+            const int cx1 = clampi((int)floor((bmaxx - lox + wdt) * inv_h), 0, ncx - 1);
+            for (int bx = cx0 / kBrick; bx <= cx1 / kBrick; ++bx) {
+                const int ca = max(cx0, bx * kBrick);
+                const int cb = min(cx1, bx * kBrick + kBrick - 1);
+                const int64_t r0 = P.cell0 + cell_rank(P, ca, cy, cz);
+                const int jb = uni(cstart[r0]);
+                const int je = uni(cstart[r0 + (cb - ca) + 1]);
+                for (int j = jb; j < je; ++j) {
+                    const vec4_t<T> aj = sx[j];
+                    const T dx = ai.x - aj.x, ddy = ai.y - aj.y, ddz = ai.z - aj.z;
+                    const T r2 = dx * dx + ddy * ddy + ddz * ddz;
+                    if (r2 < k.a2 && r2 > T(0)) {
+                        const T rinv = rsqrt_t(r2);
+                        const T rho2 = r2 * k.inv_a2;
+                        const T gs = rinv - (k.c0 + rho2 * (k.c1 + rho2 * k.c2));
+                        const T br = rinv * rinv * rinv - (k.d0 + k.d1 * rho2);
+                        u += aj.w * gs;
+                        const T t = aj.w * br;
+                        fx += t * dx;
+                        fy += t * ddy;
+                        fz += t * ddz;
+                    }
+                }
+            }
+        }
+    }
+    if (valid) {
+        vec4_t<T> o;
+        o.x = fx;
+        o.y = fy;
+        o.z = fz;
+        o.w = u;
+        out[i] = o;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Anterpolation (Section 3): q^0_mu = sum_j phi^0_mu(r_j) q_j. Gather form:
+// one thread per level-0 node sums over the atoms of the 4x4x4 cells whose
+// support covers it (cells mu-2 .. mu+1 per axis), so no atomics are needed.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__restrict__ sx,
+                                                const int *__restrict__ cstart, T *__restrict__ qgrid)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= p.nnodes[0]) return;
+    const int64_t *pref = p.node_prefix;
+    const int s = find_segment(pref, p.nsys, g);
+    const SysPlan &P = p.sys[s];
+    const int64_t loc = g - pref[s];
+    const int dx = P.gdim[0][0], dy = P.gdim[0][1];
+    const int rx = (int)(loc % dx), ry = (int)((loc / dx) % dy), rz = (int)(loc / ((int64_t)dx * dy));
+    const int ix = rx + P.gorg[0][0], iy = ry + P.gorg[0][1], iz = rz + P.gorg[0][2];
+    const T lox = T(P.lo[0]), loy = T(P.lo[1]), loz = T(P.lo[2]), inv_h = T(P.inv_h);
+    const int cx0 = max(ix - 2, 0), cx1 = min(ix + 1, P.nc[0] - 1);
+    T acc = 0;
+    for (int cz = max(iz - 2, 0); cz <= min(iz + 1, P.nc[2] - 1); ++cz)
+        for (int cy = max(iy - 2, 0); cy <= min(iy + 1, P.nc[1] - 1); ++cy)
+            for (int bx = cx0 / kBrick; cx0 <= cx1 && bx <= cx1 / kBrick; ++bx) {
+                const int ca = max(cx0, bx * kBrick), cb = min(cx1, bx * kBrick + kBrick - 1);
+                const int64_t r0 = P.cell0 + cell_rank(P, ca, cy, cz);
+                const int jb = cstart[r0], je = cstart[r0 + (cb - ca) + 1];
+                for (int j = jb; j < je; ++j) {
+                    const vec4_t<T> a = sx[j];
+                    const T tx = (a.x - lox) * inv_h, ty = (a.y - loy) * inv_h, tz = (a.z - loz) * inv_h;
+                    acc += basis(tx - T(ix)) * basis(ty - T(iy)) * basis(tz - T(iz)) * a.w;
+                }
+            }
+    const int PX = padded_x(dx), PY = padded_x(dy);
+    qgrid[P.qoff[0] + ((int64_t)(rz + kGridPad) * PY + (ry + kGridPad)) * PX + (rx + kGridPad)] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Restriction (Section 3): q^{k+1}_mu = sum_nu phi^{k+1}_mu(r^k_nu) q^k_nu.
+// Level-k node nu sits at coarse coordinate nu/2, so the weight is
+// prod_d Phi((nu_d - 2 mu_d)/2): per axis -1/16, 9/16, 1, 9/16, -1/16 at
+// offsets -3, -1, 0, 1, 3. The zero halo of the fine grid stands in for nodes
+// outside its range.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict(DevPlan p, T *__restrict__ qgrid, int k)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= p.nnodes[k + 1]) return;
+    const int64_t *pref = p.node_prefix + (int64_t)(k + 1) * (p.nsys + 1);
+    const int s = find_segment(pref, p.nsys, g);
+    const SysPlan &P = p.sys[s];
+    if (k + 1 >= P.nlev) return;
+    const int64_t loc = g - pref[s];
+    const int cdx = P.gdim[k + 1][0], cdy = P.gdim[k + 1][1];
+    const int rx = (int)(loc % cdx), ry = (int)((loc / cdx) % cdy), rz = (int)(loc / ((int64_t)cdx * cdy));
+    // fine-grid relative index of the coincident node 2 mu
+    const int fx = 2 * (rx + P.gorg[k + 1][0]) - P.gorg[k][0];
+    const int fy = 2 * (ry + P.gorg[k + 1][1]) - P.gorg[k][1];
+    const int fz = 2 * (rz + P.gorg[k + 1][2]) - P.gorg[k][2];
+    const int FX = padded_x(P.gdim[k][0]), FY = padded_x(P.gdim[k][1]);
+    const T *qf = qgrid + P.qoff[k];
+    const int off[5] = {-3, -1, 0, 1, 3};
+    const T wt[5] = {basis(T(-1.5)), basis(T(-0.5)), T(1), basis(T(0.5)), basis(T(1.5))};
+    T acc = 0;
+    for (int c = 0; c < 5; ++c) {
+        const int64_t zrow = (int64_t)(fz + off[c] + kGridPad) * FY;
+        T accy = 0;
+        for (int b = 0; b < 5; ++b) {
+            const T *row = qf + (zrow + (fy + off[b] + kGridPad)) * FX + (fx + kGridPad);
+            T accx = 0;
+            for (int a = 0; a < 5; ++a) accx += wt[a] * row[off[a]];
+            accy += wt[b] * accx;
+        }
+        acc += wt[c] * accy;
+    }
+    const int CX = padded_x(cdx), CY = padded_x(cdy);
+    qgrid[P.qoff[k + 1] + ((int64_t)(rz + kGridPad) * CY + (ry + kGridPad)) * CX + (rx + kGridPad)] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Lattice cutoff on level k < l-1 (Section 3): u^{k,cutoff}_mu =
+// sum_nu g^k(r^k_mu, r^k_nu) q^k_nu. On level k the node distance is 2^k h |o|,
+// and g^k(2^k h |o|) = 2^{-k} g^0(h |o|), so one table W[o] = g^0(h |o|),
+// zero for |o| >= 2a/h, serves every level with an exact power-of-two scale.
+// A thread owns kStencilZ consecutive z outputs of one (x, y) column and, for
+// each (ox, oy) column of the stencil, loads the z-line of charges once into
+// registers and applies the 2R+1 weights of that column to all its outputs.
+// ---------------------------------------------------------------------------
+template <typename T, int R>
+__global__ __launch_bounds__(256) void k_stencil(DevPlan p, const T *__restrict__ qgrid, T *__restrict__ ucut,
+                                                 const T *__restrict__ W, int k, int r2max)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= p.nsten[k]) return;
+    const int64_t *pref = p.sten_prefix + (int64_t)k * (p.nsys + 1);
+    const int s = find_segment(pref, p.nsys, g);
+    const SysPlan &P = p.sys[s];
+    if (k >= P.nlev - 1) return;
+    const int64_t loc = g - pref[s];
+    const int dx = P.gdim[k][0], dy = P.gdim[k][1], dz = P.gdim[k][2];
+    const int x = (int)(loc % dx), y = (int)((loc / dx) % dy), zb = (int)(loc / ((int64_t)dx * dy));
+    const int z0 = zb * kStencilZ;
+    const int PX = padded_x(dx), PY = padded_x(dy);
+    const int64_t zs = (int64_t)PX * PY;
+    const T *q = qgrid + P.qoff[k];
+    constexpr int D = 2 * R + 1;
+    constexpr int L = kStencilZ + 2 * R;
+    T acc[kStencilZ];
+#pragma unroll
+    for (int t = 0; t < kStencilZ; ++t) acc[t] = T(0);
+    for (int oy = -R; oy <= R; ++oy) {
+        for (int ox = -R; ox <= R; ++ox) {
+            if (ox * ox + oy * oy > r2max) continue;
+            const T *col = q + (int64_t)(z0 + kGridPad - R) * zs + (int64_t)(y + kGridPad + oy) * PX + (x + kGridPad + ox);
+            T line[L];
+#pragma unroll
+            for (int t = 0; t < L; ++t) line[t] = col[t * zs];
+            const T *wc = W + ((oy + R) * D + (ox + R)) * D;
+#pragma unroll
+            for (int oz = 0; oz < D; ++oz) {
+                const T wv = wc[oz];
+#pragma unroll
+                for (int t = 0; t < kStencilZ; ++t) acc[t] += wv * line[t + oz];
+            }
+        }
+    }
+    const T scale = T(ldexp(1.0, -k));
+    T *u = ucut + P.uoff[k];
+#pragma unroll
+    for (int t = 0; t < kStencilZ; ++t)
+        if (z0 + t < dz) u[((int64_t)(z0 + t) * dy + y) * dx + x] = acc[t] * scale;
+}
+
+// ---------------------------------------------------------------------------
+// Top level (Section 3): u^{l-1}_mu = sum_nu g^{l-1}(r_mu, r_nu) q^{l-1}_nu over
+// all node pairs, g^{l-1}(r) = gamma(r / (2^{l-1} a)) / (2^{l-1} a). The grid
+// is at most a few hundred nodes; each thread sums over all of them.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_top(DevPlan p, const T *__restrict__ qgrid, T *__restrict__ ucut,
+                                             T *__restrict__ ugrid, double h, double a)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= p.ntop) return;
+    const int s = find_segment(p.top_prefix, p.nsys, g);
+    const SysPlan &P = p.sys[s];
+    const int k = P.nlev - 1;
+    const int64_t loc = g - p.top_prefix[s];
+    const int dx = P.gdim[k][0], dy = P.gdim[k][1], dz = P.gdim[k][2];
+    const int x = (int)(loc % dx), y = (int)((loc / dx) % dy), z = (int)(loc / ((int64_t)dx * dy));
+    const int PX = padded_x(dx), PY = padded_x(dy);
+    const T *q = qgrid + P.qoff[k];
+    const T hk = T(ldexp(h, k)), ak = T(ldexp(a, k)), inv_ak = T(1) / ak;
+    T acc = 0;
+    for (int nz = 0; nz < dz; ++nz)
+        for (int ny = 0; ny < dy; ++ny) {
+            const T *row = q + ((int64_t)(nz + kGridPad) * PY + (ny + kGridPad)) * PX + kGridPad;
+            const int ez = nz - z, ey = ny - y;
+            for (int nx = 0; nx < dx; ++nx) {
+                const int ex = nx - x;
+                const T r = hk * sqrt(T(ex * ex + ey * ey + ez * ez));
+                acc += gamma_s(r * inv_ak) * inv_ak * row[nx];
+            }
+        }
+    const int64_t o = P.uoff[k] + ((int64_t)z * dy + y) * dx + x;
+    ucut[o] = acc;
+    ugrid[o] = acc;
+}
+
+// ---------------------------------------------------------------------------
+// Prolongation (Section 3): u^k_mu = u^{k,cutoff}_mu + sum_nu phi^{k+1}_nu(r^k_mu) u^{k+1}_nu,
+// the transpose of restriction. Per axis an even fine index 2n takes the
+// coarse node n with weight 1; an odd index 2n+1 takes n-1, n, n+1, n+2 with
+// -1/16, 9/16, 9/16, -1/16.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong(DevPlan p, const T *__restrict__ ucut, T *__restrict__ ugrid,
+                                                 int k)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= p.nnodes[k]) return;
+    const int64_t *pref = p.node_prefix + (int64_t)k * (p.nsys + 1);
+    const int s = find_segment(pref, p.nsys, g);
+    const SysPlan &P = p.sys[s];
+    if (k >= P.nlev - 1) return;
+    const int64_t loc = g - pref[s];
+    const int dx = P.gdim[k][0], dy = P.gdim[k][1];
+    const int r[3] = {(int)(loc % dx), (int)((loc / dx) % dy), (int)(loc / ((int64_t)dx * dy))};
+    int cn[3][4];
+    T cw[3][4];
+    int cnt[3];
+    for (int d = 0; d < 3; ++d) {
+        const int m = r[d] + P.gorg[k][d];          // absolute fine index
+        const int c0 = P.gorg[k + 1][d];
+        if ((m & 1) == 0) {
+            cnt[d] = 1;
+            cn[d][0] = (m >> 1) - c0;
+            cw[d][0] = T(1);
+        } else {
+            const int n = (m - 1) >> 1;             // floor(m/2)
+            cnt[d] = 4;
+            cn[d][0] = n - 1 - c0; cw[d][0] = basis(T(1.5));
+            cn[d][1] = n - c0;     cw[d][1] = basis(T(0.5));
+            cn[d][2] = n + 1 - c0; cw[d][2] = basis(T(-0.5));
+            cn[d][3] = n + 2 - c0; cw[d][3] = basis(T(-1.5));
+        }
+    }
+    const int cdx = P.gdim[k + 1][0], cdy = P.gdim[k + 1][1];
+    const T *uc = ugrid + P.uoff[k + 1];
+    T acc = 0;
+    for (int c = 0; c < cnt[2]; ++c) {
+        T accy = 0;
+        for (int b = 0; b < cnt[1]; ++b) {
+            const T *row = uc + ((int64_t)cn[2][c] * cdy + cn[1][b]) * cdx;
+            T accx = 0;
+            for (int a = 0; a < cnt[0]; ++a) accx += cw[0][a] * row[cn[0][a]];
+            accy += cw[1][b] * accx;
+        }
+        acc += cw[2][c] * accy;
+    }
+    const int64_t o = P.uoff[k] + loc;
+    ugrid[o] = ucut[o] + acc;
+}
+
+// ---------------------------------------------------------------------------
+// Interpolation (Section 3): u_i^long = sum_mu phi^0_mu(r_i) u^0_mu, with the
+// analytic gradient, and the combination into the outputs:
+// phi_i = k (u_i^short + u_i^long - q_i gamma(0)/a), F_i = k q_i (b_i - grad u_i^long),
+// written in the caller's atom order; each block also adds up q_i phi_i in
+// double for the energy, in a fixed order.
+// ---------------------------------------------------------------------------
+constexpr int kInterpThreads = 256;
+
+template <typename T>
+__global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4_t<T> *__restrict__ sx,
+                                                           const vec4_t<T> *__restrict__ shrt,
+                                                           const int *__restrict__ order,
+                                                           const T *__restrict__ ugrid, T *__restrict__ forces,
+                                                           T *__restrict__ potentials, double *__restrict__ eparts,
+                                                           T ke, T self)
+{
+    __shared__ double red[kInterpThreads];
+    const int64_t blk = blockIdx.x;
+    const int s = find_segment(p.iblk_prefix, p.nsys, blk);
+    const SysPlan &P = p.sys[s];
+    const int64_t pos = P.atom0 + (blk - p.iblk_prefix[s]) * kInterpThreads + threadIdx.x;
+    double e = 0;
+    if (pos < P.atom0 + P.natoms) {
+        const vec4_t<T> a = sx[pos];
+        const T inv_h = T(P.inv_h);
+        const T t[3] = {(a.x - T(P.lo[0])) * inv_h, (a.y - T(P.lo[1])) * inv_h, (a.z - T(P.lo[2])) * inv_h};
+        T w[3][4], dw[3][4];
+        int base[3];
+        for (int d = 0; d < 3; ++d) {
+            base[d] = cell_floor(t[d], P.nc[d]);
+            for (int m = 0; m < 4; ++m) {
+                const T o = t[d] - T(base[d] - 1 + m);
+                w[d][m] = basis(o);
+                dw[d][m] = dbasis(o) * inv_h;
+            }
+        }
+        const int dx = P.gdim[0][0], dy = P.gdim[0][1];
+        const T *u0 = ugrid + P.uoff[0];
+        T ul = 0, gx = 0, gy = 0, gz = 0;
+        for (int mz = 0; mz < 4; ++mz) {
+            for (int my = 0; my < 4; ++my) {
+                const T *row = u0 + ((int64_t)(base[2] - 1 + mz - P.gorg[0][2]) * dy + (base[1] - 1 + my - P.gorg[0][1])) * dx +
+                               (base[0] - 1 - P.gorg[0][0]);
+                T sx0 = 0, sdx = 0;
+                for (int mx = 0; mx < 4; ++mx) {
+                    const T v = row[mx];
+                    sx0 += w[0][mx] * v;
+                    sdx += dw[0][mx] * v;
+                }
+                const T wyz = w[1][my] * w[2][mz];
+                ul += wyz * sx0;
+                gx += wyz * sdx;
+                gy += dw[1][my] * w[2][mz] * sx0;
+                gz += w[1][my] * dw[2][mz] * sx0;
+            }
+        }
+        const vec4_t<T> sr = shrt[pos];
+        const T phi = ke * (sr.w + ul - a.w * self);
+        const int64_t o = order[pos];
+        if (potentials) potentials[o] = phi;
+        if (forces) {
+            const T kq = ke * a.w;
+            forces[3 * o + 0] = kq * (sr.x - gx);
+            forces[3 * o + 1] = kq * (sr.y - gy);
+            forces[3 * o + 2] = kq * (sr.z - gz);
+        }
+        e = (double)a.w * (double)phi;
+    }
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int off = kInterpThreads / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) eparts[blk] = red[0];
+}
+
+// U = 1/2 sum_i q_i phi_i per system, from the block partial sums in block order.
+__global__ void k_energy(DevPlan p, const double *__restrict__ eparts, double *__restrict__ energy)
+{
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= p.nsys) return;
+    double acc = 0;
+    for (int64_t b = p.iblk_prefix[s]; b < p.iblk_prefix[s + 1]; ++b) acc += eparts[b];
+    energy[s] = 0.5 * acc;
+}
+
+template <typename T>
+__global__ void k_stage_atoms(const SysPlan *sys, int s, const vec4_t<T> *__restrict__ shrt,
+                              const int *__restrict__ order, double *u_short, double *f_short)
+{
+    const SysPlan &P = sys[s];
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= P.natoms) return;
+    const int64_t pos = P.atom0 + i;
+    const int64_t o = order[pos] - P.atom0;
+    const vec4_t<T> v = shrt[pos];
+    if (u_short) u_short[o] = (double)v.w;
+    if (f_short) {
+        f_short[3 * o] = (double)v.x;
+        f_short[3 * o + 1] = (double)v.y;
+        f_short[3 * o + 2] = (double)v.z;
+    }
+}
+
+template <typename T>
+__global__ void k_stage_grid(const SysPlan *sys, int s, int k, const T *__restrict__ src, int padded,
+                             double *__restrict__ dst)
+{
+    const SysPlan &P = sys[s];
+    const int dx = P.gdim[k][0], dy = P.gdim[k][1], dz = P.gdim[k][2];
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= (int64_t)dx * dy * dz) return;
+    const int x = (int)(i % dx), y = (int)((i / dx) % dy), z = (int)(i / ((int64_t)dx * dy));
+    if (padded) {
+        const int PX = padded_x(dx), PY = padded_x(dy);
+        dst[i] = (double)src[P.qoff[k] + ((int64_t)(z + kGridPad) * PY + (y + kGridPad)) * PX + (x + kGridPad)];
+    } else {
+        dst[i] = (double)src[P.uoff[k] + i];
+    }
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m)
+{
+    if (p.ngroups == 0) return hipSuccess;
+    PairK<T> k;
+    const double a = m.a;
+    k.a2 = T(a * a);
+    k.reach = T(a * (1.0 + 1e-5));
+    k.inv_a2 = T(1.0 / (a * a));
+    k.c0 = T(1.875 / a);
+    k.c1 = T(-1.25 / a);
+    k.c2 = T(0.375 / a);
+    // -(d/dr)(gamma(r/a)/a) / r = (5/2 - 3/2 rho^2) / a^3, entering with a minus sign
+    k.d0 = T(2.5 / (a * a * a));
+    k.d1 = T(-1.5 / (a * a * a));
+    hipLaunchKernelGGL(k_pair<T>, dim3((unsigned)p.ngroups), dim3(kWave), 0, s, p, w.sxyzq, w.cell_start, w.shrt, k);
+    return hipGetLastError();
+}
+
+template <typename T> hipError_t Launch<T>::anterp(hipStream_t s, const DevPlan &p, const Work<T> &w)
+{
+    if (p.nnodes[0] == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_anterp<T>, dim3(nblocks(p.nnodes[0], 256)), dim3(256), 0, s, p, w.sxyzq, w.cell_start,
+                       w.qgrid);
+    return hipGetLastError();
+}
+
+template <typename T> hipError_t Launch<T>::restrict_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k)
+{
+    if (p.nnodes[k + 1] == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_restrict<T>, dim3(nblocks(p.nnodes[k + 1], 256)), dim3(256), 0, s, p, w.qgrid, k);
+    return hipGetLastError();
+}
+
+template <typename T, int R>
+static hipError_t stencil_r(hipStream_t s, const DevPlan &p, const Work<T> &w, const T *W, int k, int r2max)
+{
+    hipLaunchKernelGGL((k_stencil<T, R>), dim3(nblocks(p.nsten[k], 256)), dim3(256), 0, s, p, w.qgrid, w.ucut, W, k,
+                       r2max);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::stencil_level(hipStream_t s, const DevPlan &p, const Work<T> &w, const T *W, int reach,
+                                    int r2max, int k)
+{
+    if (p.nsten[k] == 0) return hipSuccess;
+    // r2max is the largest |o|^2 inside the sphere: columns (ox, oy) with
+    // ox^2 + oy^2 > r2max hold only zero weights and are skipped
+    switch (reach) {
+    case 1: return stencil_r<T, 1>(s, p, w, W, k, r2max);
+    case 2: return stencil_r<T, 2>(s, p, w, W, k, r2max);
+    case 3: return stencil_r<T, 3>(s, p, w, W, k, r2max);
+    case 4: return stencil_r<T, 4>(s, p, w, W, k, r2max);
+    case 5: return stencil_r<T, 5>(s, p, w, W, k, r2max);
+    case 6: return stencil_r<T, 6>(s, p, w, W, k, r2max);
+    case 7: return stencil_r<T, 7>(s, p, w, W, k, r2max);
+    case 8: return stencil_r<T, 8>(s, p, w, W, k, r2max);
+    case 9: return stencil_r<T, 9>(s, p, w, W, k, r2max);
+    case 10: return stencil_r<T, 10>(s, p, w, W, k, r2max);
+    case 11: return stencil_r<T, 11>(s, p, w, W, k, r2max);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+template <typename T>
+hipError_t Launch<T>::top_level(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m)
+{
+    if (p.ntop == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_top<T>, dim3(nblocks(p.ntop, 256)), dim3(256), 0, s, p, w.qgrid, w.ucut, w.ugrid, m.h, m.a);
+    return hipGetLastError();
+}
+
+template <typename T> hipError_t Launch<T>::prolong_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k)
+{
+    if (p.nnodes[k] == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prolong<T>, dim3(nblocks(p.nnodes[k], 256)), dim3(256), 0, s, p, w.ucut, w.ugrid, k);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::interp(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m, T *forces,
+                             T *potentials)
+{
+    if (p.niblk == 0) return hipSuccess;
+    const T self = T(1.875 / m.a);   // gamma(0)/a
+    hipLaunchKernelGGL(k_interp<T>, dim3((unsigned)p.niblk), dim3(kInterpThreads), 0, s, p, w.sxyzq, w.shrt, w.order,
+                       w.ugrid, forces, potentials, w.eparts, T(m.ke), self);
+    return hipGetLastError();
+}
+
+template <typename T> hipError_t Launch<T>::energy(hipStream_t s, const DevPlan &p, const Work<T> &w, double *energy)
+{
+    if (!energy) return hipSuccess;
+    hipLaunchKernelGGL(k_energy, dim3(nblocks(p.nsys, 64)), dim3(64), 0, s, p, w.eparts, energy);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::stage_copy(hipStream_t s, const DevPlan &p, const Work<T> &w, int sys, double *u_short,
+                                 double *f_short, double *const *qg, double *const *ucut, double *const *ug)
+{
+    // host copy of the plan of this system, for the launch sizes
+    SysPlan P;
+    hipError_t e = hipMemcpyAsync(&P, p.sys + sys, sizeof(SysPlan), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if ((u_short || f_short) && P.natoms > 0)
+        hipLaunchKernelGGL(k_stage_atoms<T>, dim3(nblocks(P.natoms, 256)), dim3(256), 0, s, p.sys, sys, w.shrt,
+                           w.order, u_short, f_short);
+    for (int k = 0; k < P.nlev; ++k) {
+        const int64_t n = (int64_t)P.gdim[k][0] * P.gdim[k][1] * P.gdim[k][2];
+        if (qg && qg[k])
+            hipLaunchKernelGGL(k_stage_grid<T>, dim3(nblocks(n, 256)), dim3(256), 0, s, p.sys, sys, k, w.qgrid, 1, qg[k]);
+        if (ucut && ucut[k])
+            hipLaunchKernelGGL(k_stage_grid<T>, dim3(nblocks(n, 256)), dim3(256), 0, s, p.sys, sys, k, w.ucut, 0, ucut[k]);
+        if (ug && ug[k])
+            hipLaunchKernelGGL(k_stage_grid<T>, dim3(nblocks(n, 256)), dim3(256), 0, s, p.sys, sys, k, w.ugrid, 0, ug[k]);
+    }
+    return hipGetLastError();
+}
+
+template struct Launch<float>;
+template struct Launch<double>;
+
+}  // namespace msmx
