@@ -128,6 +128,27 @@ int msm_debug_stages(msm_ctx *ctx, int sys, double *u_short_dev, double *f_short
                      double *const *q_grid_dev, double *const *ucut_grid_dev,
                      double *const *u_grid_dev);
 
+/* Stages of one evaluation, for msm_stage_timing. */
+enum {
+    MSM_STAGE_BIN = 0,       /* counting sort of atoms into cells */
+    MSM_STAGE_SHORT = 1,     /* short-range pair sum */
+    MSM_STAGE_ANTERP = 2,    /* anterpolation to the finest grid */
+    MSM_STAGE_RESTRICT = 3,  /* restriction, all levels */
+    MSM_STAGE_CUTOFF = 4,    /* lattice cutoff stencils, all levels below the top */
+    MSM_STAGE_TOP = 5,       /* top-level all-pairs sum */
+    MSM_STAGE_PROLONG = 6,   /* prolongation, all levels */
+    MSM_STAGE_INTERP = 7,    /* interpolation, combination and energy reduction */
+    MSM_NSTAGES = 8
+};
+
+/* Benchmark instrumentation: while enabled, every evaluation records HIP
+ * events on the context stream around each stage and waits for the last one
+ * before returning (so enabled calls are synchronous). msm_stage_timing
+ * returns the summed milliseconds per stage (MSM_NSTAGES doubles) and the
+ * number of evaluations since the last reset; reset != 0 clears them. */
+int msm_enable_stage_timing(msm_ctx *ctx, int enable);
+int msm_stage_timing(msm_ctx *ctx, double *ms_out, int64_t *evaluations, int reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -23,4 +23,5 @@ from .loader import (  # noqa: F401
     grid_shape,
     msm,
     coulomb,
+    threads,
 )

@@ -70,6 +70,8 @@ def lib():
             L.orc_msm.argtypes = [C.POINTER(_Params), C.c_int64, _dp, _dp, _dp, _dp, _dp,
                                   C.POINTER(_Stages)]
             L.orc_coulomb.restype = C.c_int
+            L.orc_threads.restype = C.c_int
+            L.orc_threads.argtypes = []
             L.orc_coulomb.argtypes = [C.c_int64, _dp, _dp, C.c_double, _dp, _dp, _dp]
             _lib = L
         return _lib
@@ -99,6 +101,11 @@ def gstar(r, a):
 
 def glevel(r, a, k, l):
     return _vec(lambda x: lib().orc_glevel(x, float(a), int(k), int(l)))(r)
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's parallel loops use."""
+    return int(lib().orc_threads())
 
 
 def levels(p: OracleParams) -> int:

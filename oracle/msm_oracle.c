@@ -26,8 +26,12 @@
 #include "msm_oracle.h"
 
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* Threads the OpenMP loops of this library use. */
+int orc_threads(void) { return omp_get_max_threads(); }
 
 /* ---- Section 3, smoothing function gamma: even Taylor polynomial for rho < 1,
  *      1/rho beyond. ---- */

@@ -39,6 +39,7 @@ typedef struct {
     double *g_long;                /* n*3: sum_mu grad phi_mu(r_i) u^0_mu */
 } orc_stages;
 
+int orc_threads(void);
 double orc_gamma(double rho);
 double orc_dgamma(double rho);
 double orc_Phi(double t);

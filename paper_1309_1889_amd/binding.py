@@ -11,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 MSM_FP64 = 0
 MSM_FP32 = 1
 MAXLEV = 16
+STAGES = ("bin", "short", "anterp", "restrict", "cutoff", "top", "prolong", "interp")
 
 _lock = threading.Lock()
 _lib = None
@@ -59,6 +60,10 @@ def lib():
         L.msm_grid_shape.restype = C.c_int
         L.msm_debug_stages.argtypes = [vp, C.c_int, vp, vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]
         L.msm_debug_stages.restype = C.c_int
+        L.msm_enable_stage_timing.argtypes = [vp, C.c_int]
+        L.msm_enable_stage_timing.restype = C.c_int
+        L.msm_stage_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
+        L.msm_stage_timing.restype = C.c_int
         _lib = L
         return L
 
@@ -136,6 +141,16 @@ class MsmContext:
         code = self.status()
         if code != 0:
             raise MsmError(code, "device status")
+
+    def enable_stage_timing(self, enable=True):
+        _check(lib().msm_enable_stage_timing(self._h, 1 if enable else 0), "msm_enable_stage_timing")
+
+    def stage_timing(self, reset=False):
+        """Summed milliseconds per stage and the number of timed evaluations."""
+        ms = (C.c_double * len(STAGES))()
+        n = C.c_int64()
+        _check(lib().msm_stage_timing(self._h, ms, C.byref(n), 1 if reset else 0), "msm_stage_timing")
+        return dict(zip(STAGES, list(ms))), int(n.value)
 
     def grid_shape(self, domain=None):
         org = (C.c_int * (3 * MAXLEV))()

@@ -207,7 +207,7 @@ hipError_t Launch<T>::bin(hipStream_t s, const DevPlan &p, const Work<T> &w, con
     return hipGetLastError();
 }
 
-template struct Launch<float>;
-template struct Launch<double>;
+template hipError_t Launch<float>::bin(hipStream_t, const DevPlan &, const Work<float> &, const vec4_t<float> *);
+template hipError_t Launch<double>::bin(hipStream_t, const DevPlan &, const Work<double> &, const vec4_t<double> *);
 
 }  // namespace msmx

@@ -20,8 +20,9 @@ constexpr int kMaxLevels = 16;
 constexpr int kBrick = 4;            // cells per brick edge; atoms are sorted brick-major
 constexpr int kBrickCells = kBrick * kBrick * kBrick;
 constexpr int kWave = 64;            // CDNA wavefront
-constexpr int kMaxReach = 12;        // largest stencil reach ceil(2a/h) - 1 built for
-constexpr int kGridPad = kMaxReach;  // zero halo around every charge grid
+constexpr int kMaxReach = 12;        // stencil reach R (largest integer below 2a/h) is at most 11
+constexpr int kGridPad = kMaxReach;  // zero halo below every charge grid (and above, plus a tile)
+constexpr int kStencilTile = 8;      // stencil output tile edge (nodes per axis)
 
 enum StatusBits : int { kStatusDomain = 1, kStatusNonFinite = 2 };
 
@@ -44,24 +45,29 @@ struct SysPlan {
     int nlev;                // number of grids l
     int gorg[kMaxLevels][3]; // first node index per level
     int gdim[kMaxLevels][3]; // node count per level
-    int64_t qoff[kMaxLevels];// offset of the padded charge grid (pad kGridPad each side,
-                             // and kGridPad + kStencilZ extra on the high z side)
+    int64_t qoff[kMaxLevels];// offset of the padded charge grid: kGridPad zero nodes below
+                             // and kGridPad + kStencilTile above the node range on each axis
     int64_t uoff[kMaxLevels];// offset of the unpadded potential grids
     int64_t group0;          // first 64-atom pair group
     int64_t ngroups;
 };
 
-constexpr int kStencilZ = 8;         // z outputs per thread in the stencil kernel
+__host__ __device__ inline int padded_x(int d) { return d + 2 * kGridPad + kStencilTile; }
+__host__ __device__ inline int padded_z(int d) { return d + 2 * kGridPad + kStencilTile; }
 
-__host__ __device__ inline int padded_x(int d) { return d + 2 * kGridPad; }
-__host__ __device__ inline int padded_z(int d) { return d + 2 * kGridPad + kStencilZ; }
-
-// Brick-major rank of cell (cx, cy, cz) within its system.
+// Rank of cell (cx, cy, cz) within its system. Bricks of 4x4x4 cells are
+// visited in a snake order (x runs alternate direction from row to row and
+// rows alternate from plane to plane), so consecutive bricks always share a
+// face and any run of consecutive sorted atoms stays spatially compact;
+// cells inside a brick are x-fastest, so a brick row of up to 4 cells along x
+// is one contiguous range.
 __host__ __device__ inline int64_t cell_rank(const SysPlan &p, int cx, int cy, int cz)
 {
     int bx = cx / kBrick, by = cy / kBrick, bz = cz / kBrick;
     int ix = cx % kBrick, iy = cy % kBrick, iz = cz % kBrick;
-    int64_t brick = ((int64_t)bz * p.nb[1] + by) * p.nb[0] + bx;
+    int64_t row = (int64_t)bz * p.nb[1] + ((bz & 1) ? p.nb[1] - 1 - by : by);
+    int xb = (row & 1) ? p.nb[0] - 1 - bx : bx;
+    int64_t brick = row * p.nb[0] + xb;
     return brick * kBrickCells + (iz * kBrick + iy) * kBrick + ix;
 }
 

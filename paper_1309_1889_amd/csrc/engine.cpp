@@ -99,7 +99,9 @@ struct msm_ctx {
     // device memory
     char *wbuf = nullptr;
     size_t wbytes = 0;
-    void *weights = nullptr;     // stencil table W[o], precision T
+    void *weights = nullptr;     // stencil weights along z per quarter-disc column, precision T
+    int2 *wcols = nullptr;       // quarter-disc columns (ox, oy)
+    int ncols = 0;
     char *plan_dev = nullptr;    // tables of the current batch
     char *plan_host = nullptr;   // pinned staging copy
     size_t plan_cap = 0;
@@ -110,6 +112,11 @@ struct msm_ctx {
     std::vector<SysPlan> host_sys;
     Work<float> wf{};
     Work<double> wd{};
+    // stage timing (benchmarks)
+    bool timing = false;
+    hipEvent_t ev[MSM_NSTAGES + 1] = {};
+    double stage_ms[MSM_NSTAGES] = {};
+    int64_t timed_evals = 0;
 };
 
 namespace {
@@ -130,7 +137,7 @@ template <typename T> void carve(msm_ctx *c, Work<T> &w, char *base, size_t *use
     w.cell_start = (int *)take(sizeof(int) * (c->cap_cells + 1));
     w.scan_blocks = (int *)take(sizeof(int) * ((c->cap_cells + 1) / 4096 + 2));
     w.order = (int *)take(sizeof(int) * na);
-    w.sxyzq = (vec4_t<T> *)take(vec_bytes<T>() * na);
+    w.sxyzq = (vec4_t<T> *)take(vec_bytes<T>() * (na + 64));   // spare tail for the pair prefetch
     w.shrt = (vec4_t<T> *)take(vec_bytes<T>() * na);
     w.qgrid = (T *)take(sizeof(T) * c->cap_q);
     w.ucut = (T *)take(sizeof(T) * c->cap_u);
@@ -159,10 +166,10 @@ int build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double *domai
     std::vector<SysPlan> sys(nsys);
     const int W = nsys + 1;
     std::vector<int64_t> atom_p(W), group_p(W), cell_p(W), iblk_p(W), top_p(W);
-    std::vector<int64_t> node_p((size_t)kMaxLevels * W), sten_p((size_t)kMaxLevels * W);
+    std::vector<int64_t> node_p((size_t)kMaxLevels * W);
     int64_t cells = 0, q = 0, u = 0, groups = 0, iblk = 0, top = 0;
-    int64_t nodes[kMaxLevels] = {0}, sten[kMaxLevels] = {0};
-    int maxlev = 1;
+    int64_t nodes[kMaxLevels] = {0};
+    int maxlev = 1, top_d2 = 0;
     for (int s = 0; s < nsys; s++) {
         const double *lo = domains ? domains + 6 * s : c->prm.lo;
         const double *hi = domains ? domains + 6 * s + 3 : c->prm.hi;
@@ -196,10 +203,7 @@ int build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double *domai
         cell_p[s] = cells;
         iblk_p[s] = iblk;
         top_p[s] = top;
-        for (int k = 0; k < kMaxLevels; k++) {
-            node_p[(size_t)k * W + s] = nodes[k];
-            sten_p[(size_t)k * W + s] = sten[k];
-        }
+        for (int k = 0; k < kMaxLevels; k++) node_p[(size_t)k * W + s] = nodes[k];
         for (int k = 0; k < g.nlev; k++) {
             P.qoff[k] = q;
             P.uoff[k] = u;
@@ -207,11 +211,12 @@ int build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double *domai
             q += round_up((int64_t)padded_x(g.gdim[k][0]) * padded_x(g.gdim[k][1]) * padded_z(g.gdim[k][2]), 64);
             u += round_up(n, 64);
             nodes[k] += n;
-            if (k < g.nlev - 1)
-                sten[k] += (int64_t)g.gdim[k][0] * g.gdim[k][1] * ((g.gdim[k][2] + kStencilZ - 1) / kStencilZ);
         }
         const int kt = g.nlev - 1;
         top += (int64_t)g.gdim[kt][0] * g.gdim[kt][1] * g.gdim[kt][2];
+        int d2 = 0;
+        for (int d = 0; d < 3; d++) d2 += (g.gdim[kt][d] - 1) * (g.gdim[kt][d] - 1);
+        top_d2 = std::max(top_d2, d2);
         cells += P.ncells;
         groups += P.ngroups;
         iblk += (P.natoms + 255) / 256;
@@ -221,10 +226,22 @@ int build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double *domai
     cell_p[nsys] = cells;
     iblk_p[nsys] = iblk;
     top_p[nsys] = top;
-    for (int k = 0; k < kMaxLevels; k++) {
-        node_p[(size_t)k * W + nsys] = nodes[k];
-        sten_p[(size_t)k * W + nsys] = sten[k];
-    }
+    for (int k = 0; k < kMaxLevels; k++) node_p[(size_t)k * W + nsys] = nodes[k];
+    // stencil tiles of every level below each system's top, segment k*nsys + s
+    const int esz = c->prm.precision == MSM_FP32 ? 4 : 8;
+    const int txy = stencil_tile_xy(esz, c->mc.reach), tz = stencil_tile_z(esz, c->mc.reach);
+    const int nseg = (maxlev - 1) * nsys;
+    std::vector<int64_t> tile_p((size_t)nseg + 1);
+    int64_t tiles = 0;
+    for (int k = 0; k + 1 < maxlev; k++)
+        for (int s = 0; s < nsys; s++) {
+            tile_p[(size_t)k * nsys + s] = tiles;
+            const SysPlan &P = sys[s];
+            if (k < P.nlev - 1)
+                tiles += (int64_t)((P.gdim[k][0] + txy - 1) / txy) * ((P.gdim[k][1] + txy - 1) / txy) *
+                         ((P.gdim[k][2] + tz - 1) / tz);
+        }
+    tile_p[nseg] = tiles;
     if (cells > c->cap_cells || q > c->cap_q || u > c->cap_u || iblk > c->cap_iblk) return MSM_ERR_CAPACITY;
     if (cells >= (int64_t)1 << 31) return MSM_ERR_CAPACITY;
 
@@ -239,7 +256,7 @@ int build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double *domai
     const size_t o_atom = place(sizeof(int64_t) * W), o_group = place(sizeof(int64_t) * W);
     const size_t o_cell = place(sizeof(int64_t) * W), o_iblk = place(sizeof(int64_t) * W);
     const size_t o_top = place(sizeof(int64_t) * W);
-    const size_t o_node = place(sizeof(int64_t) * kMaxLevels * W), o_sten = place(sizeof(int64_t) * kMaxLevels * W);
+    const size_t o_node = place(sizeof(int64_t) * kMaxLevels * W), o_tile = place(sizeof(int64_t) * (nseg + 1));
     // the staging buffer may still feed an earlier copy
     if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
     if (off > c->plan_cap) {
@@ -260,7 +277,7 @@ int build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double *domai
     std::memcpy(h + o_iblk, iblk_p.data(), sizeof(int64_t) * W);
     std::memcpy(h + o_top, top_p.data(), sizeof(int64_t) * W);
     std::memcpy(h + o_node, node_p.data(), sizeof(int64_t) * kMaxLevels * W);
-    std::memcpy(h + o_sten, sten_p.data(), sizeof(int64_t) * kMaxLevels * W);
+    std::memcpy(h + o_tile, tile_p.data(), sizeof(int64_t) * (nseg + 1));
     if (hipMemcpyAsync(c->plan_dev, h, off, hipMemcpyHostToDevice, c->stream) != hipSuccess) return MSM_ERR_HIP;
 
     DevPlan &dp = c->dp;
@@ -273,16 +290,16 @@ int build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double *domai
     dp.iblk_prefix = (const int64_t *)(d + o_iblk);
     dp.top_prefix = (const int64_t *)(d + o_top);
     dp.node_prefix = (const int64_t *)(d + o_node);
-    dp.sten_prefix = (const int64_t *)(d + o_sten);
+    dp.tile_prefix = (const int64_t *)(d + o_tile);
+    dp.ntile_seg = nseg;
+    dp.ntiles = tiles;
+    dp.top_d2 = top_d2;
     dp.natoms = offsets[nsys];
     dp.ngroups = groups;
     dp.ncells = cells;
     dp.niblk = iblk;
     dp.ntop = top;
-    for (int k = 0; k < kMaxLevels; k++) {
-        dp.nnodes[k] = nodes[k];
-        dp.nsten[k] = sten[k];
-    }
+    for (int k = 0; k < kMaxLevels; k++) dp.nnodes[k] = nodes[k];
     dp.maxlev = maxlev;
     c->host_sys = sys;
     c->last_offsets.assign(offsets, offsets + nsys + 1);
@@ -304,37 +321,80 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     Work<T> &w = work<T>(c);
     hipStream_t s = c->stream;
     hipError_t e;
+    auto mark = [&](int stage) {
+        if (c->timing) (void)hipEventRecord(c->ev[stage], s);
+    };
+    mark(MSM_STAGE_BIN);
     if ((e = L::bin(s, p, w, (const vec4_t<T> *)xyzq)) != hipSuccess) return MSM_ERR_HIP;
+    mark(MSM_STAGE_SHORT);
     if ((e = L::pair(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
+    mark(MSM_STAGE_ANTERP);
     if ((e = L::anterp(s, p, w)) != hipSuccess) return MSM_ERR_HIP;
+    mark(MSM_STAGE_RESTRICT);
     for (int k = 0; k + 1 < p.maxlev; k++)
         if ((e = L::restrict_level(s, p, w, k)) != hipSuccess) return MSM_ERR_HIP;
-    for (int k = 0; k + 1 < p.maxlev; k++)
-        if ((e = L::stencil_level(s, p, w, (const T *)c->weights, c->mc.reach, c->d2max, k)) != hipSuccess) return MSM_ERR_HIP;
+    mark(MSM_STAGE_CUTOFF);
+    {
+        StencilTables<T> tb{c->wcols, (const T *)c->weights, c->ncols, c->mc.reach};
+        if ((e = L::stencil(s, p, w, tb)) != hipSuccess) return MSM_ERR_HIP;
+    }
+    mark(MSM_STAGE_TOP);
     if ((e = L::top_level(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
+    mark(MSM_STAGE_PROLONG);
     for (int k = p.maxlev - 2; k >= 0; k--)
         if ((e = L::prolong_level(s, p, w, k)) != hipSuccess) return MSM_ERR_HIP;
+    mark(MSM_STAGE_INTERP);
     if ((e = L::interp(s, p, w, c->mc, (T *)forces, (T *)pots)) != hipSuccess) return MSM_ERR_HIP;
     if ((e = L::energy(s, p, w, energy)) != hipSuccess) return MSM_ERR_HIP;
+    if (c->timing) {
+        mark(MSM_NSTAGES);
+        if (hipEventSynchronize(c->ev[MSM_NSTAGES]) != hipSuccess) return MSM_ERR_HIP;
+        for (int st = 0; st < MSM_NSTAGES; st++) {
+            float ms = 0;
+            if (hipEventElapsedTime(&ms, c->ev[st], c->ev[st + 1]) != hipSuccess) return MSM_ERR_HIP;
+            c->stage_ms[st] += ms;
+        }
+        c->timed_evals++;
+    }
     return MSM_OK;
 }
 
-// W[o] = g^0(h |o|) = gamma(h|o|/a)/a - gamma(h|o|/(2a))/(2a) for |o|^2 <= d2max
-// (zero beyond: g^0 vanishes for r >= 2a), laid out [(oy+R)(2R+1) + ox+R](2R+1) + oz+R.
-template <typename T> std::vector<T> stencil_table(double a, double h, int R, int d2max)
+// Quarter-disc columns (ox, oy >= 0, ox^2 + oy^2 <= d2max) and, per column,
+// the weights g^0(h |o|) = gamma(h|o|/a)/a - gamma(h|o|/(2a))/(2a) for
+// oz = -R .. R (zero where |o|^2 > d2max: g^0 vanishes for r >= 2a).
+template <typename T>
+void stencil_tables(double a, double h, int R, int d2max, std::vector<int2> &cols, std::vector<T> &w)
 {
-    const int D = 2 * R + 1;
-    std::vector<T> w((size_t)D * D * D, T(0));
-    for (int oy = -R; oy <= R; oy++)
-        for (int ox = -R; ox <= R; ox++)
+    cols.clear();
+    w.clear();
+    for (int oy = 0; oy <= R; oy++)
+        for (int ox = 0; ox <= R; ox++) {
+            if (ox * ox + oy * oy > d2max) continue;
+            cols.push_back(make_int2(ox, oy));
             for (int oz = -R; oz <= R; oz++) {
                 const int d2 = ox * ox + oy * oy + oz * oz;
-                if (d2 > d2max) continue;
-                const double r = h * std::sqrt((double)d2);
-                const double g0 = gamma_s(r / a) / a - gamma_s(r / (2 * a)) / (2 * a);
-                w[((size_t)(oy + R) * D + (ox + R)) * D + (oz + R)] = T(g0);
+                double g0 = 0.0;
+                if (d2 <= d2max) {
+                    const double r = h * std::sqrt((double)d2);
+                    g0 = gamma_s(r / a) / a - gamma_s(r / (2 * a)) / (2 * a);
+                }
+                w.push_back(T(g0));
             }
-    return w;
+        }
+}
+
+template <typename T> int upload_stencil(msm_ctx *c)
+{
+    std::vector<int2> cols;
+    std::vector<T> w;
+    stencil_tables<T>(c->prm.a, c->prm.h, c->mc.reach, c->d2max, cols, w);
+    c->ncols = (int)cols.size();
+    if (hipMalloc(&c->weights, w.size() * sizeof(T)) != hipSuccess) return MSM_ERR_HIP;
+    if (hipMalloc((void **)&c->wcols, cols.size() * sizeof(int2)) != hipSuccess) return MSM_ERR_HIP;
+    if (hipMemcpy(c->weights, w.data(), w.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return MSM_ERR_HIP;
+    if (hipMemcpy(c->wcols, cols.data(), cols.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
+        return MSM_ERR_HIP;
+    return MSM_OK;
 }
 
 }  // namespace
@@ -416,20 +476,10 @@ int msm_setup(const msm_params *prm, void *stream, msm_ctx **out)
         msm_destroy(c);
         return MSM_ERR_HIP;
     }
-    if (prm->precision == MSM_FP32) {
-        auto w = stencil_table<float>(prm->a, prm->h, reach, c->d2max);
-        if (hipMalloc(&c->weights, w.size() * sizeof(float)) != hipSuccess ||
-            hipMemcpy(c->weights, w.data(), w.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
-            msm_destroy(c);
-            return MSM_ERR_HIP;
-        }
-    } else {
-        auto w = stencil_table<double>(prm->a, prm->h, reach, c->d2max);
-        if (hipMalloc(&c->weights, w.size() * sizeof(double)) != hipSuccess ||
-            hipMemcpy(c->weights, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess) {
-            msm_destroy(c);
-            return MSM_ERR_HIP;
-        }
+    rc = prm->precision == MSM_FP32 ? upload_stencil<float>(c) : upload_stencil<double>(c);
+    if (rc) {
+        msm_destroy(c);
+        return rc;
     }
     if (hipStreamSynchronize(c->stream) != hipSuccess) {
         msm_destroy(c);
@@ -443,8 +493,11 @@ void msm_destroy(msm_ctx *c)
 {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
     if (c->wbuf) (void)hipFree(c->wbuf);
     if (c->weights) (void)hipFree(c->weights);
+    if (c->wcols) (void)hipFree(c->wcols);
     if (c->plan_dev) (void)hipFree(c->plan_dev);
     if (c->plan_host) (void)hipHostFree(c->plan_host);
     delete c;
@@ -508,6 +561,29 @@ int msm_debug_stages(msm_ctx *c, int sys, double *u_short, double *f_short, doub
                        ? Launch<float>::stage_copy(c->stream, c->dp, c->wf, sys, u_short, f_short, qg, ucut, ug)
                        : Launch<double>::stage_copy(c->stream, c->dp, c->wd, sys, u_short, f_short, qg, ucut, ug);
     return hip_status(e);
+}
+
+int msm_enable_stage_timing(msm_ctx *c, int enable)
+{
+    if (!c) return MSM_ERR_ARG;
+    if (enable && !c->ev[0])
+        for (auto &e : c->ev)
+            if (hipEventCreate(&e) != hipSuccess) return MSM_ERR_HIP;
+    c->timing = enable != 0;
+    return MSM_OK;
+}
+
+int msm_stage_timing(msm_ctx *c, double *ms_out, int64_t *evaluations, int reset)
+{
+    if (!c) return MSM_ERR_ARG;
+    if (ms_out)
+        for (int st = 0; st < MSM_NSTAGES; st++) ms_out[st] = c->stage_ms[st];
+    if (evaluations) *evaluations = c->timed_evals;
+    if (reset) {
+        for (double &v : c->stage_ms) v = 0;
+        c->timed_evals = 0;
+    }
+    return MSM_OK;
 }
 
 }  // extern "C"

@@ -19,11 +19,12 @@ struct DevPlan {
     const int64_t *cell_prefix;  // nsys+1: brick-major cells
     const int64_t *node_prefix;  // kMaxLevels x (nsys+1): level-k nodes per system
     const int64_t *iblk_prefix;  // nsys+1: interpolation blocks per system
-    const int64_t *sten_prefix;  // kMaxLevels x (nsys+1): stencil threads (columns x z-blocks)
+    const int64_t *tile_prefix;  // ntile_seg+1: stencil tiles of segment k*nsys + s (levels below the top)
     const int64_t *top_prefix;   // nsys+1: top-level nodes per system
-    int64_t natoms, ngroups, ncells, niblk, ntop;
+    int ntile_seg;               // (maxlev - 1) * nsys
+    int top_d2;                  // largest squared index distance on any top grid
+    int64_t natoms, ngroups, ncells, niblk, ntop, ntiles;
     int64_t nnodes[kMaxLevels];  // level-k nodes over the batch
-    int64_t nsten[kMaxLevels];   // level-k stencil threads over the batch
     int maxlev;                  // largest level count in the batch
 };
 
@@ -43,6 +44,18 @@ template <typename T> struct Work {
     int *status;         // device status word
 };
 
+// Quarter-disc stencil columns (ox >= 0, oy >= 0 inside the sphere) and their
+// 2R+1 weights g^0(h |o|) along z.
+template <typename T> struct StencilTables {
+    const int2 *cols;
+    const T *w;
+    int ncols;
+    int reach;
+};
+
+int stencil_tile_xy(int elem_bytes, int reach);
+int stencil_tile_z(int elem_bytes, int reach);
+
 struct MethodConst {
     double a, h, ke;
     int reach;                 // stencil reach R: largest integer with R < 2a/h
@@ -55,8 +68,7 @@ template <typename T> struct Launch {
     static hipError_t pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m);
     static hipError_t anterp(hipStream_t s, const DevPlan &p, const Work<T> &w);
     static hipError_t restrict_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k);
-    static hipError_t stencil_level(hipStream_t s, const DevPlan &p, const Work<T> &w,
-                                    const T *weights, int reach, int r2max, int k);
+    static hipError_t stencil(hipStream_t s, const DevPlan &p, const Work<T> &w, const StencilTables<T> &tb);
     static hipError_t top_level(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m);
     static hipError_t prolong_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k);
     static hipError_t interp(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m,

@@ -65,17 +65,21 @@ template <typename T> struct PairK {
     T d0, d1;        // -gamma'(rho)/(a^2 rho) / a ... = d0 + d1 rho^2 (force bracket term)
 };
 
+constexpr int kPairWaves = 4;   // waves sharing one group's candidate rows
+
 template <typename T>
-__global__ __launch_bounds__(64) void k_pair(DevPlan p, const vec4_t<T> *__restrict__ sx,
-                                             const int *__restrict__ cstart, vec4_t<T> *__restrict__ out,
-                                             PairK<T> k)
+__global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const vec4_t<T> *__restrict__ sx,
+                                                              const int *__restrict__ cstart,
+                                                              vec4_t<T> *__restrict__ out, PairK<T> k)
 {
+    __shared__ vec4_t<T> red[kPairWaves][kWave];
     const int64_t g = blockIdx.x;
     const int s = find_segment(p.group_prefix, p.nsys, g);
     const SysPlan &P = p.sys[s];
     const int64_t first = P.atom0 + (g - p.group_prefix[s]) * kWave;
     const int64_t end = P.atom0 + P.natoms;
-    const int lane = threadIdx.x;
+    const int lane = threadIdx.x % kWave;
+    const int wv = uni((int)(threadIdx.x / kWave));
     const int64_t i = first + lane;
     const bool valid = i < end;
     const vec4_t<T> ai = sx[valid ? i : first];
@@ -94,6 +98,7 @@ __global__ __launch_bounds__(64) void k_pair(DevPlan p, const vec4_t<T> *__restr
     const int cz1 = clampi((int)floor((bmaxz - loz + reach) * inv_h), 0, ncz - 1);
 
     T fx = 0, fy = 0, fz = 0, u = 0;
+    int row = 0;
     for (int cz = cz0; cz <= cz1; ++cz) {
         const T z0 = loz + T(cz) * h;
         const T dz = fmax(T(0), fmax(z0 - bmaxz, bminz - (z0 + h)));
@@ -102,6 +107,8 @@ __global__ __launch_bounds__(64) void k_pair(DevPlan p, const vec4_t<T> *__restr
             const T dy = fmax(T(0), fmax(y0 - bmaxy, bminy - (y0 + h)));
             const T rem = reach2 - dy * dy - dz * dz;
             if (rem <= T(0)) continue;
+            // rows that reach the group are dealt round-robin to the waves
+            if ((row++ % kPairWaves) != wv) continue;
             const T wdt = sqrt(rem);
             const int cx0 = clampi((int)floor((bminx - lox - wdt) * inv_h), 0, ncx - 1);
             const int cx1 = clampi((int)floor((bmaxx - lox + wdt) * inv_h), 0, ncx - 1);
@@ -111,8 +118,13 @@ __global__ __launch_bounds__(64) void k_pair(DevPlan p, const vec4_t<T> *__restr
                 const int64_t r0 = P.cell0 + cell_rank(P, ca, cy, cz);
                 const int jb = uni(cstart[r0]);
                 const int je = uni(cstart[r0 + (cb - ca) + 1]);
+                if (jb >= je) continue;
+                // the atom array carries one spare element, so the prefetch of
+                // j + 1 past the last atom stays inside the allocation
+                vec4_t<T> nxt = sx[jb];
                 for (int j = jb; j < je; ++j) {
-                    const vec4_t<T> aj = sx[j];
+                    const vec4_t<T> aj = nxt;
+                    nxt = sx[j + 1];
                     const T dx = ai.x - aj.x, ddy = ai.y - aj.y, ddz = ai.z - aj.z;
                     const T r2 = dx * dx + ddy * ddy + ddz * ddz;
                     if (r2 < k.a2 && r2 > T(0)) {
@@ -130,13 +142,23 @@ __global__ __launch_bounds__(64) void k_pair(DevPlan p, const vec4_t<T> *__restr
             }
         }
     }
-    if (valid) {
-        vec4_t<T> o;
-        o.x = fx;
-        o.y = fy;
-        o.z = fz;
-        o.w = u;
-        out[i] = o;
+    vec4_t<T> o;
+    o.x = fx;
+    o.y = fy;
+    o.z = fz;
+    o.w = u;
+    red[wv][lane] = o;
+    __syncthreads();
+    if (wv == 0 && valid) {
+        vec4_t<T> acc = red[0][lane];
+        for (int w = 1; w < kPairWaves; ++w) {   // fixed order: deterministic
+            const vec4_t<T> v = red[w][lane];
+            acc.x += v.x;
+            acc.y += v.y;
+            acc.z += v.z;
+            acc.w += v.w;
+        }
+        out[i] = acc;
     }
 }
 
@@ -223,55 +245,101 @@ __global__ __launch_bounds__(256) void k_restrict(DevPlan p, T *__restrict__ qgr
 // ---------------------------------------------------------------------------
 // Lattice cutoff on level k < l-1 (Section 3): u^{k,cutoff}_mu =
 // sum_nu g^k(r^k_mu, r^k_nu) q^k_nu. On level k the node distance is 2^k h |o|,
-// and g^k(2^k h |o|) = 2^{-k} g^0(h |o|), so one table W[o] = g^0(h |o|),
+// and g^k(2^k h |o|) = 2^{-k} g^0(h |o|), so one set of weights g^0(h |o|),
 // zero for |o| >= 2a/h, serves every level with an exact power-of-two scale.
-// A thread owns kStencilZ consecutive z outputs of one (x, y) column and, for
-// each (ox, oy) column of the stencil, loads the z-line of charges once into
-// registers and applies the 2R+1 weights of that column to all its outputs.
+//
+// A workgroup owns a TXY x TXY x TZ tile of outputs and stages the charges of
+// the tile grown by the reach R in LDS. Each thread owns one (x, y) output
+// column of TZ nodes and one share of the stencil's columns (ox, oy). The
+// weights depend on |o| only, so the (up to) four mirrored columns
+// (+-ox, +-oy) are added first and share one pass of the 2R+1 weights along z:
+// the quarter-disc of columns carries the whole sphere. The shares are summed
+// in a fixed order at the end.
 // ---------------------------------------------------------------------------
+template <typename T, int R> struct StencilGeom {
+    static constexpr int TZ = (sizeof(T) == 8 && R >= 10) ? 4 : kStencilTile;
+    static constexpr int TXY = (sizeof(T) == 8 && R >= 10) ? 4 : kStencilTile;
+    static constexpr int EX = TXY + 2 * R;
+    static constexpr int EZ = TZ + 2 * R;
+    static constexpr int COLS = TXY * TXY;            // output columns per tile
+    static constexpr int SHARES = 256 / COLS;         // threads per output column
+    static constexpr int IN = EZ * EX * EX;           // staged charges
+    static constexpr int LDS = IN > 256 * TZ ? IN : 256 * TZ;   // also holds the share sums
+};
+
 template <typename T, int R>
 __global__ __launch_bounds__(256) void k_stencil(DevPlan p, const T *__restrict__ qgrid, T *__restrict__ ucut,
-                                                 const T *__restrict__ W, int k, int r2max)
+                                                 const int2 *__restrict__ qcols, const T *__restrict__ qw, int ncols)
 {
-    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= p.nsten[k]) return;
-    const int64_t *pref = p.sten_prefix + (int64_t)k * (p.nsys + 1);
-    const int s = find_segment(pref, p.nsys, g);
-    const SysPlan &P = p.sys[s];
-    if (k >= P.nlev - 1) return;
-    const int64_t loc = g - pref[s];
-    const int dx = P.gdim[k][0], dy = P.gdim[k][1], dz = P.gdim[k][2];
-    const int x = (int)(loc % dx), y = (int)((loc / dx) % dy), zb = (int)(loc / ((int64_t)dx * dy));
-    const int z0 = zb * kStencilZ;
-    const int PX = padded_x(dx), PY = padded_x(dy);
-    const int64_t zs = (int64_t)PX * PY;
-    const T *q = qgrid + P.qoff[k];
+    using G = StencilGeom<T, R>;
     constexpr int D = 2 * R + 1;
-    constexpr int L = kStencilZ + 2 * R;
-    T acc[kStencilZ];
+    constexpr int L = G::TZ + 2 * R;
+    __shared__ T tile[G::LDS];
+    const int64_t blk = blockIdx.x;
+    const int seg = find_segment(p.tile_prefix, p.ntile_seg, blk);
+    const int k = seg / p.nsys, s = seg % p.nsys;
+    const SysPlan &P = p.sys[s];
+    const int dx = P.gdim[k][0], dy = P.gdim[k][1], dz = P.gdim[k][2];
+    const int ntx = (dx + G::TXY - 1) / G::TXY, nty = (dy + G::TXY - 1) / G::TXY;
+    const int64_t t = blk - p.tile_prefix[seg];
+    const int x0 = (int)(t % ntx) * G::TXY, y0 = (int)((t / ntx) % nty) * G::TXY;
+    const int z0 = (int)(t / ((int64_t)ntx * nty)) * G::TZ;
+    const int PX = padded_x(dx), PY = padded_x(dy);
+    const T *q = qgrid + P.qoff[k];
+
+    // stage the charges of the grown tile (the grid's zero halo covers the overhang)
+    for (int e = threadIdx.x; e < G::IN; e += 256) {
+        const int ex = e % G::EX, ey = (e / G::EX) % G::EX, ez = e / (G::EX * G::EX);
+        tile[e] = q[((int64_t)(z0 + kGridPad - R + ez) * PY + (y0 + kGridPad - R + ey)) * PX + (x0 + kGridPad - R + ex)];
+    }
+    __syncthreads();
+
+    const int col = threadIdx.x % G::COLS;
+    const int share = threadIdx.x / G::COLS;
+    const int cx = col % G::TXY + R, cy = col / G::TXY + R;
+    T acc[G::TZ];
 #pragma unroll
-    for (int t = 0; t < kStencilZ; ++t) acc[t] = T(0);
-    for (int oy = -R; oy <= R; ++oy) {
-        for (int ox = -R; ox <= R; ++ox) {
-            if (ox * ox + oy * oy > r2max) continue;
-            const T *col = q + (int64_t)(z0 + kGridPad - R) * zs + (int64_t)(y + kGridPad + oy) * PX + (x + kGridPad + ox);
-            T line[L];
+    for (int z = 0; z < G::TZ; ++z) acc[z] = T(0);
+    for (int c = share; c < ncols; c += G::SHARES) {
+        const int2 o = qcols[c];
+        T S[L];
 #pragma unroll
-            for (int t = 0; t < L; ++t) line[t] = col[t * zs];
-            const T *wc = W + ((oy + R) * D + (ox + R)) * D;
+        for (int z = 0; z < L; ++z) S[z] = tile[(z * G::EX + cy + o.y) * G::EX + cx + o.x];
+        if (o.x) {
 #pragma unroll
-            for (int oz = 0; oz < D; ++oz) {
-                const T wv = wc[oz];
+            for (int z = 0; z < L; ++z) S[z] += tile[(z * G::EX + cy + o.y) * G::EX + cx - o.x];
+        }
+        if (o.y) {
 #pragma unroll
-                for (int t = 0; t < kStencilZ; ++t) acc[t] += wv * line[t + oz];
+            for (int z = 0; z < L; ++z) S[z] += tile[(z * G::EX + cy - o.y) * G::EX + cx + o.x];
+            if (o.x) {
+#pragma unroll
+                for (int z = 0; z < L; ++z) S[z] += tile[(z * G::EX + cy - o.y) * G::EX + cx - o.x];
             }
         }
+        const T *w = qw + (int64_t)c * D;
+#pragma unroll
+        for (int oz = 0; oz < D; ++oz) {
+            const T wv = w[oz];
+#pragma unroll
+            for (int z = 0; z < G::TZ; ++z) acc[z] += wv * S[z + oz];
+        }
     }
+    __syncthreads();
+    // sum the shares in a fixed order; the tile storage is reused
+    T *part = tile;
+#pragma unroll
+    for (int z = 0; z < G::TZ; ++z) part[(share * G::COLS + col) * G::TZ + z] = acc[z];
+    __syncthreads();
     const T scale = T(ldexp(1.0, -k));
     T *u = ucut + P.uoff[k];
-#pragma unroll
-    for (int t = 0; t < kStencilZ; ++t)
-        if (z0 + t < dz) u[((int64_t)(z0 + t) * dy + y) * dx + x] = acc[t] * scale;
+    for (int e = threadIdx.x; e < G::COLS * G::TZ; e += 256) {
+        const int c = e / G::TZ, z = e % G::TZ;
+        T v = part[c * G::TZ + z];
+        for (int sh = 1; sh < G::SHARES; ++sh) v += part[(sh * G::COLS + c) * G::TZ + z];
+        const int gx = x0 + c % G::TXY, gy = y0 + c / G::TXY, gz = z0 + z;
+        if (gx < dx && gy < dy && gz < dz) u[((int64_t)gz * dy + gy) * dx + gx] = v * scale;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -279,10 +347,18 @@ __global__ __launch_bounds__(256) void k_stencil(DevPlan p, const T *__restrict_
 // all node pairs, g^{l-1}(r) = gamma(r / (2^{l-1} a)) / (2^{l-1} a). The grid
 // is at most a few hundred nodes; each thread sums over all of them.
 // ---------------------------------------------------------------------------
+constexpr int kTopTable = 4096;
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_top(DevPlan p, const T *__restrict__ qgrid, T *__restrict__ ucut,
-                                             T *__restrict__ ugrid, double h, double a)
+                                             T *__restrict__ ugrid, double h, double a, int ntab)
 {
+    // weights by squared integer distance d2: gamma(h sqrt(d2) / a) / a; the
+    // level's factor 2^-(l-1) is applied to the sum
+    __shared__ T tab[kTopTable];
+    for (int d2 = threadIdx.x; d2 < ntab && d2 < kTopTable; d2 += blockDim.x)
+        tab[d2] = gamma_s(T(h / a) * sqrt(T(d2))) * T(1.0 / a);
+    __syncthreads();
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= p.ntop) return;
     const int s = find_segment(p.top_prefix, p.nsys, g);
@@ -293,18 +369,18 @@ __global__ __launch_bounds__(256) void k_top(DevPlan p, const T *__restrict__ qg
     const int x = (int)(loc % dx), y = (int)((loc / dx) % dy), z = (int)(loc / ((int64_t)dx * dy));
     const int PX = padded_x(dx), PY = padded_x(dy);
     const T *q = qgrid + P.qoff[k];
-    const T hk = T(ldexp(h, k)), ak = T(ldexp(a, k)), inv_ak = T(1) / ak;
     T acc = 0;
     for (int nz = 0; nz < dz; ++nz)
         for (int ny = 0; ny < dy; ++ny) {
             const T *row = q + ((int64_t)(nz + kGridPad) * PY + (ny + kGridPad)) * PX + kGridPad;
-            const int ez = nz - z, ey = ny - y;
+            const int eyz = (nz - z) * (nz - z) + (ny - y) * (ny - y);
             for (int nx = 0; nx < dx; ++nx) {
-                const int ex = nx - x;
-                const T r = hk * sqrt(T(ex * ex + ey * ey + ez * ez));
-                acc += gamma_s(r * inv_ak) * inv_ak * row[nx];
+                const int d2 = eyz + (nx - x) * (nx - x);
+                const T w = d2 < kTopTable ? tab[d2] : gamma_s(T(h / a) * sqrt(T(d2))) * T(1.0 / a);
+                acc += w * row[nx];
             }
         }
+    acc *= T(ldexp(1.0, -k));
     const int64_t o = P.uoff[k] + ((int64_t)z * dy + y) * dx + x;
     ucut[o] = acc;
     ugrid[o] = acc;
@@ -443,14 +519,22 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4
     if (threadIdx.x == 0) eparts[blk] = red[0];
 }
 
-// U = 1/2 sum_i q_i phi_i per system, from the block partial sums in block order.
-__global__ void k_energy(DevPlan p, const double *__restrict__ eparts, double *__restrict__ energy)
+// U = 1/2 sum_i q_i phi_i per system, from the block partial sums: one
+// workgroup per system, each thread a fixed stride of partials, then a tree.
+__global__ __launch_bounds__(256) void k_energy(DevPlan p, const double *__restrict__ eparts,
+                                                double *__restrict__ energy)
 {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= p.nsys) return;
+    __shared__ double red[256];
+    const int s = blockIdx.x;
     double acc = 0;
-    for (int64_t b = p.iblk_prefix[s]; b < p.iblk_prefix[s + 1]; ++b) acc += eparts[b];
-    energy[s] = 0.5 * acc;
+    for (int64_t b = p.iblk_prefix[s] + threadIdx.x; b < p.iblk_prefix[s + 1]; b += 256) acc += eparts[b];
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) energy[s] = 0.5 * red[0];
 }
 
 template <typename T>
@@ -505,7 +589,8 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, co
     // -(d/dr)(gamma(r/a)/a) / r = (5/2 - 3/2 rho^2) / a^3, entering with a minus sign
     k.d0 = T(2.5 / (a * a * a));
     k.d1 = T(-1.5 / (a * a * a));
-    hipLaunchKernelGGL(k_pair<T>, dim3((unsigned)p.ngroups), dim3(kWave), 0, s, p, w.sxyzq, w.cell_start, w.shrt, k);
+    hipLaunchKernelGGL(k_pair<T>, dim3((unsigned)p.ngroups), dim3(kPairWaves * kWave), 0, s, p, w.sxyzq, w.cell_start,
+                       w.shrt, k);
     return hipGetLastError();
 }
 
@@ -525,41 +610,42 @@ template <typename T> hipError_t Launch<T>::restrict_level(hipStream_t s, const 
 }
 
 template <typename T, int R>
-static hipError_t stencil_r(hipStream_t s, const DevPlan &p, const Work<T> &w, const T *W, int k, int r2max)
+static hipError_t stencil_r(hipStream_t s, const DevPlan &p, const Work<T> &w, const StencilTables<T> &tb)
 {
-    hipLaunchKernelGGL((k_stencil<T, R>), dim3(nblocks(p.nsten[k], 256)), dim3(256), 0, s, p, w.qgrid, w.ucut, W, k,
-                       r2max);
+    hipLaunchKernelGGL((k_stencil<T, R>), dim3((unsigned)p.ntiles), dim3(256), 0, s, p, w.qgrid, w.ucut, tb.cols,
+                       tb.w, tb.ncols);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t Launch<T>::stencil_level(hipStream_t s, const DevPlan &p, const Work<T> &w, const T *W, int reach,
-                                    int r2max, int k)
+hipError_t Launch<T>::stencil(hipStream_t s, const DevPlan &p, const Work<T> &w, const StencilTables<T> &tb)
 {
-    if (p.nsten[k] == 0) return hipSuccess;
-    // r2max is the largest |o|^2 inside the sphere: columns (ox, oy) with
-    // ox^2 + oy^2 > r2max hold only zero weights and are skipped
-    switch (reach) {
-    case 1: return stencil_r<T, 1>(s, p, w, W, k, r2max);
-    case 2: return stencil_r<T, 2>(s, p, w, W, k, r2max);
-    case 3: return stencil_r<T, 3>(s, p, w, W, k, r2max);
-    case 4: return stencil_r<T, 4>(s, p, w, W, k, r2max);
-    case 5: return stencil_r<T, 5>(s, p, w, W, k, r2max);
-    case 6: return stencil_r<T, 6>(s, p, w, W, k, r2max);
-    case 7: return stencil_r<T, 7>(s, p, w, W, k, r2max);
-    case 8: return stencil_r<T, 8>(s, p, w, W, k, r2max);
-    case 9: return stencil_r<T, 9>(s, p, w, W, k, r2max);
-    case 10: return stencil_r<T, 10>(s, p, w, W, k, r2max);
-    case 11: return stencil_r<T, 11>(s, p, w, W, k, r2max);
+    if (p.ntiles == 0) return hipSuccess;
+    switch (tb.reach) {
+    case 1: return stencil_r<T, 1>(s, p, w, tb);
+    case 2: return stencil_r<T, 2>(s, p, w, tb);
+    case 3: return stencil_r<T, 3>(s, p, w, tb);
+    case 4: return stencil_r<T, 4>(s, p, w, tb);
+    case 5: return stencil_r<T, 5>(s, p, w, tb);
+    case 6: return stencil_r<T, 6>(s, p, w, tb);
+    case 7: return stencil_r<T, 7>(s, p, w, tb);
+    case 8: return stencil_r<T, 8>(s, p, w, tb);
+    case 9: return stencil_r<T, 9>(s, p, w, tb);
+    case 10: return stencil_r<T, 10>(s, p, w, tb);
+    case 11: return stencil_r<T, 11>(s, p, w, tb);
     default: return hipErrorInvalidValue;
     }
 }
+
+int stencil_tile_xy(int elem_bytes, int reach) { return (elem_bytes == 8 && reach >= 10) ? 4 : kStencilTile; }
+int stencil_tile_z(int elem_bytes, int reach) { return (elem_bytes == 8 && reach >= 10) ? 4 : kStencilTile; }
 
 template <typename T>
 hipError_t Launch<T>::top_level(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m)
 {
     if (p.ntop == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_top<T>, dim3(nblocks(p.ntop, 256)), dim3(256), 0, s, p, w.qgrid, w.ucut, w.ugrid, m.h, m.a);
+    hipLaunchKernelGGL(k_top<T>, dim3(nblocks(p.ntop, 256)), dim3(256), 0, s, p, w.qgrid, w.ucut, w.ugrid, m.h, m.a,
+                       p.top_d2 + 1);
     return hipGetLastError();
 }
 
@@ -584,7 +670,7 @@ hipError_t Launch<T>::interp(hipStream_t s, const DevPlan &p, const Work<T> &w, 
 template <typename T> hipError_t Launch<T>::energy(hipStream_t s, const DevPlan &p, const Work<T> &w, double *energy)
 {
     if (!energy) return hipSuccess;
-    hipLaunchKernelGGL(k_energy, dim3(nblocks(p.nsys, 64)), dim3(64), 0, s, p, w.eparts, energy);
+    hipLaunchKernelGGL(k_energy, dim3((unsigned)p.nsys), dim3(256), 0, s, p, w.eparts, energy);
     return hipGetLastError();
 }
 

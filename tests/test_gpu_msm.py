@@ -112,7 +112,7 @@ def test_water_small_matches_oracle(precision):
 
 
 @pytest.mark.parametrize("a,h,levels", [(0.8, 0.5, 0), (1.2, 0.25, 1), (1.2, 0.25, 2), (0.6, 0.2, 0),
-                                        (1.0, 0.35, 0)])
+                                        (1.0, 0.35, 0), (0.3, 0.25, 0), (1.3, 0.25, 0), (1.4, 0.25, 0)])
 def test_fp64_parameter_variants(a, h, levels):
     w = uniform_pm(500, 3.3, seed=5, a=a, h=h, levels=levels)
     _, e, f, p = run_gpu(w, "fp64")
@@ -120,6 +120,16 @@ def test_fp64_parameter_variants(a, h, levels):
     assert e == pytest.approx(eo, rel=1e-12)
     assert max_rel(f, fo) < 1e-11
     assert max_rel(p, po) < 1e-11
+
+
+@pytest.mark.parametrize("a,h", [(0.3, 0.25), (0.8, 0.5), (1.4, 0.25)])
+def test_fp32_parameter_variants(a, h):
+    # stencil reach 2, 3 and 11: the smallest and largest shapes of the tiled stencil
+    w = uniform_pm(600, 3.3, seed=6, a=a, h=h).as_dtype(np.float32)
+    _, e, f, p = run_gpu(w, "fp32")
+    eo, fo, po = run_oracle(w)
+    assert rel_rms(f, fo) < 1e-4
+    assert rel_rms(p, po) < 1e-4
 
 
 def test_non_cubic_domain_and_boundary_atoms():
