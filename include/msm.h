@@ -128,6 +128,80 @@ int msm_debug_stages(msm_ctx *ctx, int sys, double *u_short_dev, double *f_short
                      double *const *q_grid_dev, double *const *ucut_grid_dev,
                      double *const *u_grid_dev);
 
+/* ---- Dynamics (Section 2: move particles under F = -dU/dr) ----
+ * The paper names bonded, van der Waals and Coulomb terms but gives no force
+ * field. The model here: Coulomb by this library's MSM with the pairs inside
+ * one molecule excluded, Lennard-Jones between atoms of different molecules
+ * (Lorentz-Berthelot mixing, cut and shifted to zero at the cutoff a), and
+ * optionally rigid three-site molecules held by RATTLE (Andersen 1983). */
+typedef struct {
+    int64_t period;              /* entries of the per-atom arrays; batch atom i uses
+                                    entry i % period (period = atoms of one system) */
+    const int32_t *molid_dev;    /* period molecule ids, or NULL (no exclusions); the atoms of a
+                                    molecule lie within one system and closer than a */
+    const double *lj_dev;        /* period x 2 (sigma nm, epsilon kJ/mol), or NULL */
+    int rigid_triples;           /* 1: atoms 3m, 3m+1, 3m+2 of every system are rigid; system
+                                    offsets must then be multiples of 3 */
+    double tri_len[3];           /* distances 0-1, 0-2, 1-2 of each rigid triple (nm) */
+    double constraint_tol;       /* relative tolerance of the constraint iteration (0: 1e-10
+                                    for FP64, 1e-6 for FP32) */
+} msm_md_model;
+
+/* Copy a molecular model into the context and allocate the dynamics
+ * workspace (forces, propagator state and parareal arrays for max_atoms
+ * atoms). Must precede msm_vv_run and parareal_run; a later call replaces the
+ * model. With a model bound, msm_energy_forces also applies it. */
+int msm_md_bind(msm_ctx *ctx, const msm_md_model *model);
+
+/* nsteps velocity-Verlet steps of dt ps (Section 2), in place, on nsys
+ * systems (offsets and domains as for msm_energy_forces):
+ *  xyzq_dev  N x 4 positions and charges, precision of the context;
+ *  vel_dev   N x 4 velocities (nm/ps) and inverse masses (1/amu).
+ * Each step: half kick, drift, RATTLE positions, forces, half kick, RATTLE
+ * velocities; forces are evaluated nsteps + 1 times. epot_dev / ekin_dev
+ * (nsys doubles, may be NULL) receive the potential and kinetic energy at the
+ * end. Domain exits are reported through msm_get_status. */
+int msm_vv_run(msm_ctx *ctx, int nsys, const int64_t *offsets_host, const double *domains_host, void *xyzq_dev,
+               void *vel_dev, int nsteps, double dt, double *epot_dev, double *ekin_dev);
+
+typedef struct {
+    int nslices;        /* time slices N (window of the iteration) */
+    int kmax;           /* at most this many iterations (iterations == nslices is exact) */
+    double tol;         /* stop when no position changed by more than tol (nm) */
+    int steps_f;        /* fine propagator: steps_f velocity-Verlet steps of dt_f (fine context) */
+    double dt_f;
+    int steps_g;        /* coarse propagator: steps_g steps of dt_g (coarse context) */
+    double dt_g;
+} parareal_params;
+
+typedef struct {
+    int iterations;         /* iterations done */
+    int converged;          /* 1 when the tolerance was met or every slice is exact */
+    double residual[64];    /* largest position change of iteration k (first 64) */
+    double seconds;         /* wall time of the call, including the final synchronisation */
+} parareal_report;
+
+/* Parareal (Section 4) for one system of natoms atoms in the domain of both
+ * contexts:
+ *   lambda^0_{n+1} = G(lambda^0_n), then for k = 0, 1, ...:
+ *   lambda^{k+1}_{n+1} = F(lambda^k_n) + (G(lambda^{k+1}_n) - G(lambda^k_n)),
+ * with F and G velocity Verlet on the fine and coarse context. The fine
+ * propagator of all slices that are not yet exact runs as one batch of
+ * systems; the coarse sweep is serial. The correction and the iterates are
+ * FP64. After k iterations slices 0..k equal the serial fine trajectory
+ * bitwise.
+ *  charges_dev, invmass_dev  natoms doubles;
+ *  state0_dev                natoms x 6 (x y z vx vy vz);
+ *  lambda_dev                (nslices+1) x natoms x 6, out: every slice.
+ * The fine context needs max_atoms >= nslices*natoms and max_systems >=
+ * nslices, the coarse one natoms and 1; both need a bound model and the
+ * same stream. Returns MSM_OK when converged, MSM_NOT_CONVERGED after kmax
+ * iterations, or an error (MSM_ERR_DOMAIN/NONFINITE if a state left the
+ * domain). Synchronises once per iteration to read the residual. */
+int parareal_run(msm_ctx *fine, msm_ctx *coarse, const parareal_params *params, int64_t natoms,
+                 const double *charges_dev, const double *invmass_dev, const double *state0_dev,
+                 double *lambda_dev, parareal_report *report);
+
 /* Stages of one evaluation, for msm_stage_timing. */
 enum {
     MSM_STAGE_BIN = 0,       /* counting sort of atoms into cells */

@@ -24,4 +24,8 @@ from .loader import (  # noqa: F401
     msm,
     coulomb,
     threads,
+    OracleModel,
+    md_forces,
+    vv,
+    parareal,
 )

@@ -173,3 +173,102 @@ def coulomb(xyz, q, ke: float = 138.935458):
     if rc != 0:
         raise RuntimeError(f"oracle coulomb failed with code {rc}")
     return float(e[0]), f, pot
+
+
+# ---------------------------------------------------------------------------
+# dynamics (md_oracle.c)
+# ---------------------------------------------------------------------------
+_ip = C.POINTER(C.c_int32)
+
+
+class _Model(C.Structure):
+    _fields_ = [("mass", _dp), ("molid", _ip), ("lj", _dp), ("rigid", C.c_int),
+                ("tri", C.c_double * 3), ("tol", C.c_double)]
+
+
+@dataclasses.dataclass
+class OracleModel:
+    """Molecular model of a dynamics run (see md_oracle.h)."""
+    mass: np.ndarray
+    molid: np.ndarray | None = None
+    lj: np.ndarray | None = None
+    rigid: bool = False
+    tri: tuple = (0.0, 0.0, 0.0)
+    tol: float = 1e-10
+
+    def c(self):
+        m = _Model()
+        self._keep = [np.ascontiguousarray(self.mass, dtype=np.float64)]
+        m.mass = _ptr(self._keep[0])
+        if self.molid is not None:
+            self._keep.append(np.ascontiguousarray(self.molid, dtype=np.int32))
+            m.molid = self._keep[-1].ctypes.data_as(_ip)
+        if self.lj is not None:
+            self._keep.append(np.ascontiguousarray(self.lj, dtype=np.float64))
+            m.lj = _ptr(self._keep[-1])
+        m.rigid = 1 if self.rigid else 0
+        for d in range(3):
+            m.tri[d] = float(self.tri[d])
+        m.tol = float(self.tol)
+        return m
+
+
+def _md_lib():
+    L = lib()
+    if not getattr(L, "_md_ready", False):
+        L.orc_md_forces.restype = C.c_int
+        L.orc_md_forces.argtypes = [C.POINTER(_Params), C.POINTER(_Model), C.c_int64, _dp, _dp, _dp, _dp]
+        L.orc_vv.restype = C.c_int
+        L.orc_vv.argtypes = [C.POINTER(_Params), C.POINTER(_Model), C.c_int64, _dp, _dp, _dp, C.c_double, C.c_int,
+                             _dp, _dp]
+        L.orc_parareal.restype = C.c_int
+        L.orc_parareal.argtypes = [C.POINTER(_Params), C.POINTER(_Params), C.POINTER(_Model), C.c_int64, _dp, _dp,
+                                   C.c_int, C.c_int, C.c_double, C.c_int, C.c_double, C.c_int, C.c_double, _dp,
+                                   C.POINTER(C.c_int), _dp]
+        L._md_ready = True
+    return L
+
+
+def md_forces(p: OracleParams, model: OracleModel, xyz, q):
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    f = np.zeros_like(xyz)
+    e = np.zeros(1)
+    cp, cm = p.c(), model.c()
+    rc = _md_lib().orc_md_forces(C.byref(cp), C.byref(cm), xyz.shape[0], _ptr(xyz), _ptr(q), _ptr(e), _ptr(f))
+    if rc != 0:
+        raise RuntimeError(f"oracle md_forces failed with code {rc}")
+    return float(e[0]), f
+
+
+def vv(p: OracleParams, model: OracleModel, xyz, v, q, dt, nsteps):
+    """Run nsteps of velocity Verlet; returns new (xyz, v, epot, ekin)."""
+    x = np.array(xyz, dtype=np.float64).reshape(-1, 3)
+    vv_ = np.array(v, dtype=np.float64).reshape(-1, 3)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    ep, ek = np.zeros(1), np.zeros(1)
+    cp, cm = p.c(), model.c()
+    rc = _md_lib().orc_vv(C.byref(cp), C.byref(cm), x.shape[0], _ptr(x), _ptr(vv_), _ptr(q), float(dt),
+                          int(nsteps), _ptr(ep), _ptr(ek))
+    if rc != 0:
+        raise RuntimeError(f"oracle vv failed with code {rc}")
+    return x, vv_, float(ep[0]), float(ek[0])
+
+
+def parareal(pf: OracleParams, pg: OracleParams, model: OracleModel, xyz, v, q, nslices, steps_f, dt_f,
+             steps_g, dt_g, kmax, tol):
+    """Returns (lambda[(nslices+1), n, 6], iterations, residual per iteration, return code)."""
+    x = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    n = x.shape[0]
+    state = np.ascontiguousarray(np.concatenate([x, np.asarray(v, dtype=np.float64).reshape(-1, 3)], axis=1))
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    lam = np.zeros((nslices + 1, n, 6))
+    iters = C.c_int(0)
+    resid = np.zeros(max(kmax, 1))
+    cf, cg, cm = pf.c(), pg.c(), model.c()
+    rc = _md_lib().orc_parareal(C.byref(cf), C.byref(cg), C.byref(cm), n, _ptr(q), _ptr(state), int(nslices),
+                                int(steps_f), float(dt_f), int(steps_g), float(dt_g), int(kmax), float(tol),
+                                _ptr(lam), C.byref(iters), _ptr(resid))
+    if rc < 0:
+        raise RuntimeError(f"oracle parareal failed with code {rc}")
+    return lam, iters.value, resid[:iters.value], rc

@@ -1,0 +1,307 @@
+/*
+ * FP64 CPU oracle for velocity-Verlet dynamics on the multilevel summation
+ * method and for the parareal iteration over it.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test suite, the package smoke check
+ * and the CPU-baseline leg of the benchmark. Shares no code with the HIP
+ * library.
+ *
+ * The paper (Section 2) moves particles under F = -dU_all/dr with velocity
+ * Verlet or leapfrog, U_all including bonded, van der Waals and Coulomb terms;
+ * it gives no force field. The model here (a reading): rigid three-site
+ * molecules held by RATTLE (Andersen 1983), Coulomb by MSM with the pairs
+ * inside one molecule excluded, and Lennard-Jones with Lorentz-Berthelot
+ * mixing, cut and shifted at the MSM cutoff a.
+ * Parareal follows Section 4: lambda_{n+1}^{k+1} = G(lambda_n^{k+1}) +
+ * F(lambda_n^k) - G(lambda_n^k), started from a coarse sweep.
+ */
+#include "md_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ---- Coulomb pairs inside one molecule: remove k q_i q_j / r (atoms of a molecule are contiguous) ---- */
+static void exclusions(const orc_params *p, const orc_model *m, int64_t n, const double *xyz, const double *q,
+                       double *e, double *f)
+{
+    if (!m->molid) return;
+    double acc = 0;
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t j = i + 1; j < n && m->molid[j] == m->molid[i]; j++) {
+            double d[3], r2 = 0;
+            for (int c = 0; c < 3; c++) {
+                d[c] = xyz[3 * i + c] - xyz[3 * j + c];
+                r2 += d[c] * d[c];
+            }
+            double r = sqrt(r2);
+            double u = p->ke * q[i] * q[j] / r;
+            acc += u;
+            for (int c = 0; c < 3; c++) {
+                double fc = u / r2 * d[c];      /* force of the pair on i */
+                f[3 * i + c] -= fc;
+                f[3 * j + c] += fc;
+            }
+        }
+    *e -= acc;
+}
+
+/* ---- Lennard-Jones 4 eps ((s/r)^12 - (s/r)^6), shifted to zero at the cutoff a ---- */
+static double lj_pair(double s, double eps, double r2, double rc2, double *fscal)
+{
+    double sr2 = s * s / r2, sr6 = sr2 * sr2 * sr2;
+    double sc2 = s * s / rc2, sc6 = sc2 * sc2 * sc2;
+    *fscal = 24.0 * eps * (2.0 * sr6 * sr6 - sr6) / r2;   /* F_i = fscal (r_i - r_j) */
+    return 4.0 * eps * (sr6 * sr6 - sr6) - 4.0 * eps * (sc6 * sc6 - sc6);
+}
+
+static void lennard_jones(const orc_params *p, const orc_model *m, int64_t n, const double *xyz, double *e, double *f)
+{
+    if (!m->lj || n == 0) return;
+    double rc = p->a, rc2 = rc * rc;
+    int nc[3];
+    double cs[3];
+    for (int d = 0; d < 3; d++) {
+        double len = p->hi[d] - p->lo[d];
+        nc[d] = (int)floor(len / (rc * 1.000001));
+        if (nc[d] < 1) nc[d] = 1;
+        cs[d] = len / nc[d];
+    }
+    int64_t ncell = (int64_t)nc[0] * nc[1] * nc[2];
+    int64_t *head = malloc(sizeof(int64_t) * ncell), *next = malloc(sizeof(int64_t) * n);
+    int *cell = malloc(sizeof(int) * 3 * n);
+    for (int64_t c = 0; c < ncell; c++) head[c] = -1;
+    for (int64_t i = n - 1; i >= 0; i--) {
+        int c3[3];
+        for (int d = 0; d < 3; d++) {
+            int c = (int)floor((xyz[3 * i + d] - p->lo[d]) / cs[d]);
+            c3[d] = c < 0 ? 0 : (c >= nc[d] ? nc[d] - 1 : c);
+            cell[3 * i + d] = c3[d];
+        }
+        int64_t id = ((int64_t)c3[2] * nc[1] + c3[1]) * nc[0] + c3[0];
+        next[i] = head[id];
+        head[id] = i;
+    }
+    double *ei = calloc(n, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; i++) {
+        if (m->lj[2 * i + 1] == 0.0) continue;
+        double fx = 0, fy = 0, fz = 0, u = 0;
+        for (int dz = -1; dz <= 1; dz++)
+            for (int dy = -1; dy <= 1; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    int cx = cell[3 * i] + dx, cy = cell[3 * i + 1] + dy, cz = cell[3 * i + 2] + dz;
+                    if (cx < 0 || cy < 0 || cz < 0 || cx >= nc[0] || cy >= nc[1] || cz >= nc[2]) continue;
+                    for (int64_t j = head[((int64_t)cz * nc[1] + cy) * nc[0] + cx]; j >= 0; j = next[j]) {
+                        if (j == i || m->lj[2 * j + 1] == 0.0) continue;
+                        if (m->molid && m->molid[i] == m->molid[j]) continue;
+                        double d[3], r2 = 0;
+                        for (int c = 0; c < 3; c++) {
+                            d[c] = xyz[3 * i + c] - xyz[3 * j + c];
+                            r2 += d[c] * d[c];
+                        }
+                        if (!(r2 < rc2)) continue;
+                        double s = 0.5 * (m->lj[2 * i] + m->lj[2 * j]);
+                        double eps = sqrt(m->lj[2 * i + 1] * m->lj[2 * j + 1]);
+                        double fs;
+                        u += lj_pair(s, eps, r2, rc2, &fs);
+                        fx += fs * d[0];
+                        fy += fs * d[1];
+                        fz += fs * d[2];
+                    }
+                }
+        f[3 * i] += fx;
+        f[3 * i + 1] += fy;
+        f[3 * i + 2] += fz;
+        ei[i] = u;
+    }
+    double acc = 0;
+    for (int64_t i = 0; i < n; i++) acc += ei[i];
+    *e += 0.5 * acc;
+    free(ei);
+    free(head);
+    free(next);
+    free(cell);
+}
+
+int orc_md_forces(const orc_params *p, const orc_model *m, int64_t n, const double *xyz, const double *q,
+                  double *epot, double *forces)
+{
+    double e = 0;
+    int rc = orc_msm(p, n, xyz, q, &e, forces, NULL, NULL);
+    if (rc) return rc;
+    exclusions(p, m, n, xyz, q, &e, forces);
+    lennard_jones(p, m, n, xyz, &e, forces);
+    if (epot) *epot = e;
+    return 0;
+}
+
+/* ---- RATTLE (Andersen 1983) for rigid triples ---- */
+static const int tri_a[3] = {0, 0, 1}, tri_b[3] = {1, 2, 2};
+
+/* positions: bring |r'_a - r'_b| to d along the previous bond vectors, and
+ * carry the same displacement into the half-step velocities */
+static void rattle_positions(const orc_model *m, int64_t n, const double *xold, double *x, double *v, double dt)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < n / 3; t++) {
+        for (int it = 0; it < 1000; it++) {
+            int done = 1;
+            for (int c = 0; c < 3; c++) {
+                int64_t a = 3 * t + tri_a[c], b = 3 * t + tri_b[c];
+                double d = m->tri[c];
+                double s[3], r[3], ss = 0, sr = 0;
+                for (int k = 0; k < 3; k++) {
+                    s[k] = x[3 * a + k] - x[3 * b + k];
+                    r[k] = xold[3 * a + k] - xold[3 * b + k];
+                    ss += s[k] * s[k];
+                    sr += s[k] * r[k];
+                }
+                double diff = d * d - ss;
+                if (fabs(diff) <= 2.0 * m->tol * d * d) continue;
+                done = 0;
+                double ia = 1.0 / m->mass[a], ib = 1.0 / m->mass[b];
+                double g = diff / (2.0 * sr * (ia + ib));
+                for (int k = 0; k < 3; k++) {
+                    x[3 * a + k] += g * ia * r[k];
+                    x[3 * b + k] -= g * ib * r[k];
+                    v[3 * a + k] += g * ia * r[k] / dt;
+                    v[3 * b + k] -= g * ib * r[k] / dt;
+                }
+            }
+            if (done) break;
+        }
+    }
+}
+
+/* velocities: remove the relative velocity along every bond */
+static void rattle_velocities(const orc_model *m, int64_t n, const double *x, double *v)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < n / 3; t++) {
+        for (int it = 0; it < 1000; it++) {
+            int done = 1;
+            for (int c = 0; c < 3; c++) {
+                int64_t a = 3 * t + tri_a[c], b = 3 * t + tri_b[c];
+                double d = m->tri[c];
+                double r[3], w[3], rw = 0;
+                for (int k = 0; k < 3; k++) {
+                    r[k] = x[3 * a + k] - x[3 * b + k];
+                    w[k] = v[3 * a + k] - v[3 * b + k];
+                    rw += r[k] * w[k];
+                }
+                double ia = 1.0 / m->mass[a], ib = 1.0 / m->mass[b];
+                double kk = rw / ((ia + ib) * d * d);
+                if (fabs(rw) <= m->tol * d * d) continue;
+                done = 0;
+                for (int k = 0; k < 3; k++) {
+                    v[3 * a + k] -= kk * ia * r[k];
+                    v[3 * b + k] += kk * ib * r[k];
+                }
+            }
+            if (done) break;
+        }
+    }
+}
+
+/* ---- Section 2: velocity Verlet ---- */
+int orc_vv(const orc_params *p, const orc_model *m, int64_t n, double *xyz, double *v, const double *q,
+           double dt, int nsteps, double *epot, double *ekin)
+{
+    double *f = malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
+    double *xold = malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
+    double e = 0;
+    int rc = orc_md_forces(p, m, n, xyz, q, &e, f);
+    for (int s = 0; rc == 0 && s < nsteps; s++) {
+        memcpy(xold, xyz, sizeof(double) * 3 * n);
+        for (int64_t i = 0; i < n; i++)
+            for (int k = 0; k < 3; k++) {
+                v[3 * i + k] += 0.5 * dt * f[3 * i + k] / m->mass[i];
+                xyz[3 * i + k] += dt * v[3 * i + k];
+            }
+        if (m->rigid) rattle_positions(m, n, xold, xyz, v, dt);
+        rc = orc_md_forces(p, m, n, xyz, q, &e, f);
+        if (rc) break;
+        for (int64_t i = 0; i < n; i++)
+            for (int k = 0; k < 3; k++) v[3 * i + k] += 0.5 * dt * f[3 * i + k] / m->mass[i];
+        if (m->rigid) rattle_velocities(m, n, xyz, v);
+    }
+    if (epot) *epot = e;
+    if (ekin) {
+        double k = 0;
+        for (int64_t i = 0; i < n; i++)
+            k += 0.5 * m->mass[i] * (v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2]);
+        *ekin = k;
+    }
+    free(f);
+    free(xold);
+    return rc;
+}
+
+/* ---- Section 4: parareal ---- */
+static int propagate(const orc_params *p, const orc_model *m, int64_t n, const double *q, const double *in,
+                     double *out, int steps, double dt, double *x, double *v)
+{
+    for (int64_t i = 0; i < n; i++)
+        for (int k = 0; k < 3; k++) {
+            x[3 * i + k] = in[6 * i + k];
+            v[3 * i + k] = in[6 * i + 3 + k];
+        }
+    int rc = orc_vv(p, m, n, x, v, q, dt, steps, NULL, NULL);
+    for (int64_t i = 0; i < n; i++)
+        for (int k = 0; k < 3; k++) {
+            out[6 * i + k] = x[3 * i + k];
+            out[6 * i + 3 + k] = v[3 * i + k];
+        }
+    return rc;
+}
+
+int orc_parareal(const orc_params *pf, const orc_params *pg, const orc_model *m, int64_t n, const double *q,
+                 const double *state0, int nslices, int steps_f, double dt_f, int steps_g, double dt_g, int kmax,
+                 double tol, double *lambda, int *iters, double *resid)
+{
+    if (nslices < 1 || kmax < 0 || n < 0) return -1;
+    const size_t S = (size_t)6 * n;
+    double *gold = malloc(sizeof(double) * S * (nslices + 1));
+    double *fout = malloc(sizeof(double) * S * (nslices + 1));
+    double *gnew = malloc(sizeof(double) * S);
+    double *x = malloc(sizeof(double) * 3 * (n > 0 ? n : 1)), *v = malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
+    int rc = 0, done = 0;
+    memcpy(lambda, state0, sizeof(double) * S);
+    /* initial coarse sweep: lambda^0_{n+1} = G(lambda^0_n) */
+    for (int s = 0; s < nslices && !rc; s++) {
+        rc = propagate(pg, m, n, q, lambda + S * s, lambda + S * (s + 1), steps_g, dt_g, x, v);
+        memcpy(gold + S * (s + 1), lambda + S * (s + 1), sizeof(double) * S);
+    }
+    *iters = 0;
+    for (int k = 0; k < kmax && !rc && !done; k++) {
+        /* fine propagator on every slice not yet exact (slices < k are) */
+        for (int s = k; s < nslices && !rc; s++)
+            rc = propagate(pf, m, n, q, lambda + S * s, fout + S * (s + 1), steps_f, dt_f, x, v);
+        /* serial correction sweep: lambda_{s+1} = F(lambda^k_s) + (G(lambda^{k+1}_s) - G(lambda^k_s)) */
+        double change = 0;
+        for (int s = k; s < nslices && !rc; s++) {
+            rc = propagate(pg, m, n, q, lambda + S * s, gnew, steps_g, dt_g, x, v);
+            double *lam = lambda + S * (s + 1), *fo = fout + S * (s + 1), *go = gold + S * (s + 1);
+            for (size_t e = 0; e < S; e++) {
+                double nv = fo[e] + (gnew[e] - go[e]);
+                if (e % 6 < 3) {
+                    double c = fabs(nv - lam[e]);
+                    if (c > change) change = c;
+                }
+                lam[e] = nv;
+                go[e] = gnew[e];
+            }
+        }
+        resid[k] = change;
+        *iters = k + 1;
+        if (change < tol || k + 1 >= nslices) done = 1;
+    }
+    free(gold);
+    free(fout);
+    free(gnew);
+    free(x);
+    free(v);
+    if (rc) return rc;
+    return done ? 0 : 1;
+}

@@ -1,0 +1,45 @@
+/*
+ * FP64 CPU oracle for velocity-Verlet dynamics driven by the multilevel
+ * summation method, and for the parareal iteration over it.
+ *
+ * TEST INFRASTRUCTURE ONLY (see msm_oracle.h).
+ */
+#ifndef MD_ORACLE_H
+#define MD_ORACLE_H
+#include <stdint.h>
+
+#include "msm_oracle.h"
+
+/* Molecular model of a run. Atoms of one molecule are contiguous. */
+typedef struct {
+    const double *mass;     /* n */
+    const int32_t *molid;   /* n, or NULL: no excluded pairs */
+    const double *lj;       /* n x 2 (sigma, epsilon), Lorentz-Berthelot mixing, cut and
+                               shifted to zero at the MSM cutoff a; NULL: none */
+    int rigid;              /* 1: atoms (3m, 3m+1, 3m+2) keep fixed mutual distances */
+    double tri[3];          /* |r0-r1|, |r0-r2|, |r1-r2| of every rigid triple */
+    double tol;             /* relative tolerance of the constraint iteration */
+} orc_model;
+
+/* Potential energy and forces: MSM Coulomb with intramolecular pairs
+ * excluded, plus Lennard-Jones. */
+int orc_md_forces(const orc_params *p, const orc_model *m, int64_t n, const double *xyz, const double *q,
+                  double *epot, double *forces);
+
+/* nsteps of velocity Verlet (with RATTLE for rigid triples) in place.
+ * epot/ekin receive the energies after the last step (may be NULL). */
+int orc_vv(const orc_params *p, const orc_model *m, int64_t n, double *xyz, double *v, const double *q,
+           double dt, int nsteps, double *epot, double *ekin);
+
+/* Parareal (Section 4) over nslices slices of the fine propagator
+ * (pf, steps_f x dt_f) with the coarse one (pg, steps_g x dt_g).
+ * state0: n x 6 (x y z vx vy vz). lambda: (nslices+1) x n x 6, out.
+ * Stops at the first iteration whose largest position change is below tol
+ * or after kmax iterations; *iters receives the number done and resid[k]
+ * the position change of iteration k (kmax entries). Returns 0, 1 when not
+ * converged, or a negative error. */
+int orc_parareal(const orc_params *pf, const orc_params *pg, const orc_model *m, int64_t n, const double *q,
+                 const double *state0, int nslices, int steps_f, double dt_f, int steps_g, double dt_g, int kmax,
+                 double tol, double *lambda, int *iters, double *resid);
+
+#endif

@@ -14,6 +14,7 @@ from .binding import (  # noqa: F401
     MsmContext,
     lib,
     lib_path,
+    parareal,
     status_string,
 )
 from .autograd import msm_energy  # noqa: F401

@@ -23,6 +23,21 @@ class MsmError(RuntimeError):
         super().__init__(f"{what}: {status_string(code)} ({code})" if what else f"{status_string(code)} ({code})")
 
 
+class _Model(C.Structure):
+    _fields_ = [("period", C.c_int64), ("molid_dev", C.c_void_p), ("lj_dev", C.c_void_p),
+                ("rigid_triples", C.c_int), ("tri_len", C.c_double * 3), ("constraint_tol", C.c_double)]
+
+
+class _PararealParams(C.Structure):
+    _fields_ = [("nslices", C.c_int), ("kmax", C.c_int), ("tol", C.c_double), ("steps_f", C.c_int),
+                ("dt_f", C.c_double), ("steps_g", C.c_int), ("dt_g", C.c_double)]
+
+
+class _PararealReport(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("residual", C.c_double * 64),
+                ("seconds", C.c_double)]
+
+
 class _Params(C.Structure):
     _fields_ = [("a", C.c_double), ("h", C.c_double), ("levels", C.c_int), ("precision", C.c_int),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("coulomb_k", C.c_double),
@@ -64,6 +79,14 @@ def lib():
         L.msm_enable_stage_timing.restype = C.c_int
         L.msm_stage_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
         L.msm_stage_timing.restype = C.c_int
+        L.msm_md_bind.argtypes = [vp, C.POINTER(_Model)]
+        L.msm_md_bind.restype = C.c_int
+        L.msm_vv_run.argtypes = [vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double), vp, vp, C.c_int,
+                                 C.c_double, vp, vp]
+        L.msm_vv_run.restype = C.c_int
+        L.parareal_run.argtypes = [vp, vp, C.POINTER(_PararealParams), C.c_int64, vp, vp, vp, vp,
+                                   C.POINTER(_PararealReport)]
+        L.parareal_run.restype = C.c_int
         _lib = L
         return L
 
@@ -227,3 +250,65 @@ class MsmContext:
         out["u_short"] = us
         out["f_short"] = fs
         return out
+
+
+    # ------------------------------------------------------------------
+    # dynamics
+    # ------------------------------------------------------------------
+    def bind_model(self, period, molid=None, lj=None, rigid=False, tri=(0.0, 0.0, 0.0), tol=0.0):
+        """Bind a molecular model (see msm_md_model): ``molid`` int32 and ``lj``
+        float64 (period, 2) device tensors, or None."""
+        m = _Model()
+        m.period = int(period)
+        m.molid_dev = None if molid is None else molid.data_ptr()
+        m.lj_dev = None if lj is None else lj.data_ptr()
+        m.rigid_triples = 1 if rigid else 0
+        for d in range(3):
+            m.tri_len[d] = float(tri[d])
+        m.constraint_tol = float(tol)
+        self._model_refs = (molid, lj)
+        _check(lib().msm_md_bind(self._h, C.byref(m)), "msm_md_bind")
+
+    def vv_run(self, xyzq, vel, nsteps, dt, offsets=None, domains=None, energies=True):
+        """Velocity Verlet in place on xyzq (N, 4) and vel (N, 4: v, 1/m).
+        Returns (epot, ekin) float64 tensors of length nsys, or None."""
+        import torch
+        n = xyzq.shape[0]
+        if offsets is None:
+            offsets = [0, n]
+        offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        nsys = len(offs) - 1
+        dom_p = None
+        if domains is not None:
+            dom = np.ascontiguousarray(np.asarray(domains, dtype=np.float64).reshape(nsys, 6))
+            dom_p = dom.ctypes.data_as(C.POINTER(C.c_double))
+        ep = ek = None
+        if energies:
+            ep = torch.empty(nsys, dtype=torch.float64, device=xyzq.device)
+            ek = torch.empty(nsys, dtype=torch.float64, device=xyzq.device)
+        ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+        _check(lib().msm_vv_run(self._h, nsys, offs.ctypes.data_as(C.POINTER(C.c_int64)), dom_p, ptr(xyzq),
+                                ptr(vel), int(nsteps), float(dt), ptr(ep), ptr(ek)), "msm_vv_run")
+        return ep, ek
+
+
+def parareal(fine, coarse, charges, invmass, state0, *, nslices, kmax, tol, steps_f, dt_f, steps_g, dt_g,
+             lam=None):
+    """Parareal over ``nslices`` slices (see parareal_run). ``charges``,
+    ``invmass`` (natoms,) and ``state0`` (natoms, 6) are float64 device
+    tensors. Returns (lambda[(nslices+1), natoms, 6], report dict, return code)."""
+    import torch
+    n = state0.shape[0]
+    if lam is None:
+        lam = torch.empty((nslices + 1, n, 6), dtype=torch.float64, device=state0.device)
+    pp = _PararealParams()
+    pp.nslices, pp.kmax, pp.tol = int(nslices), int(kmax), float(tol)
+    pp.steps_f, pp.dt_f, pp.steps_g, pp.dt_g = int(steps_f), float(dt_f), int(steps_g), float(dt_g)
+    rep = _PararealReport()
+    rc = lib().parareal_run(fine._h, coarse._h, C.byref(pp), n, C.c_void_p(charges.data_ptr()),
+                            C.c_void_p(invmass.data_ptr()), C.c_void_p(state0.data_ptr()),
+                            C.c_void_p(lam.data_ptr()), C.byref(rep))
+    _check(rc, "parareal_run")
+    report = {"iterations": rep.iterations, "converged": bool(rep.converged),
+              "residual": list(rep.residual[:min(rep.iterations, 64)]), "seconds": rep.seconds}
+    return lam, report, rc

@@ -140,7 +140,8 @@ __global__ void k_scatter(int64_t n, const int *__restrict__ cell_of, const int 
 
 template <typename T>
 __global__ void k_cell_sort(int64_t ncells, const int *__restrict__ start, int *__restrict__ order,
-                            const vec4_t<T> *__restrict__ xyzq, vec4_t<T> *__restrict__ sxyzq)
+                            const vec4_t<T> *__restrict__ xyzq, vec4_t<T> *__restrict__ sxyzq,
+                            const vec4_t<T> *__restrict__ maux, vec4_t<T> *__restrict__ saux, int64_t period)
 {
     int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= ncells) return;
@@ -155,6 +156,8 @@ __global__ void k_cell_sort(int64_t ncells, const int *__restrict__ start, int *
         order[j + 1] = v;
     }
     for (int i = b; i < e; i++) sxyzq[i] = xyzq[order[i]];
+    if (maux)
+        for (int i = b; i < e; i++) saux[i] = maux[order[i] % period];
 }
 
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -202,7 +205,7 @@ hipError_t Launch<T>::bin(hipStream_t s, const DevPlan &p, const Work<T> &w, con
         hipLaunchKernelGGL(k_scatter, dim3(nblocks(p.natoms, 256)), dim3(256), 0, s, p.natoms, w.cell_of,
                            w.slot_of, w.cell_start, w.order);
         hipLaunchKernelGGL(k_cell_sort<T>, dim3(nblocks(p.ncells, 256)), dim3(256), 0, s, p.ncells,
-                           w.cell_start, w.order, xyzq, w.sxyzq);
+                           w.cell_start, w.order, xyzq, w.sxyzq, (const vec4_t<T> *)w.maux, w.saux, w.period);
     }
     return hipGetLastError();
 }

@@ -9,9 +9,7 @@
 #include <new>
 #include <vector>
 
-#include "../../include/msm.h"
 #include "engine.h"
-#include "launch.h"
 
 using namespace msmx;
 
@@ -34,13 +32,6 @@ int auto_levels(double h, const double *len)
     }
     return kMaxLevels;
 }
-
-struct Geometry {
-    int nlev;
-    int nc[3];
-    int gorg[kMaxLevels][3];
-    int gdim[kMaxLevels][3];
-};
 
 int geometry(const msm_params &prm, const double *lo, const double *hi, Geometry &g)
 {
@@ -87,38 +78,6 @@ template <typename T> size_t vec_bytes() { return sizeof(vec4_t<T>); }
 
 }  // namespace
 
-struct msm_ctx {
-    msm_params prm;
-    hipStream_t stream = nullptr;
-    int device = 0;
-    MethodConst mc{};
-    int d2max = 0;
-    Geometry ctx_geom{};
-    // capacities
-    int64_t cap_cells = 0, cap_q = 0, cap_u = 0, cap_iblk = 0;
-    // device memory
-    char *wbuf = nullptr;
-    size_t wbytes = 0;
-    void *weights = nullptr;     // stencil weights along z per quarter-disc column, precision T
-    int2 *wcols = nullptr;       // quarter-disc columns (ox, oy)
-    int ncols = 0;
-    char *plan_dev = nullptr;    // tables of the current batch
-    char *plan_host = nullptr;   // pinned staging copy
-    size_t plan_cap = 0;
-    DevPlan dp{};
-    bool plan_valid = false;
-    std::vector<int64_t> last_offsets;
-    std::vector<double> last_domains;
-    std::vector<SysPlan> host_sys;
-    Work<float> wf{};
-    Work<double> wd{};
-    // stage timing (benchmarks)
-    bool timing = false;
-    hipEvent_t ev[MSM_NSTAGES + 1] = {};
-    double stage_ms[MSM_NSTAGES] = {};
-    int64_t timed_evals = 0;
-};
-
 namespace {
 
 int hip_status(hipError_t e) { return e == hipSuccess ? MSM_OK : MSM_ERR_HIP; }
@@ -148,8 +107,10 @@ template <typename T> void carve(msm_ctx *c, Work<T> &w, char *base, size_t *use
     (void)commit;
 }
 
+}  // namespace
+
 // Build the device tables of a batch; returns MSM_OK or an error.
-int build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double *domains)
+int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double *domains)
 {
     if (c->plan_valid && (int)c->last_offsets.size() == nsys + 1 &&
         std::equal(offsets, offsets + nsys + 1, c->last_offsets.begin())) {
@@ -309,6 +270,8 @@ int build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double *domai
     return MSM_OK;
 }
 
+namespace {
+
 template <typename T> Work<T> &work(msm_ctx *c);
 template <> Work<float> &work<float>(msm_ctx *c) { return c->wf; }
 template <> Work<double> &work<double>(msm_ctx *c) { return c->wd; }
@@ -359,6 +322,16 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     return MSM_OK;
 }
 
+}  // namespace
+
+int msmx::evaluate_any(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *pots)
+{
+    if (c->prm.precision == MSM_FP32) return evaluate<float>(c, xyzq, energy, forces, pots);
+    return evaluate<double>(c, xyzq, energy, forces, pots);
+}
+
+namespace {
+
 // Quarter-disc columns (ox, oy >= 0, ox^2 + oy^2 <= d2max) and, per column,
 // the weights g^0(h |o|) = gamma(h|o|/a)/a - gamma(h|o|/(2a))/(2a) for
 // oz = -R .. R (zero where |o|^2 > d2max: g^0 vanishes for r >= 2a).
@@ -399,8 +372,6 @@ template <typename T> int upload_stencil(msm_ctx *c)
 
 }  // namespace
 
-int msmx_ctx_precision(const msm_ctx *c) { return c->prm.precision; }
-hipStream_t msmx_ctx_stream(const msm_ctx *c) { return c->stream; }
 
 extern "C" {
 
@@ -500,6 +471,7 @@ void msm_destroy(msm_ctx *c)
     if (c->wcols) (void)hipFree(c->wcols);
     if (c->plan_dev) (void)hipFree(c->plan_dev);
     if (c->plan_host) (void)hipHostFree(c->plan_host);
+    if (c->mdbuf) (void)hipFree(c->mdbuf);
     delete c;
 }
 

@@ -1,9 +1,75 @@
-// Internal interface between the engine and the integrator translation units.
+// Internal interface of the engine: the context and the plan/evaluation
+// entry points shared by the C-ABI translation units.
 #pragma once
 
 #include <hip/hip_runtime.h>
 
-struct msm_ctx;
+#include <vector>
 
-int msmx_ctx_precision(const msm_ctx *c);
-hipStream_t msmx_ctx_stream(const msm_ctx *c);
+#include "../../include/msm.h"
+#include "launch.h"
+#include "md.h"
+
+namespace msmx {
+
+struct Geometry {
+    int nlev;
+    int nc[3];
+    int gorg[kMaxLevels][3];
+    int gdim[kMaxLevels][3];
+};
+
+}  // namespace msmx
+
+struct msm_ctx {
+    msm_params prm;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    msmx::MethodConst mc{};
+    int d2max = 0;
+    msmx::Geometry ctx_geom{};
+    // capacities
+    int64_t cap_cells = 0, cap_q = 0, cap_u = 0, cap_iblk = 0;
+    // device memory
+    char *wbuf = nullptr;
+    size_t wbytes = 0;
+    void *weights = nullptr;     // stencil weights along z per quarter-disc column, precision T
+    int2 *wcols = nullptr;       // quarter-disc columns (ox, oy)
+    int ncols = 0;
+    char *plan_dev = nullptr;    // tables of the current batch
+    char *plan_host = nullptr;   // pinned staging copy
+    size_t plan_cap = 0;
+    msmx::DevPlan dp{};
+    bool plan_valid = false;
+    std::vector<int64_t> last_offsets;
+    std::vector<double> last_domains;
+    std::vector<msmx::SysPlan> host_sys;
+    msmx::Work<float> wf{};
+    msmx::Work<double> wd{};
+    // stage timing (benchmarks)
+    bool timing = false;
+    hipEvent_t ev[MSM_NSTAGES + 1] = {};
+    double stage_ms[MSM_NSTAGES] = {};
+    int64_t timed_evals = 0;
+    // dynamics (msm_md_bind)
+    bool md_bound = false;
+    bool rigid = false;
+    msmx::TriModel tri{};
+    char *mdbuf = nullptr;       // model, forces and parareal scratch
+    void *md_forces = nullptr;   // max_atoms x 3, precision T
+    double *md_parts = nullptr;  // per-block partial sums (kinetic energy)
+    double *md_scalar = nullptr; // scratch scalars (change of a parareal iteration, ...)
+    void *px = nullptr, *pv = nullptr;          // propagator state, max_atoms x 4 each, precision T
+    double *fout = nullptr, *gold = nullptr;    // parareal: fine results and coarse values, max_atoms x 6
+    double *gnew = nullptr;                     // parareal: coarse result of one slice, max_atoms x 6
+};
+
+
+namespace msmx {
+
+// Build (or reuse) the device tables of a batch.
+int build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double *domains);
+// One evaluation of the current plan on xyzq (precision of the context).
+int evaluate_any(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *pots);
+
+}  // namespace msmx

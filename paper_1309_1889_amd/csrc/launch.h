@@ -42,6 +42,11 @@ template <typename T> struct Work {
     T *ugrid;            // prolongated potentials u^k
     double *eparts;      // per interpolation block: sum q_i phi_i
     int *status;         // device status word
+    // dynamics model (null when no model is bound)
+    vec4_t<T> *maux;     // per model atom: (molecule id bits, sigma/2, sqrt(eps), 0)
+    vec4_t<T> *saux;     // sorted copy of maux
+    vec4_t<T> *shlj;     // sorted order: Lennard-Jones force and energy
+    int64_t period;      // batch atom i uses model entry i % period
 };
 
 // Quarter-disc stencil columns (ox >= 0, oy >= 0 inside the sphere) and their

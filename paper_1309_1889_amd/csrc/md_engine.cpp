@@ -1,0 +1,264 @@
+// Host side of the dynamics entry points: model binding, velocity Verlet on a
+// batch of systems, and the parareal iteration (Section 4) with a batched
+// fine propagator and a serial coarse sweep.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "engine.h"
+
+using namespace msmx;
+
+namespace {
+
+template <typename T> Work<T> &work_of(msm_ctx *c);
+template <> Work<float> &work_of<float>(msm_ctx *c) { return c->wf; }
+template <> Work<double> &work_of<double>(msm_ctx *c) { return c->wd; }
+
+size_t up256(size_t b) { return (b + 255) / 256 * 256; }
+
+template <typename T> int bind(msm_ctx *c, const msm_md_model *m)
+{
+    const int64_t na = std::max<int64_t>(c->prm.max_atoms, 1);
+    const int64_t period = m->period;
+    if (period < 1) return MSM_ERR_ARG;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
+    if (c->mdbuf) {
+        (void)hipFree(c->mdbuf);
+        c->mdbuf = nullptr;
+    }
+    const bool aux = m->molid_dev || m->lj_dev;
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        size_t o = off;
+        off += up256(b);
+        return o;
+    };
+    const size_t o_maux = aux ? take(sizeof(vec4_t<T>) * period) : 0;
+    const size_t o_saux = aux ? take(sizeof(vec4_t<T>) * (na + 64)) : 0;
+    const size_t o_shlj = aux ? take(sizeof(vec4_t<T>) * na) : 0;
+    const size_t o_f = take(sizeof(T) * 3 * na);
+    const size_t o_parts = take(sizeof(double) * c->cap_iblk);
+    const size_t o_scal = take(sizeof(double) * 64);
+    const size_t o_px = take(sizeof(vec4_t<T>) * na), o_pv = take(sizeof(vec4_t<T>) * na);
+    const size_t o_fout = take(sizeof(double) * 6 * na), o_gold = take(sizeof(double) * 6 * na);
+    const size_t o_gnew = take(sizeof(double) * 6 * na);
+    if (hipMalloc((void **)&c->mdbuf, off) != hipSuccess) return MSM_ERR_HIP;
+    if (hipMemsetAsync(c->mdbuf, 0, off, c->stream) != hipSuccess) return MSM_ERR_HIP;
+    char *b = c->mdbuf;
+    Work<T> &w = work_of<T>(c);
+    w.maux = aux ? (vec4_t<T> *)(b + o_maux) : nullptr;
+    w.saux = aux ? (vec4_t<T> *)(b + o_saux) : nullptr;
+    w.shlj = aux ? (vec4_t<T> *)(b + o_shlj) : nullptr;
+    w.period = period;
+    c->md_forces = b + o_f;
+    c->md_parts = (double *)(b + o_parts);
+    c->md_scalar = (double *)(b + o_scal);
+    c->px = b + o_px;
+    c->pv = b + o_pv;
+    c->fout = (double *)(b + o_fout);
+    c->gold = (double *)(b + o_gold);
+    c->gnew = (double *)(b + o_gnew);
+    if (aux) {
+        // per model atom: (molecule id bits, sigma/2, sqrt(epsilon), 0)
+        std::vector<int32_t> mol(period, -1);
+        std::vector<double> lj(2 * period, 0.0);
+        if (m->molid_dev &&
+            hipMemcpy(mol.data(), m->molid_dev, sizeof(int32_t) * period, hipMemcpyDeviceToHost) != hipSuccess)
+            return MSM_ERR_HIP;
+        if (!m->molid_dev)
+            for (int64_t i = 0; i < period; i++) mol[i] = -1 - (int32_t)i;   // every atom its own molecule
+        if (m->lj_dev && hipMemcpy(lj.data(), m->lj_dev, sizeof(double) * 2 * period, hipMemcpyDeviceToHost) != hipSuccess)
+            return MSM_ERR_HIP;
+        std::vector<vec4_t<T>> h(period);
+        for (int64_t i = 0; i < period; i++) {
+            if (lj[2 * i] < 0 || lj[2 * i + 1] < 0 || !std::isfinite(lj[2 * i]) || !std::isfinite(lj[2 * i + 1]))
+                return MSM_ERR_ARG;
+            vec4_t<T> r;
+            if (sizeof(T) == 4) {
+                int32_t bits = mol[i];
+                std::memcpy(&r.x, &bits, 4);
+            } else {
+                int64_t bits = mol[i];
+                std::memcpy(&r.x, &bits, 8);
+            }
+            r.y = T(0.5 * lj[2 * i]);
+            r.z = T(std::sqrt(lj[2 * i + 1]));
+            r.w = T(0);
+            h[i] = r;
+        }
+        if (hipMemcpy(w.maux, h.data(), sizeof(vec4_t<T>) * period, hipMemcpyHostToDevice) != hipSuccess)
+            return MSM_ERR_HIP;
+    }
+    c->rigid = m->rigid_triples != 0;
+    for (int d = 0; d < 3; d++) c->tri.len[d] = m->tri_len[d];
+    c->tri.tol = m->constraint_tol > 0 ? m->constraint_tol : (sizeof(T) == 8 ? 1e-10 : 1e-6);
+    c->tri.max_iter = 500;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
+    c->md_bound = true;
+    return MSM_OK;
+}
+
+// Velocity Verlet on the current plan (built by the caller).
+template <typename T> int vv(msm_ctx *c, void *xyzq, void *vel, int nsteps, double dt, double *epot, double *ekin)
+{
+    using M = MdLaunch<T>;
+    hipStream_t s = c->stream;
+    const int64_t n = c->dp.natoms;
+    vec4_t<T> *x = (vec4_t<T> *)xyzq, *v = (vec4_t<T> *)vel;
+    T *f = (T *)c->md_forces;
+    const TriModel *tm = c->rigid ? &c->tri : nullptr;
+    int rc = evaluate_any(c, x, nsteps == 0 ? epot : nullptr, f, nullptr);
+    if (rc) return rc;
+    for (int st = 0; st < nsteps; st++) {
+        if (M::kick_drift(s, n, x, v, f, dt, tm) != hipSuccess) return MSM_ERR_HIP;
+        rc = evaluate_any(c, x, st == nsteps - 1 ? epot : nullptr, f, nullptr);
+        if (rc) return rc;
+        if (M::kick(s, n, x, v, f, dt, tm) != hipSuccess) return MSM_ERR_HIP;
+    }
+    if (ekin && M::kinetic(s, c->dp, v, c->md_parts, ekin) != hipSuccess) return MSM_ERR_HIP;
+    return MSM_OK;
+}
+
+int vv_any(msm_ctx *c, void *xyzq, void *vel, int nsteps, double dt, double *epot, double *ekin)
+{
+    if (c->prm.precision == MSM_FP32) return vv<float>(c, xyzq, vel, nsteps, dt, epot, ekin);
+    return vv<double>(c, xyzq, vel, nsteps, dt, epot, ekin);
+}
+
+int check_rigid_offsets(const msm_ctx *c, int nsys, const int64_t *offsets)
+{
+    if (!c->rigid) return MSM_OK;
+    for (int s = 0; s <= nsys; s++)
+        if (offsets[s] % 3) return MSM_ERR_ARG;
+    return MSM_OK;
+}
+
+// Propagate `count` consecutive slices of one system of n atoms stored in
+// lam_in (FP64, n x 6 each) and write the results to lam_out.
+int propagate(msm_ctx *c, int64_t n, int count, const double *q, const double *invm, const double *lam_in,
+              double *lam_out, int steps, double dt)
+{
+    std::vector<int64_t> offs(count + 1);
+    for (int i = 0; i <= count; i++) offs[i] = n * i;
+    int rc = build_plan(c, count, offs.data(), nullptr);
+    if (rc) return rc;
+    const int64_t tot = n * count;
+    hipStream_t s = c->stream;
+    if (c->prm.precision == MSM_FP32) {
+        if (MdLaunch<float>::state_in(s, n, tot, lam_in, q, invm, (float4 *)c->px, (float4 *)c->pv) != hipSuccess)
+            return MSM_ERR_HIP;
+    } else if (MdLaunch<double>::state_in(s, n, tot, lam_in, q, invm, (double4 *)c->px, (double4 *)c->pv) !=
+               hipSuccess) {
+        return MSM_ERR_HIP;
+    }
+    rc = vv_any(c, c->px, c->pv, steps, dt, nullptr, nullptr);
+    if (rc) return rc;
+    hipError_t e = c->prm.precision == MSM_FP32
+                       ? MdLaunch<float>::state_out(s, tot, (float4 *)c->px, (float4 *)c->pv, lam_out)
+                       : MdLaunch<double>::state_out(s, tot, (double4 *)c->px, (double4 *)c->pv, lam_out);
+    return e == hipSuccess ? MSM_OK : MSM_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" {
+
+int msm_md_bind(msm_ctx *c, const msm_md_model *m)
+{
+    if (!c || !m) return MSM_ERR_ARG;
+    if (m->rigid_triples) {
+        for (int d = 0; d < 3; d++)
+            if (!(m->tri_len[d] > 0)) return MSM_ERR_ARG;
+        if (m->period % 3) return MSM_ERR_ARG;
+    }
+    return c->prm.precision == MSM_FP32 ? bind<float>(c, m) : bind<double>(c, m);
+}
+
+int msm_vv_run(msm_ctx *c, int nsys, const int64_t *offsets, const double *domains, void *xyzq, void *vel, int nsteps,
+               double dt, double *epot, double *ekin)
+{
+    if (!c || nsys < 1 || !offsets || nsteps < 0 || !(dt > 0)) return MSM_ERR_ARG;
+    if (!c->md_bound) return MSM_ERR_ARG;
+    if (nsys > c->prm.max_systems) return MSM_ERR_CAPACITY;
+    if (offsets[nsys] > 0 && (!xyzq || !vel)) return MSM_ERR_ARG;
+    int rc = check_rigid_offsets(c, nsys, offsets);
+    if (rc) return rc;
+    rc = build_plan(c, nsys, offsets, domains);
+    if (rc) return rc;
+    return vv_any(c, xyzq, vel, nsteps, dt, epot, ekin);
+}
+
+int parareal_run(msm_ctx *fine, msm_ctx *coarse, const parareal_params *pp, int64_t n, const double *q,
+                 const double *invm, const double *state0, double *lambda, parareal_report *rep)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!fine || !coarse || !pp || !q || !invm || !state0 || !lambda || !rep || n < 1) return MSM_ERR_ARG;
+    const int S = pp->nslices;
+    if (S < 1 || pp->kmax < 0 || pp->steps_f < 0 || pp->steps_g < 0 || !(pp->dt_f > 0) || !(pp->dt_g > 0))
+        return MSM_ERR_ARG;
+    if (!fine->md_bound || !coarse->md_bound || fine->stream != coarse->stream) return MSM_ERR_ARG;
+    if ((fine->rigid || coarse->rigid) && n % 3) return MSM_ERR_ARG;
+    if (fine->prm.max_atoms < (int64_t)S * n || fine->prm.max_systems < S || coarse->prm.max_atoms < n)
+        return MSM_ERR_CAPACITY;
+    std::memset(rep, 0, sizeof(*rep));
+    hipStream_t s = fine->stream;
+    const int64_t N6 = 6 * n;
+    auto slot = [&](double *base, int i) { return base + (int64_t)i * N6; };
+    int rc = MSM_OK;
+    int converged = 0;
+    auto status = [&]() {
+        int a = msm_get_status(fine), b = msm_get_status(coarse);
+        return a ? a : b;
+    };
+
+    if (copy_f64(s, state0, lambda, N6) != hipSuccess) return MSM_ERR_HIP;
+    // initial coarse sweep: lambda^0_{n+1} = G(lambda^0_n); keep G(lambda^0_n) as the old coarse value
+    for (int i = 0; i < S && !rc; i++) {
+        rc = propagate(coarse, n, 1, q, invm, slot(lambda, i), slot(lambda, i + 1), pp->steps_g, pp->dt_g);
+        if (!rc && copy_f64(s, slot(lambda, i + 1), slot(fine->gold, i), N6) != hipSuccess) rc = MSM_ERR_HIP;
+    }
+    if (!rc) rc = status();
+    unsigned long long *change = (unsigned long long *)fine->md_scalar;
+    for (int k = 0; k < pp->kmax && !rc && !converged; k++) {
+        // fine propagator on slices k .. S-1 (slices < k are already exact), one batch
+        rc = propagate(fine, n, S - k, q, invm, slot(lambda, k), slot(fine->fout, k), pp->steps_f, pp->dt_f);
+        if (rc) break;
+        if (zero_u64(s, change) != hipSuccess) {
+            rc = MSM_ERR_HIP;
+            break;
+        }
+        // serial coarse sweep with the correction
+        for (int i = k; i < S && !rc; i++) {
+            rc = propagate(coarse, n, 1, q, invm, slot(lambda, i), fine->gnew, pp->steps_g, pp->dt_g);
+            if (!rc && parareal_correct(s, N6, slot(lambda, i + 1), slot(fine->fout, i), fine->gnew,
+                                        slot(fine->gold, i), change) != hipSuccess)
+                rc = MSM_ERR_HIP;
+        }
+        if (rc) break;
+        unsigned long long bits = 0;
+        if (hipMemcpyAsync(&bits, change, sizeof(bits), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+            rc = MSM_ERR_HIP;
+            break;
+        }
+        double ch;
+        std::memcpy(&ch, &bits, sizeof(ch));
+        rc = status();
+        if (rc) break;
+        if (k < 64) rep->residual[k] = ch;
+        rep->iterations = k + 1;
+        if (ch < pp->tol || k + 1 >= S) converged = 1;
+    }
+    if (!rc && hipStreamSynchronize(s) != hipSuccess) rc = MSM_ERR_HIP;
+    if (!rc) rc = status();
+    rep->converged = converged;
+    rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rc) return rc;
+    return converged ? MSM_OK : MSM_NOT_CONVERGED;
+}
+
+}  // extern "C"

@@ -1,0 +1,333 @@
+// Kernels of the dynamics built on the multilevel summation forces:
+// velocity Verlet (Section 2) with RATTLE for rigid three-site molecules
+// (Andersen 1983), kinetic energy, and the parareal state handling of
+// Section 4 (conversion between the FP64 iterates and the propagator state,
+// and the correction lambda_{n+1} = F(lambda^k_n) + (G(lambda^{k+1}_n) - G(lambda^k_n))).
+//
+// Propagator state: xyzq (x, y, z, q) and vel (vx, vy, vz, 1/m), both in the
+// context's precision T; forces are N x 3 in T.
+#include "md.h"
+
+namespace msmx {
+
+namespace {
+
+inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+template <typename T> struct V3 {
+    T x, y, z;
+};
+template <typename T> __device__ inline V3<T> sub(V3<T> a, V3<T> b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+template <typename T> __device__ inline T dot(V3<T> a, V3<T> b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+__constant__ int kTriA[3] = {0, 0, 1};
+__constant__ int kTriB[3] = {1, 2, 2};
+
+// Half kick and drift of one atom (no constraints).
+template <typename T>
+__global__ void k_kick_drift(int64_t n, vec4_t<T> *__restrict__ x, vec4_t<T> *__restrict__ v,
+                             const T *__restrict__ f, T dt)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    vec4_t<T> vi = v[i], xi = x[i];
+    const T h = T(0.5) * dt * vi.w;
+    vi.x += h * f[3 * i];
+    vi.y += h * f[3 * i + 1];
+    vi.z += h * f[3 * i + 2];
+    xi.x += dt * vi.x;
+    xi.y += dt * vi.y;
+    xi.z += dt * vi.z;
+    v[i] = vi;
+    x[i] = xi;
+}
+
+// Half kick, drift, then RATTLE's position stage for one rigid triple: each
+// bond is brought back to its length along the bond vector before the drift,
+// and the same displacement over dt is added to the velocities.
+template <typename T>
+__global__ void k_kick_drift_rattle(int64_t ntri, vec4_t<T> *__restrict__ x, vec4_t<T> *__restrict__ v,
+                                    const T *__restrict__ f, T dt, TriModel tm)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= ntri) return;
+    V3<T> r[3], old[3], vel[3];
+    T im[3];
+    vec4_t<T> xs[3];
+    for (int a = 0; a < 3; a++) {
+        const int64_t i = 3 * t + a;
+        xs[a] = x[i];
+        const vec4_t<T> vi = v[i];
+        im[a] = vi.w;
+        const T h = T(0.5) * dt * vi.w;
+        vel[a] = {vi.x + h * f[3 * i], vi.y + h * f[3 * i + 1], vi.z + h * f[3 * i + 2]};
+        old[a] = {xs[a].x, xs[a].y, xs[a].z};
+        r[a] = {old[a].x + dt * vel[a].x, old[a].y + dt * vel[a].y, old[a].z + dt * vel[a].z};
+    }
+    const T inv_dt = T(1) / dt;
+    for (int it = 0; it < tm.max_iter; it++) {
+        bool done = true;
+        for (int c = 0; c < 3; c++) {
+            const int a = kTriA[c], b = kTriB[c];
+            const T d2 = T(tm.len[c] * tm.len[c]);
+            const V3<T> s = sub(r[a], r[b]);
+            const V3<T> ro = sub(old[a], old[b]);
+            const T diff = d2 - dot(s, s);
+            if (fabs(diff) <= T(2) * T(tm.tol) * d2) continue;
+            done = false;
+            const T g = diff / (T(2) * dot(s, ro) * (im[a] + im[b]));
+            const T ga = g * im[a], gb = g * im[b];
+            r[a] = {r[a].x + ga * ro.x, r[a].y + ga * ro.y, r[a].z + ga * ro.z};
+            r[b] = {r[b].x - gb * ro.x, r[b].y - gb * ro.y, r[b].z - gb * ro.z};
+            vel[a] = {vel[a].x + ga * inv_dt * ro.x, vel[a].y + ga * inv_dt * ro.y, vel[a].z + ga * inv_dt * ro.z};
+            vel[b] = {vel[b].x - gb * inv_dt * ro.x, vel[b].y - gb * inv_dt * ro.y, vel[b].z - gb * inv_dt * ro.z};
+        }
+        if (done) break;
+    }
+    for (int a = 0; a < 3; a++) {
+        const int64_t i = 3 * t + a;
+        vec4_t<T> xo = xs[a];
+        xo.x = r[a].x;
+        xo.y = r[a].y;
+        xo.z = r[a].z;
+        x[i] = xo;
+        vec4_t<T> vo;
+        vo.x = vel[a].x;
+        vo.y = vel[a].y;
+        vo.z = vel[a].z;
+        vo.w = im[a];
+        v[i] = vo;
+    }
+}
+
+template <typename T>
+__global__ void k_kick(int64_t n, vec4_t<T> *__restrict__ v, const T *__restrict__ f, T dt)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    vec4_t<T> vi = v[i];
+    const T h = T(0.5) * dt * vi.w;
+    vi.x += h * f[3 * i];
+    vi.y += h * f[3 * i + 1];
+    vi.z += h * f[3 * i + 2];
+    v[i] = vi;
+}
+
+// Second half kick, then RATTLE's velocity stage: remove the relative
+// velocity along every bond of the triple.
+template <typename T>
+__global__ void k_kick_rattle(int64_t ntri, const vec4_t<T> *__restrict__ x, vec4_t<T> *__restrict__ v,
+                              const T *__restrict__ f, T dt, TriModel tm)
+{
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= ntri) return;
+    V3<T> r[3], vel[3];
+    T im[3];
+    for (int a = 0; a < 3; a++) {
+        const int64_t i = 3 * t + a;
+        const vec4_t<T> xi = x[i], vi = v[i];
+        im[a] = vi.w;
+        const T h = T(0.5) * dt * vi.w;
+        vel[a] = {vi.x + h * f[3 * i], vi.y + h * f[3 * i + 1], vi.z + h * f[3 * i + 2]};
+        r[a] = {xi.x, xi.y, xi.z};
+    }
+    for (int it = 0; it < tm.max_iter; it++) {
+        bool done = true;
+        for (int c = 0; c < 3; c++) {
+            const int a = kTriA[c], b = kTriB[c];
+            const T d2 = T(tm.len[c] * tm.len[c]);
+            const V3<T> rr = sub(r[a], r[b]);
+            const V3<T> w = sub(vel[a], vel[b]);
+            const T rw = dot(rr, w);
+            if (fabs(rw) <= T(tm.tol) * d2) continue;
+            done = false;
+            const T kk = rw / ((im[a] + im[b]) * d2);
+            const T ka = kk * im[a], kb = kk * im[b];
+            vel[a] = {vel[a].x - ka * rr.x, vel[a].y - ka * rr.y, vel[a].z - ka * rr.z};
+            vel[b] = {vel[b].x + kb * rr.x, vel[b].y + kb * rr.y, vel[b].z + kb * rr.z};
+        }
+        if (done) break;
+    }
+    for (int a = 0; a < 3; a++) {
+        vec4_t<T> vo;
+        vo.x = vel[a].x;
+        vo.y = vel[a].y;
+        vo.z = vel[a].z;
+        vo.w = im[a];
+        v[3 * t + a] = vo;
+    }
+}
+
+// Kinetic energy 1/2 sum m v^2 per interpolation-sized block of each system.
+template <typename T>
+__global__ __launch_bounds__(256) void k_kinetic(DevPlan p, const vec4_t<T> *__restrict__ v, double *__restrict__ parts)
+{
+    __shared__ double red[256];
+    const int64_t blk = blockIdx.x;
+    const int s = find_segment(p.iblk_prefix, p.nsys, blk);
+    const SysPlan &P = p.sys[s];
+    const int64_t i = P.atom0 + (blk - p.iblk_prefix[s]) * 256 + threadIdx.x;
+    double e = 0;
+    if (i < P.atom0 + P.natoms) {
+        const vec4_t<T> vi = v[i];
+        e = 0.5 * ((double)vi.x * vi.x + (double)vi.y * vi.y + (double)vi.z * vi.z) / (double)vi.w;
+    }
+    red[threadIdx.x] = e;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) parts[blk] = red[0];
+}
+
+// Propagator state of nsys consecutive slices from the FP64 iterates:
+// lambda (slice-major, n x 6 per slice) -> xyzq, vel with charges and inverse masses.
+template <typename T>
+__global__ void k_state_in(int64_t natoms, int64_t count, const double *__restrict__ lam, const double *__restrict__ q,
+                           const double *__restrict__ invm, vec4_t<T> *__restrict__ x, vec4_t<T> *__restrict__ v)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const int64_t a = i % natoms;
+    const double *l = lam + 6 * i;
+    vec4_t<T> xo, vo;
+    xo.x = T(l[0]);
+    xo.y = T(l[1]);
+    xo.z = T(l[2]);
+    xo.w = T(q[a]);
+    vo.x = T(l[3]);
+    vo.y = T(l[4]);
+    vo.z = T(l[5]);
+    vo.w = T(invm[a]);
+    x[i] = xo;
+    v[i] = vo;
+}
+
+template <typename T>
+__global__ void k_state_out(int64_t count, const vec4_t<T> *__restrict__ x, const vec4_t<T> *__restrict__ v,
+                            double *__restrict__ out)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= count) return;
+    const vec4_t<T> xi = x[i], vi = v[i];
+    double *o = out + 6 * i;
+    o[0] = xi.x;
+    o[1] = xi.y;
+    o[2] = xi.z;
+    o[3] = vi.x;
+    o[4] = vi.y;
+    o[5] = vi.z;
+}
+
+// Parareal correction (Section 4), in FP64:
+// lambda_{n+1} = F(lambda^k_n) + (G(lambda^{k+1}_n) - G(lambda^k_n)); the old
+// coarse value is replaced by the new one, and the largest position change is
+// folded into *change (max of non-negative doubles, order-independent).
+__global__ __launch_bounds__(256) void k_correct(int64_t count6, double *__restrict__ lam,
+                                                 const double *__restrict__ fout, const double *__restrict__ gnew,
+                                                 double *__restrict__ gold, unsigned long long *__restrict__ change)
+{
+    __shared__ double red[256];
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double c = 0;
+    if (e < count6) {
+        const double g = gnew[e];
+        const double nv = fout[e] + (g - gold[e]);
+        if (e % 6 < 3) c = fabs(nv - lam[e]);
+        if (!(c == c)) c = __longlong_as_double(0x7ff0000000000000LL);   // NaN -> +inf
+        lam[e] = nv;
+        gold[e] = g;
+    }
+    red[threadIdx.x] = c;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(change, (unsigned long long)__double_as_longlong(red[0]));
+}
+
+__global__ void k_copy_f64(int64_t n, const double *__restrict__ src, double *__restrict__ dst)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+__global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
+
+}  // namespace
+
+template <typename T>
+hipError_t MdLaunch<T>::kick_drift(hipStream_t s, int64_t n, vec4_t<T> *x, vec4_t<T> *v, const T *f, double dt,
+                                   const TriModel *tm)
+{
+    if (n == 0) return hipSuccess;
+    if (tm)
+        hipLaunchKernelGGL(k_kick_drift_rattle<T>, dim3(nblocks(n / 3, 128)), dim3(128), 0, s, n / 3, x, v, f, T(dt), *tm);
+    else
+        hipLaunchKernelGGL(k_kick_drift<T>, dim3(nblocks(n, 256)), dim3(256), 0, s, n, x, v, f, T(dt));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t MdLaunch<T>::kick(hipStream_t s, int64_t n, const vec4_t<T> *x, vec4_t<T> *v, const T *f, double dt,
+                             const TriModel *tm)
+{
+    if (n == 0) return hipSuccess;
+    if (tm)
+        hipLaunchKernelGGL(k_kick_rattle<T>, dim3(nblocks(n / 3, 128)), dim3(128), 0, s, n / 3, x, v, f, T(dt), *tm);
+    else
+        hipLaunchKernelGGL(k_kick<T>, dim3(nblocks(n, 256)), dim3(256), 0, s, n, v, f, T(dt));
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t MdLaunch<T>::kinetic(hipStream_t s, const DevPlan &p, const vec4_t<T> *v, double *parts, double *ekin)
+{
+    if (p.niblk > 0) hipLaunchKernelGGL(k_kinetic<T>, dim3((unsigned)p.niblk), dim3(256), 0, s, p, v, parts);
+    return reduce_blocks(s, p, parts, ekin, 1.0);
+}
+
+template <typename T>
+hipError_t MdLaunch<T>::state_in(hipStream_t s, int64_t natoms, int64_t count, const double *lam, const double *q,
+                                 const double *invm, vec4_t<T> *x, vec4_t<T> *v)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_state_in<T>, dim3(nblocks(count, 256)), dim3(256), 0, s, natoms, count, lam, q, invm, x, v);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t MdLaunch<T>::state_out(hipStream_t s, int64_t count, const vec4_t<T> *x, const vec4_t<T> *v, double *out)
+{
+    if (count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_state_out<T>, dim3(nblocks(count, 256)), dim3(256), 0, s, count, x, v, out);
+    return hipGetLastError();
+}
+
+hipError_t parareal_correct(hipStream_t s, int64_t count6, double *lam, const double *fout, const double *gnew,
+                            double *gold, unsigned long long *change)
+{
+    if (count6 == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_correct, dim3(nblocks(count6, 256)), dim3(256), 0, s, count6, lam, fout, gnew, gold, change);
+    return hipGetLastError();
+}
+
+hipError_t copy_f64(hipStream_t s, const double *src, double *dst, int64_t n)
+{
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_copy_f64, dim3(nblocks(n, 256)), dim3(256), 0, s, n, src, dst);
+    return hipGetLastError();
+}
+
+hipError_t zero_u64(hipStream_t s, unsigned long long *p)
+{
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, p);
+    return hipGetLastError();
+}
+
+template struct MdLaunch<float>;
+template struct MdLaunch<double>;
+
+}  // namespace msmx

@@ -3,6 +3,7 @@
 // systems of a batch in one launch; a thread or wave finds its system by a
 // binary search of a prefix table.
 #include "launch.h"
+#include "md.h"
 
 namespace msmx {
 
@@ -67,12 +68,25 @@ template <typename T> struct PairK {
 
 constexpr int kPairWaves = 4;   // waves sharing one group's candidate rows
 
-template <typename T>
+// molecule id stored in the first component of an aux record
+__device__ inline int mol_of(const float4 &v) { return __float_as_int(v.x); }
+__device__ inline int mol_of(const double4 &v) { return (int)__double_as_longlong(v.x); }
+
+// Dynamics variant (MD = true): pairs inside one molecule are excluded from
+// Coulomb's law, so instead of g* they contribute -gamma(r/a)/a, which cancels
+// the smooth part the grids carry for them; and a Lennard-Jones term
+// 4 eps ((s/r)^12 - (s/r)^6), shifted to zero at r = a, acts between atoms of
+// different molecules, with s = s_i/2 + s_j/2 and eps = sqrt(eps_i) sqrt(eps_j)
+// stored per atom in aux = (molecule id bits, s/2, sqrt(eps), 0).
+template <typename T, bool MD>
 __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                               const int *__restrict__ cstart,
-                                                              vec4_t<T> *__restrict__ out, PairK<T> k)
+                                                              vec4_t<T> *__restrict__ out, PairK<T> k,
+                                                              const vec4_t<T> *__restrict__ saux,
+                                                              vec4_t<T> *__restrict__ ljout)
 {
     __shared__ vec4_t<T> red[kPairWaves][kWave];
+    __shared__ vec4_t<T> redlj[MD ? kPairWaves : 1][kWave];
     const int64_t g = blockIdx.x;
     const int s = find_segment(p.group_prefix, p.nsys, g);
     const SysPlan &P = p.sys[s];
@@ -83,6 +97,8 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
     const int64_t i = first + lane;
     const bool valid = i < end;
     const vec4_t<T> ai = sx[valid ? i : first];
+    vec4_t<T> xi;
+    if (MD) xi = saux[valid ? i : first];
 
     const T bminx = uni(wave_min(ai.x)), bmaxx = uni(wave_max(ai.x));
     const T bminy = uni(wave_min(ai.y)), bmaxy = uni(wave_max(ai.y));
@@ -98,6 +114,7 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
     const int cz1 = clampi((int)floor((bmaxz - loz + reach) * inv_h), 0, ncz - 1);
 
     T fx = 0, fy = 0, fz = 0, u = 0;
+    T lx = 0, ly = 0, lz = 0, le = 0;
     int row = 0;
     for (int cz = cz0; cz <= cz1; ++cz) {
         const T z0 = loz + T(cz) * h;
@@ -127,16 +144,45 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
                     nxt = sx[j + 1];
                     const T dx = ai.x - aj.x, ddy = ai.y - aj.y, ddz = ai.z - aj.z;
                     const T r2 = dx * dx + ddy * ddy + ddz * ddz;
-                    if (r2 < k.a2 && r2 > T(0)) {
-                        const T rinv = rsqrt_t(r2);
-                        const T rho2 = r2 * k.inv_a2;
-                        const T gs = rinv - (k.c0 + rho2 * (k.c1 + rho2 * k.c2));
-                        const T br = rinv * rinv * rinv - (k.d0 + k.d1 * rho2);
-                        u += aj.w * gs;
-                        const T t = aj.w * br;
-                        fx += t * dx;
-                        fy += t * ddy;
-                        fz += t * ddz;
+                    if (!MD) {
+                        if (r2 < k.a2 && r2 > T(0)) {
+                            const T rinv = rsqrt_t(r2);
+                            const T rho2 = r2 * k.inv_a2;
+                            const T gs = rinv - (k.c0 + rho2 * (k.c1 + rho2 * k.c2));
+                            const T br = rinv * rinv * rinv - (k.d0 + k.d1 * rho2);
+                            u += aj.w * gs;
+                            const T t = aj.w * br;
+                            fx += t * dx;
+                            fy += t * ddy;
+                            fz += t * ddz;
+                        }
+                    } else {
+                        const vec4_t<T> xj = saux[j];
+                        if (r2 < k.a2 && r2 > T(0)) {
+                            const bool same = mol_of(xi) == mol_of(xj);
+                            const T rinv = rsqrt_t(r2);
+                            const T rho2 = r2 * k.inv_a2;
+                            const T rc = same ? T(0) : rinv;
+                            const T gs = rc - (k.c0 + rho2 * (k.c1 + rho2 * k.c2));
+                            const T br = rc * rinv * rinv - (k.d0 + k.d1 * rho2);
+                            u += aj.w * gs;
+                            const T t = aj.w * br;
+                            fx += t * dx;
+                            fy += t * ddy;
+                            fz += t * ddz;
+                            const T eps = same ? T(0) : xi.z * xj.z;
+                            if (eps != T(0)) {
+                                const T sg = xi.y + xj.y;
+                                const T s2 = sg * sg;
+                                const T sr2 = s2 * rinv * rinv, sr6 = sr2 * sr2 * sr2;
+                                const T sc2 = s2 * k.inv_a2, sc6 = sc2 * sc2 * sc2;
+                                le += T(4) * eps * ((sr6 * sr6 - sr6) - (sc6 * sc6 - sc6));
+                                const T fl = T(24) * eps * (T(2) * sr6 * sr6 - sr6) * rinv * rinv;
+                                lx += fl * dx;
+                                ly += fl * ddy;
+                                lz += fl * ddz;
+                            }
+                        }
                     }
                 }
             }
@@ -148,6 +194,14 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
     o.z = fz;
     o.w = u;
     red[wv][lane] = o;
+    if (MD) {
+        vec4_t<T> ol;
+        ol.x = lx;
+        ol.y = ly;
+        ol.z = lz;
+        ol.w = le;
+        redlj[MD ? wv : 0][lane] = ol;
+    }
     __syncthreads();
     if (wv == 0 && valid) {
         vec4_t<T> acc = red[0][lane];
@@ -159,6 +213,17 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
             acc.w += v.w;
         }
         out[i] = acc;
+        if (MD) {
+            vec4_t<T> al = redlj[0][lane];
+            for (int w = 1; w < kPairWaves; ++w) {
+                const vec4_t<T> v = redlj[MD ? w : 0][lane];
+                al.x += v.x;
+                al.y += v.y;
+                al.z += v.z;
+                al.w += v.w;
+            }
+            ljout[i] = al;
+        }
     }
 }
 
@@ -456,7 +521,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4
                                                            const int *__restrict__ order,
                                                            const T *__restrict__ ugrid, T *__restrict__ forces,
                                                            T *__restrict__ potentials, double *__restrict__ eparts,
-                                                           T ke, T self)
+                                                           T ke, T self, const vec4_t<T> *__restrict__ ljin)
 {
     __shared__ double red[kInterpThreads];
     const int64_t blk = blockIdx.x;
@@ -502,13 +567,16 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4
         const T phi = ke * (sr.w + ul - a.w * self);
         const int64_t o = order[pos];
         if (potentials) potentials[o] = phi;
+        vec4_t<T> lj;
+        lj.x = lj.y = lj.z = lj.w = T(0);
+        if (ljin) lj = ljin[pos];
         if (forces) {
             const T kq = ke * a.w;
-            forces[3 * o + 0] = kq * (sr.x - gx);
-            forces[3 * o + 1] = kq * (sr.y - gy);
-            forces[3 * o + 2] = kq * (sr.z - gz);
+            forces[3 * o + 0] = kq * (sr.x - gx) + lj.x;
+            forces[3 * o + 1] = kq * (sr.y - gy) + lj.y;
+            forces[3 * o + 2] = kq * (sr.z - gz) + lj.z;
         }
-        e = (double)a.w * (double)phi;
+        e = (double)a.w * (double)phi + (double)lj.w;
     }
     red[threadIdx.x] = e;
     __syncthreads();
@@ -519,10 +587,11 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4
     if (threadIdx.x == 0) eparts[blk] = red[0];
 }
 
-// U = 1/2 sum_i q_i phi_i per system, from the block partial sums: one
-// workgroup per system, each thread a fixed stride of partials, then a tree.
+// Per-system sum of block partials times `scale` (the energy U = 1/2 sum_i
+// q_i phi_i uses 1/2): one workgroup per system, each thread a fixed stride of
+// partials, then a fixed tree, so the result does not depend on timing.
 __global__ __launch_bounds__(256) void k_energy(DevPlan p, const double *__restrict__ eparts,
-                                                double *__restrict__ energy)
+                                                double *__restrict__ energy, double scale)
 {
     __shared__ double red[256];
     const int s = blockIdx.x;
@@ -534,7 +603,7 @@ __global__ __launch_bounds__(256) void k_energy(DevPlan p, const double *__restr
         if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
         __syncthreads();
     }
-    if (threadIdx.x == 0) energy[s] = 0.5 * red[0];
+    if (threadIdx.x == 0) energy[s] = scale * red[0];
 }
 
 template <typename T>
@@ -589,8 +658,12 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, co
     // -(d/dr)(gamma(r/a)/a) / r = (5/2 - 3/2 rho^2) / a^3, entering with a minus sign
     k.d0 = T(2.5 / (a * a * a));
     k.d1 = T(-1.5 / (a * a * a));
-    hipLaunchKernelGGL(k_pair<T>, dim3((unsigned)p.ngroups), dim3(kPairWaves * kWave), 0, s, p, w.sxyzq, w.cell_start,
-                       w.shrt, k);
+    if (w.saux)
+        hipLaunchKernelGGL((k_pair<T, true>), dim3((unsigned)p.ngroups), dim3(kPairWaves * kWave), 0, s, p, w.sxyzq,
+                           w.cell_start, w.shrt, k, (const vec4_t<T> *)w.saux, w.shlj);
+    else
+        hipLaunchKernelGGL((k_pair<T, false>), dim3((unsigned)p.ngroups), dim3(kPairWaves * kWave), 0, s, p, w.sxyzq,
+                           w.cell_start, w.shrt, k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
     return hipGetLastError();
 }
 
@@ -663,15 +736,21 @@ hipError_t Launch<T>::interp(hipStream_t s, const DevPlan &p, const Work<T> &w, 
     if (p.niblk == 0) return hipSuccess;
     const T self = T(1.875 / m.a);   // gamma(0)/a
     hipLaunchKernelGGL(k_interp<T>, dim3((unsigned)p.niblk), dim3(kInterpThreads), 0, s, p, w.sxyzq, w.shrt, w.order,
-                       w.ugrid, forces, potentials, w.eparts, T(m.ke), self);
+                       w.ugrid, forces, potentials, w.eparts, T(m.ke), self,
+                       (const vec4_t<T> *)(w.saux ? w.shlj : nullptr));
+    return hipGetLastError();
+}
+
+hipError_t reduce_blocks(hipStream_t s, const DevPlan &p, const double *parts, double *out, double scale)
+{
+    if (!out) return hipSuccess;
+    hipLaunchKernelGGL(k_energy, dim3((unsigned)p.nsys), dim3(256), 0, s, p, parts, out, scale);
     return hipGetLastError();
 }
 
 template <typename T> hipError_t Launch<T>::energy(hipStream_t s, const DevPlan &p, const Work<T> &w, double *energy)
 {
-    if (!energy) return hipSuccess;
-    hipLaunchKernelGGL(k_energy, dim3((unsigned)p.nsys), dim3(256), 0, s, p, w.eparts, energy);
-    return hipGetLastError();
+    return reduce_blocks(s, p, w.eparts, energy, 0.5);
 }
 
 template <typename T>

@@ -1,0 +1,121 @@
+"""Pins of the dynamics oracle: velocity Verlet (Section 2) with rigid water,
+and the parareal iteration (Section 4).
+
+Pinned against facts that do not come from the oracle: closed-form
+Lennard-Jones, exclusions equal to removing Coulomb's law for the excluded
+pairs (checked against brute force), constraint lengths, second-order energy
+drift of velocity Verlet, and the parareal properties that hold for any
+propagators (k iterations reproduce the fine trajectory on the first k
+slices; zero iterations give the coarse trajectory).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from workloads import rigid_water_velocities, water_box, water_model_arrays
+
+pytestmark = pytest.mark.filterwarnings("ignore::RuntimeWarning")
+
+
+def small_water(n_mol=64, side=1.24, seed=7, margin=0.6):
+    per = int(math.ceil(n_mol ** (1 / 3)))
+    w = water_box(n_mol, (per,) * 3, (side,) * 3, seed=seed, margin=margin)
+    mass, molid, lj, tri = water_model_arrays(w.n)
+    model = oracle.OracleModel(mass, molid, lj, True, tri, 1e-12)
+    v = rigid_water_velocities(w.xyz, 300.0, seed=seed + 1)
+    return w, model, v
+
+
+def test_lennard_jones_closed_form():
+    lo, hi = (0.0, 0.0, 0.0), (2.0, 2.0, 2.0)
+    p = oracle.OracleParams(1.0, 0.25, lo, hi, 0, 138.935458)
+    sig, eps, r = 0.3, 0.5, 0.37
+    xyz = np.array([[0.5, 0.5, 0.5], [0.5 + r, 0.5, 0.5]])
+    m = oracle.OracleModel(np.ones(2), np.array([0, 1], np.int32), np.array([[sig, eps], [sig, eps]]))
+    e, f = oracle.md_forces(p, m, xyz, np.zeros(2))
+    u = lambda x: 4 * eps * ((sig / x) ** 12 - (sig / x) ** 6)  # noqa: E731
+    assert e == pytest.approx(u(r) - u(1.0), rel=1e-13)
+    fx = (u(r + 1e-6) - u(r - 1e-6)) / 2e-6
+    assert f[1, 0] == pytest.approx(-fx, rel=1e-7)
+    assert f[0, 0] == pytest.approx(fx, rel=1e-7)
+    # same molecule: excluded; beyond the cutoff: nothing
+    m2 = oracle.OracleModel(np.ones(2), np.array([3, 3], np.int32), np.array([[sig, eps], [sig, eps]]))
+    assert oracle.md_forces(p, m2, xyz, np.zeros(2))[0] == 0.0
+    far = np.array([[0.2, 0.2, 0.2], [1.4, 0.2, 0.2]])
+    assert oracle.md_forces(p, m, far, np.zeros(2))[0] == 0.0
+
+
+def test_exclusions_remove_coulomb_of_intramolecular_pairs():
+    w = water_box(300, (10, 10, 10), (3.0, 3.0, 3.0), seed=5)
+    mass, molid, _, _ = water_model_arrays(w.n)
+    p = oracle.OracleParams.of(w)
+    m = oracle.OracleModel(mass, molid)
+    e, f = oracle.md_forces(p, m, w.xyz, w.q)
+    e0, f0, _ = oracle.coulomb(w.xyz, w.q)
+    # brute force without the intramolecular pairs
+    x = w.xyz.reshape(-1, 3, 3)
+    qm = w.q.reshape(-1, 3)
+    fx = np.zeros_like(x)
+    e_in = 0.0
+    for a, b in [(0, 1), (0, 2), (1, 2)]:
+        d = x[:, a] - x[:, b]
+        r = np.linalg.norm(d, axis=1)
+        u = 138.935458 * qm[:, a] * qm[:, b] / r
+        e_in += u.sum()
+        fx[:, a] += (u / r ** 2)[:, None] * d
+        fx[:, b] -= (u / r ** 2)[:, None] * d
+    e_ref = e0 - e_in
+    f_ref = f0 - fx.reshape(-1, 3)
+    assert abs(e - e_ref) / abs(e_ref) < 0.01
+    assert np.sqrt(((f - f_ref) ** 2).sum() / (f_ref ** 2).sum()) < 0.01
+
+
+def test_rattle_keeps_bonds_and_vv_drift_is_second_order():
+    w, model, v = small_water()
+    p = oracle.OracleParams(0.8, 0.25, tuple(w.lo), tuple(w.hi), 0, 138.935458)
+    drift = []
+    for dt, ns in [(0.002, 20), (0.001, 40)]:
+        _, _, ep0, ek0 = oracle.vv(p, model, w.xyz, v, w.q, dt, 0)
+        x, vv, ep, ek = oracle.vv(p, model, w.xyz, v, w.q, dt, ns)
+        d = x.reshape(-1, 3, 3)
+        for (a, b), L in zip([(0, 1), (0, 2), (1, 2)], model.tri):
+            assert np.abs(np.linalg.norm(d[:, a] - d[:, b], axis=1) - L).max() < 1e-10
+        # velocities along every bond vanish
+        vm = vv.reshape(-1, 3, 3)
+        for a, b in [(0, 1), (0, 2), (1, 2)]:
+            assert np.abs(((vm[:, a] - vm[:, b]) * (d[:, a] - d[:, b])).sum(1)).max() < 1e-8
+        drift.append(abs((ep + ek) - (ep0 + ek0)))
+    # velocity Verlet: halving dt over the same time cuts the drift about 4x
+    assert 2.5 < drift[0] / drift[1] < 6.0
+
+
+def test_parareal_exact_after_k_iterations_and_coarse_at_zero():
+    w, model, v = small_water(n_mol=27, side=0.93, seed=3)
+    pf = oracle.OracleParams(0.8, 0.25, tuple(w.lo), tuple(w.hi), 0, 138.935458)
+    pg = oracle.OracleParams(0.6, 0.5, tuple(w.lo), tuple(w.hi), 0, 138.935458)
+    S, sf, dtf, sg, dtg = 4, 3, 0.001, 1, 0.003
+    # serial fine and serial coarse trajectories
+    fine = [np.concatenate([w.xyz, v], 1)]
+    coarse = [fine[0]]
+    for _ in range(S):
+        x, vv, _, _ = oracle.vv(pf, model, fine[-1][:, :3], fine[-1][:, 3:], w.q, dtf, sf)
+        fine.append(np.concatenate([x, vv], 1))
+        x, vv, _, _ = oracle.vv(pg, model, coarse[-1][:, :3], coarse[-1][:, 3:], w.q, dtg, sg)
+        coarse.append(np.concatenate([x, vv], 1))
+    lam0, it0, _, _ = oracle.parareal(pf, pg, model, w.xyz, v, w.q, S, sf, dtf, sg, dtg, 0, 0.0)
+    assert it0 == 0
+    for n in range(S + 1):
+        assert np.array_equal(lam0[n], coarse[n])
+    for K in (1, 2, S):
+        lam, it, res, rc = oracle.parareal(pf, pg, model, w.xyz, v, w.q, S, sf, dtf, sg, dtg, K, 0.0)
+        assert it == K
+        for n in range(K + 1):
+            assert np.array_equal(lam[n], fine[n]), (K, n)
+        if K < S:
+            assert not np.array_equal(lam[S], fine[S])
+    assert rc == 0   # K = S is exact, reported as converged
+    # the residual shrinks as slices become exact
+    lam, it, res, rc = oracle.parareal(pf, pg, model, w.xyz, v, w.q, S, sf, dtf, sg, dtg, S, 1e-30)
+    assert res[-1] <= res[0]

@@ -16,5 +16,7 @@ from .water import (  # noqa: F401
     water_box_dims,
     maxwell_velocities,
     uneven_batch_sizes,
+    water_model_arrays,
+    rigid_water_velocities,
     named,
 )

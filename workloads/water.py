@@ -142,6 +142,45 @@ def maxwell_velocities(mass: np.ndarray, temperature: float, seed: int) -> np.nd
     return v - vcom
 
 
+# Lennard-Jones of the TIP3P oxygen (Jorgensen et al. 1983); hydrogens carry none.
+SIGMA_O = 0.315061      # nm
+EPS_O = 0.6364          # kJ/mol
+
+
+def water_model_arrays(n_atoms: int):
+    """Per-atom masses, molecule ids and (sigma, epsilon) of n_atoms/3 water
+    molecules in O, H, H order, and the three rigid distances O-H1, O-H2, H1-H2."""
+    n_mol = n_atoms // 3
+    mass = np.tile(np.array([M_O, M_H, M_H]), n_mol)
+    molid = np.repeat(np.arange(n_mol, dtype=np.int32), 3)
+    lj = np.tile(np.array([[SIGMA_O, EPS_O], [0.0, 0.0], [0.0, 0.0]]), (n_mol, 1))
+    hh = 2.0 * R_OH * math.sin(math.radians(THETA_HOH) / 2.0)
+    return mass, molid, lj, (R_OH, R_OH, hh)
+
+
+def rigid_water_velocities(xyz: np.ndarray, temperature: float, seed: int) -> np.ndarray:
+    """Velocities of rigid molecules (O, H, H triples): a Gaussian centre-of-mass
+    velocity with variance kT/M and a Gaussian angular momentum with covariance
+    kT I, so every intramolecular distance is constant to first order. The
+    total momentum is removed."""
+    rng = np.random.default_rng(seed)
+    kt = KB_KJ_PER_MOL_K * temperature
+    x = xyz.reshape(-1, 3, 3)
+    m = np.array([M_O, M_H, M_H])
+    mtot = m.sum()
+    com = (m[None, :, None] * x).sum(axis=1) / mtot
+    rel = x - com[:, None, :]
+    inertia = (m[None, :, None, None] * ((rel ** 2).sum(-1)[..., None, None] * np.eye(3)
+                                           - rel[..., :, None] * rel[..., None, :])).sum(axis=1)
+    chol = np.linalg.cholesky(kt * inertia)
+    ang = np.einsum("mij,mj->mi", chol, rng.standard_normal((x.shape[0], 3)))
+    omega = np.linalg.solve(inertia, ang[..., None])[..., 0]
+    vcom = rng.standard_normal((x.shape[0], 3)) * math.sqrt(kt / mtot)
+    vcom -= vcom.mean(axis=0)
+    v = vcom[:, None, :] + np.cross(omega[:, None, :], rel)
+    return v.reshape(-1, 3)
+
+
 def uneven_batch_sizes(count: int = 8, smallest: float = 1.0e4, ratio: float = 20.0):
     """Atom counts growing geometrically from ``smallest`` by ``ratio`` overall,
     each a multiple of 3: 9,999 ... 200,001 for the defaults."""
