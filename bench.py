@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 32-slice and uneven batches")
+    ap.add_argument("--no-parareal", action="store_true")
+    ap.add_argument("--slices", type=int, default=32)
     return ap.parse_args()
 
 
@@ -110,6 +113,150 @@ def traffic_record(kernel_file, kernel_name, workload):
     if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
         return None
     return rec.get("bytes_per_launch")
+
+
+def bench_batched(torch, msmx, w32, steps, warmup, slices, single_value):
+    """One evaluation of `slices` systems of the water box at once (the fine
+    propagator's batch in parareal), and an uneven batch of 8 water boxes of
+    9,999 .. 200,001 atoms against evaluating them one by one."""
+    from workloads import uneven_batch_sizes, water_box, water_box_dims
+    dev = torch.device("cuda", 0)
+    n = w32.n
+    rng = np.random.default_rng(44)
+    base = w32.xyzq(np.float32)
+    xs = []
+    for s in range(slices):   # each slice jittered by up to 5 pm, all inside the domain
+        x = base.copy()
+        x[:, :3] += rng.uniform(-0.005, 0.005, size=(n, 3)).astype(np.float32)
+        xs.append(x)
+    xyzq = torch.tensor(np.concatenate(xs), device=dev)
+    offs = np.arange(slices + 1, dtype=np.int64) * n
+    ctx = msmx.MsmContext(w32.a, w32.h, w32.lo, w32.hi, precision="fp32", max_atoms=slices * n,
+                          max_systems=slices)
+    out = (torch.empty(slices, dtype=torch.float64, device=dev),
+           torch.empty((slices * n, 3), dtype=torch.float32, device=dev),
+           torch.empty(slices * n, dtype=torch.float32, device=dev))
+
+    def run():
+        ctx.energy_forces(xyzq, offs, energy=out[0], forces=out[1], potentials=out[2])
+
+    for _ in range(warmup):
+        run()
+    torch.cuda.synchronize()
+    k = max(steps // 10, 3)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(k):
+        run()
+    e1.record()
+    torch.cuda.synchronize()
+    ctx.check()
+    ms = e0.elapsed_time(e1) / k
+    # slice 0 of the batch against the single-system context: identical bits
+    one = msmx.MsmContext(w32.a, w32.h, w32.lo, w32.hi, precision="fp32", max_atoms=n)
+    e_1, f_1, _ = one.energy_forces(xyzq[:n].contiguous())
+    torch.cuda.synchronize()
+    same = bool(torch.equal(f_1, out[1][:n]) and torch.equal(e_1, out[0][:1]))
+    batched = {"systems": slices, "atoms": slices * n, "ms_per_step": ms,
+               "value": slices * n / (ms * 1e-3), "unit": "atom-steps/s",
+               "speedup_vs_single_system": slices * n / (ms * 1e-3) / single_value,
+               "slice0_bitwise_equal_to_single": same}
+
+    # uneven batch
+    sizes = uneven_batch_sizes()
+    ws = []
+    for i, na in enumerate(sizes):
+        n_mol, sites, box = water_box_dims(na)
+        ws.append(water_box(n_mol, sites, box, seed=40 + i, margin=0.3).as_dtype(np.float32))
+    big = np.max([x.hi - x.lo for x in ws], axis=0)
+    uctx = msmx.MsmContext(1.2, 0.25, np.zeros(3), big, precision="fp32", max_atoms=sum(sizes), max_systems=8)
+    ux = torch.tensor(np.concatenate([x.xyzq(np.float32) for x in ws]), device=dev)
+    uoffs = np.cumsum([0] + sizes)
+    udoms = np.array([np.concatenate([x.lo, x.hi]) for x in ws])
+    for _ in range(warmup):
+        uctx.energy_forces(ux, uoffs, udoms)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(k):
+        uctx.energy_forces(ux, uoffs, udoms)
+    e1.record()
+    torch.cuda.synchronize()
+    uctx.check()
+    ums = e0.elapsed_time(e1) / k
+    singles = [msmx.MsmContext(1.2, 0.25, x.lo, x.hi, precision="fp32", max_atoms=x.n) for x in ws]
+    sx = [torch.tensor(x.xyzq(np.float32), device=dev) for x in ws]
+    for _ in range(warmup):
+        for c, x in zip(singles, sx):
+            c.energy_forces(x)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(k):
+        for c, x in zip(singles, sx):
+            c.energy_forces(x)
+    e1.record()
+    torch.cuda.synchronize()
+    sms = e0.elapsed_time(e1) / k
+    uneven = {"sizes": sizes, "atoms": int(sum(sizes)), "batched_ms": ums, "one_by_one_ms": sms,
+              "batched_value": sum(sizes) / (ums * 1e-3), "speedup_batched_vs_one_by_one": sms / ums}
+    return batched, uneven
+
+
+def bench_parareal(torch, msmx, slices, n_atoms=99999):
+    """Parareal time-to-solution (Section 4) on the water box: `slices` slices
+    of 10 velocity-Verlet steps of 2 fs with the fine MSM (a = 1.2, h = 0.25)
+    against serial fine on the same GPU, for the configured coarse propagator
+    (one 20 fs step with a = 0.8, h = 0.5) and a stable one (10 steps of 2 fs
+    with a = 0.8, h = 0.5)."""
+    from workloads import rigid_water_velocities, water_box, water_box_dims, water_model_arrays
+    dev = torch.device("cuda", 0)
+    n_mol, sites, box = water_box_dims(n_atoms)
+    # the lattice start heats up and surface molecules evaporate at ~2 nm/ps:
+    # a 3 nm margin keeps every atom inside the domain over the 640 fs
+    w = water_box(n_mol, sites, box, seed=4, margin=3.0)
+    mass, molid, lj, tri = water_model_arrays(w.n)
+    v = rigid_water_velocities(w.xyz, 300.0, seed=104)
+    xyz = w.xyz.astype(np.float32).astype(np.float64)
+    v = v.astype(np.float32).astype(np.float64)
+    mol_t = torch.tensor(molid, dtype=torch.int32, device=dev)
+    lj_t = torch.tensor(lj, dtype=torch.float64, device=dev)
+
+    def ctx(a, h, ma, ms):
+        c = msmx.MsmContext(a, h, w.lo, w.hi, precision="fp32", max_atoms=ma, max_systems=ms)
+        c.bind_model(w.n, mol_t, lj_t, rigid=True, tri=tri)
+        return c
+
+    fine = ctx(1.2, 0.25, slices * w.n, slices)
+    coarse = ctx(0.8, 0.5, w.n, 1)
+    q = torch.tensor(w.q, device=dev)
+    invm = torch.tensor(1.0 / mass, device=dev)
+    s0 = torch.tensor(np.concatenate([xyz, v], 1), device=dev).contiguous()
+    # serial fine on the same GPU: 10 steps per slice, each slice restarting from the stored state
+    serial = ctx(1.2, 0.25, w.n, 1)
+    x = torch.cat([s0[:, :3], q[:, None]], 1).float().contiguous()
+    vv = torch.cat([s0[:, 3:], invm[:, None]], 1).float().contiguous()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(slices):
+        serial.vv_run(x, vv, 10, 0.002, energies=False)
+    torch.cuda.synchronize()
+    serial_s = time.perf_counter() - t0
+    serial.check()
+    out = {"workload": f"{slices} slices x {w.n} atoms, rigid water at 300 K, fine 10 x 2 fs (a 1.2, h 0.25)",
+           "serial_fine_seconds": serial_s}
+    for name, sg, dtg in (("coarse_1x20fs", 1, 0.020), ("coarse_10x2fs", 10, 0.002)):
+        rec = {"coarse": f"{sg} x {dtg * 1000:g} fs, a 0.8, h 0.5"}
+        try:
+            lam, rep, rc = msmx.parareal(fine, coarse, q, invm, s0, nslices=slices, kmax=slices, tol=1e-4,
+                                         steps_f=10, dt_f=0.002, steps_g=sg, dt_g=dtg)
+            rec.update({"status": "converged" if rc == 0 else "not converged", "iterations": rep["iterations"],
+                        "seconds": rep["seconds"], "residual_nm": [float("%.3g" % r) for r in rep["residual"]],
+                        "speedup_vs_serial_fine": serial_s / rep["seconds"]})
+            last = lam[slices, :, :3].float()
+            rec["final_max_dev_vs_serial_nm"] = float((last - x[:, :3]).abs().max().item())
+        except msmx.MsmError as e:
+            rec.update({"status": f"failed: {e}"})
+        out[name] = rec
+    return out
 
 
 def main():
@@ -210,6 +357,12 @@ def main():
                 accuracy["fp64_force_rel_rms"] = rel_rms(out64[1].cpu().numpy(), fo)
                 accuracy["fp64_energy_rel"] = abs(out64[0].item() - eo) / abs(eo)
 
+    batched = uneven = par = None
+    if not args.no_batched:
+        batched, uneven = bench_batched(torch, msmx, w32, args.steps, args.warmup, args.slices, value)
+    if not args.no_parareal:
+        par = bench_parareal(torch, msmx, args.slices)
+
     result.update({
         "value": value,
         "unit": "atom-steps/s",
@@ -229,6 +382,10 @@ def main():
         "cpu_baseline": cpu,
         "fp64_plain": fp64,
         "speedup_fp32_vs_fp64_plain": (value / fp64["value"]) if fp64 else None,
+        "fp32_batched": batched,
+        "speedup_fp32_batched_vs_fp64_plain": (batched["value"] / fp64["value"]) if (batched and fp64) else None,
+        "uneven_batch": uneven,
+        "parareal": par,
         "accuracy": accuracy,
         "stage_ms": kernels,
     })

@@ -138,6 +138,42 @@ __global__ void k_scatter(int64_t n, const int *__restrict__ cell_of, const int 
     order[start[cell_of[i]] + slot_of[i]] = (int)i;
 }
 
+// Sort order[b..e) ascending in one thread: insertion sort for the usual
+// handful of atoms per cell, heapsort (O(n log n)) for crowded cells, which
+// arise when out-of-domain or non-finite atoms are clamped into one cell.
+__device__ inline void sort_range(int *a, int n)
+{
+    if (n <= 32) {
+        for (int i = 1; i < n; i++) {
+            int v = a[i], j = i - 1;
+            while (j >= 0 && a[j] > v) {
+                a[j + 1] = a[j];
+                j--;
+            }
+            a[j + 1] = v;
+        }
+        return;
+    }
+    auto sift = [&](int root, int end) {
+        while (2 * root + 1 < end) {
+            int child = 2 * root + 1;
+            if (child + 1 < end && a[child] < a[child + 1]) child++;
+            if (a[root] >= a[child]) return;
+            int t = a[root];
+            a[root] = a[child];
+            a[child] = t;
+            root = child;
+        }
+    };
+    for (int i = n / 2 - 1; i >= 0; i--) sift(i, n);
+    for (int end = n - 1; end > 0; end--) {
+        int t = a[0];
+        a[0] = a[end];
+        a[end] = t;
+        sift(0, end);
+    }
+}
+
 template <typename T>
 __global__ void k_cell_sort(int64_t ncells, const int *__restrict__ start, int *__restrict__ order,
                             const vec4_t<T> *__restrict__ xyzq, vec4_t<T> *__restrict__ sxyzq,
@@ -146,15 +182,7 @@ __global__ void k_cell_sort(int64_t ncells, const int *__restrict__ start, int *
     int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= ncells) return;
     int b = start[c], e = start[c + 1];
-    for (int i = b + 1; i < e; i++) {
-        int v = order[i];
-        int j = i - 1;
-        while (j >= b && order[j] > v) {
-            order[j + 1] = order[j];
-            j--;
-        }
-        order[j + 1] = v;
-    }
+    sort_range(order + b, e - b);
     for (int i = b; i < e; i++) sxyzq[i] = xyzq[order[i]];
     if (maux)
         for (int i = b; i < e; i++) saux[i] = maux[order[i] % period];

@@ -150,6 +150,21 @@ def test_non_cubic_domain_and_boundary_atoms():
     assert max_rel(p, po) < 1e-11
 
 
+def test_crowded_cell():
+    # 300 atoms inside one 0.2 nm cube (a single cell) plus 300 spread out:
+    # the per-cell ordering takes its heapsort branch
+    rng = np.random.default_rng(17)
+    xyz = np.concatenate([rng.uniform(1.02, 1.22, (300, 3)), rng.uniform(0.0, 3.0, (300, 3))])
+    q = rng.standard_normal(600) * 0.1
+    from workloads import Workload
+    w = Workload("crowded", xyz, q, np.zeros(3), np.full(3, 3.0), a=0.8, h=0.25)
+    _, e, f, p = run_gpu(w, "fp64")
+    eo, fo, po = run_oracle(w)
+    assert e == pytest.approx(eo, rel=1e-11)
+    assert max_rel(f, fo) < 1e-10
+    assert max_rel(p, po) < 1e-10
+
+
 def test_single_atom_and_pair():
     from workloads import Workload
     for xyz, q in [(np.array([[1.1, 0.7, 1.9]]), np.array([1.5])),
