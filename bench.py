@@ -53,7 +53,15 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the 32-slice and uneven batches")
     ap.add_argument("--no-parareal", action="store_true")
     ap.add_argument("--slices", type=int, default=32)
-    return ap.parse_args()
+    ap.add_argument("--only-fp32", action="store_true",
+                    help="time only the single-system FP32 path (for profiler runs)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="after the timed steps, copy a tensor of this many MiB 5 times (a plain copy "
+                         "kernel of known traffic, to calibrate the memory counters)")
+    args = ap.parse_args()
+    if args.only_fp32:
+        args.no_fp64 = args.no_accuracy = args.no_cpu_baseline = args.no_batched = args.no_parareal = True
+    return args
 
 
 def unique_pairs(xyz, a):
@@ -285,6 +293,12 @@ def main():
     ctx.check()
     stages32 = stage_profile(torch, ctx, x32, out32, args.steps)
     value = n / (ms32 * 1e-3)
+    if args.copy_calibration_mib > 0:
+        src = torch.ones(args.copy_calibration_mib * (1 << 18), dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
 
     # ---- double-precision plain path ----
     fp64 = None
