@@ -50,6 +50,9 @@ struct SysPlan {
     int64_t uoff[kMaxLevels];// offset of the unpadded potential grids
     int64_t group0;          // first 64-atom pair group
     int64_t ngroups;
+    int kc;                  // levels kc .. l-1 are small: their restriction and prolongation run in one
+                             // workgroup (kc = l: none)
+    int top_in_chain;        // the top level is evaluated by that workgroup too
 };
 
 __host__ __device__ inline int padded_x(int d) { return d + 2 * kGridPad + kStencilTile; }

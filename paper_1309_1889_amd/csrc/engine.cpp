@@ -17,6 +17,11 @@ namespace {
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
+// A level with at most this many nodes would be handled by the one-workgroup
+// chains. Measured on the 99,999-atom water box, one workgroup is slower than
+// a launch per level already for the 512-node top grid, so the chains are off.
+constexpr int64_t kChainNodes = 0;
+
 int64_t floordiv2(int64_t v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }
 int64_t ceildiv2(int64_t v) { return -floordiv2(-v); }
 
@@ -126,11 +131,12 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
 
     std::vector<SysPlan> sys(nsys);
     const int W = nsys + 1;
-    std::vector<int64_t> atom_p(W), group_p(W), cell_p(W), iblk_p(W), top_p(W);
+    std::vector<int64_t> atom_p(W), group_p(W), cell_p(W), iblk_p(W), top_p(W), ant_p(W);
     std::vector<int64_t> node_p((size_t)kMaxLevels * W);
-    int64_t cells = 0, q = 0, u = 0, groups = 0, iblk = 0, top = 0;
+    int64_t cells = 0, q = 0, u = 0, groups = 0, iblk = 0, top = 0, ant = 0;
     int64_t nodes[kMaxLevels] = {0};
-    int maxlev = 1, top_d2 = 0;
+    int maxlev = 1, top_d2 = 0, kc_max = 0;
+    bool any_chain = false;
     for (int s = 0; s < nsys; s++) {
         const double *lo = domains ? domains + 6 * s : c->prm.lo;
         const double *hi = domains ? domains + 6 * s + 3 : c->prm.hi;
@@ -164,6 +170,8 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
         cell_p[s] = cells;
         iblk_p[s] = iblk;
         top_p[s] = top;
+        ant_p[s] = ant;
+        ant += anterp_tiles(g.gdim[0][0], g.gdim[0][1], g.gdim[0][2]);
         for (int k = 0; k < kMaxLevels; k++) node_p[(size_t)k * W + s] = nodes[k];
         for (int k = 0; k < g.nlev; k++) {
             P.qoff[k] = q;
@@ -174,7 +182,19 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
             nodes[k] += n;
         }
         const int kt = g.nlev - 1;
-        top += (int64_t)g.gdim[kt][0] * g.gdim[kt][1] * g.gdim[kt][2];
+        // levels from kc on are small enough for one workgroup (restriction and
+        // prolongation chains); a small top level is evaluated there too
+        P.kc = g.nlev;
+        for (int k = 1; k < g.nlev; k++)
+            if ((int64_t)g.gdim[k][0] * g.gdim[k][1] * g.gdim[k][2] <= kChainNodes) {
+                P.kc = k;
+                break;
+            }
+        const int mtop = g.gdim[kt][0] * g.gdim[kt][1] * g.gdim[kt][2];
+        P.top_in_chain = (kChainNodes > 0 && mtop <= top_stage_limit()) ? 1 : 0;
+        if (!P.top_in_chain) top += top_blocks(mtop);
+        if (P.kc < g.nlev || P.top_in_chain) any_chain = true;
+        kc_max = std::max(kc_max, P.kc);
         int d2 = 0;
         for (int d = 0; d < 3; d++) d2 += (g.gdim[kt][d] - 1) * (g.gdim[kt][d] - 1);
         top_d2 = std::max(top_d2, d2);
@@ -187,6 +207,7 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     cell_p[nsys] = cells;
     iblk_p[nsys] = iblk;
     top_p[nsys] = top;
+    ant_p[nsys] = ant;
     for (int k = 0; k < kMaxLevels; k++) node_p[(size_t)k * W + nsys] = nodes[k];
     // stencil tiles of every level below each system's top, segment k*nsys + s
     const int esz = c->prm.precision == MSM_FP32 ? 4 : 8;
@@ -216,7 +237,7 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     const size_t o_sys = place(sizeof(SysPlan) * nsys);
     const size_t o_atom = place(sizeof(int64_t) * W), o_group = place(sizeof(int64_t) * W);
     const size_t o_cell = place(sizeof(int64_t) * W), o_iblk = place(sizeof(int64_t) * W);
-    const size_t o_top = place(sizeof(int64_t) * W);
+    const size_t o_top = place(sizeof(int64_t) * W), o_ant = place(sizeof(int64_t) * W);
     const size_t o_node = place(sizeof(int64_t) * kMaxLevels * W), o_tile = place(sizeof(int64_t) * (nseg + 1));
     // the staging buffer may still feed an earlier copy
     if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
@@ -237,6 +258,7 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     std::memcpy(h + o_cell, cell_p.data(), sizeof(int64_t) * W);
     std::memcpy(h + o_iblk, iblk_p.data(), sizeof(int64_t) * W);
     std::memcpy(h + o_top, top_p.data(), sizeof(int64_t) * W);
+    std::memcpy(h + o_ant, ant_p.data(), sizeof(int64_t) * W);
     std::memcpy(h + o_node, node_p.data(), sizeof(int64_t) * kMaxLevels * W);
     std::memcpy(h + o_tile, tile_p.data(), sizeof(int64_t) * (nseg + 1));
     if (hipMemcpyAsync(c->plan_dev, h, off, hipMemcpyHostToDevice, c->stream) != hipSuccess) return MSM_ERR_HIP;
@@ -250,6 +272,7 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     dp.cell_prefix = (const int64_t *)(d + o_cell);
     dp.iblk_prefix = (const int64_t *)(d + o_iblk);
     dp.top_prefix = (const int64_t *)(d + o_top);
+    dp.ant_prefix = (const int64_t *)(d + o_ant);
     dp.node_prefix = (const int64_t *)(d + o_node);
     dp.tile_prefix = (const int64_t *)(d + o_tile);
     dp.ntile_seg = nseg;
@@ -260,8 +283,11 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     dp.ncells = cells;
     dp.niblk = iblk;
     dp.ntop = top;
+    dp.nant = ant;
     for (int k = 0; k < kMaxLevels; k++) dp.nnodes[k] = nodes[k];
     dp.maxlev = maxlev;
+    dp.kc_max = kc_max;
+    dp.any_chain = any_chain;
     c->host_sys = sys;
     c->last_offsets.assign(offsets, offsets + nsys + 1);
     if (domains) c->last_domains.assign(domains, domains + nsys * 6);
@@ -294,8 +320,10 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     mark(MSM_STAGE_ANTERP);
     if ((e = L::anterp(s, p, w)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_RESTRICT);
-    for (int k = 0; k + 1 < p.maxlev; k++)
+    // large levels one launch each, then the small levels and a small top in one workgroup per system
+    for (int k = 0; k + 1 < p.maxlev && k + 1 < p.kc_max; k++)
         if ((e = L::restrict_level(s, p, w, k)) != hipSuccess) return MSM_ERR_HIP;
+    if (p.any_chain && (e = L::restrict_chain(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_CUTOFF);
     {
         StencilTables<T> tb{c->wcols, (const T *)c->weights, c->ncols, c->mc.reach};
@@ -304,7 +332,8 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     mark(MSM_STAGE_TOP);
     if ((e = L::top_level(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_PROLONG);
-    for (int k = p.maxlev - 2; k >= 0; k--)
+    if (p.any_chain && (e = L::prolong_chain(s, p, w)) != hipSuccess) return MSM_ERR_HIP;
+    for (int k = std::min(p.maxlev - 2, p.kc_max - 1); k >= 0; k--)
         if ((e = L::prolong_level(s, p, w, k)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_INTERP);
     if ((e = L::interp(s, p, w, c->mc, (T *)forces, (T *)pots)) != hipSuccess) return MSM_ERR_HIP;

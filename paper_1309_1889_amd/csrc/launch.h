@@ -20,10 +20,13 @@ struct DevPlan {
     const int64_t *node_prefix;  // kMaxLevels x (nsys+1): level-k nodes per system
     const int64_t *iblk_prefix;  // nsys+1: interpolation blocks per system
     const int64_t *tile_prefix;  // ntile_seg+1: stencil tiles of segment k*nsys + s (levels below the top)
-    const int64_t *top_prefix;   // nsys+1: top-level nodes per system
+    const int64_t *top_prefix;   // nsys+1: top-level workgroups per system
+    const int64_t *ant_prefix;   // nsys+1: anterpolation tiles per system
     int ntile_seg;               // (maxlev - 1) * nsys
     int top_d2;                  // largest squared index distance on any top grid
-    int64_t natoms, ngroups, ncells, niblk, ntop, ntiles;
+    int64_t natoms, ngroups, ncells, niblk, ntop, ntiles, nant;
+    int kc_max;                  // largest chain start (SysPlan::kc) over the systems
+    bool any_chain;              // some system leaves levels or its top to the chains
     int64_t nnodes[kMaxLevels];  // level-k nodes over the batch
     int maxlev;                  // largest level count in the batch
 };
@@ -59,6 +62,9 @@ template <typename T> struct StencilTables {
 };
 
 int stencil_tile_xy(int elem_bytes, int reach);
+int anterp_tiles(int dx, int dy, int dz);
+int top_blocks(int nodes);
+int top_stage_limit();
 int stencil_tile_z(int elem_bytes, int reach);
 
 struct MethodConst {
@@ -76,6 +82,8 @@ template <typename T> struct Launch {
     static hipError_t stencil(hipStream_t s, const DevPlan &p, const Work<T> &w, const StencilTables<T> &tb);
     static hipError_t top_level(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m);
     static hipError_t prolong_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k);
+    static hipError_t restrict_chain(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m);
+    static hipError_t prolong_chain(hipStream_t s, const DevPlan &p, const Work<T> &w);
     static hipError_t interp(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m,
                              T *forces, T *potentials);
     static hipError_t energy(hipStream_t s, const DevPlan &p, const Work<T> &w, double *energy);

@@ -37,6 +37,17 @@ template <typename T> __device__ inline T wave_max(T v)
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// Workgroups are handed to the 8 XCDs (each with its own L2) round-robin by
+// launch index. Remap the index so that XCD x works on one contiguous range
+// of tiles: neighbouring tiles share their halo data in that XCD's L2.
+__device__ inline int64_t xcd_remap(int64_t b, int64_t n)
+{
+    constexpr int kXcd = 8;
+    const int64_t base = n / kXcd, rem = n % kXcd;
+    const int64_t x = b % kXcd, i = b / kXcd;
+    return x * base + (x < rem ? x : rem) + i;
+}
+
 template <typename T> __device__ inline int cell_floor(T t, int nc)
 {
     // floor, clamped to the cell range; NaN maps to 0
@@ -62,15 +73,69 @@ template <typename T> struct PairK {
     T a2;            // a^2
     T reach;         // a plus a rounding margin, for the row search
     T inv_a2;        // 1/a^2
-    T c0, c1, c2;    // gamma(rho)/a = c0 + c1 rho^2 + c2 rho^4
-    T d0, d1;        // -gamma'(rho)/(a^2 rho) / a ... = d0 + d1 rho^2 (force bracket term)
+    T c0, c1, c2;    // gamma(r/a)/a = c0 + c1 r^2 + c2 r^4
+    T d0, d1;        // -(d/dr)(gamma(r/a)/a) / r = d0 + d1 r^2
 };
 
-constexpr int kPairWaves = 4;   // waves sharing one group's candidate rows
+#ifndef MSMX_PAIR_WAVES
+#define MSMX_PAIR_WAVES 8
+#endif
+constexpr int kPairWaves = MSMX_PAIR_WAVES;   // waves sharing one group's candidate rows
+#ifndef MSMX_PAIR_UNROLL
+#define MSMX_PAIR_UNROLL 8
+#endif
+constexpr int kPairUnroll = MSMX_PAIR_UNROLL;   // staged candidates read per step
 
 // molecule id stored in the first component of an aux record
 __device__ inline int mol_of(const float4 &v) { return __float_as_int(v.x); }
 __device__ inline int mol_of(const double4 &v) { return (int)__double_as_longlong(v.x); }
+
+// Per-wave LDS: the flattened candidate stream of the wave's 64 current work
+// items and the staged chunk of 64 candidate atoms.
+template <typename T, bool MD> struct PairLds {
+    int pre[kWave + 1];                // start of each item's atoms in the stream
+    int first[kWave];                  // first atom of each item
+    vec4_t<T> atom[kWave];             // staged candidates
+    vec4_t<T> aux[MD ? kWave : 1];
+};
+
+template <typename T, bool MD>
+__device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const vec4_t<T> &aj, const vec4_t<T> &xj,
+                                 const PairK<T> &k, T &fx, T &fy, T &fz, T &u, T &lx, T &ly, T &lz, T &le)
+{
+    const T dx = ai.x - aj.x, dy = ai.y - aj.y, dz = ai.z - aj.z;
+    const T r2 = dx * dx + dy * dy + dz * dz;
+    if (r2 < k.a2 && r2 > T(0)) {
+        const T rinv = rsqrt_t(r2);
+        T rc = rinv;
+        bool same = false;
+        if (MD) {
+            same = mol_of(xi) == mol_of(xj);
+            rc = same ? T(0) : rinv;
+        }
+        const T gs = rc - (k.c0 + r2 * (k.c1 + r2 * k.c2));
+        const T br = rc * rinv * rinv - (k.d0 + k.d1 * r2);
+        u += aj.w * gs;
+        const T t = aj.w * br;
+        fx += t * dx;
+        fy += t * dy;
+        fz += t * dz;
+        if (MD) {
+            const T eps = same ? T(0) : xi.z * xj.z;
+            if (eps != T(0)) {
+                const T sg = xi.y + xj.y;
+                const T s2 = sg * sg;
+                const T sr2 = s2 * rinv * rinv, sr6 = sr2 * sr2 * sr2;
+                const T sc2 = s2 * k.inv_a2, sc6 = sc2 * sc2 * sc2;
+                le += T(4) * eps * ((sr6 * sr6 - sr6) - (sc6 * sc6 - sc6));
+                const T fl = T(24) * eps * (T(2) * sr6 * sr6 - sr6) * rinv * rinv;
+                lx += fl * dx;
+                ly += fl * dy;
+                lz += fl * dz;
+            }
+        }
+    }
+}
 
 // Dynamics variant (MD = true): pairs inside one molecule are excluded from
 // Coulomb's law, so instead of g* they contribute -gamma(r/a)/a, which cancels
@@ -78,6 +143,17 @@ __device__ inline int mol_of(const double4 &v) { return (int)__double_as_longlon
 // 4 eps ((s/r)^12 - (s/r)^6), shifted to zero at r = a, acts between atoms of
 // different molecules, with s = s_i/2 + s_j/2 and eps = sqrt(eps_i) sqrt(eps_j)
 // stored per atom in aux = (molecule id bits, s/2, sqrt(eps), 0).
+//
+// Work layout: a workgroup of kPairWaves waves owns one group of 64
+// consecutive sorted atoms (one per lane). The work items are the pieces of
+// cell rows (cy, cz) inside one brick column that can reach the group's
+// bounding box; each is clipped to the chord the cutoff sphere leaves its
+// row and is one contiguous run of sorted atoms. Items are dealt round-robin
+// to the waves. A wave lays 64 items at a time out as one stream of
+// candidate atoms, stages the stream 64 atoms at a time in LDS with one
+// coalesced load (the next chunk is fetched while the current one is used),
+// and every lane reads each staged atom by broadcast and evaluates its own
+// pair. The waves' partial sums are added in a fixed order at the end.
 template <typename T, bool MD>
 __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                               const int *__restrict__ cstart,
@@ -85,6 +161,7 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
                                                               const vec4_t<T> *__restrict__ saux,
                                                               vec4_t<T> *__restrict__ ljout)
 {
+    __shared__ PairLds<T, MD> lds[kPairWaves];
     __shared__ vec4_t<T> red[kPairWaves][kWave];
     __shared__ vec4_t<T> redlj[MD ? kPairWaves : 1][kWave];
     const int64_t g = blockIdx.x;
@@ -94,6 +171,7 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
     const int64_t end = P.atom0 + P.natoms;
     const int lane = threadIdx.x % kWave;
     const int wv = uni((int)(threadIdx.x / kWave));
+    PairLds<T, MD> &L = lds[wv];
     const int64_t i = first + lane;
     const bool valid = i < end;
     const vec4_t<T> ai = sx[valid ? i : first];
@@ -107,86 +185,100 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
     const T inv_h = T(P.inv_h), h = T(1.0 / P.inv_h);
     const int ncx = P.nc[0], ncy = P.nc[1], ncz = P.nc[2];
     const T reach = k.reach, reach2 = k.reach * k.reach;
-
     const int cy0 = clampi((int)floor((bminy - loy - reach) * inv_h), 0, ncy - 1);
     const int cy1 = clampi((int)floor((bmaxy - loy + reach) * inv_h), 0, ncy - 1);
     const int cz0 = clampi((int)floor((bminz - loz - reach) * inv_h), 0, ncz - 1);
     const int cz1 = clampi((int)floor((bmaxz - loz + reach) * inv_h), 0, ncz - 1);
+    const int bx0 = clampi((int)floor((bminx - lox - reach) * inv_h), 0, ncx - 1) / kBrick;
+    const int bx1 = clampi((int)floor((bmaxx - lox + reach) * inv_h), 0, ncx - 1) / kBrick;
+    const int nbx = bx1 - bx0 + 1, ny = cy1 - cy0 + 1;
+    const int nitems = nbx * ny * (cz1 - cz0 + 1);
 
     T fx = 0, fy = 0, fz = 0, u = 0;
     T lx = 0, ly = 0, lz = 0, le = 0;
-    int row = 0;
-    for (int cz = cz0; cz <= cz1; ++cz) {
-        const T z0 = loz + T(cz) * h;
-        const T dz = fmax(T(0), fmax(z0 - bmaxz, bminz - (z0 + h)));
-        for (int cy = cy0; cy <= cy1; ++cy) {
-            const T y0 = loy + T(cy) * h;
+    // items wv, wv + W, wv + 2W, ..., 64 per batch
+    for (int ib = wv; ib < nitems; ib += kPairWaves * kWave) {
+        const int q = ib + kPairWaves * lane;            // this lane's item
+        int len = 0, jb = 0;
+        if (q < nitems) {
+            const int bx = bx0 + q % nbx, row = q / nbx;
+            const int cy = cy0 + row % ny, cz = cz0 + row / ny;
+            const T z0 = loz + T(cz) * h, y0 = loy + T(cy) * h;
+            const T dz = fmax(T(0), fmax(z0 - bmaxz, bminz - (z0 + h)));
             const T dy = fmax(T(0), fmax(y0 - bmaxy, bminy - (y0 + h)));
             const T rem = reach2 - dy * dy - dz * dz;
-            if (rem <= T(0)) continue;
-            // rows that reach the group are dealt round-robin to the waves
-            if ((row++ % kPairWaves) != wv) continue;
-            const T wdt = sqrt(rem);
-            const int cx0 = clampi((int)floor((bminx - lox - wdt) * inv_h), 0, ncx - 1);
-            const int cx1 = clampi((int)floor((bmaxx - lox + wdt) * inv_h), 0, ncx - 1);
-            for (int bx = cx0 / kBrick; bx <= cx1 / kBrick; ++bx) {
-                const int ca = max(cx0, bx * kBrick);
-                const int cb = min(cx1, bx * kBrick + kBrick - 1);
-                const int64_t r0 = P.cell0 + cell_rank(P, ca, cy, cz);
-                const int jb = uni(cstart[r0]);
-                const int je = uni(cstart[r0 + (cb - ca) + 1]);
-                if (jb >= je) continue;
-                // the atom array carries one spare element, so the prefetch of
-                // j + 1 past the last atom stays inside the allocation
-                vec4_t<T> nxt = sx[jb];
-                for (int j = jb; j < je; ++j) {
-                    const vec4_t<T> aj = nxt;
-                    nxt = sx[j + 1];
-                    const T dx = ai.x - aj.x, ddy = ai.y - aj.y, ddz = ai.z - aj.z;
-                    const T r2 = dx * dx + ddy * ddy + ddz * ddz;
-                    if (!MD) {
-                        if (r2 < k.a2 && r2 > T(0)) {
-                            const T rinv = rsqrt_t(r2);
-                            const T rho2 = r2 * k.inv_a2;
-                            const T gs = rinv - (k.c0 + rho2 * (k.c1 + rho2 * k.c2));
-                            const T br = rinv * rinv * rinv - (k.d0 + k.d1 * rho2);
-                            u += aj.w * gs;
-                            const T t = aj.w * br;
-                            fx += t * dx;
-                            fy += t * ddy;
-                            fz += t * ddz;
-                        }
-                    } else {
-                        const vec4_t<T> xj = saux[j];
-                        if (r2 < k.a2 && r2 > T(0)) {
-                            const bool same = mol_of(xi) == mol_of(xj);
-                            const T rinv = rsqrt_t(r2);
-                            const T rho2 = r2 * k.inv_a2;
-                            const T rc = same ? T(0) : rinv;
-                            const T gs = rc - (k.c0 + rho2 * (k.c1 + rho2 * k.c2));
-                            const T br = rc * rinv * rinv - (k.d0 + k.d1 * rho2);
-                            u += aj.w * gs;
-                            const T t = aj.w * br;
-                            fx += t * dx;
-                            fy += t * ddy;
-                            fz += t * ddz;
-                            const T eps = same ? T(0) : xi.z * xj.z;
-                            if (eps != T(0)) {
-                                const T sg = xi.y + xj.y;
-                                const T s2 = sg * sg;
-                                const T sr2 = s2 * rinv * rinv, sr6 = sr2 * sr2 * sr2;
-                                const T sc2 = s2 * k.inv_a2, sc6 = sc2 * sc2 * sc2;
-                                le += T(4) * eps * ((sr6 * sr6 - sr6) - (sc6 * sc6 - sc6));
-                                const T fl = T(24) * eps * (T(2) * sr6 * sr6 - sr6) * rinv * rinv;
-                                lx += fl * dx;
-                                ly += fl * ddy;
-                                lz += fl * ddz;
-                            }
-                        }
-                    }
+            if (rem > T(0)) {
+                const T wdt = sqrt(rem);
+                const int cx0 = clampi((int)floor((bminx - lox - wdt) * inv_h), 0, ncx - 1);
+                const int cx1 = clampi((int)floor((bmaxx - lox + wdt) * inv_h), 0, ncx - 1);
+                const int ca = max(cx0, bx * kBrick), cb = min(cx1, bx * kBrick + kBrick - 1);
+                if (ca <= cb) {
+                    const int64_t r0 = P.cell0 + cell_rank(P, ca, cy, cz);
+                    jb = cstart[r0];
+                    len = cstart[r0 + (cb - ca) + 1] - jb;
                 }
             }
         }
+        // exclusive prefix of the item lengths across the wave
+        int incl = len;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int v = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += v;
+        }
+        L.pre[lane] = incl - len;
+        L.first[lane] = jb;
+        const int total = uni(__shfl(incl, kWave - 1, kWave));
+        if (lane == 0) L.pre[kWave] = total;
+        // the wave's own LDS writes are seen by its later reads (one wave, in
+        // order); the barrier only keeps the compiler from moving them
+        __builtin_amdgcn_wave_barrier();
+        // stream position -> sorted atom index
+        auto locate = [&](int pos) -> int {
+            int lo_ = 0, hi_ = kWave;       // pre[lo_] <= pos < pre[hi_]
+            while (hi_ - lo_ > 1) {
+                const int mid = (lo_ + hi_) >> 1;
+                if (L.pre[mid] <= pos) lo_ = mid; else hi_ = mid;
+            }
+            return L.first[lo_] + (pos - L.pre[lo_]);
+        };
+        vec4_t<T> pa, px;
+        if (lane < total) {
+            const int j = locate(lane);
+            pa = sx[j];
+            if (MD) px = saux[j];
+        }
+        for (int c0 = 0; c0 < total; c0 += kWave) {
+            __builtin_amdgcn_wave_barrier();
+            L.atom[lane] = pa;
+            if (MD) L.aux[lane] = px;
+            __builtin_amdgcn_wave_barrier();
+            const int nxt = c0 + kWave + lane;
+            if (nxt < total) {
+                const int j = locate(nxt);
+                pa = sx[j];
+                if (MD) px = saux[j];
+            }
+            const int cnt = uni(min(kWave, total - c0));
+            int t = 0;
+            // unrolled so that several broadcast reads are in flight at once
+            for (; t + kPairUnroll <= cnt; t += kPairUnroll) {
+                vec4_t<T> aj[kPairUnroll], xj[kPairUnroll];
+#pragma unroll
+                for (int v = 0; v < kPairUnroll; ++v) {
+                    aj[v] = L.atom[t + v];
+                    xj[v] = MD ? L.aux[t + v] : aj[v];
+                }
+#pragma unroll
+                for (int v = 0; v < kPairUnroll; ++v)
+                    pair_term<T, MD>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le);
+            }
+            for (; t < cnt; ++t) {
+                const vec4_t<T> aj = L.atom[t];
+                const vec4_t<T> xj = MD ? L.aux[t] : aj;
+                pair_term<T, MD>(ai, xi, aj, xj, k, fx, fy, fz, u, lx, ly, lz, le);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
     }
     vec4_t<T> o;
     o.x = fx;
@@ -229,22 +321,26 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
 
 // ---------------------------------------------------------------------------
 // Anterpolation (Section 3): q^0_mu = sum_j phi^0_mu(r_j) q_j. Gather form:
-// one thread per level-0 node sums over the atoms of the 4x4x4 cells whose
-// support covers it (cells mu-2 .. mu+1 per axis), so no atomics are needed.
+// each level-0 node sums over the atoms of the 4x4x4 cells whose support
+// covers it (cells mu-2 .. mu+1 per axis), so no atomics are needed.
+//
+// A workgroup owns an 8x8x4 tile of nodes. It first stages the atoms of the
+// 11x11x7 cells the tile can reach in LDS, as grid coordinates
+// (t = (r - lo)/h, q), row by row in x order with a table of where each
+// cell's atoms start; each thread then gathers its node from LDS. A tile
+// whose region holds more atoms than the LDS buffer gathers from global
+// memory instead.
 // ---------------------------------------------------------------------------
+constexpr int kAntX = 8, kAntY = 8, kAntZ = 4;
+constexpr int kAntCX = kAntX + 3, kAntCY = kAntY + 3, kAntCZ = kAntZ + 3;   // cells reached
+constexpr int kAntRows = kAntCY * kAntCZ;
+constexpr int kAntCells = kAntRows * kAntCX;
+constexpr int kAntAtoms = 3072;
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__restrict__ sx,
-                                                const int *__restrict__ cstart, T *__restrict__ qgrid)
+__device__ inline T gather_global(const SysPlan &P, const vec4_t<T> *__restrict__ sx, const int *__restrict__ cstart,
+                                  int ix, int iy, int iz)
 {
-    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= p.nnodes[0]) return;
-    const int64_t *pref = p.node_prefix;
-    const int s = find_segment(pref, p.nsys, g);
-    const SysPlan &P = p.sys[s];
-    const int64_t loc = g - pref[s];
-    const int dx = P.gdim[0][0], dy = P.gdim[0][1];
-    const int rx = (int)(loc % dx), ry = (int)((loc / dx) % dy), rz = (int)(loc / ((int64_t)dx * dy));
-    const int ix = rx + P.gorg[0][0], iy = ry + P.gorg[0][1], iz = rz + P.gorg[0][2];
     const T lox = T(P.lo[0]), loy = T(P.lo[1]), loz = T(P.lo[2]), inv_h = T(P.inv_h);
     const int cx0 = max(ix - 2, 0), cx1 = min(ix + 1, P.nc[0] - 1);
     T acc = 0;
@@ -260,6 +356,101 @@ __global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__re
                     acc += basis(tx - T(ix)) * basis(ty - T(iy)) * basis(tz - T(iz)) * a.w;
                 }
             }
+    return acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__restrict__ sx,
+                                                const int *__restrict__ cstart, T *__restrict__ qgrid)
+{
+    __shared__ vec4_t<T> atoms[kAntAtoms];
+    __shared__ int start[kAntCells + 1];
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    const int s = find_segment(p.ant_prefix, p.nsys, blk);
+    const SysPlan &P = p.sys[s];
+    const int dx = P.gdim[0][0], dy = P.gdim[0][1], dz = P.gdim[0][2];
+    const int ntx = (dx + kAntX - 1) / kAntX, nty = (dy + kAntY - 1) / kAntY;
+    const int64_t t = blk - p.ant_prefix[s];
+    // tile origin in absolute node indices
+    const int x0 = (int)(t % ntx) * kAntX + P.gorg[0][0];
+    const int y0 = (int)((t / ntx) % nty) * kAntY + P.gorg[0][1];
+    const int z0 = (int)(t / ((int64_t)ntx * nty)) * kAntZ + P.gorg[0][2];
+    const int tid = threadIdx.x;
+
+    // cell counts of the reachable region (cells x0-2 .. x0+kAntX, ...), 0 outside the grid
+    for (int c = tid; c < kAntCells; c += 256) {
+        const int ex = c % kAntCX, row = c / kAntCX;
+        const int cx = x0 - 2 + ex, cy = y0 - 2 + row % kAntCY, cz = z0 - 2 + row / kAntCY;
+        int n = 0;
+        if (cx >= 0 && cy >= 0 && cz >= 0 && cx < P.nc[0] && cy < P.nc[1] && cz < P.nc[2]) {
+            const int64_t r = P.cell0 + cell_rank(P, cx, cy, cz);
+            n = cstart[r + 1] - cstart[r];
+        }
+        start[c + 1] = n;
+    }
+    if (tid == 0) start[0] = 0;
+    __syncthreads();
+    // inclusive scan of the counts (small: one pass per thread stride, in order)
+    if (tid < kWave) {
+        // each lane sums a contiguous chunk, the wave scans the chunk sums
+        constexpr int chunk = (kAntCells + kWave - 1) / kWave;
+        const int b0 = 1 + tid * chunk, b1 = min(b0 + chunk, kAntCells + 1);
+        int sum = 0;
+        for (int i = b0; i < b1; ++i) sum += start[i];
+        int incl = sum;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int v = __shfl_up(incl, off, kWave);
+            if (tid >= off) incl += v;
+        }
+        int run = incl - sum;
+        for (int i = b0; i < b1; ++i) {
+            run += start[i];
+            start[i] = run;
+        }
+    }
+    __syncthreads();
+    const int total = start[kAntCells];
+    const bool staged = total <= kAntAtoms;
+    if (staged) {
+        const T lox = T(P.lo[0]), loy = T(P.lo[1]), loz = T(P.lo[2]), inv_h = T(P.inv_h);
+        for (int c = tid; c < kAntCells; c += 256) {
+            const int n = start[c + 1] - start[c];
+            if (n == 0) continue;
+            const int ex = c % kAntCX, row = c / kAntCX;
+            const int cx = x0 - 2 + ex, cy = y0 - 2 + row % kAntCY, cz = z0 - 2 + row / kAntCY;
+            const int64_t r = P.cell0 + cell_rank(P, cx, cy, cz);
+            const int jb = cstart[r];
+            for (int k = 0; k < n; ++k) {
+                const vec4_t<T> a = sx[jb + k];
+                vec4_t<T> o;
+                o.x = (a.x - lox) * inv_h;
+                o.y = (a.y - loy) * inv_h;
+                o.z = (a.z - loz) * inv_h;
+                o.w = a.w;
+                atoms[start[c] + k] = o;
+            }
+        }
+    }
+    __syncthreads();
+    const int lx = tid % kAntX, ly = (tid / kAntX) % kAntY, lz = tid / (kAntX * kAntY);
+    const int ix = x0 + lx, iy = y0 + ly, iz = z0 + lz;
+    const int rx = ix - P.gorg[0][0], ry = iy - P.gorg[0][1], rz = iz - P.gorg[0][2];
+    if (rx >= dx || ry >= dy || rz >= dz) return;
+    T acc = 0;
+    if (staged) {
+        const T fx = T(ix), fy = T(iy), fz = T(iz);
+        for (int ez = lz; ez < lz + 4; ++ez)
+            for (int ey = ly; ey < ly + 4; ++ey) {
+                const int row = ez * kAntCY + ey;
+                const int jb = start[row * kAntCX + lx], je = start[row * kAntCX + lx + 4];
+                for (int j = jb; j < je; ++j) {
+                    const vec4_t<T> a = atoms[j];
+                    acc += basis(a.x - fx) * basis(a.y - fy) * basis(a.z - fz) * a.w;
+                }
+            }
+    } else {
+        acc = gather_global<T>(P, sx, cstart, ix, iy, iz);
+    }
     const int PX = padded_x(dx), PY = padded_x(dy);
     qgrid[P.qoff[0] + ((int64_t)(rz + kGridPad) * PY + (ry + kGridPad)) * PX + (rx + kGridPad)] = acc;
 }
@@ -271,16 +462,8 @@ __global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__re
 // offsets -3, -1, 0, 1, 3. The zero halo of the fine grid stands in for nodes
 // outside its range.
 // ---------------------------------------------------------------------------
-template <typename T>
-__global__ __launch_bounds__(256) void k_restrict(DevPlan p, T *__restrict__ qgrid, int k)
+template <typename T> __device__ inline void restrict_node(const SysPlan &P, T *__restrict__ qgrid, int k, int64_t loc)
 {
-    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= p.nnodes[k + 1]) return;
-    const int64_t *pref = p.node_prefix + (int64_t)(k + 1) * (p.nsys + 1);
-    const int s = find_segment(pref, p.nsys, g);
-    const SysPlan &P = p.sys[s];
-    if (k + 1 >= P.nlev) return;
-    const int64_t loc = g - pref[s];
     const int cdx = P.gdim[k + 1][0], cdy = P.gdim[k + 1][1];
     const int rx = (int)(loc % cdx), ry = (int)((loc / cdx) % cdy), rz = (int)(loc / ((int64_t)cdx * cdy));
     // fine-grid relative index of the coincident node 2 mu
@@ -292,12 +475,15 @@ __global__ __launch_bounds__(256) void k_restrict(DevPlan p, T *__restrict__ qgr
     const int off[5] = {-3, -1, 0, 1, 3};
     const T wt[5] = {basis(T(-1.5)), basis(T(-0.5)), T(1), basis(T(0.5)), basis(T(1.5))};
     T acc = 0;
+#pragma unroll
     for (int c = 0; c < 5; ++c) {
         const int64_t zrow = (int64_t)(fz + off[c] + kGridPad) * FY;
         T accy = 0;
+#pragma unroll
         for (int b = 0; b < 5; ++b) {
             const T *row = qf + (zrow + (fy + off[b] + kGridPad)) * FX + (fx + kGridPad);
             T accx = 0;
+#pragma unroll
             for (int a = 0; a < 5; ++a) accx += wt[a] * row[off[a]];
             accy += wt[b] * accx;
         }
@@ -305,6 +491,19 @@ __global__ __launch_bounds__(256) void k_restrict(DevPlan p, T *__restrict__ qgr
     }
     const int CX = padded_x(cdx), CY = padded_x(cdy);
     qgrid[P.qoff[k + 1] + ((int64_t)(rz + kGridPad) * CY + (ry + kGridPad)) * CX + (rx + kGridPad)] = acc;
+}
+
+// one level for every system whose coarse level k+1 is not left to the chain kernel
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict(DevPlan p, T *__restrict__ qgrid, int k)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= p.nnodes[k + 1]) return;
+    const int64_t *pref = p.node_prefix + (int64_t)(k + 1) * (p.nsys + 1);
+    const int s = find_segment(pref, p.nsys, g);
+    const SysPlan &P = p.sys[s];
+    if (k + 1 >= P.nlev || k + 1 >= P.kc) return;
+    restrict_node<T>(P, qgrid, k, g - pref[s]);
 }
 
 // ---------------------------------------------------------------------------
@@ -326,21 +525,22 @@ template <typename T, int R> struct StencilGeom {
     static constexpr int TXY = (sizeof(T) == 8 && R >= 10) ? 4 : kStencilTile;
     static constexpr int EX = TXY + 2 * R;
     static constexpr int EZ = TZ + 2 * R;
+    static constexpr int THREADS = 1024;
     static constexpr int COLS = TXY * TXY;            // output columns per tile
-    static constexpr int SHARES = 256 / COLS;         // threads per output column
+    static constexpr int SHARES = THREADS / COLS;     // threads per output column
     static constexpr int IN = EZ * EX * EX;           // staged charges
-    static constexpr int LDS = IN > 256 * TZ ? IN : 256 * TZ;   // also holds the share sums
+    static constexpr int LDS = IN > THREADS * TZ ? IN : THREADS * TZ;   // also holds the share sums
 };
 
 template <typename T, int R>
-__global__ __launch_bounds__(256) void k_stencil(DevPlan p, const T *__restrict__ qgrid, T *__restrict__ ucut,
+__global__ __launch_bounds__(1024) void k_stencil(DevPlan p, const T *__restrict__ qgrid, T *__restrict__ ucut,
                                                  const int2 *__restrict__ qcols, const T *__restrict__ qw, int ncols)
 {
     using G = StencilGeom<T, R>;
     constexpr int D = 2 * R + 1;
     constexpr int L = G::TZ + 2 * R;
     __shared__ T tile[G::LDS];
-    const int64_t blk = blockIdx.x;
+    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int seg = find_segment(p.tile_prefix, p.ntile_seg, blk);
     const int k = seg / p.nsys, s = seg % p.nsys;
     const SysPlan &P = p.sys[s];
@@ -353,7 +553,7 @@ __global__ __launch_bounds__(256) void k_stencil(DevPlan p, const T *__restrict_
     const T *q = qgrid + P.qoff[k];
 
     // stage the charges of the grown tile (the grid's zero halo covers the overhang)
-    for (int e = threadIdx.x; e < G::IN; e += 256) {
+    for (int e = threadIdx.x; e < G::IN; e += G::THREADS) {
         const int ex = e % G::EX, ey = (e / G::EX) % G::EX, ez = e / (G::EX * G::EX);
         tile[e] = q[((int64_t)(z0 + kGridPad - R + ez) * PY + (y0 + kGridPad - R + ey)) * PX + (x0 + kGridPad - R + ex)];
     }
@@ -398,7 +598,7 @@ __global__ __launch_bounds__(256) void k_stencil(DevPlan p, const T *__restrict_
     __syncthreads();
     const T scale = T(ldexp(1.0, -k));
     T *u = ucut + P.uoff[k];
-    for (int e = threadIdx.x; e < G::COLS * G::TZ; e += 256) {
+    for (int e = threadIdx.x; e < G::COLS * G::TZ; e += G::THREADS) {
         const int c = e / G::TZ, z = e % G::TZ;
         T v = part[c * G::TZ + z];
         for (int sh = 1; sh < G::SHARES; ++sh) v += part[(sh * G::COLS + c) * G::TZ + z];
@@ -412,7 +612,10 @@ __global__ __launch_bounds__(256) void k_stencil(DevPlan p, const T *__restrict_
 // all node pairs, g^{l-1}(r) = gamma(r / (2^{l-1} a)) / (2^{l-1} a). The grid
 // is at most a few hundred nodes; each thread sums over all of them.
 // ---------------------------------------------------------------------------
-constexpr int kTopTable = 4096;
+constexpr int kTopTable = 4096;   // weights by squared index distance held in LDS
+constexpr int kTopStage = 4096;   // top-grid charges held in LDS
+constexpr int kTopNodes = 32;     // output nodes per workgroup
+constexpr int kTopShares = 8;     // threads per output node (z-planes of the sources dealt round-robin)
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_top(DevPlan p, const T *__restrict__ qgrid, T *__restrict__ ucut,
@@ -421,34 +624,54 @@ __global__ __launch_bounds__(256) void k_top(DevPlan p, const T *__restrict__ qg
     // weights by squared integer distance d2: gamma(h sqrt(d2) / a) / a; the
     // level's factor 2^-(l-1) is applied to the sum
     __shared__ T tab[kTopTable];
-    for (int d2 = threadIdx.x; d2 < ntab && d2 < kTopTable; d2 += blockDim.x)
-        tab[d2] = gamma_s(T(h / a) * sqrt(T(d2))) * T(1.0 / a);
-    __syncthreads();
-    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= p.ntop) return;
-    const int s = find_segment(p.top_prefix, p.nsys, g);
+    __shared__ T qs[kTopStage];
+    __shared__ T part[kTopShares][kTopNodes];
+    const int64_t blk = blockIdx.x;
+    const int s = find_segment(p.top_prefix, p.nsys, blk);
     const SysPlan &P = p.sys[s];
     const int k = P.nlev - 1;
-    const int64_t loc = g - p.top_prefix[s];
     const int dx = P.gdim[k][0], dy = P.gdim[k][1], dz = P.gdim[k][2];
-    const int x = (int)(loc % dx), y = (int)((loc / dx) % dy), z = (int)(loc / ((int64_t)dx * dy));
+    const int M = dx * dy * dz;
     const int PX = padded_x(dx), PY = padded_x(dy);
     const T *q = qgrid + P.qoff[k];
+    const int tid = threadIdx.x;
+    for (int d2 = tid; d2 < ntab && d2 < kTopTable; d2 += 256)
+        tab[d2] = gamma_s(T(h / a) * sqrt(T(d2))) * T(1.0 / a);
+    for (int e = tid; e < M && e < kTopStage; e += 256) {
+        const int x = e % dx, y = (e / dx) % dy, z = e / (dx * dy);
+        qs[e] = q[((int64_t)(z + kGridPad) * PY + (y + kGridPad)) * PX + (x + kGridPad)];
+    }
+    __syncthreads();
+    const int lane = tid % kTopNodes, share = tid / kTopNodes;
+    const int node = (int)(blk - p.top_prefix[s]) * kTopNodes + lane;
     T acc = 0;
-    for (int nz = 0; nz < dz; ++nz)
-        for (int ny = 0; ny < dy; ++ny) {
-            const T *row = q + ((int64_t)(nz + kGridPad) * PY + (ny + kGridPad)) * PX + kGridPad;
-            const int eyz = (nz - z) * (nz - z) + (ny - y) * (ny - y);
-            for (int nx = 0; nx < dx; ++nx) {
-                const int d2 = eyz + (nx - x) * (nx - x);
-                const T w = d2 < kTopTable ? tab[d2] : gamma_s(T(h / a) * sqrt(T(d2))) * T(1.0 / a);
-                acc += w * row[nx];
+    if (node < M) {
+        const int x = node % dx, y = (node / dx) % dy, z = node / (dx * dy);
+        for (int nz = share; nz < dz; nz += kTopShares)
+            for (int ny = 0; ny < dy; ++ny) {
+                const int eyz = (nz - z) * (nz - z) + (ny - y) * (ny - y);
+                const int e0 = (nz * dy + ny) * dx;
+                for (int nx = 0; nx < dx; ++nx) {
+                    const int d2 = eyz + (nx - x) * (nx - x);
+                    const T w = d2 < kTopTable ? tab[d2] : gamma_s(T(h / a) * sqrt(T(d2))) * T(1.0 / a);
+                    const int e = e0 + nx;
+                    const T qv = e < kTopStage
+                                     ? qs[e]
+                                     : q[((int64_t)(nz + kGridPad) * PY + (ny + kGridPad)) * PX + (nx + kGridPad)];
+                    acc += w * qv;
+                }
             }
-        }
-    acc *= T(ldexp(1.0, -k));
-    const int64_t o = P.uoff[k] + ((int64_t)z * dy + y) * dx + x;
-    ucut[o] = acc;
-    ugrid[o] = acc;
+    }
+    part[share][lane] = acc;
+    __syncthreads();
+    if (share == 0 && node < M) {
+        T sum = part[0][lane];
+        for (int sh = 1; sh < kTopShares; ++sh) sum += part[sh][lane];   // fixed order
+        sum *= T(ldexp(1.0, -k));
+        const int64_t o = P.uoff[k] + node;
+        ucut[o] = sum;
+        ugrid[o] = sum;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -458,16 +681,9 @@ __global__ __launch_bounds__(256) void k_top(DevPlan p, const T *__restrict__ qg
 // -1/16, 9/16, 9/16, -1/16.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void k_prolong(DevPlan p, const T *__restrict__ ucut, T *__restrict__ ugrid,
-                                                 int k)
+__device__ inline void prolong_node(const SysPlan &P, const T *__restrict__ ucut, T *__restrict__ ugrid, int k,
+                                    int64_t loc)
 {
-    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (g >= p.nnodes[k]) return;
-    const int64_t *pref = p.node_prefix + (int64_t)k * (p.nsys + 1);
-    const int s = find_segment(pref, p.nsys, g);
-    const SysPlan &P = p.sys[s];
-    if (k >= P.nlev - 1) return;
-    const int64_t loc = g - pref[s];
     const int dx = P.gdim[k][0], dy = P.gdim[k][1];
     const int r[3] = {(int)(loc % dx), (int)((loc / dx) % dy), (int)(loc / ((int64_t)dx * dy))};
     int cn[3][4];
@@ -504,6 +720,93 @@ __global__ __launch_bounds__(256) void k_prolong(DevPlan p, const T *__restrict_
     }
     const int64_t o = P.uoff[k] + loc;
     ugrid[o] = ucut[o] + acc;
+}
+
+// one level for every system whose fine level k is not left to the chain kernel
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong(DevPlan p, const T *__restrict__ ucut, T *__restrict__ ugrid,
+                                                 int k)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= p.nnodes[k]) return;
+    const int64_t *pref = p.node_prefix + (int64_t)k * (p.nsys + 1);
+    const int s = find_segment(pref, p.nsys, g);
+    const SysPlan &P = p.sys[s];
+    if (k >= P.nlev - 1 || k >= P.kc) return;
+    prolong_node<T>(P, ucut, ugrid, k, g - pref[s]);
+}
+
+// ---------------------------------------------------------------------------
+// Coarse levels in one workgroup per system. The levels kc .. l-1 of a
+// system are small (a few ten thousand nodes at most), so one workgroup
+// walks them level by level with a barrier in between instead of one launch
+// per level: the restriction chain into them followed by the top level, and,
+// after the lattice cutoff, the prolongation chain down to level kc.
+// ---------------------------------------------------------------------------
+constexpr int kChainThreads = 1024;
+
+template <typename T>
+__device__ inline T top_weight(const T *tab, int d2, double h, double a)
+{
+    return d2 < kTopTable ? tab[d2] : gamma_s(T(h / a) * sqrt(T(d2))) * T(1.0 / a);
+}
+
+template <typename T>
+__global__ __launch_bounds__(kChainThreads) void k_restrict_chain(DevPlan p, T *__restrict__ qgrid,
+                                                                  T *__restrict__ ucut, T *__restrict__ ugrid,
+                                                                  double h, double a, int ntab)
+{
+    __shared__ T tab[kTopTable];
+    __shared__ T qs[kTopStage];
+    const SysPlan &P = p.sys[blockIdx.x];
+    const int tid = threadIdx.x;
+    for (int k = P.kc - 1; k + 1 < P.nlev; ++k) {
+        if (k < 0) continue;
+        const int64_t n = (int64_t)P.gdim[k + 1][0] * P.gdim[k + 1][1] * P.gdim[k + 1][2];
+        for (int64_t loc = tid; loc < n; loc += kChainThreads) restrict_node<T>(P, qgrid, k, loc);
+        __syncthreads();
+    }
+    if (!P.top_in_chain) return;
+    // top level: u^{l-1}_mu = 2^-(l-1) sum_nu gamma(h |mu - nu| / a) / a q^{l-1}_nu, all pairs
+    const int k = P.nlev - 1;
+    const int dx = P.gdim[k][0], dy = P.gdim[k][1], dz = P.gdim[k][2];
+    const int M = dx * dy * dz;
+    const int PX = padded_x(dx), PY = padded_x(dy);
+    const T *q = qgrid + P.qoff[k];
+    for (int d2 = tid; d2 < ntab && d2 < kTopTable; d2 += kChainThreads)
+        tab[d2] = gamma_s(T(h / a) * sqrt(T(d2))) * T(1.0 / a);
+    for (int e = tid; e < M; e += kChainThreads) {
+        const int x = e % dx, y = (e / dx) % dy, z = e / (dx * dy);
+        qs[e] = q[((int64_t)(z + kGridPad) * PY + (y + kGridPad)) * PX + (x + kGridPad)];
+    }
+    __syncthreads();
+    const T scale = T(ldexp(1.0, -k));
+    for (int node = tid; node < M; node += kChainThreads) {
+        const int x = node % dx, y = (node / dx) % dy, z = node / (dx * dy);
+        T acc = 0;
+        int e = 0;
+        for (int nz = 0; nz < dz; ++nz)
+            for (int ny = 0; ny < dy; ++ny) {
+                const int eyz = (nz - z) * (nz - z) + (ny - y) * (ny - y);
+                for (int nx = 0; nx < dx; ++nx, ++e) acc += top_weight(tab, eyz + (nx - x) * (nx - x), h, a) * qs[e];
+            }
+        acc *= scale;
+        const int64_t o = P.uoff[k] + node;
+        ucut[o] = acc;
+        ugrid[o] = acc;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kChainThreads) void k_prolong_chain(DevPlan p, const T *__restrict__ ucut,
+                                                                 T *__restrict__ ugrid)
+{
+    const SysPlan &P = p.sys[blockIdx.x];
+    for (int k = P.nlev - 2; k >= P.kc; --k) {
+        const int64_t n = (int64_t)P.gdim[k][0] * P.gdim[k][1] * P.gdim[k][2];
+        for (int64_t loc = threadIdx.x; loc < n; loc += kChainThreads) prolong_node<T>(P, ucut, ugrid, k, loc);
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -652,12 +955,13 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, co
     k.a2 = T(a * a);
     k.reach = T(a * (1.0 + 1e-5));
     k.inv_a2 = T(1.0 / (a * a));
+    // gamma(r/a)/a = (15/8 - 5/4 r^2/a^2 + 3/8 r^4/a^4) / a
     k.c0 = T(1.875 / a);
-    k.c1 = T(-1.25 / a);
-    k.c2 = T(0.375 / a);
-    // -(d/dr)(gamma(r/a)/a) / r = (5/2 - 3/2 rho^2) / a^3, entering with a minus sign
+    k.c1 = T(-1.25 / (a * a * a));
+    k.c2 = T(0.375 / (a * a * a * a * a));
+    // -(d/dr)(gamma(r/a)/a) / r = (5/2 - 3/2 r^2/a^2) / a^3
     k.d0 = T(2.5 / (a * a * a));
-    k.d1 = T(-1.5 / (a * a * a));
+    k.d1 = T(-1.5 / (a * a * a * a * a));
     if (w.saux)
         hipLaunchKernelGGL((k_pair<T, true>), dim3((unsigned)p.ngroups), dim3(kPairWaves * kWave), 0, s, p, w.sxyzq,
                            w.cell_start, w.shrt, k, (const vec4_t<T> *)w.saux, w.shlj);
@@ -669,10 +973,14 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, co
 
 template <typename T> hipError_t Launch<T>::anterp(hipStream_t s, const DevPlan &p, const Work<T> &w)
 {
-    if (p.nnodes[0] == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_anterp<T>, dim3(nblocks(p.nnodes[0], 256)), dim3(256), 0, s, p, w.sxyzq, w.cell_start,
-                       w.qgrid);
+    if (p.nant == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_anterp<T>, dim3((unsigned)p.nant), dim3(256), 0, s, p, w.sxyzq, w.cell_start, w.qgrid);
     return hipGetLastError();
+}
+
+int anterp_tiles(int dx, int dy, int dz)
+{
+    return ((dx + kAntX - 1) / kAntX) * ((dy + kAntY - 1) / kAntY) * ((dz + kAntZ - 1) / kAntZ);
 }
 
 template <typename T> hipError_t Launch<T>::restrict_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k)
@@ -685,7 +993,8 @@ template <typename T> hipError_t Launch<T>::restrict_level(hipStream_t s, const 
 template <typename T, int R>
 static hipError_t stencil_r(hipStream_t s, const DevPlan &p, const Work<T> &w, const StencilTables<T> &tb)
 {
-    hipLaunchKernelGGL((k_stencil<T, R>), dim3((unsigned)p.ntiles), dim3(256), 0, s, p, w.qgrid, w.ucut, tb.cols,
+    hipLaunchKernelGGL((k_stencil<T, R>), dim3((unsigned)p.ntiles), dim3(StencilGeom<T, R>::THREADS), 0, s, p,
+                       w.qgrid, w.ucut, tb.cols,
                        tb.w, tb.ncols);
     return hipGetLastError();
 }
@@ -710,6 +1019,9 @@ hipError_t Launch<T>::stencil(hipStream_t s, const DevPlan &p, const Work<T> &w,
     }
 }
 
+int top_blocks(int nodes) { return (nodes + kTopNodes - 1) / kTopNodes; }
+int top_stage_limit() { return kTopStage; }
+
 int stencil_tile_xy(int elem_bytes, int reach) { return (elem_bytes == 8 && reach >= 10) ? 4 : kStencilTile; }
 int stencil_tile_z(int elem_bytes, int reach) { return (elem_bytes == 8 && reach >= 10) ? 4 : kStencilTile; }
 
@@ -717,8 +1029,22 @@ template <typename T>
 hipError_t Launch<T>::top_level(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m)
 {
     if (p.ntop == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_top<T>, dim3(nblocks(p.ntop, 256)), dim3(256), 0, s, p, w.qgrid, w.ucut, w.ugrid, m.h, m.a,
+    hipLaunchKernelGGL(k_top<T>, dim3((unsigned)p.ntop), dim3(256), 0, s, p, w.qgrid, w.ucut, w.ugrid, m.h, m.a,
                        p.top_d2 + 1);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::restrict_chain(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m)
+{
+    hipLaunchKernelGGL(k_restrict_chain<T>, dim3((unsigned)p.nsys), dim3(kChainThreads), 0, s, p, w.qgrid, w.ucut,
+                       w.ugrid, m.h, m.a, p.top_d2 + 1);
+    return hipGetLastError();
+}
+
+template <typename T> hipError_t Launch<T>::prolong_chain(hipStream_t s, const DevPlan &p, const Work<T> &w)
+{
+    hipLaunchKernelGGL(k_prolong_chain<T>, dim3((unsigned)p.nsys), dim3(kChainThreads), 0, s, p, w.ucut, w.ugrid);
     return hipGetLastError();
 }
 
