@@ -23,6 +23,7 @@ from .loader import (  # noqa: F401
     grid_shape,
     msm,
     coulomb,
+    short_subset,
     threads,
     OracleModel,
     md_forces,

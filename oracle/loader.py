@@ -161,6 +161,28 @@ def msm(p: OracleParams, xyz, q, stages: bool = False):
     return float(e[0]), f, pot
 
 
+def short_subset(p: OracleParams, xyz, q, sel):
+    """u_short and the short-range force bracket of the atoms in ``sel``, each
+    by a direct loop over all atoms (spot checks of very large systems)."""
+    L = lib()
+    if not getattr(L, "_subset_ready", False):
+        L.orc_short_subset.restype = C.c_int
+        L.orc_short_subset.argtypes = [C.POINTER(_Params), C.c_int64, _dp, _dp, C.c_int64, C.POINTER(C.c_int64),
+                                       _dp, _dp]
+        L._subset_ready = True
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    sel = np.ascontiguousarray(sel, dtype=np.int64)
+    u = np.zeros(sel.shape[0])
+    f = np.zeros((sel.shape[0], 3))
+    cp = p.c()
+    rc = L.orc_short_subset(C.byref(cp), xyz.shape[0], _ptr(xyz), _ptr(q), sel.shape[0],
+                            sel.ctypes.data_as(C.POINTER(C.c_int64)), _ptr(u), _ptr(f))
+    if rc != 0:
+        raise RuntimeError(f"oracle short_subset failed with code {rc}")
+    return u, f
+
+
 def coulomb(xyz, q, ke: float = 138.935458):
     """Exact Coulomb energy, forces and potentials by the direct pair sum."""
     xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)

@@ -450,6 +450,37 @@ int orc_msm(const orc_params *p, int64_t n, const double *xyz, const double *q,
     return 0;
 }
 
+/* ---- Section 3, short-range part of selected atoms only, by a direct loop
+ *      over every other atom (for spot checks of very large systems). ---- */
+int orc_short_subset(const orc_params *p, int64_t n, const double *xyz, const double *q, int64_t nsel,
+                     const int64_t *sel, double *u, double *f)
+{
+    if (!p || n < 0 || nsel < 0 || (nsel > 0 && (!sel || !u || !f))) return -1;
+    double a = p->a;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t s = 0; s < nsel; s++) {
+        int64_t i = sel[s];
+        double ui = 0, fx = 0, fy = 0, fz = 0;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            double rx = xyz[3 * i] - xyz[3 * j], ry = xyz[3 * i + 1] - xyz[3 * j + 1], rz = xyz[3 * i + 2] - xyz[3 * j + 2];
+            double r2 = rx * rx + ry * ry + rz * rz;
+            if (!(r2 < a * a)) continue;
+            double r = sqrt(r2);
+            ui += orc_gstar(r, a) * q[j];
+            double sc = -orc_dgstar(r, a) / r * q[j];
+            fx += sc * rx;
+            fy += sc * ry;
+            fz += sc * rz;
+        }
+        u[s] = ui;
+        f[3 * s] = fx;
+        f[3 * s + 1] = fy;
+        f[3 * s + 2] = fz;
+    }
+    return 0;
+}
+
 /* ---- Section 2, Coulomb's law, summed directly over every pair i < j. ---- */
 int orc_coulomb(int64_t n, const double *xyz, const double *q, double ke,
                 double *energy, double *forces, double *pot)

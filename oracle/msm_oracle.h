@@ -54,6 +54,11 @@ int orc_grid_shape(const orc_params *p, int level, int org[3], int dim[3]);
 int orc_msm(const orc_params *p, int64_t n, const double *xyz, const double *q,
             double *energy, double *forces, double *pot, orc_stages *st);
 
+/* u_short and the short-range force bracket (as in orc_stages) of the atoms
+ * listed in sel, each by a direct loop over all atoms. */
+int orc_short_subset(const orc_params *p, int64_t n, const double *xyz, const double *q, int64_t nsel,
+                     const int64_t *sel, double *u, double *f);
+
 int orc_coulomb(int64_t n, const double *xyz, const double *q, double ke,
                 double *energy, double *forces, double *pot);
 

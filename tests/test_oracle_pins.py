@@ -354,3 +354,15 @@ def test_oracle_rejects_bad_inputs(orc):
         orc.msm(p, np.array([[0.5, 0.5, 1.2]]), np.array([1.0]))
     with pytest.raises(RuntimeError, match="-3"):
         orc.msm(p, np.array([[0.5, np.nan, 0.5]]), np.array([1.0]))
+
+
+def test_short_subset_matches_full_short_range(orc):
+    # the spot-check routine (direct loop over all atoms) and the cell-list
+    # short range of the full evaluation are two loop structures of one sum
+    w = water_box(400, (11, 11, 11), (3.4, 3.4, 3.4), seed=8)
+    p = orc.OracleParams.of(w, ke=1.0)
+    _, _, _, st = orc.msm(p, w.xyz, w.q, stages=True)
+    sel = np.array([0, 1, 2, 500, 1199])
+    u, f = orc.short_subset(p, w.xyz, w.q, sel)
+    np.testing.assert_allclose(u, st["u_short"][sel], rtol=1e-12, atol=1e-12)
+    np.testing.assert_allclose(f, st["f_short"][sel], rtol=1e-12, atol=1e-10)
