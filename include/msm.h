@@ -104,6 +104,35 @@ int msm_energy_forces(msm_ctx *ctx, int nsys, const int64_t *offsets_host,
                       const double *domains_host, const void *xyzq_dev,
                       double *energy_dev, void *forces_dev, void *potentials_dev);
 
+/* Launch configuration of the two heaviest kernels. Every configuration is
+ * deterministic, but they add the same terms in different orders, so results
+ * of different configurations agree to rounding, not bitwise (contexts that
+ * must agree bitwise, e.g. a parareal pair and its serial reference, should
+ * share one configuration). Defaults: 8 waves, 1024 threads. */
+typedef struct {
+    int pair_waves;        /* waves sharing one 64-atom group of the short-range sum: 4, 8 or 16 */
+    int stencil_threads;   /* threads per lattice-cutoff tile: 256 or 1024 */
+} msm_tuning;
+
+int msm_get_tuning(const msm_ctx *ctx, msm_tuning *out);
+int msm_set_tuning(msm_ctx *ctx, const msm_tuning *tuning);
+
+/* Autotuner: time every pair_waves candidate on the short-range stage and
+ * every stencil_threads candidate on the lattice-cutoff stage, reps
+ * evaluations each, on the caller's own batch (arguments as for
+ * msm_energy_forces; no outputs are written), keep the fastest of each and
+ * report them in *chosen (may be NULL). Synchronous. */
+int msm_autotune(msm_ctx *ctx, int nsys, const int64_t *offsets_host, const double *domains_host,
+                 const void *xyzq_dev, int reps, msm_tuning *chosen);
+
+/* Replay captured HIP graphs for evaluations (enable != 0) or launch every
+ * kernel eagerly (0, the default). With graphs on, the first evaluation of a
+ * batch shape and set of buffers is captured and later ones with the same
+ * plan and pointers replay it (a new shape or pointer captures again; up to
+ * four captures are kept per context). Results are identical either way;
+ * stage timing always runs eagerly. */
+int msm_set_graphs(msm_ctx *ctx, int enable);
+
 /* Synchronise the stream, return and clear the device status word:
  * MSM_OK, MSM_ERR_DOMAIN or MSM_ERR_NONFINITE (the first seen), or MSM_ERR_HIP. */
 int msm_get_status(msm_ctx *ctx);

@@ -38,6 +38,10 @@ class _PararealReport(C.Structure):
                 ("seconds", C.c_double)]
 
 
+class _Tuning(C.Structure):
+    _fields_ = [("pair_waves", C.c_int), ("stencil_threads", C.c_int)]
+
+
 class _Params(C.Structure):
     _fields_ = [("a", C.c_double), ("h", C.c_double), ("levels", C.c_int), ("precision", C.c_int),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("coulomb_k", C.c_double),
@@ -79,6 +83,15 @@ def lib():
         L.msm_enable_stage_timing.restype = C.c_int
         L.msm_stage_timing.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.c_int]
         L.msm_stage_timing.restype = C.c_int
+        L.msm_get_tuning.argtypes = [vp, C.POINTER(_Tuning)]
+        L.msm_get_tuning.restype = C.c_int
+        L.msm_set_tuning.argtypes = [vp, C.POINTER(_Tuning)]
+        L.msm_set_tuning.restype = C.c_int
+        L.msm_autotune.argtypes = [vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double), vp, C.c_int,
+                                   C.POINTER(_Tuning)]
+        L.msm_autotune.restype = C.c_int
+        L.msm_set_graphs.argtypes = [vp, C.c_int]
+        L.msm_set_graphs.restype = C.c_int
         L.msm_md_bind.argtypes = [vp, C.POINTER(_Model)]
         L.msm_md_bind.restype = C.c_int
         L.msm_vv_run.argtypes = [vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double), vp, vp, C.c_int,
@@ -164,6 +177,33 @@ class MsmContext:
         code = self.status()
         if code != 0:
             raise MsmError(code, "device status")
+
+    def tuning(self):
+        t = _Tuning()
+        _check(lib().msm_get_tuning(self._h, C.byref(t)), "msm_get_tuning")
+        return {"pair_waves": t.pair_waves, "stencil_threads": t.stencil_threads}
+
+    def set_tuning(self, pair_waves, stencil_threads):
+        t = _Tuning(int(pair_waves), int(stencil_threads))
+        _check(lib().msm_set_tuning(self._h, C.byref(t)), "msm_set_tuning")
+
+    def autotune(self, xyzq, offsets=None, domains=None, reps=5):
+        """Pick the fastest launch configuration on this batch (msm_autotune)."""
+        n = xyzq.shape[0]
+        offs = np.ascontiguousarray(np.asarray([0, n] if offsets is None else offsets, dtype=np.int64))
+        nsys = len(offs) - 1
+        dom_p = None
+        if domains is not None:
+            dom = np.ascontiguousarray(np.asarray(domains, dtype=np.float64).reshape(nsys, 6))
+            dom_p = dom.ctypes.data_as(C.POINTER(C.c_double))
+        t = _Tuning()
+        _check(lib().msm_autotune(self._h, nsys, offs.ctypes.data_as(C.POINTER(C.c_int64)), dom_p,
+                                  C.c_void_p(xyzq.data_ptr()), int(reps), C.byref(t)), "msm_autotune")
+        return {"pair_waves": t.pair_waves, "stencil_threads": t.stencil_threads}
+
+    def set_graphs(self, enable=True):
+        """Replay captured HIP graphs for repeated evaluations (msm_set_graphs)."""
+        _check(lib().msm_set_graphs(self._h, 1 if enable else 0), "msm_set_graphs")
 
     def enable_stage_timing(self, enable=True):
         _check(lib().msm_enable_stage_timing(self._h, 1 if enable else 0), "msm_enable_stage_timing")

@@ -293,6 +293,7 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     if (domains) c->last_domains.assign(domains, domains + nsys * 6);
     else c->last_domains.clear();
     c->plan_valid = true;
+    c->plan_version++;
     return MSM_OK;
 }
 
@@ -326,7 +327,7 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     if (p.any_chain && (e = L::restrict_chain(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_CUTOFF);
     {
-        StencilTables<T> tb{c->wcols, (const T *)c->weights, c->ncols, c->mc.reach};
+        StencilTables<T> tb{c->wcols, (const T *)c->weights, c->ncols, c->mc.reach, c->mc.stencil_threads};
         if ((e = L::stencil(s, p, w, tb)) != hipSuccess) return MSM_ERR_HIP;
     }
     mark(MSM_STAGE_TOP);
@@ -353,10 +354,68 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
 
 }  // namespace
 
-int msmx::evaluate_any(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *pots)
+static int evaluate_eager(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *pots)
 {
     if (c->prm.precision == MSM_FP32) return evaluate<float>(c, xyzq, energy, forces, pots);
     return evaluate<double>(c, xyzq, energy, forces, pots);
+}
+
+static void drop_graph(msm_ctx::GraphEntry &g)
+{
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    g = msm_ctx::GraphEntry{};
+}
+
+// With graphs enabled, an evaluation is captured once per batch plan and set
+// of buffers (on an internal stream) and replayed on the context stream; the
+// launch sequence is the same as the eager one, so results are identical.
+int msmx::evaluate_any(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *pots)
+{
+    if (!c->use_graphs || c->timing) return evaluate_eager(c, xyzq, energy, forces, pots);
+    msm_ctx::GraphEntry *hit = nullptr, *victim = &c->graphs[0];
+    for (auto &g : c->graphs) {
+        if (g.valid && g.plan_version == c->plan_version && g.xyzq == xyzq && g.energy == energy &&
+            g.forces == forces && g.pots == pots)
+            hit = &g;
+        if (!g.valid || g.last_use < victim->last_use) victim = &g;
+    }
+    if (!hit) {
+        if (!c->capture_stream && hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess)
+            return MSM_ERR_HIP;
+        drop_graph(*victim);
+        hipStream_t saved = c->stream;
+        c->stream = c->capture_stream;
+        if (hipStreamBeginCapture(c->capture_stream, hipStreamCaptureModeRelaxed) != hipSuccess) {
+            c->stream = saved;
+            return MSM_ERR_HIP;
+        }
+        int rc = evaluate_eager(c, xyzq, energy, forces, pots);
+        hipGraph_t graph = nullptr;
+        hipError_t e = hipStreamEndCapture(c->capture_stream, &graph);
+        c->stream = saved;
+        if (rc) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc;
+        }
+        if (e != hipSuccess) return MSM_ERR_HIP;
+        hipGraphExec_t exec = nullptr;
+        if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            return MSM_ERR_HIP;
+        }
+        victim->valid = true;
+        victim->plan_version = c->plan_version;
+        victim->xyzq = xyzq;
+        victim->energy = energy;
+        victim->forces = forces;
+        victim->pots = pots;
+        victim->graph = graph;
+        victim->exec = exec;
+        hit = victim;
+    }
+    hit->last_use = ++c->graph_clock;
+    return hipGraphLaunch(hit->exec, c->stream) == hipSuccess ? MSM_OK : MSM_ERR_HIP;
 }
 
 namespace {
@@ -444,6 +503,8 @@ int msm_setup(const msm_params *prm, void *stream, msm_ctx **out)
     c->mc.h = prm->h;
     c->mc.ke = prm->coulomb_k;
     c->mc.reach = reach;
+    c->mc.pair_waves = 8;
+    c->mc.stencil_threads = 1024;
     c->d2max = (int)std::ceil(ratio * ratio) - 1;      // largest integer below (2a/h)^2
     int rc = geometry(*prm, prm->lo, prm->hi, c->ctx_geom);
     if (rc) {
@@ -495,6 +556,8 @@ void msm_destroy(msm_ctx *c)
     (void)hipStreamSynchronize(c->stream);
     for (auto &e : c->ev)
         if (e) (void)hipEventDestroy(e);
+    for (auto &g : c->graphs) drop_graph(g);
+    if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->wbuf) (void)hipFree(c->wbuf);
     if (c->weights) (void)hipFree(c->weights);
     if (c->wcols) (void)hipFree(c->wcols);
@@ -520,8 +583,94 @@ int msm_energy_forces(msm_ctx *c, int nsys, const int64_t *offsets, const double
     if (offsets[nsys] > 0 && !xyzq) return MSM_ERR_ARG;
     int rc = build_plan(c, nsys, offsets, domains);
     if (rc) return rc;
-    if (c->prm.precision == MSM_FP32) return evaluate<float>(c, xyzq, energy, forces, pots);
-    return evaluate<double>(c, xyzq, energy, forces, pots);
+    return evaluate_any(c, xyzq, energy, forces, pots);
+}
+
+int msm_get_tuning(const msm_ctx *c, msm_tuning *t)
+{
+    if (!c || !t) return MSM_ERR_ARG;
+    t->pair_waves = c->mc.pair_waves;
+    t->stencil_threads = c->mc.stencil_threads;
+    return MSM_OK;
+}
+
+int msm_set_tuning(msm_ctx *c, const msm_tuning *t)
+{
+    if (!c || !t) return MSM_ERR_ARG;
+    if (t->pair_waves != 4 && t->pair_waves != 8 && t->pair_waves != 16) return MSM_ERR_ARG;
+    if (t->stencil_threads != 256 && t->stencil_threads != 1024) return MSM_ERR_ARG;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
+    for (auto &g : c->graphs) drop_graph(g);     // captured launches use the old kernels
+    c->mc.pair_waves = t->pair_waves;
+    c->mc.stencil_threads = t->stencil_threads;
+    return MSM_OK;
+}
+
+int msm_autotune(msm_ctx *c, int nsys, const int64_t *offsets, const double *domains, const void *xyzq, int reps,
+                 msm_tuning *chosen)
+{
+    if (!c || nsys < 1 || !offsets || reps < 1) return MSM_ERR_ARG;
+    if (nsys > c->prm.max_systems) return MSM_ERR_CAPACITY;
+    int rc = build_plan(c, nsys, offsets, domains);
+    if (rc) return rc;
+    const bool was_timing = c->timing;
+    const msm_tuning start{c->mc.pair_waves, c->mc.stencil_threads};
+    if ((rc = msm_enable_stage_timing(c, 1))) return rc;
+    // time one stage for one candidate: a warm-up evaluation, then reps
+    auto stage_time = [&](int stage, double *ms) {
+        int r = evaluate_any(c, xyzq, nullptr, nullptr, nullptr);
+        if (r) return r;
+        msm_stage_timing(c, nullptr, nullptr, 1);
+        for (int i = 0; i < reps && !r; i++) r = evaluate_any(c, xyzq, nullptr, nullptr, nullptr);
+        double all[MSM_NSTAGES];
+        int64_t n = 0;
+        msm_stage_timing(c, all, &n, 1);
+        *ms = all[stage] / (n ? n : 1);
+        return r;
+    };
+    msm_tuning best = start;
+    double best_ms = 1e300;
+    for (int pw : {4, 8, 16}) {
+        c->mc.pair_waves = pw;
+        double ms;
+        if ((rc = stage_time(MSM_STAGE_SHORT, &ms))) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best.pair_waves = pw;
+        }
+    }
+    c->mc.pair_waves = best.pair_waves;
+    best_ms = 1e300;
+    for (int st : {256, 1024}) {
+        if (rc) break;
+        c->mc.stencil_threads = st;
+        double ms;
+        if ((rc = stage_time(MSM_STAGE_CUTOFF, &ms))) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best.stencil_threads = st;
+        }
+    }
+    c->timing = was_timing;
+    if (rc) {
+        c->mc.pair_waves = start.pair_waves;
+        c->mc.stencil_threads = start.stencil_threads;
+        return rc;
+    }
+    int r2 = msm_set_tuning(c, &best);
+    if (r2) return r2;
+    if (chosen) *chosen = best;
+    return MSM_OK;
+}
+
+int msm_set_graphs(msm_ctx *c, int enable)
+{
+    if (!c) return MSM_ERR_ARG;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
+    c->use_graphs = enable != 0;
+    if (!c->use_graphs)
+        for (auto &g : c->graphs) drop_graph(g);
+    return MSM_OK;
 }
 
 int msm_get_status(msm_ctx *c)

@@ -51,6 +51,21 @@ struct msm_ctx {
     hipEvent_t ev[MSM_NSTAGES + 1] = {};
     double stage_ms[MSM_NSTAGES] = {};
     int64_t timed_evals = 0;
+    // captured evaluations (msm_set_graphs)
+    bool use_graphs = false;
+    hipStream_t capture_stream = nullptr;
+    uint64_t plan_version = 0;
+    struct GraphEntry {
+        bool valid = false;
+        uint64_t plan_version = 0;
+        const void *xyzq = nullptr;
+        double *energy = nullptr;
+        void *forces = nullptr, *pots = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        uint64_t last_use = 0;
+    } graphs[4];
+    uint64_t graph_clock = 0;
     // dynamics (msm_md_bind)
     bool md_bound = false;
     bool rigid = false;

@@ -59,6 +59,7 @@ template <typename T> struct StencilTables {
     const T *w;
     int ncols;
     int reach;
+    int threads;         // threads per tile: 256 or 1024
 };
 
 int stencil_tile_xy(int elem_bytes, int reach);
@@ -70,6 +71,8 @@ int stencil_tile_z(int elem_bytes, int reach);
 struct MethodConst {
     double a, h, ke;
     int reach;                 // stencil reach R: largest integer with R < 2a/h
+    int pair_waves;            // waves per 64-atom group in the pair kernel: 4, 8 or 16
+    int stencil_threads;       // threads per stencil tile: 256 or 1024
 };
 
 int scan_cells(hipStream_t s, int *counts_to_start, int64_t n, int *block_sums);

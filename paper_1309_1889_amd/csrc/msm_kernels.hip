@@ -77,10 +77,6 @@ template <typename T> struct PairK {
     T d0, d1;        // -(d/dr)(gamma(r/a)/a) / r = d0 + d1 r^2
 };
 
-#ifndef MSMX_PAIR_WAVES
-#define MSMX_PAIR_WAVES 8
-#endif
-constexpr int kPairWaves = MSMX_PAIR_WAVES;   // waves sharing one group's candidate rows
 #ifndef MSMX_PAIR_UNROLL
 #define MSMX_PAIR_UNROLL 8
 #endif
@@ -154,7 +150,7 @@ __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const
 // coalesced load (the next chunk is fetched while the current one is used),
 // and every lane reads each staged atom by broadcast and evaluates its own
 // pair. The waves' partial sums are added in a fixed order at the end.
-template <typename T, bool MD>
+template <typename T, bool MD, int kPairWaves>
 __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                               const int *__restrict__ cstart,
                                                               vec4_t<T> *__restrict__ out, PairK<T> k,
@@ -520,23 +516,23 @@ __global__ __launch_bounds__(256) void k_restrict(DevPlan p, T *__restrict__ qgr
 // the quarter-disc of columns carries the whole sphere. The shares are summed
 // in a fixed order at the end.
 // ---------------------------------------------------------------------------
-template <typename T, int R> struct StencilGeom {
+template <typename T, int R, int NT> struct StencilGeom {
     static constexpr int TZ = (sizeof(T) == 8 && R >= 10) ? 4 : kStencilTile;
     static constexpr int TXY = (sizeof(T) == 8 && R >= 10) ? 4 : kStencilTile;
     static constexpr int EX = TXY + 2 * R;
     static constexpr int EZ = TZ + 2 * R;
-    static constexpr int THREADS = 1024;
+    static constexpr int THREADS = NT;
     static constexpr int COLS = TXY * TXY;            // output columns per tile
     static constexpr int SHARES = THREADS / COLS;     // threads per output column
     static constexpr int IN = EZ * EX * EX;           // staged charges
     static constexpr int LDS = IN > THREADS * TZ ? IN : THREADS * TZ;   // also holds the share sums
 };
 
-template <typename T, int R>
-__global__ __launch_bounds__(1024) void k_stencil(DevPlan p, const T *__restrict__ qgrid, T *__restrict__ ucut,
+template <typename T, int R, int NT>
+__global__ __launch_bounds__(NT) void k_stencil(DevPlan p, const T *__restrict__ qgrid, T *__restrict__ ucut,
                                                  const int2 *__restrict__ qcols, const T *__restrict__ qw, int ncols)
 {
-    using G = StencilGeom<T, R>;
+    using G = StencilGeom<T, R, NT>;
     constexpr int D = 2 * R + 1;
     constexpr int L = G::TZ + 2 * R;
     __shared__ T tile[G::LDS];
@@ -946,6 +942,17 @@ __global__ void k_stage_grid(const SysPlan *sys, int s, int k, const T *__restri
 
 }  // namespace
 
+template <typename T, int NW>
+static void pair_launch(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k)
+{
+    if (w.saux)
+        hipLaunchKernelGGL((k_pair<T, true, NW>), dim3((unsigned)p.ngroups), dim3(NW * kWave), 0, s, p, w.sxyzq,
+                           w.cell_start, w.shrt, k, (const vec4_t<T> *)w.saux, w.shlj);
+    else
+        hipLaunchKernelGGL((k_pair<T, false, NW>), dim3((unsigned)p.ngroups), dim3(NW * kWave), 0, s, p, w.sxyzq,
+                           w.cell_start, w.shrt, k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+}
+
 template <typename T>
 hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m)
 {
@@ -962,12 +969,12 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, co
     // -(d/dr)(gamma(r/a)/a) / r = (5/2 - 3/2 r^2/a^2) / a^3
     k.d0 = T(2.5 / (a * a * a));
     k.d1 = T(-1.5 / (a * a * a * a * a));
-    if (w.saux)
-        hipLaunchKernelGGL((k_pair<T, true>), dim3((unsigned)p.ngroups), dim3(kPairWaves * kWave), 0, s, p, w.sxyzq,
-                           w.cell_start, w.shrt, k, (const vec4_t<T> *)w.saux, w.shlj);
-    else
-        hipLaunchKernelGGL((k_pair<T, false>), dim3((unsigned)p.ngroups), dim3(kPairWaves * kWave), 0, s, p, w.sxyzq,
-                           w.cell_start, w.shrt, k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+    switch (m.pair_waves) {
+    case 4: pair_launch<T, 4>(s, p, w, k); break;
+    case 8: pair_launch<T, 8>(s, p, w, k); break;
+    case 16: pair_launch<T, 16>(s, p, w, k); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
@@ -993,7 +1000,12 @@ template <typename T> hipError_t Launch<T>::restrict_level(hipStream_t s, const 
 template <typename T, int R>
 static hipError_t stencil_r(hipStream_t s, const DevPlan &p, const Work<T> &w, const StencilTables<T> &tb)
 {
-    hipLaunchKernelGGL((k_stencil<T, R>), dim3((unsigned)p.ntiles), dim3(StencilGeom<T, R>::THREADS), 0, s, p,
+    if (tb.threads == 256) {
+        hipLaunchKernelGGL((k_stencil<T, R, 256>), dim3((unsigned)p.ntiles), dim3(256), 0, s, p, w.qgrid, w.ucut,
+                           tb.cols, tb.w, tb.ncols);
+        return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_stencil<T, R, 1024>), dim3((unsigned)p.ntiles), dim3(1024), 0, s, p,
                        w.qgrid, w.ucut, tb.cols,
                        tb.w, tb.ncols);
     return hipGetLastError();

@@ -1,0 +1,95 @@
+"""Captured HIP graphs: replays must reproduce eager evaluation bitwise,
+with the inputs changed in place between replays, interleaved with eager
+work and synchronisations, and after the batch shape changes."""
+import math
+
+import numpy as np
+import pytest
+
+from workloads import rigid_water_velocities, water_box, water_model_arrays
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def test_graph_replays_match_eager_bitwise():
+    import paper_1309_1889_amd as msmx
+    w = water_box(2000, (19, 19, 19), (5.8, 5.8, 5.8), seed=41)
+    eager = msmx.MsmContext(w.a, w.h, w.lo, w.hi, precision="fp32", max_atoms=2 * w.n, max_systems=2)
+    graph = msmx.MsmContext(w.a, w.h, w.lo, w.hi, precision="fp32", max_atoms=2 * w.n, max_systems=2)
+    graph.set_graphs(True)
+    x = torch.tensor(w.xyzq(np.float32), device="cuda")
+    rng = np.random.default_rng(3)
+    outs = [torch.empty(1, dtype=torch.float64, device="cuda"), torch.empty((w.n, 3), device="cuda"),
+            torch.empty(w.n, device="cuda")]
+    for rep in range(6):
+        # change the input in place: same pointers, new data
+        x[:, :3] += torch.tensor(rng.uniform(-0.003, 0.003, (w.n, 3)), dtype=torch.float32, device="cuda")
+        graph.energy_forces(x, energy=outs[0], forces=outs[1], potentials=outs[2])
+        e0, f0, p0 = eager.energy_forces(x)
+        torch.cuda.synchronize()
+        assert graph.status() == 0
+        assert torch.equal(outs[0], e0) and torch.equal(outs[1], f0) and torch.equal(outs[2], p0), rep
+    # a new batch shape is captured again
+    x2 = torch.cat([x, x]).contiguous()
+    offs = [0, w.n, 2 * w.n]
+    for rep in range(3):
+        eg, fg, pg = graph.energy_forces(x2, offs)
+        ee, fe, pe = eager.energy_forces(x2, offs)
+        torch.cuda.synchronize()
+        assert torch.equal(eg, ee) and torch.equal(fg, fe) and torch.equal(pg, pe)
+
+
+def test_graph_velocity_verlet_matches_eager():
+    import paper_1309_1889_amd as msmx
+    n_mol = 125
+    per = int(math.ceil(n_mol ** (1 / 3)))
+    w = water_box(n_mol, (per,) * 3, (1.6,) * 3, seed=5, margin=0.6)
+    mass, molid, lj, tri = water_model_arrays(w.n)
+    v = rigid_water_velocities(w.xyz, 300.0, seed=6)
+    ctxs = []
+    for graphs in (False, True):
+        c = msmx.MsmContext(0.9, 0.25, w.lo, w.hi, precision="fp64", max_atoms=w.n)
+        c.bind_model(w.n, torch.tensor(molid, dtype=torch.int32, device="cuda"),
+                     torch.tensor(lj, device="cuda"), rigid=True, tri=tri)
+        c.set_graphs(graphs)
+        ctxs.append(c)
+    states = []
+    for c in ctxs:
+        x = torch.tensor(np.concatenate([w.xyz, w.q[:, None]], 1), device="cuda").contiguous()
+        vv = torch.tensor(np.concatenate([v, 1.0 / mass[:, None]], 1), device="cuda").contiguous()
+        ep, ek = c.vv_run(x, vv, 8, 0.002)
+        ep2, ek2 = c.vv_run(x, vv, 8, 0.002)
+        torch.cuda.synchronize()
+        states.append((x, vv, ep2, ek2))
+    for a, b in zip(states[0], states[1]):
+        assert torch.equal(a, b)
+
+
+def test_autotune_and_tunings_agree():
+    import paper_1309_1889_amd as msmx
+    w = water_box(3000, (21, 21, 21), (6.6, 6.6, 6.6), seed=8)
+    ctx = msmx.MsmContext(w.a, w.h, w.lo, w.hi, precision="fp32", max_atoms=w.n)
+    x = torch.tensor(w.xyzq(np.float32), device="cuda")
+    ref = [t.clone() for t in ctx.energy_forces(x)]
+    chosen = ctx.autotune(x, reps=3)
+    assert chosen["pair_waves"] in (4, 8, 16) and chosen["stencil_threads"] in (256, 1024)
+    assert ctx.tuning() == chosen
+    for pw in (4, 8, 16):
+        for st in (256, 1024):
+            ctx.set_tuning(pw, st)
+            e, f, p = ctx.energy_forces(x)
+            e2, f2, p2 = ctx.energy_forces(x)
+            torch.cuda.synchronize()
+            assert torch.equal(f, f2) and torch.equal(e, e2)       # each configuration is deterministic
+            rel = float(((f - ref[1]) ** 2).sum().sqrt() / (ref[1] ** 2).sum().sqrt())
+            assert rel < 1e-5, (pw, st, rel)
+            assert e.item() == pytest.approx(ref[0].item(), rel=1e-6)
+    with pytest.raises(msmx.MsmError):
+        ctx.set_tuning(5, 256)
