@@ -53,6 +53,9 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the 32-slice and uneven batches")
     ap.add_argument("--no-parareal", action="store_true")
     ap.add_argument("--slices", type=int, default=32)
+    ap.add_argument("--no-graphs", action="store_true", help="time eager launches only")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
+    ap.add_argument("--no-large", action="store_true", help="skip the 12.7M-atom slab")
     ap.add_argument("--only-fp32", action="store_true",
                     help="time only the single-system FP32 path (for profiler runs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
@@ -61,6 +64,7 @@ def parse():
     args = ap.parse_args()
     if args.only_fp32:
         args.no_fp64 = args.no_accuracy = args.no_cpu_baseline = args.no_batched = args.no_parareal = True
+        args.no_large = True
     return args
 
 
@@ -223,14 +227,14 @@ def bench_parareal(torch, msmx, slices, n_atoms=99999):
     w = water_box(n_mol, sites, box, seed=4, margin=3.0)
     mass, molid, lj, tri = water_model_arrays(w.n)
     v = rigid_water_velocities(w.xyz, 300.0, seed=104)
-    xyz = w.xyz.astype(np.float32).astype(np.float64)
-    v = v.astype(np.float32).astype(np.float64)
+    xyz = w.xyz
     mol_t = torch.tensor(molid, dtype=torch.int32, device=dev)
     lj_t = torch.tensor(lj, dtype=torch.float64, device=dev)
 
     def ctx(a, h, ma, ms):
         c = msmx.MsmContext(a, h, w.lo, w.hi, precision="fp32", max_atoms=ma, max_systems=ms)
         c.bind_model(w.n, mol_t, lj_t, rigid=True, tri=tri)
+        c.set_graphs(True)
         return c
 
     fine = ctx(1.2, 0.25, slices * w.n, slices)
@@ -240,8 +244,8 @@ def bench_parareal(torch, msmx, slices, n_atoms=99999):
     s0 = torch.tensor(np.concatenate([xyz, v], 1), device=dev).contiguous()
     # serial fine on the same GPU: 10 steps per slice, each slice restarting from the stored state
     serial = ctx(1.2, 0.25, w.n, 1)
-    x = torch.cat([s0[:, :3], q[:, None]], 1).float().contiguous()
-    vv = torch.cat([s0[:, 3:], invm[:, None]], 1).float().contiguous()
+    x = torch.cat([s0[:, :3], q[:, None]], 1).contiguous()
+    vv = torch.cat([s0[:, 3:], invm[:, None]], 1).contiguous()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(slices):
@@ -259,12 +263,57 @@ def bench_parareal(torch, msmx, slices, n_atoms=99999):
             rec.update({"status": "converged" if rc == 0 else "not converged", "iterations": rep["iterations"],
                         "seconds": rep["seconds"], "residual_nm": [float("%.3g" % r) for r in rep["residual"]],
                         "speedup_vs_serial_fine": serial_s / rep["seconds"]})
-            last = lam[slices, :, :3].float()
+            last = lam[slices, :, :3]
             rec["final_max_dev_vs_serial_nm"] = float((last - x[:, :3]).abs().max().item())
         except msmx.MsmError as e:
             rec.update({"status": f"failed: {e}"})
         out[name] = rec
     return out
+
+
+def bench_large(torch, msmx, steps=100, dt=0.002):
+    """The paper's 30 x 65 x 65 nm box with 12,675,000 water-like atoms: one
+    FP32 evaluation timed, then `steps` velocity-Verlet steps of the rigid
+    water model with the total-energy drift."""
+    from workloads import named, rigid_water_velocities, water_model_arrays
+    dev = torch.device("cuda", 0)
+    w64 = named("water_12675000", margin=1.0)
+    w = w64.as_dtype(np.float32)
+    n = w.n
+    ctx = msmx.MsmContext(w.a, w.h, w.lo, w.hi, precision="fp32", max_atoms=n)
+    x = torch.tensor(w.xyzq(np.float32), device=dev)
+    out = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float32, device=dev),
+           torch.empty(n, dtype=torch.float32, device=dev))
+    ctx.set_graphs(True)
+    ms = timed_steps(torch, ctx, x, out, 10, 2)
+    ctx.check()
+    del ctx, out
+    mass, molid, lj, tri = water_model_arrays(n)
+    v = rigid_water_velocities(w64.xyz, 300.0, seed=105)
+    md = msmx.MsmContext(w.a, w.h, w.lo, w.hi, precision="fp32", max_atoms=n)
+    md.bind_model(n, torch.tensor(molid, dtype=torch.int32, device=dev), torch.tensor(lj, device=dev), rigid=True,
+                  tri=tri)
+    md.set_graphs(True)
+    # FP64 integrator state, FP32 force evaluation
+    del x
+    x = torch.tensor(np.concatenate([w64.xyz, w64.q[:, None]], 1), device=dev).contiguous()
+    vel = torch.tensor(np.concatenate([v, 1.0 / mass[:, None]], 1), device=dev).contiguous()
+    del w64, v
+    ep0, ek0 = md.vv_run(x, vel, 0, dt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ep1, ek1 = md.vv_run(x, vel, steps, dt)
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    md.check()
+    e0, e1 = ep0.item() + ek0.item(), ep1.item() + ek1.item()
+    return {"workload": f"{n} atoms, 30x65x65 nm rigid water, a 1.2 nm, h 0.25 nm, {len(md.grid_shape())} grids, FP32 forces, FP64 state",
+            "eval_ms": ms, "eval_atom_steps_per_s": n / (ms * 1e-3),
+            "vv_steps": steps, "dt_ps": dt, "vv_seconds": secs, "vv_atom_steps_per_s": n * steps / secs,
+            "energy_start_kj_mol": e0, "energy_end_kj_mol": e1,
+            "drift_kj_mol_per_ps": (e1 - e0) / (steps * dt),
+            "drift_relative_to_kinetic": (e1 - e0) / ek0.item(),
+            "kinetic_start": ek0.item(), "kinetic_end": ek1.item()}
 
 
 def main():
@@ -289,8 +338,13 @@ def main():
     x32 = torch.tensor(w32.xyzq(np.float32), device=dev)
     out32 = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float32, device=dev),
              torch.empty(n, dtype=torch.float32, device=dev))
+    eager_default_ms = timed_steps(torch, ctx, x32, out32, args.steps, args.warmup)
+    tuning32 = ctx.autotune(x32, reps=5) if not args.no_autotune else ctx.tuning()
+    ctx.set_graphs(not args.no_graphs)
     ms32 = timed_steps(torch, ctx, x32, out32, args.steps, args.warmup)
     ctx.check()
+    ctx.set_graphs(False)
+    eager_tuned_ms = timed_steps(torch, ctx, x32, out32, args.steps, args.warmup)
     stages32 = stage_profile(torch, ctx, x32, out32, args.steps)
     value = n / (ms32 * 1e-3)
     if args.copy_calibration_mib > 0:
@@ -309,10 +363,13 @@ def main():
         out64 = (torch.empty(1, dtype=torch.float64, device=dev),
                  torch.empty((n, 3), dtype=torch.float64, device=dev),
                  torch.empty(n, dtype=torch.float64, device=dev))
+        tuning64 = ctx64.autotune(x64, reps=5) if not args.no_autotune else ctx64.tuning()
+        ctx64.set_graphs(not args.no_graphs)
         ms64 = timed_steps(torch, ctx64, x64, out64, max(args.steps // 2, 1), args.warmup)
         ctx64.check()
+        ctx64.set_graphs(False)
         stages64 = stage_profile(torch, ctx64, x64, out64, max(args.steps // 2, 1))
-        fp64 = {"value": n / (ms64 * 1e-3), "ms_per_step": ms64,
+        fp64 = {"value": n / (ms64 * 1e-3), "ms_per_step": ms64, "tuning": tuning64,
                 "stage_ms": {k: round(v, 5) for k, v in stages64.items()}}
 
     # ---- roofline of the dominant kernel (timed live, HIP events on the context stream) ----
@@ -371,11 +428,13 @@ def main():
                 accuracy["fp64_force_rel_rms"] = rel_rms(out64[1].cpu().numpy(), fo)
                 accuracy["fp64_energy_rel"] = abs(out64[0].item() - eo) / abs(eo)
 
-    batched = uneven = par = None
+    batched = uneven = par = large = None
     if not args.no_batched:
         batched, uneven = bench_batched(torch, msmx, w32, args.steps, args.warmup, args.slices, value)
     if not args.no_parareal:
         par = bench_parareal(torch, msmx, args.slices)
+    if not args.no_large:
+        large = bench_large(torch, msmx)
 
     result.update({
         "value": value,
@@ -400,6 +459,9 @@ def main():
         "speedup_fp32_batched_vs_fp64_plain": (batched["value"] / fp64["value"]) if (batched and fp64) else None,
         "uneven_batch": uneven,
         "parareal": par,
+        "large_box": large,
+        "launch": {"graphs": not args.no_graphs, "tuning": tuning32,
+                   "eager_default_ms_per_step": eager_default_ms, "eager_tuned_ms_per_step": eager_tuned_ms},
         "accuracy": accuracy,
         "stage_ms": kernels,
     })

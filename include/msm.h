@@ -172,8 +172,8 @@ typedef struct {
     int rigid_triples;           /* 1: atoms 3m, 3m+1, 3m+2 of every system are rigid; system
                                     offsets must then be multiples of 3 */
     double tri_len[3];           /* distances 0-1, 0-2, 1-2 of each rigid triple (nm) */
-    double constraint_tol;       /* relative tolerance of the constraint iteration (0: 1e-10
-                                    for FP64, 1e-6 for FP32) */
+    double constraint_tol;       /* relative tolerance of the constraint iteration (0: 1e-10);
+                                    the iteration runs in FP64 */
 } msm_md_model;
 
 /* Copy a molecular model into the context and allocate the dynamics
@@ -184,8 +184,10 @@ int msm_md_bind(msm_ctx *ctx, const msm_md_model *model);
 
 /* nsteps velocity-Verlet steps of dt ps (Section 2), in place, on nsys
  * systems (offsets and domains as for msm_energy_forces):
- *  xyzq_dev  N x 4 positions and charges, precision of the context;
- *  vel_dev   N x 4 velocities (nm/ps) and inverse masses (1/amu).
+ *  xyzq_dev  N x 4 doubles: positions and charges;
+ *  vel_dev   N x 4 doubles: velocities (nm/ps) and inverse masses (1/amu).
+ * The integrator state and the constraints are FP64 in both precisions; an
+ * FP32 context evaluates the forces from an FP32 copy of the positions.
  * Each step: half kick, drift, RATTLE positions, forces, half kick, RATTLE
  * velocities; forces are evaluated nsteps + 1 times. epot_dev / ekin_dev
  * (nsys doubles, may be NULL) receive the potential and kinetic energy at the

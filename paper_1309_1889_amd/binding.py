@@ -310,10 +310,17 @@ class MsmContext:
         _check(lib().msm_md_bind(self._h, C.byref(m)), "msm_md_bind")
 
     def vv_run(self, xyzq, vel, nsteps, dt, offsets=None, domains=None, energies=True):
-        """Velocity Verlet in place on xyzq (N, 4) and vel (N, 4: v, 1/m).
+        """Velocity Verlet in place on xyzq (N, 4) and vel (N, 4: v, 1/m),
+        both float64 device tensors whatever the context's precision.
         Returns (epot, ekin) float64 tensors of length nsys, or None."""
         import torch
+        for t in (xyzq, vel):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.dim() != 2 \
+                    or t.shape[1] != 4:
+                raise ValueError("vv_run expects contiguous float64 (N, 4) device tensors")
         n = xyzq.shape[0]
+        if vel.shape[0] != n:
+            raise ValueError("xyzq and vel differ in length")
         if offsets is None:
             offsets = [0, n]
         offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))

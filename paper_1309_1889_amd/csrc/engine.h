@@ -74,7 +74,8 @@ struct msm_ctx {
     void *md_forces = nullptr;   // max_atoms x 3, precision T
     double *md_parts = nullptr;  // per-block partial sums (kinetic energy)
     double *md_scalar = nullptr; // scratch scalars (change of a parareal iteration, ...)
-    void *px = nullptr, *pv = nullptr;          // propagator state, max_atoms x 4 each, precision T
+    void *px = nullptr, *pv = nullptr;          // propagator state, max_atoms x 4 doubles each
+    void *pe = nullptr;                         // FP32 contexts: positions for the evaluation, max_atoms x 4
     double *fout = nullptr, *gold = nullptr;    // parareal: fine results and coarse values, max_atoms x 6
     double *gnew = nullptr;                     // parareal: coarse result of one slice, max_atoms x 6
 };

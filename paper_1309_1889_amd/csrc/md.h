@@ -12,16 +12,19 @@ struct TriModel {
     int max_iter;
 };
 
+// T is the precision of the forces (the context's); the state is FP64.
 template <typename T> struct MdLaunch {
-    static hipError_t kick_drift(hipStream_t s, int64_t n, vec4_t<T> *x, vec4_t<T> *v, const T *f, double dt,
-                                 const TriModel *tm);
-    static hipError_t kick(hipStream_t s, int64_t n, const vec4_t<T> *x, vec4_t<T> *v, const T *f, double dt,
+    static hipError_t kick_drift(hipStream_t s, int64_t n, double4 *x, double4 *v, const T *f, double dt,
+                                 const TriModel *tm, vec4_t<T> *xe);
+    static hipError_t kick(hipStream_t s, int64_t n, const double4 *x, double4 *v, const T *f, double dt,
                            const TriModel *tm);
-    static hipError_t kinetic(hipStream_t s, const DevPlan &p, const vec4_t<T> *v, double *parts, double *ekin);
-    static hipError_t state_in(hipStream_t s, int64_t natoms, int64_t count, const double *lam, const double *q,
-                               const double *invm, vec4_t<T> *x, vec4_t<T> *v);
-    static hipError_t state_out(hipStream_t s, int64_t count, const vec4_t<T> *x, const vec4_t<T> *v, double *out);
+    static hipError_t to_eval(hipStream_t s, int64_t n, const double4 *x, vec4_t<T> *xe);
 };
+
+hipError_t md_kinetic(hipStream_t s, const DevPlan &p, const double4 *v, double *parts, double *ekin);
+hipError_t md_state_in(hipStream_t s, int64_t natoms, int64_t count, const double *lam, const double *q,
+                       const double *invm, double4 *x, double4 *v);
+hipError_t md_state_out(hipStream_t s, int64_t count, const double4 *x, const double4 *v, double *out);
 
 // Per-system sums of the per-block partials of the plan's interpolation
 // blocks, times `scale`, into out[nsys].

@@ -43,7 +43,8 @@ template <typename T> int bind(msm_ctx *c, const msm_md_model *m)
     const size_t o_f = take(sizeof(T) * 3 * na);
     const size_t o_parts = take(sizeof(double) * c->cap_iblk);
     const size_t o_scal = take(sizeof(double) * 64);
-    const size_t o_px = take(sizeof(vec4_t<T>) * na), o_pv = take(sizeof(vec4_t<T>) * na);
+    const size_t o_px = take(sizeof(double4) * na), o_pv = take(sizeof(double4) * na);
+    const size_t o_pe = sizeof(T) == 4 ? take(sizeof(vec4_t<T>) * na) : 0;
     const size_t o_fout = take(sizeof(double) * 6 * na), o_gold = take(sizeof(double) * 6 * na);
     const size_t o_gnew = take(sizeof(double) * 6 * na);
     if (hipMalloc((void **)&c->mdbuf, off) != hipSuccess) return MSM_ERR_HIP;
@@ -59,6 +60,7 @@ template <typename T> int bind(msm_ctx *c, const msm_md_model *m)
     c->md_scalar = (double *)(b + o_scal);
     c->px = b + o_px;
     c->pv = b + o_pv;
+    c->pe = sizeof(T) == 4 ? b + o_pe : nullptr;
     c->fout = (double *)(b + o_fout);
     c->gold = (double *)(b + o_gold);
     c->gnew = (double *)(b + o_gnew);
@@ -95,31 +97,36 @@ template <typename T> int bind(msm_ctx *c, const msm_md_model *m)
     }
     c->rigid = m->rigid_triples != 0;
     for (int d = 0; d < 3; d++) c->tri.len[d] = m->tri_len[d];
-    c->tri.tol = m->constraint_tol > 0 ? m->constraint_tol : (sizeof(T) == 8 ? 1e-10 : 1e-6);
+    c->tri.tol = m->constraint_tol > 0 ? m->constraint_tol : 1e-10;   // the state is FP64 either way
     c->tri.max_iter = 500;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
     c->md_bound = true;
     return MSM_OK;
 }
 
-// Velocity Verlet on the current plan (built by the caller).
+// Velocity Verlet on the current plan (built by the caller), FP64 state,
+// forces in the context's precision T.
 template <typename T> int vv(msm_ctx *c, void *xyzq, void *vel, int nsteps, double dt, double *epot, double *ekin)
 {
     using M = MdLaunch<T>;
     hipStream_t s = c->stream;
     const int64_t n = c->dp.natoms;
-    vec4_t<T> *x = (vec4_t<T> *)xyzq, *v = (vec4_t<T> *)vel;
+    double4 *x = (double4 *)xyzq, *v = (double4 *)vel;
+    // the evaluation reads T positions: the state itself for FP64, a copy for FP32
+    vec4_t<T> *xe = sizeof(T) == 8 ? (vec4_t<T> *)x : (vec4_t<T> *)c->pe;
+    vec4_t<T> *xe_out = sizeof(T) == 8 ? nullptr : xe;
     T *f = (T *)c->md_forces;
     const TriModel *tm = c->rigid ? &c->tri : nullptr;
-    int rc = evaluate_any(c, x, nsteps == 0 ? epot : nullptr, f, nullptr);
+    if (xe_out && M::to_eval(s, n, x, xe_out) != hipSuccess) return MSM_ERR_HIP;
+    int rc = evaluate_any(c, xe, nsteps == 0 ? epot : nullptr, f, nullptr);
     if (rc) return rc;
     for (int st = 0; st < nsteps; st++) {
-        if (M::kick_drift(s, n, x, v, f, dt, tm) != hipSuccess) return MSM_ERR_HIP;
-        rc = evaluate_any(c, x, st == nsteps - 1 ? epot : nullptr, f, nullptr);
+        if (M::kick_drift(s, n, x, v, f, dt, tm, xe_out) != hipSuccess) return MSM_ERR_HIP;
+        rc = evaluate_any(c, xe, st == nsteps - 1 ? epot : nullptr, f, nullptr);
         if (rc) return rc;
         if (M::kick(s, n, x, v, f, dt, tm) != hipSuccess) return MSM_ERR_HIP;
     }
-    if (ekin && M::kinetic(s, c->dp, v, c->md_parts, ekin) != hipSuccess) return MSM_ERR_HIP;
+    if (ekin && md_kinetic(s, c->dp, v, c->md_parts, ekin) != hipSuccess) return MSM_ERR_HIP;
     return MSM_OK;
 }
 
@@ -148,19 +155,10 @@ int propagate(msm_ctx *c, int64_t n, int count, const double *q, const double *i
     if (rc) return rc;
     const int64_t tot = n * count;
     hipStream_t s = c->stream;
-    if (c->prm.precision == MSM_FP32) {
-        if (MdLaunch<float>::state_in(s, n, tot, lam_in, q, invm, (float4 *)c->px, (float4 *)c->pv) != hipSuccess)
-            return MSM_ERR_HIP;
-    } else if (MdLaunch<double>::state_in(s, n, tot, lam_in, q, invm, (double4 *)c->px, (double4 *)c->pv) !=
-               hipSuccess) {
-        return MSM_ERR_HIP;
-    }
+    if (md_state_in(s, n, tot, lam_in, q, invm, (double4 *)c->px, (double4 *)c->pv) != hipSuccess) return MSM_ERR_HIP;
     rc = vv_any(c, c->px, c->pv, steps, dt, nullptr, nullptr);
     if (rc) return rc;
-    hipError_t e = c->prm.precision == MSM_FP32
-                       ? MdLaunch<float>::state_out(s, tot, (float4 *)c->px, (float4 *)c->pv, lam_out)
-                       : MdLaunch<double>::state_out(s, tot, (double4 *)c->px, (double4 *)c->pv, lam_out);
-    return e == hipSuccess ? MSM_OK : MSM_ERR_HIP;
+    return md_state_out(s, tot, (double4 *)c->px, (double4 *)c->pv, lam_out) == hipSuccess ? MSM_OK : MSM_ERR_HIP;
 }
 
 }  // namespace

@@ -4,8 +4,11 @@
 // Section 4 (conversion between the FP64 iterates and the propagator state,
 // and the correction lambda_{n+1} = F(lambda^k_n) + (G(lambda^{k+1}_n) - G(lambda^k_n))).
 //
-// Propagator state: xyzq (x, y, z, q) and vel (vx, vy, vz, 1/m), both in the
-// context's precision T; forces are N x 3 in T.
+// Propagator state (mixed precision): x = (x, y, z, q) and v = (vx, vy, vz,
+// 1/m) in FP64 for both context precisions, so that positions far from the
+// origin and the constraint iteration keep full resolution; the forces come
+// from the evaluation in the context's precision T (N x 3), and for T = float
+// an FP32 copy of x feeds that evaluation.
 #include "md.h"
 
 namespace msmx {
@@ -23,60 +26,70 @@ template <typename T> __device__ inline T dot(V3<T> a, V3<T> b) { return a.x * b
 __constant__ int kTriA[3] = {0, 0, 1};
 __constant__ int kTriB[3] = {1, 2, 2};
 
-// Half kick and drift of one atom (no constraints).
+// Half kick and drift of one atom (no constraints). The state is FP64; the
+// forces come in the evaluation precision T; `xe` (may be null) receives the
+// new positions and charges in T for the next force evaluation.
 template <typename T>
-__global__ void k_kick_drift(int64_t n, vec4_t<T> *__restrict__ x, vec4_t<T> *__restrict__ v,
-                             const T *__restrict__ f, T dt)
+__global__ void k_kick_drift(int64_t n, double4 *__restrict__ x, double4 *__restrict__ v, const T *__restrict__ f,
+                             double dt, vec4_t<T> *__restrict__ xe)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    vec4_t<T> vi = v[i], xi = x[i];
-    const T h = T(0.5) * dt * vi.w;
-    vi.x += h * f[3 * i];
-    vi.y += h * f[3 * i + 1];
-    vi.z += h * f[3 * i + 2];
+    double4 vi = v[i], xi = x[i];
+    const double h = 0.5 * dt * vi.w;
+    vi.x += h * (double)f[3 * i];
+    vi.y += h * (double)f[3 * i + 1];
+    vi.z += h * (double)f[3 * i + 2];
     xi.x += dt * vi.x;
     xi.y += dt * vi.y;
     xi.z += dt * vi.z;
     v[i] = vi;
     x[i] = xi;
+    if (xe) {
+        vec4_t<T> o;
+        o.x = T(xi.x);
+        o.y = T(xi.y);
+        o.z = T(xi.z);
+        o.w = T(xi.w);
+        xe[i] = o;
+    }
 }
 
 // Half kick, drift, then RATTLE's position stage for one rigid triple: each
 // bond is brought back to its length along the bond vector before the drift,
 // and the same displacement over dt is added to the velocities.
 template <typename T>
-__global__ void k_kick_drift_rattle(int64_t ntri, vec4_t<T> *__restrict__ x, vec4_t<T> *__restrict__ v,
-                                    const T *__restrict__ f, T dt, TriModel tm)
+__global__ void k_kick_drift_rattle(int64_t ntri, double4 *__restrict__ x, double4 *__restrict__ v,
+                                    const T *__restrict__ f, double dt, TriModel tm, vec4_t<T> *__restrict__ xe)
 {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= ntri) return;
-    V3<T> r[3], old[3], vel[3];
-    T im[3];
-    vec4_t<T> xs[3];
+    V3<double> r[3], old[3], vel[3];
+    double im[3], q[3];
     for (int a = 0; a < 3; a++) {
         const int64_t i = 3 * t + a;
-        xs[a] = x[i];
-        const vec4_t<T> vi = v[i];
+        const double4 xs = x[i];
+        const double4 vi = v[i];
+        q[a] = xs.w;
         im[a] = vi.w;
-        const T h = T(0.5) * dt * vi.w;
-        vel[a] = {vi.x + h * f[3 * i], vi.y + h * f[3 * i + 1], vi.z + h * f[3 * i + 2]};
-        old[a] = {xs[a].x, xs[a].y, xs[a].z};
+        const double h = 0.5 * dt * vi.w;
+        vel[a] = {vi.x + h * (double)f[3 * i], vi.y + h * (double)f[3 * i + 1], vi.z + h * (double)f[3 * i + 2]};
+        old[a] = {xs.x, xs.y, xs.z};
         r[a] = {old[a].x + dt * vel[a].x, old[a].y + dt * vel[a].y, old[a].z + dt * vel[a].z};
     }
-    const T inv_dt = T(1) / dt;
+    const double inv_dt = 1.0 / dt;
     for (int it = 0; it < tm.max_iter; it++) {
         bool done = true;
         for (int c = 0; c < 3; c++) {
             const int a = kTriA[c], b = kTriB[c];
-            const T d2 = T(tm.len[c] * tm.len[c]);
-            const V3<T> s = sub(r[a], r[b]);
-            const V3<T> ro = sub(old[a], old[b]);
-            const T diff = d2 - dot(s, s);
-            if (fabs(diff) <= T(2) * T(tm.tol) * d2) continue;
+            const double d2 = tm.len[c] * tm.len[c];
+            const V3<double> s = sub(r[a], r[b]);
+            const V3<double> ro = sub(old[a], old[b]);
+            const double diff = d2 - dot(s, s);
+            if (fabs(diff) <= 2.0 * tm.tol * d2) continue;
             done = false;
-            const T g = diff / (T(2) * dot(s, ro) * (im[a] + im[b]));
-            const T ga = g * im[a], gb = g * im[b];
+            const double g = diff / (2.0 * dot(s, ro) * (im[a] + im[b]));
+            const double ga = g * im[a], gb = g * im[b];
             r[a] = {r[a].x + ga * ro.x, r[a].y + ga * ro.y, r[a].z + ga * ro.z};
             r[b] = {r[b].x - gb * ro.x, r[b].y - gb * ro.y, r[b].z - gb * ro.z};
             vel[a] = {vel[a].x + ga * inv_dt * ro.x, vel[a].y + ga * inv_dt * ro.y, vel[a].z + ga * inv_dt * ro.z};
@@ -86,81 +99,87 @@ __global__ void k_kick_drift_rattle(int64_t ntri, vec4_t<T> *__restrict__ x, vec
     }
     for (int a = 0; a < 3; a++) {
         const int64_t i = 3 * t + a;
-        vec4_t<T> xo = xs[a];
-        xo.x = r[a].x;
-        xo.y = r[a].y;
-        xo.z = r[a].z;
-        x[i] = xo;
-        vec4_t<T> vo;
-        vo.x = vel[a].x;
-        vo.y = vel[a].y;
-        vo.z = vel[a].z;
-        vo.w = im[a];
-        v[i] = vo;
+        x[i] = make_double4(r[a].x, r[a].y, r[a].z, q[a]);
+        v[i] = make_double4(vel[a].x, vel[a].y, vel[a].z, im[a]);
+        if (xe) {
+            vec4_t<T> o;
+            o.x = T(r[a].x);
+            o.y = T(r[a].y);
+            o.z = T(r[a].z);
+            o.w = T(q[a]);
+            xe[i] = o;
+        }
     }
 }
 
 template <typename T>
-__global__ void k_kick(int64_t n, vec4_t<T> *__restrict__ v, const T *__restrict__ f, T dt)
+__global__ void k_kick(int64_t n, double4 *__restrict__ v, const T *__restrict__ f, double dt)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= n) return;
-    vec4_t<T> vi = v[i];
-    const T h = T(0.5) * dt * vi.w;
-    vi.x += h * f[3 * i];
-    vi.y += h * f[3 * i + 1];
-    vi.z += h * f[3 * i + 2];
+    double4 vi = v[i];
+    const double h = 0.5 * dt * vi.w;
+    vi.x += h * (double)f[3 * i];
+    vi.y += h * (double)f[3 * i + 1];
+    vi.z += h * (double)f[3 * i + 2];
     v[i] = vi;
 }
 
 // Second half kick, then RATTLE's velocity stage: remove the relative
 // velocity along every bond of the triple.
 template <typename T>
-__global__ void k_kick_rattle(int64_t ntri, const vec4_t<T> *__restrict__ x, vec4_t<T> *__restrict__ v,
-                              const T *__restrict__ f, T dt, TriModel tm)
+__global__ void k_kick_rattle(int64_t ntri, const double4 *__restrict__ x, double4 *__restrict__ v,
+                              const T *__restrict__ f, double dt, TriModel tm)
 {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= ntri) return;
-    V3<T> r[3], vel[3];
-    T im[3];
+    V3<double> r[3], vel[3];
+    double im[3];
     for (int a = 0; a < 3; a++) {
         const int64_t i = 3 * t + a;
-        const vec4_t<T> xi = x[i], vi = v[i];
+        const double4 xi = x[i], vi = v[i];
         im[a] = vi.w;
-        const T h = T(0.5) * dt * vi.w;
-        vel[a] = {vi.x + h * f[3 * i], vi.y + h * f[3 * i + 1], vi.z + h * f[3 * i + 2]};
+        const double h = 0.5 * dt * vi.w;
+        vel[a] = {vi.x + h * (double)f[3 * i], vi.y + h * (double)f[3 * i + 1], vi.z + h * (double)f[3 * i + 2]};
         r[a] = {xi.x, xi.y, xi.z};
     }
     for (int it = 0; it < tm.max_iter; it++) {
         bool done = true;
         for (int c = 0; c < 3; c++) {
             const int a = kTriA[c], b = kTriB[c];
-            const T d2 = T(tm.len[c] * tm.len[c]);
-            const V3<T> rr = sub(r[a], r[b]);
-            const V3<T> w = sub(vel[a], vel[b]);
-            const T rw = dot(rr, w);
-            if (fabs(rw) <= T(tm.tol) * d2) continue;
+            const double d2 = tm.len[c] * tm.len[c];
+            const V3<double> rr = sub(r[a], r[b]);
+            const V3<double> w = sub(vel[a], vel[b]);
+            const double rw = dot(rr, w);
+            if (fabs(rw) <= tm.tol * d2) continue;
             done = false;
-            const T kk = rw / ((im[a] + im[b]) * d2);
-            const T ka = kk * im[a], kb = kk * im[b];
+            const double kk = rw / ((im[a] + im[b]) * d2);
+            const double ka = kk * im[a], kb = kk * im[b];
             vel[a] = {vel[a].x - ka * rr.x, vel[a].y - ka * rr.y, vel[a].z - ka * rr.z};
             vel[b] = {vel[b].x + kb * rr.x, vel[b].y + kb * rr.y, vel[b].z + kb * rr.z};
         }
         if (done) break;
     }
-    for (int a = 0; a < 3; a++) {
-        vec4_t<T> vo;
-        vo.x = vel[a].x;
-        vo.y = vel[a].y;
-        vo.z = vel[a].z;
-        vo.w = im[a];
-        v[3 * t + a] = vo;
-    }
+    for (int a = 0; a < 3; a++) v[3 * t + a] = make_double4(vel[a].x, vel[a].y, vel[a].z, im[a]);
+}
+
+// Positions and charges in the evaluation precision.
+template <typename T>
+__global__ void k_to_eval(int64_t n, const double4 *__restrict__ x, vec4_t<T> *__restrict__ xe)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double4 xi = x[i];
+    vec4_t<T> o;
+    o.x = T(xi.x);
+    o.y = T(xi.y);
+    o.z = T(xi.z);
+    o.w = T(xi.w);
+    xe[i] = o;
 }
 
 // Kinetic energy 1/2 sum m v^2 per interpolation-sized block of each system.
-template <typename T>
-__global__ __launch_bounds__(256) void k_kinetic(DevPlan p, const vec4_t<T> *__restrict__ v, double *__restrict__ parts)
+__global__ __launch_bounds__(256) void k_kinetic(DevPlan p, const double4 *__restrict__ v, double *__restrict__ parts)
 {
     __shared__ double red[256];
     const int64_t blk = blockIdx.x;
@@ -169,8 +188,8 @@ __global__ __launch_bounds__(256) void k_kinetic(DevPlan p, const vec4_t<T> *__r
     const int64_t i = P.atom0 + (blk - p.iblk_prefix[s]) * 256 + threadIdx.x;
     double e = 0;
     if (i < P.atom0 + P.natoms) {
-        const vec4_t<T> vi = v[i];
-        e = 0.5 * ((double)vi.x * vi.x + (double)vi.y * vi.y + (double)vi.z * vi.z) / (double)vi.w;
+        const double4 vi = v[i];
+        e = 0.5 * (vi.x * vi.x + vi.y * vi.y + vi.z * vi.z) / vi.w;
     }
     red[threadIdx.x] = e;
     __syncthreads();
@@ -181,36 +200,25 @@ __global__ __launch_bounds__(256) void k_kinetic(DevPlan p, const vec4_t<T> *__r
     if (threadIdx.x == 0) parts[blk] = red[0];
 }
 
-// Propagator state of nsys consecutive slices from the FP64 iterates:
-// lambda (slice-major, n x 6 per slice) -> xyzq, vel with charges and inverse masses.
-template <typename T>
+// Propagator state of consecutive slices from the FP64 iterates:
+// lambda (slice-major, n x 6 per slice) -> x (positions, charge), v (velocity, 1/m).
 __global__ void k_state_in(int64_t natoms, int64_t count, const double *__restrict__ lam, const double *__restrict__ q,
-                           const double *__restrict__ invm, vec4_t<T> *__restrict__ x, vec4_t<T> *__restrict__ v)
+                           const double *__restrict__ invm, double4 *__restrict__ x, double4 *__restrict__ v)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= count) return;
     const int64_t a = i % natoms;
     const double *l = lam + 6 * i;
-    vec4_t<T> xo, vo;
-    xo.x = T(l[0]);
-    xo.y = T(l[1]);
-    xo.z = T(l[2]);
-    xo.w = T(q[a]);
-    vo.x = T(l[3]);
-    vo.y = T(l[4]);
-    vo.z = T(l[5]);
-    vo.w = T(invm[a]);
-    x[i] = xo;
-    v[i] = vo;
+    x[i] = make_double4(l[0], l[1], l[2], q[a]);
+    v[i] = make_double4(l[3], l[4], l[5], invm[a]);
 }
 
-template <typename T>
-__global__ void k_state_out(int64_t count, const vec4_t<T> *__restrict__ x, const vec4_t<T> *__restrict__ v,
+__global__ void k_state_out(int64_t count, const double4 *__restrict__ x, const double4 *__restrict__ v,
                             double *__restrict__ out)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= count) return;
-    const vec4_t<T> xi = x[i], vi = v[i];
+    const double4 xi = x[i], vi = v[i];
     double *o = out + 6 * i;
     o[0] = xi.x;
     o[1] = xi.y;
@@ -259,50 +267,55 @@ __global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
 }  // namespace
 
 template <typename T>
-hipError_t MdLaunch<T>::kick_drift(hipStream_t s, int64_t n, vec4_t<T> *x, vec4_t<T> *v, const T *f, double dt,
-                                   const TriModel *tm)
+hipError_t MdLaunch<T>::kick_drift(hipStream_t s, int64_t n, double4 *x, double4 *v, const T *f, double dt,
+                                   const TriModel *tm, vec4_t<T> *xe)
 {
     if (n == 0) return hipSuccess;
     if (tm)
-        hipLaunchKernelGGL(k_kick_drift_rattle<T>, dim3(nblocks(n / 3, 128)), dim3(128), 0, s, n / 3, x, v, f, T(dt), *tm);
+        hipLaunchKernelGGL(k_kick_drift_rattle<T>, dim3(nblocks(n / 3, 128)), dim3(128), 0, s, n / 3, x, v, f, dt, *tm,
+                           xe);
     else
-        hipLaunchKernelGGL(k_kick_drift<T>, dim3(nblocks(n, 256)), dim3(256), 0, s, n, x, v, f, T(dt));
+        hipLaunchKernelGGL(k_kick_drift<T>, dim3(nblocks(n, 256)), dim3(256), 0, s, n, x, v, f, dt, xe);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t MdLaunch<T>::kick(hipStream_t s, int64_t n, const vec4_t<T> *x, vec4_t<T> *v, const T *f, double dt,
+hipError_t MdLaunch<T>::kick(hipStream_t s, int64_t n, const double4 *x, double4 *v, const T *f, double dt,
                              const TriModel *tm)
 {
     if (n == 0) return hipSuccess;
     if (tm)
-        hipLaunchKernelGGL(k_kick_rattle<T>, dim3(nblocks(n / 3, 128)), dim3(128), 0, s, n / 3, x, v, f, T(dt), *tm);
+        hipLaunchKernelGGL(k_kick_rattle<T>, dim3(nblocks(n / 3, 128)), dim3(128), 0, s, n / 3, x, v, f, dt, *tm);
     else
-        hipLaunchKernelGGL(k_kick<T>, dim3(nblocks(n, 256)), dim3(256), 0, s, n, v, f, T(dt));
+        hipLaunchKernelGGL(k_kick<T>, dim3(nblocks(n, 256)), dim3(256), 0, s, n, v, f, dt);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t MdLaunch<T>::kinetic(hipStream_t s, const DevPlan &p, const vec4_t<T> *v, double *parts, double *ekin)
+template <typename T> hipError_t MdLaunch<T>::to_eval(hipStream_t s, int64_t n, const double4 *x, vec4_t<T> *xe)
 {
-    if (p.niblk > 0) hipLaunchKernelGGL(k_kinetic<T>, dim3((unsigned)p.niblk), dim3(256), 0, s, p, v, parts);
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_to_eval<T>, dim3(nblocks(n, 256)), dim3(256), 0, s, n, x, xe);
+    return hipGetLastError();
+}
+
+hipError_t md_kinetic(hipStream_t s, const DevPlan &p, const double4 *v, double *parts, double *ekin)
+{
+    if (p.niblk > 0) hipLaunchKernelGGL(k_kinetic, dim3((unsigned)p.niblk), dim3(256), 0, s, p, v, parts);
     return reduce_blocks(s, p, parts, ekin, 1.0);
 }
 
-template <typename T>
-hipError_t MdLaunch<T>::state_in(hipStream_t s, int64_t natoms, int64_t count, const double *lam, const double *q,
-                                 const double *invm, vec4_t<T> *x, vec4_t<T> *v)
+hipError_t md_state_in(hipStream_t s, int64_t natoms, int64_t count, const double *lam, const double *q,
+                       const double *invm, double4 *x, double4 *v)
 {
     if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_state_in<T>, dim3(nblocks(count, 256)), dim3(256), 0, s, natoms, count, lam, q, invm, x, v);
+    hipLaunchKernelGGL(k_state_in, dim3(nblocks(count, 256)), dim3(256), 0, s, natoms, count, lam, q, invm, x, v);
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t MdLaunch<T>::state_out(hipStream_t s, int64_t count, const vec4_t<T> *x, const vec4_t<T> *v, double *out)
+hipError_t md_state_out(hipStream_t s, int64_t count, const double4 *x, const double4 *v, double *out)
 {
     if (count == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_state_out<T>, dim3(nblocks(count, 256)), dim3(256), 0, s, count, x, v, out);
+    hipLaunchKernelGGL(k_state_out, dim3(nblocks(count, 256)), dim3(256), 0, s, count, x, v, out);
     return hipGetLastError();
 }
 

@@ -44,9 +44,10 @@ def make_ctx(w, a, h, precision, mass, molid, lj, tri, max_atoms=None, max_syste
     return ctx
 
 
-def state_tensors(xyz, v, q, mass, dt):
-    x = torch.tensor(np.concatenate([xyz, q[:, None]], 1), dtype=dt, device="cuda").contiguous()
-    vv = torch.tensor(np.concatenate([v, 1.0 / mass[:, None]], 1), dtype=dt, device="cuda").contiguous()
+def state_tensors(xyz, v, q, mass):
+    """Integrator state: FP64 in both precisions (the forces follow the context)."""
+    x = torch.tensor(np.concatenate([xyz, q[:, None]], 1), dtype=torch.float64, device="cuda").contiguous()
+    vv = torch.tensor(np.concatenate([v, 1.0 / mass[:, None]], 1), dtype=torch.float64, device="cuda").contiguous()
     return x, vv
 
 
@@ -77,20 +78,17 @@ def test_model_forces_match_oracle(precision):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_velocity_verlet_matches_oracle(precision):
     w, mass, molid, lj, tri, v = small_water(216, 1.86, seed=3)
-    dtp = np.float32 if precision == "fp32" else np.float64
-    tdt = torch.float32 if precision == "fp32" else torch.float64
-    xyz = w.xyz.astype(dtp).astype(np.float64)
-    vel = v.astype(dtp).astype(np.float64)
+    xyz, vel = w.xyz, v
     ctx = make_ctx(w, 1.0, 0.25, precision, mass, molid, lj, tri)
-    x, vv = state_tensors(xyz, vel, w.q, mass, tdt)
+    x, vv = state_tensors(xyz, vel, w.q, mass)
     ep, ek = ctx.vv_run(x, vv, 10, 0.001)
     torch.cuda.synchronize()
     assert ctx.status() == 0
     p = oracle.OracleParams(1.0, 0.25, tuple(w.lo), tuple(w.hi), 0, KE)
     model = oracle.OracleModel(mass, molid, lj, True, tri, 1e-12)
     xo, vo, epo, eko = oracle.vv(p, model, xyz, vel, w.q, 0.001, 10)
-    xg = x[:, :3].double().cpu().numpy()
-    vg = vv[:, :3].double().cpu().numpy()
+    xg = x[:, :3].cpu().numpy()
+    vg = vv[:, :3].cpu().numpy()
     if precision == "fp64":
         assert np.abs(xg - xo).max() < 1e-9
         assert rel_rms(vg, vo) < 1e-7
@@ -100,9 +98,9 @@ def test_velocity_verlet_matches_oracle(precision):
         assert np.abs(xg - xo).max() < 2e-4
         assert rel_rms(vg, vo) < 2e-3
         assert ek.item() == pytest.approx(eko, rel=2e-3)
-    # the rigid geometry holds
+    # the rigid geometry holds to the FP64 constraint tolerance in both precisions
     d = xg.reshape(-1, 3, 3)
-    lim = 1e-9 if precision == "fp64" else 2e-6
+    lim = 1e-9
     for (a, b), L in zip([(0, 1), (0, 2), (1, 2)], tri):
         assert np.abs(np.linalg.norm(d[:, a] - d[:, b], axis=1) - L).max() < lim
 
@@ -120,7 +118,7 @@ def test_uneven_batch_vv_equals_separate_bitwise():
     doms = np.array([np.concatenate([s[0].lo, s[0].hi]) for s in systems])
     big = make_ctx(systems[0][0], 0.9, 0.25, "fp32", mass, molid, lj, tri, max_atoms=int(offs[-1]), max_systems=3,
                    lo=lo, hi=hi)
-    xs, vs = zip(*[state_tensors(s[0].xyz, s[5], s[0].q, s[1], torch.float32) for s in systems])
+    xs, vs = zip(*[state_tensors(s[0].xyz, s[5], s[0].q, s[1]) for s in systems])
     x = torch.cat(xs).contiguous()
     v = torch.cat(vs).contiguous()
     ep, ek = big.vv_run(x, v, 5, 0.002, offsets=offs, domains=doms)
@@ -128,7 +126,7 @@ def test_uneven_batch_vv_equals_separate_bitwise():
     assert big.status() == 0
     for k, s in enumerate(systems):
         one = make_ctx(s[0], 0.9, 0.25, "fp32", s[1], s[2], s[3], tri)
-        x1, v1 = state_tensors(s[0].xyz, s[5], s[0].q, s[1], torch.float32)
+        x1, v1 = state_tensors(s[0].xyz, s[5], s[0].q, s[1])
         ep1, ek1 = one.vv_run(x1, v1, 5, 0.002)
         torch.cuda.synchronize()
         assert torch.equal(x[offs[k]:offs[k + 1]], x1)
@@ -138,27 +136,24 @@ def test_uneven_batch_vv_equals_separate_bitwise():
 
 def _parareal_setup(precision, S):
     w, mass, molid, lj, tri, v = small_water(125, 1.55, seed=21)
-    tdt = torch.float32 if precision == "fp32" else torch.float64
-    npdt = np.float32 if precision == "fp32" else np.float64
-    xyz = w.xyz.astype(npdt).astype(np.float64)
-    vel = v.astype(npdt).astype(np.float64)
+    xyz, vel = w.xyz, v
     fine = make_ctx(w, 0.9, 0.25, precision, mass, molid, lj, tri, max_atoms=S * w.n, max_systems=S)
     coarse = make_ctx(w, 0.7, 0.5, precision, mass, molid, lj, tri)
     q = torch.tensor(w.q, dtype=torch.float64, device="cuda")
     invm = torch.tensor(1.0 / mass, dtype=torch.float64, device="cuda")
     s0 = torch.tensor(np.concatenate([xyz, vel], 1), dtype=torch.float64, device="cuda").contiguous()
-    return w, mass, molid, lj, tri, xyz, vel, fine, coarse, q, invm, s0, tdt
+    return w, mass, molid, lj, tri, xyz, vel, fine, coarse, q, invm, s0
 
 
-def _serial(ctx, s0, q, invm, S, steps, dt, tdt):
-    """Serial propagation slice by slice through the same state conversion."""
+def _serial(ctx, s0, q, invm, S, steps, dt):
+    """Serial propagation slice by slice from the FP64 slice states."""
     out = [s0.clone()]
     for _ in range(S):
         cur = out[-1]
-        x = torch.cat([cur[:, :3], q[:, None]], 1).to(tdt).contiguous()
-        v = torch.cat([cur[:, 3:], invm[:, None]], 1).to(tdt).contiguous()
+        x = torch.cat([cur[:, :3], q[:, None]], 1).contiguous()
+        v = torch.cat([cur[:, 3:], invm[:, None]], 1).contiguous()
         ctx.vv_run(x, v, steps, dt, energies=False)
-        out.append(torch.cat([x[:, :3].double(), v[:, :3].double()], 1))
+        out.append(torch.cat([x[:, :3], v[:, :3]], 1))
     torch.cuda.synchronize()
     return out
 
@@ -166,12 +161,12 @@ def _serial(ctx, s0, q, invm, S, steps, dt, tdt):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_parareal_exact_after_k_iterations(precision):
     S, sf, dtf, sg, dtg = 5, 3, 0.001, 1, 0.003
-    w, mass, molid, lj, tri, xyz, vel, fine, coarse, q, invm, s0, tdt = _parareal_setup(precision, S)
+    w, mass, molid, lj, tri, xyz, vel, fine, coarse, q, invm, s0 = _parareal_setup(precision, S)
     m = msmx()
     # serial references on single-system contexts with the same parameters
     ref_f = make_ctx(w, 0.9, 0.25, precision, mass, molid, lj, tri)
-    serial_f = _serial(ref_f, s0, q, invm, S, sf, dtf, tdt)
-    serial_g = _serial(coarse, s0, q, invm, S, sg, dtg, tdt)
+    serial_f = _serial(ref_f, s0, q, invm, S, sf, dtf)
+    serial_g = _serial(coarse, s0, q, invm, S, sg, dtg)
     lam0, rep0, _ = m.parareal(fine, coarse, q, invm, s0, nslices=S, kmax=0, tol=0.0, steps_f=sf, dt_f=dtf,
                                steps_g=sg, dt_g=dtg)
     torch.cuda.synchronize()
@@ -193,7 +188,7 @@ def test_parareal_exact_after_k_iterations(precision):
 
 def test_parareal_fp64_matches_oracle():
     S, sf, dtf, sg, dtg = 4, 3, 0.001, 1, 0.003
-    w, mass, molid, lj, tri, xyz, vel, fine, coarse, q, invm, s0, tdt = _parareal_setup("fp64", S)
+    w, mass, molid, lj, tri, xyz, vel, fine, coarse, q, invm, s0 = _parareal_setup("fp64", S)
     m = msmx()
     lam, rep, rc = m.parareal(fine, coarse, q, invm, s0, nslices=S, kmax=2, tol=0.0, steps_f=sf, dt_f=dtf,
                               steps_g=sg, dt_g=dtg)
@@ -211,7 +206,7 @@ def test_parareal_fp64_matches_oracle():
 
 def test_parareal_reports_domain_exit():
     S = 2
-    w, mass, molid, lj, tri, xyz, vel, fine, coarse, q, invm, s0, tdt = _parareal_setup("fp64", S)
+    w, mass, molid, lj, tri, xyz, vel, fine, coarse, q, invm, s0 = _parareal_setup("fp64", S)
     m = msmx()
     fast = s0.clone()
     fast[:, 3:] += 500.0      # every atom leaves the domain within the first slice
