@@ -152,7 +152,8 @@ int msm_grid_shape(const msm_ctx *ctx, const double *domain_host, int *org, int 
  * before the factor k q_i), per-level grids q^k and u^k (prolongated; the
  * lattice-cutoff part for `ucut`) in x-fastest order of msm_grid_shape.
  * Grid pointers are arrays of `levels` device pointers in host memory.
- * Atom arrays are in the caller's order. For tests. */
+ * Atom arrays are in the caller's order. u_short is zero when that call asked
+ * for neither energy nor potentials. For tests. */
 int msm_debug_stages(msm_ctx *ctx, int sys, double *u_short_dev, double *f_short_dev,
                      double *const *q_grid_dev, double *const *ucut_grid_dev,
                      double *const *u_grid_dev);

@@ -317,7 +317,9 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     mark(MSM_STAGE_BIN);
     if ((e = L::bin(s, p, w, (const vec4_t<T> *)xyzq)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_SHORT);
-    if ((e = L::pair(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
+    // the short-range potentials are needed only for the energy and the potentials
+    const bool pot = energy || pots || c->tuning_pass;
+    if ((e = L::pair(s, p, w, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_ANTERP);
     if ((e = L::anterp(s, p, w)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_RESTRICT);
@@ -616,6 +618,7 @@ int msm_autotune(msm_ctx *c, int nsys, const int64_t *offsets, const double *dom
     const bool was_timing = c->timing;
     const msm_tuning start{c->mc.pair_waves, c->mc.stencil_threads};
     if ((rc = msm_enable_stage_timing(c, 1))) return rc;
+    c->tuning_pass = true;   // time the pair kernel that also sums the potentials
     // time one stage for one candidate: a warm-up evaluation, then reps
     auto stage_time = [&](int stage, double *ms) {
         int r = evaluate_any(c, xyzq, nullptr, nullptr, nullptr);
@@ -652,6 +655,7 @@ int msm_autotune(msm_ctx *c, int nsys, const int64_t *offsets, const double *dom
         }
     }
     c->timing = was_timing;
+    c->tuning_pass = false;
     if (rc) {
         c->mc.pair_waves = start.pair_waves;
         c->mc.stencil_threads = start.stencil_threads;

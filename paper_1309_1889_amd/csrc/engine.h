@@ -48,6 +48,7 @@ struct msm_ctx {
     msmx::Work<double> wd{};
     // stage timing (benchmarks)
     bool timing = false;
+    bool tuning_pass = false;                   // msm_autotune: evaluate as if potentials were asked for
     hipEvent_t ev[MSM_NSTAGES + 1] = {};
     double stage_ms[MSM_NSTAGES] = {};
     int64_t timed_evals = 0;

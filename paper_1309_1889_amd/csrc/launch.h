@@ -79,7 +79,8 @@ int scan_cells(hipStream_t s, int *counts_to_start, int64_t n, int *block_sums);
 
 template <typename T> struct Launch {
     static hipError_t bin(hipStream_t s, const DevPlan &p, const Work<T> &w, const vec4_t<T> *xyzq);
-    static hipError_t pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m);
+    // pot = false: forces only, the short-range potentials are left at zero
+    static hipError_t pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m, bool pot);
     static hipError_t anterp(hipStream_t s, const DevPlan &p, const Work<T> &w);
     static hipError_t restrict_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k);
     static hipError_t stencil(hipStream_t s, const DevPlan &p, const Work<T> &w, const StencilTables<T> &tb);

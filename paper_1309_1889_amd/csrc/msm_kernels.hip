@@ -95,7 +95,9 @@ template <typename T, bool MD> struct PairLds {
     vec4_t<T> aux[MD ? kWave : 1];
 };
 
-template <typename T, bool MD>
+// POT = false: forces only (no potential or energy sums), for evaluations
+// that are asked for neither.
+template <typename T, bool MD, bool POT>
 __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const vec4_t<T> &aj, const vec4_t<T> &xj,
                                  const PairK<T> &k, T &fx, T &fy, T &fz, T &u, T &lx, T &ly, T &lz, T &le)
 {
@@ -109,9 +111,11 @@ __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const
             same = mol_of(xi) == mol_of(xj);
             rc = same ? T(0) : rinv;
         }
-        const T gs = rc - (k.c0 + r2 * (k.c1 + r2 * k.c2));
         const T br = rc * rinv * rinv - (k.d0 + k.d1 * r2);
-        u += aj.w * gs;
+        if (POT) {
+            const T gs = rc - (k.c0 + r2 * (k.c1 + r2 * k.c2));
+            u += aj.w * gs;
+        }
         const T t = aj.w * br;
         fx += t * dx;
         fy += t * dy;
@@ -122,8 +126,10 @@ __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const
                 const T sg = xi.y + xj.y;
                 const T s2 = sg * sg;
                 const T sr2 = s2 * rinv * rinv, sr6 = sr2 * sr2 * sr2;
-                const T sc2 = s2 * k.inv_a2, sc6 = sc2 * sc2 * sc2;
-                le += T(4) * eps * ((sr6 * sr6 - sr6) - (sc6 * sc6 - sc6));
+                if (POT) {
+                    const T sc2 = s2 * k.inv_a2, sc6 = sc2 * sc2 * sc2;
+                    le += T(4) * eps * ((sr6 * sr6 - sr6) - (sc6 * sc6 - sc6));
+                }
                 const T fl = T(24) * eps * (T(2) * sr6 * sr6 - sr6) * rinv * rinv;
                 lx += fl * dx;
                 ly += fl * dy;
@@ -150,7 +156,7 @@ __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const
 // coalesced load (the next chunk is fetched while the current one is used),
 // and every lane reads each staged atom by broadcast and evaluates its own
 // pair. The waves' partial sums are added in a fixed order at the end.
-template <typename T, bool MD, int kPairWaves>
+template <typename T, bool MD, bool POT, int kPairWaves>
 __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                               const int *__restrict__ cstart,
                                                               vec4_t<T> *__restrict__ out, PairK<T> k,
@@ -190,6 +196,10 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
     const int nbx = bx1 - bx0 + 1, ny = cy1 - cy0 + 1;
     const int nitems = nbx * ny * (cz1 - cz0 + 1);
 
+    // The two polynomial addends are kept in vector registers: an FMA takes
+    // one scalar operand, so as kernel arguments they would be copied to
+    // vector registers again for every candidate.
+    asm volatile("" : "+v"(k.c1), "+v"(k.d0));
     T fx = 0, fy = 0, fz = 0, u = 0;
     T lx = 0, ly = 0, lz = 0, le = 0;
     // items wv, wv + W, wv + 2W, ..., 64 per batch
@@ -266,12 +276,12 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
                 }
 #pragma unroll
                 for (int v = 0; v < kPairUnroll; ++v)
-                    pair_term<T, MD>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le);
+                    pair_term<T, MD, POT>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le);
             }
             for (; t < cnt; ++t) {
                 const vec4_t<T> aj = L.atom[t];
                 const vec4_t<T> xj = MD ? L.aux[t] : aj;
-                pair_term<T, MD>(ai, xi, aj, xj, k, fx, fy, fz, u, lx, ly, lz, le);
+                pair_term<T, MD, POT>(ai, xi, aj, xj, k, fx, fy, fz, u, lx, ly, lz, le);
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -943,18 +953,26 @@ __global__ void k_stage_grid(const SysPlan *sys, int s, int k, const T *__restri
 }  // namespace
 
 template <typename T, int NW>
-static void pair_launch(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k)
+static void pair_launch(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot)
 {
-    if (w.saux)
-        hipLaunchKernelGGL((k_pair<T, true, NW>), dim3((unsigned)p.ngroups), dim3(NW * kWave), 0, s, p, w.sxyzq,
-                           w.cell_start, w.shrt, k, (const vec4_t<T> *)w.saux, w.shlj);
+    const dim3 grid((unsigned)p.ngroups), block(NW * kWave);
+    const vec4_t<T> *aux = (const vec4_t<T> *)w.saux;
+    if (w.saux && pot)
+        hipLaunchKernelGGL((k_pair<T, true, true, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k, aux,
+                           w.shlj);
+    else if (w.saux)
+        hipLaunchKernelGGL((k_pair<T, true, false, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k, aux,
+                           w.shlj);
+    else if (pot)
+        hipLaunchKernelGGL((k_pair<T, false, true, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
+                           (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
     else
-        hipLaunchKernelGGL((k_pair<T, false, NW>), dim3((unsigned)p.ngroups), dim3(NW * kWave), 0, s, p, w.sxyzq,
-                           w.cell_start, w.shrt, k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+        hipLaunchKernelGGL((k_pair<T, false, false, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
+                           (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
 }
 
 template <typename T>
-hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m)
+hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m, bool pot)
 {
     if (p.ngroups == 0) return hipSuccess;
     PairK<T> k;
@@ -970,9 +988,9 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, co
     k.d0 = T(2.5 / (a * a * a));
     k.d1 = T(-1.5 / (a * a * a * a * a));
     switch (m.pair_waves) {
-    case 4: pair_launch<T, 4>(s, p, w, k); break;
-    case 8: pair_launch<T, 8>(s, p, w, k); break;
-    case 16: pair_launch<T, 16>(s, p, w, k); break;
+    case 4: pair_launch<T, 4>(s, p, w, k, pot); break;
+    case 8: pair_launch<T, 8>(s, p, w, k, pot); break;
+    case 16: pair_launch<T, 16>(s, p, w, k, pot); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -228,6 +228,29 @@ def test_repeat_is_bitwise_deterministic():
     assert rel_rms(f3.cpu().numpy(), r1[1][perm].cpu().numpy()) < 1e-6
 
 
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_forces_only_evaluation_gives_the_same_forces(precision):
+    """An evaluation asked for forces alone skips the short-range potential
+    sums; its forces are those of the full evaluation, bit for bit, also with
+    a molecular model bound."""
+    m = _lib()
+    w = water_box(2000, (19, 19, 19), (5.8, 5.8, 5.8), seed=43)
+    dt = np.float32 if precision == "fp32" else np.float64
+    x = torch.tensor(w.xyzq(dt), device="cuda")
+    for model in (False, True):
+        ctx = m.MsmContext(w.a, w.h, w.lo, w.hi, precision=precision, max_atoms=w.n)
+        if model:
+            from workloads import water_model_arrays
+            mass, molid, lj, tri = water_model_arrays(w.n)
+            ctx.bind_model(w.n, torch.tensor(molid, dtype=torch.int32, device="cuda"),
+                           torch.tensor(lj, device="cuda"), rigid=True, tri=tri)
+        _, f_full, _ = ctx.energy_forces(x)
+        _, f_only, _ = ctx.energy_forces(x, want=("forces",))
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        assert torch.equal(f_full, f_only), model
+
+
 def test_status_reports_domain_and_nonfinite():
     m = _lib()
     w = uniform_pm(100, 2.0, seed=2)
