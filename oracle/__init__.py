@@ -12,6 +12,8 @@ fast oracle on tiny inputs.
 """
 from .loader import (  # noqa: F401
     OracleParams,
+    METHOD_MSM,
+    METHOD_CUTOFF,
     lib,
     gamma,
     dgamma,
@@ -23,6 +25,7 @@ from .loader import (  # noqa: F401
     grid_shape,
     msm,
     coulomb,
+    cutoff,
     short_subset,
     threads,
     OracleModel,

@@ -18,7 +18,11 @@ _dp = C.POINTER(C.c_double)
 
 class _Params(C.Structure):
     _fields_ = [("a", C.c_double), ("h", C.c_double), ("levels", C.c_int),
-                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("ke", C.c_double)]
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("ke", C.c_double), ("method", C.c_int)]
+
+
+METHOD_MSM = 0
+METHOD_CUTOFF = 1
 
 
 class _Stages(C.Structure):
@@ -35,10 +39,12 @@ class OracleParams:
     hi: tuple
     levels: int = 0
     ke: float = 138.935458
+    method: int = METHOD_MSM    # METHOD_CUTOFF: the simple cutoff method at a (dynamics oracle)
 
     def c(self) -> _Params:
         p = _Params()
         p.a, p.h, p.levels, p.ke = float(self.a), float(self.h), int(self.levels), float(self.ke)
+        p.method = int(self.method)
         for d in range(3):
             p.lo[d] = float(self.lo[d])
             p.hi[d] = float(self.hi[d])
@@ -73,6 +79,9 @@ def lib():
             L.orc_threads.restype = C.c_int
             L.orc_threads.argtypes = []
             L.orc_coulomb.argtypes = [C.c_int64, _dp, _dp, C.c_double, _dp, _dp, _dp]
+            L.orc_cutoff.restype = C.c_int
+            L.orc_cutoff.argtypes = [C.c_int64, _dp, _dp, C.POINTER(C.c_int32), C.c_double, C.c_double, _dp, _dp,
+                                     _dp]
             _lib = L
         return _lib
 
@@ -194,6 +203,24 @@ def coulomb(xyz, q, ke: float = 138.935458):
     rc = lib().orc_coulomb(n, _ptr(xyz), _ptr(q), float(ke), _ptr(e), _ptr(f), _ptr(pot))
     if rc != 0:
         raise RuntimeError(f"oracle coulomb failed with code {rc}")
+    return float(e[0]), f, pot
+
+
+def cutoff(xyz, q, rc, ke: float = 138.935458, molid=None):
+    """Simple cutoff method (Section 4): energy, forces and potentials of
+    Coulomb's law over the pairs closer than ``rc`` (pairs of equal ``molid``
+    left out), by the direct pair loop."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+    n = xyz.shape[0]
+    mol = None if molid is None else np.ascontiguousarray(molid, dtype=np.int32)
+    e = np.zeros(1)
+    f = np.zeros((n, 3))
+    pot = np.zeros(n)
+    rc_ = lib().orc_cutoff(n, _ptr(xyz), _ptr(q), None if mol is None else mol.ctypes.data_as(C.POINTER(C.c_int32)),
+                           float(rc), float(ke), _ptr(e), _ptr(f), _ptr(pot))
+    if rc_ != 0:
+        raise RuntimeError(f"oracle cutoff failed with code {rc_}")
     return float(e[0]), f, pot
 
 

@@ -9,9 +9,10 @@
  * The paper (Section 2) moves particles under F = -dU_all/dr with velocity
  * Verlet or leapfrog, U_all including bonded, van der Waals and Coulomb terms;
  * it gives no force field. The model here (a reading): rigid three-site
- * molecules held by RATTLE (Andersen 1983), Coulomb by MSM with the pairs
- * inside one molecule excluded, and Lennard-Jones with Lorentz-Berthelot
- * mixing, cut and shifted at the MSM cutoff a.
+ * molecules held by RATTLE (Andersen 1983), Coulomb by MSM (or, for a
+ * context with method ORC_METHOD_CUTOFF, by the simple cutoff method of
+ * Section 4) with the pairs inside one molecule excluded, and Lennard-Jones
+ * with Lorentz-Berthelot mixing, cut and shifted at the cutoff a.
  * Parareal follows Section 4: lambda_{n+1}^{k+1} = G(lambda_n^{k+1}) +
  * F(lambda_n^k) - G(lambda_n^k), started from a coarse sweep.
  */
@@ -21,7 +22,8 @@
 #include <stdlib.h>
 #include <string.h>
 
-/* ---- Coulomb pairs inside one molecule: remove k q_i q_j / r (atoms of a molecule are contiguous) ---- */
+/* ---- Coulomb pairs inside one molecule: remove k q_i q_j / r from the MSM
+ * result, which includes every pair (atoms of a molecule are contiguous) ---- */
 static void exclusions(const orc_params *p, const orc_model *m, int64_t n, const double *xyz, const double *q,
                        double *e, double *f)
 {
@@ -128,9 +130,15 @@ int orc_md_forces(const orc_params *p, const orc_model *m, int64_t n, const doub
                   double *epot, double *forces)
 {
     double e = 0;
-    int rc = orc_msm(p, n, xyz, q, &e, forces, NULL, NULL);
-    if (rc) return rc;
-    exclusions(p, m, n, xyz, q, &e, forces);
+    if (p->method == ORC_METHOD_CUTOFF) {
+        /* simple cutoff at a, intramolecular pairs left out of the sum */
+        int rc = orc_cutoff(n, xyz, q, m->molid, p->a, p->ke, &e, forces, NULL);
+        if (rc) return rc;
+    } else {
+        int rc = orc_msm(p, n, xyz, q, &e, forces, NULL, NULL);
+        if (rc) return rc;
+        exclusions(p, m, n, xyz, q, &e, forces);
+    }
     lennard_jones(p, m, n, xyz, &e, forces);
     if (epot) *epot = e;
     return 0;

@@ -516,3 +516,39 @@ int orc_coulomb(int64_t n, const double *xyz, const double *q, double ke,
     free(phi);
     return 0;
 }
+
+/* ---- Section 4: the simple cutoff method ---- */
+int orc_cutoff(int64_t n, const double *xyz, const double *q, const int32_t *molid, double rc, double ke,
+               double *energy, double *forces, double *pot)
+{
+    if (n < 0 || (n > 0 && (!xyz || !q)) || !(rc > 0)) return -1;
+    double *phi = malloc(sizeof(double) * (n > 0 ? n : 1));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; i++) {
+        double u = 0, fx = 0, fy = 0, fz = 0;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i || (molid && molid[j] == molid[i])) continue;
+            double rx = xyz[3 * i] - xyz[3 * j], ry = xyz[3 * i + 1] - xyz[3 * j + 1],
+                   rz = xyz[3 * i + 2] - xyz[3 * j + 2];
+            double r = sqrt(rx * rx + ry * ry + rz * rz);
+            if (!(r < rc)) continue;
+            u += q[j] / r;
+            /* -d(q_j/r)/dr_i = q_j (r_i - r_j) / r^3 */
+            fx += q[j] * rx / (r * r * r);
+            fy += q[j] * ry / (r * r * r);
+            fz += q[j] * rz / (r * r * r);
+        }
+        phi[i] = ke * u;
+        if (forces) {
+            forces[3 * i] = ke * q[i] * fx;
+            forces[3 * i + 1] = ke * q[i] * fy;
+            forces[3 * i + 2] = ke * q[i] * fz;
+        }
+    }
+    ksum e = {0, 0};
+    for (int64_t i = 0; i < n; i++) kadd(&e, q[i] * phi[i]);
+    if (energy) *energy = 0.5 * (e.s + e.c);
+    if (pot) memcpy(pot, phi, sizeof(double) * n);
+    free(phi);
+    return 0;
+}

@@ -18,13 +18,18 @@
 
 #define ORC_MAXLEV 16
 
+#define ORC_METHOD_MSM 0
+#define ORC_METHOD_CUTOFF 1
+
 typedef struct {
-    double a;          /* short-range cutoff */
+    double a;          /* short-range cutoff (the cutoff radius for ORC_METHOD_CUTOFF) */
     double h;          /* finest grid spacing */
     int levels;        /* number of grids l; 0 = choose from the domain */
     double lo[3];      /* domain lower corner (grid origin of every level) */
     double hi[3];      /* domain upper corner */
     double ke;         /* Coulomb constant */
+    int method;        /* ORC_METHOD_MSM, or ORC_METHOD_CUTOFF: the simple cutoff
+                          method of Section 4 (used by the dynamics oracle) */
 } orc_params;
 
 /* Optional per-stage outputs; any pointer may be NULL. Grid arrays are
@@ -61,5 +66,13 @@ int orc_short_subset(const orc_params *p, int64_t n, const double *xyz, const do
 
 int orc_coulomb(int64_t n, const double *xyz, const double *q, double ke,
                 double *energy, double *forces, double *pot);
+
+/* Simple cutoff method (Section 4, the coarse propagator the paper proposes):
+ * Coulomb's law between every pair closer than rc and nothing beyond,
+ * phi_i = ke sum_{j != i, r_ij < rc} q_j / r_ij, U = 1/2 sum_i q_i phi_i and
+ * F_i = -dU/dr_i away from the cutoff sphere. molid (may be NULL) removes the
+ * pairs of equal molecule id. Direct double loop over all pairs. */
+int orc_cutoff(int64_t n, const double *xyz, const double *q, const int32_t *molid, double rc, double ke,
+               double *energy, double *forces, double *pot);
 
 #endif

@@ -119,3 +119,23 @@ def test_parareal_exact_after_k_iterations_and_coarse_at_zero():
     # the residual shrinks as slices become exact
     lam, it, res, rc = oracle.parareal(pf, pg, model, w.xyz, v, w.q, S, sf, dtf, sg, dtg, S, 1e-30)
     assert res[-1] <= res[0]
+
+
+def test_cutoff_model_forces_are_cutoff_coulomb_plus_the_same_lennard_jones():
+    """With the simple cutoff method (Section 4) the Coulomb part is the cutoff
+    sum without intramolecular pairs, and the Lennard-Jones part is the same
+    one the MSM model adds."""
+    w, model, _ = small_water(64, 1.24, seed=17)
+    kw = dict(lo=tuple(w.lo), hi=tuple(w.hi), levels=0, ke=138.935458)
+    pc = oracle.OracleParams(0.6, 0.25, method=oracle.METHOD_CUTOFF, **kw)
+    pm = oracle.OracleParams(0.6, 0.25, method=oracle.METHOD_MSM, **kw)
+    no_lj = oracle.OracleModel(model.mass, model.molid, None, True, model.tri)
+    ec0, fc0 = oracle.md_forces(pc, no_lj, w.xyz, w.q)
+    e_ref, f_ref, _ = oracle.cutoff(w.xyz, w.q, 0.6, molid=model.molid)
+    assert ec0 == pytest.approx(e_ref, rel=1e-13)
+    np.testing.assert_allclose(fc0, f_ref, rtol=1e-12, atol=1e-9)
+    ec, fc = oracle.md_forces(pc, model, w.xyz, w.q)
+    em0, fm0 = oracle.md_forces(pm, no_lj, w.xyz, w.q)
+    em, fm = oracle.md_forces(pm, model, w.xyz, w.q)
+    assert ec - ec0 == pytest.approx(em - em0, rel=1e-10)
+    np.testing.assert_allclose(fc - fc0, fm - fm0, rtol=1e-9, atol=1e-7)

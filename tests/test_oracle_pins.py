@@ -366,3 +366,81 @@ def test_short_subset_matches_full_short_range(orc):
     u, f = orc.short_subset(p, w.xyz, w.q, sel)
     np.testing.assert_allclose(u, st["u_short"][sel], rtol=1e-12, atol=1e-12)
     np.testing.assert_allclose(f, st["f_short"][sel], rtol=1e-12, atol=1e-10)
+
+
+# --------------------------------------------------------------------------
+# the simple cutoff method (Section 4: the coarse propagator the paper picks)
+# --------------------------------------------------------------------------
+def test_cutoff_closed_forms(orc):
+    # eight unit charges on the corners of a unit cube, cutoff between the
+    # face diagonal (sqrt 2) and the body diagonal (sqrt 3): the 12 edges and
+    # 12 face diagonals count, the 4 body diagonals do not
+    c = np.array([[i, j, k] for i in (0, 1) for j in (0, 1) for k in (0, 1)], dtype=float)
+    e, f, pot = orc.cutoff(c, np.ones(8), 1.6, ke=1.0)
+    assert e == pytest.approx(12 + 12 / math.sqrt(2), rel=1e-14)
+    # every corner sees 3 edges and 3 face diagonals
+    np.testing.assert_allclose(pot, 3 + 3 / math.sqrt(2), rtol=1e-14)
+    # corner (0,0,0): edge pushes of 1 along -x, -y, -z and face-diagonal
+    # pushes of 1/2 along each of its two axes (1/r^2 times the unit vector)
+    fe = 1.0 + 2 * (1 / 2) * (1 / math.sqrt(2))
+    np.testing.assert_allclose(f[0], [-fe, -fe, -fe], rtol=1e-14)
+    # cutoff below the edge length: nothing interacts
+    e0, f0, p0 = orc.cutoff(c, np.ones(8), 0.99, ke=1.0)
+    assert e0 == 0.0 and not f0.any() and not p0.any()
+    # cutoff beyond the diagonal: all 28 pairs
+    e3, _, _ = orc.cutoff(c, np.ones(8), 1.75, ke=1.0)
+    assert e3 == pytest.approx(12 + 12 / math.sqrt(2) + 4 / math.sqrt(3), rel=1e-14)
+
+
+def test_cutoff_molecule_exclusion_closed_form(orc):
+    # two water-like triples; pairs inside a triple are left out, so the energy
+    # is the nine intermolecular terms, here written out one by one
+    x = np.array([[0.0, 0.0, 0.0], [0.1, 0.0, 0.0], [0.0, 0.1, 0.0],
+                  [0.4, 0.0, 0.0], [0.5, 0.0, 0.0], [0.4, 0.1, 0.0]])
+    q = np.array([-0.8, 0.4, 0.4, -0.8, 0.4, 0.4])
+    mol = np.array([0, 0, 0, 1, 1, 1])
+    e, _, pot = orc.cutoff(x, q, 1.0, ke=1.0, molid=mol)
+    ref = 0.0
+    for i in range(3):
+        for j in range(3, 6):
+            ref += q[i] * q[j] / np.linalg.norm(x[i] - x[j])
+    assert e == pytest.approx(ref, rel=1e-14)
+    ref0 = sum(q[j] / np.linalg.norm(x[0] - x[j]) for j in range(3, 6))
+    assert pot[0] == pytest.approx(ref0, rel=1e-14)
+
+
+def test_cutoff_gradients_newton_and_euler(orc):
+    w = uniform_pm(300, 3.0, seed=8)
+    rc = 0.9
+    e, f, pot = orc.cutoff(w.xyz, w.q, rc, ke=1.0)
+    # Newton's third law pair by pair: zero net force
+    np.testing.assert_allclose(f.sum(0), 0, atol=1e-10 * np.abs(f).max())
+    # U = 1/2 sum q phi (bilinear in q)
+    assert e == pytest.approx(0.5 * (w.q * pot).sum(), rel=1e-13)
+    # F = -dU/dr by central differences, for atoms with no pair within 3 delta of the cutoff
+    delta = 1e-5
+    d = np.linalg.norm(w.xyz[:, None, :] - w.xyz[None, :, :], axis=-1)
+    clear = [i for i in range(w.n) if np.all(np.abs(d[i] - rc) > 3 * delta)]
+    for i in clear[:4]:
+        for c in range(3):
+            xp, xm = w.xyz.copy(), w.xyz.copy()
+            xp[i, c] += delta
+            xm[i, c] -= delta
+            fd = -(orc.cutoff(xp, w.q, rc, ke=1.0)[0] - orc.cutoff(xm, w.q, rc, ke=1.0)[0]) / (2 * delta)
+            assert f[i, c] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+    # phi_i = dU/dq_i exactly (U is quadratic in q)
+    i = clear[0]
+    qp, qm = w.q.copy(), w.q.copy()
+    qp[i] += 0.5
+    qm[i] -= 0.5
+    fd = (orc.cutoff(w.xyz, qp, rc, ke=1.0)[0] - orc.cutoff(w.xyz, qm, rc, ke=1.0)[0]) / 1.0
+    assert pot[i] == pytest.approx(fd, rel=1e-12)
+
+
+def test_cutoff_beyond_the_box_is_exact_coulomb(orc):
+    w = uniform_pm(150, 2.0, seed=9)
+    ec, fc, pc = orc.coulomb(w.xyz, w.q, ke=1.0)
+    e, f, p = orc.cutoff(w.xyz, w.q, 4.0, ke=1.0)
+    assert e == pytest.approx(ec, rel=1e-13)
+    np.testing.assert_allclose(f, fc, rtol=1e-12, atol=1e-12 * np.abs(fc).max())
+    np.testing.assert_allclose(p, pc, rtol=1e-12, atol=1e-12 * np.abs(pc).max())
