@@ -217,8 +217,9 @@ def bench_parareal(torch, msmx, slices, n_atoms=99999):
     """Parareal time-to-solution (Section 4) on the water box: `slices` slices
     of 10 velocity-Verlet steps of 2 fs with the fine MSM (a = 1.2, h = 0.25)
     against serial fine on the same GPU, for the configured coarse propagator
-    (one 20 fs step with a = 0.8, h = 0.5) and a stable one (10 steps of 2 fs
-    with a = 0.8, h = 0.5)."""
+    (one 20 fs step with a = 0.8, h = 0.5), a stable MSM one (10 steps of 2 fs
+    with a = 0.8, h = 0.5) and the paper's choice, the simple cutoff method
+    at 1.2 nm with 10 steps of 2 fs."""
     from workloads import rigid_water_velocities, water_box, water_box_dims, water_model_arrays
     dev = torch.device("cuda", 0)
     n_mol, sites, box = water_box_dims(n_atoms)
@@ -231,14 +232,13 @@ def bench_parareal(torch, msmx, slices, n_atoms=99999):
     mol_t = torch.tensor(molid, dtype=torch.int32, device=dev)
     lj_t = torch.tensor(lj, dtype=torch.float64, device=dev)
 
-    def ctx(a, h, ma, ms):
-        c = msmx.MsmContext(a, h, w.lo, w.hi, precision="fp32", max_atoms=ma, max_systems=ms)
+    def ctx(a, h, ma, ms, method="msm"):
+        c = msmx.MsmContext(a, h, w.lo, w.hi, precision="fp32", max_atoms=ma, max_systems=ms, method=method)
         c.bind_model(w.n, mol_t, lj_t, rigid=True, tri=tri)
         c.set_graphs(True)
         return c
 
     fine = ctx(1.2, 0.25, slices * w.n, slices)
-    coarse = ctx(0.8, 0.5, w.n, 1)
     q = torch.tensor(w.q, device=dev)
     invm = torch.tensor(1.0 / mass, device=dev)
     s0 = torch.tensor(np.concatenate([xyz, v], 1), device=dev).contiguous()
@@ -255,8 +255,26 @@ def bench_parareal(torch, msmx, slices, n_atoms=99999):
     serial.check()
     out = {"workload": f"{slices} slices x {w.n} atoms, rigid water at 300 K, fine 10 x 2 fs (a 1.2, h 0.25)",
            "serial_fine_seconds": serial_s}
-    for name, sg, dtg in (("coarse_1x20fs", 1, 0.020), ("coarse_10x2fs", 10, 0.002)):
-        rec = {"coarse": f"{sg} x {dtg * 1000:g} fs, a 0.8, h 0.5"}
+    # coarse propagators: the configured one (MSM, one 20 fs step), a stable MSM
+    # one, and the paper's choice: the simple cutoff method at 1.2 nm with the
+    # fine step (Section 4)
+    variants = (("coarse_1x20fs", "msm", 0.8, 0.5, 1, 0.020, "MSM a 0.8, h 0.5"),
+                ("coarse_10x2fs", "msm", 0.8, 0.5, 10, 0.002, "MSM a 0.8, h 0.5"),
+                ("coarse_cutoff_10x2fs", "cutoff", 1.2, 0.25, 10, 0.002, "simple cutoff 1.2 nm"))
+    for name, method, a, h, sg, dtg, desc in variants:
+        coarse = ctx(a, h, w.n, 1, method)
+        rec = {"coarse": f"{sg} x {dtg * 1000:g} fs, {desc}"}
+        # cost of one coarse step against one fine step on one slice
+        xg, vg = x.clone(), vv.clone()
+        coarse.vv_run(xg, vg, 2, dtg, energies=False)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        coarse.vv_run(xg, vg, 20, dtg, energies=False)
+        torch.cuda.synchronize()
+        rec["coarse_step_ms"] = (time.perf_counter() - t1) / 20 * 1e3
+        st = coarse.status()     # reads and clears the status word
+        if st:
+            rec["coarse_alone_22_steps"] = msmx.status_string(st)
         try:
             lam, rep, rc = msmx.parareal(fine, coarse, q, invm, s0, nslices=slices, kmax=slices, tol=1e-4,
                                          steps_f=10, dt_f=0.002, steps_g=sg, dt_g=dtg)
@@ -268,6 +286,8 @@ def bench_parareal(torch, msmx, slices, n_atoms=99999):
         except msmx.MsmError as e:
             rec.update({"status": f"failed: {e}"})
         out[name] = rec
+        del coarse
+    out["fine_step_ms"] = serial_s / (slices * 10) * 1e3
     return out
 
 

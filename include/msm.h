@@ -50,6 +50,13 @@ enum {
 
 enum { MSM_FP64 = 0, MSM_FP32 = 1 };
 
+/* How the Coulomb interaction is evaluated. MSM_METHOD_MSM: multilevel
+ * summation (Section 3). MSM_METHOD_CUTOFF: the simple cutoff method the
+ * paper chooses for the coarse parareal propagator (Section 4): Coulomb's law
+ * between the pairs closer than a and nothing beyond; no grids are built,
+ * h is only the edge of the cells of the pair search and levels is ignored. */
+enum { MSM_METHOD_MSM = 0, MSM_METHOD_CUTOFF = 1 };
+
 typedef struct msm_ctx msm_ctx;   /* opaque; owned by the library */
 
 /* Method parameters (Section 3): cutoff a, finest spacing h, number of grids
@@ -66,6 +73,7 @@ typedef struct {
     double coulomb_k;      /* prefactor of the potential */
     int64_t max_atoms;     /* capacity: atoms summed over a batch */
     int max_systems;       /* capacity: systems per batch */
+    int method;            /* MSM_METHOD_MSM or MSM_METHOD_CUTOFF */
 } msm_params;
 
 /* Create a context: validates the parameters, builds the stencil weights and
@@ -94,7 +102,8 @@ int msm_set_stream(msm_ctx *ctx, void *stream);
  *  xyzq_dev       N x 4 (x, y, z, q), float or double per the precision.
  *  energy_dev     nsys doubles: U = 1/2 sum_i q_i phi_i per system, where phi_i
  *                 excludes the atom's own charge (the smooth self term
- *                 q_i gamma(0)/a is removed). May be NULL.
+ *                 q_i gamma(0)/a is removed). May be NULL. With
+ *                 MSM_METHOD_CUTOFF, phi_i = k sum_{j != i, r_ij < a} q_j / r_ij.
  *  forces_dev     N x 3, F_i = -dU/dr_i. May be NULL.
  *  potentials_dev N, phi_i = dU/dq_i. May be NULL.
  * Outputs are in the caller's atom order. Results for a system with an atom
@@ -220,8 +229,11 @@ typedef struct {
  * with F and G velocity Verlet on the fine and coarse context. The fine
  * propagator of all slices that are not yet exact runs as one batch of
  * systems; the coarse sweep is serial. The correction and the iterates are
- * FP64. After k iterations slices 0..k equal the serial fine trajectory
- * bitwise.
+ * FP64. When both contexts hold rigid triples, each corrected state is
+ * projected back onto the constraints (positions along their own bond
+ * vectors, then velocities, with the fine model's tolerance); states that
+ * satisfy them already, as every propagator output does, are unchanged.
+ * After k iterations slices 0..k equal the serial fine trajectory bitwise.
  *  charges_dev, invmass_dev  natoms doubles;
  *  state0_dev                natoms x 6 (x y z vx vy vz);
  *  lambda_dev                (nslices+1) x natoms x 6, out: every slice.

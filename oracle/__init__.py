@@ -26,6 +26,7 @@ from .loader import (  # noqa: F401
     msm,
     coulomb,
     cutoff,
+    cutoff_subset,
     short_subset,
     threads,
     OracleModel,

@@ -82,6 +82,9 @@ def lib():
             L.orc_cutoff.restype = C.c_int
             L.orc_cutoff.argtypes = [C.c_int64, _dp, _dp, C.POINTER(C.c_int32), C.c_double, C.c_double, _dp, _dp,
                                      _dp]
+            L.orc_cutoff_subset.restype = C.c_int
+            L.orc_cutoff_subset.argtypes = [C.c_int64, _dp, _dp, C.POINTER(C.c_int32), C.c_double, C.c_double,
+                                            C.c_int64, C.POINTER(C.c_int64), _dp, _dp]
             _lib = L
         return _lib
 
@@ -222,6 +225,24 @@ def cutoff(xyz, q, rc, ke: float = 138.935458, molid=None):
     if rc_ != 0:
         raise RuntimeError(f"oracle cutoff failed with code {rc_}")
     return float(e[0]), f, pot
+
+
+def cutoff_subset(xyz, q, rc, sel, ke: float = 138.935458, molid=None):
+    """Forces (len(sel), 3) and potentials of ``cutoff`` for the atoms in
+    ``sel``, each by a direct loop over all atoms."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+    sel = np.ascontiguousarray(sel, dtype=np.int64)
+    mol = None if molid is None else np.ascontiguousarray(molid, dtype=np.int32)
+    f = np.zeros((sel.shape[0], 3))
+    pot = np.zeros(sel.shape[0])
+    rc_ = lib().orc_cutoff_subset(xyz.shape[0], _ptr(xyz), _ptr(q),
+                                  None if mol is None else mol.ctypes.data_as(C.POINTER(C.c_int32)), float(rc),
+                                  float(ke), sel.shape[0], sel.ctypes.data_as(C.POINTER(C.c_int64)), _ptr(f),
+                                  _ptr(pot))
+    if rc_ != 0:
+        raise RuntimeError(f"oracle cutoff_subset failed with code {rc_}")
+    return f, pot
 
 
 # ---------------------------------------------------------------------------

@@ -14,7 +14,8 @@
  * Section 4) with the pairs inside one molecule excluded, and Lennard-Jones
  * with Lorentz-Berthelot mixing, cut and shifted at the cutoff a.
  * Parareal follows Section 4: lambda_{n+1}^{k+1} = G(lambda_n^{k+1}) +
- * F(lambda_n^k) - G(lambda_n^k), started from a coarse sweep.
+ * F(lambda_n^k) - G(lambda_n^k), started from a coarse sweep; for rigid
+ * molecules each corrected state is projected back onto the constraints.
  */
 #include "md_oracle.h"
 
@@ -247,6 +248,62 @@ int orc_vv(const orc_params *p, const orc_model *m, int64_t n, double *xyz, doub
 }
 
 /* ---- Section 4: parareal ---- */
+
+/* Project a corrected state (n x 6) of rigid triples back onto the
+ * constraints (a reading; the paper is silent on constraints): positions move
+ * along their own bond vectors until every bond has its length, then
+ * velocities lose their relative component along every bond. A state that
+ * already satisfies the constraints is left unchanged. */
+static void project_triples(const orc_model *m, int64_t n, double *st)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t t = 0; t < n / 3; t++) {
+        for (int it = 0; it < 1000; it++) {
+            int done = 1;
+            for (int c = 0; c < 3; c++) {
+                int64_t a = 3 * t + tri_a[c], b = 3 * t + tri_b[c];
+                double d = m->tri[c];
+                double s[3], ss = 0;
+                for (int k = 0; k < 3; k++) {
+                    s[k] = st[6 * a + k] - st[6 * b + k];
+                    ss += s[k] * s[k];
+                }
+                double diff = d * d - ss;
+                if (fabs(diff) <= 2.0 * m->tol * d * d) continue;
+                done = 0;
+                double ia = 1.0 / m->mass[a], ib = 1.0 / m->mass[b];
+                double g = diff / (2.0 * ss * (ia + ib));
+                for (int k = 0; k < 3; k++) {
+                    st[6 * a + k] += g * ia * s[k];
+                    st[6 * b + k] -= g * ib * s[k];
+                }
+            }
+            if (done) break;
+        }
+        for (int it = 0; it < 1000; it++) {
+            int done = 1;
+            for (int c = 0; c < 3; c++) {
+                int64_t a = 3 * t + tri_a[c], b = 3 * t + tri_b[c];
+                double d = m->tri[c];
+                double r[3], w[3], rw = 0;
+                for (int k = 0; k < 3; k++) {
+                    r[k] = st[6 * a + k] - st[6 * b + k];
+                    w[k] = st[6 * a + 3 + k] - st[6 * b + 3 + k];
+                    rw += r[k] * w[k];
+                }
+                if (fabs(rw) <= m->tol * d * d) continue;
+                done = 0;
+                double ia = 1.0 / m->mass[a], ib = 1.0 / m->mass[b];
+                double kk = rw / ((ia + ib) * d * d);
+                for (int k = 0; k < 3; k++) {
+                    st[6 * a + 3 + k] -= kk * ia * r[k];
+                    st[6 * b + 3 + k] += kk * ib * r[k];
+                }
+            }
+            if (done) break;
+        }
+    }
+}
 static int propagate(const orc_params *p, const orc_model *m, int64_t n, const double *q, const double *in,
                      double *out, int steps, double dt, double *x, double *v)
 {
@@ -273,6 +330,7 @@ int orc_parareal(const orc_params *pf, const orc_params *pg, const orc_model *m,
     double *gold = malloc(sizeof(double) * S * (nslices + 1));
     double *fout = malloc(sizeof(double) * S * (nslices + 1));
     double *gnew = malloc(sizeof(double) * S);
+    double *corr = malloc(sizeof(double) * S);
     double *x = malloc(sizeof(double) * 3 * (n > 0 ? n : 1)), *v = malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
     int rc = 0, done = 0;
     memcpy(lambda, state0, sizeof(double) * S);
@@ -292,13 +350,17 @@ int orc_parareal(const orc_params *pf, const orc_params *pg, const orc_model *m,
             rc = propagate(pg, m, n, q, lambda + S * s, gnew, steps_g, dt_g, x, v);
             double *lam = lambda + S * (s + 1), *fo = fout + S * (s + 1), *go = gold + S * (s + 1);
             for (size_t e = 0; e < S; e++) {
-                double nv = fo[e] + (gnew[e] - go[e]);
+                corr[e] = fo[e] + (gnew[e] - go[e]);
+                go[e] = gnew[e];
+            }
+            if (m->rigid) project_triples(m, n, corr);
+            for (size_t e = 0; e < S; e++) {
                 if (e % 6 < 3) {
-                    double c = fabs(nv - lam[e]);
+                    double c = fabs(corr[e] - lam[e]);
+                    if (c != c) c = INFINITY;
                     if (c > change) change = c;
                 }
-                lam[e] = nv;
-                go[e] = gnew[e];
+                lam[e] = corr[e];
             }
         }
         resid[k] = change;
@@ -308,6 +370,7 @@ int orc_parareal(const orc_params *pf, const orc_params *pg, const orc_model *m,
     free(gold);
     free(fout);
     free(gnew);
+    free(corr);
     free(x);
     free(v);
     if (rc) return rc;

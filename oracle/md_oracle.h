@@ -33,7 +33,9 @@ int orc_vv(const orc_params *p, const orc_model *m, int64_t n, double *xyz, doub
            double dt, int nsteps, double *epot, double *ekin);
 
 /* Parareal (Section 4) over nslices slices of the fine propagator
- * (pf, steps_f x dt_f) with the coarse one (pg, steps_g x dt_g).
+ * (pf, steps_f x dt_f) with the coarse one (pg, steps_g x dt_g). With rigid
+ * triples every corrected state is projected back onto the constraints
+ * (positions along their bond vectors, then velocities).
  * state0: n x 6 (x y z vx vy vz). lambda: (nslices+1) x n x 6, out.
  * Stops at the first iteration whose largest position change is below tol
  * or after kmax iterations; *iters receives the number done and resid[k]

@@ -552,3 +552,33 @@ int orc_cutoff(int64_t n, const double *xyz, const double *q, const int32_t *mol
     free(phi);
     return 0;
 }
+
+int orc_cutoff_subset(int64_t n, const double *xyz, const double *q, const int32_t *molid, double rc, double ke,
+                      int64_t nsel, const int64_t *sel, double *forces, double *pot)
+{
+    if (n < 0 || nsel < 0 || !(rc > 0) || (nsel > 0 && (!xyz || !q || !sel))) return -1;
+#pragma omp parallel for schedule(dynamic, 4)
+    for (int64_t s = 0; s < nsel; s++) {
+        const int64_t i = sel[s];
+        double u = 0, fx = 0, fy = 0, fz = 0;
+        if (i < 0 || i >= n) continue;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i || (molid && molid[j] == molid[i])) continue;
+            double rx = xyz[3 * i] - xyz[3 * j], ry = xyz[3 * i + 1] - xyz[3 * j + 1],
+                   rz = xyz[3 * i + 2] - xyz[3 * j + 2];
+            double r = sqrt(rx * rx + ry * ry + rz * rz);
+            if (!(r < rc)) continue;
+            u += q[j] / r;
+            fx += q[j] * rx / (r * r * r);
+            fy += q[j] * ry / (r * r * r);
+            fz += q[j] * rz / (r * r * r);
+        }
+        if (pot) pot[s] = ke * u;
+        if (forces) {
+            forces[3 * s] = ke * q[i] * fx;
+            forces[3 * s + 1] = ke * q[i] * fy;
+            forces[3 * s + 2] = ke * q[i] * fz;
+        }
+    }
+    return 0;
+}

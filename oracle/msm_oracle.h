@@ -75,4 +75,9 @@ int orc_coulomb(int64_t n, const double *xyz, const double *q, double ke,
 int orc_cutoff(int64_t n, const double *xyz, const double *q, const int32_t *molid, double rc, double ke,
                double *energy, double *forces, double *pot);
 
+/* The potentials and forces of orc_cutoff for the atoms listed in sel only,
+ * each by a direct loop over all atoms (spot checks of very large systems). */
+int orc_cutoff_subset(int64_t n, const double *xyz, const double *q, const int32_t *molid, double rc, double ke,
+                      int64_t nsel, const int64_t *sel, double *forces, double *pot);
+
 #endif

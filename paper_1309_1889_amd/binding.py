@@ -42,10 +42,13 @@ class _Tuning(C.Structure):
     _fields_ = [("pair_waves", C.c_int), ("stencil_threads", C.c_int)]
 
 
+METHODS = {"msm": 0, "cutoff": 1}
+
+
 class _Params(C.Structure):
     _fields_ = [("a", C.c_double), ("h", C.c_double), ("levels", C.c_int), ("precision", C.c_int),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("coulomb_k", C.c_double),
-                ("max_atoms", C.c_int64), ("max_systems", C.c_int)]
+                ("max_atoms", C.c_int64), ("max_systems", C.c_int), ("method", C.c_int)]
 
 
 def lib_path() -> str:
@@ -129,12 +132,17 @@ class MsmContext:
 
     a, h: cutoff and finest grid spacing (nm); lo, hi: domain corners;
     levels: number of grids (0 = from the domain); precision: "fp32" or
-    "fp64"; ke: Coulomb prefactor; max_atoms / max_systems: batch capacity.
+    "fp64"; ke: Coulomb prefactor; max_atoms / max_systems: batch capacity;
+    method: "msm", or "cutoff" for the simple cutoff method at a (Section 4's
+    coarse propagator; h is then only the cell edge of the pair search).
     """
 
     def __init__(self, a, h, lo, hi, *, levels=0, precision="fp32", ke=138.935458,
-                 max_atoms=1 << 20, max_systems=1, stream=None):
+                 max_atoms=1 << 20, max_systems=1, stream=None, method="msm"):
         import torch
+        if method not in METHODS:
+            raise ValueError(f"method must be one of {sorted(METHODS)}")
+        self.method = method
         self.precision = precision
         self.dtype = torch.float32 if precision == "fp32" else torch.float64
         p = _Params()
@@ -146,6 +154,7 @@ class MsmContext:
         p.coulomb_k = float(ke)
         p.max_atoms = int(max_atoms)
         p.max_systems = int(max_systems)
+        p.method = METHODS[method]
         self.params = p
         self.a, self.h, self.ke = float(a), float(h), float(ke)
         self.lo = tuple(float(v) for v in lo)

@@ -48,6 +48,10 @@ int geometry(const msm_params &prm, const double *lo, const double *hi, Geometry
         if (ncd > 1 << 20) return MSM_ERR_CAPACITY;
         g.nc[d] = (int)ncd;
     }
+    if (prm.method == MSM_METHOD_CUTOFF) {   // no grids: cells for the pair search only
+        g.nlev = 0;
+        return MSM_OK;
+    }
     g.nlev = prm.levels > 0 ? prm.levels : auto_levels(prm.h, len);
     if (g.nlev < 1 || g.nlev > kMaxLevels) return MSM_ERR_UNSUPPORTED;
     for (int d = 0; d < 3; d++) {
@@ -171,7 +175,7 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
         iblk_p[s] = iblk;
         top_p[s] = top;
         ant_p[s] = ant;
-        ant += anterp_tiles(g.gdim[0][0], g.gdim[0][1], g.gdim[0][2]);
+        if (g.nlev > 0) ant += anterp_tiles(g.gdim[0][0], g.gdim[0][1], g.gdim[0][2]);
         for (int k = 0; k < kMaxLevels; k++) node_p[(size_t)k * W + s] = nodes[k];
         for (int k = 0; k < g.nlev; k++) {
             P.qoff[k] = q;
@@ -181,6 +185,10 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
             u += round_up(n, 64);
             nodes[k] += n;
         }
+        cells += P.ncells;
+        groups += P.ngroups;
+        iblk += (P.natoms + 255) / 256;
+        if (g.nlev == 0) continue;   // simple cutoff method: no grids
         const int kt = g.nlev - 1;
         // levels from kc on are small enough for one workgroup (restriction and
         // prolongation chains); a small top level is evaluated there too
@@ -198,9 +206,6 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
         int d2 = 0;
         for (int d = 0; d < 3; d++) d2 += (g.gdim[kt][d] - 1) * (g.gdim[kt][d] - 1);
         top_d2 = std::max(top_d2, d2);
-        cells += P.ncells;
-        groups += P.ngroups;
-        iblk += (P.natoms + 255) / 256;
     }
     atom_p[nsys] = offsets[nsys];
     group_p[nsys] = groups;
@@ -489,9 +494,11 @@ int msm_setup(const msm_params *prm, void *stream, msm_ctx **out)
     if (prm->max_atoms < 0 || prm->max_atoms >= ((int64_t)1 << 31) || prm->max_systems < 1) return MSM_ERR_ARG;
     if (prm->levels < 0 || prm->levels > kMaxLevels) return MSM_ERR_ARG;
     if (!std::isfinite(prm->coulomb_k)) return MSM_ERR_ARG;
+    if (prm->method != MSM_METHOD_MSM && prm->method != MSM_METHOD_CUTOFF) return MSM_ERR_ARG;
+    const bool cutoff = prm->method == MSM_METHOD_CUTOFF;
     const double ratio = 2.0 * prm->a / prm->h;
     const int reach = (int)std::ceil(ratio) - 1;       // largest integer below 2a/h
-    if (reach < 1 || reach > kMaxReach - 1) return MSM_ERR_UNSUPPORTED;
+    if (!cutoff && (reach < 1 || reach > kMaxReach - 1)) return MSM_ERR_UNSUPPORTED;
 
     msm_ctx *c = new (std::nothrow) msm_ctx();
     if (!c) return MSM_ERR_ARG;
@@ -504,7 +511,8 @@ int msm_setup(const msm_params *prm, void *stream, msm_ctx **out)
     c->mc.a = prm->a;
     c->mc.h = prm->h;
     c->mc.ke = prm->coulomb_k;
-    c->mc.reach = reach;
+    c->mc.cutoff = cutoff ? 1 : 0;
+    c->mc.reach = cutoff ? 0 : reach;
     c->mc.pair_waves = 8;
     c->mc.stencil_threads = 1024;
     c->d2max = (int)std::ceil(ratio * ratio) - 1;      // largest integer below (2a/h)^2
@@ -539,7 +547,7 @@ int msm_setup(const msm_params *prm, void *stream, msm_ctx **out)
         msm_destroy(c);
         return MSM_ERR_HIP;
     }
-    rc = prm->precision == MSM_FP32 ? upload_stencil<float>(c) : upload_stencil<double>(c);
+    if (!cutoff) rc = prm->precision == MSM_FP32 ? upload_stencil<float>(c) : upload_stencil<double>(c);
     if (rc) {
         msm_destroy(c);
         return rc;

@@ -70,6 +70,7 @@ int stencil_tile_z(int elem_bytes, int reach);
 
 struct MethodConst {
     double a, h, ke;
+    int cutoff;                // 1: simple cutoff method (plain Coulomb below a, no grids)
     int reach;                 // stencil reach R: largest integer with R < 2a/h
     int pair_waves;            // waves per 64-atom group in the pair kernel: 4, 8 or 16
     int stencil_threads;       // threads per stencil tile: 256 or 1024

@@ -31,6 +31,10 @@ hipError_t md_state_out(hipStream_t s, int64_t count, const double4 *x, const do
 hipError_t reduce_blocks(hipStream_t s, const DevPlan &p, const double *parts, double *out, double scale);
 hipError_t parareal_correct(hipStream_t s, int64_t count6, double *lam, const double *fout, const double *gnew,
                             double *gold, unsigned long long *change);
+// The correction for rigid triples (natoms a multiple of 3), followed by the
+// projection of each corrected triple back onto its constraints.
+hipError_t parareal_correct_rigid(hipStream_t s, int64_t natoms, double *lam, const double *fout, const double *gnew,
+                                  double *gold, const double *invm, const TriModel &tm, unsigned long long *change);
 hipError_t copy_f64(hipStream_t s, const double *src, double *dst, int64_t n);
 hipError_t zero_u64(hipStream_t s, unsigned long long *p);
 

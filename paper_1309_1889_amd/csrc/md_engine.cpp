@@ -200,6 +200,8 @@ int parareal_run(msm_ctx *fine, msm_ctx *coarse, const parareal_params *pp, int6
         return MSM_ERR_ARG;
     if (!fine->md_bound || !coarse->md_bound || fine->stream != coarse->stream) return MSM_ERR_ARG;
     if ((fine->rigid || coarse->rigid) && n % 3) return MSM_ERR_ARG;
+    // rigid triples: the corrected states are projected back onto the constraints
+    const bool rigid = fine->rigid && coarse->rigid;
     if (fine->prm.max_atoms < (int64_t)S * n || fine->prm.max_systems < S || coarse->prm.max_atoms < n)
         return MSM_ERR_CAPACITY;
     std::memset(rep, 0, sizeof(*rep));
@@ -232,9 +234,13 @@ int parareal_run(msm_ctx *fine, msm_ctx *coarse, const parareal_params *pp, int6
         // serial coarse sweep with the correction
         for (int i = k; i < S && !rc; i++) {
             rc = propagate(coarse, n, 1, q, invm, slot(lambda, i), fine->gnew, pp->steps_g, pp->dt_g);
-            if (!rc && parareal_correct(s, N6, slot(lambda, i + 1), slot(fine->fout, i), fine->gnew,
-                                        slot(fine->gold, i), change) != hipSuccess)
-                rc = MSM_ERR_HIP;
+            if (rc) break;
+            const hipError_t e =
+                rigid ? parareal_correct_rigid(s, n, slot(lambda, i + 1), slot(fine->fout, i), fine->gnew,
+                                               slot(fine->gold, i), invm, fine->tri, change)
+                      : parareal_correct(s, N6, slot(lambda, i + 1), slot(fine->fout, i), fine->gnew,
+                                         slot(fine->gold, i), change);
+            if (e != hipSuccess) rc = MSM_ERR_HIP;
         }
         if (rc) break;
         unsigned long long bits = 0;

@@ -26,6 +26,41 @@ template <typename T> __device__ inline T dot(V3<T> a, V3<T> b) { return a.x * b
 __constant__ int kTriA[3] = {0, 0, 1};
 __constant__ int kTriB[3] = {1, 2, 2};
 
+// Bond c of a triple: s = r_a - r_b and the squared-length residual
+// diff = len^2 - |s|^2; true when |diff| is within the tolerance. One
+// function for every constraint test, so that a state one stage accepted is
+// accepted by every other stage too.
+__device__ inline bool bond_within(const V3<double> r[3], int c, const TriModel &tm, V3<double> &s, double &diff)
+{
+    const double d2 = tm.len[c] * tm.len[c];
+    s = sub(r[kTriA[c]], r[kTriB[c]]);
+    diff = d2 - dot(s, s);
+    return fabs(diff) <= 2.0 * tm.tol * d2;
+}
+
+// RATTLE's velocity stage: remove the relative velocity along every bond.
+__device__ inline void constrain_velocities(const V3<double> r[3], V3<double> vel[3], const double im[3],
+                                            const TriModel &tm)
+{
+    for (int it = 0; it < tm.max_iter; it++) {
+        bool done = true;
+        for (int c = 0; c < 3; c++) {
+            const int a = kTriA[c], b = kTriB[c];
+            const double d2 = tm.len[c] * tm.len[c];
+            const V3<double> rr = sub(r[a], r[b]);
+            const V3<double> w = sub(vel[a], vel[b]);
+            const double rw = dot(rr, w);
+            if (fabs(rw) <= tm.tol * d2) continue;
+            done = false;
+            const double kk = rw / ((im[a] + im[b]) * d2);
+            const double ka = kk * im[a], kb = kk * im[b];
+            vel[a] = {vel[a].x - ka * rr.x, vel[a].y - ka * rr.y, vel[a].z - ka * rr.z};
+            vel[b] = {vel[b].x + kb * rr.x, vel[b].y + kb * rr.y, vel[b].z + kb * rr.z};
+        }
+        if (done) break;
+    }
+}
+
 // Half kick and drift of one atom (no constraints). The state is FP64; the
 // forces come in the evaluation precision T; `xe` (may be null) receives the
 // new positions and charges in T for the next force evaluation.
@@ -82,11 +117,10 @@ __global__ void k_kick_drift_rattle(int64_t ntri, double4 *__restrict__ x, doubl
         bool done = true;
         for (int c = 0; c < 3; c++) {
             const int a = kTriA[c], b = kTriB[c];
-            const double d2 = tm.len[c] * tm.len[c];
-            const V3<double> s = sub(r[a], r[b]);
+            V3<double> s;
+            double diff;
+            if (bond_within(r, c, tm, s, diff)) continue;
             const V3<double> ro = sub(old[a], old[b]);
-            const double diff = d2 - dot(s, s);
-            if (fabs(diff) <= 2.0 * tm.tol * d2) continue;
             done = false;
             const double g = diff / (2.0 * dot(s, ro) * (im[a] + im[b]));
             const double ga = g * im[a], gb = g * im[b];
@@ -143,23 +177,7 @@ __global__ void k_kick_rattle(int64_t ntri, const double4 *__restrict__ x, doubl
         vel[a] = {vi.x + h * (double)f[3 * i], vi.y + h * (double)f[3 * i + 1], vi.z + h * (double)f[3 * i + 2]};
         r[a] = {xi.x, xi.y, xi.z};
     }
-    for (int it = 0; it < tm.max_iter; it++) {
-        bool done = true;
-        for (int c = 0; c < 3; c++) {
-            const int a = kTriA[c], b = kTriB[c];
-            const double d2 = tm.len[c] * tm.len[c];
-            const V3<double> rr = sub(r[a], r[b]);
-            const V3<double> w = sub(vel[a], vel[b]);
-            const double rw = dot(rr, w);
-            if (fabs(rw) <= tm.tol * d2) continue;
-            done = false;
-            const double kk = rw / ((im[a] + im[b]) * d2);
-            const double ka = kk * im[a], kb = kk * im[b];
-            vel[a] = {vel[a].x - ka * rr.x, vel[a].y - ka * rr.y, vel[a].z - ka * rr.z};
-            vel[b] = {vel[b].x + kb * rr.x, vel[b].y + kb * rr.y, vel[b].z + kb * rr.z};
-        }
-        if (done) break;
-    }
+    constrain_velocities(r, vel, im, tm);
     for (int a = 0; a < 3; a++) v[3 * t + a] = make_double4(vel[a].x, vel[a].y, vel[a].z, im[a]);
 }
 
@@ -256,6 +274,75 @@ __global__ __launch_bounds__(256) void k_correct(int64_t count6, double *__restr
     if (threadIdx.x == 0) atomicMax(change, (unsigned long long)__double_as_longlong(red[0]));
 }
 
+// The same correction for rigid triples (a reading: Section 4 is silent on
+// constraints). A linear combination of three constrained states is not
+// constrained, and molecules bent by it can stop the next propagator's
+// constraint iteration from converging, so the corrected state of each triple
+// is projected back: positions along their own bond vectors until every bond
+// has its length, then velocities by RATTLE's velocity stage. A state that
+// already satisfies the constraints (any propagator output, so every slice
+// that is already exact) passes both tests unchanged.
+__global__ __launch_bounds__(256) void k_correct_rigid(int64_t ntri, double *__restrict__ lam,
+                                                       const double *__restrict__ fout,
+                                                       const double *__restrict__ gnew, double *__restrict__ gold,
+                                                       const double *__restrict__ invm, TriModel tm,
+                                                       unsigned long long *__restrict__ change)
+{
+    __shared__ double red[256];
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    double ch = 0;
+    if (t < ntri) {
+        V3<double> r[3], vel[3];
+        double im[3];
+        for (int a = 0; a < 3; a++) {
+            const int64_t e = 6 * (3 * t + a);
+            double nv[6];
+            for (int c = 0; c < 6; c++) {
+                const double g = gnew[e + c];
+                nv[c] = fout[e + c] + (g - gold[e + c]);
+                gold[e + c] = g;
+            }
+            r[a] = {nv[0], nv[1], nv[2]};
+            vel[a] = {nv[3], nv[4], nv[5]};
+            im[a] = invm[3 * t + a];
+        }
+        for (int it = 0; it < tm.max_iter; it++) {
+            bool done = true;
+            for (int c = 0; c < 3; c++) {
+                const int a = kTriA[c], b = kTriB[c];
+                V3<double> s;
+                double diff;
+                if (bond_within(r, c, tm, s, diff)) continue;
+                done = false;
+                const double g = diff / (2.0 * dot(s, s) * (im[a] + im[b]));
+                const double ga = g * im[a], gb = g * im[b];
+                r[a] = {r[a].x + ga * s.x, r[a].y + ga * s.y, r[a].z + ga * s.z};
+                r[b] = {r[b].x - gb * s.x, r[b].y - gb * s.y, r[b].z - gb * s.z};
+            }
+            if (done) break;
+        }
+        constrain_velocities(r, vel, im, tm);
+        for (int a = 0; a < 3; a++) {
+            double *l = lam + 6 * (3 * t + a);
+            const double rv[3] = {r[a].x, r[a].y, r[a].z}, vv[3] = {vel[a].x, vel[a].y, vel[a].z};
+            for (int c = 0; c < 3; c++) {
+                double d = fabs(rv[c] - l[c]);
+                if (!(d == d)) d = __longlong_as_double(0x7ff0000000000000LL);   // NaN -> +inf
+                ch = fmax(ch, d);
+                l[c] = rv[c];
+                l[3 + c] = vv[c];
+            }
+        }
+    }
+    red[threadIdx.x] = ch;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) atomicMax(change, (unsigned long long)__double_as_longlong(red[0]));
+}
+
 __global__ void k_copy_f64(int64_t n, const double *__restrict__ src, double *__restrict__ dst)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -324,6 +411,16 @@ hipError_t parareal_correct(hipStream_t s, int64_t count6, double *lam, const do
 {
     if (count6 == 0) return hipSuccess;
     hipLaunchKernelGGL(k_correct, dim3(nblocks(count6, 256)), dim3(256), 0, s, count6, lam, fout, gnew, gold, change);
+    return hipGetLastError();
+}
+
+hipError_t parareal_correct_rigid(hipStream_t s, int64_t natoms, double *lam, const double *fout, const double *gnew,
+                                  double *gold, const double *invm, const TriModel &tm, unsigned long long *change)
+{
+    const int64_t ntri = natoms / 3;
+    if (ntri == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_correct_rigid, dim3(nblocks(ntri, 256)), dim3(256), 0, s, ntri, lam, fout, gnew, gold, invm,
+                       tm, change);
     return hipGetLastError();
 }
 

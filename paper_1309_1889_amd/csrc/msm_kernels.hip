@@ -824,7 +824,7 @@ __global__ __launch_bounds__(kChainThreads) void k_prolong_chain(DevPlan p, cons
 // ---------------------------------------------------------------------------
 constexpr int kInterpThreads = 256;
 
-template <typename T>
+template <typename T, bool GRID>
 __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                            const vec4_t<T> *__restrict__ shrt,
                                                            const int *__restrict__ order,
@@ -840,36 +840,38 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4
     double e = 0;
     if (pos < P.atom0 + P.natoms) {
         const vec4_t<T> a = sx[pos];
-        const T inv_h = T(P.inv_h);
-        const T t[3] = {(a.x - T(P.lo[0])) * inv_h, (a.y - T(P.lo[1])) * inv_h, (a.z - T(P.lo[2])) * inv_h};
-        T w[3][4], dw[3][4];
-        int base[3];
-        for (int d = 0; d < 3; ++d) {
-            base[d] = cell_floor(t[d], P.nc[d]);
-            for (int m = 0; m < 4; ++m) {
-                const T o = t[d] - T(base[d] - 1 + m);
-                w[d][m] = basis(o);
-                dw[d][m] = dbasis(o) * inv_h;
-            }
-        }
-        const int dx = P.gdim[0][0], dy = P.gdim[0][1];
-        const T *u0 = ugrid + P.uoff[0];
         T ul = 0, gx = 0, gy = 0, gz = 0;
-        for (int mz = 0; mz < 4; ++mz) {
-            for (int my = 0; my < 4; ++my) {
-                const T *row = u0 + ((int64_t)(base[2] - 1 + mz - P.gorg[0][2]) * dy + (base[1] - 1 + my - P.gorg[0][1])) * dx +
-                               (base[0] - 1 - P.gorg[0][0]);
-                T sx0 = 0, sdx = 0;
-                for (int mx = 0; mx < 4; ++mx) {
-                    const T v = row[mx];
-                    sx0 += w[0][mx] * v;
-                    sdx += dw[0][mx] * v;
+        if (GRID) {
+            const T inv_h = T(P.inv_h);
+            const T t[3] = {(a.x - T(P.lo[0])) * inv_h, (a.y - T(P.lo[1])) * inv_h, (a.z - T(P.lo[2])) * inv_h};
+            T w[3][4], dw[3][4];
+            int base[3];
+            for (int d = 0; d < 3; ++d) {
+                base[d] = cell_floor(t[d], P.nc[d]);
+                for (int m = 0; m < 4; ++m) {
+                    const T o = t[d] - T(base[d] - 1 + m);
+                    w[d][m] = basis(o);
+                    dw[d][m] = dbasis(o) * inv_h;
                 }
-                const T wyz = w[1][my] * w[2][mz];
-                ul += wyz * sx0;
-                gx += wyz * sdx;
-                gy += dw[1][my] * w[2][mz] * sx0;
-                gz += w[1][my] * dw[2][mz] * sx0;
+            }
+            const int dx = P.gdim[0][0], dy = P.gdim[0][1];
+            const T *u0 = ugrid + P.uoff[0];
+            for (int mz = 0; mz < 4; ++mz) {
+                for (int my = 0; my < 4; ++my) {
+                    const T *row = u0 + ((int64_t)(base[2] - 1 + mz - P.gorg[0][2]) * dy + (base[1] - 1 + my - P.gorg[0][1])) * dx +
+                                   (base[0] - 1 - P.gorg[0][0]);
+                    T sx0 = 0, sdx = 0;
+                    for (int mx = 0; mx < 4; ++mx) {
+                        const T v = row[mx];
+                        sx0 += w[0][mx] * v;
+                        sdx += dw[0][mx] * v;
+                    }
+                    const T wyz = w[1][my] * w[2][mz];
+                    ul += wyz * sx0;
+                    gx += wyz * sdx;
+                    gy += dw[1][my] * w[2][mz] * sx0;
+                    gz += w[1][my] * dw[2][mz] * sx0;
+                }
             }
         }
         const vec4_t<T> sr = shrt[pos];
@@ -987,6 +989,11 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, co
     // -(d/dr)(gamma(r/a)/a) / r = (5/2 - 3/2 r^2/a^2) / a^3
     k.d0 = T(2.5 / (a * a * a));
     k.d1 = T(-1.5 / (a * a * a * a * a));
+    if (m.cutoff) {
+        // simple cutoff method (Section 4): plain 1/r below a, nothing left
+        // for grids, so the smoothing polynomial is zero
+        k.c0 = k.c1 = k.c2 = k.d0 = k.d1 = T(0);
+    }
     switch (m.pair_waves) {
     case 4: pair_launch<T, 4>(s, p, w, k, pot); break;
     case 8: pair_launch<T, 8>(s, p, w, k, pot); break;
@@ -1090,10 +1097,13 @@ hipError_t Launch<T>::interp(hipStream_t s, const DevPlan &p, const Work<T> &w, 
                              T *potentials)
 {
     if (p.niblk == 0) return hipSuccess;
-    const T self = T(1.875 / m.a);   // gamma(0)/a
-    hipLaunchKernelGGL(k_interp<T>, dim3((unsigned)p.niblk), dim3(kInterpThreads), 0, s, p, w.sxyzq, w.shrt, w.order,
-                       w.ugrid, forces, potentials, w.eparts, T(m.ke), self,
-                       (const vec4_t<T> *)(w.saux ? w.shlj : nullptr));
+    const vec4_t<T> *lj = (const vec4_t<T> *)(w.saux ? w.shlj : nullptr);
+    if (m.cutoff)   // simple cutoff method: no grid potential and no smooth self term
+        hipLaunchKernelGGL((k_interp<T, false>), dim3((unsigned)p.niblk), dim3(kInterpThreads), 0, s, p, w.sxyzq,
+                           w.shrt, w.order, (const T *)nullptr, forces, potentials, w.eparts, T(m.ke), T(0), lj);
+    else
+        hipLaunchKernelGGL((k_interp<T, true>), dim3((unsigned)p.niblk), dim3(kInterpThreads), 0, s, p, w.sxyzq,
+                           w.shrt, w.order, w.ugrid, forces, potentials, w.eparts, T(m.ke), T(1.875 / m.a), lj);
     return hipGetLastError();
 }
 

@@ -139,3 +139,24 @@ def test_cutoff_model_forces_are_cutoff_coulomb_plus_the_same_lennard_jones():
     em, fm = oracle.md_forces(pm, model, w.xyz, w.q)
     assert ec - ec0 == pytest.approx(em - em0, rel=1e-10)
     np.testing.assert_allclose(fc - fc0, fm - fm0, rtol=1e-9, atol=1e-7)
+
+
+def test_parareal_corrected_states_keep_the_rigid_geometry():
+    """The correction of Section 4 adds and subtracts whole states; for rigid
+    molecules each corrected state is projected back, so every iterate has
+    the bond lengths and no relative velocity along any bond (the
+    propagators' own tolerance), however far the coarse propagator is from
+    the fine one (here the simple cutoff method against MSM)."""
+    w, model, v = small_water(64, 1.24, seed=29)
+    kw = dict(lo=tuple(w.lo), hi=tuple(w.hi), levels=0, ke=138.935458)
+    pf = oracle.OracleParams(0.6, 0.25, **kw)
+    pg = oracle.OracleParams(0.6, 0.25, method=oracle.METHOD_CUTOFF, **kw)
+    lam, it, res, rc = oracle.parareal(pf, pg, model, w.xyz, v, w.q, 5, 5, 0.002, 5, 0.002, 1, 0.0)
+    assert it == 1
+    for n in range(6):
+        x = lam[n, :, :3].reshape(-1, 3, 3)
+        u = lam[n, :, 3:].reshape(-1, 3, 3)
+        for (a, b), L in zip([(0, 1), (0, 2), (1, 2)], model.tri):
+            r = x[:, a] - x[:, b]
+            assert np.abs(np.linalg.norm(r, axis=1) - L).max() < 1e-9
+            assert np.abs((r * (u[:, a] - u[:, b])).sum(1)).max() < 1e-9

@@ -444,3 +444,13 @@ def test_cutoff_beyond_the_box_is_exact_coulomb(orc):
     assert e == pytest.approx(ec, rel=1e-13)
     np.testing.assert_allclose(f, fc, rtol=1e-12, atol=1e-12 * np.abs(fc).max())
     np.testing.assert_allclose(p, pc, rtol=1e-12, atol=1e-12 * np.abs(pc).max())
+
+
+def test_cutoff_subset_rows_equal_the_full_evaluation(orc):
+    w = water_box(300, (7, 7, 7), (2.2, 2.2, 2.2), seed=12)
+    mol = np.arange(w.n) // 3
+    _, f, p = orc.cutoff(w.xyz, w.q, 0.7, molid=mol)
+    sel = np.array([0, 5, 77, w.n - 1])
+    fs, ps = orc.cutoff_subset(w.xyz, w.q, 0.7, sel, molid=mol)
+    np.testing.assert_array_equal(fs, f[sel])
+    np.testing.assert_array_equal(ps, p[sel])
