@@ -257,7 +257,7 @@ def bench_parareal(torch, msmx, slices, n_atoms=99999):
            "serial_fine_seconds": serial_s}
     # coarse propagators: the configured one (MSM, one 20 fs step), a stable MSM
     # one, and the paper's choice: the simple cutoff method at 1.2 nm with the
-    # fine step (Section 4)
+    # fine step (Section 5)
     variants = (("coarse_1x20fs", "msm", 0.8, 0.5, 1, 0.020, "MSM a 0.8, h 0.5"),
                 ("coarse_10x2fs", "msm", 0.8, 0.5, 10, 0.002, "MSM a 0.8, h 0.5"),
                 ("coarse_cutoff_10x2fs", "cutoff", 1.2, 0.25, 10, 0.002, "simple cutoff 1.2 nm"))
@@ -410,7 +410,7 @@ def main():
         kernels[st] = rec
     if dominant in work:
         achieved = work[dominant] / (stages32[dominant] * 1e-3) / 1e12
-        kfile = "msm_kernels.hip"
+        kfile = "pair.hip"
         kname = {"short": "pair_short", "cutoff": "stencil"}[dominant]
         roofline = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU,
                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU, 4),

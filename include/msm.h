@@ -7,7 +7,9 @@
  * (arXiv:1309.1889). Section 2 states the problem (charges q_i, positions r_i,
  * velocities v_i in; potential energy U and forces F_i = -dU/dr_i out),
  * Section 3 the multilevel summation method (MSM) that evaluates U, and
- * Section 4 the parareal iteration that uses a fine and a coarse propagator.
+ * Section 4 the parareal iteration that uses a fine and a coarse propagator,
+ * and Section 5 the combination, with the simple cutoff method as the coarse
+ * propagator.
  *
  * Conventions
  *  - Units: nm, e, amu, ps, kJ/mol; coulomb_k = 1/(4 pi eps0) = 138.935458
@@ -52,7 +54,7 @@ enum { MSM_FP64 = 0, MSM_FP32 = 1 };
 
 /* How the Coulomb interaction is evaluated. MSM_METHOD_MSM: multilevel
  * summation (Section 3). MSM_METHOD_CUTOFF: the simple cutoff method the
- * paper chooses for the coarse parareal propagator (Section 4): Coulomb's law
+ * paper chooses for the coarse parareal propagator (Section 5): Coulomb's law
  * between the pairs closer than a and nothing beyond; no grids are built,
  * h is only the edge of the cells of the pair search and levels is ignored. */
 enum { MSM_METHOD_MSM = 0, MSM_METHOD_CUTOFF = 1 };

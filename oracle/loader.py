@@ -210,7 +210,7 @@ def coulomb(xyz, q, ke: float = 138.935458):
 
 
 def cutoff(xyz, q, rc, ke: float = 138.935458, molid=None):
-    """Simple cutoff method (Section 4): energy, forces and potentials of
+    """Simple cutoff method (Section 5): energy, forces and potentials of
     Coulomb's law over the pairs closer than ``rc`` (pairs of equal ``molid``
     left out), by the direct pair loop."""
     xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)

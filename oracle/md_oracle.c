@@ -11,7 +11,7 @@
  * it gives no force field. The model here (a reading): rigid three-site
  * molecules held by RATTLE (Andersen 1983), Coulomb by MSM (or, for a
  * context with method ORC_METHOD_CUTOFF, by the simple cutoff method of
- * Section 4) with the pairs inside one molecule excluded, and Lennard-Jones
+ * Section 5) with the pairs inside one molecule excluded, and Lennard-Jones
  * with Lorentz-Berthelot mixing, cut and shifted at the cutoff a.
  * Parareal follows Section 4: lambda_{n+1}^{k+1} = G(lambda_n^{k+1}) +
  * F(lambda_n^k) - G(lambda_n^k), started from a coarse sweep; for rigid

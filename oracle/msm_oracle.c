@@ -517,7 +517,7 @@ int orc_coulomb(int64_t n, const double *xyz, const double *q, double ke,
     return 0;
 }
 
-/* ---- Section 4: the simple cutoff method ---- */
+/* ---- Section 5: the simple cutoff method ---- */
 int orc_cutoff(int64_t n, const double *xyz, const double *q, const int32_t *molid, double rc, double ke,
                double *energy, double *forces, double *pot)
 {

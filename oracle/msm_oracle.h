@@ -29,7 +29,7 @@ typedef struct {
     double hi[3];      /* domain upper corner */
     double ke;         /* Coulomb constant */
     int method;        /* ORC_METHOD_MSM, or ORC_METHOD_CUTOFF: the simple cutoff
-                          method of Section 4 (used by the dynamics oracle) */
+                          method of Section 5 (used by the dynamics oracle) */
 } orc_params;
 
 /* Optional per-stage outputs; any pointer may be NULL. Grid arrays are
@@ -67,7 +67,7 @@ int orc_short_subset(const orc_params *p, int64_t n, const double *xyz, const do
 int orc_coulomb(int64_t n, const double *xyz, const double *q, double ke,
                 double *energy, double *forces, double *pot);
 
-/* Simple cutoff method (Section 4, the coarse propagator the paper proposes):
+/* Simple cutoff method (Section 5, the coarse propagator the paper proposes):
  * Coulomb's law between every pair closer than rc and nothing beyond,
  * phi_i = ke sum_{j != i, r_ij < rc} q_j / r_ij, U = 1/2 sum_i q_i phi_i and
  * F_i = -dU/dr_i away from the cutoff sphere. molid (may be NULL) removes the

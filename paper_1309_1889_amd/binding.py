@@ -133,7 +133,7 @@ class MsmContext:
     a, h: cutoff and finest grid spacing (nm); lo, hi: domain corners;
     levels: number of grids (0 = from the domain); precision: "fp32" or
     "fp64"; ke: Coulomb prefactor; max_atoms / max_systems: batch capacity;
-    method: "msm", or "cutoff" for the simple cutoff method at a (Section 4's
+    method: "msm", or "cutoff" for the simple cutoff method at a (Section 5's
     coarse propagator; h is then only the cell edge of the pair search).
     """
 

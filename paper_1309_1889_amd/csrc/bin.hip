@@ -138,9 +138,9 @@ __global__ void k_scatter(int64_t n, const int *__restrict__ cell_of, const int 
     order[start[cell_of[i]] + slot_of[i]] = (int)i;
 }
 
-// Sort order[b..e) ascending in one thread: insertion sort for the usual
-// handful of atoms per cell, heapsort (O(n log n)) for crowded cells, which
-// arise when out-of-domain or non-finite atoms are clamped into one cell.
+// Sort a[0..n) ascending in one thread: insertion sort for a handful of
+// atoms, heapsort (O(n log n)) for crowded cells, which arise when
+// out-of-domain or non-finite atoms are clamped into one cell.
 __device__ inline void sort_range(int *a, int n)
 {
     if (n <= 32) {
@@ -174,10 +174,15 @@ __device__ inline void sort_range(int *a, int n)
     }
 }
 
+// Order each cell's atoms by input index and gather them (and their model
+// records) into cell order, in one of two forms chosen per batch plan (the
+// order they produce is the same).
+//
+// One thread per cell, for up to a few atoms per cell on average.
 template <typename T>
-__global__ void k_cell_sort(int64_t ncells, const int *__restrict__ start, int *__restrict__ order,
-                            const vec4_t<T> *__restrict__ xyzq, vec4_t<T> *__restrict__ sxyzq,
-                            const vec4_t<T> *__restrict__ maux, vec4_t<T> *__restrict__ saux, int64_t period)
+__global__ void k_cell_sort_thread(int64_t ncells, const int *__restrict__ start, int *__restrict__ order,
+                                   const vec4_t<T> *__restrict__ xyzq, vec4_t<T> *__restrict__ sxyzq,
+                                   const vec4_t<T> *__restrict__ maux, vec4_t<T> *__restrict__ saux, int64_t period)
 {
     int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= ncells) return;
@@ -186,6 +191,42 @@ __global__ void k_cell_sort(int64_t ncells, const int *__restrict__ start, int *
     for (int i = b; i < e; i++) sxyzq[i] = xyzq[order[i]];
     if (maux)
         for (int i = b; i < e; i++) saux[i] = maux[order[i] % period];
+}
+
+// One wave per cell, for crowded cells (coarse h): lane l holds the cell's l-th
+// index as the scatter left it, counts the smaller indices of its cell (the
+// indices are distinct, so the counts are a permutation) and writes its atom
+// to that rank. A cell of more than 64 atoms (non-finite positions are all
+// clamped into one) is sorted by its first lane.
+template <typename T>
+__global__ __launch_bounds__(256) void k_cell_sort(int64_t ncells, const int *__restrict__ start,
+                                                   int *__restrict__ order, const vec4_t<T> *__restrict__ xyzq,
+                                                   vec4_t<T> *__restrict__ sxyzq, const vec4_t<T> *__restrict__ maux,
+                                                   vec4_t<T> *__restrict__ saux, int64_t period)
+{
+    const int64_t c = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
+    if (c >= ncells) return;
+    const int lane = threadIdx.x % 64;
+    const int b = __builtin_amdgcn_readfirstlane(start[c]);
+    const int n = __builtin_amdgcn_readfirstlane(start[c + 1]) - b;
+    if (n == 0) return;
+    if (n > 64) {
+        if (lane == 0) {
+            sort_range(order + b, n);
+            for (int i = b; i < b + n; i++) sxyzq[i] = xyzq[order[i]];
+            if (maux)
+                for (int i = b; i < b + n; i++) saux[i] = maux[order[i] % period];
+        }
+        return;
+    }
+    const int v = lane < n ? order[b + lane] : 0x7fffffff;
+    int rank = 0;
+    for (int k = 0; k < n; ++k) rank += __shfl(v, k, 64) < v ? 1 : 0;
+    if (lane < n) {
+        order[b + rank] = v;
+        sxyzq[b + rank] = xyzq[v];
+        if (maux) saux[b + rank] = maux[v % period];
+    }
 }
 
 inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
@@ -232,8 +273,12 @@ hipError_t Launch<T>::bin(hipStream_t s, const DevPlan &p, const Work<T> &w, con
     if (p.natoms > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(nblocks(p.natoms, 256)), dim3(256), 0, s, p.natoms, w.cell_of,
                            w.slot_of, w.cell_start, w.order);
-        hipLaunchKernelGGL(k_cell_sort<T>, dim3(nblocks(p.ncells, 256)), dim3(256), 0, s, p.ncells,
-                           w.cell_start, w.order, xyzq, w.sxyzq, (const vec4_t<T> *)w.maux, w.saux, w.period);
+        if (p.natoms > 2 * p.ncells)
+            hipLaunchKernelGGL(k_cell_sort<T>, dim3(nblocks(p.ncells, 4)), dim3(256), 0, s, p.ncells,
+                               w.cell_start, w.order, xyzq, w.sxyzq, (const vec4_t<T> *)w.maux, w.saux, w.period);
+        else
+            hipLaunchKernelGGL(k_cell_sort_thread<T>, dim3(nblocks(p.ncells, 256)), dim3(256), 0, s, p.ncells,
+                               w.cell_start, w.order, xyzq, w.sxyzq, (const vec4_t<T> *)w.maux, w.saux, w.period);
     }
     return hipGetLastError();
 }

@@ -74,6 +74,21 @@ __host__ __device__ inline int64_t cell_rank(const SysPlan &p, int cx, int cy, i
     return brick * kBrickCells + (iz * kBrick + iy) * kBrick + ix;
 }
 
+// Inverse of cell_rank: the cell coordinates of rank r within its system.
+__host__ __device__ inline void cell_coords(const SysPlan &p, int64_t r, int c[3])
+{
+    const int64_t brick = r / kBrickCells;
+    const int in = (int)(r % kBrickCells);
+    const int64_t row = brick / p.nb[0];
+    const int xb = (int)(brick % p.nb[0]);
+    const int bx = (row & 1) ? p.nb[0] - 1 - xb : xb;
+    const int bz = (int)(row / p.nb[1]), yr = (int)(row % p.nb[1]);
+    const int by = (bz & 1) ? p.nb[1] - 1 - yr : yr;
+    c[0] = bx * kBrick + in % kBrick;
+    c[1] = by * kBrick + (in / kBrick) % kBrick;
+    c[2] = bz * kBrick + in / (kBrick * kBrick);
+}
+
 // Find s with prefix[s] <= g < prefix[s+1]; prefix has n+1 increasing entries.
 __device__ inline int find_segment(const int64_t *prefix, int n, int64_t g)
 {

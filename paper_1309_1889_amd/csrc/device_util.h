@@ -1,0 +1,58 @@
+// Small device helpers shared by the kernel files: launch sizes, wave-level
+// broadcasts and reductions, and the clamped cell index of a grid coordinate.
+#pragma once
+
+#include "launch.h"
+
+namespace msmx {
+namespace {
+
+inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
+
+// Broadcast lane 0's value to the whole wave as a scalar (the value must
+// already be uniform); lets the compiler keep loop bounds and the j-atom
+// loads of the pair kernel in scalar registers.
+__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ inline float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ inline double uni(double v)
+{
+    int64_t b = __double_as_longlong(v);
+    int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
+    int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+
+template <typename T> __device__ inline T wave_min(T v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
+    return v;
+}
+template <typename T> __device__ inline T wave_max(T v)
+{
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Workgroups are handed to the 8 XCDs (each with its own L2) round-robin by
+// launch index. Remap the index so that XCD x works on one contiguous range
+// of tiles: neighbouring tiles share their halo data in that XCD's L2.
+__device__ inline int64_t xcd_remap(int64_t b, int64_t n)
+{
+    constexpr int kXcd = 8;
+    const int64_t base = n / kXcd, rem = n % kXcd;
+    const int64_t x = b % kXcd, i = b / kXcd;
+    return x * base + (x < rem ? x : rem) + i;
+}
+
+template <typename T> __device__ inline int cell_floor(T t, int nc)
+{
+    // floor, clamped to the cell range; NaN maps to 0
+    if (!(t >= T(0))) return 0;
+    int c = (int)floor(t);
+    return c > nc - 1 ? nc - 1 : c;
+}
+
+}  // namespace
+}  // namespace msmx

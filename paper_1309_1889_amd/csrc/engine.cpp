@@ -107,6 +107,11 @@ template <typename T> void carve(msm_ctx *c, Work<T> &w, char *base, size_t *use
     w.order = (int *)take(sizeof(int) * na);
     w.sxyzq = (vec4_t<T> *)take(vec_bytes<T>() * (na + 64));   // spare tail for the pair prefetch
     w.shrt = (vec4_t<T> *)take(vec_bytes<T>() * na);
+    // partial charges per cell for the two-pass anterpolation, which a plan
+    // uses only with more than 2 atoms per cell (so fewer cells than
+    // max_atoms / 2); none without grids
+    const int64_t part_cells = std::min<int64_t>(c->cap_cells, na / 2 + 1);
+    w.apart = (T *)take(c->prm.method == MSM_METHOD_CUTOFF ? 0 : sizeof(T) * kWave * part_cells);
     w.qgrid = (T *)take(sizeof(T) * c->cap_q);
     w.ucut = (T *)take(sizeof(T) * c->cap_u);
     w.ugrid = (T *)take(sizeof(T) * c->cap_u);

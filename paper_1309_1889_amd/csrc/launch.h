@@ -40,6 +40,7 @@ template <typename T> struct Work {
     int *order;          // sorted position -> input atom
     vec4_t<T> *sxyzq;    // atoms in sorted order
     vec4_t<T> *shrt;     // sorted order: (bracket of F^short, u^short)
+    T *apart;            // ncells x 64: each cell's partial charges on its 4x4x4 support nodes
     T *qgrid;            // padded charge grids, all levels and systems
     T *ucut;             // lattice-cutoff potentials (top level: u^{l-1})
     T *ugrid;            // prolongated potentials u^k
@@ -63,7 +64,6 @@ template <typename T> struct StencilTables {
 };
 
 int stencil_tile_xy(int elem_bytes, int reach);
-int anterp_tiles(int dx, int dy, int dz);
 int top_blocks(int nodes);
 int top_stage_limit();
 int stencil_tile_z(int elem_bytes, int reach);
@@ -75,6 +75,9 @@ struct MethodConst {
     int pair_waves;            // waves per 64-atom group in the pair kernel: 4, 8 or 16
     int stencil_threads;       // threads per stencil tile: 256 or 1024
 };
+
+int anterp_tiles(int dx, int dy, int dz);
+bool anterp_two_pass(const DevPlan &p);   // anterpolation by cell partials (crowded cells) rather than tiles
 
 int scan_cells(hipStream_t s, int *counts_to_start, int64_t n, int *block_sums);
 

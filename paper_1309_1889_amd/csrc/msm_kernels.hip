@@ -2,6 +2,7 @@
 // on the arithmetic type T (float or double). Every kernel works on all
 // systems of a batch in one launch; a thread or wave finds its system by a
 // binary search of a prefix table.
+#include "device_util.h"
 #include "launch.h"
 #include "md.h"
 
@@ -9,333 +10,24 @@ namespace msmx {
 
 namespace {
 
-inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
-
-// Broadcast lane 0's value to the whole wave as a scalar (the value must
-// already be uniform); lets the compiler keep loop bounds and the j-atom
-// loads of the pair kernel in scalar registers.
-__device__ inline int uni(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ inline float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
-__device__ inline double uni(double v)
-{
-    int64_t b = __double_as_longlong(v);
-    int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffff));
-    int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
-    return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
-}
-
-template <typename T> __device__ inline T wave_min(T v)
-{
-    for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));
-    return v;
-}
-template <typename T> __device__ inline T wave_max(T v)
-{
-    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
-    return v;
-}
-
-__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
-
-// Workgroups are handed to the 8 XCDs (each with its own L2) round-robin by
-// launch index. Remap the index so that XCD x works on one contiguous range
-// of tiles: neighbouring tiles share their halo data in that XCD's L2.
-__device__ inline int64_t xcd_remap(int64_t b, int64_t n)
-{
-    constexpr int kXcd = 8;
-    const int64_t base = n / kXcd, rem = n % kXcd;
-    const int64_t x = b % kXcd, i = b / kXcd;
-    return x * base + (x < rem ? x : rem) + i;
-}
-
-template <typename T> __device__ inline int cell_floor(T t, int nc)
-{
-    // floor, clamped to the cell range; NaN maps to 0
-    if (!(t >= T(0))) return 0;
-    int c = (int)floor(t);
-    return c > nc - 1 ? nc - 1 : c;
-}
-
 // ---------------------------------------------------------------------------
-// Short-range part (Section 3): u_i^short = sum_{j != i, r < a} g*(r_ij) q_j with
-// g*(r) = 1/r - gamma(r/a)/a, and the force bracket
-// b_i = sum_j q_j (-dg*/dr / r)(r_i - r_j) = sum_j q_j (1/r^3 - (5/2 - 3/2 rho^2)/a^3)(r_i - r_j),
-// so that F_i^short = k q_i b_i.
+// Anterpolation (Section 3): q^0_mu = sum_j phi^0_mu(r_j) q_j, as a gather
+// (no atomics, fixed order) in one of two forms chosen per batch plan.
 //
-// One wave owns 64 consecutive sorted atoms (a compact group, one per lane).
-// It walks the cell rows that intersect the group's bounding box grown by a,
-// each row clipped to the chord the cutoff sphere leaves it, and streams the
-// candidate j atoms as wave-uniform scalars: each lane tests its own pair.
-// Every pair is evaluated from both sides, so no atomics are needed and the
-// summation order is fixed.
-// ---------------------------------------------------------------------------
-template <typename T> struct PairK {
-    T a2;            // a^2
-    T reach;         // a plus a rounding margin, for the row search
-    T inv_a2;        // 1/a^2
-    T c0, c1, c2;    // gamma(r/a)/a = c0 + c1 r^2 + c2 r^4
-    T d0, d1;        // -(d/dr)(gamma(r/a)/a) / r = d0 + d1 r^2
-};
-
-#ifndef MSMX_PAIR_UNROLL
-#define MSMX_PAIR_UNROLL 8
-#endif
-constexpr int kPairUnroll = MSMX_PAIR_UNROLL;   // staged candidates read per step
-
-// molecule id stored in the first component of an aux record
-__device__ inline int mol_of(const float4 &v) { return __float_as_int(v.x); }
-__device__ inline int mol_of(const double4 &v) { return (int)__double_as_longlong(v.x); }
-
-// Per-wave LDS: the flattened candidate stream of the wave's 64 current work
-// items and the staged chunk of 64 candidate atoms.
-template <typename T, bool MD> struct PairLds {
-    int pre[kWave + 1];                // start of each item's atoms in the stream
-    int first[kWave];                  // first atom of each item
-    vec4_t<T> atom[kWave];             // staged candidates
-    vec4_t<T> aux[MD ? kWave : 1];
-};
-
-// POT = false: forces only (no potential or energy sums), for evaluations
-// that are asked for neither.
-template <typename T, bool MD, bool POT>
-__device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const vec4_t<T> &aj, const vec4_t<T> &xj,
-                                 const PairK<T> &k, T &fx, T &fy, T &fz, T &u, T &lx, T &ly, T &lz, T &le)
-{
-    const T dx = ai.x - aj.x, dy = ai.y - aj.y, dz = ai.z - aj.z;
-    const T r2 = dx * dx + dy * dy + dz * dz;
-    if (r2 < k.a2 && r2 > T(0)) {
-        const T rinv = rsqrt_t(r2);
-        T rc = rinv;
-        bool same = false;
-        if (MD) {
-            same = mol_of(xi) == mol_of(xj);
-            rc = same ? T(0) : rinv;
-        }
-        const T br = rc * rinv * rinv - (k.d0 + k.d1 * r2);
-        if (POT) {
-            const T gs = rc - (k.c0 + r2 * (k.c1 + r2 * k.c2));
-            u += aj.w * gs;
-        }
-        const T t = aj.w * br;
-        fx += t * dx;
-        fy += t * dy;
-        fz += t * dz;
-        if (MD) {
-            const T eps = same ? T(0) : xi.z * xj.z;
-            if (eps != T(0)) {
-                const T sg = xi.y + xj.y;
-                const T s2 = sg * sg;
-                const T sr2 = s2 * rinv * rinv, sr6 = sr2 * sr2 * sr2;
-                if (POT) {
-                    const T sc2 = s2 * k.inv_a2, sc6 = sc2 * sc2 * sc2;
-                    le += T(4) * eps * ((sr6 * sr6 - sr6) - (sc6 * sc6 - sc6));
-                }
-                const T fl = T(24) * eps * (T(2) * sr6 * sr6 - sr6) * rinv * rinv;
-                lx += fl * dx;
-                ly += fl * dy;
-                lz += fl * dz;
-            }
-        }
-    }
-}
-
-// Dynamics variant (MD = true): pairs inside one molecule are excluded from
-// Coulomb's law, so instead of g* they contribute -gamma(r/a)/a, which cancels
-// the smooth part the grids carry for them; and a Lennard-Jones term
-// 4 eps ((s/r)^12 - (s/r)^6), shifted to zero at r = a, acts between atoms of
-// different molecules, with s = s_i/2 + s_j/2 and eps = sqrt(eps_i) sqrt(eps_j)
-// stored per atom in aux = (molecule id bits, s/2, sqrt(eps), 0).
+// Tiled, for up to a few atoms per cell: a workgroup owns an 8x8x4 tile of
+// nodes. It stages the atoms of the 11x11x7 cells the tile can reach in LDS,
+// as grid coordinates (t = (r - lo)/h, q), row by row in x order with a table
+// of where each cell's atoms start; each thread then sums its node over the
+// atoms of the 4x4x4 cells mu-2 .. mu+1 whose support covers it. A tile whose
+// region holds more atoms than the LDS buffer gathers from global memory.
 //
-// Work layout: a workgroup of kPairWaves waves owns one group of 64
-// consecutive sorted atoms (one per lane). The work items are the pieces of
-// cell rows (cy, cz) inside one brick column that can reach the group's
-// bounding box; each is clipped to the chord the cutoff sphere leaves its
-// row and is one contiguous run of sorted atoms. Items are dealt round-robin
-// to the waves. A wave lays 64 items at a time out as one stream of
-// candidate atoms, stages the stream 64 atoms at a time in LDS with one
-// coalesced load (the next chunk is fetched while the current one is used),
-// and every lane reads each staged atom by broadcast and evaluates its own
-// pair. The waves' partial sums are added in a fixed order at the end.
-template <typename T, bool MD, bool POT, int kPairWaves>
-__global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const vec4_t<T> *__restrict__ sx,
-                                                              const int *__restrict__ cstart,
-                                                              vec4_t<T> *__restrict__ out, PairK<T> k,
-                                                              const vec4_t<T> *__restrict__ saux,
-                                                              vec4_t<T> *__restrict__ ljout)
-{
-    __shared__ PairLds<T, MD> lds[kPairWaves];
-    __shared__ vec4_t<T> red[kPairWaves][kWave];
-    __shared__ vec4_t<T> redlj[MD ? kPairWaves : 1][kWave];
-    const int64_t g = blockIdx.x;
-    const int s = find_segment(p.group_prefix, p.nsys, g);
-    const SysPlan &P = p.sys[s];
-    const int64_t first = P.atom0 + (g - p.group_prefix[s]) * kWave;
-    const int64_t end = P.atom0 + P.natoms;
-    const int lane = threadIdx.x % kWave;
-    const int wv = uni((int)(threadIdx.x / kWave));
-    PairLds<T, MD> &L = lds[wv];
-    const int64_t i = first + lane;
-    const bool valid = i < end;
-    const vec4_t<T> ai = sx[valid ? i : first];
-    vec4_t<T> xi;
-    if (MD) xi = saux[valid ? i : first];
-
-    const T bminx = uni(wave_min(ai.x)), bmaxx = uni(wave_max(ai.x));
-    const T bminy = uni(wave_min(ai.y)), bmaxy = uni(wave_max(ai.y));
-    const T bminz = uni(wave_min(ai.z)), bmaxz = uni(wave_max(ai.z));
-    const T lox = T(P.lo[0]), loy = T(P.lo[1]), loz = T(P.lo[2]);
-    const T inv_h = T(P.inv_h), h = T(1.0 / P.inv_h);
-    const int ncx = P.nc[0], ncy = P.nc[1], ncz = P.nc[2];
-    const T reach = k.reach, reach2 = k.reach * k.reach;
-    const int cy0 = clampi((int)floor((bminy - loy - reach) * inv_h), 0, ncy - 1);
-    const int cy1 = clampi((int)floor((bmaxy - loy + reach) * inv_h), 0, ncy - 1);
-    const int cz0 = clampi((int)floor((bminz - loz - reach) * inv_h), 0, ncz - 1);
-    const int cz1 = clampi((int)floor((bmaxz - loz + reach) * inv_h), 0, ncz - 1);
-    const int bx0 = clampi((int)floor((bminx - lox - reach) * inv_h), 0, ncx - 1) / kBrick;
-    const int bx1 = clampi((int)floor((bmaxx - lox + reach) * inv_h), 0, ncx - 1) / kBrick;
-    const int nbx = bx1 - bx0 + 1, ny = cy1 - cy0 + 1;
-    const int nitems = nbx * ny * (cz1 - cz0 + 1);
-
-    // The two polynomial addends are kept in vector registers: an FMA takes
-    // one scalar operand, so as kernel arguments they would be copied to
-    // vector registers again for every candidate.
-    asm volatile("" : "+v"(k.c1), "+v"(k.d0));
-    T fx = 0, fy = 0, fz = 0, u = 0;
-    T lx = 0, ly = 0, lz = 0, le = 0;
-    // items wv, wv + W, wv + 2W, ..., 64 per batch
-    for (int ib = wv; ib < nitems; ib += kPairWaves * kWave) {
-        const int q = ib + kPairWaves * lane;            // this lane's item
-        int len = 0, jb = 0;
-        if (q < nitems) {
-            const int bx = bx0 + q % nbx, row = q / nbx;
-            const int cy = cy0 + row % ny, cz = cz0 + row / ny;
-            const T z0 = loz + T(cz) * h, y0 = loy + T(cy) * h;
-            const T dz = fmax(T(0), fmax(z0 - bmaxz, bminz - (z0 + h)));
-            const T dy = fmax(T(0), fmax(y0 - bmaxy, bminy - (y0 + h)));
-            const T rem = reach2 - dy * dy - dz * dz;
-            if (rem > T(0)) {
-                const T wdt = sqrt(rem);
-                const int cx0 = clampi((int)floor((bminx - lox - wdt) * inv_h), 0, ncx - 1);
-                const int cx1 = clampi((int)floor((bmaxx - lox + wdt) * inv_h), 0, ncx - 1);
-                const int ca = max(cx0, bx * kBrick), cb = min(cx1, bx * kBrick + kBrick - 1);
-                if (ca <= cb) {
-                    const int64_t r0 = P.cell0 + cell_rank(P, ca, cy, cz);
-                    jb = cstart[r0];
-                    len = cstart[r0 + (cb - ca) + 1] - jb;
-                }
-            }
-        }
-        // exclusive prefix of the item lengths across the wave
-        int incl = len;
-        for (int off = 1; off < kWave; off <<= 1) {
-            const int v = __shfl_up(incl, off, kWave);
-            if (lane >= off) incl += v;
-        }
-        L.pre[lane] = incl - len;
-        L.first[lane] = jb;
-        const int total = uni(__shfl(incl, kWave - 1, kWave));
-        if (lane == 0) L.pre[kWave] = total;
-        // the wave's own LDS writes are seen by its later reads (one wave, in
-        // order); the barrier only keeps the compiler from moving them
-        __builtin_amdgcn_wave_barrier();
-        // stream position -> sorted atom index
-        auto locate = [&](int pos) -> int {
-            int lo_ = 0, hi_ = kWave;       // pre[lo_] <= pos < pre[hi_]
-            while (hi_ - lo_ > 1) {
-                const int mid = (lo_ + hi_) >> 1;
-                if (L.pre[mid] <= pos) lo_ = mid; else hi_ = mid;
-            }
-            return L.first[lo_] + (pos - L.pre[lo_]);
-        };
-        vec4_t<T> pa, px;
-        if (lane < total) {
-            const int j = locate(lane);
-            pa = sx[j];
-            if (MD) px = saux[j];
-        }
-        for (int c0 = 0; c0 < total; c0 += kWave) {
-            __builtin_amdgcn_wave_barrier();
-            L.atom[lane] = pa;
-            if (MD) L.aux[lane] = px;
-            __builtin_amdgcn_wave_barrier();
-            const int nxt = c0 + kWave + lane;
-            if (nxt < total) {
-                const int j = locate(nxt);
-                pa = sx[j];
-                if (MD) px = saux[j];
-            }
-            const int cnt = uni(min(kWave, total - c0));
-            int t = 0;
-            // unrolled so that several broadcast reads are in flight at once
-            for (; t + kPairUnroll <= cnt; t += kPairUnroll) {
-                vec4_t<T> aj[kPairUnroll], xj[kPairUnroll];
-#pragma unroll
-                for (int v = 0; v < kPairUnroll; ++v) {
-                    aj[v] = L.atom[t + v];
-                    xj[v] = MD ? L.aux[t + v] : aj[v];
-                }
-#pragma unroll
-                for (int v = 0; v < kPairUnroll; ++v)
-                    pair_term<T, MD, POT>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le);
-            }
-            for (; t < cnt; ++t) {
-                const vec4_t<T> aj = L.atom[t];
-                const vec4_t<T> xj = MD ? L.aux[t] : aj;
-                pair_term<T, MD, POT>(ai, xi, aj, xj, k, fx, fy, fz, u, lx, ly, lz, le);
-            }
-        }
-        __builtin_amdgcn_wave_barrier();
-    }
-    vec4_t<T> o;
-    o.x = fx;
-    o.y = fy;
-    o.z = fz;
-    o.w = u;
-    red[wv][lane] = o;
-    if (MD) {
-        vec4_t<T> ol;
-        ol.x = lx;
-        ol.y = ly;
-        ol.z = lz;
-        ol.w = le;
-        redlj[MD ? wv : 0][lane] = ol;
-    }
-    __syncthreads();
-    if (wv == 0 && valid) {
-        vec4_t<T> acc = red[0][lane];
-        for (int w = 1; w < kPairWaves; ++w) {   // fixed order: deterministic
-            const vec4_t<T> v = red[w][lane];
-            acc.x += v.x;
-            acc.y += v.y;
-            acc.z += v.z;
-            acc.w += v.w;
-        }
-        out[i] = acc;
-        if (MD) {
-            vec4_t<T> al = redlj[0][lane];
-            for (int w = 1; w < kPairWaves; ++w) {
-                const vec4_t<T> v = redlj[MD ? w : 0][lane];
-                al.x += v.x;
-                al.y += v.y;
-                al.z += v.z;
-                al.w += v.w;
-            }
-            ljout[i] = al;
-        }
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Anterpolation (Section 3): q^0_mu = sum_j phi^0_mu(r_j) q_j. Gather form:
-// each level-0 node sums over the atoms of the 4x4x4 cells whose support
-// covers it (cells mu-2 .. mu+1 per axis), so no atomics are needed.
-//
-// A workgroup owns an 8x8x4 tile of nodes. It first stages the atoms of the
-// 11x11x7 cells the tile can reach in LDS, as grid coordinates
-// (t = (r - lo)/h, q), row by row in x order with a table of where each
-// cell's atoms start; each thread then gathers its node from LDS. A tile
-// whose region holds more atoms than the LDS buffer gathers from global
-// memory instead.
+// Two passes, for crowded cells (coarse h), whose cost does not depend on the
+// atoms per cell:
+//  1. k_anterp_cells: one wave per cell; lane (mx, my, mz) sums the weights
+//     of the cell's atoms (sorted order) on node c - 1 + m of the cell's
+//     4x4x4 support, giving 64 partial charges per cell (zero when empty).
+//  2. k_anterp_nodes: one thread per level-0 node adds the partials of the
+//     64 cells mu-2 .. mu+1 whose support covers it, in a fixed order.
 // ---------------------------------------------------------------------------
 constexpr int kAntX = 8, kAntY = 8, kAntZ = 4;
 constexpr int kAntCX = kAntX + 3, kAntCY = kAntY + 3, kAntCZ = kAntZ + 3;   // cells reached
@@ -457,6 +149,55 @@ __global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__re
     } else {
         acc = gather_global<T>(P, sx, cstart, ix, iy, iz);
     }
+    const int PX = padded_x(dx), PY = padded_x(dy);
+    qgrid[P.qoff[0] + ((int64_t)(rz + kGridPad) * PY + (ry + kGridPad)) * PX + (rx + kGridPad)] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_anterp_cells(DevPlan p, const vec4_t<T> *__restrict__ sx,
+                                                      const int *__restrict__ cstart, T *__restrict__ part)
+{
+    const int64_t c = (int64_t)blockIdx.x * (256 / kWave) + uni((int)(threadIdx.x / kWave));   // batch cell
+    if (c >= p.ncells) return;
+    const int lane = threadIdx.x % kWave;
+    const int jb = uni(cstart[c]), je = uni(cstart[c + 1]);
+    T acc = 0;
+    if (je > jb) {
+        const int s = uni(find_segment(p.cell_prefix, p.nsys, c));
+        const SysPlan &P = p.sys[s];
+        int cc[3];
+        cell_coords(P, c - P.cell0, cc);
+        const T lox = T(P.lo[0]), loy = T(P.lo[1]), loz = T(P.lo[2]), inv_h = T(P.inv_h);
+        const T nx = T(cc[0] - 1 + (lane & 3)), ny = T(cc[1] - 1 + ((lane >> 2) & 3)), nz = T(cc[2] - 1 + (lane >> 4));
+        for (int j = jb; j < je; ++j) {
+            const vec4_t<T> a = sx[j];
+            acc += basis((a.x - lox) * inv_h - nx) * basis((a.y - loy) * inv_h - ny) *
+                   basis((a.z - loz) * inv_h - nz) * a.w;
+        }
+    }
+    part[c * kWave + lane] = acc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_anterp_nodes(DevPlan p, const T *__restrict__ part, T *__restrict__ qgrid)
+{
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= p.nnodes[0]) return;
+    const int64_t *pref = p.node_prefix;   // level 0
+    const int s = find_segment(pref, p.nsys, g);
+    const SysPlan &P = p.sys[s];
+    const int dx = P.gdim[0][0], dy = P.gdim[0][1];
+    const int loc = (int)(g - pref[s]);
+    const int rx = loc % dx, ry = (loc / dx) % dy, rz = loc / (dx * dy);
+    const int mx = rx + P.gorg[0][0], my = ry + P.gorg[0][1], mz = rz + P.gorg[0][2];   // absolute node
+    T acc = 0;
+    for (int cz = max(mz - 2, 0); cz <= min(mz + 1, P.nc[2] - 1); ++cz)
+        for (int cy = max(my - 2, 0); cy <= min(my + 1, P.nc[1] - 1); ++cy)
+            for (int cx = max(mx - 2, 0); cx <= min(mx + 1, P.nc[0] - 1); ++cx) {
+                const int64_t r = P.cell0 + cell_rank(P, cx, cy, cz);
+                const int m = (mx - cx + 1) + 4 * (my - cy + 1) + 16 * (mz - cz + 1);
+                acc += part[r * kWave + m];
+            }
     const int PX = padded_x(dx), PY = padded_x(dy);
     qgrid[P.qoff[0] + ((int64_t)(rz + kGridPad) * PY + (ry + kGridPad)) * PX + (rx + kGridPad)] = acc;
 }
@@ -954,65 +695,27 @@ __global__ void k_stage_grid(const SysPlan *sys, int s, int k, const T *__restri
 
 }  // namespace
 
-template <typename T, int NW>
-static void pair_launch(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot)
-{
-    const dim3 grid((unsigned)p.ngroups), block(NW * kWave);
-    const vec4_t<T> *aux = (const vec4_t<T> *)w.saux;
-    if (w.saux && pot)
-        hipLaunchKernelGGL((k_pair<T, true, true, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k, aux,
-                           w.shlj);
-    else if (w.saux)
-        hipLaunchKernelGGL((k_pair<T, true, false, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k, aux,
-                           w.shlj);
-    else if (pot)
-        hipLaunchKernelGGL((k_pair<T, false, true, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
-                           (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
-    else
-        hipLaunchKernelGGL((k_pair<T, false, false, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
-                           (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
-}
-
-template <typename T>
-hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m, bool pot)
-{
-    if (p.ngroups == 0) return hipSuccess;
-    PairK<T> k;
-    const double a = m.a;
-    k.a2 = T(a * a);
-    k.reach = T(a * (1.0 + 1e-5));
-    k.inv_a2 = T(1.0 / (a * a));
-    // gamma(r/a)/a = (15/8 - 5/4 r^2/a^2 + 3/8 r^4/a^4) / a
-    k.c0 = T(1.875 / a);
-    k.c1 = T(-1.25 / (a * a * a));
-    k.c2 = T(0.375 / (a * a * a * a * a));
-    // -(d/dr)(gamma(r/a)/a) / r = (5/2 - 3/2 r^2/a^2) / a^3
-    k.d0 = T(2.5 / (a * a * a));
-    k.d1 = T(-1.5 / (a * a * a * a * a));
-    if (m.cutoff) {
-        // simple cutoff method (Section 4): plain 1/r below a, nothing left
-        // for grids, so the smoothing polynomial is zero
-        k.c0 = k.c1 = k.c2 = k.d0 = k.d1 = T(0);
-    }
-    switch (m.pair_waves) {
-    case 4: pair_launch<T, 4>(s, p, w, k, pot); break;
-    case 8: pair_launch<T, 8>(s, p, w, k, pot); break;
-    case 16: pair_launch<T, 16>(s, p, w, k, pot); break;
-    default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
-
-template <typename T> hipError_t Launch<T>::anterp(hipStream_t s, const DevPlan &p, const Work<T> &w)
-{
-    if (p.nant == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_anterp<T>, dim3((unsigned)p.nant), dim3(256), 0, s, p, w.sxyzq, w.cell_start, w.qgrid);
-    return hipGetLastError();
-}
-
 int anterp_tiles(int dx, int dy, int dz)
 {
     return ((dx + kAntX - 1) / kAntX) * ((dy + kAntY - 1) / kAntY) * ((dz + kAntZ - 1) / kAntZ);
+}
+
+// The tiles hold kAntAtoms atoms of an 11x11x7-cell region: above about 2
+// atoms per cell on average, many would overflow to the global gather.
+bool anterp_two_pass(const DevPlan &p) { return p.natoms > 2 * p.ncells; }
+
+template <typename T> hipError_t Launch<T>::anterp(hipStream_t s, const DevPlan &p, const Work<T> &w)
+{
+    if (p.nnodes[0] == 0) return hipSuccess;   // no grids (simple cutoff method)
+    if (!anterp_two_pass(p)) {
+        hipLaunchKernelGGL(k_anterp<T>, dim3((unsigned)p.nant), dim3(256), 0, s, p, w.sxyzq, w.cell_start, w.qgrid);
+        return hipGetLastError();
+    }
+    if (p.ncells > 0)
+        hipLaunchKernelGGL(k_anterp_cells<T>, dim3((unsigned)((p.ncells + 3) / 4)), dim3(256), 0, s, p, w.sxyzq,
+                           w.cell_start, w.apart);
+    hipLaunchKernelGGL(k_anterp_nodes<T>, dim3(nblocks(p.nnodes[0], 256)), dim3(256), 0, s, p, w.apart, w.qgrid);
+    return hipGetLastError();
 }
 
 template <typename T> hipError_t Launch<T>::restrict_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k)

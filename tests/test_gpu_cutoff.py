@@ -1,4 +1,4 @@
-"""Parity of the simple cutoff method (Section 4: the coarse propagator the
+"""Parity of the simple cutoff method (Section 5: the coarse propagator the
 paper proposes for parareal) on the GPU with the FP64 oracle.
 
 The cutoff is a discontinuity: a pair whose distance is within rounding of

@@ -78,6 +78,27 @@ def test_fp64_matches_oracle_per_stage_charges_2000():
         assert max_rel(g["u_grid"][k].cpu().numpy(), st["u_grid"][k]) < 1e-12, k
 
 
+@pytest.mark.parametrize("h,two_pass", [(0.25, False), (0.5, True)])
+def test_anterpolation_forms_match_oracle_per_stage(h, two_pass):
+    """Anterpolation runs as LDS tiles up to 2 atoms per cell on average and
+    as per-cell partial charges above; both against the oracle's scatter, on
+    the grid charges q^k and the outputs."""
+    w = water_box(1500, (12, 12, 12), (3.6, 3.6, 3.6), seed=23, a=0.8, h=h)
+    ctx, e, f, p = run_gpu(w, "fp64")
+    ncells = 1
+    for d in range(3):
+        nc = int(np.floor((w.hi[d] - w.lo[d]) / h)) + 1
+        ncells *= (nc + 3) // 4 * 4
+    assert (w.n > 2 * ncells) == two_pass
+    eo, fo, po, st = run_oracle(w, stages=True)
+    assert e == pytest.approx(eo, rel=1e-12)
+    assert max_rel(f, fo) < 1e-11
+    assert max_rel(p, po) < 1e-11
+    g = ctx.stages(w.n)
+    for k in range(len(st["q_grid"])):
+        assert max_rel(g["q_grid"][k].cpu().numpy(), st["q_grid"][k]) < 1e-12, k
+
+
 def test_grid_shapes_agree_with_oracle():
     m = _lib()
     for w in [named("charges_2000"), water_box(500, (12, 12, 12), (3.7, 3.7, 3.7), seed=3)]:
@@ -150,14 +171,18 @@ def test_non_cubic_domain_and_boundary_atoms():
     assert max_rel(p, po) < 1e-11
 
 
-def test_crowded_cell():
-    # 300 atoms inside one 0.2 nm cube (a single cell) plus 300 spread out:
-    # the per-cell ordering takes its heapsort branch
+@pytest.mark.parametrize("n_spread,h", [(300, 0.25), (1200, 0.6)])
+def test_crowded_cell(n_spread, h):
+    # 300 atoms inside one 0.2 nm cube (a single cell) plus more spread out:
+    # the per-cell ordering takes its heapsort branch, in the one-thread-per-
+    # cell form (few atoms per cell on average) and the one-wave-per-cell form
     rng = np.random.default_rng(17)
-    xyz = np.concatenate([rng.uniform(1.02, 1.22, (300, 3)), rng.uniform(0.0, 3.0, (300, 3))])
-    q = rng.standard_normal(600) * 0.1
+    xyz = np.concatenate([rng.uniform(1.02, 1.22, (300, 3)), rng.uniform(0.0, 3.0, (n_spread, 3))])
+    q = rng.standard_normal(300 + n_spread) * 0.1
     from workloads import Workload
-    w = Workload("crowded", xyz, q, np.zeros(3), np.full(3, 3.0), a=0.8, h=0.25)
+    w = Workload("crowded", xyz, q, np.zeros(3), np.full(3, 3.0), a=0.8, h=h)
+    nb = (int(np.floor(3.0 / h)) + 1 + 3) // 4 * 4
+    assert (w.n > 2 * nb ** 3) == (h > 0.5)
     _, e, f, p = run_gpu(w, "fp64")
     eo, fo, po = run_oracle(w)
     assert e == pytest.approx(eo, rel=1e-11)

@@ -122,7 +122,7 @@ def test_parareal_exact_after_k_iterations_and_coarse_at_zero():
 
 
 def test_cutoff_model_forces_are_cutoff_coulomb_plus_the_same_lennard_jones():
-    """With the simple cutoff method (Section 4) the Coulomb part is the cutoff
+    """With the simple cutoff method (Section 5) the Coulomb part is the cutoff
     sum without intramolecular pairs, and the Lennard-Jones part is the same
     one the MSM model adds."""
     w, model, _ = small_water(64, 1.24, seed=17)

@@ -369,7 +369,7 @@ def test_short_subset_matches_full_short_range(orc):
 
 
 # --------------------------------------------------------------------------
-# the simple cutoff method (Section 4: the coarse propagator the paper picks)
+# the simple cutoff method (Section 5: the coarse propagator the paper picks)
 # --------------------------------------------------------------------------
 def test_cutoff_closed_forms(orc):
     # eight unit charges on the corners of a unit cube, cutoff between the
