@@ -360,12 +360,17 @@ def main():
              torch.empty(n, dtype=torch.float32, device=dev))
     eager_default_ms = timed_steps(torch, ctx, x32, out32, args.steps, args.warmup)
     tuning32 = ctx.autotune(x32, reps=5) if not args.no_autotune else ctx.tuning()
-    ctx.set_graphs(not args.no_graphs)
-    ms32 = timed_steps(torch, ctx, x32, out32, args.steps, args.warmup)
-    ctx.check()
-    ctx.set_graphs(False)
+    graph_ms = None
+    if not args.no_graphs:
+        ctx.set_graphs(True)
+        graph_ms = timed_steps(torch, ctx, x32, out32, args.steps, args.warmup)
+        ctx.check()
+        ctx.set_graphs(False)
     eager_tuned_ms = timed_steps(torch, ctx, x32, out32, args.steps, args.warmup)
     stages32 = stage_profile(torch, ctx, x32, out32, args.steps)
+    # the headline uses the faster of the two launch modes; both are reported
+    launch_mode = "graph" if graph_ms is not None and graph_ms < eager_tuned_ms else "eager"
+    ms32 = graph_ms if launch_mode == "graph" else eager_tuned_ms
     value = n / (ms32 * 1e-3)
     if args.copy_calibration_mib > 0:
         src = torch.ones(args.copy_calibration_mib * (1 << 18), dtype=torch.float32, device=dev)
@@ -384,10 +389,12 @@ def main():
                  torch.empty((n, 3), dtype=torch.float64, device=dev),
                  torch.empty(n, dtype=torch.float64, device=dev))
         tuning64 = ctx64.autotune(x64, reps=5) if not args.no_autotune else ctx64.tuning()
-        ctx64.set_graphs(not args.no_graphs)
         ms64 = timed_steps(torch, ctx64, x64, out64, max(args.steps // 2, 1), args.warmup)
-        ctx64.check()
-        ctx64.set_graphs(False)
+        if not args.no_graphs:
+            ctx64.set_graphs(True)
+            ms64 = min(ms64, timed_steps(torch, ctx64, x64, out64, max(args.steps // 2, 1), args.warmup))
+            ctx64.check()
+            ctx64.set_graphs(False)
         stages64 = stage_profile(torch, ctx64, x64, out64, max(args.steps // 2, 1))
         fp64 = {"value": n / (ms64 * 1e-3), "ms_per_step": ms64, "tuning": tuning64,
                 "stage_ms": {k: round(v, 5) for k, v in stages64.items()}}
@@ -480,7 +487,7 @@ def main():
         "uneven_batch": uneven,
         "parareal": par,
         "large_box": large,
-        "launch": {"graphs": not args.no_graphs, "tuning": tuning32,
+        "launch": {"mode": launch_mode, "tuning": tuning32, "graph_ms_per_step": graph_ms,
                    "eager_default_ms_per_step": eager_default_ms, "eager_tuned_ms_per_step": eager_tuned_ms},
         "accuracy": accuracy,
         "stage_ms": kernels,
