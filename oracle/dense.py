@@ -24,10 +24,15 @@ import math
 import numpy as np
 
 
-def gamma(rho):
+def gamma(rho, m=2):
+    """1/rho for rho >= 1; inside, (rho^2)^(-1/2) expanded about rho^2 = 1 up
+    to the (rho^2 - 1)^m term (m = 2: 15/8 - 5/4 rho^2 + 3/8 rho^4)."""
     rho = np.asarray(rho, dtype=np.float64)
+    u = rho ** 2 - 1.0
+    inner = np.zeros_like(rho)
+    for k in range(m + 1):
+        inner = inner + math.prod(-0.5 - i for i in range(k)) / math.factorial(k) * u ** k
     with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
-        inner = 1.875 - 1.25 * rho ** 2 + 0.375 * rho ** 4
         outer = 1.0 / rho
     return np.where(rho >= 1.0, outer, inner)
 
@@ -39,16 +44,16 @@ def Phi(t):
     return np.where(s <= 1.0, near, np.where(s < 2.0, far, 0.0))
 
 
-def g_level(r, a, k, l):
+def g_level(r, a, k, l, m=2):
     ak = a * 2.0 ** k
     if k == l - 1:
-        return gamma(r / ak) / ak
-    return gamma(r / ak) / ak - gamma(r / (2 * ak)) / (2 * ak)
+        return gamma(r / ak, m) / ak
+    return gamma(r / ak, m) / ak - gamma(r / (2 * ak), m) / (2 * ak)
 
 
-def g_star(r, a):
+def g_star(r, a, m=2):
     with np.errstate(divide="ignore"):
-        return np.where(r < a, 1.0 / r - gamma(r / a) / a, 0.0)
+        return np.where(r < a, 1.0 / r - gamma(r / a, m) / a, 0.0)
 
 
 def _nodes(lo, h, k, lo_idx, hi_idx):
@@ -71,7 +76,7 @@ def _pair_dist(x):
     return np.sqrt((diff ** 2).sum(axis=-1))
 
 
-def long_range_matrix(xyz, a, h, lo, hi, levels, pad=2):
+def long_range_matrix(xyz, a, h, lo, hi, levels, pad=2, m=2):
     """The N x N matrix of the nested grid approximation of g_a = g^0 + ... + g^{l-1}."""
     xyz = np.asarray(xyz, dtype=np.float64)
     lo = np.asarray(lo, dtype=np.float64)
@@ -84,7 +89,7 @@ def long_range_matrix(xyz, a, h, lo, hi, levels, pad=2):
         n_lo = np.floor((n_lo - 3) / 2.0).astype(int) - pad
         n_hi = np.ceil((n_hi + 3) / 2.0).astype(int) + pad
     nodes = [_nodes(lo, h, k, *ranges[k]) for k in range(levels)]
-    Gs = [g_level(_pair_dist(nodes[k]), a, k, levels) for k in range(levels)]
+    Gs = [g_level(_pair_dist(nodes[k]), a, k, levels, m) for k in range(levels)]
     K = Gs[levels - 1]
     for k in range(levels - 2, -1, -1):
         R = _basis(nodes[k], nodes[k + 1], (2.0 ** (k + 1)) * h).T   # R[mu_coarse, nu_fine]
@@ -93,18 +98,19 @@ def long_range_matrix(xyz, a, h, lo, hi, levels, pad=2):
     return P0 @ K @ P0.T
 
 
-def energy_potential(xyz, q, a, h, lo, hi, levels, ke=1.0, pad=2):
-    """Energy and per-atom potentials of the multilevel approximation, dense."""
+def energy_potential(xyz, q, a, h, lo, hi, levels, ke=1.0, pad=2, m=2):
+    """Energy and per-atom potentials of the multilevel approximation, dense,
+    with the smoothing function of order m."""
     xyz = np.asarray(xyz, dtype=np.float64)
     q = np.asarray(q, dtype=np.float64)
-    M = long_range_matrix(xyz, a, h, lo, hi, levels, pad)
+    M = long_range_matrix(xyz, a, h, lo, hi, levels, pad, m)
     r = _pair_dist(xyz)
     np.fill_diagonal(r, np.inf)
-    S = g_star(r, a)
+    S = g_star(r, a, m)
     np.fill_diagonal(S, 0.0)
     u_short = S @ q
     u_long = M @ q
-    phi = ke * (u_short + u_long - q * float(gamma(0.0)) / a)
+    phi = ke * (u_short + u_long - q * float(gamma(0.0, m)) / a)
     return 0.5 * float(q @ phi), phi, u_short, u_long
 
 

@@ -18,7 +18,8 @@ _dp = C.POINTER(C.c_double)
 
 class _Params(C.Structure):
     _fields_ = [("a", C.c_double), ("h", C.c_double), ("levels", C.c_int),
-                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("ke", C.c_double), ("method", C.c_int)]
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("ke", C.c_double), ("method", C.c_int),
+                ("smoothing", C.c_int)]
 
 
 METHOD_MSM = 0
@@ -40,19 +41,21 @@ class OracleParams:
     levels: int = 0
     ke: float = 138.935458
     method: int = METHOD_MSM    # METHOD_CUTOFF: the simple cutoff method at a (dynamics oracle)
+    smoothing: int = 0          # order m of gamma (degree 2m); 0 = 2
 
     def c(self) -> _Params:
         p = _Params()
         p.a, p.h, p.levels, p.ke = float(self.a), float(self.h), int(self.levels), float(self.ke)
         p.method = int(self.method)
+        p.smoothing = int(self.smoothing)
         for d in range(3):
             p.lo[d] = float(self.lo[d])
             p.hi[d] = float(self.hi[d])
         return p
 
     @classmethod
-    def of(cls, w, ke: float = 138.935458) -> "OracleParams":
-        return cls(w.a, w.h, tuple(w.lo), tuple(w.hi), w.levels, ke)
+    def of(cls, w, ke: float = 138.935458, smoothing: int = 0) -> "OracleParams":
+        return cls(w.a, w.h, tuple(w.lo), tuple(w.hi), w.levels, ke, smoothing=smoothing)
 
 
 def lib():
@@ -64,6 +67,13 @@ def lib():
             for name in ("orc_gamma", "orc_dgamma", "orc_Phi", "orc_dPhi"):
                 getattr(L, name).restype = C.c_double
                 getattr(L, name).argtypes = [C.c_double]
+            for name in ("orc_gamma_m", "orc_dgamma_m"):
+                getattr(L, name).restype = C.c_double
+                getattr(L, name).argtypes = [C.c_double, C.c_int]
+            L.orc_gstar_m.restype = C.c_double
+            L.orc_gstar_m.argtypes = [C.c_double, C.c_double, C.c_int]
+            L.orc_glevel_m.restype = C.c_double
+            L.orc_glevel_m.argtypes = [C.c_double, C.c_double, C.c_int, C.c_int, C.c_int]
             L.orc_gstar.restype = C.c_double
             L.orc_gstar.argtypes = [C.c_double, C.c_double]
             L.orc_glevel.restype = C.c_double
@@ -101,18 +111,23 @@ def _vec(f):
     return g
 
 
-gamma = _vec(lambda x: lib().orc_gamma(x))
-dgamma = _vec(lambda x: lib().orc_dgamma(x))
+def gamma(rho, m: int = 2):
+    """Smoothing function of order m (degree 2m); m = 2 is the paper's."""
+    return _vec(lambda x: lib().orc_gamma_m(x, int(m)))(rho)
+
+
+def dgamma(rho, m: int = 2):
+    return _vec(lambda x: lib().orc_dgamma_m(x, int(m)))(rho)
 Phi = _vec(lambda x: lib().orc_Phi(x))
 dPhi = _vec(lambda x: lib().orc_dPhi(x))
 
 
-def gstar(r, a):
-    return _vec(lambda x: lib().orc_gstar(x, float(a)))(r)
+def gstar(r, a, m: int = 2):
+    return _vec(lambda x: lib().orc_gstar_m(x, float(a), int(m)))(r)
 
 
-def glevel(r, a, k, l):
-    return _vec(lambda x: lib().orc_glevel(x, float(a), int(k), int(l)))(r)
+def glevel(r, a, k, l, m: int = 2):
+    return _vec(lambda x: lib().orc_glevel_m(x, float(a), int(k), int(l), int(m)))(r)
 
 
 def threads() -> int:

@@ -33,20 +33,44 @@
 /* Threads the OpenMP loops of this library use. */
 int orc_threads(void) { return omp_get_max_threads(); }
 
-/* ---- Section 3, smoothing function gamma: even Taylor polynomial for rho < 1,
- *      1/rho beyond. ---- */
-double orc_gamma(double rho)
+/* ---- Section 3, smoothing function gamma of degree 2m: for rho < 1 the
+ *      Taylor polynomial of (rho^2)^(-1/2) about rho^2 = 1 up to the
+ *      (rho^2 - 1)^m term, which joins 1/rho with m continuous derivatives;
+ *      1/rho beyond. m = 2 is the even quartic the paper selects. ---- */
+static double binom_mhalf(int k)   /* binomial coefficient (-1/2 choose k) */
 {
-    if (rho >= 1.0) return 1.0 / rho;
-    double r2 = rho * rho;
-    return 15.0 / 8.0 - (5.0 / 4.0) * r2 + (3.0 / 8.0) * r2 * r2;
+    double c = 1.0;
+    for (int i = 0; i < k; i++) c *= (-0.5 - i) / (i + 1);
+    return c;
 }
 
-double orc_dgamma(double rho)
+double orc_gamma_m(double rho, int m)
+{
+    if (rho >= 1.0) return 1.0 / rho;
+    double s = rho * rho - 1.0, term = 1.0, acc = 0.0;
+    for (int k = 0; k <= m; k++) {
+        acc += binom_mhalf(k) * term;
+        term *= s;
+    }
+    return acc;
+}
+
+double orc_dgamma_m(double rho, int m)
 {
     if (rho >= 1.0) return -1.0 / (rho * rho);
-    return -(5.0 / 2.0) * rho + (3.0 / 2.0) * rho * rho * rho;
+    /* d/drho (rho^2 - 1)^k = 2 k rho (rho^2 - 1)^(k-1) */
+    double s = rho * rho - 1.0, term = 1.0, acc = 0.0;
+    for (int k = 1; k <= m; k++) {
+        acc += binom_mhalf(k) * k * term;
+        term *= s;
+    }
+    return 2.0 * rho * acc;
 }
+
+double orc_gamma(double rho) { return orc_gamma_m(rho, 2); }
+double orc_dgamma(double rho) { return orc_dgamma_m(rho, 2); }
+
+static int smooth_of(const orc_params *p) { return p->smoothing > 0 ? p->smoothing : 2; }
 
 /* ---- Section 3, nodal basis Phi: cubic numerical Hermite interpolant of the
  *      cardinal data. Node values c(n) = [n == 0]; node slopes are the central
@@ -79,17 +103,21 @@ double orc_dPhi(double t)
 }
 
 /* ---- Section 3, kernel splitting 1/r = g* + g^0 + ... + g^{l-1}. ---- */
-double orc_gstar(double r, double a) { return 1.0 / r - orc_gamma(r / a) / a; }
+double orc_gstar_m(double r, double a, int m) { return 1.0 / r - orc_gamma_m(r / a, m) / a; }
 
-double orc_dgstar(double r, double a) { return -1.0 / (r * r) - orc_dgamma(r / a) / (a * a); }
+double orc_dgstar_m(double r, double a, int m) { return -1.0 / (r * r) - orc_dgamma_m(r / a, m) / (a * a); }
 
-double orc_glevel(double r, double a, int k, int l)
+double orc_glevel_m(double r, double a, int k, int l, int m)
 {
     double ak = ldexp(a, k);
-    if (k == l - 1) return orc_gamma(r / ak) / ak;
+    if (k == l - 1) return orc_gamma_m(r / ak, m) / ak;
     double ak1 = ldexp(a, k + 1);
-    return orc_gamma(r / ak) / ak - orc_gamma(r / ak1) / ak1;
+    return orc_gamma_m(r / ak, m) / ak - orc_gamma_m(r / ak1, m) / ak1;
 }
+
+double orc_gstar(double r, double a) { return orc_gstar_m(r, a, 2); }
+double orc_dgstar(double r, double a) { return orc_dgstar_m(r, a, 2); }
+double orc_glevel(double r, double a, int k, int l) { return orc_glevel_m(r, a, k, l, 2); }
 
 /* ---- grids ---- */
 int orc_levels(const orc_params *p)
@@ -210,6 +238,7 @@ static void short_range(const orc_params *p, int64_t n, const double *xyz, const
         head[cid] = i;
     }
     double a = p->a;
+    const int m = smooth_of(p);
 #pragma omp parallel for schedule(dynamic, 64)
     for (int64_t i = 0; i < n; i++) {
         double ui = 0, fx = 0, fy = 0, fz = 0;
@@ -225,8 +254,8 @@ static void short_range(const orc_params *p, int64_t n, const double *xyz, const
                         double rz = xyz[3 * i + 2] - xyz[3 * j + 2];
                         double r = sqrt(rx * rx + ry * ry + rz * rz);
                         if (!(r < a)) continue;
-                        ui += orc_gstar(r, a) * q[j];
-                        double s = -orc_dgstar(r, a) / r * q[j];
+                        ui += orc_gstar_m(r, a, m) * q[j];
+                        double s = -orc_dgstar_m(r, a, m) / r * q[j];
                         fx += s * rx;
                         fy += s * ry;
                         fz += s * rz;
@@ -317,7 +346,7 @@ static void level_potential(const orc_params *p, const plan_t *pl, int k, const 
                             double dx = (nx - mx) * hk, dy = (ny - my) * hk, dz = (nz - mz) * hk;
                             double r = sqrt(dx * dx + dy * dy + dz * dz);
                             if (!top && !(r < rcut)) continue;
-                            kadd(&acc, orc_glevel(r, p->a, k, pl->l) * qk[g]);
+                            kadd(&acc, orc_glevel_m(r, p->a, k, pl->l, smooth_of(p)) * qk[g]);
                         }
                 uk[(z * dm[1] + y) * dm[0] + x] = acc.s + acc.c;
             }
@@ -420,7 +449,7 @@ int orc_msm(const orc_params *p, int64_t n, const double *xyz, const double *q,
     interpolate(p, &pl, n, xyz, ug[0], ul, gl);
 
     /* step 9: combination into per-atom potentials, energy and forces */
-    double self = orc_gamma(0.0) / p->a;
+    double self = orc_gamma_m(0.0, smooth_of(p)) / p->a;
     ksum e = {0, 0};
     for (int64_t i = 0; i < n; i++) {
         double phi = p->ke * (us[i] + ul[i] - q[i] * self);
@@ -457,6 +486,7 @@ int orc_short_subset(const orc_params *p, int64_t n, const double *xyz, const do
 {
     if (!p || n < 0 || nsel < 0 || (nsel > 0 && (!sel || !u || !f))) return -1;
     double a = p->a;
+    const int m = smooth_of(p);
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t s = 0; s < nsel; s++) {
         int64_t i = sel[s];
@@ -467,8 +497,8 @@ int orc_short_subset(const orc_params *p, int64_t n, const double *xyz, const do
             double r2 = rx * rx + ry * ry + rz * rz;
             if (!(r2 < a * a)) continue;
             double r = sqrt(r2);
-            ui += orc_gstar(r, a) * q[j];
-            double sc = -orc_dgstar(r, a) / r * q[j];
+            ui += orc_gstar_m(r, a, m) * q[j];
+            double sc = -orc_dgstar_m(r, a, m) / r * q[j];
             fx += sc * rx;
             fy += sc * ry;
             fz += sc * rz;

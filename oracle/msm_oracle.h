@@ -30,6 +30,7 @@ typedef struct {
     double ke;         /* Coulomb constant */
     int method;        /* ORC_METHOD_MSM, or ORC_METHOD_CUTOFF: the simple cutoff
                           method of Section 5 (used by the dynamics oracle) */
+    int smoothing;     /* order m of the smoothing function (degree 2m); 0 = 2 */
 } orc_params;
 
 /* Optional per-stage outputs; any pointer may be NULL. Grid arrays are
@@ -45,6 +46,9 @@ typedef struct {
 } orc_stages;
 
 int orc_threads(void);
+/* gamma of order m (degree 2m) and its derivative; the unsuffixed forms are m = 2 */
+double orc_gamma_m(double rho, int m);
+double orc_dgamma_m(double rho, int m);
 double orc_gamma(double rho);
 double orc_dgamma(double rho);
 double orc_Phi(double t);
@@ -52,6 +56,9 @@ double orc_dPhi(double t);
 double orc_gstar(double r, double a);
 double orc_dgstar(double r, double a);
 double orc_glevel(double r, double a, int k, int l);
+double orc_gstar_m(double r, double a, int m);
+double orc_dgstar_m(double r, double a, int m);
+double orc_glevel_m(double r, double a, int k, int l, int m);
 
 int orc_levels(const orc_params *p);
 int orc_grid_shape(const orc_params *p, int level, int org[3], int dim[3]);

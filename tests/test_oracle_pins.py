@@ -454,3 +454,72 @@ def test_cutoff_subset_rows_equal_the_full_evaluation(orc):
     fs, ps = orc.cutoff_subset(w.xyz, w.q, 0.7, sel, molid=mol)
     np.testing.assert_array_equal(fs, f[sel])
     np.testing.assert_array_equal(ps, p[sel])
+
+
+# --------------------------------------------------------------------------
+# smoothing functions of other orders (Section 3: gamma of degree 2m; the
+# paper selects m = 2 and names the trade-off between order and cost)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_gamma_of_order_m_joins_reciprocal_with_m_derivatives(orc, m):
+    # inside, gamma_m is an even polynomial of degree 2m: an exact fit in rho^2
+    # of degree m reproduces it, and no lower degree does
+    s = np.linspace(0.0, 0.99, 4 * m + 3)
+    vals = orc.gamma(s, m)
+    coef = np.polyfit(s ** 2, vals, m)
+    assert np.abs(np.polyval(coef, s ** 2) - vals).max() < 1e-12
+    low = np.polyfit(s ** 2, vals, m - 1)
+    assert np.abs(np.polyval(low, s ** 2) - vals).max() > 1e-4
+    # as a polynomial in rho its derivatives at rho = 1 equal those of 1/rho,
+    # (-1)^j j!, for j = 0 .. m, and the (m+1)-th does not
+    poly = np.zeros(2 * m + 1)
+    poly[::2] = coef   # highest power first: rho^(2m), rho^(2m-2), ...
+    for j in range(m + 2):
+        dj = np.polyval(np.polyder(poly, j), 1.0) if j else np.polyval(poly, 1.0)
+        if j <= m:
+            assert dj == pytest.approx((-1) ** j * math.factorial(j), rel=1e-9), j
+        else:
+            assert abs(dj - (-1) ** j * math.factorial(j)) > 1e-3
+    assert orc.gamma(1.5, m) == pytest.approx(1 / 1.5, rel=1e-15)
+    # derivative against central differences
+    for rho in [0.2, 0.7, 0.95, 1.3]:
+        fd = (orc.gamma(rho + 1e-6, m) - orc.gamma(rho - 1e-6, m)) / 2e-6
+        assert orc.dgamma(rho, m) == pytest.approx(fd, rel=1e-7, abs=1e-9)
+
+
+def test_gamma_order_two_is_the_printed_quartic(orc):
+    for rho in [0.0, 0.3, 0.77, 0.999]:
+        assert orc.gamma(rho, 2) == pytest.approx(15 / 8 - 5 / 4 * rho ** 2 + 3 / 8 * rho ** 4, rel=1e-14)
+
+
+@pytest.mark.parametrize("m", [1, 3])
+def test_splitting_of_order_m_telescopes(orc, m):
+    a, l = 1.2, 4
+    for r in [0.05, 0.3, 1.1, 2.0, 3.7, 9.0, 30.0]:
+        total = orc.gstar(r, a, m) + sum(orc.glevel(r, a, k, l, m) for k in range(l))
+        assert total == pytest.approx(1.0 / r, rel=1e-13)
+    assert orc.gstar(1.3 * a, a, m) == pytest.approx(0.0, abs=1e-15)
+
+
+@pytest.mark.parametrize("m", [1, 3])
+def test_fast_oracle_of_order_m_equals_dense_nested_formula(orc, m):
+    xyz, q, lo, hi = _tiny()
+    p = orc.OracleParams(0.5, 0.25, tuple(lo), tuple(hi), 3, 1.0, smoothing=m)
+    e, f, pot = orc.msm(p, xyz, q)
+    ed, phid, us, ul = dense.energy_potential(xyz, q, 0.5, 0.25, lo, hi, 3, pad=1, m=m)
+    assert e == pytest.approx(ed, rel=1e-13)
+    np.testing.assert_allclose(pot, phid, rtol=0, atol=1e-13 * np.abs(phid).max())
+
+
+@pytest.mark.parametrize("m", [1, 3])
+def test_msm_of_order_m_within_stated_error_of_bruteforce(orc, m):
+    w = uniform_pm(2000, 4.0, seed=1)
+    p = orc.OracleParams.of(w, smoothing=m)
+    e, f, pot = orc.msm(p, w.xyz, w.q)
+    e0, f0, p0 = orc.coulomb(w.xyz, w.q)
+    assert _rel_rms(pot, p0) < 0.01
+    assert _rel_rms(f, f0) < 0.01
+    assert abs(e - e0) / abs(e0) < 0.01
+    # the smoothing order changes the result (the self term gamma_m(0)/a differs)
+    e2, _, _ = orc.msm(orc.OracleParams.of(w), w.xyz, w.q)
+    assert e != e2
