@@ -62,9 +62,9 @@ enum { MSM_METHOD_MSM = 0, MSM_METHOD_CUTOFF = 1 };
 typedef struct msm_ctx msm_ctx;   /* opaque; owned by the library */
 
 /* Method parameters (Section 3): cutoff a, finest spacing h, number of grids
- * l, and the domain. The smoothing function is the C2 even Taylor polynomial
- * of Section 3 and the nodal basis the C1 cubic numerical Hermite interpolant
- * (p = 3), the pair the paper selects for accuracy and cost. */
+ * l, the order m of the smoothing function, and the domain. The nodal basis
+ * is the C1 cubic numerical Hermite interpolant (p = 3); with m = 2 (the even
+ * quartic, C2) this is the pair the paper selects for accuracy and cost. */
 typedef struct {
     double a;              /* short-range cutoff (nm), > 0 */
     double h;              /* finest grid spacing (nm), > 0; a/h <= 6 */
@@ -76,6 +76,10 @@ typedef struct {
     int64_t max_atoms;     /* capacity: atoms summed over a batch */
     int max_systems;       /* capacity: systems per batch */
     int method;            /* MSM_METHOD_MSM or MSM_METHOD_CUTOFF */
+    int smoothing;         /* order m of gamma (Section 3: degree 2m), 1 .. 3; 0 = 2.
+                              For rho < 1 gamma is the Taylor polynomial of
+                              (rho^2)^(-1/2) about rho^2 = 1 up to (rho^2 - 1)^m,
+                              which joins 1/rho with m continuous derivatives */
 } msm_params;
 
 /* Create a context: validates the parameters, builds the stencil weights and

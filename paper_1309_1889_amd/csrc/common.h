@@ -50,9 +50,6 @@ struct SysPlan {
     int64_t uoff[kMaxLevels];// offset of the unpadded potential grids
     int64_t group0;          // first 64-atom pair group
     int64_t ngroups;
-    int kc;                  // levels kc .. l-1 are small: their restriction and prolongation run in one
-                             // workgroup (kc = l: none)
-    int top_in_chain;        // the top level is evaluated by that workgroup too
 };
 
 __host__ __device__ inline int padded_x(int d) { return d + 2 * kGridPad + kStencilTile; }
@@ -100,12 +97,42 @@ __device__ inline int find_segment(const int64_t *prefix, int n, int64_t g)
     return lo;
 }
 
-// ---- Section 3: smoothing function gamma (C2, even quartic inside rho < 1) ----
-template <typename T> __host__ __device__ inline T gamma_s(T rho)
+// ---- Section 3: smoothing function gamma of order m (degree 2m). For rho < 1
+// it is the Taylor polynomial of (rho^2)^(-1/2) about rho^2 = 1 up to the
+// (rho^2 - 1)^m term, held here expanded in powers of rho^2:
+// gamma(rho) = c[0] + c[1] rho^2 + ... + c[m] rho^(2m); 1/rho beyond. m = 2
+// (15/8 - 5/4 rho^2 + 3/8 rho^4) is the paper's choice. ----
+constexpr int kMaxSmooth = 3;
+struct Smooth {
+    double c[kMaxSmooth + 1];
+    int m;
+};
+
+// Coefficients of gamma_m: with b_k = (-1/2 choose k),
+// sum_k b_k (rho^2 - 1)^k = sum_j rho^(2j) sum_{k >= j} b_k (k choose j) (-1)^(k-j).
+inline Smooth make_smooth(int m)
+{
+    Smooth g{};
+    g.m = m;
+    double b = 1.0;   // b_k
+    for (int k = 0; k <= m; k++) {
+        double kj = 1.0;   // (k choose j)
+        for (int j = 0; j <= k; j++) {
+            g.c[j] += b * kj * (((k - j) & 1) ? -1.0 : 1.0);
+            kj = kj * (k - j) / (j + 1);
+        }
+        b *= (-0.5 - k) / (k + 1);
+    }
+    return g;
+}
+
+template <typename T> __host__ __device__ inline T gamma_s(T rho, const Smooth &g)
 {
     if (rho >= T(1)) return T(1) / rho;
-    T r2 = rho * rho;
-    return T(1.875) + r2 * (T(-1.25) + r2 * T(0.375));
+    const T r2 = rho * rho;
+    T acc = T(g.c[g.m]);
+    for (int k = g.m - 1; k >= 0; --k) acc = acc * r2 + T(g.c[k]);
+    return acc;
 }
 
 // ---- Section 3: nodal basis Phi, the C1 cubic numerical Hermite interpolant

@@ -17,11 +17,6 @@ namespace {
 
 int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
-// A level with at most this many nodes would be handled by the one-workgroup
-// chains. Measured on the 99,999-atom water box, one workgroup is slower than
-// a launch per level already for the 512-node top grid, so the chains are off.
-constexpr int64_t kChainNodes = 0;
-
 int64_t floordiv2(int64_t v) { return v >= 0 ? v / 2 : -((-v + 1) / 2); }
 int64_t ceildiv2(int64_t v) { return -floordiv2(-v); }
 
@@ -144,8 +139,7 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     std::vector<int64_t> node_p((size_t)kMaxLevels * W);
     int64_t cells = 0, q = 0, u = 0, groups = 0, iblk = 0, top = 0, ant = 0;
     int64_t nodes[kMaxLevels] = {0};
-    int maxlev = 1, top_d2 = 0, kc_max = 0;
-    bool any_chain = false;
+    int maxlev = 1, top_d2 = 0;
     for (int s = 0; s < nsys; s++) {
         const double *lo = domains ? domains + 6 * s : c->prm.lo;
         const double *hi = domains ? domains + 6 * s + 3 : c->prm.hi;
@@ -195,19 +189,7 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
         iblk += (P.natoms + 255) / 256;
         if (g.nlev == 0) continue;   // simple cutoff method: no grids
         const int kt = g.nlev - 1;
-        // levels from kc on are small enough for one workgroup (restriction and
-        // prolongation chains); a small top level is evaluated there too
-        P.kc = g.nlev;
-        for (int k = 1; k < g.nlev; k++)
-            if ((int64_t)g.gdim[k][0] * g.gdim[k][1] * g.gdim[k][2] <= kChainNodes) {
-                P.kc = k;
-                break;
-            }
-        const int mtop = g.gdim[kt][0] * g.gdim[kt][1] * g.gdim[kt][2];
-        P.top_in_chain = (kChainNodes > 0 && mtop <= top_stage_limit()) ? 1 : 0;
-        if (!P.top_in_chain) top += top_blocks(mtop);
-        if (P.kc < g.nlev || P.top_in_chain) any_chain = true;
-        kc_max = std::max(kc_max, P.kc);
+        top += top_blocks(g.gdim[kt][0] * g.gdim[kt][1] * g.gdim[kt][2]);
         int d2 = 0;
         for (int d = 0; d < 3; d++) d2 += (g.gdim[kt][d] - 1) * (g.gdim[kt][d] - 1);
         top_d2 = std::max(top_d2, d2);
@@ -296,8 +278,6 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     dp.nant = ant;
     for (int k = 0; k < kMaxLevels; k++) dp.nnodes[k] = nodes[k];
     dp.maxlev = maxlev;
-    dp.kc_max = kc_max;
-    dp.any_chain = any_chain;
     c->host_sys = sys;
     c->last_offsets.assign(offsets, offsets + nsys + 1);
     if (domains) c->last_domains.assign(domains, domains + nsys * 6);
@@ -333,10 +313,9 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     mark(MSM_STAGE_ANTERP);
     if ((e = L::anterp(s, p, w)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_RESTRICT);
-    // large levels one launch each, then the small levels and a small top in one workgroup per system
-    for (int k = 0; k + 1 < p.maxlev && k + 1 < p.kc_max; k++)
+    // one launch per level, each for all systems of the batch
+    for (int k = 0; k + 1 < p.maxlev; k++)
         if ((e = L::restrict_level(s, p, w, k)) != hipSuccess) return MSM_ERR_HIP;
-    if (p.any_chain && (e = L::restrict_chain(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_CUTOFF);
     {
         StencilTables<T> tb{c->wcols, (const T *)c->weights, c->ncols, c->mc.reach, c->mc.stencil_threads};
@@ -345,8 +324,7 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     mark(MSM_STAGE_TOP);
     if ((e = L::top_level(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_PROLONG);
-    if (p.any_chain && (e = L::prolong_chain(s, p, w)) != hipSuccess) return MSM_ERR_HIP;
-    for (int k = std::min(p.maxlev - 2, p.kc_max - 1); k >= 0; k--)
+    for (int k = p.maxlev - 2; k >= 0; k--)
         if ((e = L::prolong_level(s, p, w, k)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_INTERP);
     if ((e = L::interp(s, p, w, c->mc, (T *)forces, (T *)pots)) != hipSuccess) return MSM_ERR_HIP;
@@ -436,7 +414,8 @@ namespace {
 // the weights g^0(h |o|) = gamma(h|o|/a)/a - gamma(h|o|/(2a))/(2a) for
 // oz = -R .. R (zero where |o|^2 > d2max: g^0 vanishes for r >= 2a).
 template <typename T>
-void stencil_tables(double a, double h, int R, int d2max, std::vector<int2> &cols, std::vector<T> &w)
+void stencil_tables(double a, double h, int R, int d2max, const Smooth &g, std::vector<int2> &cols,
+                    std::vector<T> &w)
 {
     cols.clear();
     w.clear();
@@ -449,7 +428,7 @@ void stencil_tables(double a, double h, int R, int d2max, std::vector<int2> &col
                 double g0 = 0.0;
                 if (d2 <= d2max) {
                     const double r = h * std::sqrt((double)d2);
-                    g0 = gamma_s(r / a) / a - gamma_s(r / (2 * a)) / (2 * a);
+                    g0 = gamma_s(r / a, g) / a - gamma_s(r / (2 * a), g) / (2 * a);
                 }
                 w.push_back(T(g0));
             }
@@ -460,7 +439,7 @@ template <typename T> int upload_stencil(msm_ctx *c)
 {
     std::vector<int2> cols;
     std::vector<T> w;
-    stencil_tables<T>(c->prm.a, c->prm.h, c->mc.reach, c->d2max, cols, w);
+    stencil_tables<T>(c->prm.a, c->prm.h, c->mc.reach, c->d2max, c->mc.g, cols, w);
     c->ncols = (int)cols.size();
     if (hipMalloc(&c->weights, w.size() * sizeof(T)) != hipSuccess) return MSM_ERR_HIP;
     if (hipMalloc((void **)&c->wcols, cols.size() * sizeof(int2)) != hipSuccess) return MSM_ERR_HIP;
@@ -500,6 +479,8 @@ int msm_setup(const msm_params *prm, void *stream, msm_ctx **out)
     if (prm->levels < 0 || prm->levels > kMaxLevels) return MSM_ERR_ARG;
     if (!std::isfinite(prm->coulomb_k)) return MSM_ERR_ARG;
     if (prm->method != MSM_METHOD_MSM && prm->method != MSM_METHOD_CUTOFF) return MSM_ERR_ARG;
+    const int smoothing = prm->smoothing ? prm->smoothing : 2;
+    if (smoothing < 1 || smoothing > kMaxSmooth) return MSM_ERR_UNSUPPORTED;
     const bool cutoff = prm->method == MSM_METHOD_CUTOFF;
     const double ratio = 2.0 * prm->a / prm->h;
     const int reach = (int)std::ceil(ratio) - 1;       // largest integer below 2a/h
@@ -517,6 +498,7 @@ int msm_setup(const msm_params *prm, void *stream, msm_ctx **out)
     c->mc.h = prm->h;
     c->mc.ke = prm->coulomb_k;
     c->mc.cutoff = cutoff ? 1 : 0;
+    c->mc.g = make_smooth(smoothing);
     c->mc.reach = cutoff ? 0 : reach;
     c->mc.pair_waves = 8;
     c->mc.stencil_threads = 1024;

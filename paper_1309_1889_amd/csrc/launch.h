@@ -25,8 +25,6 @@ struct DevPlan {
     int ntile_seg;               // (maxlev - 1) * nsys
     int top_d2;                  // largest squared index distance on any top grid
     int64_t natoms, ngroups, ncells, niblk, ntop, ntiles, nant;
-    int kc_max;                  // largest chain start (SysPlan::kc) over the systems
-    bool any_chain;              // some system leaves levels or its top to the chains
     int64_t nnodes[kMaxLevels];  // level-k nodes over the batch
     int maxlev;                  // largest level count in the batch
 };
@@ -65,12 +63,12 @@ template <typename T> struct StencilTables {
 
 int stencil_tile_xy(int elem_bytes, int reach);
 int top_blocks(int nodes);
-int top_stage_limit();
 int stencil_tile_z(int elem_bytes, int reach);
 
 struct MethodConst {
     double a, h, ke;
     int cutoff;                // 1: simple cutoff method (plain Coulomb below a, no grids)
+    Smooth g;                  // smoothing function gamma of order g.m
     int reach;                 // stencil reach R: largest integer with R < 2a/h
     int pair_waves;            // waves per 64-atom group in the pair kernel: 4, 8 or 16
     int stencil_threads;       // threads per stencil tile: 256 or 1024
@@ -90,8 +88,6 @@ template <typename T> struct Launch {
     static hipError_t stencil(hipStream_t s, const DevPlan &p, const Work<T> &w, const StencilTables<T> &tb);
     static hipError_t top_level(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m);
     static hipError_t prolong_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k);
-    static hipError_t restrict_chain(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m);
-    static hipError_t prolong_chain(hipStream_t s, const DevPlan &p, const Work<T> &w);
     static hipError_t interp(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m,
                              T *forces, T *potentials);
     static hipError_t energy(hipStream_t s, const DevPlan &p, const Work<T> &w, double *energy);

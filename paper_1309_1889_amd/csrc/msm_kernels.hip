@@ -240,7 +240,7 @@ template <typename T> __device__ inline void restrict_node(const SysPlan &P, T *
     qgrid[P.qoff[k + 1] + ((int64_t)(rz + kGridPad) * CY + (ry + kGridPad)) * CX + (rx + kGridPad)] = acc;
 }
 
-// one level for every system whose coarse level k+1 is not left to the chain kernel
+// one level for every system that has a level k+1
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict(DevPlan p, T *__restrict__ qgrid, int k)
 {
@@ -249,7 +249,7 @@ __global__ __launch_bounds__(256) void k_restrict(DevPlan p, T *__restrict__ qgr
     const int64_t *pref = p.node_prefix + (int64_t)(k + 1) * (p.nsys + 1);
     const int s = find_segment(pref, p.nsys, g);
     const SysPlan &P = p.sys[s];
-    if (k + 1 >= P.nlev || k + 1 >= P.kc) return;
+    if (k + 1 >= P.nlev) return;
     restrict_node<T>(P, qgrid, k, g - pref[s]);
 }
 
@@ -366,7 +366,7 @@ constexpr int kTopShares = 8;     // threads per output node (z-planes of the so
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_top(DevPlan p, const T *__restrict__ qgrid, T *__restrict__ ucut,
-                                             T *__restrict__ ugrid, double h, double a, int ntab)
+                                             T *__restrict__ ugrid, double h, double a, int ntab, Smooth g)
 {
     // weights by squared integer distance d2: gamma(h sqrt(d2) / a) / a; the
     // level's factor 2^-(l-1) is applied to the sum
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(256) void k_top(DevPlan p, const T *__restrict__ qg
     const T *q = qgrid + P.qoff[k];
     const int tid = threadIdx.x;
     for (int d2 = tid; d2 < ntab && d2 < kTopTable; d2 += 256)
-        tab[d2] = gamma_s(T(h / a) * sqrt(T(d2))) * T(1.0 / a);
+        tab[d2] = gamma_s(T(h / a) * sqrt(T(d2)), g) * T(1.0 / a);
     for (int e = tid; e < M && e < kTopStage; e += 256) {
         const int x = e % dx, y = (e / dx) % dy, z = e / (dx * dy);
         qs[e] = q[((int64_t)(z + kGridPad) * PY + (y + kGridPad)) * PX + (x + kGridPad)];
@@ -400,7 +400,7 @@ __global__ __launch_bounds__(256) void k_top(DevPlan p, const T *__restrict__ qg
                 const int e0 = (nz * dy + ny) * dx;
                 for (int nx = 0; nx < dx; ++nx) {
                     const int d2 = eyz + (nx - x) * (nx - x);
-                    const T w = d2 < kTopTable ? tab[d2] : gamma_s(T(h / a) * sqrt(T(d2))) * T(1.0 / a);
+                    const T w = d2 < kTopTable ? tab[d2] : gamma_s(T(h / a) * sqrt(T(d2)), g) * T(1.0 / a);
                     const int e = e0 + nx;
                     const T qv = e < kTopStage
                                      ? qs[e]
@@ -469,7 +469,7 @@ __device__ inline void prolong_node(const SysPlan &P, const T *__restrict__ ucut
     ugrid[o] = ucut[o] + acc;
 }
 
-// one level for every system whose fine level k is not left to the chain kernel
+// one level for every system that has a level k+1 above level k
 template <typename T>
 __global__ __launch_bounds__(256) void k_prolong(DevPlan p, const T *__restrict__ ucut, T *__restrict__ ugrid,
                                                  int k)
@@ -479,81 +479,8 @@ __global__ __launch_bounds__(256) void k_prolong(DevPlan p, const T *__restrict_
     const int64_t *pref = p.node_prefix + (int64_t)k * (p.nsys + 1);
     const int s = find_segment(pref, p.nsys, g);
     const SysPlan &P = p.sys[s];
-    if (k >= P.nlev - 1 || k >= P.kc) return;
+    if (k >= P.nlev - 1) return;
     prolong_node<T>(P, ucut, ugrid, k, g - pref[s]);
-}
-
-// ---------------------------------------------------------------------------
-// Coarse levels in one workgroup per system. The levels kc .. l-1 of a
-// system are small (a few ten thousand nodes at most), so one workgroup
-// walks them level by level with a barrier in between instead of one launch
-// per level: the restriction chain into them followed by the top level, and,
-// after the lattice cutoff, the prolongation chain down to level kc.
-// ---------------------------------------------------------------------------
-constexpr int kChainThreads = 1024;
-
-template <typename T>
-__device__ inline T top_weight(const T *tab, int d2, double h, double a)
-{
-    return d2 < kTopTable ? tab[d2] : gamma_s(T(h / a) * sqrt(T(d2))) * T(1.0 / a);
-}
-
-template <typename T>
-__global__ __launch_bounds__(kChainThreads) void k_restrict_chain(DevPlan p, T *__restrict__ qgrid,
-                                                                  T *__restrict__ ucut, T *__restrict__ ugrid,
-                                                                  double h, double a, int ntab)
-{
-    __shared__ T tab[kTopTable];
-    __shared__ T qs[kTopStage];
-    const SysPlan &P = p.sys[blockIdx.x];
-    const int tid = threadIdx.x;
-    for (int k = P.kc - 1; k + 1 < P.nlev; ++k) {
-        if (k < 0) continue;
-        const int64_t n = (int64_t)P.gdim[k + 1][0] * P.gdim[k + 1][1] * P.gdim[k + 1][2];
-        for (int64_t loc = tid; loc < n; loc += kChainThreads) restrict_node<T>(P, qgrid, k, loc);
-        __syncthreads();
-    }
-    if (!P.top_in_chain) return;
-    // top level: u^{l-1}_mu = 2^-(l-1) sum_nu gamma(h |mu - nu| / a) / a q^{l-1}_nu, all pairs
-    const int k = P.nlev - 1;
-    const int dx = P.gdim[k][0], dy = P.gdim[k][1], dz = P.gdim[k][2];
-    const int M = dx * dy * dz;
-    const int PX = padded_x(dx), PY = padded_x(dy);
-    const T *q = qgrid + P.qoff[k];
-    for (int d2 = tid; d2 < ntab && d2 < kTopTable; d2 += kChainThreads)
-        tab[d2] = gamma_s(T(h / a) * sqrt(T(d2))) * T(1.0 / a);
-    for (int e = tid; e < M; e += kChainThreads) {
-        const int x = e % dx, y = (e / dx) % dy, z = e / (dx * dy);
-        qs[e] = q[((int64_t)(z + kGridPad) * PY + (y + kGridPad)) * PX + (x + kGridPad)];
-    }
-    __syncthreads();
-    const T scale = T(ldexp(1.0, -k));
-    for (int node = tid; node < M; node += kChainThreads) {
-        const int x = node % dx, y = (node / dx) % dy, z = node / (dx * dy);
-        T acc = 0;
-        int e = 0;
-        for (int nz = 0; nz < dz; ++nz)
-            for (int ny = 0; ny < dy; ++ny) {
-                const int eyz = (nz - z) * (nz - z) + (ny - y) * (ny - y);
-                for (int nx = 0; nx < dx; ++nx, ++e) acc += top_weight(tab, eyz + (nx - x) * (nx - x), h, a) * qs[e];
-            }
-        acc *= scale;
-        const int64_t o = P.uoff[k] + node;
-        ucut[o] = acc;
-        ugrid[o] = acc;
-    }
-}
-
-template <typename T>
-__global__ __launch_bounds__(kChainThreads) void k_prolong_chain(DevPlan p, const T *__restrict__ ucut,
-                                                                 T *__restrict__ ugrid)
-{
-    const SysPlan &P = p.sys[blockIdx.x];
-    for (int k = P.nlev - 2; k >= P.kc; --k) {
-        const int64_t n = (int64_t)P.gdim[k][0] * P.gdim[k][1] * P.gdim[k][2];
-        for (int64_t loc = threadIdx.x; loc < n; loc += kChainThreads) prolong_node<T>(P, ucut, ugrid, k, loc);
-        __syncthreads();
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -760,7 +687,6 @@ hipError_t Launch<T>::stencil(hipStream_t s, const DevPlan &p, const Work<T> &w,
 }
 
 int top_blocks(int nodes) { return (nodes + kTopNodes - 1) / kTopNodes; }
-int top_stage_limit() { return kTopStage; }
 
 int stencil_tile_xy(int elem_bytes, int reach) { return (elem_bytes == 8 && reach >= 10) ? 4 : kStencilTile; }
 int stencil_tile_z(int elem_bytes, int reach) { return (elem_bytes == 8 && reach >= 10) ? 4 : kStencilTile; }
@@ -770,21 +696,7 @@ hipError_t Launch<T>::top_level(hipStream_t s, const DevPlan &p, const Work<T> &
 {
     if (p.ntop == 0) return hipSuccess;
     hipLaunchKernelGGL(k_top<T>, dim3((unsigned)p.ntop), dim3(256), 0, s, p, w.qgrid, w.ucut, w.ugrid, m.h, m.a,
-                       p.top_d2 + 1);
-    return hipGetLastError();
-}
-
-template <typename T>
-hipError_t Launch<T>::restrict_chain(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m)
-{
-    hipLaunchKernelGGL(k_restrict_chain<T>, dim3((unsigned)p.nsys), dim3(kChainThreads), 0, s, p, w.qgrid, w.ucut,
-                       w.ugrid, m.h, m.a, p.top_d2 + 1);
-    return hipGetLastError();
-}
-
-template <typename T> hipError_t Launch<T>::prolong_chain(hipStream_t s, const DevPlan &p, const Work<T> &w)
-{
-    hipLaunchKernelGGL(k_prolong_chain<T>, dim3((unsigned)p.nsys), dim3(kChainThreads), 0, s, p, w.ucut, w.ugrid);
+                       p.top_d2 + 1, m.g);
     return hipGetLastError();
 }
 
@@ -804,9 +716,9 @@ hipError_t Launch<T>::interp(hipStream_t s, const DevPlan &p, const Work<T> &w, 
     if (m.cutoff)   // simple cutoff method: no grid potential and no smooth self term
         hipLaunchKernelGGL((k_interp<T, false>), dim3((unsigned)p.niblk), dim3(kInterpThreads), 0, s, p, w.sxyzq,
                            w.shrt, w.order, (const T *)nullptr, forces, potentials, w.eparts, T(m.ke), T(0), lj);
-    else
+    else   // smooth self term gamma(0)/a
         hipLaunchKernelGGL((k_interp<T, true>), dim3((unsigned)p.niblk), dim3(kInterpThreads), 0, s, p, w.sxyzq,
-                           w.shrt, w.order, w.ugrid, forces, potentials, w.eparts, T(m.ke), T(1.875 / m.a), lj);
+                           w.shrt, w.order, w.ugrid, forces, potentials, w.eparts, T(m.ke), T(m.g.c[0] / m.a), lj);
     return hipGetLastError();
 }
 

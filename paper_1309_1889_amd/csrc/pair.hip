@@ -1,6 +1,8 @@
 // The short-range pair kernel of the multilevel summation method (Section 3),
 // also the whole evaluation of the simple cutoff method (Section 5), templated
 // on the arithmetic type T (float or double).
+#include <cmath>
+
 #include "device_util.h"
 #include "launch.h"
 
@@ -24,11 +26,11 @@ namespace {
 // the simple cutoff method.
 // ---------------------------------------------------------------------------
 template <typename T> struct PairK {
-    T a2;            // a^2
-    T reach;         // a plus a rounding margin, for the row search
-    T inv_a2;        // 1/a^2
-    T c0, c1, c2;    // gamma(r/a)/a = c0 + c1 r^2 + c2 r^4
-    T d0, d1;        // -(d/dr)(gamma(r/a)/a) / r = d0 + d1 r^2
+    T a2;               // a^2
+    T reach;            // a plus a rounding margin, for the row search
+    T inv_a2;           // 1/a^2
+    T c0, c1, c2, c3;   // gamma(r/a)/a = c0 + c1 r^2 + c2 r^4 (+ c3 r^6 for m = 3)
+    T d0, d1, d2;       // -(d/dr)(gamma(r/a)/a) / r = d0 + d1 r^2 (+ d2 r^4 for m = 3)
 };
 
 #ifndef MSMX_PAIR_UNROLL
@@ -50,8 +52,9 @@ template <typename T, bool MD> struct PairLds {
 };
 
 // POT = false: forces only (no potential or energy sums), for evaluations
-// that are asked for neither.
-template <typename T, bool MD, bool POT>
+// that are asked for neither. HIGH: the smoothing polynomial of degree 6
+// (m = 3); otherwise of degree at most 4.
+template <typename T, bool MD, bool POT, bool HIGH>
 __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const vec4_t<T> &aj, const vec4_t<T> &xj,
                                  const PairK<T> &k, T &fx, T &fy, T &fz, T &u, T &lx, T &ly, T &lz, T &le)
 {
@@ -65,9 +68,11 @@ __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const
             same = mol_of(xi) == mol_of(xj);
             rc = same ? T(0) : rinv;
         }
-        const T br = rc * rinv * rinv - (k.d0 + k.d1 * r2);
+        const T br = HIGH ? rc * rinv * rinv - (k.d0 + r2 * (k.d1 + r2 * k.d2))
+                          : rc * rinv * rinv - (k.d0 + k.d1 * r2);
         if (POT) {
-            const T gs = rc - (k.c0 + r2 * (k.c1 + r2 * k.c2));
+            const T gs = HIGH ? rc - (k.c0 + r2 * (k.c1 + r2 * (k.c2 + r2 * k.c3)))
+                              : rc - (k.c0 + r2 * (k.c1 + r2 * k.c2));
             u += aj.w * gs;
         }
         const T t = aj.w * br;
@@ -110,7 +115,7 @@ __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const
 // coalesced load (the next chunk is fetched while the current one is used),
 // and every lane reads each staged atom by broadcast and evaluates its own
 // pair. The waves' partial sums are added in a fixed order at the end.
-template <typename T, bool MD, bool POT, int kPairWaves>
+template <typename T, bool MD, bool POT, bool HIGH, int kPairWaves>
 __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                               const int *__restrict__ cstart,
                                                               vec4_t<T> *__restrict__ out, PairK<T> k,
@@ -150,10 +155,14 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
     const int nbx = bx1 - bx0 + 1, ny = cy1 - cy0 + 1;
     const int nitems = nbx * ny * (cz1 - cz0 + 1);
 
-    // The two polynomial addends are kept in vector registers: an FMA takes
-    // one scalar operand, so as kernel arguments they would be copied to
-    // vector registers again for every candidate.
-    asm volatile("" : "+v"(k.c1), "+v"(k.d0));
+    // The polynomial addends that meet a scalar multiplier in the Horner
+    // chains are kept in vector registers: an FMA takes one scalar operand,
+    // so as kernel arguments they would be copied to vector registers again
+    // for every candidate.
+    if (HIGH)
+        asm volatile("" : "+v"(k.c2), "+v"(k.d1));
+    else
+        asm volatile("" : "+v"(k.c1), "+v"(k.d0));
     T fx = 0, fy = 0, fz = 0, u = 0;
     T lx = 0, ly = 0, lz = 0, le = 0;
     // items wv, wv + W, wv + 2W, ..., 64 per batch
@@ -230,12 +239,12 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
                 }
 #pragma unroll
                 for (int v = 0; v < kPairUnroll; ++v)
-                    pair_term<T, MD, POT>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le);
+                    pair_term<T, MD, POT, HIGH>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le);
             }
             for (; t < cnt; ++t) {
                 const vec4_t<T> aj = L.atom[t];
                 const vec4_t<T> xj = MD ? L.aux[t] : aj;
-                pair_term<T, MD, POT>(ai, xi, aj, xj, k, fx, fy, fz, u, lx, ly, lz, le);
+                pair_term<T, MD, POT, HIGH>(ai, xi, aj, xj, k, fx, fy, fz, u, lx, ly, lz, le);
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -279,23 +288,30 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
     }
 }
 
-template <typename T, int NW>
+template <typename T, bool HIGH, int NW>
 static void pair_launch(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot)
 {
     const dim3 grid((unsigned)p.ngroups), block(NW * kWave);
     const vec4_t<T> *aux = (const vec4_t<T> *)w.saux;
     if (w.saux && pot)
-        hipLaunchKernelGGL((k_pair<T, true, true, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k, aux,
-                           w.shlj);
+        hipLaunchKernelGGL((k_pair<T, true, true, HIGH, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
+                           aux, w.shlj);
     else if (w.saux)
-        hipLaunchKernelGGL((k_pair<T, true, false, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k, aux,
-                           w.shlj);
+        hipLaunchKernelGGL((k_pair<T, true, false, HIGH, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
+                           aux, w.shlj);
     else if (pot)
-        hipLaunchKernelGGL((k_pair<T, false, true, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
+        hipLaunchKernelGGL((k_pair<T, false, true, HIGH, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
                            (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
     else
-        hipLaunchKernelGGL((k_pair<T, false, false, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
-                           (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+        hipLaunchKernelGGL((k_pair<T, false, false, HIGH, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt,
+                           k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+}
+
+template <typename T, int NW>
+static void pair_launch_m(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot, bool high)
+{
+    if (high) pair_launch<T, true, NW>(s, p, w, k, pot);
+    else pair_launch<T, false, NW>(s, p, w, k, pot);
 }
 
 }  // namespace
@@ -304,27 +320,34 @@ template <typename T>
 hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m, bool pot)
 {
     if (p.ngroups == 0) return hipSuccess;
-    PairK<T> k;
+    PairK<T> k{};
     const double a = m.a;
     k.a2 = T(a * a);
     k.reach = T(a * (1.0 + 1e-5));
     k.inv_a2 = T(1.0 / (a * a));
-    // gamma(r/a)/a = (15/8 - 5/4 r^2/a^2 + 3/8 r^4/a^4) / a
-    k.c0 = T(1.875 / a);
-    k.c1 = T(-1.25 / (a * a * a));
-    k.c2 = T(0.375 / (a * a * a * a * a));
-    // -(d/dr)(gamma(r/a)/a) / r = (5/2 - 3/2 r^2/a^2) / a^3
-    k.d0 = T(2.5 / (a * a * a));
-    k.d1 = T(-1.5 / (a * a * a * a * a));
-    if (m.cutoff) {
-        // simple cutoff method (Section 5): plain 1/r below a, nothing left
-        // for grids, so the smoothing polynomial is zero
-        k.c0 = k.c1 = k.c2 = k.d0 = k.d1 = T(0);
-    }
+    // gamma(r/a)/a = sum_j g_j r^(2j) / a^(2j+1) and
+    // -(d/dr)(gamma(r/a)/a) / r = -sum_{j>=1} 2 j g_j r^(2j-2) / a^(2j+1)
+    // (m = 2: 15/8 a^-1 - 5/4 a^-3 r^2 + 3/8 a^-5 r^4 and 5/2 a^-3 - 3/2 a^-5 r^2);
+    // the simple cutoff method (Section 5) has no smoothing: all zero
+    double cp[kMaxSmooth + 1] = {}, dp[kMaxSmooth] = {};
+    if (!m.cutoff)
+        for (int j = 0; j <= m.g.m; j++) {
+            const double aj = std::pow(a, 2 * j + 1);
+            cp[j] = m.g.c[j] / aj;
+            if (j >= 1) dp[j - 1] = -2.0 * j * m.g.c[j] / aj;
+        }
+    k.c0 = T(cp[0]);
+    k.c1 = T(cp[1]);
+    k.c2 = T(cp[2]);
+    k.c3 = T(cp[3]);
+    k.d0 = T(dp[0]);
+    k.d1 = T(dp[1]);
+    k.d2 = T(dp[2]);
+    const bool high = !m.cutoff && m.g.m == 3;
     switch (m.pair_waves) {
-    case 4: pair_launch<T, 4>(s, p, w, k, pot); break;
-    case 8: pair_launch<T, 8>(s, p, w, k, pot); break;
-    case 16: pair_launch<T, 16>(s, p, w, k, pot); break;
+    case 4: pair_launch_m<T, 4>(s, p, w, k, pot, high); break;
+    case 8: pair_launch_m<T, 8>(s, p, w, k, pot, high); break;
+    case 16: pair_launch_m<T, 16>(s, p, w, k, pot, high); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -41,11 +41,12 @@ def max_rel(x, ref):
     return float(np.abs(x - ref).max() / max(np.abs(ref).max(), 1e-300))
 
 
-def run_gpu(w, precision, ke=138.935458, levels=None, max_systems=1):
+def run_gpu(w, precision, ke=138.935458, levels=None, max_systems=1, smoothing=2):
     m = _lib()
     dt = np.float32 if precision == "fp32" else np.float64
     ctx = m.MsmContext(w.a, w.h, w.lo, w.hi, levels=w.levels if levels is None else levels,
-                       precision=precision, ke=ke, max_atoms=max(w.n, 1), max_systems=max_systems)
+                       precision=precision, ke=ke, max_atoms=max(w.n, 1), max_systems=max_systems,
+                       smoothing=smoothing)
     xyzq = torch.tensor(w.xyzq(dt), device="cuda")
     e, f, p = ctx.energy_forces(xyzq)
     torch.cuda.synchronize()
@@ -53,8 +54,9 @@ def run_gpu(w, precision, ke=138.935458, levels=None, max_systems=1):
     return ctx, float(e[0].item()), f.double().cpu().numpy(), p.double().cpu().numpy()
 
 
-def run_oracle(w, ke=138.935458, levels=None, stages=False):
-    p = oracle.OracleParams(w.a, w.h, tuple(w.lo), tuple(w.hi), w.levels if levels is None else levels, ke)
+def run_oracle(w, ke=138.935458, levels=None, stages=False, smoothing=0):
+    p = oracle.OracleParams(w.a, w.h, tuple(w.lo), tuple(w.hi), w.levels if levels is None else levels, ke,
+                            smoothing=smoothing)
     return oracle.msm(p, w.xyz, w.q, stages=stages)
 
 
@@ -97,6 +99,40 @@ def test_anterpolation_forms_match_oracle_per_stage(h, two_pass):
     g = ctx.stages(w.n)
     for k in range(len(st["q_grid"])):
         assert max_rel(g["q_grid"][k].cpu().numpy(), st["q_grid"][k]) < 1e-12, k
+
+
+@pytest.mark.parametrize("m", [1, 2, 3])
+def test_smoothing_orders_match_oracle_per_stage(m):
+    """gamma of order m (degree 2m) in the pair kernel, the stencil weights,
+    the top level and the self term, against the oracle's own gamma_m."""
+    w = water_box(700, (13, 13, 13), (4.1, 4.1, 4.1), seed=24)
+    ctx, e, f, p = run_gpu(w, "fp64", smoothing=m)
+    eo, fo, po, st = run_oracle(w, stages=True, smoothing=m)
+    assert e == pytest.approx(eo, rel=1e-12)
+    assert max_rel(f, fo) < 1e-11
+    assert max_rel(p, po) < 1e-11
+    g = ctx.stages(w.n)
+    assert max_rel(g["u_short"].cpu().numpy(), st["u_short"]) < 1e-12
+    assert max_rel(g["f_short"].cpu().numpy(), st["f_short"]) < 1e-12
+    for k in range(len(st["ucut_grid"])):
+        assert max_rel(g["ucut_grid"][k].cpu().numpy(), st["ucut_grid"][k]) < 1e-12, k
+
+
+@pytest.mark.parametrize("m", [1, 3])
+def test_smoothing_orders_fp32(m):
+    w = water_box(700, (13, 13, 13), (4.1, 4.1, 4.1), seed=25).as_dtype(np.float32)
+    _, e, f, p = run_gpu(w, "fp32", smoothing=m)
+    eo, fo, po = run_oracle(w, smoothing=m)
+    assert rel_rms(f, fo) < 1e-4
+    assert rel_rms(p, po) < 1e-4
+    assert e == pytest.approx(eo, rel=1e-4)
+
+
+def test_smoothing_order_out_of_range_is_rejected():
+    m = _lib()
+    with pytest.raises(m.MsmError) as ei:
+        m.MsmContext(1.2, 0.25, (0, 0, 0), (3, 3, 3), precision="fp64", max_atoms=10, smoothing=4)
+    assert ei.value.code == -6
 
 
 def test_grid_shapes_agree_with_oracle():
