@@ -37,7 +37,39 @@ def gamma(rho, m=2):
     return np.where(rho >= 1.0, outer, inner)
 
 
-def Phi(t):
+def _cardinal_hermite(t, order, stencils):
+    """Hermite interpolant of the cardinal data c(n) = [n == 0] on each unit
+    interval, with node derivatives of orders 1 .. order taken from the given
+    central-difference stencils; the interpolating polynomial on [n, n+1] is
+    found by solving its 2(order+1) end conditions."""
+    t = np.asarray(t, dtype=np.float64)
+    deg = 2 * order + 1
+    out = np.zeros_like(t)
+    n_all = np.floor(t).astype(int)
+    for n in np.unique(n_all):
+        rows, rhs = [], []
+        for end, node in ((0.0, n), (1.0, n + 1)):
+            vals = [1.0 if node == 0 else 0.0]
+            for st in stencils[:order]:
+                vals.append(sum(c * (1.0 if node + off == 0 else 0.0) for off, c in st))
+            for d, v in enumerate(vals):
+                # d-th derivative of sum_j a_j s^j at s = end
+                rows.append([math.perm(j, d) * end ** (j - d) if j >= d else 0.0 for j in range(deg + 1)])
+                rhs.append(v)
+        coef = np.linalg.solve(np.array(rows), np.array(rhs))
+        sel = n_all == n
+        s = t[sel] - n
+        out[sel] = sum(c * s ** j for j, c in enumerate(coef))
+    return out
+
+
+def Phi(t, p=3):
+    """Nodal basis of degree p: p = 3 in closed form; p = 5 from its
+    definition (slopes and second derivatives by five-point differences)."""
+    if p == 5:
+        d1 = ((-2, 1 / 12), (-1, -8 / 12), (1, 8 / 12), (2, -1 / 12))
+        d2 = ((-2, -1 / 12), (-1, 16 / 12), (0, -30 / 12), (1, 16 / 12), (2, -1 / 12))
+        return _cardinal_hermite(t, 2, (d1, d2))
     s = np.abs(np.asarray(t, dtype=np.float64))
     near = (1.0 - s) * (1.0 + s - 1.5 * s * s)
     far = -0.5 * (s - 1.0) * (2.0 - s) ** 2
@@ -63,11 +95,11 @@ def _nodes(lo, h, k, lo_idx, hi_idx):
     return np.stack([xx.ravel(), yy.ravel(), zz.ravel()], axis=1)
 
 
-def _basis(points, nodes, spacing):
-    """Matrix B[p, mu] = prod_d Phi((x_p,d - x_mu,d) / spacing)."""
+def _basis(points, nodes, spacing, p=3):
+    """Matrix B[i, mu] = prod_d Phi((x_i,d - x_mu,d) / spacing)."""
     w = np.ones((points.shape[0], nodes.shape[0]))
     for d in range(3):
-        w *= Phi((points[:, d][:, None] - nodes[:, d][None, :]) / spacing)
+        w *= Phi((points[:, d][:, None] - nodes[:, d][None, :]) / spacing, p)
     return w
 
 
@@ -76,34 +108,35 @@ def _pair_dist(x):
     return np.sqrt((diff ** 2).sum(axis=-1))
 
 
-def long_range_matrix(xyz, a, h, lo, hi, levels, pad=2, m=2):
+def long_range_matrix(xyz, a, h, lo, hi, levels, pad=2, m=2, p=3):
     """The N x N matrix of the nested grid approximation of g_a = g^0 + ... + g^{l-1}."""
     xyz = np.asarray(xyz, dtype=np.float64)
     lo = np.asarray(lo, dtype=np.float64)
     hi = np.asarray(hi, dtype=np.float64)
-    n_lo = np.full(3, -2 - pad)
-    n_hi = np.floor((hi - lo) / h).astype(int) + 3 + pad
+    S = (p + 1) // 2
+    n_lo = np.full(3, -S - pad)
+    n_hi = np.floor((hi - lo) / h).astype(int) + S + 1 + pad
     ranges = []
     for k in range(levels):
         ranges.append((n_lo.copy(), n_hi.copy()))
-        n_lo = np.floor((n_lo - 3) / 2.0).astype(int) - pad
-        n_hi = np.ceil((n_hi + 3) / 2.0).astype(int) + pad
+        n_lo = np.floor((n_lo - (2 * S - 1)) / 2.0).astype(int) - pad
+        n_hi = np.ceil((n_hi + (2 * S - 1)) / 2.0).astype(int) + pad
     nodes = [_nodes(lo, h, k, *ranges[k]) for k in range(levels)]
     Gs = [g_level(_pair_dist(nodes[k]), a, k, levels, m) for k in range(levels)]
     K = Gs[levels - 1]
     for k in range(levels - 2, -1, -1):
-        R = _basis(nodes[k], nodes[k + 1], (2.0 ** (k + 1)) * h).T   # R[mu_coarse, nu_fine]
+        R = _basis(nodes[k], nodes[k + 1], (2.0 ** (k + 1)) * h, p).T   # R[mu_coarse, nu_fine]
         K = Gs[k] + R.T @ K @ R
-    P0 = _basis(xyz, nodes[0], h)
+    P0 = _basis(xyz, nodes[0], h, p)
     return P0 @ K @ P0.T
 
 
-def energy_potential(xyz, q, a, h, lo, hi, levels, ke=1.0, pad=2, m=2):
+def energy_potential(xyz, q, a, h, lo, hi, levels, ke=1.0, pad=2, m=2, p=3):
     """Energy and per-atom potentials of the multilevel approximation, dense,
     with the smoothing function of order m."""
     xyz = np.asarray(xyz, dtype=np.float64)
     q = np.asarray(q, dtype=np.float64)
-    M = long_range_matrix(xyz, a, h, lo, hi, levels, pad, m)
+    M = long_range_matrix(xyz, a, h, lo, hi, levels, pad, m, p)
     r = _pair_dist(xyz)
     np.fill_diagonal(r, np.inf)
     S = g_star(r, a, m)

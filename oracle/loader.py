@@ -19,7 +19,7 @@ _dp = C.POINTER(C.c_double)
 class _Params(C.Structure):
     _fields_ = [("a", C.c_double), ("h", C.c_double), ("levels", C.c_int),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("ke", C.c_double), ("method", C.c_int),
-                ("smoothing", C.c_int)]
+                ("smoothing", C.c_int), ("basis", C.c_int)]
 
 
 METHOD_MSM = 0
@@ -42,20 +42,22 @@ class OracleParams:
     ke: float = 138.935458
     method: int = METHOD_MSM    # METHOD_CUTOFF: the simple cutoff method at a (dynamics oracle)
     smoothing: int = 0          # order m of gamma (degree 2m); 0 = 2
+    basis: int = 0              # degree p of Phi: 3 (0 = 3) or 5
 
     def c(self) -> _Params:
         p = _Params()
         p.a, p.h, p.levels, p.ke = float(self.a), float(self.h), int(self.levels), float(self.ke)
         p.method = int(self.method)
         p.smoothing = int(self.smoothing)
+        p.basis = int(self.basis)
         for d in range(3):
             p.lo[d] = float(self.lo[d])
             p.hi[d] = float(self.hi[d])
         return p
 
     @classmethod
-    def of(cls, w, ke: float = 138.935458, smoothing: int = 0) -> "OracleParams":
-        return cls(w.a, w.h, tuple(w.lo), tuple(w.hi), w.levels, ke, smoothing=smoothing)
+    def of(cls, w, ke: float = 138.935458, smoothing: int = 0, basis: int = 0) -> "OracleParams":
+        return cls(w.a, w.h, tuple(w.lo), tuple(w.hi), w.levels, ke, smoothing=smoothing, basis=basis)
 
 
 def lib():
@@ -67,6 +69,9 @@ def lib():
             for name in ("orc_gamma", "orc_dgamma", "orc_Phi", "orc_dPhi"):
                 getattr(L, name).restype = C.c_double
                 getattr(L, name).argtypes = [C.c_double]
+            for name in ("orc_Phi_p", "orc_dPhi_p"):
+                getattr(L, name).restype = C.c_double
+                getattr(L, name).argtypes = [C.c_double, C.c_int]
             for name in ("orc_gamma_m", "orc_dgamma_m"):
                 getattr(L, name).restype = C.c_double
                 getattr(L, name).argtypes = [C.c_double, C.c_int]
@@ -118,8 +123,13 @@ def gamma(rho, m: int = 2):
 
 def dgamma(rho, m: int = 2):
     return _vec(lambda x: lib().orc_dgamma_m(x, int(m)))(rho)
-Phi = _vec(lambda x: lib().orc_Phi(x))
-dPhi = _vec(lambda x: lib().orc_dPhi(x))
+def Phi(t, p: int = 3):
+    """Nodal basis of degree p (3: the paper's cubic Hermite; 5: quintic)."""
+    return _vec(lambda x: lib().orc_Phi_p(x, int(p)))(t)
+
+
+def dPhi(t, p: int = 3):
+    return _vec(lambda x: lib().orc_dPhi_p(x, int(p)))(t)
 
 
 def gstar(r, a, m: int = 2):

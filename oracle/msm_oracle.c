@@ -72,35 +72,75 @@ double orc_dgamma(double rho) { return orc_dgamma_m(rho, 2); }
 
 static int smooth_of(const orc_params *p) { return p->smoothing > 0 ? p->smoothing : 2; }
 
-/* ---- Section 3, nodal basis Phi: cubic numerical Hermite interpolant of the
- *      cardinal data. Node values c(n) = [n == 0]; node slopes are the central
- *      differences (c(n+1) - c(n-1)) / 2. ---- */
+/* ---- Section 3, nodal basis Phi of degree p: the Hermite interpolant of the
+ *      cardinal data c(n) = [n == 0] whose node derivatives are central
+ *      differences of the data. p = 3 (the paper's cubic numerical Hermite
+ *      interpolant): slopes (c(n+1) - c(n-1)) / 2, support |t| < 2.
+ *      p = 5 (a reading of "degree p" for the quintic): first and second
+ *      derivatives from the five-point central differences, support |t| < 3;
+ *      C2, and it reproduces polynomials up to degree 4. ---- */
 static double card(long n) { return n == 0 ? 1.0 : 0.0; }
 static double card_slope(long n) { return 0.5 * (card(n + 1) - card(n - 1)); }
-
-double orc_Phi(double t)
+static double card_d1_5(long n) { return (card(n - 2) - 8 * card(n - 1) + 8 * card(n + 1) - card(n + 2)) / 12.0; }
+static double card_d2_5(long n)
 {
-    double f = floor(t);
-    long n = (long)f;
-    double s = t - f;
-    double h00 = 2 * s * s * s - 3 * s * s + 1;
-    double h10 = s * s * s - 2 * s * s + s;
-    double h01 = -2 * s * s * s + 3 * s * s;
-    double h11 = s * s * s - s * s;
-    return card(n) * h00 + card_slope(n) * h10 + card(n + 1) * h01 + card_slope(n + 1) * h11;
+    return (-card(n - 2) + 16 * card(n - 1) - 30 * card(n) + 16 * card(n + 1) - card(n + 2)) / 12.0;
 }
 
-double orc_dPhi(double t)
+static double phi3(double t, int deriv)
 {
     double f = floor(t);
     long n = (long)f;
     double s = t - f;
+    if (!deriv) {
+        double h00 = 2 * s * s * s - 3 * s * s + 1;
+        double h10 = s * s * s - 2 * s * s + s;
+        double h01 = -2 * s * s * s + 3 * s * s;
+        double h11 = s * s * s - s * s;
+        return card(n) * h00 + card_slope(n) * h10 + card(n + 1) * h01 + card_slope(n + 1) * h11;
+    }
     double d00 = 6 * s * s - 6 * s;
     double d10 = 3 * s * s - 4 * s + 1;
     double d01 = -6 * s * s + 6 * s;
     double d11 = 3 * s * s - 2 * s;
     return card(n) * d00 + card_slope(n) * d10 + card(n + 1) * d01 + card_slope(n + 1) * d11;
 }
+
+/* quintic Hermite basis on [0, 1]: value, first and second derivative at 0
+ * (e0, e1, e2) and at 1 (f0, f1, f2), or their derivatives in s */
+static double phi5(double t, int deriv)
+{
+    double f = floor(t);
+    long n = (long)f;
+    double s = t - f, s2 = s * s, s3 = s2 * s, s4 = s3 * s, s5 = s4 * s;
+    double e0, e1, e2, f0, f1, f2;
+    if (!deriv) {
+        e0 = 1 - 10 * s3 + 15 * s4 - 6 * s5;
+        e1 = s - 6 * s3 + 8 * s4 - 3 * s5;
+        e2 = 0.5 * s2 - 1.5 * s3 + 1.5 * s4 - 0.5 * s5;
+        f0 = 10 * s3 - 15 * s4 + 6 * s5;
+        f1 = -4 * s3 + 7 * s4 - 3 * s5;
+        f2 = 0.5 * s3 - s4 + 0.5 * s5;
+    } else {
+        e0 = -30 * s2 + 60 * s3 - 30 * s4;
+        e1 = 1 - 18 * s2 + 32 * s3 - 15 * s4;
+        e2 = s - 4.5 * s2 + 6 * s3 - 2.5 * s4;
+        f0 = 30 * s2 - 60 * s3 + 30 * s4;
+        f1 = -12 * s2 + 28 * s3 - 15 * s4;
+        f2 = 1.5 * s2 - 4 * s3 + 2.5 * s4;
+    }
+    return card(n) * e0 + card_d1_5(n) * e1 + card_d2_5(n) * e2 + card(n + 1) * f0 + card_d1_5(n + 1) * f1 +
+           card_d2_5(n + 1) * f2;
+}
+
+double orc_Phi_p(double t, int p) { return p == 5 ? phi5(t, 0) : phi3(t, 0); }
+double orc_dPhi_p(double t, int p) { return p == 5 ? phi5(t, 1) : phi3(t, 1); }
+double orc_Phi(double t) { return phi3(t, 0); }
+double orc_dPhi(double t) { return phi3(t, 1); }
+
+static int basis_of(const orc_params *p) { return p->basis == 5 ? 5 : 3; }
+/* half-width S of the support of Phi: |t| < S, S = (p + 1) / 2 */
+static int support_of(const orc_params *p) { return (basis_of(p) + 1) / 2; }
 
 /* ---- Section 3, kernel splitting 1/r = g* + g^0 + ... + g^{l-1}. ---- */
 double orc_gstar_m(double r, double a, int m) { return 1.0 / r - orc_gamma_m(r / a, m) / a; }
@@ -141,12 +181,15 @@ int orc_grid_shape(const orc_params *p, int level, int org[3], int dim[3])
 {
     int l = orc_levels(p);
     if (level < 0 || level >= l) return -1;
+    /* level 0: every node an atom in [lo, hi] reaches, base - (S-1) .. base + S;
+     * level k+1: every node whose restriction window 2 mu -+ (2S-1) meets level k */
+    const long S = support_of(p), W = 2 * S - 1;
     for (int d = 0; d < 3; d++) {
-        long i0 = -1;
-        long i1 = (long)floor((p->hi[d] - p->lo[d]) / p->h) + 2;
+        long i0 = -(S - 1);
+        long i1 = (long)floor((p->hi[d] - p->lo[d]) / p->h) + S;
         for (int k = 0; k < level; k++) {
-            i0 = ceildiv2(i0 - 3);
-            i1 = floordiv2(i1 + 3);
+            i0 = ceildiv2(i0 - W);
+            i1 = floordiv2(i1 + W);
         }
         org[d] = (int)i0;
         dim[d] = (int)(i1 - i0 + 1);
@@ -156,6 +199,7 @@ int orc_grid_shape(const orc_params *p, int level, int org[3], int dim[3])
 
 typedef struct {
     int l;
+    int p, S;   /* basis degree and support half-width */
     int org[ORC_MAXLEV][3];
     int dim[ORC_MAXLEV][3];
     int64_t size[ORC_MAXLEV];
@@ -164,6 +208,8 @@ typedef struct {
 static void make_plan(const orc_params *p, plan_t *pl)
 {
     pl->l = orc_levels(p);
+    pl->p = basis_of(p);
+    pl->S = support_of(p);
     for (int k = 0; k < pl->l; k++) {
         orc_grid_shape(p, k, pl->org[k], pl->dim[k]);
         pl->size[k] = (int64_t)pl->dim[k][0] * pl->dim[k][1] * pl->dim[k][2];
@@ -272,7 +318,7 @@ static void short_range(const orc_params *p, int64_t n, const double *xyz, const
 }
 
 /* ---- Section 3, anterpolation: q^0_mu = sum_j phi^0_mu(r_j) q_j, written as a
- *      scatter from each atom to the 4x4x4 nodes around it. ---- */
+ *      scatter from each atom to the (2S)^3 nodes around it. ---- */
 static void anterpolate(const orc_params *p, const plan_t *pl, int64_t n, const double *xyz,
                         const double *q, double *q0)
 {
@@ -284,10 +330,11 @@ static void anterpolate(const orc_params *p, const plan_t *pl, int64_t n, const 
             t[d] = (xyz[3 * j + d] - p->lo[d]) / p->h;
             base[d] = (long)floor(t[d]);
         }
-        for (long mz = base[2] - 1; mz <= base[2] + 2; mz++)
-            for (long my = base[1] - 1; my <= base[1] + 2; my++)
-                for (long mx = base[0] - 1; mx <= base[0] + 2; mx++) {
-                    double w = orc_Phi(t[0] - mx) * orc_Phi(t[1] - my) * orc_Phi(t[2] - mz);
+        const long S = pl->S;
+        for (long mz = base[2] - (S - 1); mz <= base[2] + S; mz++)
+            for (long my = base[1] - (S - 1); my <= base[1] + S; my++)
+                for (long mx = base[0] - (S - 1); mx <= base[0] + S; mx++) {
+                    double w = orc_Phi_p(t[0] - mx, pl->p) * orc_Phi_p(t[1] - my, pl->p) * orc_Phi_p(t[2] - mz, pl->p);
                     if (w == 0.0) continue;
                     int64_t g = gidx(pl, 0, mx, my, mz);
                     q0[g] += w * q[j];
@@ -308,13 +355,14 @@ static void restrict_level(const plan_t *pl, int k, const double *qk, double *qk
             for (long cx = 0; cx < dc[0]; cx++) {
                 long mx = cx + oc[0], my = cy + oc[1], mz = cz + oc[2];
                 double acc = 0;
-                for (long nz = 2 * mz - 3; nz <= 2 * mz + 3; nz++)
-                    for (long ny = 2 * my - 3; ny <= 2 * my + 3; ny++)
-                        for (long nx = 2 * mx - 3; nx <= 2 * mx + 3; nx++) {
+                const long W = 2 * pl->S - 1;
+                for (long nz = 2 * mz - W; nz <= 2 * mz + W; nz++)
+                    for (long ny = 2 * my - W; ny <= 2 * my + W; ny++)
+                        for (long nx = 2 * mx - W; nx <= 2 * mx + W; nx++) {
                             int64_t g = gidx(pl, k, nx, ny, nz);
                             if (g < 0) continue;
-                            double w = orc_Phi((nx - 2.0 * mx) / 2.0) * orc_Phi((ny - 2.0 * my) / 2.0) *
-                                       orc_Phi((nz - 2.0 * mz) / 2.0);
+                            double w = orc_Phi_p((nx - 2.0 * mx) / 2.0, pl->p) * orc_Phi_p((ny - 2.0 * my) / 2.0, pl->p) *
+                                       orc_Phi_p((nz - 2.0 * mz) / 2.0, pl->p);
                             acc += w * qk[g];
                         }
                 qk1[(cz * dc[1] + cy) * dc[0] + cx] = acc;
@@ -363,11 +411,12 @@ static void prolong_level(const plan_t *pl, int k, const double *uk1, double *uk
             for (long x = 0; x < dm[0]; x++) {
                 long mx = x + o[0], my = y + o[1], mz = z + o[2];
                 double acc = 0;
-                for (long nz = floordiv2(mz - 3); nz <= floordiv2(mz + 3) + 1; nz++)
-                    for (long ny = floordiv2(my - 3); ny <= floordiv2(my + 3) + 1; ny++)
-                        for (long nx = floordiv2(mx - 3); nx <= floordiv2(mx + 3) + 1; nx++) {
-                            double w = orc_Phi((mx - 2.0 * nx) / 2.0) * orc_Phi((my - 2.0 * ny) / 2.0) *
-                                       orc_Phi((mz - 2.0 * nz) / 2.0);
+                const long W = 2 * pl->S - 1;
+                for (long nz = floordiv2(mz - W); nz <= floordiv2(mz + W) + 1; nz++)
+                    for (long ny = floordiv2(my - W); ny <= floordiv2(my + W) + 1; ny++)
+                        for (long nx = floordiv2(mx - W); nx <= floordiv2(mx + W) + 1; nx++) {
+                            double w = orc_Phi_p((mx - 2.0 * nx) / 2.0, pl->p) * orc_Phi_p((my - 2.0 * ny) / 2.0, pl->p) *
+                                       orc_Phi_p((mz - 2.0 * nz) / 2.0, pl->p);
                             if (w == 0.0) continue;
                             int64_t g = gidx(pl, k + 1, nx, ny, nz);
                             /* every node with a non-zero weight lies in the coarse range */
@@ -391,13 +440,15 @@ static void interpolate(const orc_params *p, const plan_t *pl, int64_t n, const 
             base[d] = (long)floor(t[d]);
         }
         double u = 0, gx = 0, gy = 0, gz = 0;
-        for (long mz = base[2] - 1; mz <= base[2] + 2; mz++)
-            for (long my = base[1] - 1; my <= base[1] + 2; my++)
-                for (long mx = base[0] - 1; mx <= base[0] + 2; mx++) {
+        const long S = pl->S;
+        const int pd = pl->p;
+        for (long mz = base[2] - (S - 1); mz <= base[2] + S; mz++)
+            for (long my = base[1] - (S - 1); my <= base[1] + S; my++)
+                for (long mx = base[0] - (S - 1); mx <= base[0] + S; mx++) {
                     int64_t g = gidx(pl, 0, mx, my, mz);
-                    double px = orc_Phi(t[0] - mx), py = orc_Phi(t[1] - my), pz = orc_Phi(t[2] - mz);
-                    double dx = orc_dPhi(t[0] - mx) / p->h, dy = orc_dPhi(t[1] - my) / p->h,
-                           dz = orc_dPhi(t[2] - mz) / p->h;
+                    double px = orc_Phi_p(t[0] - mx, pd), py = orc_Phi_p(t[1] - my, pd), pz = orc_Phi_p(t[2] - mz, pd);
+                    double dx = orc_dPhi_p(t[0] - mx, pd) / p->h, dy = orc_dPhi_p(t[1] - my, pd) / p->h,
+                           dz = orc_dPhi_p(t[2] - mz, pd) / p->h;
                     double v = u0[g];
                     u += px * py * pz * v;
                     gx += dx * py * pz * v;

@@ -31,6 +31,7 @@ typedef struct {
     int method;        /* ORC_METHOD_MSM, or ORC_METHOD_CUTOFF: the simple cutoff
                           method of Section 5 (used by the dynamics oracle) */
     int smoothing;     /* order m of the smoothing function (degree 2m); 0 = 2 */
+    int basis;         /* degree p of the nodal basis Phi: 3 (0 means 3) or 5 */
 } orc_params;
 
 /* Optional per-stage outputs; any pointer may be NULL. Grid arrays are
@@ -52,6 +53,8 @@ double orc_dgamma_m(double rho, int m);
 double orc_gamma(double rho);
 double orc_dgamma(double rho);
 double orc_Phi(double t);
+double orc_Phi_p(double t, int p);
+double orc_dPhi_p(double t, int p);
 double orc_dPhi(double t);
 double orc_gstar(double r, double a);
 double orc_dgstar(double r, double a);

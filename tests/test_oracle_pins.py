@@ -523,3 +523,88 @@ def test_msm_of_order_m_within_stated_error_of_bruteforce(orc, m):
     # the smoothing order changes the result (the self term gamma_m(0)/a differs)
     e2, _, _ = orc.msm(orc.OracleParams.of(w), w.xyz, w.q)
     assert e != e2
+
+
+# --------------------------------------------------------------------------
+# the quintic nodal basis (Section 3: Phi of degree p; the paper selects p = 3)
+# --------------------------------------------------------------------------
+def test_quintic_basis_interpolates_and_reproduces_quartics(orc):
+    nodes = np.arange(-4, 5).astype(float)
+    np.testing.assert_array_equal(orc.Phi(nodes, 5), (nodes == 0).astype(float))
+    # support |t| < 3
+    for t in [3.0, 3.2, -3.0, -4.1]:
+        assert orc.Phi(t, 5) == 0.0
+    assert abs(orc.Phi(2.5, 5)) > 1e-3
+    n = np.arange(-6, 7).astype(float)
+    for x in [0.0, 0.21, 0.5, 0.93]:
+        for deg in range(5):
+            assert (orc.Phi(x - n, 5) * n ** deg).sum() == pytest.approx(x ** deg, abs=1e-13)
+    x = 0.37
+    assert abs((orc.Phi(x - n, 5) * n ** 5).sum() - x ** 5) > 1e-3
+
+
+def test_quintic_basis_is_c2(orc):
+    e = 1e-9
+    for knot in [-2.0, -1.0, 0.0, 1.0, 2.0, 3.0]:
+        assert orc.Phi(knot - e, 5) == pytest.approx(orc.Phi(knot + e, 5), abs=1e-8)
+        assert orc.dPhi(knot - e, 5) == pytest.approx(orc.dPhi(knot + e, 5), abs=1e-7)
+        # second derivative from one-sided differences of Phi'
+        d = 1e-5
+        left = (orc.dPhi(knot - e, 5) - orc.dPhi(knot - d, 5)) / (d - e)
+        right = (orc.dPhi(knot + d, 5) - orc.dPhi(knot + e, 5)) / (d - e)
+        assert left == pytest.approx(right, abs=2e-4)
+    # Phi' against central differences
+    for t in [-2.7, -1.3, -0.4, 0.2, 1.6, 2.9]:
+        fd = (orc.Phi(t + 1e-6, 5) - orc.Phi(t - 1e-6, 5)) / 2e-6
+        assert orc.dPhi(t, 5) == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_quintic_restriction_weights_are_six_point_midpoint_interpolation(orc):
+    # Phi(d/2) at odd d equals the weights of the degree-5 Lagrange polynomial
+    # through the six nodes -2 .. 3 evaluated at 1/2 (computed here from its
+    # definition), mirrored
+    nodes = np.arange(-2, 4).astype(float)
+    lag = []
+    for j, xj in enumerate(nodes):
+        others = np.delete(nodes, j)
+        lag.append(np.prod((0.5 - others) / (xj - others)))
+    # node xj sits at distance |0.5 - xj| = |d|/2 from the midpoint
+    for xj, wj in zip(nodes, lag):
+        d = 2 * (0.5 - xj)
+        assert orc.Phi(d / 2, 5) == pytest.approx(wj, abs=1e-15)
+    assert sum(orc.Phi(d / 2, 5) for d in range(-6, 7)) == pytest.approx(2.0, abs=1e-14)
+
+
+def test_quintic_basis_equals_dense_derivation(orc):
+    # the C basis uses the quintic Hermite polynomials; the dense one solves
+    # the six end conditions of each interval from scratch
+    t = np.linspace(-3.4, 3.4, 137)
+    np.testing.assert_allclose(orc.Phi(t, 5), dense.Phi(t, 5), atol=1e-14)
+
+
+def test_quintic_grid_ranges(orc):
+    p = orc.OracleParams(1.2, 0.25, (0, 0, 0), (4, 4, 4), 0, 1.0, basis=5)
+    # level 0 spans base - 2 .. base + 3 of every atom: [-2, 16 + 3]
+    assert orc.grid_shape(p, 0) == ((-2, -2, -2), (22, 22, 22))
+    # level 1: ceil((-2 - 5) / 2) = -3 .. floor((19 + 5) / 2) = 12
+    assert orc.grid_shape(p, 1) == ((-3, -3, -3), (16, 16, 16))
+
+
+@pytest.mark.parametrize("m", [2, 3])
+def test_fast_oracle_quintic_equals_dense_nested_formula(orc, m):
+    xyz, q, lo, hi = _tiny()
+    p = orc.OracleParams(0.5, 0.25, tuple(lo), tuple(hi), 3, 1.0, smoothing=m, basis=5)
+    e, f, pot = orc.msm(p, xyz, q)
+    ed, phid, us, ul = dense.energy_potential(xyz, q, 0.5, 0.25, lo, hi, 3, pad=1, m=m, p=5)
+    assert e == pytest.approx(ed, rel=1e-13)
+    np.testing.assert_allclose(pot, phid, rtol=0, atol=1e-13 * np.abs(phid).max())
+
+
+def test_quintic_with_order_three_smoothing_beats_the_cubic_pair(orc):
+    w = uniform_pm(2000, 4.0, seed=1)
+    e0, f0, p0 = orc.coulomb(w.xyz, w.q)
+    e3, f3, q3 = orc.msm(orc.OracleParams.of(w), w.xyz, w.q)
+    e5, f5, q5 = orc.msm(orc.OracleParams.of(w, smoothing=3, basis=5), w.xyz, w.q)
+    assert _rel_rms(f5, f0) < 0.5 * _rel_rms(f3, f0)
+    assert _rel_rms(q5, p0) < 0.5 * _rel_rms(q3, p0)
+    assert _rel_rms(f5, f0) < 0.01 and abs(e5 - e0) / abs(e0) < 0.01
