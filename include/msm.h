@@ -62,9 +62,10 @@ enum { MSM_METHOD_MSM = 0, MSM_METHOD_CUTOFF = 1 };
 typedef struct msm_ctx msm_ctx;   /* opaque; owned by the library */
 
 /* Method parameters (Section 3): cutoff a, finest spacing h, number of grids
- * l, the order m of the smoothing function, and the domain. The nodal basis
- * is the C1 cubic numerical Hermite interpolant (p = 3); with m = 2 (the even
- * quartic, C2) this is the pair the paper selects for accuracy and cost. */
+ * l, the order m of the smoothing function, the degree p of the nodal basis,
+ * and the domain. p = 3 (the C1 cubic numerical Hermite interpolant) with
+ * m = 2 (the C2 even quartic) is the pair the paper selects for accuracy and
+ * cost; higher orders trade cost for accuracy. */
 typedef struct {
     double a;              /* short-range cutoff (nm), > 0 */
     double h;              /* finest grid spacing (nm), > 0; a/h <= 6 */
@@ -80,6 +81,11 @@ typedef struct {
                               For rho < 1 gamma is the Taylor polynomial of
                               (rho^2)^(-1/2) about rho^2 = 1 up to (rho^2 - 1)^m,
                               which joins 1/rho with m continuous derivatives */
+    int basis;             /* degree p of the nodal basis Phi (Section 3), 3 or 5;
+                              0 = 3. p = 5: the quintic Hermite interpolant of the
+                              cardinal data with five-point central differences
+                              for the node first and second derivatives (C2,
+                              support |t| < 3: 6 nodes per axis per atom) */
 } msm_params;
 
 /* Create a context: validates the parameters, builds the stencil weights and

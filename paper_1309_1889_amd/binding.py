@@ -49,7 +49,7 @@ class _Params(C.Structure):
     _fields_ = [("a", C.c_double), ("h", C.c_double), ("levels", C.c_int), ("precision", C.c_int),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("coulomb_k", C.c_double),
                 ("max_atoms", C.c_int64), ("max_systems", C.c_int), ("method", C.c_int),
-                ("smoothing", C.c_int)]
+                ("smoothing", C.c_int), ("basis", C.c_int)]
 
 
 def lib_path() -> str:
@@ -136,11 +136,12 @@ class MsmContext:
     "fp64"; ke: Coulomb prefactor; max_atoms / max_systems: batch capacity;
     method: "msm", or "cutoff" for the simple cutoff method at a (Section 5's
     coarse propagator; h is then only the cell edge of the pair search);
-    smoothing: order m of the smoothing function (degree 2m), 1 .. 3.
+    smoothing: order m of the smoothing function (degree 2m), 1 .. 3;
+    basis: degree p of the nodal basis, 3 or 5.
     """
 
     def __init__(self, a, h, lo, hi, *, levels=0, precision="fp32", ke=138.935458,
-                 max_atoms=1 << 20, max_systems=1, stream=None, method="msm", smoothing=2):
+                 max_atoms=1 << 20, max_systems=1, stream=None, method="msm", smoothing=2, basis=3):
         import torch
         if method not in METHODS:
             raise ValueError(f"method must be one of {sorted(METHODS)}")
@@ -158,7 +159,8 @@ class MsmContext:
         p.max_systems = int(max_systems)
         p.method = METHODS[method]
         p.smoothing = int(smoothing)
-        self.smoothing = int(smoothing)
+        p.basis = int(basis)
+        self.smoothing, self.basis = int(smoothing), int(basis)
         self.params = p
         self.a, self.h, self.ke = float(a), float(h), float(ke)
         self.lo = tuple(float(v) for v in lo)

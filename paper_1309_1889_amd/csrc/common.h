@@ -156,6 +156,44 @@ template <typename T> __device__ inline T dbasis(T t)
     return t < T(0) ? -v : v;
 }
 
+// ---- Section 3: nodal basis of degree 5 (support |t| < 3), the quintic
+// Hermite interpolant of the cardinal data whose node first and second
+// derivatives are the five-point central differences; expanded here in
+// x = |t| piece by piece:
+//   [0,1): 1 - 5/4 x^2 - 35/12 x^3 + 21/4 x^4 - 25/12 x^5
+//   [1,2): -4 + 75/4 x - 245/8 x^2 + 545/24 x^3 - 63/8 x^4 + 25/24 x^5
+//   [2,3): 18 - 153/4 x + 255/8 x^2 - 313/24 x^3 + 21/8 x^4 - 5/24 x^5
+template <typename T> __device__ inline T basis5(T t)
+{
+    const T x = fabs(t);
+    if (x < T(1)) return T(1) + x * x * (T(-1.25) + x * (T(-35.0 / 12) + x * (T(5.25) + x * T(-25.0 / 12))));
+    if (x < T(2))
+        return T(-4) + x * (T(18.75) + x * (T(-30.625) + x * (T(545.0 / 24) + x * (T(-7.875) + x * T(25.0 / 24)))));
+    if (x < T(3))
+        return T(18) + x * (T(-38.25) + x * (T(31.875) + x * (T(-313.0 / 24) + x * (T(2.625) + x * T(-5.0 / 24)))));
+    return T(0);
+}
+
+template <typename T> __device__ inline T dbasis5(T t)
+{
+    const T x = fabs(t);
+    T v = T(0);
+    if (x < T(1))
+        v = x * (T(-2.5) + x * (T(-8.75) + x * (T(21) + x * T(-125.0 / 12))));
+    else if (x < T(2))
+        v = T(18.75) + x * (T(-61.25) + x * (T(545.0 / 8) + x * (T(-31.5) + x * T(125.0 / 24))));
+    else if (x < T(3))
+        v = T(-38.25) + x * (T(63.75) + x * (T(-313.0 / 8) + x * (T(10.5) + x * T(-25.0 / 24))));
+    return t < T(0) ? -v : v;
+}
+
+// Basis of degree P (3 or 5) and its support half-width S: Phi(t) = 0 for |t| >= S.
+template <int P> struct Basis {
+    static constexpr int S = (P + 1) / 2;
+    template <typename T> __device__ static T phi(T t) { return P == 5 ? basis5(t) : basis(t); }
+    template <typename T> __device__ static T dphi(T t) { return P == 5 ? dbasis5(t) : dbasis(t); }
+};
+
 // Reciprocal square root: the hardware estimate for float; for double the
 // estimate refined by two Newton-Raphson steps y <- y (3 - x y^2) / 2.
 __device__ inline float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }

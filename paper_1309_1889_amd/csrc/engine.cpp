@@ -33,6 +33,8 @@ int auto_levels(double h, const double *len)
     return kMaxLevels;
 }
 
+int basis_degree(const msm_params &prm) { return prm.basis ? prm.basis : 3; }
+
 int geometry(const msm_params &prm, const double *lo, const double *hi, Geometry &g)
 {
     double len[3];
@@ -49,13 +51,16 @@ int geometry(const msm_params &prm, const double *lo, const double *hi, Geometry
     }
     g.nlev = prm.levels > 0 ? prm.levels : auto_levels(prm.h, len);
     if (g.nlev < 1 || g.nlev > kMaxLevels) return MSM_ERR_UNSUPPORTED;
+    // level 0: the nodes base-(S-1) .. base+S of every cell; level k+1: the
+    // nodes whose restriction window 2 mu -+ (2S-1) meets level k
+    const int S = (basis_degree(prm) + 1) / 2, W = 2 * S - 1;
     for (int d = 0; d < 3; d++) {
-        int64_t i0 = -1, i1 = g.nc[d] + 1;
+        int64_t i0 = -(S - 1), i1 = (g.nc[d] - 1) + S;
         for (int k = 0; k < g.nlev; k++) {
             g.gorg[k][d] = (int)i0;
             g.gdim[k][d] = (int)(i1 - i0 + 1);
-            i0 = ceildiv2(i0 - 3);
-            i1 = floordiv2(i1 + 3);
+            i0 = ceildiv2(i0 - W);
+            i1 = floordiv2(i1 + W);
         }
     }
     return MSM_OK;
@@ -106,7 +111,9 @@ template <typename T> void carve(msm_ctx *c, Work<T> &w, char *base, size_t *use
     // uses only with more than 2 atoms per cell (so fewer cells than
     // max_atoms / 2); none without grids
     const int64_t part_cells = std::min<int64_t>(c->cap_cells, na / 2 + 1);
-    w.apart = (T *)take(c->prm.method == MSM_METHOD_CUTOFF ? 0 : sizeof(T) * kWave * part_cells);
+    const int64_t support = 2 * ((basis_degree(c->prm) + 1) / 2);   // nodes per axis an atom reaches
+    w.apart = (T *)take(c->prm.method == MSM_METHOD_CUTOFF ? 0
+                                                         : sizeof(T) * support * support * support * part_cells);
     w.qgrid = (T *)take(sizeof(T) * c->cap_q);
     w.ucut = (T *)take(sizeof(T) * c->cap_u);
     w.ugrid = (T *)take(sizeof(T) * c->cap_u);
@@ -311,11 +318,11 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     const bool pot = energy || pots || c->tuning_pass;
     if ((e = L::pair(s, p, w, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_ANTERP);
-    if ((e = L::anterp(s, p, w)) != hipSuccess) return MSM_ERR_HIP;
+    if ((e = L::anterp(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_RESTRICT);
     // one launch per level, each for all systems of the batch
     for (int k = 0; k + 1 < p.maxlev; k++)
-        if ((e = L::restrict_level(s, p, w, k)) != hipSuccess) return MSM_ERR_HIP;
+        if ((e = L::restrict_level(s, p, w, k, c->mc)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_CUTOFF);
     {
         StencilTables<T> tb{c->wcols, (const T *)c->weights, c->ncols, c->mc.reach, c->mc.stencil_threads};
@@ -325,7 +332,7 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     if ((e = L::top_level(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_PROLONG);
     for (int k = p.maxlev - 2; k >= 0; k--)
-        if ((e = L::prolong_level(s, p, w, k)) != hipSuccess) return MSM_ERR_HIP;
+        if ((e = L::prolong_level(s, p, w, k, c->mc)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_INTERP);
     if ((e = L::interp(s, p, w, c->mc, (T *)forces, (T *)pots)) != hipSuccess) return MSM_ERR_HIP;
     if ((e = L::energy(s, p, w, energy)) != hipSuccess) return MSM_ERR_HIP;
@@ -481,6 +488,7 @@ int msm_setup(const msm_params *prm, void *stream, msm_ctx **out)
     if (prm->method != MSM_METHOD_MSM && prm->method != MSM_METHOD_CUTOFF) return MSM_ERR_ARG;
     const int smoothing = prm->smoothing ? prm->smoothing : 2;
     if (smoothing < 1 || smoothing > kMaxSmooth) return MSM_ERR_UNSUPPORTED;
+    if (prm->basis != 0 && prm->basis != 3 && prm->basis != 5) return MSM_ERR_UNSUPPORTED;
     const bool cutoff = prm->method == MSM_METHOD_CUTOFF;
     const double ratio = 2.0 * prm->a / prm->h;
     const int reach = (int)std::ceil(ratio) - 1;       // largest integer below 2a/h
@@ -499,6 +507,7 @@ int msm_setup(const msm_params *prm, void *stream, msm_ctx **out)
     c->mc.ke = prm->coulomb_k;
     c->mc.cutoff = cutoff ? 1 : 0;
     c->mc.g = make_smooth(smoothing);
+    c->mc.p = basis_degree(*prm);
     c->mc.reach = cutoff ? 0 : reach;
     c->mc.pair_waves = 8;
     c->mc.stencil_threads = 1024;

@@ -69,6 +69,7 @@ struct MethodConst {
     double a, h, ke;
     int cutoff;                // 1: simple cutoff method (plain Coulomb below a, no grids)
     Smooth g;                  // smoothing function gamma of order g.m
+    int p;                     // degree of the nodal basis Phi: 3 or 5
     int reach;                 // stencil reach R: largest integer with R < 2a/h
     int pair_waves;            // waves per 64-atom group in the pair kernel: 4, 8 or 16
     int stencil_threads;       // threads per stencil tile: 256 or 1024
@@ -83,11 +84,11 @@ template <typename T> struct Launch {
     static hipError_t bin(hipStream_t s, const DevPlan &p, const Work<T> &w, const vec4_t<T> *xyzq);
     // pot = false: forces only, the short-range potentials are left at zero
     static hipError_t pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m, bool pot);
-    static hipError_t anterp(hipStream_t s, const DevPlan &p, const Work<T> &w);
-    static hipError_t restrict_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k);
+    static hipError_t anterp(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m);
+    static hipError_t restrict_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k, const MethodConst &m);
     static hipError_t stencil(hipStream_t s, const DevPlan &p, const Work<T> &w, const StencilTables<T> &tb);
     static hipError_t top_level(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m);
-    static hipError_t prolong_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k);
+    static hipError_t prolong_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k, const MethodConst &m);
     static hipError_t interp(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m,
                              T *forces, T *potentials);
     static hipError_t energy(hipStream_t s, const DevPlan &p, const Work<T> &w, double *energy);

@@ -12,38 +12,46 @@ namespace {
 
 // ---------------------------------------------------------------------------
 // Anterpolation (Section 3): q^0_mu = sum_j phi^0_mu(r_j) q_j, as a gather
-// (no atomics, fixed order) in one of two forms chosen per batch plan.
+// (no atomics, fixed order) in one of two forms chosen per batch plan. With a
+// basis of support half-width S (2 for the cubic, 3 for the quintic) an atom
+// in cell c reaches nodes c-(S-1) .. c+S, so node mu gathers from cells
+// mu-S .. mu+S-1.
 //
 // Tiled, for up to a few atoms per cell: a workgroup owns an 8x8x4 tile of
-// nodes. It stages the atoms of the 11x11x7 cells the tile can reach in LDS,
-// as grid coordinates (t = (r - lo)/h, q), row by row in x order with a table
-// of where each cell's atoms start; each thread then sums its node over the
-// atoms of the 4x4x4 cells mu-2 .. mu+1 whose support covers it. A tile whose
-// region holds more atoms than the LDS buffer gathers from global memory.
+// nodes. It stages the atoms of the (8+2S-1)x(8+2S-1)x(4+2S-1) cells the
+// tile can reach in LDS, as grid coordinates (t = (r - lo)/h, q), row by row
+// in x order with a table of where each cell's atoms start; each thread then
+// sums its node over the atoms of its (2S)^3 cells. A tile whose region holds
+// more atoms than the LDS buffer gathers from global memory.
 //
 // Two passes, for crowded cells (coarse h), whose cost does not depend on the
 // atoms per cell:
-//  1. k_anterp_cells: one wave per cell; lane (mx, my, mz) sums the weights
-//     of the cell's atoms (sorted order) on node c - 1 + m of the cell's
-//     4x4x4 support, giving 64 partial charges per cell (zero when empty).
+//  1. k_anterp_cells: one workgroup per cell; thread m sums the weights of the
+//     cell's atoms (sorted order) on node c-(S-1)+m of the cell's (2S)^3
+//     support, giving (2S)^3 partial charges per cell (zero when empty).
 //  2. k_anterp_nodes: one thread per level-0 node adds the partials of the
-//     64 cells mu-2 .. mu+1 whose support covers it, in a fixed order.
+//     (2S)^3 cells whose support covers it, in a fixed order.
 // ---------------------------------------------------------------------------
 constexpr int kAntX = 8, kAntY = 8, kAntZ = 4;
-constexpr int kAntCX = kAntX + 3, kAntCY = kAntY + 3, kAntCZ = kAntZ + 3;   // cells reached
-constexpr int kAntRows = kAntCY * kAntCZ;
-constexpr int kAntCells = kAntRows * kAntCX;
 constexpr int kAntAtoms = 3072;
 
-template <typename T>
+template <int S> struct AntTile {
+    static constexpr int CX = kAntX + 2 * S - 1, CY = kAntY + 2 * S - 1, CZ = kAntZ + 2 * S - 1;   // cells reached
+    static constexpr int Rows = CY * CZ;
+    static constexpr int Cells = Rows * CX;
+};
+
+template <typename T, int PD>
 __device__ inline T gather_global(const SysPlan &P, const vec4_t<T> *__restrict__ sx, const int *__restrict__ cstart,
                                   int ix, int iy, int iz)
 {
+    using B = Basis<PD>;
+    constexpr int S = B::S;
     const T lox = T(P.lo[0]), loy = T(P.lo[1]), loz = T(P.lo[2]), inv_h = T(P.inv_h);
-    const int cx0 = max(ix - 2, 0), cx1 = min(ix + 1, P.nc[0] - 1);
+    const int cx0 = max(ix - S, 0), cx1 = min(ix + S - 1, P.nc[0] - 1);
     T acc = 0;
-    for (int cz = max(iz - 2, 0); cz <= min(iz + 1, P.nc[2] - 1); ++cz)
-        for (int cy = max(iy - 2, 0); cy <= min(iy + 1, P.nc[1] - 1); ++cy)
+    for (int cz = max(iz - S, 0); cz <= min(iz + S - 1, P.nc[2] - 1); ++cz)
+        for (int cy = max(iy - S, 0); cy <= min(iy + S - 1, P.nc[1] - 1); ++cy)
             for (int bx = cx0 / kBrick; cx0 <= cx1 && bx <= cx1 / kBrick; ++bx) {
                 const int ca = max(cx0, bx * kBrick), cb = min(cx1, bx * kBrick + kBrick - 1);
                 const int64_t r0 = P.cell0 + cell_rank(P, ca, cy, cz);
@@ -51,18 +59,21 @@ __device__ inline T gather_global(const SysPlan &P, const vec4_t<T> *__restrict_
                 for (int j = jb; j < je; ++j) {
                     const vec4_t<T> a = sx[j];
                     const T tx = (a.x - lox) * inv_h, ty = (a.y - loy) * inv_h, tz = (a.z - loz) * inv_h;
-                    acc += basis(tx - T(ix)) * basis(ty - T(iy)) * basis(tz - T(iz)) * a.w;
+                    acc += B::phi(tx - T(ix)) * B::phi(ty - T(iy)) * B::phi(tz - T(iz)) * a.w;
                 }
             }
     return acc;
 }
 
-template <typename T>
+template <typename T, int PD>
 __global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                 const int *__restrict__ cstart, T *__restrict__ qgrid)
 {
+    using B = Basis<PD>;
+    constexpr int S = B::S;
+    using A = AntTile<S>;
     __shared__ vec4_t<T> atoms[kAntAtoms];
-    __shared__ int start[kAntCells + 1];
+    __shared__ int start[A::Cells + 1];
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int s = find_segment(p.ant_prefix, p.nsys, blk);
     const SysPlan &P = p.sys[s];
@@ -75,10 +86,10 @@ __global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__re
     const int z0 = (int)(t / ((int64_t)ntx * nty)) * kAntZ + P.gorg[0][2];
     const int tid = threadIdx.x;
 
-    // cell counts of the reachable region (cells x0-2 .. x0+kAntX, ...), 0 outside the grid
-    for (int c = tid; c < kAntCells; c += 256) {
-        const int ex = c % kAntCX, row = c / kAntCX;
-        const int cx = x0 - 2 + ex, cy = y0 - 2 + row % kAntCY, cz = z0 - 2 + row / kAntCY;
+    // cell counts of the reachable region (cells x0-S .. x0+kAntX+S-2, ...), 0 outside the grid
+    for (int c = tid; c < A::Cells; c += 256) {
+        const int ex = c % A::CX, row = c / A::CX;
+        const int cx = x0 - S + ex, cy = y0 - S + row % A::CY, cz = z0 - S + row / A::CY;
         int n = 0;
         if (cx >= 0 && cy >= 0 && cz >= 0 && cx < P.nc[0] && cy < P.nc[1] && cz < P.nc[2]) {
             const int64_t r = P.cell0 + cell_rank(P, cx, cy, cz);
@@ -88,11 +99,11 @@ __global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__re
     }
     if (tid == 0) start[0] = 0;
     __syncthreads();
-    // inclusive scan of the counts (small: one pass per thread stride, in order)
+    // inclusive scan of the counts: each lane of the first wave sums a
+    // contiguous chunk, the wave scans the chunk sums
     if (tid < kWave) {
-        // each lane sums a contiguous chunk, the wave scans the chunk sums
-        constexpr int chunk = (kAntCells + kWave - 1) / kWave;
-        const int b0 = 1 + tid * chunk, b1 = min(b0 + chunk, kAntCells + 1);
+        constexpr int chunk = (A::Cells + kWave - 1) / kWave;
+        const int b0 = 1 + tid * chunk, b1 = min(b0 + chunk, A::Cells + 1);
         int sum = 0;
         for (int i = b0; i < b1; ++i) sum += start[i];
         int incl = sum;
@@ -107,15 +118,15 @@ __global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__re
         }
     }
     __syncthreads();
-    const int total = start[kAntCells];
+    const int total = start[A::Cells];
     const bool staged = total <= kAntAtoms;
     if (staged) {
         const T lox = T(P.lo[0]), loy = T(P.lo[1]), loz = T(P.lo[2]), inv_h = T(P.inv_h);
-        for (int c = tid; c < kAntCells; c += 256) {
+        for (int c = tid; c < A::Cells; c += 256) {
             const int n = start[c + 1] - start[c];
             if (n == 0) continue;
-            const int ex = c % kAntCX, row = c / kAntCX;
-            const int cx = x0 - 2 + ex, cy = y0 - 2 + row % kAntCY, cz = z0 - 2 + row / kAntCY;
+            const int ex = c % A::CX, row = c / A::CX;
+            const int cx = x0 - S + ex, cy = y0 - S + row % A::CY, cz = z0 - S + row / A::CY;
             const int64_t r = P.cell0 + cell_rank(P, cx, cy, cz);
             const int jb = cstart[r];
             for (int k = 0; k < n; ++k) {
@@ -137,50 +148,66 @@ __global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__re
     T acc = 0;
     if (staged) {
         const T fx = T(ix), fy = T(iy), fz = T(iz);
-        for (int ez = lz; ez < lz + 4; ++ez)
-            for (int ey = ly; ey < ly + 4; ++ey) {
-                const int row = ez * kAntCY + ey;
-                const int jb = start[row * kAntCX + lx], je = start[row * kAntCX + lx + 4];
+        // the node's cells ix-S .. ix+S-1 are region columns lx .. lx+2S-1
+        for (int ez = lz; ez < lz + 2 * S; ++ez)
+            for (int ey = ly; ey < ly + 2 * S; ++ey) {
+                const int row = ez * A::CY + ey;
+                const int jb = start[row * A::CX + lx], je = start[row * A::CX + lx + 2 * S];
                 for (int j = jb; j < je; ++j) {
                     const vec4_t<T> a = atoms[j];
-                    acc += basis(a.x - fx) * basis(a.y - fy) * basis(a.z - fz) * a.w;
+                    acc += B::phi(a.x - fx) * B::phi(a.y - fy) * B::phi(a.z - fz) * a.w;
                 }
             }
     } else {
-        acc = gather_global<T>(P, sx, cstart, ix, iy, iz);
+        acc = gather_global<T, PD>(P, sx, cstart, ix, iy, iz);
     }
     const int PX = padded_x(dx), PY = padded_x(dy);
     qgrid[P.qoff[0] + ((int64_t)(rz + kGridPad) * PY + (ry + kGridPad)) * PX + (rx + kGridPad)] = acc;
 }
 
-template <typename T>
+// pass 1: 256 / (2S)^3 cells per workgroup of 256 threads (4 for the cubic,
+// one wave each; 1 for the quintic), one thread per support node
+template <int PD> constexpr int ant_cells_per_block()
+{
+    return 256 / ((2 * Basis<PD>::S) * (2 * Basis<PD>::S) * (2 * Basis<PD>::S));
+}
+
+template <typename T, int PD>
 __global__ __launch_bounds__(256) void k_anterp_cells(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                       const int *__restrict__ cstart, T *__restrict__ part)
 {
-    const int64_t c = (int64_t)blockIdx.x * (256 / kWave) + uni((int)(threadIdx.x / kWave));   // batch cell
+    using B = Basis<PD>;
+    constexpr int S = B::S, W = 2 * S, NP = W * W * W;   // partials per cell
+    constexpr int CPB = ant_cells_per_block<PD>();
+    if ((int)threadIdx.x >= CPB * NP) return;
+    // the cell index is uniform over each wave (NP is a multiple of 64 or CPB is 1)
+    const int64_t c = (int64_t)blockIdx.x * CPB + uni((int)(threadIdx.x / NP));   // batch cell
     if (c >= p.ncells) return;
-    const int lane = threadIdx.x % kWave;
+    const int m = threadIdx.x % NP;
     const int jb = uni(cstart[c]), je = uni(cstart[c + 1]);
     T acc = 0;
     if (je > jb) {
-        const int s = uni(find_segment(p.cell_prefix, p.nsys, c));
+        const int s = find_segment(p.cell_prefix, p.nsys, c);
         const SysPlan &P = p.sys[s];
         int cc[3];
         cell_coords(P, c - P.cell0, cc);
         const T lox = T(P.lo[0]), loy = T(P.lo[1]), loz = T(P.lo[2]), inv_h = T(P.inv_h);
-        const T nx = T(cc[0] - 1 + (lane & 3)), ny = T(cc[1] - 1 + ((lane >> 2) & 3)), nz = T(cc[2] - 1 + (lane >> 4));
+        const T nx = T(cc[0] - (S - 1) + m % W), ny = T(cc[1] - (S - 1) + (m / W) % W),
+                nz = T(cc[2] - (S - 1) + m / (W * W));
         for (int j = jb; j < je; ++j) {
             const vec4_t<T> a = sx[j];
-            acc += basis((a.x - lox) * inv_h - nx) * basis((a.y - loy) * inv_h - ny) *
-                   basis((a.z - loz) * inv_h - nz) * a.w;
+            acc += B::phi((a.x - lox) * inv_h - nx) * B::phi((a.y - loy) * inv_h - ny) *
+                   B::phi((a.z - loz) * inv_h - nz) * a.w;
         }
     }
-    part[c * kWave + lane] = acc;
+    part[c * NP + m] = acc;
 }
 
-template <typename T>
+// pass 2
+template <typename T, int PD>
 __global__ __launch_bounds__(256) void k_anterp_nodes(DevPlan p, const T *__restrict__ part, T *__restrict__ qgrid)
 {
+    constexpr int S = Basis<PD>::S, W = 2 * S, NP = W * W * W;
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= p.nnodes[0]) return;
     const int64_t *pref = p.node_prefix;   // level 0
@@ -191,12 +218,13 @@ __global__ __launch_bounds__(256) void k_anterp_nodes(DevPlan p, const T *__rest
     const int rx = loc % dx, ry = (loc / dx) % dy, rz = loc / (dx * dy);
     const int mx = rx + P.gorg[0][0], my = ry + P.gorg[0][1], mz = rz + P.gorg[0][2];   // absolute node
     T acc = 0;
-    for (int cz = max(mz - 2, 0); cz <= min(mz + 1, P.nc[2] - 1); ++cz)
-        for (int cy = max(my - 2, 0); cy <= min(my + 1, P.nc[1] - 1); ++cy)
-            for (int cx = max(mx - 2, 0); cx <= min(mx + 1, P.nc[0] - 1); ++cx) {
+    for (int cz = max(mz - S, 0); cz <= min(mz + S - 1, P.nc[2] - 1); ++cz)
+        for (int cy = max(my - S, 0); cy <= min(my + S - 1, P.nc[1] - 1); ++cy)
+            for (int cx = max(mx - S, 0); cx <= min(mx + S - 1, P.nc[0] - 1); ++cx) {
                 const int64_t r = P.cell0 + cell_rank(P, cx, cy, cz);
-                const int m = (mx - cx + 1) + 4 * (my - cy + 1) + 16 * (mz - cz + 1);
-                acc += part[r * kWave + m];
+                // node mu is entry mu - (c - (S-1)) of cell c's support
+                const int e = (mx - cx + S - 1) + W * (my - cy + S - 1) + W * W * (mz - cz + S - 1);
+                acc += part[r * NP + e];
             }
     const int PX = padded_x(dx), PY = padded_x(dy);
     qgrid[P.qoff[0] + ((int64_t)(rz + kGridPad) * PY + (ry + kGridPad)) * PX + (rx + kGridPad)] = acc;
@@ -205,12 +233,16 @@ __global__ __launch_bounds__(256) void k_anterp_nodes(DevPlan p, const T *__rest
 // ---------------------------------------------------------------------------
 // Restriction (Section 3): q^{k+1}_mu = sum_nu phi^{k+1}_mu(r^k_nu) q^k_nu.
 // Level-k node nu sits at coarse coordinate nu/2, so the weight is
-// prod_d Phi((nu_d - 2 mu_d)/2): per axis -1/16, 9/16, 1, 9/16, -1/16 at
-// offsets -3, -1, 0, 1, 3. The zero halo of the fine grid stands in for nodes
-// outside its range.
+// prod_d Phi((nu_d - 2 mu_d)/2), non-zero at the offsets nu_d - 2 mu_d = 0
+// and odd |d| < 2S: for the cubic 1, 9/16, -1/16 at 0, +-1, +-3; for the
+// quintic 1, 150/256, -25/256, 3/256 at 0, +-1, +-3, +-5. The zero halo of
+// the fine grid stands in for nodes outside its range.
 // ---------------------------------------------------------------------------
-template <typename T> __device__ inline void restrict_node(const SysPlan &P, T *__restrict__ qgrid, int k, int64_t loc)
+template <typename T, int PD>
+__device__ inline void restrict_node(const SysPlan &P, T *__restrict__ qgrid, int k, int64_t loc)
 {
+    using B = Basis<PD>;
+    constexpr int S = B::S, NT = 2 * S + 1;   // taps per axis
     const int cdx = P.gdim[k + 1][0], cdy = P.gdim[k + 1][1];
     const int rx = (int)(loc % cdx), ry = (int)((loc / cdx) % cdy), rz = (int)(loc / ((int64_t)cdx * cdy));
     // fine-grid relative index of the coincident node 2 mu
@@ -219,19 +251,25 @@ template <typename T> __device__ inline void restrict_node(const SysPlan &P, T *
     const int fz = 2 * (rz + P.gorg[k + 1][2]) - P.gorg[k][2];
     const int FX = padded_x(P.gdim[k][0]), FY = padded_x(P.gdim[k][1]);
     const T *qf = qgrid + P.qoff[k];
-    const int off[5] = {-3, -1, 0, 1, 3};
-    const T wt[5] = {basis(T(-1.5)), basis(T(-0.5)), T(1), basis(T(0.5)), basis(T(1.5))};
+    int off[NT];
+    T wt[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) {   // offsets -(2S-1), .., -1, 0, 1, .., 2S-1 (odd, and 0)
+        const int o = i < S ? -(2 * (S - i) - 1) : (i == S ? 0 : 2 * (i - S) - 1);
+        off[i] = o;
+        wt[i] = o == 0 ? T(1) : B::phi(T(0.5 * o));
+    }
     T acc = 0;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) {
+    for (int c = 0; c < NT; ++c) {
         const int64_t zrow = (int64_t)(fz + off[c] + kGridPad) * FY;
         T accy = 0;
 #pragma unroll
-        for (int b = 0; b < 5; ++b) {
+        for (int b = 0; b < NT; ++b) {
             const T *row = qf + (zrow + (fy + off[b] + kGridPad)) * FX + (fx + kGridPad);
             T accx = 0;
 #pragma unroll
-            for (int a = 0; a < 5; ++a) accx += wt[a] * row[off[a]];
+            for (int a = 0; a < NT; ++a) accx += wt[a] * row[off[a]];
             accy += wt[b] * accx;
         }
         acc += wt[c] * accy;
@@ -241,7 +279,7 @@ template <typename T> __device__ inline void restrict_node(const SysPlan &P, T *
 }
 
 // one level for every system that has a level k+1
-template <typename T>
+template <typename T, int PD>
 __global__ __launch_bounds__(256) void k_restrict(DevPlan p, T *__restrict__ qgrid, int k)
 {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -250,7 +288,7 @@ __global__ __launch_bounds__(256) void k_restrict(DevPlan p, T *__restrict__ qgr
     const int s = find_segment(pref, p.nsys, g);
     const SysPlan &P = p.sys[s];
     if (k + 1 >= P.nlev) return;
-    restrict_node<T>(P, qgrid, k, g - pref[s]);
+    restrict_node<T, PD>(P, qgrid, k, g - pref[s]);
 }
 
 // ---------------------------------------------------------------------------
@@ -424,17 +462,19 @@ __global__ __launch_bounds__(256) void k_top(DevPlan p, const T *__restrict__ qg
 // ---------------------------------------------------------------------------
 // Prolongation (Section 3): u^k_mu = u^{k,cutoff}_mu + sum_nu phi^{k+1}_nu(r^k_mu) u^{k+1}_nu,
 // the transpose of restriction. Per axis an even fine index 2n takes the
-// coarse node n with weight 1; an odd index 2n+1 takes n-1, n, n+1, n+2 with
-// -1/16, 9/16, 9/16, -1/16.
+// coarse node n with weight 1; an odd index 2n+1 takes the 2S coarse nodes
+// n-(S-1) .. n+S (cubic: n-1 .. n+2 with -1/16, 9/16, 9/16, -1/16).
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int PD>
 __device__ inline void prolong_node(const SysPlan &P, const T *__restrict__ ucut, T *__restrict__ ugrid, int k,
                                     int64_t loc)
 {
+    using B = Basis<PD>;
+    constexpr int S = B::S, W = 2 * S;
     const int dx = P.gdim[k][0], dy = P.gdim[k][1];
     const int r[3] = {(int)(loc % dx), (int)((loc / dx) % dy), (int)(loc / ((int64_t)dx * dy))};
-    int cn[3][4];
-    T cw[3][4];
+    int cn[3][W];
+    T cw[3][W];
     int cnt[3];
     for (int d = 0; d < 3; ++d) {
         const int m = r[d] + P.gorg[k][d];          // absolute fine index
@@ -444,12 +484,15 @@ __device__ inline void prolong_node(const SysPlan &P, const T *__restrict__ ucut
             cn[d][0] = (m >> 1) - c0;
             cw[d][0] = T(1);
         } else {
+            // the coarse nodes n-(S-1) .. n+S around m = 2n+1, at fine offsets m - 2 nu = 2S-1 .. -(2S-1)
             const int n = (m - 1) >> 1;             // floor(m/2)
-            cnt[d] = 4;
-            cn[d][0] = n - 1 - c0; cw[d][0] = basis(T(1.5));
-            cn[d][1] = n - c0;     cw[d][1] = basis(T(0.5));
-            cn[d][2] = n + 1 - c0; cw[d][2] = basis(T(-0.5));
-            cn[d][3] = n + 2 - c0; cw[d][3] = basis(T(-1.5));
+            cnt[d] = W;
+#pragma unroll
+            for (int j = 0; j < W; ++j) {
+                const int nu = n - (S - 1) + j;
+                cn[d][j] = nu - c0;
+                cw[d][j] = B::phi(T(0.5 * (m - 2 * nu)));
+            }
         }
     }
     const int cdx = P.gdim[k + 1][0], cdy = P.gdim[k + 1][1];
@@ -470,7 +513,7 @@ __device__ inline void prolong_node(const SysPlan &P, const T *__restrict__ ucut
 }
 
 // one level for every system that has a level k+1 above level k
-template <typename T>
+template <typename T, int PD>
 __global__ __launch_bounds__(256) void k_prolong(DevPlan p, const T *__restrict__ ucut, T *__restrict__ ugrid,
                                                  int k)
 {
@@ -480,7 +523,7 @@ __global__ __launch_bounds__(256) void k_prolong(DevPlan p, const T *__restrict_
     const int s = find_segment(pref, p.nsys, g);
     const SysPlan &P = p.sys[s];
     if (k >= P.nlev - 1) return;
-    prolong_node<T>(P, ucut, ugrid, k, g - pref[s]);
+    prolong_node<T, PD>(P, ucut, ugrid, k, g - pref[s]);
 }
 
 // ---------------------------------------------------------------------------
@@ -492,7 +535,7 @@ __global__ __launch_bounds__(256) void k_prolong(DevPlan p, const T *__restrict_
 // ---------------------------------------------------------------------------
 constexpr int kInterpThreads = 256;
 
-template <typename T, bool GRID>
+template <typename T, bool GRID, int PD>
 __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                            const vec4_t<T> *__restrict__ shrt,
                                                            const int *__restrict__ order,
@@ -510,26 +553,31 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4
         const vec4_t<T> a = sx[pos];
         T ul = 0, gx = 0, gy = 0, gz = 0;
         if (GRID) {
+            // the nodes base-(S-1) .. base+S of each axis
+            using B = Basis<PD>;
+            constexpr int S = B::S, W = 2 * S;
             const T inv_h = T(P.inv_h);
             const T t[3] = {(a.x - T(P.lo[0])) * inv_h, (a.y - T(P.lo[1])) * inv_h, (a.z - T(P.lo[2])) * inv_h};
-            T w[3][4], dw[3][4];
+            T w[3][W], dw[3][W];
             int base[3];
             for (int d = 0; d < 3; ++d) {
-                base[d] = cell_floor(t[d], P.nc[d]);
-                for (int m = 0; m < 4; ++m) {
-                    const T o = t[d] - T(base[d] - 1 + m);
-                    w[d][m] = basis(o);
-                    dw[d][m] = dbasis(o) * inv_h;
+                base[d] = cell_floor(t[d], P.nc[d]) - (S - 1);
+#pragma unroll
+                for (int m = 0; m < W; ++m) {
+                    const T o = t[d] - T(base[d] + m);
+                    w[d][m] = B::phi(o);
+                    dw[d][m] = B::dphi(o) * inv_h;
                 }
             }
             const int dx = P.gdim[0][0], dy = P.gdim[0][1];
             const T *u0 = ugrid + P.uoff[0];
-            for (int mz = 0; mz < 4; ++mz) {
-                for (int my = 0; my < 4; ++my) {
-                    const T *row = u0 + ((int64_t)(base[2] - 1 + mz - P.gorg[0][2]) * dy + (base[1] - 1 + my - P.gorg[0][1])) * dx +
-                                   (base[0] - 1 - P.gorg[0][0]);
+            for (int mz = 0; mz < W; ++mz) {
+                for (int my = 0; my < W; ++my) {
+                    const T *row = u0 + ((int64_t)(base[2] + mz - P.gorg[0][2]) * dy + (base[1] + my - P.gorg[0][1])) * dx +
+                                   (base[0] - P.gorg[0][0]);
                     T sx0 = 0, sdx = 0;
-                    for (int mx = 0; mx < 4; ++mx) {
+#pragma unroll
+                    for (int mx = 0; mx < W; ++mx) {
                         const T v = row[mx];
                         sx0 += w[0][mx] * v;
                         sdx += dw[0][mx] * v;
@@ -631,24 +679,37 @@ int anterp_tiles(int dx, int dy, int dz)
 // atoms per cell on average, many would overflow to the global gather.
 bool anterp_two_pass(const DevPlan &p) { return p.natoms > 2 * p.ncells; }
 
-template <typename T> hipError_t Launch<T>::anterp(hipStream_t s, const DevPlan &p, const Work<T> &w)
+template <typename T, int PD> static hipError_t anterp_p(hipStream_t s, const DevPlan &p, const Work<T> &w)
 {
-    if (p.nnodes[0] == 0) return hipSuccess;   // no grids (simple cutoff method)
     if (!anterp_two_pass(p)) {
-        hipLaunchKernelGGL(k_anterp<T>, dim3((unsigned)p.nant), dim3(256), 0, s, p, w.sxyzq, w.cell_start, w.qgrid);
+        hipLaunchKernelGGL((k_anterp<T, PD>), dim3((unsigned)p.nant), dim3(256), 0, s, p, w.sxyzq, w.cell_start,
+                           w.qgrid);
         return hipGetLastError();
     }
+    constexpr int cpb = ant_cells_per_block<PD>();
     if (p.ncells > 0)
-        hipLaunchKernelGGL(k_anterp_cells<T>, dim3((unsigned)((p.ncells + 3) / 4)), dim3(256), 0, s, p, w.sxyzq,
-                           w.cell_start, w.apart);
-    hipLaunchKernelGGL(k_anterp_nodes<T>, dim3(nblocks(p.nnodes[0], 256)), dim3(256), 0, s, p, w.apart, w.qgrid);
+        hipLaunchKernelGGL((k_anterp_cells<T, PD>), dim3((unsigned)((p.ncells + cpb - 1) / cpb)), dim3(256), 0, s, p,
+                           w.sxyzq, w.cell_start, w.apart);
+    hipLaunchKernelGGL((k_anterp_nodes<T, PD>), dim3(nblocks(p.nnodes[0], 256)), dim3(256), 0, s, p, w.apart,
+                       w.qgrid);
     return hipGetLastError();
 }
 
-template <typename T> hipError_t Launch<T>::restrict_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k)
+template <typename T>
+hipError_t Launch<T>::anterp(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m)
+{
+    if (p.nnodes[0] == 0) return hipSuccess;   // no grids (simple cutoff method)
+    return m.p == 5 ? anterp_p<T, 5>(s, p, w) : anterp_p<T, 3>(s, p, w);
+}
+
+template <typename T>
+hipError_t Launch<T>::restrict_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k, const MethodConst &m)
 {
     if (p.nnodes[k + 1] == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_restrict<T>, dim3(nblocks(p.nnodes[k + 1], 256)), dim3(256), 0, s, p, w.qgrid, k);
+    if (m.p == 5)
+        hipLaunchKernelGGL((k_restrict<T, 5>), dim3(nblocks(p.nnodes[k + 1], 256)), dim3(256), 0, s, p, w.qgrid, k);
+    else
+        hipLaunchKernelGGL((k_restrict<T, 3>), dim3(nblocks(p.nnodes[k + 1], 256)), dim3(256), 0, s, p, w.qgrid, k);
     return hipGetLastError();
 }
 
@@ -700,10 +761,14 @@ hipError_t Launch<T>::top_level(hipStream_t s, const DevPlan &p, const Work<T> &
     return hipGetLastError();
 }
 
-template <typename T> hipError_t Launch<T>::prolong_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k)
+template <typename T>
+hipError_t Launch<T>::prolong_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k, const MethodConst &m)
 {
     if (p.nnodes[k] == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_prolong<T>, dim3(nblocks(p.nnodes[k], 256)), dim3(256), 0, s, p, w.ucut, w.ugrid, k);
+    if (m.p == 5)
+        hipLaunchKernelGGL((k_prolong<T, 5>), dim3(nblocks(p.nnodes[k], 256)), dim3(256), 0, s, p, w.ucut, w.ugrid, k);
+    else
+        hipLaunchKernelGGL((k_prolong<T, 3>), dim3(nblocks(p.nnodes[k], 256)), dim3(256), 0, s, p, w.ucut, w.ugrid, k);
     return hipGetLastError();
 }
 
@@ -713,12 +778,17 @@ hipError_t Launch<T>::interp(hipStream_t s, const DevPlan &p, const Work<T> &w, 
 {
     if (p.niblk == 0) return hipSuccess;
     const vec4_t<T> *lj = (const vec4_t<T> *)(w.saux ? w.shlj : nullptr);
+    const dim3 grid((unsigned)p.niblk), block(kInterpThreads);
+    const T self = T(m.g.c[0] / m.a);   // smooth self term gamma(0)/a
     if (m.cutoff)   // simple cutoff method: no grid potential and no smooth self term
-        hipLaunchKernelGGL((k_interp<T, false>), dim3((unsigned)p.niblk), dim3(kInterpThreads), 0, s, p, w.sxyzq,
-                           w.shrt, w.order, (const T *)nullptr, forces, potentials, w.eparts, T(m.ke), T(0), lj);
-    else   // smooth self term gamma(0)/a
-        hipLaunchKernelGGL((k_interp<T, true>), dim3((unsigned)p.niblk), dim3(kInterpThreads), 0, s, p, w.sxyzq,
-                           w.shrt, w.order, w.ugrid, forces, potentials, w.eparts, T(m.ke), T(m.g.c[0] / m.a), lj);
+        hipLaunchKernelGGL((k_interp<T, false, 3>), grid, block, 0, s, p, w.sxyzq, w.shrt, w.order, (const T *)nullptr,
+                           forces, potentials, w.eparts, T(m.ke), T(0), lj);
+    else if (m.p == 5)
+        hipLaunchKernelGGL((k_interp<T, true, 5>), grid, block, 0, s, p, w.sxyzq, w.shrt, w.order, w.ugrid, forces,
+                           potentials, w.eparts, T(m.ke), self, lj);
+    else
+        hipLaunchKernelGGL((k_interp<T, true, 3>), grid, block, 0, s, p, w.sxyzq, w.shrt, w.order, w.ugrid, forces,
+                           potentials, w.eparts, T(m.ke), self, lj);
     return hipGetLastError();
 }
 

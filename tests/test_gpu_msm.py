@@ -41,12 +41,12 @@ def max_rel(x, ref):
     return float(np.abs(x - ref).max() / max(np.abs(ref).max(), 1e-300))
 
 
-def run_gpu(w, precision, ke=138.935458, levels=None, max_systems=1, smoothing=2):
+def run_gpu(w, precision, ke=138.935458, levels=None, max_systems=1, smoothing=2, basis=3):
     m = _lib()
     dt = np.float32 if precision == "fp32" else np.float64
     ctx = m.MsmContext(w.a, w.h, w.lo, w.hi, levels=w.levels if levels is None else levels,
                        precision=precision, ke=ke, max_atoms=max(w.n, 1), max_systems=max_systems,
-                       smoothing=smoothing)
+                       smoothing=smoothing, basis=basis)
     xyzq = torch.tensor(w.xyzq(dt), device="cuda")
     e, f, p = ctx.energy_forces(xyzq)
     torch.cuda.synchronize()
@@ -54,9 +54,9 @@ def run_gpu(w, precision, ke=138.935458, levels=None, max_systems=1, smoothing=2
     return ctx, float(e[0].item()), f.double().cpu().numpy(), p.double().cpu().numpy()
 
 
-def run_oracle(w, ke=138.935458, levels=None, stages=False, smoothing=0):
+def run_oracle(w, ke=138.935458, levels=None, stages=False, smoothing=0, basis=0):
     p = oracle.OracleParams(w.a, w.h, tuple(w.lo), tuple(w.hi), w.levels if levels is None else levels, ke,
-                            smoothing=smoothing)
+                            smoothing=smoothing, basis=basis)
     return oracle.msm(p, w.xyz, w.q, stages=stages)
 
 
@@ -128,10 +128,63 @@ def test_smoothing_orders_fp32(m):
     assert e == pytest.approx(eo, rel=1e-4)
 
 
+@pytest.mark.parametrize("m,h", [(2, 0.25), (3, 0.25), (3, 0.5)])
+def test_quintic_basis_matches_oracle_per_stage(m, h):
+    """The degree-5 nodal basis in anterpolation (tiles at h = 0.25, cell
+    partials at h = 0.5), restriction, prolongation and interpolation, on
+    every grid and the outputs, against the oracle."""
+    w = water_box(1500, (12, 12, 12), (3.6, 3.6, 3.6), seed=26, a=0.8, h=h)
+    ctx, e, f, p = run_gpu(w, "fp64", smoothing=m, basis=5)
+    eo, fo, po, st = run_oracle(w, stages=True, smoothing=m, basis=5)
+    assert e == pytest.approx(eo, rel=1e-12)
+    assert max_rel(f, fo) < 1e-11
+    assert max_rel(p, po) < 1e-11
+    shapes = ctx.grid_shape()
+    g = ctx.stages(w.n)
+    assert len(shapes) == len(st["q_grid"])
+    # the quintic restriction adds 7^3 terms per node (the cubic 5^3), in
+    # separable passes on the GPU and as one 3-D sum in the oracle, over grids
+    # of cancelling charges: rounding relative to the largest value reaches
+    # ~1.5e-12 on the coarse levels, so the grids are held to 1e-11
+    for k in range(len(shapes)):
+        assert tuple(g["q_grid"][k].shape) == st["q_grid"][k].shape, k
+        assert max_rel(g["q_grid"][k].cpu().numpy(), st["q_grid"][k]) < 1e-11, k
+        assert max_rel(g["u_grid"][k].cpu().numpy(), st["u_grid"][k]) < 1e-11, k
+
+
+def test_quintic_basis_fp32_and_batched():
+    m = _lib()
+    ws = [water_box(700, (13, 13, 13), (4.1, 4.1, 4.1), seed=27), water_box(300, (10, 10, 10), (3.1, 3.1, 3.1),
+                                                                            seed=28)]
+    w = ws[0].as_dtype(np.float32)
+    _, e, f, p = run_gpu(w, "fp32", smoothing=3, basis=5)
+    eo, fo, po = run_oracle(w, smoothing=3, basis=5)
+    assert rel_rms(f, fo) < 1e-4
+    assert rel_rms(p, po) < 1e-4
+    # two systems in one call equal each alone, bitwise
+    hi = np.maximum(ws[0].hi - ws[0].lo, ws[1].hi - ws[1].lo)
+    big = m.MsmContext(0.9, 0.25, np.zeros(3), hi, precision="fp32", max_atoms=ws[0].n + ws[1].n, max_systems=2,
+                       smoothing=3, basis=5)
+    x = torch.tensor(np.concatenate([v.xyzq(np.float32) for v in ws]), device="cuda")
+    offs = [0, ws[0].n, ws[0].n + ws[1].n]
+    doms = np.array([np.concatenate([v.lo, v.hi]) for v in ws])
+    eb, fb, pb = big.energy_forces(x, offs, doms)
+    torch.cuda.synchronize()
+    for k, v in enumerate(ws):
+        one = m.MsmContext(0.9, 0.25, v.lo, v.hi, precision="fp32", max_atoms=v.n, smoothing=3, basis=5)
+        e1, f1, p1 = one.energy_forces(torch.tensor(v.xyzq(np.float32), device="cuda"))
+        torch.cuda.synchronize()
+        assert torch.equal(eb[k:k + 1], e1)
+        assert torch.equal(fb[offs[k]:offs[k + 1]], f1)
+
+
 def test_smoothing_order_out_of_range_is_rejected():
     m = _lib()
     with pytest.raises(m.MsmError) as ei:
         m.MsmContext(1.2, 0.25, (0, 0, 0), (3, 3, 3), precision="fp64", max_atoms=10, smoothing=4)
+    assert ei.value.code == -6
+    with pytest.raises(m.MsmError) as ei:
+        m.MsmContext(1.2, 0.25, (0, 0, 0), (3, 3, 3), precision="fp64", max_atoms=10, basis=4)
     assert ei.value.code == -6
 
 
