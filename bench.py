@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--slices", type=int, default=32)
     ap.add_argument("--no-graphs", action="store_true", help="time eager launches only")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
+    ap.add_argument("--no-orders", action="store_true", help="skip the smoothing-order / basis-degree study")
     ap.add_argument("--no-large", action="store_true", help="skip the 12.7M-atom slab")
     ap.add_argument("--only-fp32", action="store_true",
                     help="time only the single-system FP32 path (for profiler runs)")
@@ -64,7 +65,7 @@ def parse():
     args = ap.parse_args()
     if args.only_fp32:
         args.no_fp64 = args.no_accuracy = args.no_cpu_baseline = args.no_batched = args.no_parareal = True
-        args.no_large = True
+        args.no_large = args.no_orders = True
     return args
 
 
@@ -291,6 +292,49 @@ def bench_parareal(torch, msmx, slices, n_atoms=99999):
     return out
 
 
+def exact_coulomb_rows(xyz, q, sel, ke=138.935458, chunk=64):
+    """Exact Coulomb potentials and forces of the atoms in `sel` (direct FP64
+    sums over all atoms, in NumPy): the reference of the order study."""
+    pot = np.zeros(len(sel))
+    f = np.zeros((len(sel), 3))
+    for c0 in range(0, len(sel), chunk):
+        idx = sel[c0:c0 + chunk]
+        d = xyz[idx][:, None, :] - xyz[None, :, :]
+        r2 = (d ** 2).sum(-1)
+        r2[np.arange(len(idx)), idx] = np.inf
+        rinv = 1.0 / np.sqrt(r2)
+        pot[c0:c0 + chunk] = ke * (rinv * q[None, :]).sum(1)
+        f[c0:c0 + chunk] = ke * q[idx][:, None] * ((q[None, :] * rinv ** 3)[..., None] * d).sum(1)
+    return pot, f
+
+
+def bench_orders(torch, msmx, w32, steps=20, warmup=3):
+    """Accuracy and cost of the smoothing order m and basis degree p (Section
+    3 names the trade-off): FP32 evaluation time of the water box and the
+    relative force and potential RMS error against exact Coulomb on 256
+    sampled atoms."""
+    dev = torch.device("cuda", 0)
+    n = w32.n
+    x = torch.tensor(w32.xyzq(np.float32), device=dev)
+    out = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float32, device=dev),
+           torch.empty(n, dtype=torch.float32, device=dev))
+    sel = np.sort(np.random.default_rng(81).choice(n, 256, replace=False))
+    pot_ex, f_ex = exact_coulomb_rows(w32.xyz.astype(np.float64), w32.q.astype(np.float64), sel)
+    rec = []
+    for m, p in ((2, 3), (1, 3), (3, 3), (2, 5), (3, 5)):
+        ctx = msmx.MsmContext(w32.a, w32.h, w32.lo, w32.hi, precision="fp32", max_atoms=n, smoothing=m, basis=p)
+        ms = timed_steps(torch, ctx, x, out, steps, warmup)
+        ctx.check()
+        f = out[1].double().cpu().numpy()[sel]
+        pt = out[2].double().cpu().numpy()[sel]
+        rec.append({"smoothing_m": m, "basis_p": p, "ms_per_eval": ms,
+                    "force_rel_rms_vs_exact": float(np.sqrt(((f - f_ex) ** 2).sum() / (f_ex ** 2).sum())),
+                    "potential_rel_rms_vs_exact": float(np.sqrt(((pt - pot_ex) ** 2).sum() / (pot_ex ** 2).sum()))})
+        del ctx
+    return {"workload": f"{n} atoms (water box), a {w32.a} nm, h {w32.h} nm, FP32; error on 256 sampled atoms",
+            "variants": rec}
+
+
 def bench_large(torch, msmx, steps=100, dt=0.002):
     """The paper's 30 x 65 x 65 nm box with 12,675,000 water-like atoms: one
     FP32 evaluation timed, then `steps` velocity-Verlet steps of the rigid
@@ -455,13 +499,15 @@ def main():
                 accuracy["fp64_force_rel_rms"] = rel_rms(out64[1].cpu().numpy(), fo)
                 accuracy["fp64_energy_rel"] = abs(out64[0].item() - eo) / abs(eo)
 
-    batched = uneven = par = large = None
+    batched = uneven = par = large = orders = None
     if not args.no_batched:
         batched, uneven = bench_batched(torch, msmx, w32, args.steps, args.warmup, args.slices, value)
     if not args.no_parareal:
         par = bench_parareal(torch, msmx, args.slices)
     if not args.no_large:
         large = bench_large(torch, msmx)
+    if not args.no_orders:
+        orders = bench_orders(torch, msmx, w32)
 
     result.update({
         "value": value,
@@ -487,6 +533,7 @@ def main():
         "uneven_batch": uneven,
         "parareal": par,
         "large_box": large,
+        "orders": orders,
         "launch": {"mode": launch_mode, "tuning": tuning32, "graph_ms_per_step": graph_ms,
                    "eager_default_ms_per_step": eager_default_ms, "eager_tuned_ms_per_step": eager_tuned_ms},
         "accuracy": accuracy,
