@@ -14,6 +14,7 @@ from .loader import (  # noqa: F401
     OracleParams,
     METHOD_MSM,
     METHOD_CUTOFF,
+    METHOD_WOLF,
     lib,
     gamma,
     dgamma,
@@ -27,6 +28,7 @@ from .loader import (  # noqa: F401
     coulomb,
     cutoff,
     cutoff_subset,
+    wolf,
     short_subset,
     threads,
     OracleModel,

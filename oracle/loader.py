@@ -19,11 +19,12 @@ _dp = C.POINTER(C.c_double)
 class _Params(C.Structure):
     _fields_ = [("a", C.c_double), ("h", C.c_double), ("levels", C.c_int),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("ke", C.c_double), ("method", C.c_int),
-                ("smoothing", C.c_int), ("basis", C.c_int)]
+                ("smoothing", C.c_int), ("basis", C.c_int), ("alpha", C.c_double)]
 
 
 METHOD_MSM = 0
 METHOD_CUTOFF = 1
+METHOD_WOLF = 2
 
 
 class _Stages(C.Structure):
@@ -43,6 +44,7 @@ class OracleParams:
     method: int = METHOD_MSM    # METHOD_CUTOFF: the simple cutoff method at a (dynamics oracle)
     smoothing: int = 0          # order m of gamma (degree 2m); 0 = 2
     basis: int = 0              # degree p of Phi: 3 (0 = 3) or 5
+    alpha: float = 0.0          # Wolf damping (1/nm), METHOD_WOLF only
 
     def c(self) -> _Params:
         p = _Params()
@@ -50,6 +52,7 @@ class OracleParams:
         p.method = int(self.method)
         p.smoothing = int(self.smoothing)
         p.basis = int(self.basis)
+        p.alpha = float(self.alpha)
         for d in range(3):
             p.lo[d] = float(self.lo[d])
             p.hi[d] = float(self.hi[d])
@@ -97,6 +100,9 @@ def lib():
             L.orc_cutoff.restype = C.c_int
             L.orc_cutoff.argtypes = [C.c_int64, _dp, _dp, C.POINTER(C.c_int32), C.c_double, C.c_double, _dp, _dp,
                                      _dp]
+            L.orc_wolf.restype = C.c_int
+            L.orc_wolf.argtypes = [C.c_int64, _dp, _dp, C.POINTER(C.c_int32), C.c_double, C.c_double, C.c_double,
+                                   _dp, _dp, _dp]
             L.orc_cutoff_subset.restype = C.c_int
             L.orc_cutoff_subset.argtypes = [C.c_int64, _dp, _dp, C.POINTER(C.c_int32), C.c_double, C.c_double,
                                             C.c_int64, C.POINTER(C.c_int64), _dp, _dp]
@@ -249,6 +255,23 @@ def cutoff(xyz, q, rc, ke: float = 138.935458, molid=None):
                            float(rc), float(ke), _ptr(e), _ptr(f), _ptr(pot))
     if rc_ != 0:
         raise RuntimeError(f"oracle cutoff failed with code {rc_}")
+    return float(e[0]), f, pot
+
+
+def wolf(xyz, q, rc, alpha, ke: float = 138.935458, molid=None):
+    """Wolf summation (Section 5): damped, shifted Coulomb below ``rc`` with
+    damping ``alpha`` and the self term; energy, forces and potentials."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1)
+    n = xyz.shape[0]
+    mol = None if molid is None else np.ascontiguousarray(molid, dtype=np.int32)
+    e = np.zeros(1)
+    f = np.zeros((n, 3))
+    pot = np.zeros(n)
+    rc_ = lib().orc_wolf(n, _ptr(xyz), _ptr(q), None if mol is None else mol.ctypes.data_as(C.POINTER(C.c_int32)),
+                         float(rc), float(alpha), float(ke), _ptr(e), _ptr(f), _ptr(pot))
+    if rc_ != 0:
+        raise RuntimeError(f"oracle wolf failed with code {rc_}")
     return float(e[0]), f, pot
 
 

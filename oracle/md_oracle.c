@@ -10,8 +10,9 @@
  * Verlet or leapfrog, U_all including bonded, van der Waals and Coulomb terms;
  * it gives no force field. The model here (a reading): rigid three-site
  * molecules held by RATTLE (Andersen 1983), Coulomb by MSM (or, for a
- * context with method ORC_METHOD_CUTOFF, by the simple cutoff method of
- * Section 5) with the pairs inside one molecule excluded, and Lennard-Jones
+ * context with method ORC_METHOD_CUTOFF or ORC_METHOD_WOLF, by the simple
+ * cutoff method or Wolf summation of Section 5) with the pairs inside one
+ * molecule excluded, and Lennard-Jones
  * with Lorentz-Berthelot mixing, cut and shifted at the cutoff a.
  * Parareal follows Section 4: lambda_{n+1}^{k+1} = G(lambda_n^{k+1}) +
  * F(lambda_n^k) - G(lambda_n^k), started from a coarse sweep; for rigid
@@ -134,6 +135,10 @@ int orc_md_forces(const orc_params *p, const orc_model *m, int64_t n, const doub
     if (p->method == ORC_METHOD_CUTOFF) {
         /* simple cutoff at a, intramolecular pairs left out of the sum */
         int rc = orc_cutoff(n, xyz, q, m->molid, p->a, p->ke, &e, forces, NULL);
+        if (rc) return rc;
+    } else if (p->method == ORC_METHOD_WOLF) {
+        /* Wolf summation at a with damping alpha, intramolecular pairs left out */
+        int rc = orc_wolf(n, xyz, q, m->molid, p->a, p->alpha, p->ke, &e, forces, NULL);
         if (rc) return rc;
     } else {
         int rc = orc_msm(p, n, xyz, q, &e, forces, NULL, NULL);

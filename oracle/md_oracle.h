@@ -21,9 +21,10 @@ typedef struct {
     double tol;             /* relative tolerance of the constraint iteration */
 } orc_model;
 
-/* Potential energy and forces: Coulomb by MSM (p->method ORC_METHOD_MSM) or
- * by the simple cutoff at p->a (ORC_METHOD_CUTOFF), intramolecular pairs
- * excluded, plus Lennard-Jones. */
+/* Potential energy and forces: Coulomb by MSM (p->method ORC_METHOD_MSM), by
+ * the simple cutoff at p->a (ORC_METHOD_CUTOFF) or by Wolf summation at p->a
+ * with damping p->alpha (ORC_METHOD_WOLF), intramolecular pairs excluded,
+ * plus Lennard-Jones. */
 int orc_md_forces(const orc_params *p, const orc_model *m, int64_t n, const double *xyz, const double *q,
                   double *epot, double *forces);
 

@@ -634,6 +634,46 @@ int orc_cutoff(int64_t n, const double *xyz, const double *q, const int32_t *mol
     return 0;
 }
 
+/* ---- Section 5: Wolf summation ---- */
+int orc_wolf(int64_t n, const double *xyz, const double *q, const int32_t *molid, double rc, double alpha, double ke,
+             double *energy, double *forces, double *pot)
+{
+    if (n < 0 || (n > 0 && (!xyz || !q)) || !(rc > 0) || !(alpha >= 0)) return -1;
+    const double shift = erfc(alpha * rc) / rc;
+    const double sqrt_pi = sqrt(acos(-1.0));
+    const double self = erfc(alpha * rc) / (2.0 * rc) + alpha / sqrt_pi;
+    double *phi = malloc(sizeof(double) * (n > 0 ? n : 1));
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t i = 0; i < n; i++) {
+        double u = 0, fx = 0, fy = 0, fz = 0;
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i || (molid && molid[j] == molid[i])) continue;
+            double rx = xyz[3 * i] - xyz[3 * j], ry = xyz[3 * i + 1] - xyz[3 * j + 1],
+                   rz = xyz[3 * i + 2] - xyz[3 * j + 2];
+            double r = sqrt(rx * rx + ry * ry + rz * rz);
+            if (!(r < rc)) continue;
+            u += q[j] * (erfc(alpha * r) / r - shift);
+            /* -d/dr (erfc(alpha r)/r) = erfc(alpha r)/r^2 + (2 alpha / sqrt(pi)) exp(-alpha^2 r^2) / r */
+            double g = (erfc(alpha * r) / (r * r) + 2.0 * alpha / sqrt_pi * exp(-alpha * alpha * r * r) / r) / r;
+            fx += q[j] * g * rx;
+            fy += q[j] * g * ry;
+            fz += q[j] * g * rz;
+        }
+        phi[i] = ke * (u - 2.0 * self * q[i]);
+        if (forces) {
+            forces[3 * i] = ke * q[i] * fx;
+            forces[3 * i + 1] = ke * q[i] * fy;
+            forces[3 * i + 2] = ke * q[i] * fz;
+        }
+    }
+    ksum e = {0, 0};
+    for (int64_t i = 0; i < n; i++) kadd(&e, q[i] * phi[i]);
+    if (energy) *energy = 0.5 * (e.s + e.c);
+    if (pot) memcpy(pot, phi, sizeof(double) * n);
+    free(phi);
+    return 0;
+}
+
 int orc_cutoff_subset(int64_t n, const double *xyz, const double *q, const int32_t *molid, double rc, double ke,
                       int64_t nsel, const int64_t *sel, double *forces, double *pot)
 {

@@ -20,6 +20,7 @@
 
 #define ORC_METHOD_MSM 0
 #define ORC_METHOD_CUTOFF 1
+#define ORC_METHOD_WOLF 2
 
 typedef struct {
     double a;          /* short-range cutoff (the cutoff radius for ORC_METHOD_CUTOFF) */
@@ -32,6 +33,7 @@ typedef struct {
                           method of Section 5 (used by the dynamics oracle) */
     int smoothing;     /* order m of the smoothing function (degree 2m); 0 = 2 */
     int basis;         /* degree p of the nodal basis Phi: 3 (0 means 3) or 5 */
+    double alpha;      /* damping of the Wolf method (1/nm), ORC_METHOD_WOLF only */
 } orc_params;
 
 /* Optional per-stage outputs; any pointer may be NULL. Grid arrays are
@@ -84,6 +86,16 @@ int orc_coulomb(int64_t n, const double *xyz, const double *q, double ke,
  * pairs of equal molecule id. Direct double loop over all pairs. */
 int orc_cutoff(int64_t n, const double *xyz, const double *q, const int32_t *molid, double rc, double ke,
                double *energy, double *forces, double *pot);
+
+/* Wolf summation (Section 5 names it as a coarse propagator; Wolf et al.
+ * 1999): damped, shifted pair potential below rc,
+ *   phi_i = ke [ sum_{j != i, r_ij < rc} q_j (erfc(alpha r)/r - erfc(alpha rc)/rc) - 2 C q_i ],
+ *   C = erfc(alpha rc)/(2 rc) + alpha/sqrt(pi),
+ * U = 1/2 sum_i q_i phi_i, F_i = -dU/dr_i (the shift and the self term are
+ * constant in the positions). molid (may be NULL) removes the pairs of equal
+ * molecule id. Direct double loop over all pairs. */
+int orc_wolf(int64_t n, const double *xyz, const double *q, const int32_t *molid, double rc, double alpha, double ke,
+             double *energy, double *forces, double *pot);
 
 /* The potentials and forces of orc_cutoff for the atoms listed in sel only,
  * each by a direct loop over all atoms (spot checks of very large systems). */

@@ -608,3 +608,86 @@ def test_quintic_with_order_three_smoothing_beats_the_cubic_pair(orc):
     assert _rel_rms(f5, f0) < 0.5 * _rel_rms(f3, f0)
     assert _rel_rms(q5, p0) < 0.5 * _rel_rms(q3, p0)
     assert _rel_rms(f5, f0) < 0.01 and abs(e5 - e0) / abs(e0) < 0.01
+
+
+# --------------------------------------------------------------------------
+# Wolf summation (Section 5: the refined coarse propagator it proposes)
+# --------------------------------------------------------------------------
+def test_wolf_without_damping_beyond_a_neutral_cluster_is_exact_coulomb(orc):
+    # with alpha = 0 the shift and self terms sum to -(sum q)^2 / (2 rc), zero
+    # for a neutral system, so with every pair inside rc Wolf is exact Coulomb
+    w = uniform_pm(120, 1.0, seed=3)
+    assert abs(w.q.sum()) < 1e-12
+    e0, f0, p0 = orc.coulomb(w.xyz, w.q, ke=1.0)
+    e, f, p = orc.wolf(w.xyz, w.q, 5.0, 0.0, ke=1.0)
+    assert e == pytest.approx(e0, rel=1e-13)
+    np.testing.assert_allclose(f, f0, rtol=0, atol=1e-12 * np.abs(f0).max())
+    np.testing.assert_allclose(p, p0, rtol=0, atol=1e-12 * np.abs(p0).max())
+    # with damping the result moves away from it
+    e2, _, _ = orc.wolf(w.xyz, w.q, 5.0, 2.0, ke=1.0)
+    assert abs(e2 - e0) > 1e-3 * abs(e0)
+
+
+def test_wolf_energy_is_continuous_where_the_simple_cutoff_jumps(orc):
+    # move one charge of a pair across the cutoff sphere: the shifted pair
+    # potential vanishes there, the plain cutoff jumps by q q / rc
+    rc, alpha = 1.0, 2.5
+    q = np.array([1.0, -1.0])
+    for r in (rc - 1e-9, rc + 1e-9):
+        x = np.array([[0.0, 0.0, 0.0], [r, 0.0, 0.0]])
+        e, _, _ = orc.wolf(x, q, rc, alpha, ke=1.0)
+        ec, _, _ = orc.cutoff(x, q, rc, ke=1.0)
+        if r < rc:
+            e_in, ec_in = e, ec
+        else:
+            e_out, ec_out = e, ec
+    assert abs(e_in - e_out) < 1e-8
+    assert abs(ec_in - ec_out) == pytest.approx(1.0 / rc, rel=1e-6)
+
+
+def test_wolf_gradients_newton_and_self_term(orc):
+    w = uniform_pm(300, 3.0, seed=11)
+    rc, alpha = 0.9, 3.0
+    e, f, pot = orc.wolf(w.xyz, w.q, rc, alpha, ke=1.0)
+    np.testing.assert_allclose(f.sum(0), 0, atol=1e-10 * np.abs(f).max())
+    assert e == pytest.approx(0.5 * (w.q * pot).sum(), rel=1e-13)
+    delta = 1e-5
+    d = np.linalg.norm(w.xyz[:, None, :] - w.xyz[None, :, :], axis=-1)
+    clear = [i for i in range(w.n) if np.all(np.abs(d[i] - rc) > 3 * delta)]
+    for i in clear[:3]:
+        for c in range(3):
+            xp, xm = w.xyz.copy(), w.xyz.copy()
+            xp[i, c] += delta
+            xm[i, c] -= delta
+            fd = -(orc.wolf(xp, w.q, rc, alpha, ke=1.0)[0] - orc.wolf(xm, w.q, rc, alpha, ke=1.0)[0]) / (2 * delta)
+            assert f[i, c] == pytest.approx(fd, rel=1e-6, abs=1e-8)
+    # phi_i = dU/dq_i exactly (U is quadratic in q), the self term included
+    i = clear[0]
+    qp, qm = w.q.copy(), w.q.copy()
+    qp[i] += 0.5
+    qm[i] -= 0.5
+    fd = orc.wolf(w.xyz, qp, rc, alpha, ke=1.0)[0] - orc.wolf(w.xyz, qm, rc, alpha, ke=1.0)[0]
+    assert pot[i] == pytest.approx(fd, rel=1e-12)
+    # an isolated charge sees only the self term: phi = -2 (erfc(alpha rc)/(2 rc) + alpha/sqrt(pi)) q
+    e1, _, p1 = orc.wolf(np.zeros((1, 3)), np.array([1.0]), rc, 0.0, ke=1.0)
+    assert p1[0] == pytest.approx(-1.0 / rc, rel=1e-14)
+    assert e1 == pytest.approx(-0.5 / rc, rel=1e-14)
+
+
+def test_wolf_model_forces_are_wolf_plus_the_same_lennard_jones():
+    import oracle
+    w = water_box(64, (4, 4, 4), (1.24, 1.24, 1.24), seed=17, margin=0.6)
+    from workloads import water_model_arrays
+    mass, molid, lj, tri = water_model_arrays(w.n)
+    kw = dict(lo=tuple(w.lo), hi=tuple(w.hi), levels=0, ke=138.935458)
+    pw = oracle.OracleParams(0.6, 0.25, method=oracle.METHOD_WOLF, alpha=3.0, **kw)
+    pc = oracle.OracleParams(0.6, 0.25, method=oracle.METHOD_CUTOFF, **kw)
+    full = oracle.OracleModel(mass, molid, lj, True, tri)
+    no_lj = oracle.OracleModel(mass, molid, None, True, tri)
+    ew0, fw0 = oracle.md_forces(pw, no_lj, w.xyz, w.q)
+    e_ref, f_ref, _ = oracle.wolf(w.xyz, w.q, 0.6, 3.0, molid=molid)
+    assert ew0 == pytest.approx(e_ref, rel=1e-13)
+    ew, fw = oracle.md_forces(pw, full, w.xyz, w.q)
+    ec0, fc0 = oracle.md_forces(pc, no_lj, w.xyz, w.q)
+    ec, fc = oracle.md_forces(pc, full, w.xyz, w.q)
+    assert ew - ew0 == pytest.approx(ec - ec0, rel=1e-10)
