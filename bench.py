@@ -219,8 +219,8 @@ def bench_parareal(torch, msmx, slices, n_atoms=99999):
     of 10 velocity-Verlet steps of 2 fs with the fine MSM (a = 1.2, h = 0.25)
     against serial fine on the same GPU, for the configured coarse propagator
     (one 20 fs step with a = 0.8, h = 0.5), a stable MSM one (10 steps of 2 fs
-    with a = 0.8, h = 0.5) and the paper's choice, the simple cutoff method
-    at 1.2 nm with 10 steps of 2 fs."""
+    with a = 0.8, h = 0.5), the paper's choice, the simple cutoff method at
+    1.2 nm with 10 steps of 2 fs, and Wolf summation with the same cutoff."""
     from workloads import rigid_water_velocities, water_box, water_box_dims, water_model_arrays
     dev = torch.device("cuda", 0)
     n_mol, sites, box = water_box_dims(n_atoms)
@@ -233,8 +233,9 @@ def bench_parareal(torch, msmx, slices, n_atoms=99999):
     mol_t = torch.tensor(molid, dtype=torch.int32, device=dev)
     lj_t = torch.tensor(lj, dtype=torch.float64, device=dev)
 
-    def ctx(a, h, ma, ms, method="msm"):
-        c = msmx.MsmContext(a, h, w.lo, w.hi, precision="fp32", max_atoms=ma, max_systems=ms, method=method)
+    def ctx(a, h, ma, ms, method="msm", alpha=0.0):
+        c = msmx.MsmContext(a, h, w.lo, w.hi, precision="fp32", max_atoms=ma, max_systems=ms, method=method,
+                            alpha=alpha)
         c.bind_model(w.n, mol_t, lj_t, rigid=True, tri=tri)
         c.set_graphs(True)
         return c
@@ -257,13 +258,14 @@ def bench_parareal(torch, msmx, slices, n_atoms=99999):
     out = {"workload": f"{slices} slices x {w.n} atoms, rigid water at 300 K, fine 10 x 2 fs (a 1.2, h 0.25)",
            "serial_fine_seconds": serial_s}
     # coarse propagators: the configured one (MSM, one 20 fs step), a stable MSM
-    # one, and the paper's choice: the simple cutoff method at 1.2 nm with the
-    # fine step (Section 5)
+    # one, the paper's choice, the simple cutoff method at 1.2 nm with the fine
+    # step (Section 5), and its refinement, Wolf summation (alpha 2 / nm)
     variants = (("coarse_1x20fs", "msm", 0.8, 0.5, 1, 0.020, "MSM a 0.8, h 0.5"),
                 ("coarse_10x2fs", "msm", 0.8, 0.5, 10, 0.002, "MSM a 0.8, h 0.5"),
-                ("coarse_cutoff_10x2fs", "cutoff", 1.2, 0.25, 10, 0.002, "simple cutoff 1.2 nm"))
+                ("coarse_cutoff_10x2fs", "cutoff", 1.2, 0.25, 10, 0.002, "simple cutoff 1.2 nm"),
+                ("coarse_wolf_10x2fs", "wolf", 1.2, 0.25, 10, 0.002, "Wolf summation 1.2 nm, alpha 2 / nm"))
     for name, method, a, h, sg, dtg, desc in variants:
-        coarse = ctx(a, h, w.n, 1, method)
+        coarse = ctx(a, h, w.n, 1, method, alpha=2.0 if method == "wolf" else 0.0)
         rec = {"coarse": f"{sg} x {dtg * 1000:g} fs, {desc}"}
         # cost of one coarse step against one fine step on one slice
         xg, vg = x.clone(), vv.clone()

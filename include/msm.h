@@ -55,9 +55,13 @@ enum { MSM_FP64 = 0, MSM_FP32 = 1 };
 /* How the Coulomb interaction is evaluated. MSM_METHOD_MSM: multilevel
  * summation (Section 3). MSM_METHOD_CUTOFF: the simple cutoff method the
  * paper chooses for the coarse parareal propagator (Section 5): Coulomb's law
- * between the pairs closer than a and nothing beyond; no grids are built,
- * h is only the edge of the cells of the pair search and levels is ignored. */
-enum { MSM_METHOD_MSM = 0, MSM_METHOD_CUTOFF = 1 };
+ * between the pairs closer than a and nothing beyond. MSM_METHOD_WOLF: Wolf
+ * summation, which Section 5 proposes as its refinement (Wolf et al. 1999):
+ * the damped, shifted pair potential erfc(alpha r)/r - erfc(alpha a)/a below
+ * a and the self term -(erfc(alpha a)/(2a) + alpha/sqrt(pi)) q_i^2. Neither
+ * builds grids: h is only the edge of the cells of the pair search and
+ * levels, smoothing and basis are ignored. */
+enum { MSM_METHOD_MSM = 0, MSM_METHOD_CUTOFF = 1, MSM_METHOD_WOLF = 2 };
 
 typedef struct msm_ctx msm_ctx;   /* opaque; owned by the library */
 
@@ -86,6 +90,7 @@ typedef struct {
                               cardinal data with five-point central differences
                               for the node first and second derivatives (C2,
                               support |t| < 3: 6 nodes per axis per atom) */
+    double alpha;          /* Wolf damping alpha (1/nm), >= 0; MSM_METHOD_WOLF only */
 } msm_params;
 
 /* Create a context: validates the parameters, builds the stencil weights and
@@ -115,7 +120,10 @@ int msm_set_stream(msm_ctx *ctx, void *stream);
  *  energy_dev     nsys doubles: U = 1/2 sum_i q_i phi_i per system, where phi_i
  *                 excludes the atom's own charge (the smooth self term
  *                 q_i gamma(0)/a is removed). May be NULL. With
- *                 MSM_METHOD_CUTOFF, phi_i = k sum_{j != i, r_ij < a} q_j / r_ij.
+ *                 MSM_METHOD_CUTOFF, phi_i = k sum_{j != i, r_ij < a} q_j / r_ij;
+ *                 with MSM_METHOD_WOLF, phi_i = k (sum_{j != i, r_ij < a}
+ *                 q_j (erfc(alpha r)/r - erfc(alpha a)/a) - 2 C q_i),
+ *                 C = erfc(alpha a)/(2a) + alpha/sqrt(pi).
  *  forces_dev     N x 3, F_i = -dU/dr_i. May be NULL.
  *  potentials_dev N, phi_i = dU/dq_i. May be NULL.
  * Outputs are in the caller's atom order. Results for a system with an atom

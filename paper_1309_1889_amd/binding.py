@@ -42,14 +42,14 @@ class _Tuning(C.Structure):
     _fields_ = [("pair_waves", C.c_int), ("stencil_threads", C.c_int)]
 
 
-METHODS = {"msm": 0, "cutoff": 1}
+METHODS = {"msm": 0, "cutoff": 1, "wolf": 2}
 
 
 class _Params(C.Structure):
     _fields_ = [("a", C.c_double), ("h", C.c_double), ("levels", C.c_int), ("precision", C.c_int),
                 ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("coulomb_k", C.c_double),
                 ("max_atoms", C.c_int64), ("max_systems", C.c_int), ("method", C.c_int),
-                ("smoothing", C.c_int), ("basis", C.c_int)]
+                ("smoothing", C.c_int), ("basis", C.c_int), ("alpha", C.c_double)]
 
 
 def lib_path() -> str:
@@ -134,14 +134,15 @@ class MsmContext:
     a, h: cutoff and finest grid spacing (nm); lo, hi: domain corners;
     levels: number of grids (0 = from the domain); precision: "fp32" or
     "fp64"; ke: Coulomb prefactor; max_atoms / max_systems: batch capacity;
-    method: "msm", or "cutoff" for the simple cutoff method at a (Section 5's
-    coarse propagator; h is then only the cell edge of the pair search);
+    method: "msm", "cutoff" for the simple cutoff method at a (Section 5's
+    coarse propagator) or "wolf" for Wolf summation at a with damping alpha
+    (1/nm); for both h is only the cell edge of the pair search;
     smoothing: order m of the smoothing function (degree 2m), 1 .. 3;
     basis: degree p of the nodal basis, 3 or 5.
     """
 
     def __init__(self, a, h, lo, hi, *, levels=0, precision="fp32", ke=138.935458,
-                 max_atoms=1 << 20, max_systems=1, stream=None, method="msm", smoothing=2, basis=3):
+                 max_atoms=1 << 20, max_systems=1, stream=None, method="msm", smoothing=2, basis=3, alpha=0.0):
         import torch
         if method not in METHODS:
             raise ValueError(f"method must be one of {sorted(METHODS)}")
@@ -160,6 +161,7 @@ class MsmContext:
         p.method = METHODS[method]
         p.smoothing = int(smoothing)
         p.basis = int(basis)
+        p.alpha = float(alpha)
         self.smoothing, self.basis = int(smoothing), int(basis)
         self.params = p
         self.a, self.h, self.ke = float(a), float(h), float(ke)

@@ -45,7 +45,7 @@ int geometry(const msm_params &prm, const double *lo, const double *hi, Geometry
         if (ncd > 1 << 20) return MSM_ERR_CAPACITY;
         g.nc[d] = (int)ncd;
     }
-    if (prm.method == MSM_METHOD_CUTOFF) {   // no grids: cells for the pair search only
+    if (prm.method != MSM_METHOD_MSM) {   // no grids: cells for the pair search only
         g.nlev = 0;
         return MSM_OK;
     }
@@ -112,7 +112,7 @@ template <typename T> void carve(msm_ctx *c, Work<T> &w, char *base, size_t *use
     // max_atoms / 2); none without grids
     const int64_t part_cells = std::min<int64_t>(c->cap_cells, na / 2 + 1);
     const int64_t support = 2 * ((basis_degree(c->prm) + 1) / 2);   // nodes per axis an atom reaches
-    w.apart = (T *)take(c->prm.method == MSM_METHOD_CUTOFF ? 0
+    w.apart = (T *)take(c->prm.method != MSM_METHOD_MSM ? 0
                                                          : sizeof(T) * support * support * support * part_cells);
     w.qgrid = (T *)take(sizeof(T) * c->cap_q);
     w.ucut = (T *)take(sizeof(T) * c->cap_u);
@@ -485,11 +485,13 @@ int msm_setup(const msm_params *prm, void *stream, msm_ctx **out)
     if (prm->max_atoms < 0 || prm->max_atoms >= ((int64_t)1 << 31) || prm->max_systems < 1) return MSM_ERR_ARG;
     if (prm->levels < 0 || prm->levels > kMaxLevels) return MSM_ERR_ARG;
     if (!std::isfinite(prm->coulomb_k)) return MSM_ERR_ARG;
-    if (prm->method != MSM_METHOD_MSM && prm->method != MSM_METHOD_CUTOFF) return MSM_ERR_ARG;
+    if (prm->method != MSM_METHOD_MSM && prm->method != MSM_METHOD_CUTOFF && prm->method != MSM_METHOD_WOLF)
+        return MSM_ERR_ARG;
+    if (prm->method == MSM_METHOD_WOLF && !(prm->alpha >= 0 && std::isfinite(prm->alpha))) return MSM_ERR_ARG;
     const int smoothing = prm->smoothing ? prm->smoothing : 2;
     if (smoothing < 1 || smoothing > kMaxSmooth) return MSM_ERR_UNSUPPORTED;
     if (prm->basis != 0 && prm->basis != 3 && prm->basis != 5) return MSM_ERR_UNSUPPORTED;
-    const bool cutoff = prm->method == MSM_METHOD_CUTOFF;
+    const bool cutoff = prm->method != MSM_METHOD_MSM;   // no grids
     const double ratio = 2.0 * prm->a / prm->h;
     const int reach = (int)std::ceil(ratio) - 1;       // largest integer below 2a/h
     if (!cutoff && (reach < 1 || reach > kMaxReach - 1)) return MSM_ERR_UNSUPPORTED;
@@ -505,7 +507,9 @@ int msm_setup(const msm_params *prm, void *stream, msm_ctx **out)
     c->mc.a = prm->a;
     c->mc.h = prm->h;
     c->mc.ke = prm->coulomb_k;
+    c->mc.method = prm->method;
     c->mc.cutoff = cutoff ? 1 : 0;
+    c->mc.alpha = prm->method == MSM_METHOD_WOLF ? prm->alpha : 0.0;
     c->mc.g = make_smooth(smoothing);
     c->mc.p = basis_degree(*prm);
     c->mc.reach = cutoff ? 0 : reach;

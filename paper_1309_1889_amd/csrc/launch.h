@@ -7,6 +7,7 @@
 #include <stdint.h>
 
 #include "common.h"
+#include "../../include/msm.h"
 
 namespace msmx {
 
@@ -67,7 +68,9 @@ int stencil_tile_z(int elem_bytes, int reach);
 
 struct MethodConst {
     double a, h, ke;
-    int cutoff;                // 1: simple cutoff method (plain Coulomb below a, no grids)
+    int method;                // MSM_METHOD_MSM, _CUTOFF or _WOLF
+    int cutoff;                // 1: no grids (the simple cutoff method or Wolf summation)
+    double alpha;              // Wolf damping (1/nm)
     Smooth g;                  // smoothing function gamma of order g.m
     int p;                     // degree of the nodal basis Phi: 3 or 5
     int reach;                 // stencil reach R: largest integer with R < 2a/h

@@ -2,6 +2,8 @@
 // on the arithmetic type T (float or double). Every kernel works on all
 // systems of a batch in one launch; a thread or wave finds its system by a
 // binary search of a prefix table.
+#include <cmath>
+
 #include "device_util.h"
 #include "launch.h"
 #include "md.h"
@@ -780,10 +782,14 @@ hipError_t Launch<T>::interp(hipStream_t s, const DevPlan &p, const Work<T> &w, 
     const vec4_t<T> *lj = (const vec4_t<T> *)(w.saux ? w.shlj : nullptr);
     const dim3 grid((unsigned)p.niblk), block(kInterpThreads);
     const T self = T(m.g.c[0] / m.a);   // smooth self term gamma(0)/a
-    if (m.cutoff)   // simple cutoff method: no grid potential and no smooth self term
+    if (m.cutoff) {
+        // no grid potential; the simple cutoff has no self term, Wolf's is
+        // 2 C q_i in phi_i with C = erfc(alpha a)/(2a) + alpha/sqrt(pi)
+        const double c_wolf = std::erfc(m.alpha * m.a) / (2.0 * m.a) + m.alpha / std::sqrt(std::acos(-1.0));
+        const T self_nogrid = m.method == MSM_METHOD_WOLF ? T(2.0 * c_wolf) : T(0);
         hipLaunchKernelGGL((k_interp<T, false, 3>), grid, block, 0, s, p, w.sxyzq, w.shrt, w.order, (const T *)nullptr,
-                           forces, potentials, w.eparts, T(m.ke), T(0), lj);
-    else if (m.p == 5)
+                           forces, potentials, w.eparts, T(m.ke), self_nogrid, lj);
+    } else if (m.p == 5)
         hipLaunchKernelGGL((k_interp<T, true, 5>), grid, block, 0, s, p, w.sxyzq, w.shrt, w.order, w.ugrid, forces,
                            potentials, w.eparts, T(m.ke), self, lj);
     else

@@ -1,6 +1,6 @@
 // The short-range pair kernel of the multilevel summation method (Section 3),
-// also the whole evaluation of the simple cutoff method (Section 5), templated
-// on the arithmetic type T (float or double).
+// also the whole pair sum of the simple cutoff method and of Wolf summation
+// (Section 5), templated on the arithmetic type T (float or double).
 #include <cmath>
 
 #include "device_util.h"
@@ -31,7 +31,14 @@ template <typename T> struct PairK {
     T inv_a2;           // 1/a^2
     T c0, c1, c2, c3;   // gamma(r/a)/a = c0 + c1 r^2 + c2 r^4 (+ c3 r^6 for m = 3)
     T d0, d1, d2;       // -(d/dr)(gamma(r/a)/a) / r = d0 + d1 r^2 (+ d2 r^4 for m = 3)
+    T alpha, alpha2;    // Wolf damping alpha and alpha^2
+    T wshift, wexp;     // erfc(alpha a)/a and 2 alpha / sqrt(pi)
 };
+
+// Pair kernel forms: the smoothing polynomial of degree at most 4 (MSM with
+// m <= 2, and the simple cutoff method with a zero polynomial), of degree 6
+// (m = 3), and Wolf's damped, shifted Coulomb (Section 5).
+enum PairKind { kPoly = 0, kPolyHigh = 1, kWolf = 2 };
 
 #ifndef MSMX_PAIR_UNROLL
 #define MSMX_PAIR_UNROLL 8
@@ -52,9 +59,8 @@ template <typename T, bool MD> struct PairLds {
 };
 
 // POT = false: forces only (no potential or energy sums), for evaluations
-// that are asked for neither. HIGH: the smoothing polynomial of degree 6
-// (m = 3); otherwise of degree at most 4.
-template <typename T, bool MD, bool POT, bool HIGH>
+// that are asked for neither. KIND: one of PairKind.
+template <typename T, bool MD, bool POT, int KIND>
 __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const vec4_t<T> &aj, const vec4_t<T> &xj,
                                  const PairK<T> &k, T &fx, T &fy, T &fz, T &u, T &lx, T &ly, T &lz, T &le)
 {
@@ -68,12 +74,22 @@ __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const
             same = mol_of(xi) == mol_of(xj);
             rc = same ? T(0) : rinv;
         }
-        const T br = HIGH ? rc * rinv * rinv - (k.d0 + r2 * (k.d1 + r2 * k.d2))
-                          : rc * rinv * rinv - (k.d0 + k.d1 * r2);
-        if (POT) {
-            const T gs = HIGH ? rc - (k.c0 + r2 * (k.c1 + r2 * (k.c2 + r2 * k.c3)))
-                              : rc - (k.c0 + r2 * (k.c1 + r2 * k.c2));
-            u += aj.w * gs;
+        T br;
+        if (KIND == kWolf) {
+            // erfc(alpha r)/r - erfc(alpha a)/a, and -(d/dr)(erfc(alpha r)/r)/r
+            // = (erfc(alpha r)/r + 2 alpha/sqrt(pi) exp(-alpha^2 r^2)) / r^2;
+            // an excluded pair (rc = 0) contributes nothing
+            const T r = r2 * rinv;
+            const T er = erfc(k.alpha * r);
+            const T on = rc * r;   // 1, or 0 for an excluded pair
+            br = on * (er * rinv + k.wexp * exp(-k.alpha2 * r2)) * rinv * rinv;
+            if (POT) u += aj.w * on * (er * rinv - k.wshift);
+        } else if (KIND == kPolyHigh) {
+            br = rc * rinv * rinv - (k.d0 + r2 * (k.d1 + r2 * k.d2));
+            if (POT) u += aj.w * (rc - (k.c0 + r2 * (k.c1 + r2 * (k.c2 + r2 * k.c3))));
+        } else {
+            br = rc * rinv * rinv - (k.d0 + k.d1 * r2);
+            if (POT) u += aj.w * (rc - (k.c0 + r2 * (k.c1 + r2 * k.c2)));
         }
         const T t = aj.w * br;
         fx += t * dx;
@@ -115,7 +131,7 @@ __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const
 // coalesced load (the next chunk is fetched while the current one is used),
 // and every lane reads each staged atom by broadcast and evaluates its own
 // pair. The waves' partial sums are added in a fixed order at the end.
-template <typename T, bool MD, bool POT, bool HIGH, int kPairWaves>
+template <typename T, bool MD, bool POT, int KIND, int kPairWaves>
 __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                               const int *__restrict__ cstart,
                                                               vec4_t<T> *__restrict__ out, PairK<T> k,
@@ -159,9 +175,9 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
     // chains are kept in vector registers: an FMA takes one scalar operand,
     // so as kernel arguments they would be copied to vector registers again
     // for every candidate.
-    if (HIGH)
+    if (KIND == kPolyHigh)
         asm volatile("" : "+v"(k.c2), "+v"(k.d1));
-    else
+    else if (KIND == kPoly)
         asm volatile("" : "+v"(k.c1), "+v"(k.d0));
     T fx = 0, fy = 0, fz = 0, u = 0;
     T lx = 0, ly = 0, lz = 0, le = 0;
@@ -239,12 +255,12 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
                 }
 #pragma unroll
                 for (int v = 0; v < kPairUnroll; ++v)
-                    pair_term<T, MD, POT, HIGH>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le);
+                    pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le);
             }
             for (; t < cnt; ++t) {
                 const vec4_t<T> aj = L.atom[t];
                 const vec4_t<T> xj = MD ? L.aux[t] : aj;
-                pair_term<T, MD, POT, HIGH>(ai, xi, aj, xj, k, fx, fy, fz, u, lx, ly, lz, le);
+                pair_term<T, MD, POT, KIND>(ai, xi, aj, xj, k, fx, fy, fz, u, lx, ly, lz, le);
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -288,30 +304,31 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
     }
 }
 
-template <typename T, bool HIGH, int NW>
+template <typename T, int KIND, int NW>
 static void pair_launch(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot)
 {
     const dim3 grid((unsigned)p.ngroups), block(NW * kWave);
     const vec4_t<T> *aux = (const vec4_t<T> *)w.saux;
     if (w.saux && pot)
-        hipLaunchKernelGGL((k_pair<T, true, true, HIGH, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
+        hipLaunchKernelGGL((k_pair<T, true, true, KIND, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
                            aux, w.shlj);
     else if (w.saux)
-        hipLaunchKernelGGL((k_pair<T, true, false, HIGH, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
+        hipLaunchKernelGGL((k_pair<T, true, false, KIND, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
                            aux, w.shlj);
     else if (pot)
-        hipLaunchKernelGGL((k_pair<T, false, true, HIGH, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
+        hipLaunchKernelGGL((k_pair<T, false, true, KIND, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
                            (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
     else
-        hipLaunchKernelGGL((k_pair<T, false, false, HIGH, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt,
+        hipLaunchKernelGGL((k_pair<T, false, false, KIND, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt,
                            k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
 }
 
 template <typename T, int NW>
-static void pair_launch_m(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot, bool high)
+static void pair_launch_m(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot, int kind)
 {
-    if (high) pair_launch<T, true, NW>(s, p, w, k, pot);
-    else pair_launch<T, false, NW>(s, p, w, k, pot);
+    if (kind == kWolf) pair_launch<T, kWolf, NW>(s, p, w, k, pot);
+    else if (kind == kPolyHigh) pair_launch<T, kPolyHigh, NW>(s, p, w, k, pot);
+    else pair_launch<T, kPoly, NW>(s, p, w, k, pot);
 }
 
 }  // namespace
@@ -328,9 +345,10 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, co
     // gamma(r/a)/a = sum_j g_j r^(2j) / a^(2j+1) and
     // -(d/dr)(gamma(r/a)/a) / r = -sum_{j>=1} 2 j g_j r^(2j-2) / a^(2j+1)
     // (m = 2: 15/8 a^-1 - 5/4 a^-3 r^2 + 3/8 a^-5 r^4 and 5/2 a^-3 - 3/2 a^-5 r^2);
-    // the simple cutoff method (Section 5) has no smoothing: all zero
+    // the simple cutoff method and Wolf summation (Section 5) have no
+    // smoothing: all zero
     double cp[kMaxSmooth + 1] = {}, dp[kMaxSmooth] = {};
-    if (!m.cutoff)
+    if (m.method == MSM_METHOD_MSM)
         for (int j = 0; j <= m.g.m; j++) {
             const double aj = std::pow(a, 2 * j + 1);
             cp[j] = m.g.c[j] / aj;
@@ -343,11 +361,15 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, co
     k.d0 = T(dp[0]);
     k.d1 = T(dp[1]);
     k.d2 = T(dp[2]);
-    const bool high = !m.cutoff && m.g.m == 3;
+    k.alpha = T(m.alpha);
+    k.alpha2 = T(m.alpha * m.alpha);
+    k.wshift = T(std::erfc(m.alpha * a) / a);
+    k.wexp = T(2.0 * m.alpha / std::sqrt(std::acos(-1.0)));
+    const int kind = m.method == MSM_METHOD_WOLF ? kWolf : (m.method == MSM_METHOD_MSM && m.g.m == 3 ? kPolyHigh : kPoly);
     switch (m.pair_waves) {
-    case 4: pair_launch_m<T, 4>(s, p, w, k, pot, high); break;
-    case 8: pair_launch_m<T, 8>(s, p, w, k, pot, high); break;
-    case 16: pair_launch_m<T, 16>(s, p, w, k, pot, high); break;
+    case 4: pair_launch_m<T, 4>(s, p, w, k, pot, kind); break;
+    case 8: pair_launch_m<T, 8>(s, p, w, k, pot, kind); break;
+    case 16: pair_launch_m<T, 16>(s, p, w, k, pot, kind); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -1,5 +1,6 @@
 """Parity of the simple cutoff method (Section 5: the coarse propagator the
-paper proposes for parareal) on the GPU with the FP64 oracle.
+paper proposes for parareal) and of Wolf summation (its refinement, also
+Section 5) on the GPU with the FP64 oracle.
 
 The cutoff is a discontinuity: a pair whose distance is within rounding of
 the cutoff may be counted on one side and not on the other. Atoms in such a
@@ -225,3 +226,77 @@ def test_parareal_with_cutoff_coarse_matches_oracle():
     assert np.abs(got[..., :3] - lo_[..., :3]).max() < 1e-9
     assert np.abs(got[..., 3:] - lo_[..., 3:]).max() < 1e-6
     np.testing.assert_allclose(rep["residual"], res, rtol=1e-5, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Wolf summation (Section 5's refinement of the simple cutoff)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision,rc,h,alpha", [("fp64", 1.2, 0.25, 2.0), ("fp64", 0.9, 0.3, 3.5),
+                                                  ("fp32", 1.2, 0.25, 2.0), ("fp32", 0.9, 0.45, 3.5)])
+def test_wolf_matches_oracle(precision, rc, h, alpha):
+    w = box(1500, 3.6, seed=53)
+    dt = np.float32 if precision == "fp32" else np.float64
+    if precision == "fp32":
+        w = w.as_dtype(np.float32)
+    ctx = msmx().MsmContext(rc, h, w.lo, w.hi, precision=precision, method="wolf", alpha=alpha, max_atoms=w.n)
+    e, f, p = ctx.energy_forces(torch.tensor(w.xyzq(dt), device="cuda"))
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    eo, fo, po = oracle.wolf(w.xyz, w.q, rc, alpha)
+    # the Wolf potential vanishes at the cutoff, so only the (small) force
+    # jump of pairs within rounding of it is ambiguous
+    amb = ambiguous_pairs(w.xyz, rc, band(precision))
+    keep = np.setdiff1d(np.arange(w.n), amb.ravel())
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    assert rel_rms(f.double().cpu().numpy()[keep], fo[keep]) < tol
+    assert rel_rms(p.double().cpu().numpy(), po) < tol
+    assert e.item() == pytest.approx(eo, rel=tol)
+
+
+def test_wolf_model_forces_match_oracle():
+    w, mass, molid, lj, tri, v = small_water(300, 3.0, seed=14)
+    c = msmx().MsmContext(0.9, 0.3, w.lo, w.hi, precision="fp64", ke=KE, max_atoms=w.n, method="wolf", alpha=3.0)
+    c.bind_model(len(mass), torch.tensor(molid, dtype=torch.int32, device="cuda"),
+                 torch.tensor(lj, dtype=torch.float64, device="cuda"), rigid=True, tri=tri)
+    e, f, _ = c.energy_forces(torch.tensor(w.xyzq(np.float64), device="cuda"))
+    torch.cuda.synchronize()
+    p = oracle.OracleParams(0.9, 0.3, tuple(w.lo), tuple(w.hi), 0, KE, method=oracle.METHOD_WOLF, alpha=3.0)
+    eo, fo = oracle.md_forces(p, oracle.OracleModel(mass, molid, lj, True, tri), w.xyz, w.q)
+    amb = ambiguous_pairs(w.xyz, 0.9, band("fp64"))
+    keep = np.setdiff1d(np.arange(w.n), amb.ravel())
+    assert rel_rms(f.cpu().numpy()[keep], fo[keep]) < 1e-11
+    assert e.item() == pytest.approx(eo, rel=1e-11)
+
+
+def test_parareal_with_wolf_coarse_matches_oracle_and_is_exact():
+    S, sf, dtf, sg, dtg = 4, 3, 0.001, 3, 0.001
+    w, mass, molid, lj, tri, v = small_water(125, 1.55, seed=21)
+    q = torch.tensor(w.q, dtype=torch.float64, device="cuda")
+    invm = torch.tensor(1.0 / mass, dtype=torch.float64, device="cuda")
+    s0 = torch.tensor(np.concatenate([w.xyz, v], 1), dtype=torch.float64, device="cuda").contiguous()
+    fine = model_ctx(w, 0.9, 0.25, "fp64", mass, molid, lj, tri, "msm", max_atoms=S * w.n, max_systems=S)
+    coarse = msmx().MsmContext(0.9, 0.45, w.lo, w.hi, precision="fp64", ke=KE, max_atoms=w.n, method="wolf",
+                               alpha=3.0)
+    coarse.bind_model(len(mass), torch.tensor(molid, dtype=torch.int32, device="cuda"),
+                      torch.tensor(lj, dtype=torch.float64, device="cuda"), rigid=True, tri=tri)
+    lam, rep, rc = msmx().parareal(fine, coarse, q, invm, s0, nslices=S, kmax=2, tol=0.0, steps_f=sf, dt_f=dtf,
+                                   steps_g=sg, dt_g=dtg)
+    torch.cuda.synchronize()
+    pf = oracle.OracleParams(0.9, 0.25, tuple(w.lo), tuple(w.hi), 0, KE)
+    pg = oracle.OracleParams(0.9, 0.45, tuple(w.lo), tuple(w.hi), 0, KE, method=oracle.METHOD_WOLF, alpha=3.0)
+    model = oracle.OracleModel(mass, molid, lj, True, tri, 1e-12)
+    lo_, it, res, rco = oracle.parareal(pf, pg, model, w.xyz, v, w.q, S, sf, dtf, sg, dtg, 2, 0.0)
+    assert it == rep["iterations"] == 2
+    got = lam.cpu().numpy()
+    assert np.abs(got[..., :3] - lo_[..., :3]).max() < 1e-9
+    assert np.abs(got[..., 3:] - lo_[..., 3:]).max() < 1e-6
+    # slices 0..2 equal the serial fine trajectory bitwise
+    ref = model_ctx(w, 0.9, 0.25, "fp64", mass, molid, lj, tri, "msm")
+    cur = s0.clone()
+    for n in range(1, 3):
+        x = torch.cat([cur[:, :3], q[:, None]], 1).contiguous()
+        vv = torch.cat([cur[:, 3:], invm[:, None]], 1).contiguous()
+        ref.vv_run(x, vv, sf, dtf, energies=False)
+        cur = torch.cat([x[:, :3], vv[:, :3]], 1)
+        torch.cuda.synchronize()
+        assert torch.equal(lam[n], cur), n
