@@ -33,6 +33,8 @@ from .loader import (  # noqa: F401
     threads,
     OracleModel,
     md_forces,
+    md_forces_split,
+    vv_mts,
     vv,
     parareal,
 )

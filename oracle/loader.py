@@ -343,6 +343,12 @@ def _md_lib():
         L.orc_parareal.argtypes = [C.POINTER(_Params), C.POINTER(_Params), C.POINTER(_Model), C.c_int64, _dp, _dp,
                                    C.c_int, C.c_int, C.c_double, C.c_int, C.c_double, C.c_int, C.c_double, _dp,
                                    C.POINTER(C.c_int), _dp]
+        L.orc_md_forces_split.restype = C.c_int
+        L.orc_md_forces_split.argtypes = [C.POINTER(_Params), C.POINTER(_Model), C.c_int64, _dp, _dp, _dp, _dp,
+                                          _dp, _dp]
+        L.orc_vv_mts.restype = C.c_int
+        L.orc_vv_mts.argtypes = [C.POINTER(_Params), C.POINTER(_Model), C.c_int64, _dp, _dp, _dp, C.c_double,
+                                 C.c_int, C.c_int, _dp, _dp]
         L._md_ready = True
     return L
 
@@ -357,6 +363,36 @@ def md_forces(p: OracleParams, model: OracleModel, xyz, q):
     if rc != 0:
         raise RuntimeError(f"oracle md_forces failed with code {rc}")
     return float(e[0]), f
+
+
+def md_forces_split(p: OracleParams, model: OracleModel, xyz, q):
+    """(e_fast, f_fast, e_slow, f_slow): the multiple-time-step split of the
+    MSM model force (fast: short-range pairs and Lennard-Jones; slow: grid)."""
+    xyz = np.ascontiguousarray(xyz, dtype=np.float64).reshape(-1, 3)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    ff, fs = np.zeros_like(xyz), np.zeros_like(xyz)
+    ef, es = np.zeros(1), np.zeros(1)
+    cp, cm = p.c(), model.c()
+    rc = _md_lib().orc_md_forces_split(C.byref(cp), C.byref(cm), xyz.shape[0], _ptr(xyz), _ptr(q), _ptr(ef),
+                                       _ptr(ff), _ptr(es), _ptr(fs))
+    if rc != 0:
+        raise RuntimeError(f"oracle md_forces_split failed with code {rc}")
+    return float(ef[0]), ff, float(es[0]), fs
+
+
+def vv_mts(p: OracleParams, model: OracleModel, xyz, v, q, dt, ninner, nouter):
+    """nouter multiple-time-step steps of dt with ninner fast steps each;
+    returns new (xyz, v, epot, ekin)."""
+    x = np.array(xyz, dtype=np.float64).reshape(-1, 3)
+    vv_ = np.array(v, dtype=np.float64).reshape(-1, 3)
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    ep, ek = np.zeros(1), np.zeros(1)
+    cp, cm = p.c(), model.c()
+    rc = _md_lib().orc_vv_mts(C.byref(cp), C.byref(cm), x.shape[0], _ptr(x), _ptr(vv_), _ptr(q), float(dt),
+                              int(ninner), int(nouter), _ptr(ep), _ptr(ek))
+    if rc != 0:
+        raise RuntimeError(f"oracle vv_mts failed with code {rc}")
+    return x, vv_, float(ep[0]), float(ek[0])
 
 
 def vv(p: OracleParams, model: OracleModel, xyz, v, q, dt, nsteps):

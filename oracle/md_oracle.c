@@ -252,6 +252,102 @@ int orc_vv(const orc_params *p, const orc_model *m, int64_t n, double *xyz, doub
     return rc;
 }
 
+/* ---- Multiple time steps (Section 5 names them as a further improvement) ----
+ * The MSM force splits into a fast part, the short-range pairs (g* for every
+ * pair inside a, Coulomb removed again for the excluded pairs) plus
+ * Lennard-Jones, and a slow part, the grid potential's gradient; the smooth
+ * self term is constant and goes with the slow energy. */
+int orc_md_forces_split(const orc_params *p, const orc_model *m, int64_t n, const double *xyz, const double *q,
+                        double *e_fast, double *f_fast, double *e_slow, double *f_slow)
+{
+    if (p->method != ORC_METHOD_MSM) return -1;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    double *us = malloc(sizeof(double) * nn), *fs = malloc(sizeof(double) * 3 * nn);
+    double *ul = malloc(sizeof(double) * nn), *gl = malloc(sizeof(double) * 3 * nn);
+    orc_stages st;
+    memset(&st, 0, sizeof(st));
+    st.u_short = us;
+    st.f_short = fs;
+    st.u_long = ul;
+    st.g_long = gl;
+    double etot = 0;
+    int rc = orc_msm(p, n, xyz, q, &etot, NULL, NULL, &st);
+    if (!rc) {
+        const double self = orc_gamma_m(0.0, p->smoothing > 0 ? p->smoothing : 2) / p->a;
+        double ef = 0, es = 0;
+        for (int64_t i = 0; i < n; i++) {
+            ef += 0.5 * p->ke * q[i] * us[i];
+            es += 0.5 * p->ke * q[i] * (ul[i] - q[i] * self);
+            for (int k = 0; k < 3; k++) {
+                f_fast[3 * i + k] = p->ke * q[i] * fs[3 * i + k];
+                f_slow[3 * i + k] = -p->ke * q[i] * gl[3 * i + k];
+            }
+        }
+        exclusions(p, m, n, xyz, q, &ef, f_fast);
+        lennard_jones(p, m, n, xyz, &ef, f_fast);
+        *e_fast = ef;
+        *e_slow = es;
+    }
+    free(us);
+    free(fs);
+    free(ul);
+    free(gl);
+    return rc;
+}
+
+/* Impulse multiple-time-step velocity Verlet (r-RESPA, Tuckerman et al.
+ * 1992): every outer step of dt is a half kick with the slow force, ninner
+ * velocity-Verlet steps of dt/ninner with the fast force (RATTLE for rigid
+ * triples), the slow force at the new positions and a second slow half kick
+ * (followed by the velocity constraints). */
+int orc_vv_mts(const orc_params *p, const orc_model *m, int64_t n, double *xyz, double *v, const double *q,
+               double dt, int ninner, int nouter, double *epot, double *ekin)
+{
+    if (ninner < 1 || nouter < 0) return -1;
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    double *ff = malloc(sizeof(double) * 3 * nn), *fsl = malloc(sizeof(double) * 3 * nn);
+    double *xold = malloc(sizeof(double) * 3 * nn);
+    double ef = 0, es = 0;
+    const double di = dt / ninner;
+    int rc = orc_md_forces_split(p, m, n, xyz, q, &ef, ff, &es, fsl);
+    for (int o = 0; rc == 0 && o < nouter; o++) {
+        for (int64_t i = 0; i < n; i++)
+            for (int k = 0; k < 3; k++) v[3 * i + k] += 0.5 * dt * fsl[3 * i + k] / m->mass[i];
+        if (m->rigid) rattle_velocities(m, n, xyz, v);
+        for (int s = 0; rc == 0 && s < ninner; s++) {
+            memcpy(xold, xyz, sizeof(double) * 3 * n);
+            for (int64_t i = 0; i < n; i++)
+                for (int k = 0; k < 3; k++) {
+                    v[3 * i + k] += 0.5 * di * ff[3 * i + k] / m->mass[i];
+                    xyz[3 * i + k] += di * v[3 * i + k];
+                }
+            if (m->rigid) rattle_positions(m, n, xold, xyz, v, di);
+            /* both parts at the new positions; the inner step uses the fast
+             * one, and after the last inner step fsl is the slow force for
+             * the closing slow kick */
+            rc = orc_md_forces_split(p, m, n, xyz, q, &ef, ff, &es, fsl);
+            if (rc) break;
+            for (int64_t i = 0; i < n; i++)
+                for (int k = 0; k < 3; k++) v[3 * i + k] += 0.5 * di * ff[3 * i + k] / m->mass[i];
+            if (m->rigid) rattle_velocities(m, n, xyz, v);
+        }
+        for (int64_t i = 0; i < n; i++)
+            for (int k = 0; k < 3; k++) v[3 * i + k] += 0.5 * dt * fsl[3 * i + k] / m->mass[i];
+        if (m->rigid) rattle_velocities(m, n, xyz, v);
+    }
+    if (epot) *epot = ef + es;
+    if (ekin) {
+        double kk = 0;
+        for (int64_t i = 0; i < n; i++)
+            kk += 0.5 * m->mass[i] * (v[3 * i] * v[3 * i] + v[3 * i + 1] * v[3 * i + 1] + v[3 * i + 2] * v[3 * i + 2]);
+        *ekin = kk;
+    }
+    free(ff);
+    free(fsl);
+    free(xold);
+    return rc;
+}
+
 /* ---- Section 4: parareal ---- */
 
 /* Project a corrected state (n x 6) of rigid triples back onto the

@@ -28,6 +28,19 @@ typedef struct {
 int orc_md_forces(const orc_params *p, const orc_model *m, int64_t n, const double *xyz, const double *q,
                   double *epot, double *forces);
 
+/* The MSM model force split for multiple time steps: fast = the short-range
+ * pairs (g* for every pair inside a, Coulomb removed again for excluded
+ * pairs) plus Lennard-Jones; slow = the grid potential's gradient (the smooth
+ * self term goes with the slow energy). fast + slow = orc_md_forces. MSM only. */
+int orc_md_forces_split(const orc_params *p, const orc_model *m, int64_t n, const double *xyz, const double *q,
+                        double *e_fast, double *f_fast, double *e_slow, double *f_slow);
+
+/* nouter impulse multiple-time-step steps of dt (r-RESPA): slow half kick,
+ * ninner velocity-Verlet steps of dt/ninner with the fast force, slow half
+ * kick; RATTLE for rigid triples. epot/ekin after the last step. */
+int orc_vv_mts(const orc_params *p, const orc_model *m, int64_t n, double *xyz, double *v, const double *q,
+               double dt, int ninner, int nouter, double *epot, double *ekin);
+
 /* nsteps of velocity Verlet (with RATTLE for rigid triples) in place.
  * epot/ekin receive the energies after the last step (may be NULL). */
 int orc_vv(const orc_params *p, const orc_model *m, int64_t n, double *xyz, double *v, const double *q,

@@ -160,3 +160,43 @@ def test_parareal_corrected_states_keep_the_rigid_geometry():
             r = x[:, a] - x[:, b]
             assert np.abs(np.linalg.norm(r, axis=1) - L).max() < 1e-9
             assert np.abs((r * (u[:, a] - u[:, b])).sum(1)).max() < 1e-9
+
+
+# ---------------------------------------------------------------------------
+# multiple time steps (Section 5 names them): impulse r-RESPA with the grid
+# part of MSM as the slow force
+# ---------------------------------------------------------------------------
+def test_force_split_adds_up_to_the_model_force():
+    w, model, _ = small_water(64, 1.24, seed=7)
+    p = oracle.OracleParams(0.6, 0.2, tuple(w.lo), tuple(w.hi), 0)
+    e, f = oracle.md_forces(p, model, w.xyz, w.q)
+    ef, ff, es, fs = oracle.md_forces_split(p, model, w.xyz, w.q)
+    assert ef + es == pytest.approx(e, rel=1e-12)
+    np.testing.assert_allclose(ff + fs, f, rtol=0, atol=1e-12 * np.abs(f).max())
+
+
+def test_mts_with_one_inner_step_is_velocity_verlet():
+    w, model, v = small_water(64, 1.24, seed=7)
+    p = oracle.OracleParams(0.6, 0.2, tuple(w.lo), tuple(w.hi), 0)
+    x1, v1, ep1, ek1 = oracle.vv(p, model, w.xyz, v, w.q, 0.001, 10)
+    x2, v2, ep2, ek2 = oracle.vv_mts(p, model, w.xyz, v, w.q, 0.001, 1, 10)
+    assert np.abs(x1 - x2).max() < 1e-10
+    assert np.abs(v1 - v2).max() < 1e-8
+    assert ep2 == pytest.approx(ep1, rel=1e-10)
+
+
+def test_mts_energy_error_is_second_order_and_shrinks_with_inner_steps():
+    w, model, v = small_water(64, 1.24, seed=7)
+    p = oracle.OracleParams(0.6, 0.2, tuple(w.lo), tuple(w.hi), 0)
+
+    def drift(dt, n):
+        _, _, e0, k0 = oracle.vv_mts(p, model, w.xyz, v, w.q, dt, n, 0)
+        x, vv, e1, k1 = oracle.vv_mts(p, model, w.xyz, v, w.q, dt, n, int(round(0.2 / dt)))
+        d = x.reshape(-1, 3, 3)
+        assert np.abs(np.linalg.norm(d[:, 0] - d[:, 1], axis=1) - model.tri[0]).max() < 1e-9
+        return abs((e1 + k1) - (e0 + k0))
+
+    for n in (2, 4):
+        ratio = drift(0.004, n) / drift(0.002, n)
+        assert 2.5 < ratio < 6.0, (n, ratio)
+    assert drift(0.004, 4) < drift(0.004, 2) < drift(0.004, 1)
