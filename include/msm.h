@@ -225,6 +225,21 @@ int msm_md_bind(msm_ctx *ctx, const msm_md_model *model);
 int msm_vv_run(msm_ctx *ctx, int nsys, const int64_t *offsets_host, const double *domains_host, void *xyzq_dev,
                void *vel_dev, int nsteps, double dt, double *epot_dev, double *ekin_dev);
 
+/* Multiple time steps (Section 5 names them as an improvement): nouter steps
+ * of dt ps of impulse multiple-time-step velocity Verlet (r-RESPA), in place,
+ * arguments as for msm_vv_run. The force splits into a fast part, the
+ * short-range pairs (with the excluded pairs' smooth correction and the
+ * model's Lennard-Jones), and a slow part, the grid (long-range) part with the
+ * smooth self term. Each outer step: half kick with the slow force, ninner
+ * velocity-Verlet steps of dt/ninner with the fast force (RATTLE positions
+ * and velocities), the slow force at the new positions, half kick with it
+ * (then RATTLE velocities). The grid part is evaluated nouter + 1 times, the
+ * pairs nouter * ninner + 1 times; epot_dev gets a full evaluation at the
+ * end. MSM contexts only (MSM_ERR_UNSUPPORTED for the cutoff methods). */
+int msm_vv_mts_run(msm_ctx *ctx, int nsys, const int64_t *offsets_host, const double *domains_host,
+                   void *xyzq_dev, void *vel_dev, int nouter, int ninner, double dt, double *epot_dev,
+                   double *ekin_dev);
+
 typedef struct {
     int nslices;        /* time slices N (window of the iteration) */
     int kmax;           /* at most this many iterations (iterations == nslices is exact) */

@@ -101,6 +101,9 @@ def lib():
         L.msm_vv_run.argtypes = [vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double), vp, vp, C.c_int,
                                  C.c_double, vp, vp]
         L.msm_vv_run.restype = C.c_int
+        L.msm_vv_mts_run.argtypes = [vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double), vp, vp, C.c_int,
+                                     C.c_int, C.c_double, vp, vp]
+        L.msm_vv_mts_run.restype = C.c_int
         L.parareal_run.argtypes = [vp, vp, C.POINTER(_PararealParams), C.c_int64, vp, vp, vp, vp,
                                    C.POINTER(_PararealReport)]
         L.parareal_run.restype = C.c_int
@@ -353,6 +356,34 @@ class MsmContext:
         ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
         _check(lib().msm_vv_run(self._h, nsys, offs.ctypes.data_as(C.POINTER(C.c_int64)), dom_p, ptr(xyzq),
                                 ptr(vel), int(nsteps), float(dt), ptr(ep), ptr(ek)), "msm_vv_run")
+        return ep, ek
+
+    def vv_mts_run(self, xyzq, vel, nouter, ninner, dt, offsets=None, domains=None, energies=True):
+        """Multiple-time-step velocity Verlet in place (see msm_vv_mts_run):
+        nouter steps of dt, each with ninner short-range steps of dt/ninner.
+        Same tensors as vv_run. Returns (epot, ekin) or None."""
+        import torch
+        for t in (xyzq, vel):
+            if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.dim() != 2 \
+                    or t.shape[1] != 4:
+                raise ValueError("vv_mts_run expects contiguous float64 (N, 4) device tensors")
+        n = xyzq.shape[0]
+        if offsets is None:
+            offsets = [0, n]
+        offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        nsys = len(offs) - 1
+        dom_p = None
+        if domains is not None:
+            dom = np.ascontiguousarray(np.asarray(domains, dtype=np.float64).reshape(nsys, 6))
+            dom_p = dom.ctypes.data_as(C.POINTER(C.c_double))
+        ep = ek = None
+        if energies:
+            ep = torch.empty(nsys, dtype=torch.float64, device=xyzq.device)
+            ek = torch.empty(nsys, dtype=torch.float64, device=xyzq.device)
+        ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
+        _check(lib().msm_vv_mts_run(self._h, nsys, offs.ctypes.data_as(C.POINTER(C.c_int64)), dom_p, ptr(xyzq),
+                                    ptr(vel), int(nouter), int(ninner), float(dt), ptr(ep), ptr(ek)),
+               "msm_vv_mts_run")
         return ep, ek
 
 

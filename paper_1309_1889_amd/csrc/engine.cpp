@@ -301,7 +301,7 @@ template <> Work<float> &work<float>(msm_ctx *c) { return c->wf; }
 template <> Work<double> &work<double>(msm_ctx *c) { return c->wd; }
 
 template <typename T>
-int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *pots)
+int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *pots, int part)
 {
     using L = Launch<T>;
     const DevPlan &p = c->dp;
@@ -316,25 +316,26 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     mark(MSM_STAGE_SHORT);
     // the short-range potentials are needed only for the energy and the potentials
     const bool pot = energy || pots || c->tuning_pass;
-    if ((e = L::pair(s, p, w, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
+    const bool do_short = part != kEvalLong, do_long = part != kEvalShort;
+    if (do_short && (e = L::pair(s, p, w, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_ANTERP);
-    if ((e = L::anterp(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
+    if (do_long && (e = L::anterp(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_RESTRICT);
     // one launch per level, each for all systems of the batch
-    for (int k = 0; k + 1 < p.maxlev; k++)
+    for (int k = 0; do_long && k + 1 < p.maxlev; k++)
         if ((e = L::restrict_level(s, p, w, k, c->mc)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_CUTOFF);
-    {
+    if (do_long) {
         StencilTables<T> tb{c->wcols, (const T *)c->weights, c->ncols, c->mc.reach, c->mc.stencil_threads};
         if ((e = L::stencil(s, p, w, tb)) != hipSuccess) return MSM_ERR_HIP;
     }
     mark(MSM_STAGE_TOP);
-    if ((e = L::top_level(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
+    if (do_long && (e = L::top_level(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_PROLONG);
-    for (int k = p.maxlev - 2; k >= 0; k--)
+    for (int k = p.maxlev - 2; do_long && k >= 0; k--)
         if ((e = L::prolong_level(s, p, w, k, c->mc)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_INTERP);
-    if ((e = L::interp(s, p, w, c->mc, (T *)forces, (T *)pots)) != hipSuccess) return MSM_ERR_HIP;
+    if ((e = L::interp(s, p, w, c->mc, (T *)forces, (T *)pots, part)) != hipSuccess) return MSM_ERR_HIP;
     if ((e = L::energy(s, p, w, energy)) != hipSuccess) return MSM_ERR_HIP;
     if (c->timing) {
         mark(MSM_NSTAGES);
@@ -351,10 +352,10 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
 
 }  // namespace
 
-static int evaluate_eager(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *pots)
+static int evaluate_eager(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *pots, int part)
 {
-    if (c->prm.precision == MSM_FP32) return evaluate<float>(c, xyzq, energy, forces, pots);
-    return evaluate<double>(c, xyzq, energy, forces, pots);
+    if (c->prm.precision == MSM_FP32) return evaluate<float>(c, xyzq, energy, forces, pots, part);
+    return evaluate<double>(c, xyzq, energy, forces, pots, part);
 }
 
 static void drop_graph(msm_ctx::GraphEntry &g)
@@ -367,13 +368,13 @@ static void drop_graph(msm_ctx::GraphEntry &g)
 // With graphs enabled, an evaluation is captured once per batch plan and set
 // of buffers (on an internal stream) and replayed on the context stream; the
 // launch sequence is the same as the eager one, so results are identical.
-int msmx::evaluate_any(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *pots)
+int msmx::evaluate_any(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *pots, int part)
 {
-    if (!c->use_graphs || c->timing) return evaluate_eager(c, xyzq, energy, forces, pots);
+    if (!c->use_graphs || c->timing) return evaluate_eager(c, xyzq, energy, forces, pots, part);
     msm_ctx::GraphEntry *hit = nullptr, *victim = &c->graphs[0];
     for (auto &g : c->graphs) {
         if (g.valid && g.plan_version == c->plan_version && g.xyzq == xyzq && g.energy == energy &&
-            g.forces == forces && g.pots == pots)
+            g.forces == forces && g.pots == pots && g.part == part)
             hit = &g;
         if (!g.valid || g.last_use < victim->last_use) victim = &g;
     }
@@ -387,7 +388,7 @@ int msmx::evaluate_any(msm_ctx *c, const void *xyzq, double *energy, void *force
             c->stream = saved;
             return MSM_ERR_HIP;
         }
-        int rc = evaluate_eager(c, xyzq, energy, forces, pots);
+        int rc = evaluate_eager(c, xyzq, energy, forces, pots, part);
         hipGraph_t graph = nullptr;
         hipError_t e = hipStreamEndCapture(c->capture_stream, &graph);
         c->stream = saved;
@@ -407,6 +408,7 @@ int msmx::evaluate_any(msm_ctx *c, const void *xyzq, double *energy, void *force
         victim->energy = energy;
         victim->forces = forces;
         victim->pots = pots;
+        victim->part = part;
         victim->graph = graph;
         victim->exec = exec;
         hit = victim;

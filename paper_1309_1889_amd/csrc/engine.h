@@ -62,17 +62,19 @@ struct msm_ctx {
         const void *xyzq = nullptr;
         double *energy = nullptr;
         void *forces = nullptr, *pots = nullptr;
+        int part = 0;
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         uint64_t last_use = 0;
-    } graphs[4];
+    } graphs[8];
     uint64_t graph_clock = 0;
     // dynamics (msm_md_bind)
     bool md_bound = false;
     bool rigid = false;
     msmx::TriModel tri{};
     char *mdbuf = nullptr;       // model, forces and parareal scratch
-    void *md_forces = nullptr;   // max_atoms x 3, precision T
+    void *md_forces = nullptr;                  // max_atoms x 3, precision T
+    void *md_forces_slow = nullptr;             // multiple time steps: the grid part, max_atoms x 3
     double *md_parts = nullptr;  // per-block partial sums (kinetic energy)
     double *md_scalar = nullptr; // scratch scalars (change of a parareal iteration, ...)
     void *px = nullptr, *pv = nullptr;          // propagator state, max_atoms x 4 doubles each
@@ -87,6 +89,10 @@ namespace msmx {
 // Build (or reuse) the device tables of a batch.
 int build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double *domains);
 // One evaluation of the current plan on xyzq (precision of the context).
-int evaluate_any(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *pots);
+// Which part of the MSM interaction an evaluation computes: everything, only
+// the short-range pairs (with the model's Lennard-Jones), or only the grid
+// (long-range) part with the smooth self term, for multiple time steps.
+enum EvalPart { kEvalAll = 0, kEvalShort = 1, kEvalLong = 2 };
+int evaluate_any(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *pots, int part = kEvalAll);
 
 }  // namespace msmx

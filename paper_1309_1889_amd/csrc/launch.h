@@ -92,8 +92,9 @@ template <typename T> struct Launch {
     static hipError_t stencil(hipStream_t s, const DevPlan &p, const Work<T> &w, const StencilTables<T> &tb);
     static hipError_t top_level(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m);
     static hipError_t prolong_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k, const MethodConst &m);
+    // part: 0 everything, 1 the short-range pairs only, 2 the grid part only
     static hipError_t interp(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m,
-                             T *forces, T *potentials);
+                             T *forces, T *potentials, int part);
     static hipError_t energy(hipStream_t s, const DevPlan &p, const Work<T> &w, double *energy);
     static hipError_t stage_copy(hipStream_t s, const DevPlan &p, const Work<T> &w, int sys,
                                  double *u_short, double *f_short, double *const *qg,

@@ -40,7 +40,7 @@ template <typename T> int bind(msm_ctx *c, const msm_md_model *m)
     const size_t o_maux = aux ? take(sizeof(vec4_t<T>) * period) : 0;
     const size_t o_saux = aux ? take(sizeof(vec4_t<T>) * (na + 64)) : 0;
     const size_t o_shlj = aux ? take(sizeof(vec4_t<T>) * na) : 0;
-    const size_t o_f = take(sizeof(T) * 3 * na);
+    const size_t o_f = take(sizeof(T) * 3 * na), o_fs = take(sizeof(T) * 3 * na);
     const size_t o_parts = take(sizeof(double) * c->cap_iblk);
     const size_t o_scal = take(sizeof(double) * 64);
     const size_t o_px = take(sizeof(double4) * na), o_pv = take(sizeof(double4) * na);
@@ -56,6 +56,7 @@ template <typename T> int bind(msm_ctx *c, const msm_md_model *m)
     w.shlj = aux ? (vec4_t<T> *)(b + o_shlj) : nullptr;
     w.period = period;
     c->md_forces = b + o_f;
+    c->md_forces_slow = b + o_fs;
     c->md_parts = (double *)(b + o_parts);
     c->md_scalar = (double *)(b + o_scal);
     c->px = b + o_px;
@@ -130,6 +131,42 @@ template <typename T> int vv(msm_ctx *c, void *xyzq, void *vel, int nsteps, doub
     return MSM_OK;
 }
 
+// Impulse multiple-time-step velocity Verlet (r-RESPA): each outer step of dt
+// is a half kick with the grid (slow) force, ninner velocity-Verlet steps of
+// dt/ninner with the short-range (fast) force, the slow force at the new
+// positions and a second slow half kick; the kicks of rigid triples end with
+// RATTLE's velocity stage. The energy is a full evaluation at the end.
+template <typename T>
+int vv_mts(msm_ctx *c, void *xyzq, void *vel, int nouter, int ninner, double dt, double *epot, double *ekin)
+{
+    using M = MdLaunch<T>;
+    hipStream_t s = c->stream;
+    const int64_t n = c->dp.natoms;
+    double4 *x = (double4 *)xyzq, *v = (double4 *)vel;
+    vec4_t<T> *xe = sizeof(T) == 8 ? (vec4_t<T> *)x : (vec4_t<T> *)c->pe;
+    vec4_t<T> *xe_out = sizeof(T) == 8 ? nullptr : xe;
+    T *ff = (T *)c->md_forces, *fs = (T *)c->md_forces_slow;
+    const TriModel *tm = c->rigid ? &c->tri : nullptr;
+    const double di = dt / ninner;
+    if (xe_out && M::to_eval(s, n, x, xe_out) != hipSuccess) return MSM_ERR_HIP;
+    int rc = evaluate_any(c, xe, nullptr, fs, nullptr, kEvalLong);
+    if (!rc) rc = evaluate_any(c, xe, nullptr, ff, nullptr, kEvalShort);
+    for (int o = 0; o < nouter && !rc; o++) {
+        if (M::kick(s, n, x, v, fs, dt, tm) != hipSuccess) return MSM_ERR_HIP;
+        for (int i = 0; i < ninner && !rc; i++) {
+            if (M::kick_drift(s, n, x, v, ff, di, tm, xe_out) != hipSuccess) return MSM_ERR_HIP;
+            rc = evaluate_any(c, xe, nullptr, ff, nullptr, kEvalShort);
+            if (!rc && M::kick(s, n, x, v, ff, di, tm) != hipSuccess) return MSM_ERR_HIP;
+        }
+        if (!rc) rc = evaluate_any(c, xe, nullptr, fs, nullptr, kEvalLong);
+        if (!rc && M::kick(s, n, x, v, fs, dt, tm) != hipSuccess) return MSM_ERR_HIP;
+    }
+    if (rc) return rc;
+    if (epot && (rc = evaluate_any(c, xe, epot, nullptr, nullptr, kEvalAll))) return rc;
+    if (ekin && md_kinetic(s, c->dp, v, c->md_parts, ekin) != hipSuccess) return MSM_ERR_HIP;
+    return MSM_OK;
+}
+
 int vv_any(msm_ctx *c, void *xyzq, void *vel, int nsteps, double dt, double *epot, double *ekin)
 {
     if (c->prm.precision == MSM_FP32) return vv<float>(c, xyzq, vel, nsteps, dt, epot, ekin);
@@ -188,6 +225,22 @@ int msm_vv_run(msm_ctx *c, int nsys, const int64_t *offsets, const double *domai
     rc = build_plan(c, nsys, offsets, domains);
     if (rc) return rc;
     return vv_any(c, xyzq, vel, nsteps, dt, epot, ekin);
+}
+
+int msm_vv_mts_run(msm_ctx *c, int nsys, const int64_t *offsets, const double *domains, void *xyzq, void *vel,
+                   int nouter, int ninner, double dt, double *epot, double *ekin)
+{
+    if (!c || nsys < 1 || !offsets || nouter < 0 || ninner < 1 || !(dt > 0)) return MSM_ERR_ARG;
+    if (!c->md_bound) return MSM_ERR_ARG;
+    if (c->prm.method != MSM_METHOD_MSM) return MSM_ERR_UNSUPPORTED;   // no grid part to split off
+    if (nsys > c->prm.max_systems) return MSM_ERR_CAPACITY;
+    if (offsets[nsys] > 0 && (!xyzq || !vel)) return MSM_ERR_ARG;
+    int rc = check_rigid_offsets(c, nsys, offsets);
+    if (rc) return rc;
+    rc = build_plan(c, nsys, offsets, domains);
+    if (rc) return rc;
+    if (c->prm.precision == MSM_FP32) return vv_mts<float>(c, xyzq, vel, nouter, ninner, dt, epot, ekin);
+    return vv_mts<double>(c, xyzq, vel, nouter, ninner, dt, epot, ekin);
 }
 
 int parareal_run(msm_ctx *fine, msm_ctx *coarse, const parareal_params *pp, int64_t n, const double *q,

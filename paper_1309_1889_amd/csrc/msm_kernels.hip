@@ -537,7 +537,9 @@ __global__ __launch_bounds__(256) void k_prolong(DevPlan p, const T *__restrict_
 // ---------------------------------------------------------------------------
 constexpr int kInterpThreads = 256;
 
-template <typename T, bool GRID, int PD>
+// GRID: add the grid part; SHORT: add the short-range pair part (and the
+// model's Lennard-Jones) that the pair kernel left in shrt / ljin.
+template <typename T, bool GRID, bool SHORT, int PD>
 __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                            const vec4_t<T> *__restrict__ shrt,
                                                            const int *__restrict__ order,
@@ -592,13 +594,15 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4
                 }
             }
         }
-        const vec4_t<T> sr = shrt[pos];
+        vec4_t<T> sr;
+        sr.x = sr.y = sr.z = sr.w = T(0);
+        if (SHORT) sr = shrt[pos];
         const T phi = ke * (sr.w + ul - a.w * self);
         const int64_t o = order[pos];
         if (potentials) potentials[o] = phi;
         vec4_t<T> lj;
         lj.x = lj.y = lj.z = lj.w = T(0);
-        if (ljin) lj = ljin[pos];
+        if (SHORT && ljin) lj = ljin[pos];
         if (forces) {
             const T kq = ke * a.w;
             forces[3 * o + 0] = kq * (sr.x - gx) + lj.x;
@@ -776,25 +780,38 @@ hipError_t Launch<T>::prolong_level(hipStream_t s, const DevPlan &p, const Work<
 
 template <typename T>
 hipError_t Launch<T>::interp(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m, T *forces,
-                             T *potentials)
+                             T *potentials, int part)
 {
     if (p.niblk == 0) return hipSuccess;
     const vec4_t<T> *lj = (const vec4_t<T> *)(w.saux ? w.shlj : nullptr);
     const dim3 grid((unsigned)p.niblk), block(kInterpThreads);
-    const T self = T(m.g.c[0] / m.a);   // smooth self term gamma(0)/a
     if (m.cutoff) {
         // no grid potential; the simple cutoff has no self term, Wolf's is
         // 2 C q_i in phi_i with C = erfc(alpha a)/(2a) + alpha/sqrt(pi)
         const double c_wolf = std::erfc(m.alpha * m.a) / (2.0 * m.a) + m.alpha / std::sqrt(std::acos(-1.0));
         const T self_nogrid = m.method == MSM_METHOD_WOLF ? T(2.0 * c_wolf) : T(0);
-        hipLaunchKernelGGL((k_interp<T, false, 3>), grid, block, 0, s, p, w.sxyzq, w.shrt, w.order, (const T *)nullptr,
-                           forces, potentials, w.eparts, T(m.ke), self_nogrid, lj);
-    } else if (m.p == 5)
-        hipLaunchKernelGGL((k_interp<T, true, 5>), grid, block, 0, s, p, w.sxyzq, w.shrt, w.order, w.ugrid, forces,
-                           potentials, w.eparts, T(m.ke), self, lj);
+        hipLaunchKernelGGL((k_interp<T, false, true, 3>), grid, block, 0, s, p, w.sxyzq, w.shrt, w.order,
+                           (const T *)nullptr, forces, potentials, w.eparts, T(m.ke), self_nogrid, lj);
+        return hipGetLastError();
+    }
+    // the smooth self term gamma(0)/a goes with the grid part
+    const T self = part == 1 ? T(0) : T(m.g.c[0] / m.a);
+    const T *ug = w.ugrid;
+    const T ke = T(m.ke);
+#define MSMX_INTERP(G, S, P)                                                                                        \
+    hipLaunchKernelGGL((k_interp<T, G, S, P>), grid, block, 0, s, p, w.sxyzq, w.shrt, w.order, ug, forces,          \
+                       potentials, w.eparts, ke, self, lj)
+    if (part == 1)
+        MSMX_INTERP(false, true, 3);
+    else if (part == 2 && m.p == 5)
+        MSMX_INTERP(true, false, 5);
+    else if (part == 2)
+        MSMX_INTERP(true, false, 3);
+    else if (m.p == 5)
+        MSMX_INTERP(true, true, 5);
     else
-        hipLaunchKernelGGL((k_interp<T, true, 3>), grid, block, 0, s, p, w.sxyzq, w.shrt, w.order, w.ugrid, forces,
-                           potentials, w.eparts, T(m.ke), self, lj);
+        MSMX_INTERP(true, true, 3);
+#undef MSMX_INTERP
     return hipGetLastError();
 }
 

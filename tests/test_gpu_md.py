@@ -214,3 +214,57 @@ def test_parareal_reports_domain_exit():
         m.parareal(fine, coarse, q, invm, fast, nslices=S, kmax=1, tol=0.0, steps_f=2, dt_f=0.002, steps_g=1,
                    dt_g=0.004)
     assert ei.value.code == -2
+
+
+# ---------------------------------------------------------------------------
+# multiple time steps (impulse r-RESPA: grid part slow, short-range part fast)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_mts_matches_oracle(precision):
+    w, mass, molid, lj, tri, v = small_water(216, 1.86, seed=3)
+    ctx = make_ctx(w, 1.0, 0.25, precision, mass, molid, lj, tri)
+    x, vv = state_tensors(w.xyz, v, w.q, mass)
+    ep, ek = ctx.vv_mts_run(x, vv, 5, 2, 0.002)
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    p = oracle.OracleParams(1.0, 0.25, tuple(w.lo), tuple(w.hi), 0, KE)
+    model = oracle.OracleModel(mass, molid, lj, True, tri, 1e-12)
+    xo, vo, epo, eko = oracle.vv_mts(p, model, w.xyz, v, w.q, 0.002, 2, 5)
+    xg = x[:, :3].cpu().numpy()
+    vg = vv[:, :3].cpu().numpy()
+    if precision == "fp64":
+        assert np.abs(xg - xo).max() < 1e-9
+        assert rel_rms(vg, vo) < 1e-7
+        assert ep.item() == pytest.approx(epo, rel=1e-8)
+        assert ek.item() == pytest.approx(eko, rel=1e-8)
+    else:
+        assert np.abs(xg - xo).max() < 2e-4
+        assert rel_rms(vg, vo) < 2e-3
+        assert ek.item() == pytest.approx(eko, rel=2e-3)
+    d = xg.reshape(-1, 3, 3)
+    for (a_, b_), L in zip([(0, 1), (0, 2), (1, 2)], tri):
+        assert np.abs(np.linalg.norm(d[:, a_] - d[:, b_], axis=1) - L).max() < 1e-9
+
+
+def test_mts_with_one_inner_step_is_velocity_verlet():
+    w, mass, molid, lj, tri, v = small_water(125, 1.55, seed=9)
+    ctx = make_ctx(w, 0.9, 0.25, "fp64", mass, molid, lj, tri)
+    x1, v1 = state_tensors(w.xyz, v, w.q, mass)
+    x2, v2 = state_tensors(w.xyz, v, w.q, mass)
+    ep1, ek1 = ctx.vv_run(x1, v1, 6, 0.001)
+    ep2, ek2 = ctx.vv_mts_run(x2, v2, 6, 1, 0.001)
+    torch.cuda.synchronize()
+    assert (x1 - x2).abs().max().item() < 1e-10
+    assert (v1 - v2).abs().max().item() < 1e-8
+    assert ep2.item() == pytest.approx(ep1.item(), rel=1e-10)
+
+
+def test_mts_is_for_msm_contexts_only():
+    w, mass, molid, lj, tri, v = small_water(27, 0.95, seed=10)
+    c = msmx().MsmContext(0.9, 0.25, w.lo, w.hi, precision="fp64", max_atoms=w.n, method="cutoff")
+    c.bind_model(len(mass), torch.tensor(molid, dtype=torch.int32, device="cuda"),
+                 torch.tensor(lj, dtype=torch.float64, device="cuda"), rigid=True, tri=tri)
+    x, vv = state_tensors(w.xyz, v, w.q, mass)
+    with pytest.raises(msmx().MsmError) as ei:
+        c.vv_mts_run(x, vv, 1, 2, 0.002)
+    assert ei.value.code == -6
