@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--no-graphs", action="store_true", help="time eager launches only")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--no-orders", action="store_true", help="skip the smoothing-order / basis-degree study")
+    ap.add_argument("--no-mts", action="store_true", help="skip the multiple-time-step dynamics")
     ap.add_argument("--no-large", action="store_true", help="skip the 12.7M-atom slab")
     ap.add_argument("--only-fp32", action="store_true",
                     help="time only the single-system FP32 path (for profiler runs)")
@@ -65,7 +66,7 @@ def parse():
     args = ap.parse_args()
     if args.only_fp32:
         args.no_fp64 = args.no_accuracy = args.no_cpu_baseline = args.no_batched = args.no_parareal = True
-        args.no_large = args.no_orders = True
+        args.no_large = args.no_orders = args.no_mts = True
     return args
 
 
@@ -337,6 +338,41 @@ def bench_orders(torch, msmx, w32, steps=20, warmup=3):
             "variants": rec}
 
 
+def bench_mts(torch, msmx, inner_steps=100, dt_inner=0.002):
+    """Multiple time steps on the 99,999-atom water box (rigid water at 300 K,
+    FP32 forces): the grid part every 1 (plain velocity Verlet), 2 and 4
+    inner steps of 2 fs; time per inner step and total-energy drift."""
+    from workloads import rigid_water_velocities, water_box, water_box_dims, water_model_arrays
+    dev = torch.device("cuda", 0)
+    n_mol, sites, box = water_box_dims(99999)
+    w = water_box(n_mol, sites, box, seed=4, margin=3.0)
+    mass, molid, lj, tri = water_model_arrays(w.n)
+    v = rigid_water_velocities(w.xyz, 300.0, seed=104)
+    c = msmx.MsmContext(1.2, 0.25, w.lo, w.hi, precision="fp32", max_atoms=w.n)
+    c.bind_model(w.n, torch.tensor(molid, dtype=torch.int32, device=dev), torch.tensor(lj, device=dev), rigid=True,
+                 tri=tri)
+    c.set_graphs(True)
+    rec = []
+    for ninner in (1, 2, 4):
+        x = torch.tensor(np.concatenate([w.xyz, w.q[:, None]], 1), device=dev).contiguous()
+        vv = torch.tensor(np.concatenate([v, 1.0 / mass[:, None]], 1), device=dev).contiguous()
+        dt = dt_inner * ninner
+        c.vv_mts_run(x.clone(), vv.clone(), 2, ninner, dt, energies=False)   # warm-up, graphs captured
+        ep0, ek0 = c.vv_mts_run(x, vv, 0, ninner, dt)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ep1, ek1 = c.vv_mts_run(x, vv, inner_steps // ninner, ninner, dt)
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        c.check()
+        e0, e1 = ep0.item() + ek0.item(), ep1.item() + ek1.item()
+        rec.append({"grid_every_inner_steps": ninner, "dt_outer_fs": dt * 1000, "inner_steps": inner_steps,
+                    "ms_per_inner_step": secs / inner_steps * 1e3,
+                    "drift_relative_to_kinetic": (e1 - e0) / ek0.item()})
+    return {"workload": f"{w.n} atoms, rigid water at 300 K, a 1.2 nm, h 0.25 nm, FP32 forces, inner step "
+                        f"{dt_inner * 1000:g} fs", "variants": rec}
+
+
 def bench_large(torch, msmx, steps=100, dt=0.002):
     """The paper's 30 x 65 x 65 nm box with 12,675,000 water-like atoms: one
     FP32 evaluation timed, then `steps` velocity-Verlet steps of the rigid
@@ -501,7 +537,7 @@ def main():
                 accuracy["fp64_force_rel_rms"] = rel_rms(out64[1].cpu().numpy(), fo)
                 accuracy["fp64_energy_rel"] = abs(out64[0].item() - eo) / abs(eo)
 
-    batched = uneven = par = large = orders = None
+    batched = uneven = par = large = orders = mts = None
     if not args.no_batched:
         batched, uneven = bench_batched(torch, msmx, w32, args.steps, args.warmup, args.slices, value)
     if not args.no_parareal:
@@ -510,6 +546,8 @@ def main():
         large = bench_large(torch, msmx)
     if not args.no_orders:
         orders = bench_orders(torch, msmx, w32)
+    if not args.no_mts:
+        mts = bench_mts(torch, msmx)
 
     result.update({
         "value": value,
@@ -536,6 +574,7 @@ def main():
         "parareal": par,
         "large_box": large,
         "orders": orders,
+        "mts": mts,
         "launch": {"mode": launch_mode, "tuning": tuning32, "graph_ms_per_step": graph_ms,
                    "eager_default_ms_per_step": eager_default_ms, "eager_tuned_ms_per_step": eager_tuned_ms},
         "accuracy": accuracy,
