@@ -37,4 +37,7 @@ from .loader import (  # noqa: F401
     vv_mts,
     vv,
     parareal,
+    parareal_window,
+    window_buffers,
+    WindowState,
 )

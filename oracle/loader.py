@@ -331,6 +331,18 @@ class OracleModel:
         return m
 
 
+class WindowState(C.Structure):
+    """Resumable state of a sliding-window parareal run (zeros: a new run)."""
+    _fields_ = [("start", C.c_int), ("window_valid", C.c_int), ("iterations", C.c_int),
+                ("last_accepted", C.c_int), ("fine_slices", C.c_int64), ("coarse_slices", C.c_int64),
+                ("last_change", C.c_double)]
+
+    def copy(self):
+        c = WindowState()
+        C.memmove(C.byref(c), C.byref(self), C.sizeof(WindowState))
+        return c
+
+
 def _md_lib():
     L = lib()
     if not getattr(L, "_md_ready", False):
@@ -349,6 +361,10 @@ def _md_lib():
         L.orc_vv_mts.restype = C.c_int
         L.orc_vv_mts.argtypes = [C.POINTER(_Params), C.POINTER(_Model), C.c_int64, _dp, _dp, _dp, C.c_double,
                                  C.c_int, C.c_int, _dp, _dp]
+        L.orc_parareal_window.restype = C.c_int
+        L.orc_parareal_window.argtypes = [C.POINTER(_Params), C.POINTER(_Params), C.POINTER(_Model), C.c_int64, _dp,
+                                          C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_double, C.c_double,
+                                          C.c_int, _dp, _dp, C.POINTER(WindowState)]
         L._md_ready = True
     return L
 
@@ -426,3 +442,30 @@ def parareal(pf: OracleParams, pg: OracleParams, model: OracleModel, xyz, v, q, 
     if rc < 0:
         raise RuntimeError(f"oracle parareal failed with code {rc}")
     return lam, iters.value, resid[:iters.value], rc
+
+
+def window_buffers(xyz, v, nslices, width):
+    """lambda[(nslices+1), n, 6] holding the initial state in slice 0, and a zero
+    coarse ring[width, n, 6], for a new sliding-window run."""
+    x = np.asarray(xyz, dtype=np.float64).reshape(-1, 3)
+    lam = np.zeros((nslices + 1, x.shape[0], 6))
+    lam[0, :, :3] = x
+    lam[0, :, 3:] = np.asarray(v, dtype=np.float64).reshape(-1, 3)
+    return lam, np.zeros((width, x.shape[0], 6))
+
+
+def parareal_window(pf: OracleParams, pg: OracleParams, model: OracleModel, lam, ring, q, state: WindowState,
+                    width, steps_f, dt_f, steps_g, dt_g, tol, max_iters=0):
+    """Sliding-window parareal in place on lam and ring (float64, C order) and
+    state; returns 0 when every slice is final, 1 when stopped by max_iters."""
+    assert lam.dtype == np.float64 and lam.flags.c_contiguous and lam.shape[2] == 6
+    assert ring.dtype == np.float64 and ring.flags.c_contiguous and ring.shape[0] == width
+    q = np.ascontiguousarray(q, dtype=np.float64)
+    cf, cg, cm = pf.c(), pg.c(), model.c()
+    rc = _md_lib().orc_parareal_window(C.byref(cf), C.byref(cg), C.byref(cm), lam.shape[1], _ptr(q),
+                                       lam.shape[0] - 1, int(width), int(steps_f), float(dt_f), int(steps_g),
+                                       float(dt_g), float(tol), int(max_iters), _ptr(lam), _ptr(ring),
+                                       C.byref(state))
+    if rc < 0:
+        raise RuntimeError(f"oracle parareal_window failed with code {rc}")
+    return rc

@@ -477,3 +477,99 @@ int orc_parareal(const orc_params *pf, const orc_params *pg, const orc_model *m,
     if (rc) return rc;
     return done ? 0 : 1;
 }
+
+/* Parareal over a computational window that slides along the time axis
+ * (Section 4). The states lambda_{start+1} .. lambda_{start+We} (We =
+ * min(width, nslices - start)) are iterated with the update of Section 4
+ * while lambda_0 .. lambda_start are final. After an iteration the first open
+ * state is exact (its fine run started from a final state), and each further
+ * leading state whose positions moved by less than tol is accepted too; the
+ * window then starts at the last accepted state and its new tail states get
+ * the coarse prediction. */
+int orc_parareal_window(const orc_params *pf, const orc_params *pg, const orc_model *m, int64_t n, const double *q,
+                        int nslices, int width, int steps_f, double dt_f, int steps_g, double dt_g, double tol,
+                        int max_iters, double *lambda, double *ring, orc_window_state *st)
+{
+    if (nslices < 1 || width < 1 || n < 0 || max_iters < 0 || !st) return -1;
+    if (st->start < 0 || st->start > nslices) return -1;
+    const size_t S = (size_t)6 * n;
+    double *fout = malloc(sizeof(double) * S * width);
+    double *gnew = malloc(sizeof(double) * S);
+    double *corr = malloc(sizeof(double) * S);
+    double *chg = malloc(sizeof(double) * width);
+    double *x = malloc(sizeof(double) * 3 * (n > 0 ? n : 1)), *v = malloc(sizeof(double) * 3 * (n > 0 ? n : 1));
+    int rc = 0, done_here = 0;
+#define LAM(s) (lambda + S * (size_t)(s))
+#define RING(s) (ring + S * (size_t)((s) % width))
+    int b = st->start;
+    int end = b + (width < nslices - b ? width : nslices - b);   /* last state of the window */
+    if (!st->window_valid) {
+        /* coarse prediction of the window: lambda_{s+1} = G(lambda_s), kept as G(lambda_s) */
+        for (int s = b; s < end && !rc; s++) {
+            rc = propagate(pg, m, n, q, LAM(s), LAM(s + 1), steps_g, dt_g, x, v);
+            memcpy(RING(s), LAM(s + 1), sizeof(double) * S);
+            st->coarse_slices++;
+        }
+        st->window_valid = 1;
+    }
+    while (!rc && b < nslices && (max_iters == 0 || done_here < max_iters)) {
+        const int we = end - b;
+        /* fine propagator on every open slice */
+        for (int j = 0; j < we && !rc; j++)
+            rc = propagate(pf, m, n, q, LAM(b + j), fout + S * j, steps_f, dt_f, x, v);
+        st->fine_slices += we;
+        /* serial sweep: lambda_{s+1} = F(lambda^k_s) + (G(lambda^{k+1}_s) - G(lambda^k_s)) */
+        for (int j = 0; j < we && !rc; j++) {
+            const int s = b + j;
+            rc = propagate(pg, m, n, q, LAM(s), gnew, steps_g, dt_g, x, v);
+            double *lam = LAM(s + 1), *go = RING(s), *fo = fout + S * j;
+            for (size_t e = 0; e < S; e++) {
+                corr[e] = fo[e] + (gnew[e] - go[e]);
+                go[e] = gnew[e];
+            }
+            if (m->rigid) project_triples(m, n, corr);
+            double change = 0;
+            for (size_t e = 0; e < S; e++) {
+                if (e % 6 < 3) {
+                    double c = fabs(corr[e] - lam[e]);
+                    if (c != c) c = INFINITY;
+                    if (c > change) change = c;
+                }
+                lam[e] = corr[e];
+            }
+            chg[j] = change;
+        }
+        st->coarse_slices += we;
+        if (rc) break;
+        /* the first open state is exact; accept the following ones that moved less than tol */
+        int acc = 1;
+        while (acc < we && chg[acc] < tol) acc++;
+        double worst = 0;
+        for (int j = 0; j < we; j++)
+            if (chg[j] > worst) worst = chg[j];
+        st->last_accepted = acc;
+        st->last_change = worst;
+        st->iterations++;
+        done_here++;
+        b += acc;
+        /* slide: coarse predictions for the states that enter the window */
+        const int new_end = b + (width < nslices - b ? width : nslices - b);
+        for (int s = end; s < new_end && !rc; s++) {
+            rc = propagate(pg, m, n, q, LAM(s), LAM(s + 1), steps_g, dt_g, x, v);
+            memcpy(RING(s), LAM(s + 1), sizeof(double) * S);
+            st->coarse_slices++;
+        }
+        end = new_end;
+    }
+#undef LAM
+#undef RING
+    st->start = b;
+    free(fout);
+    free(gnew);
+    free(corr);
+    free(chg);
+    free(x);
+    free(v);
+    if (rc) return rc;
+    return b == nslices ? 0 : 1;
+}

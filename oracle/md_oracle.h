@@ -59,4 +59,32 @@ int orc_parareal(const orc_params *pf, const orc_params *pg, const orc_model *m,
                  const double *state0, int nslices, int steps_f, double dt_f, int steps_g, double dt_g, int kmax,
                  double tol, double *lambda, int *iters, double *resid);
 
+/* Resumable state of a sliding-window parareal run: a checkpoint is this
+ * struct with lambda and the coarse ring. A new run starts from zeros. */
+typedef struct {
+    int start;              /* lambda_0 .. lambda_start are final */
+    int window_valid;       /* 1: the window's states and the ring hold iterates;
+                               0: the window is predicted from lambda_start */
+    int iterations;         /* iterations so far */
+    int last_accepted;      /* states accepted by the last iteration */
+    int64_t fine_slices;    /* fine-propagator slice runs so far */
+    int64_t coarse_slices;  /* coarse-propagator slice runs so far */
+    double last_change;     /* largest position change of the last iteration */
+} orc_window_state;
+
+/* Parareal with a sliding computational window (Section 4) over nslices
+ * slices, width slices iterated at once. After each iteration the first open
+ * state is exact and the following states that moved by less than tol (nm)
+ * are accepted; the window moves past the accepted states and the states
+ * entering it get the coarse prediction. tol = 0 accepts exact states only,
+ * which gives the serial fine trajectory bitwise.
+ * lambda: (nslices+1) x n x 6, lambda_0 in, every state out;
+ * ring: width x n x 6, G(lambda_s) of the window's slice s at slot s % width.
+ * Runs at most max_iters iterations (0: no limit). Returns 0 when every slice
+ * is final, 1 when stopped early (resume by calling again with the same
+ * lambda, ring and state), or a negative error. */
+int orc_parareal_window(const orc_params *pf, const orc_params *pg, const orc_model *m, int64_t n, const double *q,
+                        int nslices, int width, int steps_f, double dt_f, int steps_g, double dt_g, double tol,
+                        int max_iters, double *lambda, double *ring, orc_window_state *st);
+
 #endif

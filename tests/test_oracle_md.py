@@ -163,6 +163,111 @@ def test_parareal_corrected_states_keep_the_rigid_geometry():
 
 
 # ---------------------------------------------------------------------------
+# sliding computational window (Section 4): the first open state is exact after
+# every iteration, states that moved less than the tolerance are accepted, and
+# the window moves on; its state (lambda, coarse ring, counters) is a checkpoint
+# ---------------------------------------------------------------------------
+def _window_case():
+    w, model, v = small_water(n_mol=27, side=0.93, seed=3)
+    pf = oracle.OracleParams(0.8, 0.25, tuple(w.lo), tuple(w.hi), 0, 138.935458)
+    pg = oracle.OracleParams(0.6, 0.5, tuple(w.lo), tuple(w.hi), 0, 138.935458)
+    return w, model, v, pf, pg, (3, 0.001, 1, 0.003)
+
+
+def _serial(p, model, w, v, steps, dt, T):
+    out = [np.concatenate([w.xyz, v], 1)]
+    for _ in range(T):
+        x, vv, _, _ = oracle.vv(p, model, out[-1][:, :3], out[-1][:, 3:], w.q, dt, steps)
+        out.append(np.concatenate([x, vv], 1))
+    return np.stack(out)
+
+
+@pytest.mark.parametrize("width", [1, 3, 7])
+def test_window_with_zero_tolerance_is_the_serial_fine_trajectory(width):
+    w, model, v, pf, pg, (sf, dtf, sg, dtg) = _window_case()
+    T = 7
+    fine = _serial(pf, model, w, v, sf, dtf, T)
+    lam, ring = oracle.window_buffers(w.xyz, v, T, width)
+    st = oracle.WindowState()
+    rc = oracle.parareal_window(pf, pg, model, lam, ring, w.q, st, width, sf, dtf, sg, dtg, 0.0)
+    assert rc == 0 and st.start == T
+    assert np.array_equal(lam, fine)
+    # exact states only: one per iteration, each iteration runs F on the whole window
+    assert st.iterations == T
+    assert st.fine_slices == sum(min(width, T - b) for b in range(T))
+
+
+def test_full_window_iterates_are_plain_parareal():
+    """A window as wide as the run with tolerance 0 moves by one slice per
+    iteration, so after K iterations every state, converged or not, is plain
+    parareal's after K iterations."""
+    w, model, v, pf, pg, (sf, dtf, sg, dtg) = _window_case()
+    T = 5
+    for K in (1, 2, 4):
+        ref, it, _, _ = oracle.parareal(pf, pg, model, w.xyz, v, w.q, T, sf, dtf, sg, dtg, K, 0.0)
+        lam, ring = oracle.window_buffers(w.xyz, v, T, T)
+        st = oracle.WindowState()
+        rc = oracle.parareal_window(pf, pg, model, lam, ring, w.q, st, T, sf, dtf, sg, dtg, 0.0, max_iters=K)
+        assert st.iterations == K and st.start == K
+        assert np.array_equal(lam, ref), K
+
+
+def _tolerance_run(max_iters_first=0):
+    w, model, v, pf, pg, (sf, dtf, sg, dtg) = _window_case()
+    T, W, tol = 9, 4, 2e-4
+    lam, ring = oracle.window_buffers(w.xyz, v, T, W)
+    st = oracle.WindowState()
+    rc = oracle.parareal_window(pf, pg, model, lam, ring, w.q, st, W, sf, dtf, sg, dtg, tol,
+                                max_iters=max_iters_first)
+    return (w, model, v, pf, pg, sf, dtf, sg, dtg, T, W, tol), lam, ring, st, rc
+
+
+def test_window_tolerance_accepts_several_states_per_iteration():
+    (w, model, v, pf, pg, sf, dtf, sg, dtg, T, W, tol), lam, ring, st, rc = _tolerance_run()
+    assert rc == 0 and st.start == T
+    assert st.iterations < T   # some iteration accepted more than the exact state
+    fine = _serial(pf, model, w, v, sf, dtf, T)
+    coarse = _serial(pg, model, w, v, sg, dtg, T)
+    err = np.abs(lam[:, :, :3] - fine[:, :, :3]).max()
+    assert err < np.abs(coarse[:, :, :3] - fine[:, :, :3]).max()
+    assert np.array_equal(lam[1], fine[1])   # the first state is always exact
+
+
+def test_window_resume_from_a_checkpoint_is_bitwise_the_uninterrupted_run():
+    case, full, _, st_full, _ = _tolerance_run()
+    (w, model, v, pf, pg, sf, dtf, sg, dtg, T, W, tol) = case
+    for stop in (1, 2, 3):
+        _, lam, ring, st, rc = _tolerance_run(stop)
+        assert rc == 1 and st.iterations == stop
+        # checkpoint: copies of lambda, the ring and the state, then resume
+        lam2, ring2, st2 = lam.copy(), ring.copy(), st.copy()
+        rc = oracle.parareal_window(pf, pg, model, lam2, ring2, w.q, st2, W, sf, dtf, sg, dtg, tol)
+        assert rc == 0
+        assert np.array_equal(lam2, full)
+        assert (st2.iterations, st2.fine_slices, st2.coarse_slices) == \
+            (st_full.iterations, st_full.fine_slices, st_full.coarse_slices)
+
+
+def test_window_resume_from_the_window_edge_with_zero_tolerance_is_serial_fine():
+    """A checkpoint of the final states alone (the window rebuilt by the coarse
+    prediction from its edge) still ends on the serial fine trajectory when
+    only exact states are accepted."""
+    w, model, v, pf, pg, (sf, dtf, sg, dtg) = _window_case()
+    T, W = 6, 3
+    fine = _serial(pf, model, w, v, sf, dtf, T)
+    lam, ring = oracle.window_buffers(w.xyz, v, T, W)
+    st = oracle.WindowState()
+    assert oracle.parareal_window(pf, pg, model, lam, ring, w.q, st, W, sf, dtf, sg, dtg, 0.0, max_iters=2) == 1
+    b = st.start
+    lam2, ring2 = oracle.window_buffers(w.xyz, v, T, W)
+    lam2[:b + 1] = lam[:b + 1]
+    st2 = oracle.WindowState()
+    st2.start = b
+    assert oracle.parareal_window(pf, pg, model, lam2, ring2, w.q, st2, W, sf, dtf, sg, dtg, 0.0) == 0
+    assert np.array_equal(lam2, fine)
+
+
+# ---------------------------------------------------------------------------
 # multiple time steps (Section 5 names them): impulse r-RESPA with the grid
 # part of MSM as the slow force
 # ---------------------------------------------------------------------------
