@@ -281,6 +281,68 @@ int parareal_run(msm_ctx *fine, msm_ctx *coarse, const parareal_params *params, 
                  const double *charges_dev, const double *invmass_dev, const double *state0_dev,
                  double *lambda_dev, parareal_report *report);
 
+typedef struct {
+    int nslices;        /* slices of the whole run */
+    int width;          /* slices iterated at once: the computational window */
+    int max_iters;      /* return after this many iterations of this call (0: run to the end) */
+    int pipeline;       /* 0: one fine batch over the window before each coarse sweep;
+                           1: fine batches start as soon as the sweep has produced their
+                           states, overlapping the sweep (fine and coarse contexts on
+                           different streams) */
+    int chunk;          /* pipelined mode: slices per fine batch (0: width/4 rounded up) */
+    double tol;         /* accept a state whose positions moved by less than tol (nm);
+                           0 accepts exact states only */
+    int steps_f;        /* fine propagator: steps_f velocity-Verlet steps of dt_f (fine context) */
+    double dt_f;
+    int steps_g;        /* coarse propagator: steps_g steps of dt_g (coarse context) */
+    double dt_g;
+} parareal_window_params;
+
+/* Resumable state of a sliding-window run, kept by the caller between calls.
+ * All zeros starts a new run. Together with lambda and the coarse ring it is
+ * a checkpoint: copying the three away and back and calling again continues
+ * the run bitwise as if it had not stopped. */
+typedef struct {
+    int start;              /* lambda_0 .. lambda_start are final */
+    int window_valid;       /* 1: the window's states and the ring hold iterates;
+                               0: the window is predicted by the coarse propagator
+                               from lambda_start (a restart from the window edge) */
+    int iterations;         /* iterations so far, over all calls */
+    int last_accepted;      /* states accepted by the last iteration */
+    int64_t fine_slices;    /* fine-propagator slice runs so far (pipelined runs count
+                               the speculative ones too) */
+    int64_t coarse_slices;  /* coarse-propagator slice runs so far */
+    double last_change;     /* largest position change of the last iteration (nm) */
+    double seconds;         /* wall time over all calls */
+} parareal_window_state;
+
+/* Parareal with a sliding computational window (Section 4: converged early
+ * time points let the window move on along the time axis). The states
+ * lambda_{start+1} .. lambda_{start+We}, We = min(width, nslices - start),
+ * are iterated with the update of parareal_run while lambda_0 .. lambda_start
+ * are final. After each iteration the first open state is exact (its fine run
+ * started from a final state), and each further leading state whose
+ * positions moved by less than tol is accepted; the window moves past the
+ * accepted states and the states entering it get the coarse prediction.
+ * With tol = 0 the result is the serial fine trajectory bitwise; with width
+ * = nslices and tol = 0, k iterations leave every state equal to
+ * parareal_run's after k iterations.
+ *  charges_dev, invmass_dev  natoms doubles;
+ *  lambda_dev   (nslices+1) x natoms x 6 (x y z vx vy vz): lambda_0 in, every state out;
+ *  ring_dev     width x natoms x 6: G(lambda_s) of the window's slice s at slot s % width;
+ *  state        host, in and out.
+ * The fine context needs max_atoms >= width*natoms and max_systems >= width,
+ * the coarse one natoms and 1; both need a bound model on the same device.
+ * Their streams may differ (the pipelined mode overlaps only then); the call
+ * orders its work across them with events and returns with both idle.
+ * Returns MSM_OK when every slice is final, MSM_NOT_CONVERGED when it stopped
+ * after max_iters iterations (call again to resume), or an error
+ * (MSM_ERR_DOMAIN/NONFINITE if a state left the domain; the buffers are then
+ * no valid checkpoint). Synchronises once per iteration to read the changes. */
+int parareal_window_run(msm_ctx *fine, msm_ctx *coarse, const parareal_window_params *params, int64_t natoms,
+                        const double *charges_dev, const double *invmass_dev, double *lambda_dev, double *ring_dev,
+                        parareal_window_state *state);
+
 /* Stages of one evaluation, for msm_stage_timing. */
 enum {
     MSM_STAGE_BIN = 0,       /* counting sort of atoms into cells */

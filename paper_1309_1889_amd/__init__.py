@@ -15,6 +15,8 @@ from .binding import (  # noqa: F401
     lib,
     lib_path,
     parareal,
+    parareal_window,
     status_string,
+    WindowState,
 )
 from .autograd import msm_energy  # noqa: F401

@@ -33,6 +33,25 @@ class _PararealParams(C.Structure):
                 ("dt_f", C.c_double), ("steps_g", C.c_int), ("dt_g", C.c_double)]
 
 
+class _WindowParams(C.Structure):
+    _fields_ = [("nslices", C.c_int), ("width", C.c_int), ("max_iters", C.c_int), ("pipeline", C.c_int),
+                ("chunk", C.c_int), ("tol", C.c_double), ("steps_f", C.c_int), ("dt_f", C.c_double),
+                ("steps_g", C.c_int), ("dt_g", C.c_double)]
+
+
+class WindowState(C.Structure):
+    """Resumable state of a sliding-window parareal run (parareal_window_state);
+    all zeros starts a new run."""
+    _fields_ = [("start", C.c_int), ("window_valid", C.c_int), ("iterations", C.c_int),
+                ("last_accepted", C.c_int), ("fine_slices", C.c_int64), ("coarse_slices", C.c_int64),
+                ("last_change", C.c_double), ("seconds", C.c_double)]
+
+    def copy(self):
+        c = WindowState()
+        C.memmove(C.byref(c), C.byref(self), C.sizeof(WindowState))
+        return c
+
+
 class _PararealReport(C.Structure):
     _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("residual", C.c_double * 64),
                 ("seconds", C.c_double)]
@@ -107,6 +126,9 @@ def lib():
         L.parareal_run.argtypes = [vp, vp, C.POINTER(_PararealParams), C.c_int64, vp, vp, vp, vp,
                                    C.POINTER(_PararealReport)]
         L.parareal_run.restype = C.c_int
+        L.parareal_window_run.argtypes = [vp, vp, C.POINTER(_WindowParams), C.c_int64, vp, vp, vp, vp,
+                                          C.POINTER(WindowState)]
+        L.parareal_window_run.restype = C.c_int
         _lib = L
         return L
 
@@ -407,3 +429,31 @@ def parareal(fine, coarse, charges, invmass, state0, *, nslices, kmax, tol, step
     report = {"iterations": rep.iterations, "converged": bool(rep.converged),
               "residual": list(rep.residual[:min(rep.iterations, 64)]), "seconds": rep.seconds}
     return lam, report, rc
+
+
+def parareal_window(fine, coarse, charges, invmass, lam, ring, state, *, width, tol, steps_f, dt_f, steps_g,
+                    dt_g, max_iters=0, pipeline=False, chunk=0):
+    """Sliding-window parareal (see parareal_window_run) in place on ``lam``
+    ((nslices+1), natoms, 6; slice 0 holds the initial state), ``ring``
+    (width, natoms, 6) and ``state`` (a WindowState). ``charges`` and
+    ``invmass`` are (natoms,) float64 device tensors. Returns the return code:
+    MSM_OK (0) when every slice is final, 1 when stopped after max_iters."""
+    for t in (charges, invmass, lam, ring):
+        if t.dtype != _torch_f64() or not t.is_contiguous():
+            raise ValueError("parareal_window: float64 contiguous device tensors expected")
+    n = lam.shape[1]
+    if lam.shape[2] != 6 or tuple(ring.shape) != (width, n, 6) or charges.numel() != n or invmass.numel() != n:
+        raise ValueError("parareal_window: shapes do not match")
+    pp = _WindowParams()
+    pp.nslices, pp.width, pp.max_iters = lam.shape[0] - 1, int(width), int(max_iters)
+    pp.pipeline, pp.chunk, pp.tol = int(bool(pipeline)), int(chunk), float(tol)
+    pp.steps_f, pp.dt_f, pp.steps_g, pp.dt_g = int(steps_f), float(dt_f), int(steps_g), float(dt_g)
+    rc = lib().parareal_window_run(fine._h, coarse._h, C.byref(pp), n, C.c_void_p(charges.data_ptr()),
+                                   C.c_void_p(invmass.data_ptr()), C.c_void_p(lam.data_ptr()),
+                                   C.c_void_p(ring.data_ptr()), C.byref(state))
+    return _check(rc, "parareal_window_run")
+
+
+def _torch_f64():
+    import torch
+    return torch.float64

@@ -238,19 +238,27 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     const size_t o_cell = place(sizeof(int64_t) * W), o_iblk = place(sizeof(int64_t) * W);
     const size_t o_top = place(sizeof(int64_t) * W), o_ant = place(sizeof(int64_t) * W);
     const size_t o_node = place(sizeof(int64_t) * kMaxLevels * W), o_tile = place(sizeof(int64_t) * (nseg + 1));
-    // the staging buffer may still feed an earlier copy
-    if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
     if (off > c->plan_cap) {
+        // the current tables may still be read by queued work
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
         if (c->plan_dev) (void)hipFree(c->plan_dev);
         if (c->plan_host) (void)hipHostFree(c->plan_host);
         c->plan_dev = nullptr;
         c->plan_host = nullptr;
         c->plan_cap = 0;
         if (hipMalloc((void **)&c->plan_dev, off) != hipSuccess) return MSM_ERR_HIP;
-        if (hipHostMalloc((void **)&c->plan_host, off, hipHostMallocDefault) != hipSuccess) return MSM_ERR_HIP;
+        if (hipHostMalloc((void **)&c->plan_host, off * msm_ctx::kPlanStage, hipHostMallocDefault) != hipSuccess)
+            return MSM_ERR_HIP;
         c->plan_cap = off;
+        for (bool &l : c->plan_ev_live) l = false;
     }
-    char *h = c->plan_host;
+    const int slot = c->plan_slot;
+    c->plan_slot = (slot + 1) % msm_ctx::kPlanStage;
+    if (!c->plan_ev[slot] && hipEventCreateWithFlags(&c->plan_ev[slot], hipEventDisableTiming) != hipSuccess)
+        return MSM_ERR_HIP;
+    // the slot's previous copy must have run before it is overwritten
+    if (c->plan_ev_live[slot] && hipEventSynchronize(c->plan_ev[slot]) != hipSuccess) return MSM_ERR_HIP;
+    char *h = c->plan_host + (size_t)slot * c->plan_cap;
     std::memcpy(h + o_sys, sys.data(), sizeof(SysPlan) * nsys);
     std::memcpy(h + o_atom, atom_p.data(), sizeof(int64_t) * W);
     std::memcpy(h + o_group, group_p.data(), sizeof(int64_t) * W);
@@ -261,6 +269,8 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     std::memcpy(h + o_node, node_p.data(), sizeof(int64_t) * kMaxLevels * W);
     std::memcpy(h + o_tile, tile_p.data(), sizeof(int64_t) * (nseg + 1));
     if (hipMemcpyAsync(c->plan_dev, h, off, hipMemcpyHostToDevice, c->stream) != hipSuccess) return MSM_ERR_HIP;
+    if (hipEventRecord(c->plan_ev[slot], c->stream) != hipSuccess) return MSM_ERR_HIP;
+    c->plan_ev_live[slot] = true;
 
     DevPlan &dp = c->dp;
     char *d = c->plan_dev;
@@ -567,6 +577,8 @@ void msm_destroy(msm_ctx *c)
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     for (auto &e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto &e : c->plan_ev)
         if (e) (void)hipEventDestroy(e);
     for (auto &g : c->graphs) drop_graph(g);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);

@@ -37,8 +37,15 @@ struct msm_ctx {
     int2 *wcols = nullptr;       // quarter-disc columns (ox, oy)
     int ncols = 0;
     char *plan_dev = nullptr;    // tables of the current batch
-    char *plan_host = nullptr;   // pinned staging copy
+    // pinned staging copies of the tables: a ring of kPlanStage slots of
+    // plan_cap bytes, each reused only after the copy it fed has run, so a new
+    // plan never waits for the work queued on the stream
+    static constexpr int kPlanStage = 4;
+    char *plan_host = nullptr;
     size_t plan_cap = 0;
+    hipEvent_t plan_ev[kPlanStage] = {};
+    bool plan_ev_live[kPlanStage] = {};
+    int plan_slot = 0;
     msmx::DevPlan dp{};
     bool plan_valid = false;
     std::vector<int64_t> last_offsets;
@@ -76,7 +83,7 @@ struct msm_ctx {
     void *md_forces = nullptr;                  // max_atoms x 3, precision T
     void *md_forces_slow = nullptr;             // multiple time steps: the grid part, max_atoms x 3
     double *md_parts = nullptr;  // per-block partial sums (kinetic energy)
-    double *md_scalar = nullptr; // scratch scalars (change of a parareal iteration, ...)
+    double *md_scalar = nullptr; // scratch words: the changes of a parareal iteration, 64 + max_systems
     void *px = nullptr, *pv = nullptr;          // propagator state, max_atoms x 4 doubles each
     void *pe = nullptr;                         // FP32 contexts: positions for the evaluation, max_atoms x 4
     double *fout = nullptr, *gold = nullptr;    // parareal: fine results and coarse values, max_atoms x 6

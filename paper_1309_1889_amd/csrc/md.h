@@ -36,6 +36,7 @@ hipError_t parareal_correct(hipStream_t s, int64_t count6, double *lam, const do
 hipError_t parareal_correct_rigid(hipStream_t s, int64_t natoms, double *lam, const double *fout, const double *gnew,
                                   double *gold, const double *invm, const TriModel &tm, unsigned long long *change);
 hipError_t copy_f64(hipStream_t s, const double *src, double *dst, int64_t n);
-hipError_t zero_u64(hipStream_t s, unsigned long long *p);
+// Clear n words (a fill kernel, so it may sit in a captured graph).
+hipError_t zero_u64(hipStream_t s, unsigned long long *p, int n = 1);
 
 }  // namespace msmx

@@ -3,6 +3,7 @@
 // fine propagator and a serial coarse sweep.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -42,7 +43,7 @@ template <typename T> int bind(msm_ctx *c, const msm_md_model *m)
     const size_t o_shlj = aux ? take(sizeof(vec4_t<T>) * na) : 0;
     const size_t o_f = take(sizeof(T) * 3 * na), o_fs = take(sizeof(T) * 3 * na);
     const size_t o_parts = take(sizeof(double) * c->cap_iblk);
-    const size_t o_scal = take(sizeof(double) * 64);
+    const size_t o_scal = take(sizeof(double) * (64 + std::max(c->prm.max_systems, 1)));
     const size_t o_px = take(sizeof(double4) * na), o_pv = take(sizeof(double4) * na);
     const size_t o_pe = sizeof(T) == 4 ? take(sizeof(vec4_t<T>) * na) : 0;
     const size_t o_fout = take(sizeof(double) * 6 * na), o_gold = take(sizeof(double) * 6 * na);
@@ -198,6 +199,193 @@ int propagate(msm_ctx *c, int64_t n, int count, const double *q, const double *i
     return md_state_out(s, tot, (double4 *)c->px, (double4 *)c->pv, lam_out) == hipSuccess ? MSM_OK : MSM_ERR_HIP;
 }
 
+// Sliding-window parareal (Section 4). The coarse context's stream runs the
+// serial coarse work (predictions, sweeps), the fine context's stream the
+// batched fine runs; events order the two. The window's fine results sit in
+// two buffers used alternately: the sweep of one iteration reads one while
+// the fine runs for the next iteration (pipelined mode) fill the other. A
+// slice s uses slot s % width of the coarse ring and of either buffer.
+class WindowRun {
+  public:
+    WindowRun(msm_ctx *fine, msm_ctx *coarse, const parareal_window_params *pp, int64_t n, const double *q,
+              const double *invm, double *lambda, double *ring, parareal_window_state *st, bool rigid)
+        : f_(fine), g_(coarse), p_(*pp), n_(n), q_(q), invm_(invm), lam_(lambda), ring_(ring), st_(st),
+          rigid_(rigid), W_(pp->width), N6_(6 * n), fev_(2 * pp->width, nullptr), frec_(2 * pp->width, 0)
+    {
+        fbuf_[0] = fine->fout;
+        fbuf_[1] = fine->gold;
+        chunk_ = p_.pipeline ? (p_.chunk > 0 ? std::min(p_.chunk, W_) : (W_ + 3) / 4) : W_;
+    }
+    ~WindowRun()
+    {
+        // the caller waits for both streams before the events go
+        (void)hipStreamSynchronize(f_->stream);
+        (void)hipStreamSynchronize(g_->stream);
+        for (hipEvent_t e : fev_)
+            if (e) (void)hipEventDestroy(e);
+        if (eva_) (void)hipEventDestroy(eva_);
+    }
+
+    int run()
+    {
+        for (hipEvent_t &e : fev_)
+            if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) return MSM_ERR_HIP;
+        if (hipEventCreateWithFlags(&eva_, hipEventDisableTiming) != hipSuccess) return MSM_ERR_HIP;
+        const int T = p_.nslices;
+        int b = st_->start;
+        if (b == T) return MSM_OK;
+        int end = b + std::min(W_, T - b);
+        int cur = 0, rc = MSM_OK;
+        const bool pipe = p_.pipeline != 0;
+        // fine runs of the first iteration: from the window's states as they are ready
+        if (!st_->window_valid) {
+            if ((rc = produced(cur, b, end))) return rc;
+            for (int s = b; s < end; s++) {
+                if ((rc = predict(s))) return rc;
+                if (pipe && (rc = produced(cur, s + 1, end))) return rc;
+            }
+            st_->window_valid = 1;
+            for (int s = b + 1; !pipe && s < end; s++)   // one batch after the prediction
+                if ((rc = produced(cur, s, end))) return rc;
+        } else {
+            for (int s = b; s < end; s++)
+                if ((rc = produced(cur, s, end))) return rc;
+        }
+        if ((rc = flush())) return rc;
+        std::vector<unsigned long long> bits(W_);
+        for (int it = 0; b < T && (p_.max_iters == 0 || it < p_.max_iters); it++) {
+            const int we = end - b;
+            const int nxt = pipe ? 1 - cur : cur;
+            const bool ahead = pipe && !(p_.max_iters > 0 && it + 1 == p_.max_iters);
+            if (!pipe && it > 0 && (rc = launch_f(cur, b, end))) return rc;
+            if (zero_u64(g_->stream, change(), we) != hipSuccess) return MSM_ERR_HIP;
+            for (int s = b; s < end; s++) {
+                if ((rc = sweep_step(cur, s, end, s - b))) return rc;
+                if (ahead && (rc = produced(nxt, s + 1, T))) return rc;
+            }
+            if ((rc = flush())) return rc;
+            st_->coarse_slices += we;
+            if (hipMemcpyAsync(bits.data(), change(), sizeof(unsigned long long) * we, hipMemcpyDeviceToHost,
+                               g_->stream) != hipSuccess ||
+                hipStreamSynchronize(g_->stream) != hipSuccess)
+                return MSM_ERR_HIP;
+            std::vector<double> chg(we);
+            std::memcpy(chg.data(), bits.data(), sizeof(double) * we);
+            // the first open state is exact; then accept the leading states that moved less than tol
+            int acc = 1;
+            while (acc < we && chg[acc] < p_.tol) acc++;
+            st_->last_accepted = acc;
+            st_->last_change = *std::max_element(chg.begin(), chg.end());
+            st_->iterations++;
+            b += acc;
+            st_->start = b;
+            const int new_end = b + std::min(W_, T - b);
+            for (int s = end; s < new_end; s++) {
+                if ((rc = predict(s))) return rc;
+                if (ahead && (rc = produced(nxt, s + 1, new_end))) return rc;
+            }
+            if ((rc = flush())) return rc;
+            end = new_end;
+            cur = nxt;
+        }
+        return MSM_OK;
+    }
+
+  private:
+    double *lam(int s) const { return lam_ + (int64_t)s * N6_; }
+    double *rslot(int s) const { return ring_ + (int64_t)(s % W_) * N6_; }
+    double *fslot(int par, int s) const { return fbuf_[par] + (int64_t)(s % W_) * N6_; }
+    unsigned long long *change() const { return (unsigned long long *)f_->md_scalar; }
+
+    // lambda_{s+1} = G(lambda_s), kept in the ring as the old coarse value
+    int predict(int s)
+    {
+        int rc = propagate(g_, n_, 1, q_, invm_, lam(s), lam(s + 1), p_.steps_g, p_.dt_g);
+        if (rc) return rc;
+        st_->coarse_slices++;
+        return copy_f64(g_->stream, lam(s + 1), rslot(s), N6_) == hipSuccess ? MSM_OK : MSM_ERR_HIP;
+    }
+
+    // Fine runs of slices [s0, s1) into buffer par, as batches that do not wrap the ring.
+    int launch_f(int par, int s0, int s1)
+    {
+        while (s0 < s1) {
+            const int e = std::min(s1, s0 + (W_ - s0 % W_));
+            if (hipEventRecord(eva_, g_->stream) != hipSuccess || hipStreamWaitEvent(f_->stream, eva_, 0) != hipSuccess)
+                return MSM_ERR_HIP;
+            int rc = propagate(f_, n_, e - s0, q_, invm_, lam(s0), fslot(par, s0), p_.steps_f, p_.dt_f);
+            if (rc) return rc;
+            for (int s = s0; s < e; s++) {
+                const int k = par * W_ + s % W_;
+                if (hipEventRecord(fev_[k], f_->stream) != hipSuccess) return MSM_ERR_HIP;
+                frec_[k] = 1;
+            }
+            st_->fine_slices += e - s0;
+            s0 = e;
+        }
+        return MSM_OK;
+    }
+
+    // lambda_s is set for the coming sweep and needs a fine run (s < limit):
+    // queue it, and start the queued batch once it holds chunk slices.
+    int produced(int par, int s, int limit)
+    {
+        if (s >= limit) return MSM_OK;
+        if (pend0_ < 0) {
+            pend0_ = s;
+            ppar_ = par;
+        }
+        pend1_ = s + 1;
+        return pend1_ - pend0_ >= chunk_ ? flush() : MSM_OK;
+    }
+    int flush()
+    {
+        if (pend0_ < 0) return MSM_OK;
+        const int a = pend0_, e = pend1_;
+        pend0_ = -1;
+        return launch_f(ppar_, a, e);
+    }
+
+    int wait_f(int par, int s)
+    {
+        const int k = par * W_ + s % W_;
+        if (frec_[k] && hipStreamWaitEvent(g_->stream, fev_[k], 0) != hipSuccess) return MSM_ERR_HIP;
+        return MSM_OK;
+    }
+
+    // One step of the coarse sweep: lambda_{s+1} = F(lambda_s) + (G(lambda_s) - G_old(lambda_s)).
+    int sweep_step(int cur, int s, int end, int j)
+    {
+        // F(lambda_s) must be done, and the run that reads lambda_{s+1} before it is overwritten
+        int rc = wait_f(cur, s);
+        if (!rc && s + 1 < end) rc = wait_f(cur, s + 1);
+        if (rc) return rc;
+        double *gnew = g_->gnew;
+        if ((rc = propagate(g_, n_, 1, q_, invm_, lam(s), gnew, p_.steps_g, p_.dt_g))) return rc;
+        const hipError_t e =
+            rigid_ ? parareal_correct_rigid(g_->stream, n_, lam(s + 1), fslot(cur, s), gnew, rslot(s), invm_, f_->tri,
+                                            change() + j)
+                   : parareal_correct(g_->stream, N6_, lam(s + 1), fslot(cur, s), gnew, rslot(s), change() + j);
+        return e == hipSuccess ? MSM_OK : MSM_ERR_HIP;
+    }
+
+    msm_ctx *f_, *g_;
+    parareal_window_params p_;
+    int64_t n_;
+    const double *q_, *invm_;
+    double *lam_, *ring_;
+    parareal_window_state *st_;
+    bool rigid_;
+    int W_;
+    int64_t N6_;
+    int chunk_ = 1;
+    double *fbuf_[2] = {};
+    std::vector<hipEvent_t> fev_;
+    std::vector<char> frec_;
+    hipEvent_t eva_ = nullptr;
+    int pend0_ = -1, pend1_ = -1, ppar_ = 0;
+};
+
 }  // namespace
 
 extern "C" {
@@ -316,6 +504,31 @@ int parareal_run(msm_ctx *fine, msm_ctx *coarse, const parareal_params *pp, int6
     rep->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
     if (rc) return rc;
     return converged ? MSM_OK : MSM_NOT_CONVERGED;
+}
+
+int parareal_window_run(msm_ctx *fine, msm_ctx *coarse, const parareal_window_params *pp, int64_t n,
+                        const double *q, const double *invm, double *lambda, double *ring,
+                        parareal_window_state *st)
+{
+    const auto t0 = std::chrono::steady_clock::now();
+    if (!fine || !coarse || !pp || !q || !invm || !lambda || !ring || !st || n < 1) return MSM_ERR_ARG;
+    const int T = pp->nslices, W = pp->width;
+    if (T < 1 || W < 1 || pp->max_iters < 0 || pp->chunk < 0 || pp->steps_f < 0 || pp->steps_g < 0 ||
+        !(pp->dt_f > 0) || !(pp->dt_g > 0) || !(pp->tol >= 0))
+        return MSM_ERR_ARG;
+    if (st->start < 0 || st->start > T) return MSM_ERR_ARG;
+    if (!fine->md_bound || !coarse->md_bound || fine->device != coarse->device) return MSM_ERR_ARG;
+    if ((fine->rigid || coarse->rigid) && n % 3) return MSM_ERR_ARG;
+    const bool rigid = fine->rigid && coarse->rigid;
+    if (fine->prm.max_atoms < (int64_t)W * n || fine->prm.max_systems < W || coarse->prm.max_atoms < n)
+        return MSM_ERR_CAPACITY;
+    WindowRun r(fine, coarse, pp, n, q, invm, lambda, ring, st, rigid);
+    int rc = r.run();
+    const int sa = msm_get_status(coarse), sb = msm_get_status(fine);   // both streams idle after these
+    if (!rc) rc = sa ? sa : sb;
+    st->seconds += std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    if (rc) return rc;
+    return st->start == T ? MSM_OK : MSM_NOT_CONVERGED;
 }
 
 }  // extern "C"

@@ -349,7 +349,11 @@ __global__ void k_copy_f64(int64_t n, const double *__restrict__ src, double *__
     if (i < n) dst[i] = src[i];
 }
 
-__global__ void k_zero_u64(unsigned long long *p) { *p = 0ull; }
+__global__ void k_zero_u64(int n, unsigned long long *p)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0ull;
+}
 
 }  // namespace
 
@@ -431,9 +435,10 @@ hipError_t copy_f64(hipStream_t s, const double *src, double *dst, int64_t n)
     return hipGetLastError();
 }
 
-hipError_t zero_u64(hipStream_t s, unsigned long long *p)
+hipError_t zero_u64(hipStream_t s, unsigned long long *p, int n)
 {
-    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, p);
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_zero_u64, dim3((n + 255) / 256), dim3(256), 0, s, n, p);
     return hipGetLastError();
 }
 

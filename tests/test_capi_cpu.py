@@ -20,7 +20,7 @@ def declared_functions():
 def test_header_declares_the_boundary():
     names = declared_functions()
     for required in ("msm_setup", "msm_energy_forces", "msm_destroy", "msm_get_status", "parareal_run",
-                     "msm_vv_run", "msm_md_bind"):
+                     "parareal_window_run", "msm_vv_run", "msm_vv_mts_run", "msm_md_bind"):
         assert required in names
     assert len(names) >= 12
 
@@ -78,3 +78,43 @@ def test_setup_validates_parameters_before_touching_a_device():
     assert setup(basis=4) == -6
     assert setup(h=0.01) == -6          # a/h beyond the stencil's reach
     assert setup(method=1, h=0.01) != -6   # no stencil for the cutoff method
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    """The ctypes mirrors of the header's structs have the C sizes and field
+    offsets (a C program built from include/msm.h prints them)."""
+    import ctypes as C
+    import shutil
+    import subprocess
+    from paper_1309_1889_amd import binding
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    structs = {"msm_params": binding._Params, "msm_md_model": binding._Model,
+               "parareal_params": binding._PararealParams, "parareal_report": binding._PararealReport,
+               "parareal_window_params": binding._WindowParams, "parareal_window_state": binding.WindowState,
+               "msm_tuning": binding._Tuning}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "msm.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in py._fields_:
+            lines.append(f'printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {tuple(line.split()[:2]): int(line.split()[2]) for line in out if line.strip()}
+    for cname, py in structs.items():
+        assert got[(cname, "size")] == C.sizeof(py), cname
+        for fname, _ in py._fields_:
+            assert got[(cname, fname)] == getattr(py, fname).offset, (cname, fname)
+
+
+def test_window_run_validates_arguments_before_touching_a_device():
+    import ctypes as C
+    from paper_1309_1889_amd import binding
+    pp = binding._WindowParams()
+    st = binding.WindowState()
+    L = binding.lib()
+    assert L.parareal_window_run(None, None, C.byref(pp), 3, None, None, None, None, C.byref(st)) == -1
