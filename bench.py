@@ -57,6 +57,7 @@ def parse():
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--no-orders", action="store_true", help="skip the smoothing-order / basis-degree study")
     ap.add_argument("--no-mts", action="store_true", help="skip the multiple-time-step dynamics")
+    ap.add_argument("--no-window", action="store_true", help="skip the sliding-window parareal runs")
     ap.add_argument("--no-large", action="store_true", help="skip the 12.7M-atom slab")
     ap.add_argument("--only-fp32", action="store_true",
                     help="time only the single-system FP32 path (for profiler runs)")
@@ -66,7 +67,7 @@ def parse():
     args = ap.parse_args()
     if args.only_fp32:
         args.no_fp64 = args.no_accuracy = args.no_cpu_baseline = args.no_batched = args.no_parareal = True
-        args.no_large = args.no_orders = args.no_mts = True
+        args.no_large = args.no_orders = args.no_mts = args.no_window = True
     return args
 
 
@@ -338,6 +339,76 @@ def bench_orders(torch, msmx, w32, steps=20, warmup=3):
             "variants": rec}
 
 
+def bench_window(torch, msmx, slices=50, width=5, tol=1e-4, n_atoms=99999):
+    """Sliding-window parareal (Section 4's example: a 1 ps run with a 100 fs
+    window) on the water box: `slices` slices of 10 velocity-Verlet steps of
+    2 fs with the fine MSM (a = 1.2, h = 0.25), a window of `width` slices,
+    states accepted below `tol` nm; plain (one fine batch, then the coarse
+    sweep) and pipelined (fine batches on their own stream as soon as the
+    sweep has produced their states), against serial fine on the same GPU."""
+    from workloads import rigid_water_velocities, water_box, water_box_dims, water_model_arrays
+    dev = torch.device("cuda", 0)
+    n_mol, sites, box = water_box_dims(n_atoms)
+    w = water_box(n_mol, sites, box, seed=4, margin=3.0)
+    mass, molid, lj, tri = water_model_arrays(w.n)
+    v = rigid_water_velocities(w.xyz, 300.0, seed=104)
+    mol_t = torch.tensor(molid, dtype=torch.int32, device=dev)
+    lj_t = torch.tensor(lj, dtype=torch.float64, device=dev)
+
+    def ctx(a, h, ma, ms, method="msm", graphs=True, stream=None):
+        c = msmx.MsmContext(a, h, w.lo, w.hi, precision="fp32", max_atoms=ma, max_systems=ms, method=method)
+        c.bind_model(w.n, mol_t, lj_t, rigid=True, tri=tri)
+        c.set_graphs(graphs)
+        if stream is not None:
+            c.set_stream(stream)
+        return c
+
+    q = torch.tensor(w.q, device=dev)
+    invm = torch.tensor(1.0 / mass, device=dev)
+    s0 = torch.tensor(np.concatenate([w.xyz, v], 1), device=dev).contiguous()
+    serial = ctx(1.2, 0.25, w.n, 1)
+    x = torch.cat([s0[:, :3], q[:, None]], 1).contiguous()
+    vv = torch.cat([s0[:, 3:], invm[:, None]], 1).contiguous()
+    serial.vv_run(x.clone(), vv.clone(), 2, 0.002, energies=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    serial.vv_run(x, vv, 10 * slices, 0.002, energies=False)
+    torch.cuda.synchronize()
+    serial_s = time.perf_counter() - t0
+    serial.check()
+    out = {"workload": f"{slices} slices x 10 x 2 fs ({slices * 20} fs), window {width} slices ({width * 20} fs), "
+                       f"{w.n} atoms, rigid water at 300 K, fine MSM a 1.2 h 0.25, tolerance {tol:g} nm",
+           "serial_fine_seconds": serial_s}
+    side = torch.cuda.Stream()
+    for name, method, a, h, desc in (("coarse_cutoff_10x2fs", "cutoff", 1.2, 0.25, "simple cutoff 1.2 nm"),
+                                     ("coarse_msm_10x2fs", "msm", 0.8, 0.5, "MSM a 0.8, h 0.5")):
+        coarse = ctx(a, h, w.n, 1, method)
+        rec = {"coarse": f"10 x 2 fs, {desc}"}
+        for mode, pipe in (("plain", False), ("pipelined", True)):
+            fine = ctx(1.2, 0.25, width * w.n, width, graphs=False, stream=side if pipe else None)
+            lam = torch.zeros((slices + 1, w.n, 6), dtype=torch.float64, device=dev)
+            lam[0] = s0
+            ring = torch.zeros((width, w.n, 6), dtype=torch.float64, device=dev)
+            st = msmx.WindowState()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            try:
+                msmx.parareal_window(fine, coarse, q, invm, lam, ring, st, width=width, tol=tol, steps_f=10,
+                                     dt_f=0.002, steps_g=10, dt_g=0.002, pipeline=pipe)
+                secs = time.perf_counter() - t1
+                rec[mode] = {"seconds": secs, "iterations": st.iterations, "fine_slice_runs": st.fine_slices,
+                             "coarse_slice_runs": st.coarse_slices, "speedup_vs_serial_fine": serial_s / secs,
+                             "final_max_dev_vs_serial_nm": float((lam[slices, :, :3] - x[:, :3]).abs().max()),
+                             "final_rms_dev_vs_serial_nm": float((lam[slices, :, :3] - x[:, :3]).pow(2).sum(1)
+                                                                 .mean().sqrt())}
+            except msmx.MsmError as e:
+                rec[mode] = {"status": f"failed: {e}"}
+            del fine, lam, ring
+        out[name] = rec
+        del coarse
+    return out
+
+
 def bench_mts(torch, msmx, inner_steps=100, dt_inner=0.002):
     """Multiple time steps on the 99,999-atom water box (rigid water at 300 K,
     FP32 forces): the grid part every 1 (plain velocity Verlet), 2 and 4
@@ -537,7 +608,7 @@ def main():
                 accuracy["fp64_force_rel_rms"] = rel_rms(out64[1].cpu().numpy(), fo)
                 accuracy["fp64_energy_rel"] = abs(out64[0].item() - eo) / abs(eo)
 
-    batched = uneven = par = large = orders = mts = None
+    batched = uneven = par = large = orders = mts = window = None
     if not args.no_batched:
         batched, uneven = bench_batched(torch, msmx, w32, args.steps, args.warmup, args.slices, value)
     if not args.no_parareal:
@@ -548,6 +619,8 @@ def main():
         orders = bench_orders(torch, msmx, w32)
     if not args.no_mts:
         mts = bench_mts(torch, msmx)
+    if not args.no_window:
+        window = bench_window(torch, msmx)
 
     result.update({
         "value": value,
@@ -575,6 +648,7 @@ def main():
         "large_box": large,
         "orders": orders,
         "mts": mts,
+        "window": window,
         "launch": {"mode": launch_mode, "tuning": tuning32, "graph_ms_per_step": graph_ms,
                    "eager_default_ms_per_step": eager_default_ms, "eager_tuned_ms_per_step": eager_tuned_ms},
         "accuracy": accuracy,

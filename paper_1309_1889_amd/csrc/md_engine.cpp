@@ -201,10 +201,12 @@ int propagate(msm_ctx *c, int64_t n, int count, const double *q, const double *i
 
 // Sliding-window parareal (Section 4). The coarse context's stream runs the
 // serial coarse work (predictions, sweeps), the fine context's stream the
-// batched fine runs; events order the two. The window's fine results sit in
-// two buffers used alternately: the sweep of one iteration reads one while
-// the fine runs for the next iteration (pipelined mode) fill the other. A
-// slice s uses slot s % width of the coarse ring and of either buffer.
+// batched fine runs; events order the two. Slice s keeps G(lambda_s) in slot
+// s % width of the coarse ring. The plain mode runs the window's fine batch at
+// the start of each iteration into one buffer, slice s at slot s - start. The
+// pipelined mode uses two buffers alternately, slice s at slot s % width: the
+// sweep of one iteration reads one while the fine runs for the next iteration
+// fill the other.
 class WindowRun {
   public:
     WindowRun(msm_ctx *fine, msm_ctx *coarse, const parareal_window_params *pp, int64_t n, const double *q,
@@ -214,7 +216,8 @@ class WindowRun {
     {
         fbuf_[0] = fine->fout;
         fbuf_[1] = fine->gold;
-        chunk_ = p_.pipeline ? (p_.chunk > 0 ? std::min(p_.chunk, W_) : (W_ + 3) / 4) : W_;
+        pipe_ = p_.pipeline != 0;
+        chunk_ = pipe_ ? (p_.chunk > 0 ? std::min(p_.chunk, W_) : (W_ + 3) / 4) : W_;
     }
     ~WindowRun()
     {
@@ -236,7 +239,8 @@ class WindowRun {
         if (b == T) return MSM_OK;
         int end = b + std::min(W_, T - b);
         int cur = 0, rc = MSM_OK;
-        const bool pipe = p_.pipeline != 0;
+        const bool pipe = pipe_;
+        base_ = b;
         // fine runs of the first iteration: from the window's states as they are ready
         if (!st_->window_valid) {
             if ((rc = produced(cur, b, end))) return rc;
@@ -257,7 +261,10 @@ class WindowRun {
             const int we = end - b;
             const int nxt = pipe ? 1 - cur : cur;
             const bool ahead = pipe && !(p_.max_iters > 0 && it + 1 == p_.max_iters);
-            if (!pipe && it > 0 && (rc = launch_f(cur, b, end))) return rc;
+            if (!pipe && it > 0) {
+                base_ = b;
+                if ((rc = launch_f(cur, b, end))) return rc;
+            }
             if (zero_u64(g_->stream, change(), we) != hipSuccess) return MSM_ERR_HIP;
             for (int s = b; s < end; s++) {
                 if ((rc = sweep_step(cur, s, end, s - b))) return rc;
@@ -294,7 +301,8 @@ class WindowRun {
   private:
     double *lam(int s) const { return lam_ + (int64_t)s * N6_; }
     double *rslot(int s) const { return ring_ + (int64_t)(s % W_) * N6_; }
-    double *fslot(int par, int s) const { return fbuf_[par] + (int64_t)(s % W_) * N6_; }
+    int slot(int s) const { return pipe_ ? s % W_ : s - base_; }
+    double *fslot(int par, int s) const { return fbuf_[par] + (int64_t)slot(s) * N6_; }
     unsigned long long *change() const { return (unsigned long long *)f_->md_scalar; }
 
     // lambda_{s+1} = G(lambda_s), kept in the ring as the old coarse value
@@ -306,17 +314,17 @@ class WindowRun {
         return copy_f64(g_->stream, lam(s + 1), rslot(s), N6_) == hipSuccess ? MSM_OK : MSM_ERR_HIP;
     }
 
-    // Fine runs of slices [s0, s1) into buffer par, as batches that do not wrap the ring.
+    // Fine runs of slices [s0, s1) into buffer par, as batches whose slots do not wrap.
     int launch_f(int par, int s0, int s1)
     {
         while (s0 < s1) {
-            const int e = std::min(s1, s0 + (W_ - s0 % W_));
+            const int e = std::min(s1, s0 + (W_ - slot(s0)));
             if (hipEventRecord(eva_, g_->stream) != hipSuccess || hipStreamWaitEvent(f_->stream, eva_, 0) != hipSuccess)
                 return MSM_ERR_HIP;
             int rc = propagate(f_, n_, e - s0, q_, invm_, lam(s0), fslot(par, s0), p_.steps_f, p_.dt_f);
             if (rc) return rc;
             for (int s = s0; s < e; s++) {
-                const int k = par * W_ + s % W_;
+                const int k = par * W_ + slot(s);
                 if (hipEventRecord(fev_[k], f_->stream) != hipSuccess) return MSM_ERR_HIP;
                 frec_[k] = 1;
             }
@@ -348,7 +356,7 @@ class WindowRun {
 
     int wait_f(int par, int s)
     {
-        const int k = par * W_ + s % W_;
+        const int k = par * W_ + slot(s);
         if (frec_[k] && hipStreamWaitEvent(g_->stream, fev_[k], 0) != hipSuccess) return MSM_ERR_HIP;
         return MSM_OK;
     }
@@ -378,7 +386,9 @@ class WindowRun {
     bool rigid_;
     int W_;
     int64_t N6_;
+    bool pipe_ = false;
     int chunk_ = 1;
+    int base_ = 0;   // plain mode: the window's first slice
     double *fbuf_[2] = {};
     std::vector<hipEvent_t> fev_;
     std::vector<char> frec_;
