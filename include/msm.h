@@ -133,24 +133,32 @@ int msm_energy_forces(msm_ctx *ctx, int nsys, const int64_t *offsets_host,
                       const double *domains_host, const void *xyzq_dev,
                       double *energy_dev, void *forces_dev, void *potentials_dev);
 
-/* Launch configuration of the two heaviest kernels. Every configuration is
- * deterministic, but they add the same terms in different orders, so results
- * of different configurations agree to rounding, not bitwise (contexts that
- * must agree bitwise, e.g. a parareal pair and its serial reference, should
- * share one configuration). Defaults: 8 waves, 1024 threads. */
+/* Launch configuration of the two heaviest kernels, and of the stream use of
+ * an evaluation. Every configuration is deterministic, but pair_waves and
+ * stencil_threads add the same terms in different orders, so results of
+ * different values agree to rounding, not bitwise (contexts that must agree
+ * bitwise, e.g. a parareal pair and its serial reference, should share one
+ * configuration); concurrent changes no result bit. Defaults: 4 waves, 1024
+ * threads, concurrent. */
 typedef struct {
-    int pair_waves;        /* waves sharing one 64-atom group of the short-range sum: 4, 8 or 16 */
+    int pair_waves;        /* short-range sum: 4, 8 or 16 waves share one 64-atom group, one
+                              lane per atom; 1: each wave owns 16 atoms, four lanes per atom */
     int stencil_threads;   /* threads per lattice-cutoff tile: 256 or 1024 */
+    int concurrent;        /* 1: the short-range sum runs on a second stream of the context,
+                              concurrently with the grid stages (forked after binning,
+                              joined before interpolation; HIP graphs capture both branches);
+                              0: every stage on the context stream in turn. Stage timing
+                              always runs the stages in turn. */
 } msm_tuning;
 
 int msm_get_tuning(const msm_ctx *ctx, msm_tuning *out);
 int msm_set_tuning(msm_ctx *ctx, const msm_tuning *tuning);
 
-/* Autotuner: time every pair_waves candidate on the short-range stage and
- * every stencil_threads candidate on the lattice-cutoff stage, reps
- * evaluations each, on the caller's own batch (arguments as for
- * msm_energy_forces; no outputs are written), keep the fastest of each and
- * report them in *chosen (may be NULL). Synchronous. */
+/* Autotuner: time whole evaluations (launched eagerly, with the context's
+ * concurrent setting) for every pair_waves and stencil_threads candidate,
+ * reps evaluations each, on the caller's own batch (arguments as for
+ * msm_energy_forces; no outputs are written), keep the fastest pair and
+ * report it in *chosen (may be NULL). Synchronous. */
 int msm_autotune(msm_ctx *ctx, int nsys, const int64_t *offsets_host, const double *domains_host,
                  const void *xyzq_dev, int reps, msm_tuning *chosen);
 

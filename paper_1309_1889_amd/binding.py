@@ -58,7 +58,7 @@ class _PararealReport(C.Structure):
 
 
 class _Tuning(C.Structure):
-    _fields_ = [("pair_waves", C.c_int), ("stencil_threads", C.c_int)]
+    _fields_ = [("pair_waves", C.c_int), ("stencil_threads", C.c_int), ("concurrent", C.c_int)]
 
 
 METHODS = {"msm": 0, "cutoff": 1, "wolf": 2}
@@ -223,10 +223,14 @@ class MsmContext:
     def tuning(self):
         t = _Tuning()
         _check(lib().msm_get_tuning(self._h, C.byref(t)), "msm_get_tuning")
-        return {"pair_waves": t.pair_waves, "stencil_threads": t.stencil_threads}
+        return {"pair_waves": t.pair_waves, "stencil_threads": t.stencil_threads, "concurrent": t.concurrent}
 
-    def set_tuning(self, pair_waves, stencil_threads):
-        t = _Tuning(int(pair_waves), int(stencil_threads))
+    def set_tuning(self, pair_waves=None, stencil_threads=None, concurrent=None):
+        """Set the launch configuration (msm_set_tuning); None keeps a field."""
+        cur = self.tuning()
+        t = _Tuning(int(cur["pair_waves"] if pair_waves is None else pair_waves),
+                    int(cur["stencil_threads"] if stencil_threads is None else stencil_threads),
+                    int(cur["concurrent"] if concurrent is None else concurrent))
         _check(lib().msm_set_tuning(self._h, C.byref(t)), "msm_set_tuning")
 
     def autotune(self, xyzq, offsets=None, domains=None, reps=5):
@@ -241,7 +245,7 @@ class MsmContext:
         t = _Tuning()
         _check(lib().msm_autotune(self._h, nsys, offs.ctypes.data_as(C.POINTER(C.c_int64)), dom_p,
                                   C.c_void_p(xyzq.data_ptr()), int(reps), C.byref(t)), "msm_autotune")
-        return {"pair_waves": t.pair_waves, "stencil_threads": t.stencil_threads}
+        return {"pair_waves": t.pair_waves, "stencil_threads": t.stencil_threads, "concurrent": t.concurrent}
 
     def set_graphs(self, enable=True):
         """Replay captured HIP graphs for repeated evaluations (msm_set_graphs)."""

@@ -327,7 +327,23 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     // the short-range potentials are needed only for the energy and the potentials
     const bool pot = energy || pots || c->tuning_pass;
     const bool do_short = part != kEvalLong, do_long = part != kEvalShort;
-    if (do_short && (e = L::pair(s, p, w, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
+    // the pair sum and the grid stages share only the binned atoms: with
+    // concurrency on, the pair kernel runs on the side stream from here until
+    // the join before interpolation
+    const bool fork = do_short && do_long && c->concurrent && !c->timing && p.nnodes[0] > 0;
+    hipStream_t ps = s;
+    if (fork) {
+        if (!c->side_stream && hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking) != hipSuccess)
+            return MSM_ERR_HIP;
+        if (!c->ev_fork && hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess)
+            return MSM_ERR_HIP;
+        if (!c->ev_join && hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess)
+            return MSM_ERR_HIP;
+        if (hipEventRecord(c->ev_fork, s) != hipSuccess || hipStreamWaitEvent(c->side_stream, c->ev_fork, 0) != hipSuccess)
+            return MSM_ERR_HIP;
+        ps = c->side_stream;
+    }
+    if (do_short && (e = L::pair(ps, p, w, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_ANTERP);
     if (do_long && (e = L::anterp(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_RESTRICT);
@@ -344,6 +360,8 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     mark(MSM_STAGE_PROLONG);
     for (int k = p.maxlev - 2; do_long && k >= 0; k--)
         if ((e = L::prolong_level(s, p, w, k, c->mc)) != hipSuccess) return MSM_ERR_HIP;
+    if (fork && (hipEventRecord(c->ev_join, ps) != hipSuccess || hipStreamWaitEvent(s, c->ev_join, 0) != hipSuccess))
+        return MSM_ERR_HIP;
     mark(MSM_STAGE_INTERP);
     if ((e = L::interp(s, p, w, c->mc, (T *)forces, (T *)pots, part)) != hipSuccess) return MSM_ERR_HIP;
     if ((e = L::energy(s, p, w, energy)) != hipSuccess) return MSM_ERR_HIP;
@@ -525,7 +543,7 @@ int msm_setup(const msm_params *prm, void *stream, msm_ctx **out)
     c->mc.g = make_smooth(smoothing);
     c->mc.p = basis_degree(*prm);
     c->mc.reach = cutoff ? 0 : reach;
-    c->mc.pair_waves = 8;
+    c->mc.pair_waves = 4;
     c->mc.stencil_threads = 1024;
     c->d2max = (int)std::ceil(ratio * ratio) - 1;      // largest integer below (2a/h)^2
     int rc = geometry(*prm, prm->lo, prm->hi, c->ctx_geom);
@@ -580,6 +598,12 @@ void msm_destroy(msm_ctx *c)
         if (e) (void)hipEventDestroy(e);
     for (auto &e : c->plan_ev)
         if (e) (void)hipEventDestroy(e);
+    if (c->side_stream) {
+        (void)hipStreamSynchronize(c->side_stream);
+        (void)hipStreamDestroy(c->side_stream);
+    }
+    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+    if (c->ev_join) (void)hipEventDestroy(c->ev_join);
     for (auto &g : c->graphs) drop_graph(g);
     if (c->capture_stream) (void)hipStreamDestroy(c->capture_stream);
     if (c->wbuf) (void)hipFree(c->wbuf);
@@ -615,18 +639,21 @@ int msm_get_tuning(const msm_ctx *c, msm_tuning *t)
     if (!c || !t) return MSM_ERR_ARG;
     t->pair_waves = c->mc.pair_waves;
     t->stencil_threads = c->mc.stencil_threads;
+    t->concurrent = c->concurrent ? 1 : 0;
     return MSM_OK;
 }
 
 int msm_set_tuning(msm_ctx *c, const msm_tuning *t)
 {
     if (!c || !t) return MSM_ERR_ARG;
-    if (t->pair_waves != 4 && t->pair_waves != 8 && t->pair_waves != 16) return MSM_ERR_ARG;
+    if (t->pair_waves != 1 && t->pair_waves != 4 && t->pair_waves != 8 && t->pair_waves != 16) return MSM_ERR_ARG;
     if (t->stencil_threads != 256 && t->stencil_threads != 1024) return MSM_ERR_ARG;
+    if (t->concurrent != 0 && t->concurrent != 1) return MSM_ERR_ARG;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
     for (auto &g : c->graphs) drop_graph(g);     // captured launches use the old kernels
     c->mc.pair_waves = t->pair_waves;
     c->mc.stencil_threads = t->stencil_threads;
+    c->concurrent = t->concurrent != 0;
     return MSM_OK;
 }
 
@@ -637,52 +664,52 @@ int msm_autotune(msm_ctx *c, int nsys, const int64_t *offsets, const double *dom
     if (nsys > c->prm.max_systems) return MSM_ERR_CAPACITY;
     int rc = build_plan(c, nsys, offsets, domains);
     if (rc) return rc;
-    const bool was_timing = c->timing;
-    const msm_tuning start{c->mc.pair_waves, c->mc.stencil_threads};
-    if ((rc = msm_enable_stage_timing(c, 1))) return rc;
+    const msm_tuning start{c->mc.pair_waves, c->mc.stencil_threads, c->concurrent ? 1 : 0};
+    // whole evaluations, launched eagerly with the context's stream use: with
+    // concurrent stages the pair kernel that fits best beside the grid stages
+    // is not the fastest one alone
+    const bool was_timing = c->timing, had_graphs = c->use_graphs;
+    c->timing = false;
+    c->use_graphs = false;
     c->tuning_pass = true;   // time the pair kernel that also sums the potentials
-    // time one stage for one candidate: a warm-up evaluation, then reps
-    auto stage_time = [&](int stage, double *ms) {
-        int r = evaluate_any(c, xyzq, nullptr, nullptr, nullptr);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = MSM_ERR_HIP;
+    auto eval_time = [&](double *ms) {
+        int r = evaluate_any(c, xyzq, nullptr, nullptr, nullptr);   // warm-up
         if (r) return r;
-        msm_stage_timing(c, nullptr, nullptr, 1);
+        if (hipEventRecord(e0, c->stream) != hipSuccess) return (int)MSM_ERR_HIP;
         for (int i = 0; i < reps && !r; i++) r = evaluate_any(c, xyzq, nullptr, nullptr, nullptr);
-        double all[MSM_NSTAGES];
-        int64_t n = 0;
-        msm_stage_timing(c, all, &n, 1);
-        *ms = all[stage] / (n ? n : 1);
-        return r;
+        if (r) return r;
+        float t = 0;
+        if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+            hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+            return (int)MSM_ERR_HIP;
+        *ms = t / reps;
+        return (int)MSM_OK;
     };
     msm_tuning best = start;
     double best_ms = 1e300;
-    for (int pw : {4, 8, 16}) {
-        c->mc.pair_waves = pw;
-        double ms;
-        if ((rc = stage_time(MSM_STAGE_SHORT, &ms))) break;
-        if (ms < best_ms) {
-            best_ms = ms;
-            best.pair_waves = pw;
+    for (int pw : {1, 4, 8, 16})
+        for (int st : {256, 1024}) {
+            if (rc) break;
+            c->mc.pair_waves = pw;
+            c->mc.stencil_threads = st;
+            double ms = 0;
+            if ((rc = eval_time(&ms))) break;
+            if (ms < best_ms) {
+                best_ms = ms;
+                best.pair_waves = pw;
+                best.stencil_threads = st;
+            }
         }
-    }
-    c->mc.pair_waves = best.pair_waves;
-    best_ms = 1e300;
-    for (int st : {256, 1024}) {
-        if (rc) break;
-        c->mc.stencil_threads = st;
-        double ms;
-        if ((rc = stage_time(MSM_STAGE_CUTOFF, &ms))) break;
-        if (ms < best_ms) {
-            best_ms = ms;
-            best.stencil_threads = st;
-        }
-    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
     c->timing = was_timing;
+    c->use_graphs = had_graphs;
     c->tuning_pass = false;
-    if (rc) {
-        c->mc.pair_waves = start.pair_waves;
-        c->mc.stencil_threads = start.stencil_threads;
-        return rc;
-    }
+    c->mc.pair_waves = start.pair_waves;
+    c->mc.stencil_threads = start.stencil_threads;
+    if (rc) return rc;
     int r2 = msm_set_tuning(c, &best);
     if (r2) return r2;
     if (chosen) *chosen = best;

@@ -59,6 +59,10 @@ struct msm_ctx {
     hipEvent_t ev[MSM_NSTAGES + 1] = {};
     double stage_ms[MSM_NSTAGES] = {};
     int64_t timed_evals = 0;
+    // concurrent stages: the short-range sum on side_stream between the two events
+    bool concurrent = true;
+    hipStream_t side_stream = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // captured evaluations (msm_set_graphs)
     bool use_graphs = false;
     hipStream_t capture_stream = nullptr;

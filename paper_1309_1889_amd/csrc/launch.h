@@ -74,7 +74,7 @@ struct MethodConst {
     Smooth g;                  // smoothing function gamma of order g.m
     int p;                     // degree of the nodal basis Phi: 3 or 5
     int reach;                 // stencil reach R: largest integer with R < 2a/h
-    int pair_waves;            // waves per 64-atom group in the pair kernel: 4, 8 or 16
+    int pair_waves;            // waves per 64-atom group in the pair kernel: 4, 8 or 16; 1: 16-atom sub-groups
     int stencil_threads;       // threads per stencil tile: 256 or 1024
 };
 

@@ -463,9 +463,15 @@ __global__ __launch_bounds__(256) void k_top(DevPlan p, const T *__restrict__ qg
 
 // ---------------------------------------------------------------------------
 // Prolongation (Section 3): u^k_mu = u^{k,cutoff}_mu + sum_nu phi^{k+1}_nu(r^k_mu) u^{k+1}_nu,
-// the transpose of restriction. Per axis an even fine index 2n takes the
-// coarse node n with weight 1; an odd index 2n+1 takes the 2S coarse nodes
-// n-(S-1) .. n+S (cubic: n-1 .. n+2 with -1/16, 9/16, 9/16, -1/16).
+// the transpose of restriction. Per axis, fine index m sits at coarse
+// coordinate m/2; with n = floor(m/2) the coarse nodes n-(S-1) .. n+S carry
+// the weights Phi((m - 2 nu)/2). For odd m these are the 2S nodes of the
+// support (cubic: -1/16, 9/16, 9/16, -1/16); for even m Phi of an integer is
+// 1 at nu = n and 0 elsewhere (set exactly), so the same 2S taps serve both
+// parities. The taps are fully unrolled, so the loads of a node do not wait
+// for one another. An even m at the top of the range can name a coarse node
+// one past the coarse grid; its weight is 0 and its index is clamped into the
+// grid.
 // ---------------------------------------------------------------------------
 template <typename T, int PD>
 __device__ inline void prolong_node(const SysPlan &P, const T *__restrict__ ucut, T *__restrict__ ugrid, int k,
@@ -477,35 +483,31 @@ __device__ inline void prolong_node(const SysPlan &P, const T *__restrict__ ucut
     const int r[3] = {(int)(loc % dx), (int)((loc / dx) % dy), (int)(loc / ((int64_t)dx * dy))};
     int cn[3][W];
     T cw[3][W];
-    int cnt[3];
+#pragma unroll
     for (int d = 0; d < 3; ++d) {
         const int m = r[d] + P.gorg[k][d];          // absolute fine index
-        const int c0 = P.gorg[k + 1][d];
-        if ((m & 1) == 0) {
-            cnt[d] = 1;
-            cn[d][0] = (m >> 1) - c0;
-            cw[d][0] = T(1);
-        } else {
-            // the coarse nodes n-(S-1) .. n+S around m = 2n+1, at fine offsets m - 2 nu = 2S-1 .. -(2S-1)
-            const int n = (m - 1) >> 1;             // floor(m/2)
-            cnt[d] = W;
+        const int c0 = P.gorg[k + 1][d], cd = P.gdim[k + 1][d];
+        const int n = m >> 1;                       // floor(m/2), m may be negative
 #pragma unroll
-            for (int j = 0; j < W; ++j) {
-                const int nu = n - (S - 1) + j;
-                cn[d][j] = nu - c0;
-                cw[d][j] = B::phi(T(0.5 * (m - 2 * nu)));
-            }
+        for (int j = 0; j < W; ++j) {
+            const int nu = n - (S - 1) + j;
+            cn[d][j] = min(max(nu - c0, 0), cd - 1);
+            // even m: exactly the cardinal weights (1 at nu = n)
+            cw[d][j] = (m & 1) ? B::phi(T(0.5 * (m - 2 * nu))) : T(j == S - 1 ? 1 : 0);
         }
     }
     const int cdx = P.gdim[k + 1][0], cdy = P.gdim[k + 1][1];
     const T *uc = ugrid + P.uoff[k + 1];
     T acc = 0;
-    for (int c = 0; c < cnt[2]; ++c) {
+#pragma unroll
+    for (int c = 0; c < W; ++c) {
         T accy = 0;
-        for (int b = 0; b < cnt[1]; ++b) {
+#pragma unroll
+        for (int b = 0; b < W; ++b) {
             const T *row = uc + ((int64_t)cn[2][c] * cdy + cn[1][b]) * cdx;
             T accx = 0;
-            for (int a = 0; a < cnt[0]; ++a) accx += cw[0][a] * row[cn[0][a]];
+#pragma unroll
+            for (int a = 0; a < W; ++a) accx += cw[0][a] * row[cn[0][a]];
             accy += cw[1][b] * accx;
         }
         acc += cw[2][c] * accy;

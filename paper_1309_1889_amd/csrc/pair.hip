@@ -304,6 +304,199 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
     }
 }
 
+// Sub-group form (pair_waves = 1): each wave of a 4-wave workgroup owns 16
+// of the group's 64 atoms, four lanes per atom. The candidate region of 16
+// atoms is smaller than that of 64 (about 0.7 times the candidates per atom
+// at the default water density), and the lanes of one atom read four
+// consecutive candidates of the stream at a time, so a wave still evaluates
+// 64 pairs per step. The four partial sums of an atom are added across its
+// lanes in a fixed order; the waves share nothing, so there is no barrier.
+constexpr int kSub = 16;                 // atoms per wave
+constexpr int kSubLanes = kWave / kSub;  // lanes per atom
+constexpr int kSubUnroll = 4;            // steps of kSubLanes candidates read at once
+
+template <typename T> __device__ inline T sum_lanes(T v)
+{
+    v += __shfl_xor(v, kSub, kWave);
+    v += __shfl_xor(v, 2 * kSub, kWave);
+    return v;
+}
+
+template <typename T, bool MD, bool POT, int KIND>
+__global__ __launch_bounds__(kSubLanes * kWave) void k_pair_sub(DevPlan p, const vec4_t<T> *__restrict__ sx,
+                                                                const int *__restrict__ cstart,
+                                                                vec4_t<T> *__restrict__ out, PairK<T> k,
+                                                                const vec4_t<T> *__restrict__ saux,
+                                                                vec4_t<T> *__restrict__ ljout)
+{
+    __shared__ PairLds<T, MD> lds[kWave / kSub];
+    const int64_t g = blockIdx.x;
+    const int s = find_segment(p.group_prefix, p.nsys, g);
+    const SysPlan &P = p.sys[s];
+    const int lane = threadIdx.x % kWave;
+    const int wv = uni((int)(threadIdx.x / kWave));
+    PairLds<T, MD> &L = lds[wv];
+    const int64_t first = P.atom0 + (g - p.group_prefix[s]) * kWave + wv * kSub;
+    const int64_t end = P.atom0 + P.natoms;
+    if (first >= end) return;   // the whole wave: no atoms in this sub-group
+    const int me = lane % kSub, slot = lane / kSub;   // the lane's atom and candidate slot
+    const int64_t i = first + me;
+    const bool valid = i < end;
+    const vec4_t<T> ai = sx[valid ? i : first];
+    vec4_t<T> xi;
+    if (MD) xi = saux[valid ? i : first];
+
+    const T bminx = uni(wave_min(ai.x)), bmaxx = uni(wave_max(ai.x));
+    const T bminy = uni(wave_min(ai.y)), bmaxy = uni(wave_max(ai.y));
+    const T bminz = uni(wave_min(ai.z)), bmaxz = uni(wave_max(ai.z));
+    const T lox = T(P.lo[0]), loy = T(P.lo[1]), loz = T(P.lo[2]);
+    const T inv_h = T(P.inv_h), h = T(1.0 / P.inv_h);
+    const int ncx = P.nc[0], ncy = P.nc[1], ncz = P.nc[2];
+    const T reach = k.reach, reach2 = k.reach * k.reach;
+    const int cy0 = clampi((int)floor((bminy - loy - reach) * inv_h), 0, ncy - 1);
+    const int cy1 = clampi((int)floor((bmaxy - loy + reach) * inv_h), 0, ncy - 1);
+    const int cz0 = clampi((int)floor((bminz - loz - reach) * inv_h), 0, ncz - 1);
+    const int cz1 = clampi((int)floor((bmaxz - loz + reach) * inv_h), 0, ncz - 1);
+    const int bx0 = clampi((int)floor((bminx - lox - reach) * inv_h), 0, ncx - 1) / kBrick;
+    const int bx1 = clampi((int)floor((bmaxx - lox + reach) * inv_h), 0, ncx - 1) / kBrick;
+    const int nbx = bx1 - bx0 + 1, ny = cy1 - cy0 + 1;
+    const int nitems = nbx * ny * (cz1 - cz0 + 1);
+
+    if (KIND == kPolyHigh)
+        asm volatile("" : "+v"(k.c2), "+v"(k.d1));
+    else if (KIND == kPoly)
+        asm volatile("" : "+v"(k.c1), "+v"(k.d0));
+    T fx = 0, fy = 0, fz = 0, u = 0;
+    T lx = 0, ly = 0, lz = 0, le = 0;
+    for (int ib = 0; ib < nitems; ib += kWave) {
+        const int q = ib + lane;   // this lane's item
+        int len = 0, jb = 0;
+        if (q < nitems) {
+            const int bx = bx0 + q % nbx, row = q / nbx;
+            const int cy = cy0 + row % ny, cz = cz0 + row / ny;
+            const T z0 = loz + T(cz) * h, y0 = loy + T(cy) * h;
+            const T dz = fmax(T(0), fmax(z0 - bmaxz, bminz - (z0 + h)));
+            const T dy = fmax(T(0), fmax(y0 - bmaxy, bminy - (y0 + h)));
+            const T rem = reach2 - dy * dy - dz * dz;
+            if (rem > T(0)) {
+                const T wdt = sqrt(rem);
+                const int cx0 = clampi((int)floor((bminx - lox - wdt) * inv_h), 0, ncx - 1);
+                const int cx1 = clampi((int)floor((bmaxx - lox + wdt) * inv_h), 0, ncx - 1);
+                const int ca = max(cx0, bx * kBrick), cb = min(cx1, bx * kBrick + kBrick - 1);
+                if (ca <= cb) {
+                    const int64_t r0 = P.cell0 + cell_rank(P, ca, cy, cz);
+                    jb = cstart[r0];
+                    len = cstart[r0 + (cb - ca) + 1] - jb;
+                }
+            }
+        }
+        int incl = len;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int v = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += v;
+        }
+        L.pre[lane] = incl - len;
+        L.first[lane] = jb;
+        const int total = uni(__shfl(incl, kWave - 1, kWave));
+        if (lane == 0) L.pre[kWave] = total;
+        __builtin_amdgcn_wave_barrier();
+        auto locate = [&](int pos) -> int {
+            int lo_ = 0, hi_ = kWave;
+            while (hi_ - lo_ > 1) {
+                const int mid = (lo_ + hi_) >> 1;
+                if (L.pre[mid] <= pos) lo_ = mid; else hi_ = mid;
+            }
+            return L.first[lo_] + (pos - L.pre[lo_]);
+        };
+        vec4_t<T> pa, px;
+        if (lane < total) {
+            const int j = locate(lane);
+            pa = sx[j];
+            if (MD) px = saux[j];
+        }
+        for (int c0 = 0; c0 < total; c0 += kWave) {
+            __builtin_amdgcn_wave_barrier();
+            L.atom[lane] = pa;
+            if (MD) L.aux[lane] = px;
+            __builtin_amdgcn_wave_barrier();
+            const int nxt = c0 + kWave + lane;
+            if (nxt < total) {
+                const int j = locate(nxt);
+                pa = sx[j];
+                if (MD) px = saux[j];
+            }
+            const int cnt = uni(min(kWave, total - c0));
+            int t = 0;
+            constexpr int step = kSubLanes * kSubUnroll;
+            for (; t + step <= cnt; t += step) {
+                vec4_t<T> aj[kSubUnroll], xj[kSubUnroll];
+#pragma unroll
+                for (int v = 0; v < kSubUnroll; ++v) {
+                    aj[v] = L.atom[t + kSubLanes * v + slot];
+                    xj[v] = MD ? L.aux[t + kSubLanes * v + slot] : aj[v];
+                }
+#pragma unroll
+                for (int v = 0; v < kSubUnroll; ++v)
+                    pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le);
+            }
+            for (; t < cnt; t += kSubLanes) {
+                const int tj = t + slot;
+                if (tj < cnt) {
+                    const vec4_t<T> aj = L.atom[tj];
+                    const vec4_t<T> xj = MD ? L.aux[tj] : aj;
+                    pair_term<T, MD, POT, KIND>(ai, xi, aj, xj, k, fx, fy, fz, u, lx, ly, lz, le);
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    fx = sum_lanes(fx);
+    fy = sum_lanes(fy);
+    fz = sum_lanes(fz);
+    if (POT) u = sum_lanes(u);
+    if (MD) {
+        lx = sum_lanes(lx);
+        ly = sum_lanes(ly);
+        lz = sum_lanes(lz);
+        if (POT) le = sum_lanes(le);
+    }
+    if (slot == 0 && valid) {
+        vec4_t<T> o;
+        o.x = fx;
+        o.y = fy;
+        o.z = fz;
+        o.w = u;
+        out[i] = o;
+        if (MD) {
+            vec4_t<T> ol;
+            ol.x = lx;
+            ol.y = ly;
+            ol.z = lz;
+            ol.w = le;
+            ljout[i] = ol;
+        }
+    }
+}
+
+template <typename T, int KIND>
+static void pair_launch_sub(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot)
+{
+    const dim3 grid((unsigned)p.ngroups), block(kSubLanes * kWave);
+    const vec4_t<T> *aux = (const vec4_t<T> *)w.saux;
+    if (w.saux && pot)
+        hipLaunchKernelGGL((k_pair_sub<T, true, true, KIND>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
+                           aux, w.shlj);
+    else if (w.saux)
+        hipLaunchKernelGGL((k_pair_sub<T, true, false, KIND>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt,
+                           k, aux, w.shlj);
+    else if (pot)
+        hipLaunchKernelGGL((k_pair_sub<T, false, true, KIND>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt,
+                           k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+    else
+        hipLaunchKernelGGL((k_pair_sub<T, false, false, KIND>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt,
+                           k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+}
+
 template <typename T, int KIND, int NW>
 static void pair_launch(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot)
 {
@@ -326,6 +519,12 @@ static void pair_launch(hipStream_t s, const DevPlan &p, const Work<T> &w, const
 template <typename T, int NW>
 static void pair_launch_m(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot, int kind)
 {
+    if (NW == 1) {   // sub-group form
+        if (kind == kWolf) pair_launch_sub<T, kWolf>(s, p, w, k, pot);
+        else if (kind == kPolyHigh) pair_launch_sub<T, kPolyHigh>(s, p, w, k, pot);
+        else pair_launch_sub<T, kPoly>(s, p, w, k, pot);
+        return;
+    }
     if (kind == kWolf) pair_launch<T, kWolf, NW>(s, p, w, k, pot);
     else if (kind == kPolyHigh) pair_launch<T, kPolyHigh, NW>(s, p, w, k, pot);
     else pair_launch<T, kPoly, NW>(s, p, w, k, pot);
@@ -367,6 +566,7 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, co
     k.wexp = T(2.0 * m.alpha / std::sqrt(std::acos(-1.0)));
     const int kind = m.method == MSM_METHOD_WOLF ? kWolf : (m.method == MSM_METHOD_MSM && m.g.m == 3 ? kPolyHigh : kPoly);
     switch (m.pair_waves) {
+    case 1: pair_launch_m<T, 1>(s, p, w, k, pot, kind); break;
     case 4: pair_launch_m<T, 4>(s, p, w, k, pot, kind); break;
     case 8: pair_launch_m<T, 8>(s, p, w, k, pot, kind); break;
     case 16: pair_launch_m<T, 16>(s, p, w, k, pot, kind); break;

@@ -79,9 +79,9 @@ def test_autotune_and_tunings_agree():
     x = torch.tensor(w.xyzq(np.float32), device="cuda")
     ref = [t.clone() for t in ctx.energy_forces(x)]
     chosen = ctx.autotune(x, reps=3)
-    assert chosen["pair_waves"] in (4, 8, 16) and chosen["stencil_threads"] in (256, 1024)
+    assert chosen["pair_waves"] in (1, 4, 8, 16) and chosen["stencil_threads"] in (256, 1024)
     assert ctx.tuning() == chosen
-    for pw in (4, 8, 16):
+    for pw in (1, 4, 8, 16):
         for st in (256, 1024):
             ctx.set_tuning(pw, st)
             e, f, p = ctx.energy_forces(x)
@@ -93,3 +93,33 @@ def test_autotune_and_tunings_agree():
             assert e.item() == pytest.approx(ref[0].item(), rel=1e-6)
     with pytest.raises(msmx.MsmError):
         ctx.set_tuning(5, 256)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_concurrent_stages_change_no_bit(precision):
+    """The short-range sum on the context's second stream, beside the grid
+    stages, gives the same bits as every stage in turn, eagerly and in graph
+    replays (each replay checked, with eager work between replays), for
+    every pair kernel form."""
+    import paper_1309_1889_amd as msmx
+    w = water_box(3000, (21, 21, 21), (6.6, 6.6, 6.6), seed=12)
+    dt = np.float32 if precision == "fp32" else np.float64
+    x = torch.tensor(w.xyzq(dt), device="cuda")
+    seq = msmx.MsmContext(w.a, w.h, w.lo, w.hi, precision=precision, max_atoms=w.n)
+    conc = msmx.MsmContext(w.a, w.h, w.lo, w.hi, precision=precision, max_atoms=w.n)
+    seq.set_tuning(concurrent=0)
+    assert conc.tuning()["concurrent"] == 1
+    for pw in (1, 4, 8):
+        seq.set_tuning(pair_waves=pw)
+        conc.set_tuning(pair_waves=pw)
+        ref = seq.energy_forces(x)
+        for graphs in (False, True):
+            conc.set_graphs(graphs)
+            for rep in range(3):
+                got = conc.energy_forces(x)
+                again = seq.energy_forces(x)       # eager work between replays
+                torch.cuda.synchronize()
+                for a, b, c in zip(got, ref, again):
+                    assert torch.equal(a, b) and torch.equal(b, c), (pw, graphs, rep)
+        conc.set_graphs(False)
+    assert seq.status() == 0 and conc.status() == 0
