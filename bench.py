@@ -489,6 +489,11 @@ def bench_large(torch, msmx, steps=100, dt=0.002):
             "kinetic_start": ek0.item(), "kinetic_end": ek1.item()}
 
 
+def log(msg):
+    """Progress of the legs on stderr (the JSON line alone goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -608,19 +613,26 @@ def main():
                 accuracy["fp64_force_rel_rms"] = rel_rms(out64[1].cpu().numpy(), fo)
                 accuracy["fp64_energy_rel"] = abs(out64[0].item() - eo) / abs(eo)
 
+    log(f"single system done: fp32 {ms32:.4f} ms per step")
     batched = uneven = par = large = orders = mts = window = None
     if not args.no_batched:
         batched, uneven = bench_batched(torch, msmx, w32, args.steps, args.warmup, args.slices, value)
+        log("batched done")
     if not args.no_parareal:
         par = bench_parareal(torch, msmx, args.slices)
+        log("parareal done")
     if not args.no_large:
         large = bench_large(torch, msmx)
+        log("large box done")
     if not args.no_orders:
         orders = bench_orders(torch, msmx, w32)
+        log("orders done")
     if not args.no_mts:
         mts = bench_mts(torch, msmx)
+        log("multiple time steps done")
     if not args.no_window:
         window = bench_window(torch, msmx)
+        log("window done")
 
     result.update({
         "value": value,
