@@ -138,11 +138,14 @@ int msm_energy_forces(msm_ctx *ctx, int nsys, const int64_t *offsets_host,
  * stencil_threads add the same terms in different orders, so results of
  * different values agree to rounding, not bitwise (contexts that must agree
  * bitwise, e.g. a parareal pair and its serial reference, should share one
- * configuration); concurrent changes no result bit. Defaults: 4 waves, 1024
+ * configuration); concurrent changes no result bit. Defaults: the cluster form (2), 1024
  * threads, concurrent. */
 typedef struct {
     int pair_waves;        /* short-range sum: 4, 8 or 16 waves share one 64-atom group, one
-                              lane per atom; 1: each wave owns 16 atoms, four lanes per atom */
+                              lane per atom; 1: each wave owns 16 atoms, four lanes per atom;
+                              2: each of 8 waves owns an 8-atom cluster of the group, eight
+                              lanes per atom, and evaluates only the candidates within the
+                              cutoff of the cluster's bounding box */
     int stencil_threads;   /* threads per lattice-cutoff tile: 256 or 1024 */
     int concurrent;        /* 1: the short-range sum runs on a second stream of the context,
                               concurrently with the grid stages (forked after binning,

@@ -107,6 +107,7 @@ template <typename T> void carve(msm_ctx *c, Work<T> &w, char *base, size_t *use
     w.order = (int *)take(sizeof(int) * na);
     w.sxyzq = (vec4_t<T> *)take(vec_bytes<T>() * (na + 64));   // spare tail for the pair prefetch
     w.shrt = (vec4_t<T> *)take(vec_bytes<T>() * na);
+    w.cluster = (int *)take(sizeof(int) * (na + (int64_t)kWave * c->prm.max_systems));
     // partial charges per cell for the two-pass anterpolation, which a plan
     // uses only with more than 2 atoms per cell (so fewer cells than
     // max_atoms / 2); none without grids
@@ -543,7 +544,7 @@ int msm_setup(const msm_params *prm, void *stream, msm_ctx **out)
     c->mc.g = make_smooth(smoothing);
     c->mc.p = basis_degree(*prm);
     c->mc.reach = cutoff ? 0 : reach;
-    c->mc.pair_waves = 4;
+    c->mc.pair_waves = 2;
     c->mc.stencil_threads = 1024;
     c->d2max = (int)std::ceil(ratio * ratio) - 1;      // largest integer below (2a/h)^2
     int rc = geometry(*prm, prm->lo, prm->hi, c->ctx_geom);
@@ -646,7 +647,8 @@ int msm_get_tuning(const msm_ctx *c, msm_tuning *t)
 int msm_set_tuning(msm_ctx *c, const msm_tuning *t)
 {
     if (!c || !t) return MSM_ERR_ARG;
-    if (t->pair_waves != 1 && t->pair_waves != 4 && t->pair_waves != 8 && t->pair_waves != 16) return MSM_ERR_ARG;
+    if (t->pair_waves != 1 && t->pair_waves != 2 && t->pair_waves != 4 && t->pair_waves != 8 && t->pair_waves != 16)
+        return MSM_ERR_ARG;
     if (t->stencil_threads != 256 && t->stencil_threads != 1024) return MSM_ERR_ARG;
     if (t->concurrent != 0 && t->concurrent != 1) return MSM_ERR_ARG;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
@@ -689,7 +691,7 @@ int msm_autotune(msm_ctx *c, int nsys, const int64_t *offsets, const double *dom
     };
     msm_tuning best = start;
     double best_ms = 1e300;
-    for (int pw : {1, 4, 8, 16})
+    for (int pw : {1, 2, 4, 8, 16})
         for (int st : {256, 1024}) {
             if (rc) break;
             c->mc.pair_waves = pw;

@@ -39,6 +39,7 @@ template <typename T> struct Work {
     int *order;          // sorted position -> input atom
     vec4_t<T> *sxyzq;    // atoms in sorted order
     vec4_t<T> *shrt;     // sorted order: (bracket of F^short, u^short)
+    int *cluster;        // per 64-atom pair group: its atoms in k-d cluster order (sorted index, -1 absent)
     T *apart;            // ncells x 64: each cell's partial charges on its 4x4x4 support nodes
     T *qgrid;            // padded charge grids, all levels and systems
     T *ucut;             // lattice-cutoff potentials (top level: u^{l-1})
@@ -74,7 +75,8 @@ struct MethodConst {
     Smooth g;                  // smoothing function gamma of order g.m
     int p;                     // degree of the nodal basis Phi: 3 or 5
     int reach;                 // stencil reach R: largest integer with R < 2a/h
-    int pair_waves;            // waves per 64-atom group in the pair kernel: 4, 8 or 16; 1: 16-atom sub-groups
+    int pair_waves;            // waves per 64-atom group in the pair kernel: 4, 8 or 16; 1: 16-atom sub-groups;
+                               // 2: 8-atom clusters with bounding-box candidate filtering
     int stencil_threads;       // threads per stencil tile: 256 or 1024
 };
 

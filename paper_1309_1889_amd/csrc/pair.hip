@@ -478,6 +478,320 @@ __global__ __launch_bounds__(kSubLanes * kWave) void k_pair_sub(DevPlan p, const
     }
 }
 
+// Cluster form (pair_waves = 2), in two kernels.
+//
+// k_clusters: one wave per 64-atom group splits the group into 8 clusters of
+// 8 atoms by median cuts (k-d order: halve along the longest extent of the
+// group, then of each half, then of each quarter), which gives compact boxes
+// whatever the group's shape, and writes the cluster order.
+//
+// k_pair_cl: one wave per cluster, eight lanes per atom (lane = 8 slot +
+// atom). The wave lays out the cell-row pieces that can reach its cluster's
+// box (each clipped to the chord the cutoff sphere leaves its row) as one
+// stream, 64 pieces at a time, with a table in LDS from stream position to
+// atom; it loads the stream 64 candidates at a time (the next chunk is in
+// flight while the current one is used), keeps those whose distance to the
+// box is below the cutoff (a ballot and a prefix count give each its place in
+// a ring in LDS), and evaluates the ring 8 candidates per step, one per slot,
+// whenever it holds 32. More than half of the evaluated lane pairs are inside
+// the cutoff, against a fifth in the forms above. The waves share nothing.
+// The eight partial sums of an atom are added across its lanes in a fixed
+// order.
+constexpr int kClAtoms = 8;                    // atoms per cluster
+constexpr int kClSlots = kWave / kClAtoms;     // candidates per step: 8
+constexpr int kClUnroll = 4;                   // steps per evaluated block
+constexpr int kClBlock = kClSlots * kClUnroll; // candidates per block: 32
+constexpr int kClRing = 128;                   // ring capacity (a multiple of kClBlock, power of two)
+constexpr int kClMap = 512;                    // stream positions with a table entry
+constexpr int kClWgWaves = 4;                  // waves per workgroup (independent)
+
+template <typename T> __device__ inline T sum_slots(T v)
+{
+    v += __shfl_xor(v, kClAtoms, kWave);
+    v += __shfl_xor(v, 2 * kClAtoms, kWave);
+    v += __shfl_xor(v, 4 * kClAtoms, kWave);
+    return v;
+}
+
+// min / max over aligned segments of n lanes
+template <typename T> __device__ inline T seg_min(T v, int n)
+{
+    for (int off = 1; off < n; off <<= 1) v = fmin(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+template <typename T> __device__ inline T seg_max(T v, int n)
+{
+    for (int off = 1; off < n; off <<= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+    return v;
+}
+
+// One median cut of every aligned segment of n lanes: lane l holds group
+// position pos; each segment is sorted ascending (bitonic network) by the
+// coordinate along its longest extent, ties by position. Positions at or
+// beyond natoms are absent atoms and sort last.
+template <typename T>
+__device__ inline int kd_cut(const vec4_t<T> *grp, int pos, int natoms, int n, int lane)
+{
+    const vec4_t<T> a = grp[pos];
+    const bool real = pos < natoms;
+    const T inf = T(1e30);
+    const T ex = seg_max(real ? a.x : -inf, n) - seg_min(real ? a.x : inf, n);
+    const T ey = seg_max(real ? a.y : -inf, n) - seg_min(real ? a.y : inf, n);
+    const T ez = seg_max(real ? a.z : -inf, n) - seg_min(real ? a.z : inf, n);
+    const int axis = (ex >= ey && ex >= ez) ? 0 : (ey >= ez ? 1 : 2);
+    T key = real ? (axis == 0 ? a.x : (axis == 1 ? a.y : a.z)) : inf;
+    int p = pos;
+    for (int kk = 2; kk <= n; kk <<= 1)
+        for (int j = kk >> 1; j > 0; j >>= 1) {
+            const T ok = __shfl_xor(key, j, kWave);
+            const int op = __shfl_xor(p, j, kWave);
+            const bool up = kk == n || (lane & kk) == 0;   // every segment ascending
+            const bool lower = (lane & j) == 0;
+            const bool less = ok < key || (ok == key && op < p);   // the partner comes first
+            if (less == (lower == up)) {
+                key = ok;
+                p = op;
+            }
+        }
+    return p;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kWave) void k_clusters(DevPlan p, const vec4_t<T> *__restrict__ sx,
+                                                    int *__restrict__ cluster)
+{
+    __shared__ vec4_t<T> grp[kWave];
+    const int64_t g = blockIdx.x;
+    const int s = find_segment(p.group_prefix, p.nsys, g);
+    const SysPlan &P = p.sys[s];
+    const int64_t first = P.atom0 + (g - p.group_prefix[s]) * kWave;
+    const int natoms = (int)min((int64_t)kWave, P.atom0 + P.natoms - first);
+    const int lane = threadIdx.x;
+    grp[lane] = sx[first + min(lane, natoms - 1)];
+    __syncthreads();
+    int pos = lane;
+    for (int n = kWave; n > kClAtoms; n >>= 1) pos = kd_cut<T>(grp, pos, natoms, n, lane);
+    cluster[g * kWave + lane] = pos < natoms ? (int)(first + pos) : -1;
+}
+
+template <typename T, bool MD> struct ClLds {
+    vec4_t<T> ring[kClWgWaves][kClRing];
+    vec4_t<T> raux[MD ? kClWgWaves : 1][MD ? kClRing : 1];
+    int map[kClWgWaves][kClMap];        // stream position -> sorted atom
+    int pre[kClWgWaves][kWave + 1];     // item stream offsets (positions beyond the table)
+    int first[kClWgWaves][kWave];       // first atom of each item
+};
+
+template <typename T, bool MD, bool POT, int KIND>
+__global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const vec4_t<T> *__restrict__ sx,
+                                                                const int *__restrict__ cstart,
+                                                                const int *__restrict__ cluster,
+                                                                vec4_t<T> *__restrict__ out, PairK<T> k,
+                                                                const vec4_t<T> *__restrict__ saux,
+                                                                vec4_t<T> *__restrict__ ljout)
+{
+    __shared__ ClLds<T, MD> L;
+    const int lane = threadIdx.x % kWave;
+    const int wv = uni((int)(threadIdx.x / kWave));
+    // clusters of neighbouring groups share candidates: keep them on one XCD's L2
+    const int64_t c = xcd_remap(blockIdx.x, gridDim.x) * kClWgWaves + wv;   // cluster
+    if (c >= p.ngroups * (kWave / kClAtoms)) return;
+    const int me = lane % kClAtoms, slot = lane / kClAtoms;
+    const int m0 = uni(cluster[c * kClAtoms]);
+    if (m0 < 0) return;   // a cluster of absent atoms (the last group of a system)
+    const int64_t g = c / (kWave / kClAtoms);
+    const int s = find_segment(p.group_prefix, p.nsys, g);
+    const SysPlan &P = p.sys[s];
+    const int mi = cluster[c * kClAtoms + me];
+    const bool valid = mi >= 0;
+    const int64_t i = valid ? mi : m0;
+    const vec4_t<T> ai = sx[i];
+    vec4_t<T> xi;
+    if (MD) xi = saux[i];
+
+    const T bminx = uni(seg_min(ai.x, kClAtoms)), bmaxx = uni(seg_max(ai.x, kClAtoms));
+    const T bminy = uni(seg_min(ai.y, kClAtoms)), bmaxy = uni(seg_max(ai.y, kClAtoms));
+    const T bminz = uni(seg_min(ai.z, kClAtoms)), bmaxz = uni(seg_max(ai.z, kClAtoms));
+    const T lox = T(P.lo[0]), loy = T(P.lo[1]), loz = T(P.lo[2]);
+    const T inv_h = T(P.inv_h), h = T(1.0 / P.inv_h);
+    const int ncx = P.nc[0], ncy = P.nc[1], ncz = P.nc[2];
+    const T reach = k.reach, reach2 = k.reach * k.reach;
+    const int cy0 = clampi((int)floor((bminy - loy - reach) * inv_h), 0, ncy - 1);
+    const int cy1 = clampi((int)floor((bmaxy - loy + reach) * inv_h), 0, ncy - 1);
+    const int cz0 = clampi((int)floor((bminz - loz - reach) * inv_h), 0, ncz - 1);
+    const int cz1 = clampi((int)floor((bmaxz - loz + reach) * inv_h), 0, ncz - 1);
+    const int bx0 = clampi((int)floor((bminx - lox - reach) * inv_h), 0, ncx - 1) / kBrick;
+    const int bx1 = clampi((int)floor((bmaxx - lox + reach) * inv_h), 0, ncx - 1) / kBrick;
+    const int nbx = bx1 - bx0 + 1, ny = cy1 - cy0 + 1;
+    const int nitems = nbx * ny * (cz1 - cz0 + 1);
+
+    if (KIND == kPolyHigh)
+        asm volatile("" : "+v"(k.c2), "+v"(k.d1));
+    else if (KIND == kPoly)
+        asm volatile("" : "+v"(k.c1), "+v"(k.d0));
+    T fx = 0, fy = 0, fz = 0, u = 0;
+    T lx = 0, ly = 0, lz = 0, le = 0;
+    vec4_t<T> *ring = L.ring[wv];
+    vec4_t<T> *raux = L.raux[MD ? wv : 0];
+    int *map = L.map[wv], *pre = L.pre[wv], *fst = L.first[wv];
+    int head = 0, tail = 0;   // ring positions (uniform; taken modulo the capacity)
+    auto eval_block = [&]() {
+        // a block starts at a multiple of its size, so it does not wrap
+        const int e0 = (head & (kClRing - 1)) + slot;
+        vec4_t<T> aj[kClUnroll], xj[kClUnroll];
+#pragma unroll
+        for (int v = 0; v < kClUnroll; ++v) {
+            aj[v] = ring[e0 + kClSlots * v];
+            xj[v] = MD ? raux[MD ? e0 + kClSlots * v : 0] : aj[v];
+        }
+#pragma unroll
+        for (int v = 0; v < kClUnroll; ++v)
+            pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le);
+        head += kClBlock;
+    };
+    for (int ib = 0; ib < nitems; ib += kWave) {
+        const int q = ib + lane;   // this lane's item
+        int len = 0, jb = 0;
+        if (q < nitems) {
+            const int bx = bx0 + q % nbx, row = q / nbx;
+            const int cy = cy0 + row % ny, cz = cz0 + row / ny;
+            const T z0 = loz + T(cz) * h, y0 = loy + T(cy) * h;
+            const T dz = fmax(T(0), fmax(z0 - bmaxz, bminz - (z0 + h)));
+            const T dy = fmax(T(0), fmax(y0 - bmaxy, bminy - (y0 + h)));
+            const T rem = reach2 - dy * dy - dz * dz;
+            if (rem > T(0)) {
+                const T wdt = sqrt(rem);
+                const int cx0 = clampi((int)floor((bminx - lox - wdt) * inv_h), 0, ncx - 1);
+                const int cx1 = clampi((int)floor((bmaxx - lox + wdt) * inv_h), 0, ncx - 1);
+                const int ca = max(cx0, bx * kBrick), cb = min(cx1, bx * kBrick + kBrick - 1);
+                if (ca <= cb) {
+                    const int64_t r0 = P.cell0 + cell_rank(P, ca, cy, cz);
+                    jb = cstart[r0];
+                    len = cstart[r0 + (cb - ca) + 1] - jb;
+                }
+            }
+        }
+        int incl = len;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int v = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += v;
+        }
+        const int start = incl - len;
+        pre[lane] = start;
+        fst[lane] = jb;
+        const int total = uni(__shfl(incl, kWave - 1, kWave));
+        if (lane == 0) pre[kWave] = total;
+        // table of the first kClMap stream positions
+        int maxlen = len;
+        for (int off = 32; off > 0; off >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, off, kWave));
+        maxlen = uni(maxlen);
+        for (int t = 0; t < maxlen; ++t)
+            if (t < len && start + t < kClMap) map[start + t] = jb + t;
+        __builtin_amdgcn_wave_barrier();
+        auto atom_at = [&](int pos) -> int {
+            if (pos < kClMap) return map[pos];
+            int lo_ = 0, hi_ = kWave;   // pre[lo_] <= pos < pre[hi_]
+            while (hi_ - lo_ > 1) {
+                const int mid = (lo_ + hi_) >> 1;
+                if (pre[mid] <= pos) lo_ = mid; else hi_ = mid;
+            }
+            return fst[lo_] + (pos - pre[lo_]);
+        };
+        vec4_t<T> pa, px;
+        if (lane < total) {
+            const int j = atom_at(lane);
+            pa = sx[j];
+            if (MD) px = saux[j];
+        }
+        for (int c0 = 0; c0 < total; c0 += kWave) {
+            const bool have = c0 + lane < total;
+            const vec4_t<T> ca = pa;
+            vec4_t<T> cx;
+            if (MD) cx = px;
+            const int nxt = c0 + kWave + lane;   // the next chunk
+            if (nxt < total) {
+                const int j = atom_at(nxt);
+                pa = sx[j];
+                if (MD) px = saux[j];
+            }
+            const T ddx = fmax(T(0), fmax(bminx - ca.x, ca.x - bmaxx));
+            const T ddy = fmax(T(0), fmax(bminy - ca.y, ca.y - bmaxy));
+            const T ddz = fmax(T(0), fmax(bminz - ca.z, ca.z - bmaxz));
+            const bool keep = have && ddx * ddx + ddy * ddy + ddz * ddz < reach2;
+            const uint64_t m = __ballot(keep);
+            if (keep) {
+                const int e = (tail + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u))) &
+                              (kClRing - 1);
+                ring[e] = ca;
+                if (MD) raux[MD ? e : 0] = cx;
+            }
+            tail += __popcll(m);
+            __builtin_amdgcn_wave_barrier();
+            while (tail - head >= kClBlock) eval_block();
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if (tail > head) {   // the last partial block, padded with a far-away atom
+        if (lane < head + kClBlock - tail) {
+            vec4_t<T> far;
+            far.x = far.y = far.z = T(1e18);
+            far.w = T(0);
+            ring[(tail + lane) & (kClRing - 1)] = far;
+            if (MD) raux[MD ? (tail + lane) & (kClRing - 1) : 0] = far;
+        }
+        __builtin_amdgcn_wave_barrier();
+        eval_block();
+    }
+    fx = sum_slots(fx);
+    fy = sum_slots(fy);
+    fz = sum_slots(fz);
+    if (POT) u = sum_slots(u);
+    if (MD) {
+        lx = sum_slots(lx);
+        ly = sum_slots(ly);
+        lz = sum_slots(lz);
+        if (POT) le = sum_slots(le);
+    }
+    if (slot == 0 && valid) {
+        vec4_t<T> o;
+        o.x = fx;
+        o.y = fy;
+        o.z = fz;
+        o.w = u;
+        out[i] = o;
+        if (MD) {
+            vec4_t<T> ol;
+            ol.x = lx;
+            ol.y = ly;
+            ol.z = lz;
+            ol.w = le;
+            ljout[i] = ol;
+        }
+    }
+}
+
+template <typename T, int KIND>
+static void pair_launch_cl(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot)
+{
+    hipLaunchKernelGGL((k_clusters<T>), dim3((unsigned)p.ngroups), dim3(kWave), 0, s, p, w.sxyzq, w.cluster);
+    const int64_t nclusters = p.ngroups * (kWave / kClAtoms);
+    const dim3 grid((unsigned)((nclusters + kClWgWaves - 1) / kClWgWaves)), block(kClWgWaves * kWave);
+    const vec4_t<T> *aux = (const vec4_t<T> *)w.saux;
+    if (w.saux && pot)
+        hipLaunchKernelGGL((k_pair_cl<T, true, true, KIND>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.cluster,
+                           w.shrt, k, aux, w.shlj);
+    else if (w.saux)
+        hipLaunchKernelGGL((k_pair_cl<T, true, false, KIND>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
+                           w.cluster, w.shrt, k, aux, w.shlj);
+    else if (pot)
+        hipLaunchKernelGGL((k_pair_cl<T, false, true, KIND>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
+                           w.cluster, w.shrt, k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+    else
+        hipLaunchKernelGGL((k_pair_cl<T, false, false, KIND>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
+                           w.cluster, w.shrt, k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+}
+
 template <typename T, int KIND>
 static void pair_launch_sub(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot)
 {
@@ -519,6 +833,12 @@ static void pair_launch(hipStream_t s, const DevPlan &p, const Work<T> &w, const
 template <typename T, int NW>
 static void pair_launch_m(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot, int kind)
 {
+    if (NW == 2) {   // cluster form
+        if (kind == kWolf) pair_launch_cl<T, kWolf>(s, p, w, k, pot);
+        else if (kind == kPolyHigh) pair_launch_cl<T, kPolyHigh>(s, p, w, k, pot);
+        else pair_launch_cl<T, kPoly>(s, p, w, k, pot);
+        return;
+    }
     if (NW == 1) {   // sub-group form
         if (kind == kWolf) pair_launch_sub<T, kWolf>(s, p, w, k, pot);
         else if (kind == kPolyHigh) pair_launch_sub<T, kPolyHigh>(s, p, w, k, pot);
@@ -567,6 +887,7 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, co
     const int kind = m.method == MSM_METHOD_WOLF ? kWolf : (m.method == MSM_METHOD_MSM && m.g.m == 3 ? kPolyHigh : kPoly);
     switch (m.pair_waves) {
     case 1: pair_launch_m<T, 1>(s, p, w, k, pot, kind); break;
+    case 2: pair_launch_m<T, 2>(s, p, w, k, pot, kind); break;
     case 4: pair_launch_m<T, 4>(s, p, w, k, pot, kind); break;
     case 8: pair_launch_m<T, 8>(s, p, w, k, pot, kind); break;
     case 16: pair_launch_m<T, 16>(s, p, w, k, pot, kind); break;
