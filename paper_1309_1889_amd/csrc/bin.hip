@@ -1,11 +1,16 @@
 // Binning of atoms into cells of edge h (the cells that the short-range pair
 // search and the gather forms of anterpolation and interpolation walk), as a
-// counting sort: histogram, exclusive scan, scatter. Cells are ranked
-// brick-major (4x4x4 cells per brick) so that 64 consecutive sorted atoms form
-// a compact group, while the cells of one brick row along x stay contiguous.
+// counting sort: histogram, exclusive scan (block sums, then each block adds
+// the sums before it), scatter. The histogram lives in a counts array that is
+// zero between evaluations (the scan clears it), so no launch clears it.
+// Cells are ranked brick-major (4x4x4 cells per brick) so that 64 consecutive
+// sorted atoms form a compact group, while the cells of one brick row along x
+// stay contiguous.
 // A final per-cell sort by input index makes the order independent of the
 // arrival order of the histogram atomics, so every evaluation is bitwise
 // reproducible.
+#include <algorithm>
+
 #include "launch.h"
 
 namespace msmx {
@@ -32,16 +37,16 @@ template <typename T>
 __global__ void k_bin_count(DevPlan p, const vec4_t<T> *__restrict__ xyzq, int *__restrict__ cell_of,
                             int *__restrict__ slot_of, int *__restrict__ counts, int *__restrict__ status)
 {
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= p.natoms) return;
-    int s = find_segment(p.atom_prefix, p.nsys, i);
+    const int s = find_segment(p.atom_prefix, p.nsys, i);
     const SysPlan &P = p.sys[s];
-    vec4_t<T> a = xyzq[i];
-    T pos[3] = {a.x, a.y, a.z};
+    const vec4_t<T> a = xyzq[i];
+    const T pos[3] = {a.x, a.y, a.z};
     int c[3];
     int bad = 0;
     for (int d = 0; d < 3; d++) {
-        T t = (pos[d] - T(P.lo[d])) * T(P.inv_h);
+        const T t = (pos[d] - T(P.lo[d])) * T(P.inv_h);
         // an atom may sit on the boundary; a rounding overshoot of a fraction
         // of a cell is tolerated and binned into the edge cell
         if (!(t >= T(-1e-4) && t <= T(P.tmax[d] + 1e-4))) bad |= isfinite(t) ? kStatusDomain : kStatusNonFinite;
@@ -52,7 +57,7 @@ __global__ void k_bin_count(DevPlan p, const vec4_t<T> *__restrict__ xyzq, int *
     }
     if (!isfinite(a.w)) bad |= kStatusNonFinite;
     if (bad) atomicOr(status, bad);
-    int cell = (int)(P.cell0 + cell_rank(P, c[0], c[1], c[2]));
+    const int cell = (int)(P.cell0 + cell_rank(P, c[0], c[1], c[2]));
     cell_of[i] = cell;
     slot_of[i] = atomicAdd(&counts[cell], 1);
 }
@@ -95,22 +100,10 @@ __device__ inline int block_exclusive_scan(int v, int *sh, int &total)
     return incl - v;
 }
 
-__global__ __launch_bounds__(1024) void k_scan_blocksums(int *__restrict__ bsum, int nb)
-{
-    __shared__ int sh[1024];
-    int carry = 0;
-    for (int base = 0; base < nb; base += 1024) {
-        int idx = base + threadIdx.x;
-        int v = idx < nb ? bsum[idx] : 0;
-        int total;
-        int ex = block_exclusive_scan(v, sh, total);
-        if (idx < nb) bsum[idx] = ex + carry;
-        carry += total;
-    }
-}
-
-__global__ __launch_bounds__(kScanThreads) void k_scan_apply(int *__restrict__ data, int64_t n,
-                                                              const int *__restrict__ bsum)
+// start[idx] = exclusive prefix of counts for idx < n (the caller passes n =
+// cells + 1 with a zero count at the end), clearing counts
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(int *__restrict__ counts, int *__restrict__ start,
+                                                              int64_t n, const int *__restrict__ bsum)
 {
     __shared__ int sh[kScanThreads];
     int64_t base = blockIdx.x * (int64_t)kScanBlock + (int64_t)threadIdx.x * kScanItems;
@@ -118,14 +111,28 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int *__restrict__ d
     int acc = 0;
     for (int j = 0; j < kScanItems; j++) {
         int64_t idx = base + j;
-        v[j] = idx < n ? data[idx] : 0;
+        v[j] = idx < n ? counts[idx] : 0;
         acc += v[j];
     }
+    // this block's offset: the sum of the earlier blocks' sums
+    int before = 0;
+    for (int b = threadIdx.x; b < (int)blockIdx.x; b += kScanThreads) before += bsum[b];
+    __shared__ int red[kScanThreads];
+    red[threadIdx.x] = before;
+    __syncthreads();
+    for (int off = kScanThreads / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+        __syncthreads();
+    }
+    before = red[0];
     int total;
-    int ex = block_exclusive_scan(acc, sh, total) + bsum[blockIdx.x];
+    int ex = block_exclusive_scan(acc, sh, total) + before;
     for (int j = 0; j < kScanItems; j++) {
         int64_t idx = base + j;
-        if (idx < n) data[idx] = ex;
+        if (idx < n) {
+            start[idx] = ex;
+            counts[idx] = 0;
+        }
         ex += v[j];
     }
 }
@@ -249,27 +256,25 @@ template <typename T> hipError_t fill_t(hipStream_t s, T *p, int64_t n, T v)
 template hipError_t fill_t<float>(hipStream_t, float *, int64_t, float);
 template hipError_t fill_t<double>(hipStream_t, double *, int64_t, double);
 
-// Exclusive scan in place over n ints (n + 1 entries are rewritten when the
-// caller appends a zero count: entry n then holds the total).
-int scan_cells(hipStream_t s, int *data, int64_t n, int *block_sums)
+// Exclusive scan of n counts into start, clearing the counts (the caller
+// passes n = cells + 1 with a zero count at the end: start[cells] then holds
+// the total).
+int scan_cells(hipStream_t s, int *counts, int *start, int64_t n, int *block_sums)
 {
     int64_t nb = (n + kScanBlock - 1) / kScanBlock;
     if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, block_sums);
-    hipLaunchKernelGGL(k_scan_blocksums, dim3(1), dim3(1024), 0, s, block_sums, (int)nb);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, data, n, block_sums);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n, block_sums);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, start, n, block_sums);
     return (int)hipGetLastError();
 }
 
 template <typename T>
 hipError_t Launch<T>::bin(hipStream_t s, const DevPlan &p, const Work<T> &w, const vec4_t<T> *xyzq)
 {
-    hipError_t e = fill_i32(s, w.cell_start, p.ncells + 1, 0);
-    if (e != hipSuccess) return e;
     if (p.natoms > 0)
         hipLaunchKernelGGL(k_bin_count<T>, dim3(nblocks(p.natoms, 256)), dim3(256), 0, s, p, xyzq, w.cell_of,
-                           w.slot_of, w.cell_start, w.status);
-    scan_cells(s, w.cell_start, p.ncells + 1, w.scan_blocks);
+                           w.slot_of, w.counts, w.status);
+    scan_cells(s, w.counts, w.cell_start, p.ncells + 1, w.scan_blocks);
     if (p.natoms > 0) {
         hipLaunchKernelGGL(k_scatter, dim3(nblocks(p.natoms, 256)), dim3(256), 0, s, p.natoms, w.cell_of,
                            w.slot_of, w.cell_start, w.order);

@@ -103,6 +103,7 @@ template <typename T> void carve(msm_ctx *c, Work<T> &w, char *base, size_t *use
     w.cell_of = (int *)take(sizeof(int) * na);
     w.slot_of = (int *)take(sizeof(int) * na);
     w.cell_start = (int *)take(sizeof(int) * (c->cap_cells + 1));
+    w.counts = (int *)take(sizeof(int) * (c->cap_cells + 1));
     w.scan_blocks = (int *)take(sizeof(int) * ((c->cap_cells + 1) / 4096 + 2));
     w.order = (int *)take(sizeof(int) * na);
     w.sxyzq = (vec4_t<T> *)take(vec_bytes<T>() * (na + 64));   // spare tail for the pair prefetch
@@ -354,10 +355,9 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     mark(MSM_STAGE_CUTOFF);
     if (do_long) {
         StencilTables<T> tb{c->wcols, (const T *)c->weights, c->ncols, c->mc.reach, c->mc.stencil_threads};
-        if ((e = L::stencil(s, p, w, tb)) != hipSuccess) return MSM_ERR_HIP;
+        if ((e = L::stencil(s, p, w, tb, c->mc)) != hipSuccess) return MSM_ERR_HIP;
     }
-    mark(MSM_STAGE_TOP);
-    if (do_long && (e = L::top_level(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
+    mark(MSM_STAGE_TOP);   // the top level runs in the lattice-cutoff launch
     mark(MSM_STAGE_PROLONG);
     for (int k = p.maxlev - 2; do_long && k >= 0; k--)
         if ((e = L::prolong_level(s, p, w, k, c->mc)) != hipSuccess) return MSM_ERR_HIP;

@@ -35,6 +35,7 @@ template <typename T> struct Work {
     int *cell_of;        // per input atom: brick-major cell (batch-global)
     int *slot_of;        // per input atom: arrival slot within its cell
     int *cell_start;     // ncells + 1: exclusive scan of cell counts
+    int *counts;         // ncells + 1: cell histogram, zero between evaluations
     int *scan_blocks;    // block sums of the scan
     int *order;          // sorted position -> input atom
     vec4_t<T> *sxyzq;    // atoms in sorted order
@@ -83,7 +84,7 @@ struct MethodConst {
 int anterp_tiles(int dx, int dy, int dz);
 bool anterp_two_pass(const DevPlan &p);   // anterpolation by cell partials (crowded cells) rather than tiles
 
-int scan_cells(hipStream_t s, int *counts_to_start, int64_t n, int *block_sums);
+int scan_cells(hipStream_t s, int *counts, int *start, int64_t n, int *block_sums);
 
 template <typename T> struct Launch {
     static hipError_t bin(hipStream_t s, const DevPlan &p, const Work<T> &w, const vec4_t<T> *xyzq);
@@ -91,8 +92,9 @@ template <typename T> struct Launch {
     static hipError_t pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m, bool pot);
     static hipError_t anterp(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m);
     static hipError_t restrict_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k, const MethodConst &m);
-    static hipError_t stencil(hipStream_t s, const DevPlan &p, const Work<T> &w, const StencilTables<T> &tb);
-    static hipError_t top_level(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m);
+    // the lattice cutoff of every level below the top and the top level
+    static hipError_t stencil(hipStream_t s, const DevPlan &p, const Work<T> &w, const StencilTables<T> &tb,
+                              const MethodConst &m);
     static hipError_t prolong_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k, const MethodConst &m);
     // part: 0 everything, 1 the short-range pairs only, 2 the grid part only
     static hipError_t interp(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m,

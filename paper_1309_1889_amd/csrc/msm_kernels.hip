@@ -35,7 +35,7 @@ namespace {
 //     (2S)^3 cells whose support covers it, in a fixed order.
 // ---------------------------------------------------------------------------
 constexpr int kAntX = 8, kAntY = 8, kAntZ = 4;
-constexpr int kAntAtoms = 3072;
+constexpr int kAntAtoms = 2048;
 
 template <int S> struct AntTile {
     static constexpr int CX = kAntX + 2 * S - 1, CY = kAntY + 2 * S - 1, CZ = kAntZ + 2 * S - 1;   // cells reached
@@ -75,7 +75,9 @@ __global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__re
     constexpr int S = B::S;
     using A = AntTile<S>;
     __shared__ vec4_t<T> atoms[kAntAtoms];
-    __shared__ int start[A::Cells + 1];
+    __shared__ int start[A::Cells + 1];   // staged position of each region cell's first atom
+    __shared__ int gfirst[A::Cells];      // its sorted index
+    __shared__ int wsum[4];
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int s = find_segment(p.ant_prefix, p.nsys, blk);
     const SysPlan &P = p.sys[s];
@@ -86,60 +88,66 @@ __global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__re
     const int x0 = (int)(t % ntx) * kAntX + P.gorg[0][0];
     const int y0 = (int)((t / ntx) % nty) * kAntY + P.gorg[0][1];
     const int z0 = (int)(t / ((int64_t)ntx * nty)) * kAntZ + P.gorg[0][2];
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
 
-    // cell counts of the reachable region (cells x0-S .. x0+kAntX+S-2, ...), 0 outside the grid
-    for (int c = tid; c < A::Cells; c += 256) {
-        const int ex = c % A::CX, row = c / A::CX;
-        const int cx = x0 - S + ex, cy = y0 - S + row % A::CY, cz = z0 - S + row / A::CY;
-        int n = 0;
-        if (cx >= 0 && cy >= 0 && cz >= 0 && cx < P.nc[0] && cy < P.nc[1] && cz < P.nc[2]) {
-            const int64_t r = P.cell0 + cell_rank(P, cx, cy, cz);
-            n = cstart[r + 1] - cstart[r];
+    // cells of the reachable region (cells x0-S .. x0+kAntX+S-2, ...), 0 atoms
+    // outside the grid: each thread counts a contiguous run of cells, a
+    // workgroup scan places the runs
+    constexpr int per = (A::Cells + 255) / 256;
+    int cnt[per];
+    int sum = 0;
+#pragma unroll
+    for (int j = 0; j < per; ++j) {
+        const int c = tid * per + j;
+        int n = 0, f = 0;
+        if (c < A::Cells) {
+            const int ex = c % A::CX, row = c / A::CX;
+            const int cx = x0 - S + ex, cy = y0 - S + row % A::CY, cz = z0 - S + row / A::CY;
+            if (cx >= 0 && cy >= 0 && cz >= 0 && cx < P.nc[0] && cy < P.nc[1] && cz < P.nc[2]) {
+                const int64_t r = P.cell0 + cell_rank(P, cx, cy, cz);
+                f = cstart[r];
+                n = cstart[r + 1] - f;
+            }
+            gfirst[c] = f;
         }
-        start[c + 1] = n;
+        cnt[j] = n;
+        sum += n;
     }
-    if (tid == 0) start[0] = 0;
+    int incl = sum;
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int v = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += v;
+    }
+    if (lane == kWave - 1) wsum[wv] = incl;
     __syncthreads();
-    // inclusive scan of the counts: each lane of the first wave sums a
-    // contiguous chunk, the wave scans the chunk sums
-    if (tid < kWave) {
-        constexpr int chunk = (A::Cells + kWave - 1) / kWave;
-        const int b0 = 1 + tid * chunk, b1 = min(b0 + chunk, A::Cells + 1);
-        int sum = 0;
-        for (int i = b0; i < b1; ++i) sum += start[i];
-        int incl = sum;
-        for (int off = 1; off < kWave; off <<= 1) {
-            const int v = __shfl_up(incl, off, kWave);
-            if (tid >= off) incl += v;
-        }
-        int run = incl - sum;
-        for (int i = b0; i < b1; ++i) {
-            run += start[i];
-            start[i] = run;
-        }
+    int run = incl - sum;
+    for (int w = 0; w < wv; ++w) run += wsum[w];
+#pragma unroll
+    for (int j = 0; j < per; ++j) {
+        const int c = tid * per + j;
+        if (c < A::Cells) start[c] = run;
+        run += cnt[j];
     }
+    if (tid == 255) start[A::Cells] = run;
     __syncthreads();
     const int total = start[A::Cells];
     const bool staged = total <= kAntAtoms;
     if (staged) {
+        // one staged atom per thread and step: its cell by binary search
         const T lox = T(P.lo[0]), loy = T(P.lo[1]), loz = T(P.lo[2]), inv_h = T(P.inv_h);
-        for (int c = tid; c < A::Cells; c += 256) {
-            const int n = start[c + 1] - start[c];
-            if (n == 0) continue;
-            const int ex = c % A::CX, row = c / A::CX;
-            const int cx = x0 - S + ex, cy = y0 - S + row % A::CY, cz = z0 - S + row / A::CY;
-            const int64_t r = P.cell0 + cell_rank(P, cx, cy, cz);
-            const int jb = cstart[r];
-            for (int k = 0; k < n; ++k) {
-                const vec4_t<T> a = sx[jb + k];
-                vec4_t<T> o;
-                o.x = (a.x - lox) * inv_h;
-                o.y = (a.y - loy) * inv_h;
-                o.z = (a.z - loz) * inv_h;
-                o.w = a.w;
-                atoms[start[c] + k] = o;
+        for (int pos = tid; pos < total; pos += 256) {
+            int lo_ = 0, hi_ = A::Cells;   // start[lo_] <= pos < start[hi_]
+            while (hi_ - lo_ > 1) {
+                const int mid = (lo_ + hi_) >> 1;
+                if (start[mid] <= pos) lo_ = mid; else hi_ = mid;
             }
+            const vec4_t<T> a = sx[gfirst[lo_] + (pos - start[lo_])];
+            vec4_t<T> o;
+            o.x = (a.x - lox) * inv_h;
+            o.y = (a.y - loy) * inv_h;
+            o.z = (a.z - loz) * inv_h;
+            o.w = a.w;
+            atoms[pos] = o;
         }
     }
     __syncthreads();
@@ -246,7 +254,8 @@ __device__ inline void restrict_node(const SysPlan &P, T *__restrict__ qgrid, in
     using B = Basis<PD>;
     constexpr int S = B::S, NT = 2 * S + 1;   // taps per axis
     const int cdx = P.gdim[k + 1][0], cdy = P.gdim[k + 1][1];
-    const int rx = (int)(loc % cdx), ry = (int)((loc / cdx) % cdy), rz = (int)(loc / ((int64_t)cdx * cdy));
+    const int l = (int)loc;   // nodes of one grid fit in int
+    const int rx = l % cdx, ry = (l / cdx) % cdy, rz = l / (cdx * cdy);
     // fine-grid relative index of the coincident node 2 mu
     const int fx = 2 * (rx + P.gorg[k + 1][0]) - P.gorg[k][0];
     const int fy = 2 * (ry + P.gorg[k + 1][1]) - P.gorg[k][1];
@@ -294,6 +303,97 @@ __global__ __launch_bounds__(256) void k_restrict(DevPlan p, T *__restrict__ qgr
 }
 
 // ---------------------------------------------------------------------------
+// Top level (Section 3): u^{l-1}_mu = sum_nu g^{l-1}(r_mu, r_nu) q^{l-1}_nu over
+// all node pairs, g^{l-1}(r) = gamma(r / (2^{l-1} a)) / (2^{l-1} a). The grid
+// is at most a few hundred nodes; 8 threads share each output node (the
+// source z-planes dealt round-robin). The blocks run in the lattice-cutoff
+// launch, in LDS the tiles do not use at that point, or alone when a batch
+// has no lattice-cutoff tiles.
+// ---------------------------------------------------------------------------
+constexpr int kTopTable = 4096;   // weights by squared index distance held in LDS (at most)
+constexpr int kTopStage = 4096;   // top-grid charges held in LDS (at most)
+constexpr int kTopNodes = 32;     // output nodes per block
+constexpr int kTopShares = 8;     // threads per output node
+constexpr int kTopThreads = kTopNodes * kTopShares;
+
+// top block blk on threads 0..255; lds holds at least kTopThreads + 2 elements
+template <typename T>
+__device__ inline void top_block(const DevPlan &p, int64_t blk, const T *__restrict__ qgrid, T *__restrict__ ucut,
+                                 T *__restrict__ ugrid, double h, double a, int ntab, const Smooth &g, T *lds,
+                                 int ldsn)
+{
+    // weights by squared integer distance d2: gamma(h sqrt(d2) / a) / a; the
+    // level's factor 2^-(l-1) is applied to the sum
+    T *part = lds;                                   // [kTopShares][kTopNodes]
+    const int avail = (ldsn - kTopThreads) / 2;
+    const int tabcap = min(kTopTable, avail), qcap = min(kTopStage, avail);
+    T *tab = lds + kTopThreads;
+    T *qs = tab + tabcap;
+    const int s = find_segment(p.top_prefix, p.nsys, blk);
+    const SysPlan &P = p.sys[s];
+    const int k = P.nlev - 1;
+    const int dx = P.gdim[k][0], dy = P.gdim[k][1], dz = P.gdim[k][2];
+    const int M = dx * dy * dz;
+    const int PX = padded_x(dx), PY = padded_x(dy);
+    const T *q = qgrid + P.qoff[k];
+    const int tid = threadIdx.x;
+    const bool on = tid < kTopThreads;
+    for (int d2 = tid; on && d2 < ntab && d2 < tabcap; d2 += kTopThreads)
+        tab[d2] = gamma_s(T(h / a) * sqrt(T(d2)), g) * T(1.0 / a);
+    for (int e = tid; on && e < M && e < qcap; e += kTopThreads) {
+        const int x = e % dx, y = (e / dx) % dy, z = e / (dx * dy);
+        qs[e] = q[((int64_t)(z + kGridPad) * PY + (y + kGridPad)) * PX + (x + kGridPad)];
+    }
+    __syncthreads();
+    const int lane = tid % kTopNodes, share = tid / kTopNodes;
+    const int node = (int)(blk - p.top_prefix[s]) * kTopNodes + lane;
+    T acc = 0;
+    if (on && node < M) {
+        const int x = node % dx, y = (node / dx) % dy, z = node / (dx * dy);
+        for (int nz = share; nz < dz; nz += kTopShares)
+            for (int ny = 0; ny < dy; ++ny) {
+                const int eyz = (nz - z) * (nz - z) + (ny - y) * (ny - y);
+                const int e0 = (nz * dy + ny) * dx;
+                for (int nx = 0; nx < dx; ++nx) {
+                    const int d2 = eyz + (nx - x) * (nx - x);
+                    const T w = d2 < tabcap ? tab[d2] : gamma_s(T(h / a) * sqrt(T(d2)), g) * T(1.0 / a);
+                    const int e = e0 + nx;
+                    const T qv = e < qcap
+                                     ? qs[e]
+                                     : q[((int64_t)(nz + kGridPad) * PY + (ny + kGridPad)) * PX + (nx + kGridPad)];
+                    acc += w * qv;
+                }
+            }
+    }
+    if (on) part[share * kTopNodes + lane] = acc;
+    __syncthreads();
+    if (on && share == 0 && node < M) {
+        T sum = part[lane];
+        for (int sh = 1; sh < kTopShares; ++sh) sum += part[sh * kTopNodes + lane];   // fixed order
+        sum *= T(ldexp(1.0, -k));
+        const int64_t o = P.uoff[k] + node;
+        ucut[o] = sum;
+        ugrid[o] = sum;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kTopThreads) void k_top(DevPlan p, const T *__restrict__ qgrid, T *__restrict__ ucut,
+                                                     T *__restrict__ ugrid, double h, double a, int ntab, Smooth g)
+{
+    __shared__ T lds[kTopThreads + kTopTable + kTopStage];
+    top_block<T>(p, blockIdx.x, qgrid, ucut, ugrid, h, a, ntab, g, lds, kTopThreads + kTopTable + kTopStage);
+}
+
+// Top-level parameters for the lattice-cutoff launch.
+struct TopArgs {
+    double h, a;
+    int ntab;
+    int64_t nblocks;     // top blocks run first in the launch (0: none)
+    Smooth g;
+};
+
+// ---------------------------------------------------------------------------
 // Lattice cutoff on level k < l-1 (Section 3): u^{k,cutoff}_mu =
 // sum_nu g^k(r^k_mu, r^k_nu) q^k_nu. On level k the node distance is 2^k h |o|,
 // and g^k(2^k h |o|) = 2^{-k} g^0(h |o|), so one set of weights g^0(h |o|),
@@ -321,13 +421,19 @@ template <typename T, int R, int NT> struct StencilGeom {
 
 template <typename T, int R, int NT>
 __global__ __launch_bounds__(NT) void k_stencil(DevPlan p, const T *__restrict__ qgrid, T *__restrict__ ucut,
-                                                 const int2 *__restrict__ qcols, const T *__restrict__ qw, int ncols)
+                                                 const int2 *__restrict__ qcols, const T *__restrict__ qw, int ncols,
+                                                 T *__restrict__ ugrid, TopArgs top)
 {
     using G = StencilGeom<T, R, NT>;
     constexpr int D = 2 * R + 1;
     constexpr int L = G::TZ + 2 * R;
-    __shared__ T tile[G::LDS];
-    const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+    constexpr int NL = G::LDS > kTopThreads + 2 ? G::LDS : kTopThreads + 2;
+    __shared__ T tile[NL];
+    if ((int64_t)blockIdx.x < top.nblocks) {
+        top_block<T>(p, blockIdx.x, qgrid, ucut, ugrid, top.h, top.a, top.ntab, top.g, tile, NL);
+        return;
+    }
+    const int64_t blk = xcd_remap(blockIdx.x - top.nblocks, gridDim.x - top.nblocks);
     const int seg = find_segment(p.tile_prefix, p.ntile_seg, blk);
     const int k = seg / p.nsys, s = seg % p.nsys;
     const SysPlan &P = p.sys[s];
@@ -395,73 +501,6 @@ __global__ __launch_bounds__(NT) void k_stencil(DevPlan p, const T *__restrict__
 }
 
 // ---------------------------------------------------------------------------
-// Top level (Section 3): u^{l-1}_mu = sum_nu g^{l-1}(r_mu, r_nu) q^{l-1}_nu over
-// all node pairs, g^{l-1}(r) = gamma(r / (2^{l-1} a)) / (2^{l-1} a). The grid
-// is at most a few hundred nodes; each thread sums over all of them.
-// ---------------------------------------------------------------------------
-constexpr int kTopTable = 4096;   // weights by squared index distance held in LDS
-constexpr int kTopStage = 4096;   // top-grid charges held in LDS
-constexpr int kTopNodes = 32;     // output nodes per workgroup
-constexpr int kTopShares = 8;     // threads per output node (z-planes of the sources dealt round-robin)
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_top(DevPlan p, const T *__restrict__ qgrid, T *__restrict__ ucut,
-                                             T *__restrict__ ugrid, double h, double a, int ntab, Smooth g)
-{
-    // weights by squared integer distance d2: gamma(h sqrt(d2) / a) / a; the
-    // level's factor 2^-(l-1) is applied to the sum
-    __shared__ T tab[kTopTable];
-    __shared__ T qs[kTopStage];
-    __shared__ T part[kTopShares][kTopNodes];
-    const int64_t blk = blockIdx.x;
-    const int s = find_segment(p.top_prefix, p.nsys, blk);
-    const SysPlan &P = p.sys[s];
-    const int k = P.nlev - 1;
-    const int dx = P.gdim[k][0], dy = P.gdim[k][1], dz = P.gdim[k][2];
-    const int M = dx * dy * dz;
-    const int PX = padded_x(dx), PY = padded_x(dy);
-    const T *q = qgrid + P.qoff[k];
-    const int tid = threadIdx.x;
-    for (int d2 = tid; d2 < ntab && d2 < kTopTable; d2 += 256)
-        tab[d2] = gamma_s(T(h / a) * sqrt(T(d2)), g) * T(1.0 / a);
-    for (int e = tid; e < M && e < kTopStage; e += 256) {
-        const int x = e % dx, y = (e / dx) % dy, z = e / (dx * dy);
-        qs[e] = q[((int64_t)(z + kGridPad) * PY + (y + kGridPad)) * PX + (x + kGridPad)];
-    }
-    __syncthreads();
-    const int lane = tid % kTopNodes, share = tid / kTopNodes;
-    const int node = (int)(blk - p.top_prefix[s]) * kTopNodes + lane;
-    T acc = 0;
-    if (node < M) {
-        const int x = node % dx, y = (node / dx) % dy, z = node / (dx * dy);
-        for (int nz = share; nz < dz; nz += kTopShares)
-            for (int ny = 0; ny < dy; ++ny) {
-                const int eyz = (nz - z) * (nz - z) + (ny - y) * (ny - y);
-                const int e0 = (nz * dy + ny) * dx;
-                for (int nx = 0; nx < dx; ++nx) {
-                    const int d2 = eyz + (nx - x) * (nx - x);
-                    const T w = d2 < kTopTable ? tab[d2] : gamma_s(T(h / a) * sqrt(T(d2)), g) * T(1.0 / a);
-                    const int e = e0 + nx;
-                    const T qv = e < kTopStage
-                                     ? qs[e]
-                                     : q[((int64_t)(nz + kGridPad) * PY + (ny + kGridPad)) * PX + (nx + kGridPad)];
-                    acc += w * qv;
-                }
-            }
-    }
-    part[share][lane] = acc;
-    __syncthreads();
-    if (share == 0 && node < M) {
-        T sum = part[0][lane];
-        for (int sh = 1; sh < kTopShares; ++sh) sum += part[sh][lane];   // fixed order
-        sum *= T(ldexp(1.0, -k));
-        const int64_t o = P.uoff[k] + node;
-        ucut[o] = sum;
-        ugrid[o] = sum;
-    }
-}
-
-// ---------------------------------------------------------------------------
 // Prolongation (Section 3): u^k_mu = u^{k,cutoff}_mu + sum_nu phi^{k+1}_nu(r^k_mu) u^{k+1}_nu,
 // the transpose of restriction. Per axis, fine index m sits at coarse
 // coordinate m/2; with n = floor(m/2) the coarse nodes n-(S-1) .. n+S carry
@@ -480,7 +519,8 @@ __device__ inline void prolong_node(const SysPlan &P, const T *__restrict__ ucut
     using B = Basis<PD>;
     constexpr int S = B::S, W = 2 * S;
     const int dx = P.gdim[k][0], dy = P.gdim[k][1];
-    const int r[3] = {(int)(loc % dx), (int)((loc / dx) % dy), (int)(loc / ((int64_t)dx * dy))};
+    const int l = (int)loc;   // nodes of one grid fit in int
+    const int r[3] = {l % dx, (l / dx) % dy, l / (dx * dy)};
     int cn[3][W];
     T cw[3][W];
 #pragma unroll
@@ -722,35 +762,45 @@ hipError_t Launch<T>::restrict_level(hipStream_t s, const DevPlan &p, const Work
 }
 
 template <typename T, int R>
-static hipError_t stencil_r(hipStream_t s, const DevPlan &p, const Work<T> &w, const StencilTables<T> &tb)
+static hipError_t stencil_r(hipStream_t s, const DevPlan &p, const Work<T> &w, const StencilTables<T> &tb,
+                            const TopArgs &top)
 {
+    const dim3 grid((unsigned)(p.ntiles + top.nblocks));
     if (tb.threads == 256) {
-        hipLaunchKernelGGL((k_stencil<T, R, 256>), dim3((unsigned)p.ntiles), dim3(256), 0, s, p, w.qgrid, w.ucut,
-                           tb.cols, tb.w, tb.ncols);
+        hipLaunchKernelGGL((k_stencil<T, R, 256>), grid, dim3(256), 0, s, p, w.qgrid, w.ucut, tb.cols, tb.w,
+                           tb.ncols, w.ugrid, top);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL((k_stencil<T, R, 1024>), dim3((unsigned)p.ntiles), dim3(1024), 0, s, p,
-                       w.qgrid, w.ucut, tb.cols,
-                       tb.w, tb.ncols);
+    hipLaunchKernelGGL((k_stencil<T, R, 1024>), grid, dim3(1024), 0, s, p, w.qgrid, w.ucut, tb.cols, tb.w, tb.ncols,
+                       w.ugrid, top);
     return hipGetLastError();
 }
 
+// The lattice cutoff of every level below the top, with the top level's
+// blocks in the same launch; the top alone when there are no tiles.
 template <typename T>
-hipError_t Launch<T>::stencil(hipStream_t s, const DevPlan &p, const Work<T> &w, const StencilTables<T> &tb)
+hipError_t Launch<T>::stencil(hipStream_t s, const DevPlan &p, const Work<T> &w, const StencilTables<T> &tb,
+                              const MethodConst &m)
 {
-    if (p.ntiles == 0) return hipSuccess;
+    TopArgs top{m.h, m.a, p.top_d2 + 1, p.ntop, m.g};
+    if (p.ntiles == 0) {
+        if (p.ntop == 0) return hipSuccess;
+        hipLaunchKernelGGL(k_top<T>, dim3((unsigned)p.ntop), dim3(kTopThreads), 0, s, p, w.qgrid, w.ucut, w.ugrid,
+                           m.h, m.a, p.top_d2 + 1, m.g);
+        return hipGetLastError();
+    }
     switch (tb.reach) {
-    case 1: return stencil_r<T, 1>(s, p, w, tb);
-    case 2: return stencil_r<T, 2>(s, p, w, tb);
-    case 3: return stencil_r<T, 3>(s, p, w, tb);
-    case 4: return stencil_r<T, 4>(s, p, w, tb);
-    case 5: return stencil_r<T, 5>(s, p, w, tb);
-    case 6: return stencil_r<T, 6>(s, p, w, tb);
-    case 7: return stencil_r<T, 7>(s, p, w, tb);
-    case 8: return stencil_r<T, 8>(s, p, w, tb);
-    case 9: return stencil_r<T, 9>(s, p, w, tb);
-    case 10: return stencil_r<T, 10>(s, p, w, tb);
-    case 11: return stencil_r<T, 11>(s, p, w, tb);
+    case 1: return stencil_r<T, 1>(s, p, w, tb, top);
+    case 2: return stencil_r<T, 2>(s, p, w, tb, top);
+    case 3: return stencil_r<T, 3>(s, p, w, tb, top);
+    case 4: return stencil_r<T, 4>(s, p, w, tb, top);
+    case 5: return stencil_r<T, 5>(s, p, w, tb, top);
+    case 6: return stencil_r<T, 6>(s, p, w, tb, top);
+    case 7: return stencil_r<T, 7>(s, p, w, tb, top);
+    case 8: return stencil_r<T, 8>(s, p, w, tb, top);
+    case 9: return stencil_r<T, 9>(s, p, w, tb, top);
+    case 10: return stencil_r<T, 10>(s, p, w, tb, top);
+    case 11: return stencil_r<T, 11>(s, p, w, tb, top);
     default: return hipErrorInvalidValue;
     }
 }
@@ -759,15 +809,6 @@ int top_blocks(int nodes) { return (nodes + kTopNodes - 1) / kTopNodes; }
 
 int stencil_tile_xy(int elem_bytes, int reach) { return (elem_bytes == 8 && reach >= 10) ? 4 : kStencilTile; }
 int stencil_tile_z(int elem_bytes, int reach) { return (elem_bytes == 8 && reach >= 10) ? 4 : kStencilTile; }
-
-template <typename T>
-hipError_t Launch<T>::top_level(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m)
-{
-    if (p.ntop == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_top<T>, dim3((unsigned)p.ntop), dim3(256), 0, s, p, w.qgrid, w.ucut, w.ugrid, m.h, m.a,
-                       p.top_d2 + 1, m.g);
-    return hipGetLastError();
-}
 
 template <typename T>
 hipError_t Launch<T>::prolong_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k, const MethodConst &m)
