@@ -48,6 +48,8 @@ struct SysPlan {
     int64_t qoff[kMaxLevels];// offset of the padded charge grid: kGridPad zero nodes below
                              // and kGridPad + kStencilTile above the node range on each axis
     int64_t uoff[kMaxLevels];// offset of the unpadded potential grids
+    int64_t toff[kMaxLevels];// composite restriction scratch of level k (>= 1)
+    int64_t woff[kMaxLevels];// composite prolongation scratch of level k (>= 1)
     int64_t group0;          // first 64-atom pair group
     int64_t ngroups;
 };
@@ -137,7 +139,7 @@ template <typename T> __host__ __device__ inline T gamma_s(T rho, const Smooth &
 
 // ---- Section 3: nodal basis Phi, the C1 cubic numerical Hermite interpolant
 // (p = 3): 1 - 5/2 s^2 + 3/2 s^3 on |t| <= 1, -1/2 (s-1)(2-s)^2 on 1 < |t| < 2.
-template <typename T> __device__ inline T basis(T t)
+template <typename T> __host__ __device__ inline T basis(T t)
 {
     T s = fabs(t);
     T inner = T(1) + s * s * (T(-2.5) + T(1.5) * s);
@@ -163,7 +165,7 @@ template <typename T> __device__ inline T dbasis(T t)
 //   [0,1): 1 - 5/4 x^2 - 35/12 x^3 + 21/4 x^4 - 25/12 x^5
 //   [1,2): -4 + 75/4 x - 245/8 x^2 + 545/24 x^3 - 63/8 x^4 + 25/24 x^5
 //   [2,3): 18 - 153/4 x + 255/8 x^2 - 313/24 x^3 + 21/8 x^4 - 5/24 x^5
-template <typename T> __device__ inline T basis5(T t)
+template <typename T> __host__ __device__ inline T basis5(T t)
 {
     const T x = fabs(t);
     if (x < T(1)) return T(1) + x * x * (T(-1.25) + x * (T(-35.0 / 12) + x * (T(5.25) + x * T(-25.0 / 12))));

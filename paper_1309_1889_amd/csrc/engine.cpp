@@ -67,8 +67,29 @@ int geometry(const msm_params &prm, const double *lo, const double *hi, Geometry
 }
 
 struct Sizes {
-    int64_t cells, q, u;
+    int64_t cells, q, u, t, w;
 };
+
+// composite-transfer scratch of one system's geometry (elements)
+int64_t comp_t(const int gdim[][3], int nlev, int k)
+{
+    return round_up((int64_t)gdim[0][2] * gdim[k][1] * gdim[k][0], 64);
+}
+int64_t comp_w(const int gdim[][3], int nlev, int k)
+{
+    return round_up((int64_t)gdim[k][2] * gdim[0][1] * gdim[0][0], 64);
+}
+
+// a system's grids fit the composite transfers' LDS planes
+bool comp_fits(const int gdim[][3], int nlev)
+{
+    if (nlev < 2 || (int64_t)gdim[0][0] * gdim[0][1] > kPlaneCap) return false;
+    for (int k = 1; k < nlev; k++) {
+        if ((int64_t)gdim[0][1] * gdim[k][0] > kTmpCap || (int64_t)gdim[k][1] * gdim[0][0] > kTmpCap) return false;
+        if ((int64_t)gdim[k][1] * gdim[k][0] > kPlaneCap) return false;
+    }
+    return true;
+}
 
 Sizes sizes_of(const Geometry &g)
 {
@@ -80,6 +101,11 @@ Sizes sizes_of(const Geometry &g)
         s.q += round_up((int64_t)padded_x(g.gdim[k][0]) * padded_x(g.gdim[k][1]) * padded_z(g.gdim[k][2]), 64);
         s.u += round_up((int64_t)g.gdim[k][0] * g.gdim[k][1] * g.gdim[k][2], 64);
     }
+    if (comp_fits(g.gdim, g.nlev))
+        for (int k = 1; k < g.nlev; k++) {
+            s.t += comp_t(g.gdim, g.nlev, k);
+            s.w += comp_w(g.gdim, g.nlev, k);
+        }
     return s;
 }
 
@@ -119,6 +145,8 @@ template <typename T> void carve(msm_ctx *c, Work<T> &w, char *base, size_t *use
     w.qgrid = (T *)take(sizeof(T) * c->cap_q);
     w.ucut = (T *)take(sizeof(T) * c->cap_u);
     w.ugrid = (T *)take(sizeof(T) * c->cap_u);
+    w.tscr = (T *)take(sizeof(T) * c->cap_t);
+    w.wscr = (T *)take(sizeof(T) * c->cap_w);
     w.eparts = (double *)take(sizeof(double) * c->cap_iblk);
     w.status = (int *)take(sizeof(int) * 64);
     *used = off;
@@ -147,6 +175,9 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     std::vector<int64_t> atom_p(W), group_p(W), cell_p(W), iblk_p(W), top_p(W), ant_p(W);
     std::vector<int64_t> node_p((size_t)kMaxLevels * W);
     int64_t cells = 0, q = 0, u = 0, groups = 0, iblk = 0, top = 0, ant = 0;
+    int64_t tsz = 0, wsz = 0, rxy = 0, pxy = 0;
+    bool composite = true;
+    std::vector<int64_t> rxy_p(W), pxy_p(W);
     int64_t nodes[kMaxLevels] = {0};
     int maxlev = 1, top_d2 = 0;
     for (int s = 0; s < nsys; s++) {
@@ -193,6 +224,19 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
             u += round_up(n, 64);
             nodes[k] += n;
         }
+        rxy_p[s] = rxy;
+        pxy_p[s] = pxy;
+        if (g.nlev >= 2) {
+            if (!comp_fits(g.gdim, g.nlev)) composite = false;
+            rxy += (int64_t)g.gdim[0][2] * (g.nlev - 1);
+            for (int k = 1; k < g.nlev; k++) {
+                P.toff[k] = tsz;
+                P.woff[k] = wsz;
+                tsz += comp_t(g.gdim, g.nlev, k);
+                wsz += comp_w(g.gdim, g.nlev, k);
+                pxy += g.gdim[k][2];
+            }
+        }
         cells += P.ncells;
         groups += P.ngroups;
         iblk += (P.natoms + 255) / 256;
@@ -202,6 +246,40 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
         int d2 = 0;
         for (int d = 0; d < 3; d++) d2 += (g.gdim[kt][d] - 1) * (g.gdim[kt][d] - 1);
         top_d2 = std::max(top_d2, d2);
+    }
+    rxy_p[nsys] = rxy;
+    pxy_p[nsys] = pxy;
+    if (tsz > c->cap_t || wsz > c->cap_w || maxlev < 2) composite = false;
+    // composite filters of the transfers between level 0 and level k:
+    // phi_1(m) = Phi(m/2) and phi_{k+1}(m) = sum_j phi_1(j) phi_k(m - 2^k j),
+    // |m| <= s_k with s_1 = 2S-1 and s_{k+1} = s_k + 2^k s_1 (exact dyadic
+    // rationals: products and sums of the half-integer basis values)
+    const int S = (basis_degree(c->prm) + 1) / 2, s1 = 2 * S - 1;
+    std::vector<double> phi_tab;
+    int phi_off[kMaxLevels] = {0}, phi_s[kMaxLevels] = {0};
+    {
+        std::vector<double> p1(2 * s1 + 1);
+        for (int m = -s1; m <= s1; m++)
+            p1[m + s1] = m == 0 ? 1.0 : ((m & 1) ? (S == 3 ? basis5(0.5 * m) : basis(0.5 * m)) : 0.0);
+        std::vector<double> cur = p1;
+        int sk = s1;
+        for (int k = 1; k < maxlev && k < kMaxLevels; k++) {
+            phi_off[k] = (int)phi_tab.size();
+            phi_s[k] = sk;
+            phi_tab.insert(phi_tab.end(), cur.begin(), cur.end());
+            const int sn = sk + (1 << k) * s1;
+            std::vector<double> nxt(2 * sn + 1, 0.0);
+            for (int m = -sn; m <= sn; m++) {
+                double acc = 0;
+                for (int j = -s1; j <= s1; j++) {
+                    const int mm = m - (1 << k) * j;
+                    if (mm >= -sk && mm <= sk) acc += p1[j + s1] * cur[mm + sk];
+                }
+                nxt[m + sn] = acc;
+            }
+            cur.swap(nxt);
+            sk = sn;
+        }
     }
     atom_p[nsys] = offsets[nsys];
     group_p[nsys] = groups;
@@ -240,6 +318,8 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     const size_t o_cell = place(sizeof(int64_t) * W), o_iblk = place(sizeof(int64_t) * W);
     const size_t o_top = place(sizeof(int64_t) * W), o_ant = place(sizeof(int64_t) * W);
     const size_t o_node = place(sizeof(int64_t) * kMaxLevels * W), o_tile = place(sizeof(int64_t) * (nseg + 1));
+    const size_t o_rxy = place(sizeof(int64_t) * W), o_pxy = place(sizeof(int64_t) * W);
+    const size_t o_phi = place(sizeof(double) * std::max<size_t>(phi_tab.size(), 1));
     if (off > c->plan_cap) {
         // the current tables may still be read by queued work
         if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
@@ -270,6 +350,9 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     std::memcpy(h + o_ant, ant_p.data(), sizeof(int64_t) * W);
     std::memcpy(h + o_node, node_p.data(), sizeof(int64_t) * kMaxLevels * W);
     std::memcpy(h + o_tile, tile_p.data(), sizeof(int64_t) * (nseg + 1));
+    std::memcpy(h + o_rxy, rxy_p.data(), sizeof(int64_t) * W);
+    std::memcpy(h + o_pxy, pxy_p.data(), sizeof(int64_t) * W);
+    if (!phi_tab.empty()) std::memcpy(h + o_phi, phi_tab.data(), sizeof(double) * phi_tab.size());
     if (hipMemcpyAsync(c->plan_dev, h, off, hipMemcpyHostToDevice, c->stream) != hipSuccess) return MSM_ERR_HIP;
     if (hipEventRecord(c->plan_ev[slot], c->stream) != hipSuccess) return MSM_ERR_HIP;
     c->plan_ev_live[slot] = true;
@@ -297,6 +380,16 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     dp.nant = ant;
     for (int k = 0; k < kMaxLevels; k++) dp.nnodes[k] = nodes[k];
     dp.maxlev = maxlev;
+    dp.composite = composite ? 1 : 0;
+    dp.phi = (const double *)(d + o_phi);
+    std::memcpy(dp.phi_off, phi_off, sizeof(phi_off));
+    std::memcpy(dp.phi_s, phi_s, sizeof(phi_s));
+    dp.rxy_prefix = (const int64_t *)(d + o_rxy);
+    dp.pxy_prefix = (const int64_t *)(d + o_pxy);
+    dp.nrxy = rxy;
+    dp.npxy = pxy;
+    dp.nrz = 0;
+    for (int k = 1; k < kMaxLevels; k++) dp.nrz += nodes[k];
     c->host_sys = sys;
     c->last_offsets.assign(offsets, offsets + nsys + 1);
     if (domains) c->last_domains.assign(domains, domains + nsys * 6);
@@ -349,9 +442,14 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     mark(MSM_STAGE_ANTERP);
     if (do_long && (e = L::anterp(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
     mark(MSM_STAGE_RESTRICT);
-    // one launch per level, each for all systems of the batch
-    for (int k = 0; do_long && k + 1 < p.maxlev; k++)
-        if ((e = L::restrict_level(s, p, w, k, c->mc)) != hipSuccess) return MSM_ERR_HIP;
+    // every level from level 0 by composite filters (two launches), or one
+    // launch per level; each launch serves all systems of the batch
+    if (do_long && p.composite) {
+        if ((e = L::restrict_all(s, p, w)) != hipSuccess) return MSM_ERR_HIP;
+    } else {
+        for (int k = 0; do_long && k + 1 < p.maxlev; k++)
+            if ((e = L::restrict_level(s, p, w, k, c->mc)) != hipSuccess) return MSM_ERR_HIP;
+    }
     mark(MSM_STAGE_CUTOFF);
     if (do_long) {
         StencilTables<T> tb{c->wcols, (const T *)c->weights, c->ncols, c->mc.reach, c->mc.stencil_threads};
@@ -359,8 +457,12 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     }
     mark(MSM_STAGE_TOP);   // the top level runs in the lattice-cutoff launch
     mark(MSM_STAGE_PROLONG);
-    for (int k = p.maxlev - 2; do_long && k >= 0; k--)
-        if ((e = L::prolong_level(s, p, w, k, c->mc)) != hipSuccess) return MSM_ERR_HIP;
+    if (do_long && p.composite) {   // u^0 from every level at once; u^k (k >= 1) is not formed
+        if ((e = L::prolong_all(s, p, w)) != hipSuccess) return MSM_ERR_HIP;
+    } else {
+        for (int k = p.maxlev - 2; do_long && k >= 0; k--)
+            if ((e = L::prolong_level(s, p, w, k, c->mc)) != hipSuccess) return MSM_ERR_HIP;
+    }
     if (fork && (hipEventRecord(c->ev_join, ps) != hipSuccess || hipStreamWaitEvent(s, c->ev_join, 0) != hipSuccess))
         return MSM_ERR_HIP;
     mark(MSM_STAGE_INTERP);
@@ -557,6 +659,8 @@ int msm_setup(const msm_params *prm, void *stream, msm_ctx **out)
     c->cap_cells = sz.cells * ns;
     c->cap_q = sz.q * ns;
     c->cap_u = sz.u * ns;
+    c->cap_t = sz.t * ns;
+    c->cap_w = sz.w * ns;
     c->cap_iblk = (prm->max_atoms + 255) / 256 + ns;
     if (c->cap_cells >= ((int64_t)1 << 31)) {
         delete c;
@@ -762,6 +866,14 @@ int msm_debug_stages(msm_ctx *c, int sys, double *u_short, double *f_short, doub
                      double *const *ucut, double *const *ug)
 {
     if (!c || !c->plan_valid || sys < 0 || sys >= c->dp.nsys) return MSM_ERR_ARG;
+    // the composite prolongation forms u^0 only: form every level's u^k one
+    // level at a time from the lattice-cutoff potentials the evaluation left
+    for (int k = c->dp.maxlev - 2; c->dp.composite && k >= 0; k--) {
+        const hipError_t pe = c->prm.precision == MSM_FP32
+                                  ? Launch<float>::prolong_level(c->stream, c->dp, c->wf, k, c->mc)
+                                  : Launch<double>::prolong_level(c->stream, c->dp, c->wd, k, c->mc);
+        if (pe != hipSuccess) return MSM_ERR_HIP;
+    }
     hipError_t e = c->prm.precision == MSM_FP32
                        ? Launch<float>::stage_copy(c->stream, c->dp, c->wf, sys, u_short, f_short, qg, ucut, ug)
                        : Launch<double>::stage_copy(c->stream, c->dp, c->wd, sys, u_short, f_short, qg, ucut, ug);

@@ -29,7 +29,7 @@ struct msm_ctx {
     int d2max = 0;
     msmx::Geometry ctx_geom{};
     // capacities
-    int64_t cap_cells = 0, cap_q = 0, cap_u = 0, cap_iblk = 0;
+    int64_t cap_cells = 0, cap_q = 0, cap_u = 0, cap_iblk = 0, cap_t = 0, cap_w = 0;
     // device memory
     char *wbuf = nullptr;
     size_t wbytes = 0;

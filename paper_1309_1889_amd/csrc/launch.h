@@ -28,6 +28,13 @@ struct DevPlan {
     int64_t natoms, ngroups, ncells, niblk, ntop, ntiles, nant;
     int64_t nnodes[kMaxLevels];  // level-k nodes over the batch
     int maxlev;                  // largest level count in the batch
+    // composite transfers (all levels at once; composite = 0: one launch per level)
+    int composite;
+    const double *phi;           // composite filters: phi_k(m) at phi[phi_off[k] + m + phi_s[k]], |m| <= phi_s[k]
+    int phi_off[kMaxLevels], phi_s[kMaxLevels];
+    const int64_t *rxy_prefix;   // nsys+1: level-0 z-planes x levels >= 1 (restriction xy blocks)
+    const int64_t *pxy_prefix;   // nsys+1: z-planes of levels >= 1 (prolongation xy blocks)
+    int64_t nrxy, npxy, nrz;     // those block counts, and the nodes of levels >= 1
 };
 
 // Scratch arrays owned by the context.
@@ -45,6 +52,8 @@ template <typename T> struct Work {
     T *qgrid;            // padded charge grids, all levels and systems
     T *ucut;             // lattice-cutoff potentials (top level: u^{l-1})
     T *ugrid;            // prolongated potentials u^k
+    T *tscr;             // composite restriction: per level, level-0 z-planes x level-k (y, x)
+    T *wscr;             // composite prolongation: per level, level-k z-planes x level-0 (y, x)
     double *eparts;      // per interpolation block: sum q_i phi_i
     int *status;         // device status word
     // dynamics model (null when no model is bound)
@@ -82,6 +91,10 @@ struct MethodConst {
 };
 
 int anterp_tiles(int dx, int dy, int dz);
+// composite transfers: LDS capacity (elements) of a level-0 xy plane and of
+// the one-axis partial sums
+constexpr int kPlaneCap = 6144;
+constexpr int kTmpCap = 4096;
 bool anterp_two_pass(const DevPlan &p);   // anterpolation by cell partials (crowded cells) rather than tiles
 
 int scan_cells(hipStream_t s, int *counts, int *start, int64_t n, int *block_sums);
@@ -96,6 +109,9 @@ template <typename T> struct Launch {
     static hipError_t stencil(hipStream_t s, const DevPlan &p, const Work<T> &w, const StencilTables<T> &tb,
                               const MethodConst &m);
     static hipError_t prolong_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k, const MethodConst &m);
+    // every level >= 1 from level 0 / u^0 from every level, by composite filters
+    static hipError_t restrict_all(hipStream_t s, const DevPlan &p, const Work<T> &w);
+    static hipError_t prolong_all(hipStream_t s, const DevPlan &p, const Work<T> &w);
     // part: 0 everything, 1 the short-range pairs only, 2 the grid part only
     static hipError_t interp(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m,
                              T *forces, T *potentials, int part);

@@ -571,6 +571,216 @@ __global__ __launch_bounds__(256) void k_prolong(DevPlan p, const T *__restrict_
 }
 
 // ---------------------------------------------------------------------------
+// Composite transfers. Restriction from level k to k+1 and prolongation back
+// are, axis by axis, the filter phi_1(m) = Phi(m/2) between level-k node F
+// and level-(k+1) node C (absolute indices) at m = F - 2C (Section 3: the
+// level-(k+1) basis function at a level-k node), so the restriction from
+// level 0 straight to level k is the product of three one-axis filters
+// phi_k(F - 2^k C) with phi_{k+1}(m) = sum_j phi_1(j) phi_k(m - 2^k j), and
+// the prolongation from level k straight to level 0 is its transpose. The
+// level ranges keep every non-zero term, so q^k = R_k q^0 and
+// u^0 = u^{0,cutoff} + sum_k P_k u^{k,cutoff} (u^{l-1,cutoff} being the top
+// level's u) equal the level-by-level results up to rounding. Each takes two
+// launches for all levels and systems: one workgroup per plane does two axes
+// in LDS, then one thread per output node does the third.
+// ---------------------------------------------------------------------------
+__device__ inline int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+
+constexpr int kPhiCap = 1024;   // composite filter entries staged in LDS (all levels)
+
+// stage the composite filters in LDS in the working precision; returns false
+// when they do not fit (the caller then reads the table in global memory)
+template <typename T> __device__ inline int stage_phi(const DevPlan &p, T *lphi)
+{
+    const int k = p.maxlev - 1;
+    const int n = k >= 1 ? p.phi_off[k] + 2 * p.phi_s[k] + 1 : 0;
+    for (int e = threadIdx.x; e < n && e < kPhiCap; e += blockDim.x) lphi[e] = T(p.phi[e]);
+    __syncthreads();
+    return n;
+}
+
+// restriction, x and y: block = (system, level-0 z-plane fz, level k >= 1):
+// tscr_k[fz][cy][cx] = sum_{y,x} phi_k(y - 2^k cy) phi_k(x - 2^k cx) q^0[fz][y][x]
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict_xy(DevPlan p, const T *__restrict__ qgrid, T *__restrict__ tscr)
+{
+    __shared__ T plane[kPlaneCap];
+    __shared__ T tmp[kTmpCap];
+    __shared__ T lphi[kPhiCap];
+    const int64_t blk = blockIdx.x;
+    const int s = find_segment(p.rxy_prefix, p.nsys, blk);
+    const SysPlan &P = p.sys[s];
+    const int r = (int)(blk - p.rxy_prefix[s]);
+    const int fz = r / (P.nlev - 1), k = 1 + r % (P.nlev - 1);
+    const int fx_n = P.gdim[0][0], fy_n = P.gdim[0][1];
+    const int gx0 = P.gorg[0][0], gy0 = P.gorg[0][1];
+    const int PX = padded_x(fx_n), PY = padded_x(fy_n);
+    const T *q0 = qgrid + P.qoff[0] + ((int64_t)(fz + kGridPad) * PY + kGridPad) * PX + kGridPad;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < fx_n * fy_n; e += 256) {
+        const int y = e / fx_n, x = e - y * fx_n;
+        plane[e] = q0[(int64_t)y * PX + x];
+    }
+    const bool lds_phi = stage_phi<T>(p, lphi) <= kPhiCap;   // (synchronizes)
+    const int cx_n = P.gdim[k][0], cy_n = P.gdim[k][1];
+    const int st = 1 << k, sk = p.phi_s[k];
+    const T *lph = lphi + p.phi_off[k] + sk;                 // lph[m], |m| <= sk
+    const double *gph = p.phi + p.phi_off[k] + sk;
+    auto w = [&](int m) { return lds_phi ? lph[m] : T(gph[m]); };
+    // x: tmp[y][cx]
+    for (int e = tid; e < fy_n * cx_n; e += 256) {
+        const int y = e / cx_n, cx = e - y * cx_n;
+        const int c = st * (cx + P.gorg[k][0]);                 // 2^k C in absolute level-0 index
+        const int x0 = max(c - sk - gx0, 0), x1 = min(c + sk - gx0, fx_n - 1);
+        T acc = 0;
+#pragma unroll 4
+        for (int x = x0; x <= x1; ++x) acc += w(x + gx0 - c) * plane[y * fx_n + x];
+        tmp[e] = acc;
+    }
+    __syncthreads();
+    // y: into the scratch
+    T *out = tscr + P.toff[k] + (int64_t)fz * cy_n * cx_n;
+    for (int e = tid; e < cy_n * cx_n; e += 256) {
+        const int cy = e / cx_n, cx = e - cy * cx_n;
+        const int c = st * (cy + P.gorg[k][1]);
+        const int y0 = max(c - sk - gy0, 0), y1 = min(c + sk - gy0, fy_n - 1);
+        T acc = 0;
+#pragma unroll 4
+        for (int y = y0; y <= y1; ++y) acc += w(y + gy0 - c) * tmp[y * cx_n + cx];
+        out[e] = acc;
+    }
+}
+
+// level of a node of the flat range over levels >= 1, and its index in that level
+__device__ inline int level_of(const DevPlan &p, int64_t &g)
+{
+    int k = 1;
+    while (k + 1 < kMaxLevels && g >= p.nnodes[k]) {
+        g -= p.nnodes[k];
+        ++k;
+    }
+    return k;
+}
+
+// restriction, z: one thread per node of every level >= 1
+template <typename T>
+__global__ __launch_bounds__(256) void k_restrict_z(DevPlan p, const T *__restrict__ tscr, T *__restrict__ qgrid)
+{
+    __shared__ T lphi[kPhiCap];
+    const bool lds_phi = stage_phi<T>(p, lphi) <= kPhiCap;
+    int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= p.nrz) return;
+    const int k = level_of(p, g);
+    const int64_t *pref = p.node_prefix + (int64_t)k * (p.nsys + 1);
+    const int s = find_segment(pref, p.nsys, g);
+    const SysPlan &P = p.sys[s];
+    const int loc = (int)(g - pref[s]);
+    const int cx_n = P.gdim[k][0], cy_n = P.gdim[k][1];
+    const int cx = loc % cx_n, cy = (loc / cx_n) % cy_n, cz = loc / (cx_n * cy_n);
+    const int st = 1 << k, sk = p.phi_s[k];
+    const T *lph = lphi + p.phi_off[k] + sk;
+    const double *gph = p.phi + p.phi_off[k] + sk;
+    const int gz0 = P.gorg[0][2], fz_n = P.gdim[0][2];
+    const int c = st * (cz + P.gorg[k][2]);
+    const int z0 = max(c - sk - gz0, 0), z1 = min(c + sk - gz0, fz_n - 1);
+    const T *src = tscr + P.toff[k] + (int64_t)cy * cx_n + cx;
+    const int64_t plane = (int64_t)cy_n * cx_n;
+    T acc = 0;
+#pragma unroll 8
+    for (int z = z0; z <= z1; ++z) acc += (lds_phi ? lph[z + gz0 - c] : T(gph[z + gz0 - c])) * src[z * plane];
+    const int CX = padded_x(cx_n), CY = padded_x(cy_n);
+    qgrid[P.qoff[k] + ((int64_t)(cz + kGridPad) * CY + (cy + kGridPad)) * CX + (cx + kGridPad)] = acc;
+}
+
+// prolongation, x and y: block = (system, level k >= 1, level-k z-plane cz):
+// wscr_k[cz][fy][fx] = sum_{cy,cx} phi_k(fy - 2^k cy) phi_k(fx - 2^k cx) u^{k,cutoff}[cz][cy][cx]
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong_xy(DevPlan p, const T *__restrict__ ucut, T *__restrict__ wscr)
+{
+    __shared__ T plane[kPlaneCap];
+    __shared__ T tmp[kTmpCap];
+    __shared__ T lphi[kPhiCap];
+    const bool lds_phi = stage_phi<T>(p, lphi) <= kPhiCap;
+    const int64_t blk = blockIdx.x;
+    const int s = find_segment(p.pxy_prefix, p.nsys, blk);
+    const SysPlan &P = p.sys[s];
+    int r = (int)(blk - p.pxy_prefix[s]);
+    int k = 1;
+    while (r >= P.gdim[k][2]) {
+        r -= P.gdim[k][2];
+        ++k;
+    }
+    const int cz = r;
+    const int cx_n = P.gdim[k][0], cy_n = P.gdim[k][1];
+    const int fx_n = P.gdim[0][0], fy_n = P.gdim[0][1];
+    const int st = 1 << k, sk = p.phi_s[k];
+    const T *lph = lphi + p.phi_off[k] + sk;
+    const double *gph = p.phi + p.phi_off[k] + sk;
+    auto w = [&](int m) { return lds_phi ? lph[m] : T(gph[m]); };
+    const T *src = ucut + P.uoff[k] + (int64_t)cz * cy_n * cx_n;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < cy_n * cx_n; e += 256) plane[e] = src[e];
+    __syncthreads();
+    // x: tmp[cy][fx]
+    for (int e = tid; e < cy_n * fx_n; e += 256) {
+        const int cy = e / fx_n, fx = e - cy * fx_n;
+        const int f = fx + P.gorg[0][0];                            // absolute level-0 index
+        const int c0 = max(floor_div(f - sk + st - 1, st), P.gorg[k][0]);
+        const int c1 = min(floor_div(f + sk, st), P.gorg[k][0] + cx_n - 1);
+        T acc = 0;
+#pragma unroll 4
+        for (int c = c0; c <= c1; ++c) acc += w(f - st * c) * plane[cy * cx_n + (c - P.gorg[k][0])];
+        tmp[e] = acc;
+    }
+    __syncthreads();
+    // y: into the scratch
+    T *out = wscr + P.woff[k] + (int64_t)cz * fy_n * fx_n;
+    for (int e = tid; e < fy_n * fx_n; e += 256) {
+        const int fy = e / fx_n, fx = e - fy * fx_n;
+        const int f = fy + P.gorg[0][1];
+        const int c0 = max(floor_div(f - sk + st - 1, st), P.gorg[k][1]);
+        const int c1 = min(floor_div(f + sk, st), P.gorg[k][1] + cy_n - 1);
+        T acc = 0;
+#pragma unroll 4
+        for (int c = c0; c <= c1; ++c) acc += w(f - st * c) * tmp[(c - P.gorg[k][1]) * fx_n + fx];
+        out[e] = acc;
+    }
+}
+
+// prolongation, z, and the sum over levels: one thread per level-0 node
+template <typename T>
+__global__ __launch_bounds__(256) void k_prolong_z(DevPlan p, const T *__restrict__ ucut, const T *__restrict__ wscr,
+                                                   T *__restrict__ ugrid)
+{
+    __shared__ T lphi[kPhiCap];
+    const bool lds_phi = stage_phi<T>(p, lphi) <= kPhiCap;
+    const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (g >= p.nnodes[0]) return;
+    const int64_t *pref = p.node_prefix;   // level 0
+    const int s = find_segment(pref, p.nsys, g);
+    const SysPlan &P = p.sys[s];
+    const int loc = (int)(g - pref[s]);
+    const int fx_n = P.gdim[0][0], fy_n = P.gdim[0][1];
+    const int fx = loc % fx_n, fy = (loc / fx_n) % fy_n, fz = loc / (fx_n * fy_n);
+    const int f = fz + P.gorg[0][2];
+    const int64_t plane = (int64_t)fy_n * fx_n;
+    T acc = 0;
+    for (int k = 1; k < P.nlev; ++k) {
+        const int st = 1 << k, sk = p.phi_s[k];
+        const T *lph = lphi + p.phi_off[k] + sk;
+        const double *gph = p.phi + p.phi_off[k] + sk;
+        const int c0 = max(floor_div(f - sk + st - 1, st), P.gorg[k][2]);
+        const int c1 = min(floor_div(f + sk, st), P.gorg[k][2] + P.gdim[k][2] - 1);
+        const T *src = wscr + P.woff[k] + (int64_t)fy * fx_n + fx;
+#pragma unroll 4
+        for (int c = c0; c <= c1; ++c)
+            acc += (lds_phi ? lph[f - st * c] : T(gph[f - st * c])) * src[(c - P.gorg[k][2]) * plane];
+    }
+    const int64_t o = P.uoff[0] + loc;
+    ugrid[o] = ucut[o] + acc;
+}
+
+// ---------------------------------------------------------------------------
 // Interpolation (Section 3): u_i^long = sum_mu phi^0_mu(r_i) u^0_mu, with the
 // analytic gradient, and the combination into the outputs:
 // phi_i = k (u_i^short + u_i^long - q_i gamma(0)/a), F_i = k q_i (b_i - grad u_i^long),
@@ -818,6 +1028,23 @@ hipError_t Launch<T>::prolong_level(hipStream_t s, const DevPlan &p, const Work<
         hipLaunchKernelGGL((k_prolong<T, 5>), dim3(nblocks(p.nnodes[k], 256)), dim3(256), 0, s, p, w.ucut, w.ugrid, k);
     else
         hipLaunchKernelGGL((k_prolong<T, 3>), dim3(nblocks(p.nnodes[k], 256)), dim3(256), 0, s, p, w.ucut, w.ugrid, k);
+    return hipGetLastError();
+}
+
+template <typename T> hipError_t Launch<T>::restrict_all(hipStream_t s, const DevPlan &p, const Work<T> &w)
+{
+    if (p.nrxy == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_restrict_xy<T>, dim3((unsigned)p.nrxy), dim3(256), 0, s, p, w.qgrid, w.tscr);
+    hipLaunchKernelGGL(k_restrict_z<T>, dim3(nblocks(p.nrz, 256)), dim3(256), 0, s, p, w.tscr, w.qgrid);
+    return hipGetLastError();
+}
+
+template <typename T> hipError_t Launch<T>::prolong_all(hipStream_t s, const DevPlan &p, const Work<T> &w)
+{
+    if (p.npxy == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prolong_xy<T>, dim3((unsigned)p.npxy), dim3(256), 0, s, p, w.ucut, w.wscr);
+    hipLaunchKernelGGL(k_prolong_z<T>, dim3(nblocks(p.nnodes[0], 256)), dim3(256), 0, s, p, w.ucut, w.wscr,
+                       w.ugrid);
     return hipGetLastError();
 }
 
