@@ -189,6 +189,35 @@ template <typename T> __device__ inline T dbasis5(T t)
     return t < T(0) ? -v : v;
 }
 
+// Phi of degree P on its piece j <= |t| <= j+1 (pieces meet with equal values
+// at the knots, so a piece may be evaluated on its closed interval; 0 beyond
+// the support, for an atom binned into an edge cell it lies outside of), and
+// Phi anywhere inside |t| <= S by selecting the piece without a branch.
+template <int P, typename T> __device__ inline T phi_piece(T t, int j)
+{
+    const T x = fabs(t);
+    T v;
+    if (P == 3) {
+        const T u = T(2) - x;
+        v = j == 0 ? T(1) + x * x * (T(-2.5) + T(1.5) * x) : T(-0.5) * (x - T(1)) * u * u;
+        return x < T(2) ? v : T(0);
+    }
+    if (j == 0)
+        v = T(1) + x * x * (T(-1.25) + x * (T(-35.0 / 12) + x * (T(5.25) + x * T(-25.0 / 12))));
+    else if (j == 1)
+        v = T(-4) + x * (T(18.75) + x * (T(-30.625) + x * (T(545.0 / 24) + x * (T(-7.875) + x * T(25.0 / 24)))));
+    else
+        v = T(18) + x * (T(-38.25) + x * (T(31.875) + x * (T(-313.0 / 24) + x * (T(2.625) + x * T(-5.0 / 24)))));
+    return x < T(3) ? v : T(0);
+}
+
+template <int P, typename T> __device__ inline T phi_inside(T t)
+{
+    const T x = fabs(t);
+    if (P == 3) return x <= T(1) ? phi_piece<3>(t, 0) : phi_piece<3>(t, 1);
+    return x < T(1) ? phi_piece<5>(t, 0) : (x < T(2) ? phi_piece<5>(t, 1) : phi_piece<5>(t, 2));
+}
+
 // Basis of degree P (3 or 5) and its support half-width S: Phi(t) = 0 for |t| >= S.
 template <int P> struct Basis {
     static constexpr int S = (P + 1) / 2;

@@ -158,16 +158,24 @@ __global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__re
     T acc = 0;
     if (staged) {
         const T fx = T(ix), fy = T(iy), fz = T(iz);
-        // the node's cells ix-S .. ix+S-1 are region columns lx .. lx+2S-1
-        for (int ez = lz; ez < lz + 2 * S; ++ez)
-            for (int ey = ly; ey < ly + 2 * S; ++ey) {
-                const int row = ez * A::CY + ey;
+        // the node's cells ix-S .. ix+S-1 are region columns lx .. lx+2S-1;
+        // an atom in the node's cell row c (0 .. 2S-1) along an axis lies at
+        // |t - node| in [|c - S|, |c - S| + 1] or [S - 1 - c, S - c], so the
+        // piece of Phi along y and z is known for each row
+#pragma unroll
+        for (int c = 0; c < 2 * S; ++c) {
+            const int pz = c < S ? S - 1 - c : c - S;
+#pragma unroll
+            for (int b = 0; b < 2 * S; ++b) {
+                const int py = b < S ? S - 1 - b : b - S;
+                const int row = (lz + c) * A::CY + (ly + b);
                 const int jb = start[row * A::CX + lx], je = start[row * A::CX + lx + 2 * S];
                 for (int j = jb; j < je; ++j) {
                     const vec4_t<T> a = atoms[j];
-                    acc += B::phi(a.x - fx) * B::phi(a.y - fy) * B::phi(a.z - fz) * a.w;
+                    acc += phi_inside<PD>(a.x - fx) * phi_piece<PD>(a.y - fy, py) * phi_piece<PD>(a.z - fz, pz) * a.w;
                 }
             }
+        }
     } else {
         acc = gather_global<T, PD>(P, sx, cstart, ix, iy, iz);
     }
