@@ -4,6 +4,8 @@
 // binary search of a prefix table.
 #include <cmath>
 
+#include <type_traits>
+
 #include "device_util.h"
 #include "launch.h"
 #include "md.h"
@@ -67,17 +69,26 @@ __device__ inline T gather_global(const SysPlan &P, const vec4_t<T> *__restrict_
     return acc;
 }
 
+// threads per node in the tiled form: one per cell layer along z (two for the
+// quintic, whose six layers would need 1536 threads)
+template <int PD> constexpr int ant_layers_per_thread() { return Basis<PD>::S == 2 ? 1 : 2; }
+template <int PD> constexpr int ant_threads()
+{
+    return kAntX * kAntY * kAntZ * (2 * Basis<PD>::S / ant_layers_per_thread<PD>());
+}
+
 template <typename T, int PD>
-__global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__restrict__ sx,
-                                                const int *__restrict__ cstart, T *__restrict__ qgrid)
+__global__ __launch_bounds__(ant_threads<PD>()) void k_anterp(DevPlan p, const vec4_t<T> *__restrict__ sx,
+                                                              const int *__restrict__ cstart, T *__restrict__ qgrid)
 {
     using B = Basis<PD>;
     constexpr int S = B::S;
     using A = AntTile<S>;
+    constexpr int NT = ant_threads<PD>(), NODES = kAntX * kAntY * kAntZ, CPT = ant_layers_per_thread<PD>();
     __shared__ vec4_t<T> atoms[kAntAtoms];
     __shared__ int start[A::Cells + 1];   // staged position of each region cell's first atom
     __shared__ int gfirst[A::Cells];      // its sorted index
-    __shared__ int wsum[4];
+    __shared__ int wsum[NT / kWave];
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int s = find_segment(p.ant_prefix, p.nsys, blk);
     const SysPlan &P = p.sys[s];
@@ -93,7 +104,7 @@ __global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__re
     // cells of the reachable region (cells x0-S .. x0+kAntX+S-2, ...), 0 atoms
     // outside the grid: each thread counts a contiguous run of cells, a
     // workgroup scan places the runs
-    constexpr int per = (A::Cells + 255) / 256;
+    constexpr int per = (A::Cells + NT - 1) / NT;
     int cnt[per];
     int sum = 0;
 #pragma unroll
@@ -128,14 +139,14 @@ __global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__re
         if (c < A::Cells) start[c] = run;
         run += cnt[j];
     }
-    if (tid == 255) start[A::Cells] = run;
+    if (tid == NT - 1) start[A::Cells] = run;
     __syncthreads();
     const int total = start[A::Cells];
     const bool staged = total <= kAntAtoms;
     if (staged) {
         // one staged atom per thread and step: its cell by binary search
         const T lox = T(P.lo[0]), loy = T(P.lo[1]), loz = T(P.lo[2]), inv_h = T(P.inv_h);
-        for (int pos = tid; pos < total; pos += 256) {
+        for (int pos = tid; pos < total; pos += NT) {
             int lo_ = 0, hi_ = A::Cells;   // start[lo_] <= pos < start[hi_]
             while (hi_ - lo_ > 1) {
                 const int mid = (lo_ + hi_) >> 1;
@@ -151,19 +162,22 @@ __global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__re
         }
     }
     __syncthreads();
-    const int lx = tid % kAntX, ly = (tid / kAntX) % kAntY, lz = tid / (kAntX * kAntY);
+    // node of this thread, and its share of the node's cell layers along z
+    const int node = tid % NODES, q = uni(tid / NODES);
+    const int lx = node % kAntX, ly = (node / kAntX) % kAntY, lz = node / (kAntX * kAntY);
     const int ix = x0 + lx, iy = y0 + ly, iz = z0 + lz;
     const int rx = ix - P.gorg[0][0], ry = iy - P.gorg[0][1], rz = iz - P.gorg[0][2];
-    if (rx >= dx || ry >= dy || rz >= dz) return;
+    const bool inside = rx < dx && ry < dy && rz < dz;
     T acc = 0;
-    if (staged) {
+    if (inside && staged) {
         const T fx = T(ix), fy = T(iy), fz = T(iz);
         // the node's cells ix-S .. ix+S-1 are region columns lx .. lx+2S-1;
         // an atom in the node's cell row c (0 .. 2S-1) along an axis lies at
         // |t - node| in [|c - S|, |c - S| + 1] or [S - 1 - c, S - c], so the
         // piece of Phi along y and z is known for each row
 #pragma unroll
-        for (int c = 0; c < 2 * S; ++c) {
+        for (int cc = 0; cc < CPT; ++cc) {
+            const int c = q * CPT + cc;
             const int pz = c < S ? S - 1 - c : c - S;
 #pragma unroll
             for (int b = 0; b < 2 * S; ++b) {
@@ -176,11 +190,19 @@ __global__ __launch_bounds__(256) void k_anterp(DevPlan p, const vec4_t<T> *__re
                 }
             }
         }
-    } else {
+    } else if (inside && q == 0) {
         acc = gather_global<T, PD>(P, sx, cstart, ix, iy, iz);
     }
+    // the layers' partial sums, added in a fixed order
+    __syncthreads();
+    T *part = reinterpret_cast<T *>(atoms);
+    part[tid] = acc;
+    __syncthreads();
+    if (q != 0 || !inside) return;
+    T v = part[node];
+    for (int r = 1; r < NT / NODES; ++r) v += part[r * NODES + node];
     const int PX = padded_x(dx), PY = padded_x(dy);
-    qgrid[P.qoff[0] + ((int64_t)(rz + kGridPad) * PY + (ry + kGridPad)) * PX + (rx + kGridPad)] = acc;
+    qgrid[P.qoff[0] + ((int64_t)(rz + kGridPad) * PY + (ry + kGridPad)) * PX + (rx + kGridPad)] = v;
 }
 
 // pass 1: 256 / (2S)^3 cells per workgroup of 256 threads (4 for the cubic,
@@ -423,7 +445,14 @@ template <typename T, int R, int NT> struct StencilGeom {
     static constexpr int THREADS = NT;
     static constexpr int COLS = TXY * TXY;            // output columns per tile
     static constexpr int SHARES = THREADS / COLS;     // threads per output column
-    static constexpr int IN = EZ * EX * EX;           // staged charges
+    // LDS holds each (x, y) column's EZ charges contiguously, padded to EZP so
+    // that a column is a whole number of 16-byte vectors and the stride
+    // between neighbouring columns is an odd number of them: 8 lanes reading
+    // 8 neighbouring columns with 16-byte reads then touch all 32 banks once
+    static constexpr int VW = 16 / (int)sizeof(T);
+    static constexpr int EZV = (EZ + VW - 1) / VW;    // vectors per column
+    static constexpr int EZP = (EZV % 2 ? EZV : EZV + 1) * VW;
+    static constexpr int IN = EZP * EX * EX;          // staged charges
     static constexpr int LDS = IN > THREADS * TZ ? IN : THREADS * TZ;   // also holds the share sums
 };
 
@@ -436,7 +465,7 @@ __global__ __launch_bounds__(NT) void k_stencil(DevPlan p, const T *__restrict__
     constexpr int D = 2 * R + 1;
     constexpr int L = G::TZ + 2 * R;
     constexpr int NL = G::LDS > kTopThreads + 2 ? G::LDS : kTopThreads + 2;
-    __shared__ T tile[NL];
+    __shared__ __align__(16) T tile[NL];
     if ((int64_t)blockIdx.x < top.nblocks) {
         top_block<T>(p, blockIdx.x, qgrid, ucut, ugrid, top.h, top.a, top.ntab, top.g, tile, NL);
         return;
@@ -453,12 +482,27 @@ __global__ __launch_bounds__(NT) void k_stencil(DevPlan p, const T *__restrict__
     const int PX = padded_x(dx), PY = padded_x(dy);
     const T *q = qgrid + P.qoff[k];
 
-    // stage the charges of the grown tile (the grid's zero halo covers the overhang)
-    for (int e = threadIdx.x; e < G::IN; e += G::THREADS) {
+    // stage the charges of the grown tile (the grid's zero halo covers the
+    // overhang), read along x, stored column by column
+    for (int e = threadIdx.x; e < G::EZ * G::EX * G::EX; e += G::THREADS) {
         const int ex = e % G::EX, ey = (e / G::EX) % G::EX, ez = e / (G::EX * G::EX);
-        tile[e] = q[((int64_t)(z0 + kGridPad - R + ez) * PY + (y0 + kGridPad - R + ey)) * PX + (x0 + kGridPad - R + ex)];
+        tile[(ey * G::EX + ex) * G::EZP + ez] =
+            q[((int64_t)(z0 + kGridPad - R + ez) * PY + (y0 + kGridPad - R + ey)) * PX + (x0 + kGridPad - R + ex)];
     }
     __syncthreads();
+    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+    constexpr int NV = (L + G::VW - 1) / G::VW;   // vectors read per column
+    auto column = [&](int x, int y, T *S) {
+        const V *cp = reinterpret_cast<const V *>(tile + (y * G::EX + x) * G::EZP);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+            const V d = cp[v];
+            const T *dv = reinterpret_cast<const T *>(&d);
+#pragma unroll
+            for (int i = 0; i < G::VW; ++i)
+                if (v * G::VW + i < L) S[v * G::VW + i] += dv[i];
+        }
+    };
 
     const int col = threadIdx.x % G::COLS;
     const int share = threadIdx.x / G::COLS;
@@ -470,18 +514,12 @@ __global__ __launch_bounds__(NT) void k_stencil(DevPlan p, const T *__restrict__
         const int2 o = qcols[c];
         T S[L];
 #pragma unroll
-        for (int z = 0; z < L; ++z) S[z] = tile[(z * G::EX + cy + o.y) * G::EX + cx + o.x];
-        if (o.x) {
-#pragma unroll
-            for (int z = 0; z < L; ++z) S[z] += tile[(z * G::EX + cy + o.y) * G::EX + cx - o.x];
-        }
+        for (int z = 0; z < L; ++z) S[z] = T(0);
+        column(cx + o.x, cy + o.y, S);
+        if (o.x) column(cx - o.x, cy + o.y, S);
         if (o.y) {
-#pragma unroll
-            for (int z = 0; z < L; ++z) S[z] += tile[(z * G::EX + cy - o.y) * G::EX + cx + o.x];
-            if (o.x) {
-#pragma unroll
-                for (int z = 0; z < L; ++z) S[z] += tile[(z * G::EX + cy - o.y) * G::EX + cx - o.x];
-            }
+            column(cx + o.x, cy - o.y, S);
+            if (o.x) column(cx - o.x, cy - o.y, S);
         }
         const T *w = qw + (int64_t)c * D;
 #pragma unroll
@@ -948,7 +986,8 @@ bool anterp_two_pass(const DevPlan &p) { return p.natoms > 2 * p.ncells; }
 template <typename T, int PD> static hipError_t anterp_p(hipStream_t s, const DevPlan &p, const Work<T> &w)
 {
     if (!anterp_two_pass(p)) {
-        hipLaunchKernelGGL((k_anterp<T, PD>), dim3((unsigned)p.nant), dim3(256), 0, s, p, w.sxyzq, w.cell_start,
+        hipLaunchKernelGGL((k_anterp<T, PD>), dim3((unsigned)p.nant), dim3(ant_threads<PD>()), 0, s, p, w.sxyzq,
+                           w.cell_start,
                            w.qgrid);
         return hipGetLastError();
     }
