@@ -145,7 +145,9 @@ typedef struct {
                               lane per atom; 1: each wave owns 16 atoms, four lanes per atom;
                               2: each of 8 waves owns an 8-atom cluster of the group, eight
                               lanes per atom, and evaluates only the candidates within the
-                              cutoff of the cluster's bounding box */
+                              cutoff of the cluster's bounding box; 3: as 2, but each of 4 waves
+                              takes two clusters and lays out one candidate stream for both
+                              (same terms in the same order as 2, so the same bits) */
     int stencil_threads;   /* threads per lattice-cutoff tile: 256 or 1024 */
     int concurrent;        /* 1: the short-range sum runs on a second stream of the context,
                               concurrently with the grid stages (forked after binning,

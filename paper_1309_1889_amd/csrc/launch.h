@@ -86,7 +86,8 @@ struct MethodConst {
     int p;                     // degree of the nodal basis Phi: 3 or 5
     int reach;                 // stencil reach R: largest integer with R < 2a/h
     int pair_waves;            // waves per 64-atom group in the pair kernel: 4, 8 or 16; 1: 16-atom sub-groups;
-                               // 2: 8-atom clusters with bounding-box candidate filtering
+                               // 2: 8-atom clusters with bounding-box candidate filtering;
+                               // 3: two such clusters per wave sharing one candidate stream
     int stencil_threads;       // threads per stencil tile: 256 or 1024
 };
 

@@ -574,15 +574,20 @@ __global__ __launch_bounds__(kWave) void k_clusters(DevPlan p, const vec4_t<T> *
     cluster[g * kWave + lane] = pos < natoms ? (int)(first + pos) : -1;
 }
 
-template <typename T, bool MD> struct ClLds {
-    vec4_t<T> ring[kClWgWaves][kClRing];
-    vec4_t<T> raux[MD ? kClWgWaves : 1][MD ? kClRing : 1];
+template <typename T, bool MD, int NSUB> struct ClLds {
+    vec4_t<T> ring[kClWgWaves][NSUB][kClRing];
+    vec4_t<T> raux[MD ? kClWgWaves : 1][NSUB][MD ? kClRing : 1];
     int map[kClWgWaves][kClMap];        // stream position -> sorted atom
     int pre[kClWgWaves][kWave + 1];     // item stream offsets (positions beyond the table)
     int first[kClWgWaves][kWave];       // first atom of each item
 };
 
-template <typename T, bool MD, bool POT, int KIND>
+// NSUB = 2: a wave takes the two clusters of one 16-atom k-d half-quarter,
+// lays out one candidate stream for their common box and keeps each
+// candidate for each cluster whose box is within the cutoff (a ring per
+// cluster): the stream's cost is shared, and each cluster's evaluations stay
+// those of its own box.
+template <typename T, bool MD, bool POT, int KIND, int NSUB>
 __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                                 const int *__restrict__ cstart,
                                                                 const int *__restrict__ cluster,
@@ -590,28 +595,44 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
                                                                 const vec4_t<T> *__restrict__ saux,
                                                                 vec4_t<T> *__restrict__ ljout)
 {
-    __shared__ ClLds<T, MD> L;
+    __shared__ ClLds<T, MD, NSUB> L;
     const int lane = threadIdx.x % kWave;
     const int wv = uni((int)(threadIdx.x / kWave));
     // clusters of neighbouring groups share candidates: keep them on one XCD's L2
-    const int64_t c = xcd_remap(blockIdx.x, gridDim.x) * kClWgWaves + wv;   // cluster
+    const int64_t c = (xcd_remap(blockIdx.x, gridDim.x) * kClWgWaves + wv) * NSUB;   // first cluster
     if (c >= p.ngroups * (kWave / kClAtoms)) return;
     const int me = lane % kClAtoms, slot = lane / kClAtoms;
     const int m0 = uni(cluster[c * kClAtoms]);
-    if (m0 < 0) return;   // a cluster of absent atoms (the last group of a system)
+    if (m0 < 0) return;   // clusters of absent atoms (the last group of a system)
     const int64_t g = c / (kWave / kClAtoms);
     const int s = find_segment(p.group_prefix, p.nsys, g);
     const SysPlan &P = p.sys[s];
-    const int mi = cluster[c * kClAtoms + me];
-    const bool valid = mi >= 0;
-    const int64_t i = valid ? mi : m0;
-    const vec4_t<T> ai = sx[i];
-    vec4_t<T> xi;
-    if (MD) xi = saux[i];
-
-    const T bminx = uni(seg_min(ai.x, kClAtoms)), bmaxx = uni(seg_max(ai.x, kClAtoms));
-    const T bminy = uni(seg_min(ai.y, kClAtoms)), bmaxy = uni(seg_max(ai.y, kClAtoms));
-    const T bminz = uni(seg_min(ai.z, kClAtoms)), bmaxz = uni(seg_max(ai.z, kClAtoms));
+    bool on[NSUB], valid[NSUB];
+    int64_t i[NSUB];
+    vec4_t<T> ai[NSUB], xi[NSUB];
+    T bx_lo[NSUB], bx_hi[NSUB], by_lo[NSUB], by_hi[NSUB], bz_lo[NSUB], bz_hi[NSUB];
+#pragma unroll
+    for (int sc = 0; sc < NSUB; ++sc) {
+        const int first = uni(cluster[(c + sc) * kClAtoms]);
+        on[sc] = first >= 0;   // uniform
+        const int mi = cluster[(c + sc) * kClAtoms + me];
+        valid[sc] = mi >= 0;
+        i[sc] = valid[sc] ? mi : (on[sc] ? first : m0);
+        ai[sc] = sx[i[sc]];
+        if (MD) xi[sc] = saux[i[sc]];
+        bx_lo[sc] = uni(seg_min(ai[sc].x, kClAtoms)), bx_hi[sc] = uni(seg_max(ai[sc].x, kClAtoms));
+        by_lo[sc] = uni(seg_min(ai[sc].y, kClAtoms)), by_hi[sc] = uni(seg_max(ai[sc].y, kClAtoms));
+        bz_lo[sc] = uni(seg_min(ai[sc].z, kClAtoms)), bz_hi[sc] = uni(seg_max(ai[sc].z, kClAtoms));
+    }
+    // the stream covers the box of the clusters together
+    T bminx = bx_lo[0], bmaxx = bx_hi[0], bminy = by_lo[0], bmaxy = by_hi[0], bminz = bz_lo[0], bmaxz = bz_hi[0];
+#pragma unroll
+    for (int sc = 1; sc < NSUB; ++sc)
+        if (on[sc]) {
+            bminx = fmin(bminx, bx_lo[sc]), bmaxx = fmax(bmaxx, bx_hi[sc]);
+            bminy = fmin(bminy, by_lo[sc]), bmaxy = fmax(bmaxy, by_hi[sc]);
+            bminz = fmin(bminz, bz_lo[sc]), bmaxz = fmax(bmaxz, bz_hi[sc]);
+        }
     const T lox = T(P.lo[0]), loy = T(P.lo[1]), loz = T(P.lo[2]);
     const T inv_h = T(P.inv_h), h = T(1.0 / P.inv_h);
     const int ncx = P.nc[0], ncy = P.nc[1], ncz = P.nc[2];
@@ -629,15 +650,18 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
         asm volatile("" : "+v"(k.c2), "+v"(k.d1));
     else if (KIND == kPoly)
         asm volatile("" : "+v"(k.c1), "+v"(k.d0));
-    T fx = 0, fy = 0, fz = 0, u = 0;
-    T lx = 0, ly = 0, lz = 0, le = 0;
-    vec4_t<T> *ring = L.ring[wv];
-    vec4_t<T> *raux = L.raux[MD ? wv : 0];
+    T fx[NSUB], fy[NSUB], fz[NSUB], u[NSUB], lx[NSUB], ly[NSUB], lz[NSUB], le[NSUB];
+#pragma unroll
+    for (int sc = 0; sc < NSUB; ++sc) fx[sc] = fy[sc] = fz[sc] = u[sc] = lx[sc] = ly[sc] = lz[sc] = le[sc] = T(0);
     int *map = L.map[wv], *pre = L.pre[wv], *fst = L.first[wv];
-    int head = 0, tail = 0;   // ring positions (uniform; taken modulo the capacity)
-    auto eval_block = [&]() {
+    int head[NSUB], tail[NSUB];   // ring positions (uniform; taken modulo the capacity)
+#pragma unroll
+    for (int sc = 0; sc < NSUB; ++sc) head[sc] = tail[sc] = 0;
+    auto eval_block = [&](int sc) {
         // a block starts at a multiple of its size, so it does not wrap
-        const int e0 = (head & (kClRing - 1)) + slot;
+        const vec4_t<T> *ring = L.ring[wv][sc];
+        const vec4_t<T> *raux = L.raux[MD ? wv : 0][MD ? sc : 0];
+        const int e0 = (head[sc] & (kClRing - 1)) + slot;
         vec4_t<T> aj[kClUnroll], xj[kClUnroll];
 #pragma unroll
         for (int v = 0; v < kClUnroll; ++v) {
@@ -646,8 +670,9 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
         }
 #pragma unroll
         for (int v = 0; v < kClUnroll; ++v)
-            pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le);
-        head += kClBlock;
+            pair_term<T, MD, POT, KIND>(ai[sc], xi[sc], aj[v], xj[v], k, fx[sc], fy[sc], fz[sc], u[sc], lx[sc],
+                                        ly[sc], lz[sc], le[sc]);
+        head[sc] += kClBlock;
     };
     for (int ib = 0; ib < nitems; ib += kWave) {
         const int q = ib + lane;   // this lane's item
@@ -714,81 +739,90 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
                 pa = sx[j];
                 if (MD) px = saux[j];
             }
-            const T ddx = fmax(T(0), fmax(bminx - ca.x, ca.x - bmaxx));
-            const T ddy = fmax(T(0), fmax(bminy - ca.y, ca.y - bmaxy));
-            const T ddz = fmax(T(0), fmax(bminz - ca.z, ca.z - bmaxz));
-            const bool keep = have && ddx * ddx + ddy * ddy + ddz * ddz < reach2;
-            const uint64_t m = __ballot(keep);
-            if (keep) {
-                const int e = (tail + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
-                                                                     __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u))) &
-                              (kClRing - 1);
-                ring[e] = ca;
-                if (MD) raux[MD ? e : 0] = cx;
+#pragma unroll
+            for (int sc = 0; sc < NSUB; ++sc) {
+                const T ddx = fmax(T(0), fmax(bx_lo[sc] - ca.x, ca.x - bx_hi[sc]));
+                const T ddy = fmax(T(0), fmax(by_lo[sc] - ca.y, ca.y - by_hi[sc]));
+                const T ddz = fmax(T(0), fmax(bz_lo[sc] - ca.z, ca.z - bz_hi[sc]));
+                const bool keep = on[sc] && have && ddx * ddx + ddy * ddy + ddz * ddz < reach2;
+                const uint64_t m = __ballot(keep);
+                if (keep) {
+                    const int e = (tail[sc] + (int)__builtin_amdgcn_mbcnt_hi(
+                                                  (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u))) &
+                                  (kClRing - 1);
+                    L.ring[wv][sc][e] = ca;
+                    if (MD) L.raux[MD ? wv : 0][MD ? sc : 0][MD ? e : 0] = cx;
+                }
+                tail[sc] += __popcll(m);
             }
-            tail += __popcll(m);
             __builtin_amdgcn_wave_barrier();
-            while (tail - head >= kClBlock) eval_block();
+#pragma unroll
+            for (int sc = 0; sc < NSUB; ++sc)
+                while (tail[sc] - head[sc] >= kClBlock) eval_block(sc);
             __builtin_amdgcn_wave_barrier();
         }
     }
-    if (tail > head) {   // the last partial block, padded with a far-away atom
-        if (lane < head + kClBlock - tail) {
-            vec4_t<T> far;
-            far.x = far.y = far.z = T(1e18);
-            far.w = T(0);
-            ring[(tail + lane) & (kClRing - 1)] = far;
-            if (MD) raux[MD ? (tail + lane) & (kClRing - 1) : 0] = far;
+#pragma unroll
+    for (int sc = 0; sc < NSUB; ++sc) {
+        if (tail[sc] > head[sc]) {   // the last partial block, padded with a far-away atom
+            if (lane < head[sc] + kClBlock - tail[sc]) {
+                vec4_t<T> far;
+                far.x = far.y = far.z = T(1e18);
+                far.w = T(0);
+                L.ring[wv][sc][(tail[sc] + lane) & (kClRing - 1)] = far;
+                if (MD) L.raux[MD ? wv : 0][MD ? sc : 0][MD ? (tail[sc] + lane) & (kClRing - 1) : 0] = far;
+            }
+            __builtin_amdgcn_wave_barrier();
+            eval_block(sc);
         }
-        __builtin_amdgcn_wave_barrier();
-        eval_block();
-    }
-    fx = sum_slots(fx);
-    fy = sum_slots(fy);
-    fz = sum_slots(fz);
-    if (POT) u = sum_slots(u);
-    if (MD) {
-        lx = sum_slots(lx);
-        ly = sum_slots(ly);
-        lz = sum_slots(lz);
-        if (POT) le = sum_slots(le);
-    }
-    if (slot == 0 && valid) {
-        vec4_t<T> o;
-        o.x = fx;
-        o.y = fy;
-        o.z = fz;
-        o.w = u;
-        out[i] = o;
+        fx[sc] = sum_slots(fx[sc]);
+        fy[sc] = sum_slots(fy[sc]);
+        fz[sc] = sum_slots(fz[sc]);
+        if (POT) u[sc] = sum_slots(u[sc]);
         if (MD) {
-            vec4_t<T> ol;
-            ol.x = lx;
-            ol.y = ly;
-            ol.z = lz;
-            ol.w = le;
-            ljout[i] = ol;
+            lx[sc] = sum_slots(lx[sc]);
+            ly[sc] = sum_slots(ly[sc]);
+            lz[sc] = sum_slots(lz[sc]);
+            if (POT) le[sc] = sum_slots(le[sc]);
+        }
+        if (slot == 0 && valid[sc]) {
+            vec4_t<T> o;
+            o.x = fx[sc];
+            o.y = fy[sc];
+            o.z = fz[sc];
+            o.w = u[sc];
+            out[i[sc]] = o;
+            if (MD) {
+                vec4_t<T> ol;
+                ol.x = lx[sc];
+                ol.y = ly[sc];
+                ol.z = lz[sc];
+                ol.w = le[sc];
+                ljout[i[sc]] = ol;
+            }
         }
     }
 }
 
-template <typename T, int KIND>
+template <typename T, int KIND, int NSUB>
 static void pair_launch_cl(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot)
 {
     hipLaunchKernelGGL((k_clusters<T>), dim3((unsigned)p.ngroups), dim3(kWave), 0, s, p, w.sxyzq, w.cluster);
     const int64_t nclusters = p.ngroups * (kWave / kClAtoms);
-    const dim3 grid((unsigned)((nclusters + kClWgWaves - 1) / kClWgWaves)), block(kClWgWaves * kWave);
+    const int64_t per_wg = (int64_t)kClWgWaves * NSUB;
+    const dim3 grid((unsigned)((nclusters + per_wg - 1) / per_wg)), block(kClWgWaves * kWave);
     const vec4_t<T> *aux = (const vec4_t<T> *)w.saux;
     if (w.saux && pot)
-        hipLaunchKernelGGL((k_pair_cl<T, true, true, KIND>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.cluster,
-                           w.shrt, k, aux, w.shlj);
+        hipLaunchKernelGGL((k_pair_cl<T, true, true, KIND, NSUB>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
+                           w.cluster, w.shrt, k, aux, w.shlj);
     else if (w.saux)
-        hipLaunchKernelGGL((k_pair_cl<T, true, false, KIND>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
+        hipLaunchKernelGGL((k_pair_cl<T, true, false, KIND, NSUB>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
                            w.cluster, w.shrt, k, aux, w.shlj);
     else if (pot)
-        hipLaunchKernelGGL((k_pair_cl<T, false, true, KIND>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
+        hipLaunchKernelGGL((k_pair_cl<T, false, true, KIND, NSUB>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
                            w.cluster, w.shrt, k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
     else
-        hipLaunchKernelGGL((k_pair_cl<T, false, false, KIND>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
+        hipLaunchKernelGGL((k_pair_cl<T, false, false, KIND, NSUB>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
                            w.cluster, w.shrt, k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
 }
 
@@ -833,10 +867,11 @@ static void pair_launch(hipStream_t s, const DevPlan &p, const Work<T> &w, const
 template <typename T, int NW>
 static void pair_launch_m(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot, int kind)
 {
-    if (NW == 2) {   // cluster form
-        if (kind == kWolf) pair_launch_cl<T, kWolf>(s, p, w, k, pot);
-        else if (kind == kPolyHigh) pair_launch_cl<T, kPolyHigh>(s, p, w, k, pot);
-        else pair_launch_cl<T, kPoly>(s, p, w, k, pot);
+    if (NW == 2 || NW == 3) {   // cluster form: one cluster per wave, or two sharing a stream
+        constexpr int NS = NW == 2 ? 1 : 2;
+        if (kind == kWolf) pair_launch_cl<T, kWolf, NS>(s, p, w, k, pot);
+        else if (kind == kPolyHigh) pair_launch_cl<T, kPolyHigh, NS>(s, p, w, k, pot);
+        else pair_launch_cl<T, kPoly, NS>(s, p, w, k, pot);
         return;
     }
     if (NW == 1) {   // sub-group form
@@ -888,6 +923,7 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, co
     switch (m.pair_waves) {
     case 1: pair_launch_m<T, 1>(s, p, w, k, pot, kind); break;
     case 2: pair_launch_m<T, 2>(s, p, w, k, pot, kind); break;
+    case 3: pair_launch_m<T, 3>(s, p, w, k, pot, kind); break;
     case 4: pair_launch_m<T, 4>(s, p, w, k, pot, kind); break;
     case 8: pair_launch_m<T, 8>(s, p, w, k, pot, kind); break;
     case 16: pair_launch_m<T, 16>(s, p, w, k, pot, kind); break;

@@ -79,9 +79,9 @@ def test_autotune_and_tunings_agree():
     x = torch.tensor(w.xyzq(np.float32), device="cuda")
     ref = [t.clone() for t in ctx.energy_forces(x)]
     chosen = ctx.autotune(x, reps=3)
-    assert chosen["pair_waves"] in (1, 2, 4, 8, 16) and chosen["stencil_threads"] in (256, 1024)
+    assert chosen["pair_waves"] in (1, 2, 3, 4, 8, 16) and chosen["stencil_threads"] in (256, 1024)
     assert ctx.tuning() == chosen
-    for pw in (1, 2, 4, 8, 16):
+    for pw in (1, 2, 3, 4, 8, 16):
         for st in (256, 1024):
             ctx.set_tuning(pw, st)
             e, f, p = ctx.energy_forces(x)
@@ -109,7 +109,7 @@ def test_concurrent_stages_change_no_bit(precision):
     conc = msmx.MsmContext(w.a, w.h, w.lo, w.hi, precision=precision, max_atoms=w.n)
     seq.set_tuning(concurrent=0)
     assert conc.tuning()["concurrent"] == 1
-    for pw in (1, 2, 4, 8):
+    for pw in (1, 2, 3, 4, 8):
         seq.set_tuning(pair_waves=pw)
         conc.set_tuning(pair_waves=pw)
         ref = seq.energy_forces(x)
@@ -123,3 +123,27 @@ def test_concurrent_stages_change_no_bit(precision):
                     assert torch.equal(a, b) and torch.equal(b, c), (pw, graphs, rep)
         conc.set_graphs(False)
     assert seq.status() == 0 and conc.status() == 0
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_two_clusters_per_wave_same_bits(precision):
+    """Two clusters sharing one candidate stream keep, for each cluster, the
+    candidates of its own box in the same order, so the sums are the one-
+    cluster form's bit for bit; systems whose last group is partly empty
+    included."""
+    import paper_1309_1889_amd as msmx
+    dt = np.float32 if precision == "fp32" else np.float64
+    parts = [water_box(n, (p,) * 3, (s,) * 3, seed=20 + n) for n, p, s in ((1000, 10, 3.2), (733, 10, 3.0))]
+    w = parts[0]
+    x = torch.tensor(np.concatenate([p.xyzq(dt) for p in parts]), device="cuda")
+    offs = [0, parts[0].n, parts[0].n + parts[1].n]
+    doms = [list(p.lo) + list(p.hi) for p in parts]
+    ctx = msmx.MsmContext(w.a, w.h, w.lo, w.hi, precision=precision, max_atoms=offs[-1], max_systems=2)
+    got = {}
+    for pw in (2, 3):
+        ctx.set_tuning(pair_waves=pw)
+        got[pw] = [t.clone() for t in ctx.energy_forces(x, offs, doms)]
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    for a, b in zip(got[2], got[3]):
+        assert torch.equal(a, b)
