@@ -117,9 +117,10 @@ def sphere_taps(a, h):
     return int(((h * np.sqrt(X ** 2 + Y ** 2 + Z ** 2)) < 2 * a).sum())
 
 
-def traffic_record(kernel_file, kernel_name, workload):
-    """HBM bytes per launch from committed counter summaries, if they were
-    taken on the current kernel source; otherwise None."""
+def traffic_record(kernel_file, kernel_name, workload, form):
+    """HBM bytes per launch of the kernel form ``form`` (the pair_waves value
+    of the launch configuration) from committed counter summaries, if they
+    were taken on the current kernel source; otherwise None."""
     path = os.path.join(ROOT, "profiles", f"{kernel_name}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
@@ -127,7 +128,8 @@ def traffic_record(kernel_file, kernel_name, workload):
     src = open(os.path.join(ROOT, "paper_1309_1889_amd", "csrc", kernel_file), "rb").read()
     if rec.get("source_sha256") != hashlib.sha256(src).hexdigest():
         return None
-    return rec.get("bytes_per_launch")
+    got = rec.get("forms", {}).get(str(form))
+    return None if got is None else got.get("bytes_per_launch")
 
 
 def bench_batched(torch, msmx, w32, steps, warmup, slices, single_value):
@@ -579,7 +581,8 @@ def main():
         kname = {"short": "pair_short", "cutoff": "stencil"}[dominant]
         roofline = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU,
                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU, 4),
-                    "traffic": traffic_record(kfile, kname, args.workload),
+                    "traffic": traffic_record(kfile, kname, args.workload, ctx.tuning()["pair_waves"])
+                    if dominant == "short" else None,
                     "algorithmic_flops_per_launch": float(work[dominant]),
                     "unique_pairs": pairs, "flops_per_pair": FLOPS_PER_PAIR, "stencil_taps": taps}
     else:
