@@ -17,9 +17,6 @@ namespace msmx {
 
 namespace {
 
-constexpr int kScanThreads = 256;
-constexpr int kScanItems = 16;
-constexpr int kScanBlock = kScanThreads * kScanItems;
 
 __global__ void k_fill_i32(int *p, int64_t n, int v)
 {
@@ -62,78 +59,101 @@ __global__ void k_bin_count(DevPlan p, const vec4_t<T> *__restrict__ xyzq, int *
     slot_of[i] = atomicAdd(&counts[cell], 1);
 }
 
-// exclusive scan of int counts, three passes
+// Exclusive scan of int counts: per-block sums, then each block adds the
+// sums of the blocks before it to its own scan. A thread takes IPT
+// consecutive counts (16-byte loads), waves scan with lane shuffles, and one
+// barrier joins the waves of a block.
+template <int IPT> __device__ inline void load_counts(const int *__restrict__ in, int64_t n, int64_t idx, int (&v)[IPT])
+{
+    if (idx + IPT <= n) {
+#pragma unroll
+        for (int q = 0; q < IPT / 4; q++) {
+            const int4 t = *(const int4 *)(in + idx + 4 * q);
+            v[4 * q] = t.x, v[4 * q + 1] = t.y, v[4 * q + 2] = t.z, v[4 * q + 3] = t.w;
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < IPT; j++) v[j] = idx + j < n ? in[idx + j] : 0;
+    }
+}
+
+__device__ inline int wave_sum_i(int v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+    return v;
+}
+
+template <int IPT>
 __global__ __launch_bounds__(kScanThreads) void k_scan_reduce(const int *__restrict__ in, int64_t n,
                                                                int *__restrict__ bsum)
 {
-    __shared__ int red[kScanThreads];
-    int64_t base = blockIdx.x * (int64_t)kScanBlock;
+    __shared__ int red[kScanThreads / kWave];
+    const int64_t idx = blockIdx.x * (int64_t)(kScanThreads * IPT) + (int64_t)threadIdx.x * IPT;
+    int v[IPT];
+    load_counts<IPT>(in, n, idx, v);
     int acc = 0;
-    for (int j = 0; j < kScanItems; j++) {
-        int64_t idx = base + (int64_t)j * kScanThreads + threadIdx.x;
-        if (idx < n) acc += in[idx];
-    }
-    red[threadIdx.x] = acc;
+#pragma unroll
+    for (int j = 0; j < IPT; j++) acc += v[j];
+    acc = wave_sum_i(acc);
+    if (threadIdx.x % kWave == 0) red[threadIdx.x / kWave] = acc;
     __syncthreads();
-    for (int off = kScanThreads / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < kScanThreads / kWave; w++) t += red[w];
+        bsum[blockIdx.x] = t;
     }
-    if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
-}
-
-// in-block exclusive scan of one value per thread; returns the block total
-__device__ inline int block_exclusive_scan(int v, int *sh, int &total)
-{
-    int tid = threadIdx.x;
-    sh[tid] = v;
-    __syncthreads();
-    for (int off = 1; off < (int)blockDim.x; off <<= 1) {
-        int add = (tid >= off) ? sh[tid - off] : 0;
-        __syncthreads();
-        sh[tid] += add;
-        __syncthreads();
-    }
-    int incl = sh[tid];
-    total = sh[blockDim.x - 1];
-    __syncthreads();
-    return incl - v;
 }
 
 // start[idx] = exclusive prefix of counts for idx < n (the caller passes n =
 // cells + 1 with a zero count at the end), clearing counts
+template <int IPT>
 __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int *__restrict__ counts, int *__restrict__ start,
                                                               int64_t n, const int *__restrict__ bsum)
 {
-    __shared__ int sh[kScanThreads];
-    int64_t base = blockIdx.x * (int64_t)kScanBlock + (int64_t)threadIdx.x * kScanItems;
-    int v[kScanItems];
+    __shared__ int wsum[kScanThreads / kWave], wbefore[kScanThreads / kWave];
+    const int64_t idx = blockIdx.x * (int64_t)(kScanThreads * IPT) + (int64_t)threadIdx.x * IPT;
+    const int lane = threadIdx.x % kWave, wv = threadIdx.x / kWave;
+    int v[IPT];
+    load_counts<IPT>(counts, n, idx, v);
     int acc = 0;
-    for (int j = 0; j < kScanItems; j++) {
-        int64_t idx = base + j;
-        v[j] = idx < n ? counts[idx] : 0;
-        acc += v[j];
-    }
+#pragma unroll
+    for (int j = 0; j < IPT; j++) acc += v[j];
     // this block's offset: the sum of the earlier blocks' sums
     int before = 0;
     for (int b = threadIdx.x; b < (int)blockIdx.x; b += kScanThreads) before += bsum[b];
-    __shared__ int red[kScanThreads];
-    red[threadIdx.x] = before;
-    __syncthreads();
-    for (int off = kScanThreads / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
+    before = wave_sum_i(before);
+    int incl = acc;   // inclusive scan over the wave's threads
+    for (int off = 1; off < kWave; off <<= 1) {
+        const int t = __shfl_up(incl, off, kWave);
+        if (lane >= off) incl += t;
     }
-    before = red[0];
-    int total;
-    int ex = block_exclusive_scan(acc, sh, total) + before;
-    for (int j = 0; j < kScanItems; j++) {
-        int64_t idx = base + j;
-        if (idx < n) {
-            start[idx] = ex;
-            counts[idx] = 0;
-        }
+    if (lane == kWave - 1) wsum[wv] = incl;
+    if (lane == 0) wbefore[wv] = before;
+    __syncthreads();
+    int ex = incl - acc;
+    for (int w = 0; w < kScanThreads / kWave; w++) {
+        ex += w < wv ? wsum[w] : 0;
+        ex += wbefore[w];
+    }
+    int o[IPT];
+#pragma unroll
+    for (int j = 0; j < IPT; j++) {
+        o[j] = ex;
         ex += v[j];
+    }
+    if (idx + IPT <= n) {
+#pragma unroll
+        for (int q = 0; q < IPT / 4; q++) {
+            *(int4 *)(start + idx + 4 * q) = make_int4(o[4 * q], o[4 * q + 1], o[4 * q + 2], o[4 * q + 3]);
+            *(int4 *)(counts + idx + 4 * q) = make_int4(0, 0, 0, 0);
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < IPT; j++)
+            if (idx + j < n) {
+                start[idx + j] = o[j];
+                counts[idx + j] = 0;
+            }
     }
 }
 
@@ -261,10 +281,18 @@ template hipError_t fill_t<double>(hipStream_t, double *, int64_t, double);
 // the total).
 int scan_cells(hipStream_t s, int *counts, int *start, int64_t n, int *block_sums)
 {
-    int64_t nb = (n + kScanBlock - 1) / kScanBlock;
-    if (nb < 1) nb = 1;
-    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, n, block_sums);
-    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, s, counts, start, n, block_sums);
+    // four counts per thread while that takes at most kScanFewBlocks blocks
+    // (more blocks in flight), sixteen beyond (fewer block sums to add up)
+    const int64_t nb4 = (n + kScanThreads * 4 - 1) / (kScanThreads * 4);
+    if (nb4 <= kScanFewBlocks) {
+        const unsigned nb = (unsigned)std::max<int64_t>(nb4, 1);
+        hipLaunchKernelGGL(k_scan_reduce<4>, dim3(nb), dim3(kScanThreads), 0, s, counts, n, block_sums);
+        hipLaunchKernelGGL(k_scan_apply<4>, dim3(nb), dim3(kScanThreads), 0, s, counts, start, n, block_sums);
+    } else {
+        const unsigned nb = (unsigned)((n + kScanThreads * 16 - 1) / (kScanThreads * 16));
+        hipLaunchKernelGGL(k_scan_reduce<16>, dim3(nb), dim3(kScanThreads), 0, s, counts, n, block_sums);
+        hipLaunchKernelGGL(k_scan_apply<16>, dim3(nb), dim3(kScanThreads), 0, s, counts, start, n, block_sums);
+    }
     return (int)hipGetLastError();
 }
 

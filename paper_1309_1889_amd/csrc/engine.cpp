@@ -130,7 +130,7 @@ template <typename T> void carve(msm_ctx *c, Work<T> &w, char *base, size_t *use
     w.slot_of = (int *)take(sizeof(int) * na);
     w.cell_start = (int *)take(sizeof(int) * (c->cap_cells + 1));
     w.counts = (int *)take(sizeof(int) * (c->cap_cells + 1));
-    w.scan_blocks = (int *)take(sizeof(int) * ((c->cap_cells + 1) / 4096 + 2));
+    w.scan_blocks = (int *)take(sizeof(int) * std::max<int64_t>(kScanFewBlocks, (c->cap_cells + 1) / 4096 + 2));
     w.order = (int *)take(sizeof(int) * na);
     w.sxyzq = (vec4_t<T> *)take(vec_bytes<T>() * (na + 64));   // spare tail for the pair prefetch
     w.shrt = (vec4_t<T> *)take(vec_bytes<T>() * na);

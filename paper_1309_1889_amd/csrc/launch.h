@@ -98,6 +98,11 @@ constexpr int kPlaneCap = 6144;
 constexpr int kTmpCap = 4096;
 bool anterp_two_pass(const DevPlan &p);   // anterpolation by cell partials (crowded cells) rather than tiles
 
+// exclusive scan of the cell counts: threads per block, and the largest block
+// count of the four-counts-per-thread form (block sums needed: at most
+// max(kScanFewBlocks, (n + 4095) / 4096))
+constexpr int kScanThreads = 256;
+constexpr int kScanFewBlocks = 256;
 int scan_cells(hipStream_t s, int *counts, int *start, int64_t n, int *block_sums);
 
 template <typename T> struct Launch {
