@@ -1,5 +1,5 @@
 // Small device helpers shared by the kernel files: launch sizes, wave-level
-// broadcasts and reductions, and the clamped cell index of a grid coordinate.
+// broadcasts and reductions, workgroup reductions, and the clamped cell index of a grid coordinate.
 #pragma once
 
 #include "launch.h"
@@ -31,6 +31,30 @@ template <typename T> __device__ inline T wave_max(T v)
 {
     for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
     return v;
+}
+
+// Sum (max) over a workgroup of NT threads in a fixed order: a butterfly
+// across the lanes of each wave, then the waves in turn; one barrier. The
+// result is valid in thread 0; wpart holds NT / 64 values.
+template <int NT> __device__ inline double block_sum(double v, double *wpart)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (threadIdx.x % 64 == 0) wpart[threadIdx.x / 64] = v;
+    __syncthreads();
+    double t = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NT / 64; ++w) t += wpart[w];
+    return t;
+}
+template <int NT> __device__ inline double block_max(double v, double *wpart)
+{
+    v = wave_max(v);
+    if (threadIdx.x % 64 == 0) wpart[threadIdx.x / 64] = v;
+    __syncthreads();
+    double t = 0;
+    if (threadIdx.x == 0)
+        for (int w = 0; w < NT / 64; ++w) t = fmax(t, wpart[w]);
+    return t;
 }
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }

@@ -9,13 +9,12 @@
 // origin and the constraint iteration keep full resolution; the forces come
 // from the evaluation in the context's precision T (N x 3), and for T = float
 // an FP32 copy of x feeds that evaluation.
+#include "device_util.h"
 #include "md.h"
 
 namespace msmx {
 
 namespace {
-
-inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 template <typename T> struct V3 {
     T x, y, z;
@@ -199,7 +198,7 @@ __global__ void k_to_eval(int64_t n, const double4 *__restrict__ x, vec4_t<T> *_
 // Kinetic energy 1/2 sum m v^2 per interpolation-sized block of each system.
 __global__ __launch_bounds__(256) void k_kinetic(DevPlan p, const double4 *__restrict__ v, double *__restrict__ parts)
 {
-    __shared__ double red[256];
+    __shared__ double wpart[256 / 64];
     const int64_t blk = blockIdx.x;
     const int s = find_segment(p.iblk_prefix, p.nsys, blk);
     const SysPlan &P = p.sys[s];
@@ -209,13 +208,8 @@ __global__ __launch_bounds__(256) void k_kinetic(DevPlan p, const double4 *__res
         const double4 vi = v[i];
         e = 0.5 * (vi.x * vi.x + vi.y * vi.y + vi.z * vi.z) / vi.w;
     }
-    red[threadIdx.x] = e;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) parts[blk] = red[0];
+    e = block_sum<256>(e, wpart);
+    if (threadIdx.x == 0) parts[blk] = e;
 }
 
 // Propagator state of consecutive slices from the FP64 iterates:
@@ -254,7 +248,7 @@ __global__ __launch_bounds__(256) void k_correct(int64_t count6, double *__restr
                                                  const double *__restrict__ fout, const double *__restrict__ gnew,
                                                  double *__restrict__ gold, unsigned long long *__restrict__ change)
 {
-    __shared__ double red[256];
+    __shared__ double wpart[256 / 64];
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double c = 0;
     if (e < count6) {
@@ -265,13 +259,8 @@ __global__ __launch_bounds__(256) void k_correct(int64_t count6, double *__restr
         lam[e] = nv;
         gold[e] = g;
     }
-    red[threadIdx.x] = c;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicMax(change, (unsigned long long)__double_as_longlong(red[0]));
+    c = block_max<256>(c, wpart);
+    if (threadIdx.x == 0) atomicMax(change, (unsigned long long)__double_as_longlong(c));
 }
 
 // The same correction for rigid triples (a reading: Section 4 is silent on
@@ -288,7 +277,7 @@ __global__ __launch_bounds__(256) void k_correct_rigid(int64_t ntri, double *__r
                                                        const double *__restrict__ invm, TriModel tm,
                                                        unsigned long long *__restrict__ change)
 {
-    __shared__ double red[256];
+    __shared__ double wpart[256 / 64];
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     double ch = 0;
     if (t < ntri) {
@@ -334,13 +323,8 @@ __global__ __launch_bounds__(256) void k_correct_rigid(int64_t ntri, double *__r
             }
         }
     }
-    red[threadIdx.x] = ch;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] = fmax(red[threadIdx.x], red[threadIdx.x + off]);
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) atomicMax(change, (unsigned long long)__double_as_longlong(red[0]));
+    ch = block_max<256>(ch, wpart);
+    if (threadIdx.x == 0) atomicMax(change, (unsigned long long)__double_as_longlong(ch));
 }
 
 __global__ void k_copy_f64(int64_t n, const double *__restrict__ src, double *__restrict__ dst)

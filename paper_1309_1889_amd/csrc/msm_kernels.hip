@@ -845,7 +845,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4
                                                            T *__restrict__ potentials, double *__restrict__ eparts,
                                                            T ke, T self, const vec4_t<T> *__restrict__ ljin)
 {
-    __shared__ double red[kInterpThreads];
+    __shared__ double wpart[kInterpThreads / kWave];
     const int64_t blk = blockIdx.x;
     const int s = find_segment(p.iblk_prefix, p.nsys, blk);
     const SysPlan &P = p.sys[s];
@@ -909,32 +909,23 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4
         }
         e = (double)a.w * (double)phi + (double)lj.w;
     }
-    red[threadIdx.x] = e;
-    __syncthreads();
-    for (int off = kInterpThreads / 2; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) eparts[blk] = red[0];
+    e = block_sum<kInterpThreads>(e, wpart);
+    if (threadIdx.x == 0) eparts[blk] = e;
 }
 
 // Per-system sum of block partials times `scale` (the energy U = 1/2 sum_i
 // q_i phi_i uses 1/2): one workgroup per system, each thread a fixed stride of
-// partials, then a fixed tree, so the result does not depend on timing.
+// partials, then a fixed order across lanes and waves, so the result does not
+// depend on timing.
 __global__ __launch_bounds__(256) void k_energy(DevPlan p, const double *__restrict__ eparts,
                                                 double *__restrict__ energy, double scale)
 {
-    __shared__ double red[256];
+    __shared__ double wpart[256 / kWave];
     const int s = blockIdx.x;
     double acc = 0;
     for (int64_t b = p.iblk_prefix[s] + threadIdx.x; b < p.iblk_prefix[s + 1]; b += 256) acc += eparts[b];
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) energy[s] = scale * red[0];
+    acc = block_sum<256>(acc, wpart);
+    if (threadIdx.x == 0) energy[s] = scale * acc;
 }
 
 template <typename T>
