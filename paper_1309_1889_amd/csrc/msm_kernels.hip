@@ -630,7 +630,7 @@ __global__ __launch_bounds__(256) void k_prolong(DevPlan p, const T *__restrict_
 // launches for all levels and systems: one workgroup per plane does two axes
 // in LDS, then one thread per output node does the third.
 // ---------------------------------------------------------------------------
-__device__ inline int floor_div(int a, int b) { return a >= 0 ? a / b : -((-a + b - 1) / b); }
+constexpr int kZBatch = 16;   // z terms of the composite transfers loaded together
 
 constexpr int kPhiCap = 1024;   // composite filter entries staged in LDS (all levels)
 
@@ -712,8 +712,6 @@ __device__ inline int level_of(const DevPlan &p, int64_t &g)
 template <typename T>
 __global__ __launch_bounds__(256) void k_restrict_z(DevPlan p, const T *__restrict__ tscr, T *__restrict__ qgrid)
 {
-    __shared__ T lphi[kPhiCap];
-    const bool lds_phi = stage_phi<T>(p, lphi) <= kPhiCap;
     int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= p.nrz) return;
     const int k = level_of(p, g);
@@ -724,16 +722,29 @@ __global__ __launch_bounds__(256) void k_restrict_z(DevPlan p, const T *__restri
     const int cx_n = P.gdim[k][0], cy_n = P.gdim[k][1];
     const int cx = loc % cx_n, cy = (loc / cx_n) % cy_n, cz = loc / (cx_n * cy_n);
     const int st = 1 << k, sk = p.phi_s[k];
-    const T *lph = lphi + p.phi_off[k] + sk;
     const double *gph = p.phi + p.phi_off[k] + sk;
     const int gz0 = P.gorg[0][2], fz_n = P.gdim[0][2];
     const int c = st * (cz + P.gorg[k][2]);
     const int z0 = max(c - sk - gz0, 0), z1 = min(c + sk - gz0, fz_n - 1);
     const T *src = tscr + P.toff[k] + (int64_t)cy * cx_n + cx;
     const int64_t plane = (int64_t)cy_n * cx_n;
+    // the terms in z order; each batch's weights and values are loaded together
     T acc = 0;
-#pragma unroll 8
-    for (int z = z0; z <= z1; ++z) acc += (lds_phi ? lph[z + gz0 - c] : T(gph[z + gz0 - c])) * src[z * plane];
+    for (int zb = z0; zb <= z1; zb += kZBatch) {
+        // indices past the range repeat the last term's (valid addresses, no
+        // branches between the loads); those terms are not added
+        T v[kZBatch];
+        double wt[kZBatch];
+#pragma unroll
+        for (int j = 0; j < kZBatch; ++j) {
+            const int z = min(zb + j, z1);
+            v[j] = src[z * plane];
+            wt[j] = gph[z + gz0 - c];
+        }
+#pragma unroll
+        for (int j = 0; j < kZBatch; ++j)
+            if (zb + j <= z1) acc += T(wt[j]) * v[j];
+    }
     const int CX = padded_x(cx_n), CY = padded_x(cy_n);
     qgrid[P.qoff[k] + ((int64_t)(cz + kGridPad) * CY + (cy + kGridPad)) * CX + (cx + kGridPad)] = acc;
 }
@@ -771,8 +782,8 @@ __global__ __launch_bounds__(256) void k_prolong_xy(DevPlan p, const T *__restri
     for (int e = tid; e < cy_n * fx_n; e += 256) {
         const int cy = e / fx_n, fx = e - cy * fx_n;
         const int f = fx + P.gorg[0][0];                            // absolute level-0 index
-        const int c0 = max(floor_div(f - sk + st - 1, st), P.gorg[k][0]);
-        const int c1 = min(floor_div(f + sk, st), P.gorg[k][0] + cx_n - 1);
+        const int c0 = max((f - sk + st - 1) >> k, P.gorg[k][0]);   // floor division by 2^k
+        const int c1 = min((f + sk) >> k, P.gorg[k][0] + cx_n - 1);
         T acc = 0;
 #pragma unroll 4
         for (int c = c0; c <= c1; ++c) acc += w(f - st * c) * plane[cy * cx_n + (c - P.gorg[k][0])];
@@ -784,8 +795,8 @@ __global__ __launch_bounds__(256) void k_prolong_xy(DevPlan p, const T *__restri
     for (int e = tid; e < fy_n * fx_n; e += 256) {
         const int fy = e / fx_n, fx = e - fy * fx_n;
         const int f = fy + P.gorg[0][1];
-        const int c0 = max(floor_div(f - sk + st - 1, st), P.gorg[k][1]);
-        const int c1 = min(floor_div(f + sk, st), P.gorg[k][1] + cy_n - 1);
+        const int c0 = max((f - sk + st - 1) >> k, P.gorg[k][1]);
+        const int c1 = min((f + sk) >> k, P.gorg[k][1] + cy_n - 1);
         T acc = 0;
 #pragma unroll 4
         for (int c = c0; c <= c1; ++c) acc += w(f - st * c) * tmp[(c - P.gorg[k][1]) * fx_n + fx];
@@ -798,8 +809,6 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_prolong_z(DevPlan p, const T *__restrict__ ucut, const T *__restrict__ wscr,
                                                    T *__restrict__ ugrid)
 {
-    __shared__ T lphi[kPhiCap];
-    const bool lds_phi = stage_phi<T>(p, lphi) <= kPhiCap;
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= p.nnodes[0]) return;
     const int64_t *pref = p.node_prefix;   // level 0
@@ -813,14 +822,25 @@ __global__ __launch_bounds__(256) void k_prolong_z(DevPlan p, const T *__restric
     T acc = 0;
     for (int k = 1; k < P.nlev; ++k) {
         const int st = 1 << k, sk = p.phi_s[k];
-        const T *lph = lphi + p.phi_off[k] + sk;
         const double *gph = p.phi + p.phi_off[k] + sk;
-        const int c0 = max(floor_div(f - sk + st - 1, st), P.gorg[k][2]);
-        const int c1 = min(floor_div(f + sk, st), P.gorg[k][2] + P.gdim[k][2] - 1);
+        // level-k planes c with |f - 2^k c| <= s_k (arithmetic shifts: floor division by 2^k)
+        const int c0 = max((f - sk + st - 1) >> k, P.gorg[k][2]);
+        const int c1 = min((f + sk) >> k, P.gorg[k][2] + P.gdim[k][2] - 1);
         const T *src = wscr + P.woff[k] + (int64_t)fy * fx_n + fx;
-#pragma unroll 4
-        for (int c = c0; c <= c1; ++c)
-            acc += (lds_phi ? lph[f - st * c] : T(gph[f - st * c])) * src[(c - P.gorg[k][2]) * plane];
+        // the terms in plane order; each batch's weights and values are loaded together
+        for (int cb = c0; cb <= c1; cb += kZBatch) {
+            T v[kZBatch];
+            double wt[kZBatch];
+#pragma unroll
+            for (int j = 0; j < kZBatch; ++j) {
+                const int c = min(cb + j, c1);   // as in the restriction: valid, not added
+                v[j] = src[(c - P.gorg[k][2]) * plane];
+                wt[j] = gph[f - st * c];
+            }
+#pragma unroll
+            for (int j = 0; j < kZBatch; ++j)
+                if (cb + j <= c1) acc += T(wt[j]) * v[j];
+        }
     }
     const int64_t o = P.uoff[0] + loc;
     ugrid[o] = ucut[o] + acc;
