@@ -631,6 +631,9 @@ __global__ __launch_bounds__(256) void k_prolong(DevPlan p, const T *__restrict_
 // in LDS, then one thread per output node does the third.
 // ---------------------------------------------------------------------------
 constexpr int kZBatch = 16;   // z terms of the composite transfers loaded together
+// threads of a plane workgroup: the planes are few (one per level-0 z-plane and
+// level, or per level-k z-plane), so each gets a full CU's worth of waves
+constexpr int kXYThreads = 1024;
 
 constexpr int kPhiCap = 1024;   // composite filter entries staged in LDS (all levels)
 
@@ -648,7 +651,7 @@ template <typename T> __device__ inline int stage_phi(const DevPlan &p, T *lphi)
 // restriction, x and y: block = (system, level-0 z-plane fz, level k >= 1):
 // tscr_k[fz][cy][cx] = sum_{y,x} phi_k(y - 2^k cy) phi_k(x - 2^k cx) q^0[fz][y][x]
 template <typename T>
-__global__ __launch_bounds__(256) void k_restrict_xy(DevPlan p, const T *__restrict__ qgrid, T *__restrict__ tscr)
+__global__ __launch_bounds__(kXYThreads) void k_restrict_xy(DevPlan p, const T *__restrict__ qgrid, T *__restrict__ tscr)
 {
     __shared__ T plane[kPlaneCap];
     __shared__ T tmp[kTmpCap];
@@ -663,7 +666,7 @@ __global__ __launch_bounds__(256) void k_restrict_xy(DevPlan p, const T *__restr
     const int PX = padded_x(fx_n), PY = padded_x(fy_n);
     const T *q0 = qgrid + P.qoff[0] + ((int64_t)(fz + kGridPad) * PY + kGridPad) * PX + kGridPad;
     const int tid = threadIdx.x;
-    for (int e = tid; e < fx_n * fy_n; e += 256) {
+    for (int e = tid; e < fx_n * fy_n; e += kXYThreads) {
         const int y = e / fx_n, x = e - y * fx_n;
         plane[e] = q0[(int64_t)y * PX + x];
     }
@@ -674,7 +677,7 @@ __global__ __launch_bounds__(256) void k_restrict_xy(DevPlan p, const T *__restr
     const double *gph = p.phi + p.phi_off[k] + sk;
     auto w = [&](int m) { return lds_phi ? lph[m] : T(gph[m]); };
     // x: tmp[y][cx]
-    for (int e = tid; e < fy_n * cx_n; e += 256) {
+    for (int e = tid; e < fy_n * cx_n; e += kXYThreads) {
         const int y = e / cx_n, cx = e - y * cx_n;
         const int c = st * (cx + P.gorg[k][0]);                 // 2^k C in absolute level-0 index
         const int x0 = max(c - sk - gx0, 0), x1 = min(c + sk - gx0, fx_n - 1);
@@ -686,7 +689,7 @@ __global__ __launch_bounds__(256) void k_restrict_xy(DevPlan p, const T *__restr
     __syncthreads();
     // y: into the scratch
     T *out = tscr + P.toff[k] + (int64_t)fz * cy_n * cx_n;
-    for (int e = tid; e < cy_n * cx_n; e += 256) {
+    for (int e = tid; e < cy_n * cx_n; e += kXYThreads) {
         const int cy = e / cx_n, cx = e - cy * cx_n;
         const int c = st * (cy + P.gorg[k][1]);
         const int y0 = max(c - sk - gy0, 0), y1 = min(c + sk - gy0, fy_n - 1);
@@ -752,7 +755,7 @@ __global__ __launch_bounds__(256) void k_restrict_z(DevPlan p, const T *__restri
 // prolongation, x and y: block = (system, level k >= 1, level-k z-plane cz):
 // wscr_k[cz][fy][fx] = sum_{cy,cx} phi_k(fy - 2^k cy) phi_k(fx - 2^k cx) u^{k,cutoff}[cz][cy][cx]
 template <typename T>
-__global__ __launch_bounds__(256) void k_prolong_xy(DevPlan p, const T *__restrict__ ucut, T *__restrict__ wscr)
+__global__ __launch_bounds__(kXYThreads) void k_prolong_xy(DevPlan p, const T *__restrict__ ucut, T *__restrict__ wscr)
 {
     __shared__ T plane[kPlaneCap];
     __shared__ T tmp[kTmpCap];
@@ -776,10 +779,10 @@ __global__ __launch_bounds__(256) void k_prolong_xy(DevPlan p, const T *__restri
     auto w = [&](int m) { return lds_phi ? lph[m] : T(gph[m]); };
     const T *src = ucut + P.uoff[k] + (int64_t)cz * cy_n * cx_n;
     const int tid = threadIdx.x;
-    for (int e = tid; e < cy_n * cx_n; e += 256) plane[e] = src[e];
+    for (int e = tid; e < cy_n * cx_n; e += kXYThreads) plane[e] = src[e];
     __syncthreads();
     // x: tmp[cy][fx]
-    for (int e = tid; e < cy_n * fx_n; e += 256) {
+    for (int e = tid; e < cy_n * fx_n; e += kXYThreads) {
         const int cy = e / fx_n, fx = e - cy * fx_n;
         const int f = fx + P.gorg[0][0];                            // absolute level-0 index
         const int c0 = max((f - sk + st - 1) >> k, P.gorg[k][0]);   // floor division by 2^k
@@ -792,7 +795,7 @@ __global__ __launch_bounds__(256) void k_prolong_xy(DevPlan p, const T *__restri
     __syncthreads();
     // y: into the scratch
     T *out = wscr + P.woff[k] + (int64_t)cz * fy_n * fx_n;
-    for (int e = tid; e < fy_n * fx_n; e += 256) {
+    for (int e = tid; e < fy_n * fx_n; e += kXYThreads) {
         const int fy = e / fx_n, fx = e - fy * fx_n;
         const int f = fy + P.gorg[0][1];
         const int c0 = max((f - sk + st - 1) >> k, P.gorg[k][1]);
@@ -1092,7 +1095,7 @@ hipError_t Launch<T>::prolong_level(hipStream_t s, const DevPlan &p, const Work<
 template <typename T> hipError_t Launch<T>::restrict_all(hipStream_t s, const DevPlan &p, const Work<T> &w)
 {
     if (p.nrxy == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_restrict_xy<T>, dim3((unsigned)p.nrxy), dim3(256), 0, s, p, w.qgrid, w.tscr);
+    hipLaunchKernelGGL(k_restrict_xy<T>, dim3((unsigned)p.nrxy), dim3(kXYThreads), 0, s, p, w.qgrid, w.tscr);
     hipLaunchKernelGGL(k_restrict_z<T>, dim3(nblocks(p.nrz, 256)), dim3(256), 0, s, p, w.tscr, w.qgrid);
     return hipGetLastError();
 }
@@ -1100,7 +1103,7 @@ template <typename T> hipError_t Launch<T>::restrict_all(hipStream_t s, const De
 template <typename T> hipError_t Launch<T>::prolong_all(hipStream_t s, const DevPlan &p, const Work<T> &w)
 {
     if (p.npxy == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_prolong_xy<T>, dim3((unsigned)p.npxy), dim3(256), 0, s, p, w.ucut, w.wscr);
+    hipLaunchKernelGGL(k_prolong_xy<T>, dim3((unsigned)p.npxy), dim3(kXYThreads), 0, s, p, w.ucut, w.wscr);
     hipLaunchKernelGGL(k_prolong_z<T>, dim3(nblocks(p.nnodes[0], 256)), dim3(256), 0, s, p, w.ucut, w.wscr,
                        w.ugrid);
     return hipGetLastError();
