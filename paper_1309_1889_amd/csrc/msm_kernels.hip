@@ -634,6 +634,9 @@ constexpr int kZBatch = 16;   // z terms of the composite transfers loaded toget
 // threads of a plane workgroup: the planes are few (one per level-0 z-plane and
 // level, or per level-k z-plane), so each gets a full CU's worth of waves
 constexpr int kXYThreads = 1024;
+// threads of a z workgroup (one thread per output node): small workgroups
+// spread the few nodes over more CUs
+constexpr int kZThreads = 64;
 
 constexpr int kPhiCap = 1024;   // composite filter entries staged in LDS (all levels)
 
@@ -713,7 +716,7 @@ __device__ inline int level_of(const DevPlan &p, int64_t &g)
 
 // restriction, z: one thread per node of every level >= 1
 template <typename T>
-__global__ __launch_bounds__(256) void k_restrict_z(DevPlan p, const T *__restrict__ tscr, T *__restrict__ qgrid)
+__global__ __launch_bounds__(kZThreads) void k_restrict_z(DevPlan p, const T *__restrict__ tscr, T *__restrict__ qgrid)
 {
     int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (g >= p.nrz) return;
@@ -809,7 +812,7 @@ __global__ __launch_bounds__(kXYThreads) void k_prolong_xy(DevPlan p, const T *_
 
 // prolongation, z, and the sum over levels: one thread per level-0 node
 template <typename T>
-__global__ __launch_bounds__(256) void k_prolong_z(DevPlan p, const T *__restrict__ ucut, const T *__restrict__ wscr,
+__global__ __launch_bounds__(kZThreads) void k_prolong_z(DevPlan p, const T *__restrict__ ucut, const T *__restrict__ wscr,
                                                    T *__restrict__ ugrid)
 {
     const int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -1096,7 +1099,7 @@ template <typename T> hipError_t Launch<T>::restrict_all(hipStream_t s, const De
 {
     if (p.nrxy == 0) return hipSuccess;
     hipLaunchKernelGGL(k_restrict_xy<T>, dim3((unsigned)p.nrxy), dim3(kXYThreads), 0, s, p, w.qgrid, w.tscr);
-    hipLaunchKernelGGL(k_restrict_z<T>, dim3(nblocks(p.nrz, 256)), dim3(256), 0, s, p, w.tscr, w.qgrid);
+    hipLaunchKernelGGL(k_restrict_z<T>, dim3(nblocks(p.nrz, kZThreads)), dim3(kZThreads), 0, s, p, w.tscr, w.qgrid);
     return hipGetLastError();
 }
 
@@ -1104,7 +1107,7 @@ template <typename T> hipError_t Launch<T>::prolong_all(hipStream_t s, const Dev
 {
     if (p.npxy == 0) return hipSuccess;
     hipLaunchKernelGGL(k_prolong_xy<T>, dim3((unsigned)p.npxy), dim3(kXYThreads), 0, s, p, w.ucut, w.wscr);
-    hipLaunchKernelGGL(k_prolong_z<T>, dim3(nblocks(p.nnodes[0], 256)), dim3(256), 0, s, p, w.ucut, w.wscr,
+    hipLaunchKernelGGL(k_prolong_z<T>, dim3(nblocks(p.nnodes[0], kZThreads)), dim3(kZThreads), 0, s, p, w.ucut, w.wscr,
                        w.ugrid);
     return hipGetLastError();
 }
