@@ -37,7 +37,12 @@ namespace {
 //     (2S)^3 cells whose support covers it, in a fixed order.
 // ---------------------------------------------------------------------------
 constexpr int kAntX = 8, kAntY = 8, kAntZ = 4;
-constexpr int kAntAtoms = 2048;
+// atoms a tile stages in LDS: the cubic's 11x11x7-cell region holds about
+// 1,300 water atoms, the quintic's 13x13x9 about 2,400 (FP64: 3,072 x 32 bytes)
+template <typename T, int PD> constexpr int ant_atoms()
+{
+    return Basis<PD>::S == 2 ? 2048 : (sizeof(T) == 4 ? 4096 : 3072);
+}
 
 template <int S> struct AntTile {
     static constexpr int CX = kAntX + 2 * S - 1, CY = kAntY + 2 * S - 1, CZ = kAntZ + 2 * S - 1;   // cells reached
@@ -85,7 +90,7 @@ __global__ __launch_bounds__(ant_threads<PD>()) void k_anterp(DevPlan p, const v
     constexpr int S = B::S;
     using A = AntTile<S>;
     constexpr int NT = ant_threads<PD>(), NODES = kAntX * kAntY * kAntZ, CPT = ant_layers_per_thread<PD>();
-    __shared__ vec4_t<T> atoms[kAntAtoms];
+    __shared__ vec4_t<T> atoms[ant_atoms<T, PD>()];
     __shared__ int start[A::Cells + 1];   // staged position of each region cell's first atom
     __shared__ int gfirst[A::Cells];      // its sorted index
     __shared__ int wsum[NT / kWave];
@@ -142,7 +147,7 @@ __global__ __launch_bounds__(ant_threads<PD>()) void k_anterp(DevPlan p, const v
     if (tid == NT - 1) start[A::Cells] = run;
     __syncthreads();
     const int total = start[A::Cells];
-    const bool staged = total <= kAntAtoms;
+    const bool staged = total <= ant_atoms<T, PD>();
     if (staged) {
         // one staged atom per thread and step: its cell by binary search
         const T lox = T(P.lo[0]), loy = T(P.lo[1]), loz = T(P.lo[2]), inv_h = T(P.inv_h);
@@ -996,8 +1001,10 @@ int anterp_tiles(int dx, int dy, int dz)
     return ((dx + kAntX - 1) / kAntX) * ((dy + kAntY - 1) / kAntY) * ((dz + kAntZ - 1) / kAntZ);
 }
 
-// The tiles hold kAntAtoms atoms of an 11x11x7-cell region: above about 2
-// atoms per cell on average, many would overflow to the global gather.
+// The tiles stage at least twice as many atoms as their region has cells
+// (2,048 for the cubic's 847 cells, 3,072 or 4,096 for the quintic's 1,521):
+// above about 2 atoms per cell on average, many would overflow to the global
+// gather.
 bool anterp_two_pass(const DevPlan &p) { return p.natoms > 2 * p.ncells; }
 
 template <typename T, int PD> static hipError_t anterp_p(hipStream_t s, const DevPlan &p, const Work<T> &w)
