@@ -147,7 +147,9 @@ typedef struct {
                               lanes per atom, and evaluates only the candidates within the
                               cutoff of the cluster's bounding box; 3: as 2, but each of 4 waves
                               takes two clusters and lays out one candidate stream for both
-                              (same terms in the same order as 2, so the same bits) */
+                              (same terms in the same order as 2, so the same bits); 5 and 6:
+                              as 2 with 16-atom clusters, four lanes per atom (5), or 32-atom
+                              clusters, two lanes per atom (6) */
     int stencil_threads;   /* threads per lattice-cutoff tile: 256 or 1024 */
     int concurrent;        /* 1: the short-range sum runs on a second stream of the context,
                               concurrently with the grid stages (forked after binning,

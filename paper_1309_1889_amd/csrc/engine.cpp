@@ -751,8 +751,8 @@ int msm_get_tuning(const msm_ctx *c, msm_tuning *t)
 int msm_set_tuning(msm_ctx *c, const msm_tuning *t)
 {
     if (!c || !t) return MSM_ERR_ARG;
-    if (t->pair_waves != 1 && t->pair_waves != 2 && t->pair_waves != 3 && t->pair_waves != 4 && t->pair_waves != 8 &&
-        t->pair_waves != 16)
+    if (t->pair_waves != 1 && t->pair_waves != 2 && t->pair_waves != 3 && t->pair_waves != 4 && t->pair_waves != 5 &&
+        t->pair_waves != 6 && t->pair_waves != 8 && t->pair_waves != 16)
         return MSM_ERR_ARG;
     if (t->stencil_threads != 256 && t->stencil_threads != 1024) return MSM_ERR_ARG;
     if (t->concurrent != 0 && t->concurrent != 1) return MSM_ERR_ARG;
@@ -796,7 +796,7 @@ int msm_autotune(msm_ctx *c, int nsys, const int64_t *offsets, const double *dom
     };
     msm_tuning best = start;
     double best_ms = 1e300;
-    for (int pw : {1, 2, 3, 4, 8, 16})
+    for (int pw : {1, 2, 3, 4, 5, 6, 8, 16})
         for (int st : {256, 1024}) {
             if (rc) break;
             c->mc.pair_waves = pw;

@@ -87,7 +87,8 @@ struct MethodConst {
     int reach;                 // stencil reach R: largest integer with R < 2a/h
     int pair_waves;            // waves per 64-atom group in the pair kernel: 4, 8 or 16; 1: 16-atom sub-groups;
                                // 2: 8-atom clusters with bounding-box candidate filtering;
-                               // 3: two such clusters per wave sharing one candidate stream
+                               // 3: two such clusters per wave sharing one candidate stream;
+                               // 5, 6: one 16-atom (5) or 32-atom (6) cluster per wave
     int stencil_threads;       // threads per stencil tile: 256 or 1024
 };
 

@@ -478,38 +478,36 @@ __global__ __launch_bounds__(kSubLanes * kWave) void k_pair_sub(DevPlan p, const
     }
 }
 
-// Cluster form (pair_waves = 2), in two kernels.
+// Cluster form (pair_waves = 2, 3, 5, 6), in two kernels, for clusters of
+// CA = 8, 16 or 32 atoms.
 //
-// k_clusters: one wave per 64-atom group splits the group into 8 clusters of
-// 8 atoms by median cuts (k-d order: halve along the longest extent of the
-// group, then of each half, then of each quarter), which gives compact boxes
-// whatever the group's shape, and writes the cluster order.
+// k_clusters: one wave per 64-atom group splits the group into 64 / CA
+// clusters of CA atoms by median cuts (k-d order: halve along the longest
+// extent of the group, then of each half, and so on), which gives compact
+// boxes whatever the group's shape, and writes the cluster order.
 //
-// k_pair_cl: one wave per cluster, eight lanes per atom (lane = 8 slot +
+// k_pair_cl: one wave per cluster, 64 / CA lanes per atom (lane = CA slot +
 // atom). The wave lays out the cell-row pieces that can reach its cluster's
 // box (each clipped to the chord the cutoff sphere leaves its row) as one
 // stream, 64 pieces at a time, with a table in LDS from stream position to
 // atom; it loads the stream 64 candidates at a time (the next chunk is in
 // flight while the current one is used), keeps those whose distance to the
 // box is below the cutoff (a ballot and a prefix count give each its place in
-// a ring in LDS), and evaluates the ring 8 candidates per step, one per slot,
-// whenever it holds 32. More than half of the evaluated lane pairs are inside
-// the cutoff, against a fifth in the forms above. The waves share nothing.
-// The eight partial sums of an atom are added across its lanes in a fixed
-// order.
-constexpr int kClAtoms = 8;                    // atoms per cluster
-constexpr int kClSlots = kWave / kClAtoms;     // candidates per step: 8
+// a ring in LDS), and evaluates the ring 64 / CA candidates per step, one per
+// slot, whenever it holds four steps' worth. With 8-atom clusters more than
+// half of the evaluated lane pairs are inside the cutoff, against a fifth in
+// the forms above; larger clusters keep more candidates per box but share the
+// cost of building the stream among more atoms. The waves share nothing. The
+// partial sums of an atom are added across its lanes in a fixed order.
 constexpr int kClUnroll = 4;                   // steps per evaluated block
-constexpr int kClBlock = kClSlots * kClUnroll; // candidates per block: 32
-constexpr int kClRing = 128;                   // ring capacity (a multiple of kClBlock, power of two)
+constexpr int kClRing = 128;                   // ring capacity (a multiple of kBlock, power of two)
 constexpr int kClMap = 512;                    // stream positions with a table entry
 constexpr int kClWgWaves = 4;                  // waves per workgroup (independent)
 
-template <typename T> __device__ inline T sum_slots(T v)
+template <int CA, typename T> __device__ inline T sum_slots(T v)
 {
-    v += __shfl_xor(v, kClAtoms, kWave);
-    v += __shfl_xor(v, 2 * kClAtoms, kWave);
-    v += __shfl_xor(v, 4 * kClAtoms, kWave);
+#pragma unroll
+    for (int off = CA; off < kWave; off <<= 1) v += __shfl_xor(v, off, kWave);
     return v;
 }
 
@@ -556,7 +554,7 @@ __device__ inline int kd_cut(const vec4_t<T> *grp, int pos, int natoms, int n, i
     return p;
 }
 
-template <typename T>
+template <typename T, int CA>
 __global__ __launch_bounds__(kWave) void k_clusters(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                     int *__restrict__ cluster)
 {
@@ -570,7 +568,7 @@ __global__ __launch_bounds__(kWave) void k_clusters(DevPlan p, const vec4_t<T> *
     grp[lane] = sx[first + min(lane, natoms - 1)];
     __syncthreads();
     int pos = lane;
-    for (int n = kWave; n > kClAtoms; n >>= 1) pos = kd_cut<T>(grp, pos, natoms, n, lane);
+    for (int n = kWave; n > CA; n >>= 1) pos = kd_cut<T>(grp, pos, natoms, n, lane);
     cluster[g * kWave + lane] = pos < natoms ? (int)(first + pos) : -1;
 }
 
@@ -587,7 +585,7 @@ template <typename T, bool MD, int NSUB> struct ClLds {
 // candidate for each cluster whose box is within the cutoff (a ring per
 // cluster): the stream's cost is shared, and each cluster's evaluations stay
 // those of its own box.
-template <typename T, bool MD, bool POT, int KIND, int NSUB>
+template <typename T, bool MD, bool POT, int KIND, int NSUB, int CA>
 __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                                 const int *__restrict__ cstart,
                                                                 const int *__restrict__ cluster,
@@ -595,16 +593,18 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
                                                                 const vec4_t<T> *__restrict__ saux,
                                                                 vec4_t<T> *__restrict__ ljout)
 {
+    constexpr int kSlots = kWave / CA;          // candidates per step
+    constexpr int kBlock = kSlots * kClUnroll;  // candidates per evaluated block
     __shared__ ClLds<T, MD, NSUB> L;
     const int lane = threadIdx.x % kWave;
     const int wv = uni((int)(threadIdx.x / kWave));
     // clusters of neighbouring groups share candidates: keep them on one XCD's L2
     const int64_t c = (xcd_remap(blockIdx.x, gridDim.x) * kClWgWaves + wv) * NSUB;   // first cluster
-    if (c >= p.ngroups * (kWave / kClAtoms)) return;
-    const int me = lane % kClAtoms, slot = lane / kClAtoms;
-    const int m0 = uni(cluster[c * kClAtoms]);
+    if (c >= p.ngroups * (kWave / CA)) return;
+    const int me = lane % CA, slot = lane / CA;
+    const int m0 = uni(cluster[c * CA]);
     if (m0 < 0) return;   // clusters of absent atoms (the last group of a system)
-    const int64_t g = c / (kWave / kClAtoms);
+    const int64_t g = c / (kWave / CA);
     const int s = find_segment(p.group_prefix, p.nsys, g);
     const SysPlan &P = p.sys[s];
     bool on[NSUB], valid[NSUB];
@@ -613,16 +613,16 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
     T bx_lo[NSUB], bx_hi[NSUB], by_lo[NSUB], by_hi[NSUB], bz_lo[NSUB], bz_hi[NSUB];
 #pragma unroll
     for (int sc = 0; sc < NSUB; ++sc) {
-        const int first = uni(cluster[(c + sc) * kClAtoms]);
+        const int first = uni(cluster[(c + sc) * CA]);
         on[sc] = first >= 0;   // uniform
-        const int mi = cluster[(c + sc) * kClAtoms + me];
+        const int mi = cluster[(c + sc) * CA + me];
         valid[sc] = mi >= 0;
         i[sc] = valid[sc] ? mi : (on[sc] ? first : m0);
         ai[sc] = sx[i[sc]];
         if (MD) xi[sc] = saux[i[sc]];
-        bx_lo[sc] = uni(seg_min(ai[sc].x, kClAtoms)), bx_hi[sc] = uni(seg_max(ai[sc].x, kClAtoms));
-        by_lo[sc] = uni(seg_min(ai[sc].y, kClAtoms)), by_hi[sc] = uni(seg_max(ai[sc].y, kClAtoms));
-        bz_lo[sc] = uni(seg_min(ai[sc].z, kClAtoms)), bz_hi[sc] = uni(seg_max(ai[sc].z, kClAtoms));
+        bx_lo[sc] = uni(seg_min(ai[sc].x, CA)), bx_hi[sc] = uni(seg_max(ai[sc].x, CA));
+        by_lo[sc] = uni(seg_min(ai[sc].y, CA)), by_hi[sc] = uni(seg_max(ai[sc].y, CA));
+        bz_lo[sc] = uni(seg_min(ai[sc].z, CA)), bz_hi[sc] = uni(seg_max(ai[sc].z, CA));
     }
     // the stream covers the box of the clusters together
     T bminx = bx_lo[0], bmaxx = bx_hi[0], bminy = by_lo[0], bmaxy = by_hi[0], bminz = bz_lo[0], bmaxz = bz_hi[0];
@@ -665,14 +665,14 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
         vec4_t<T> aj[kClUnroll], xj[kClUnroll];
 #pragma unroll
         for (int v = 0; v < kClUnroll; ++v) {
-            aj[v] = ring[e0 + kClSlots * v];
-            xj[v] = MD ? raux[MD ? e0 + kClSlots * v : 0] : aj[v];
+            aj[v] = ring[e0 + kSlots * v];
+            xj[v] = MD ? raux[MD ? e0 + kSlots * v : 0] : aj[v];
         }
 #pragma unroll
         for (int v = 0; v < kClUnroll; ++v)
             pair_term<T, MD, POT, KIND>(ai[sc], xi[sc], aj[v], xj[v], k, fx[sc], fy[sc], fz[sc], u[sc], lx[sc],
                                         ly[sc], lz[sc], le[sc]);
-        head[sc] += kClBlock;
+        head[sc] += kBlock;
     };
     for (int ib = 0; ib < nitems; ib += kWave) {
         const int q = ib + lane;   // this lane's item
@@ -758,14 +758,14 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int sc = 0; sc < NSUB; ++sc)
-                while (tail[sc] - head[sc] >= kClBlock) eval_block(sc);
+                while (tail[sc] - head[sc] >= kBlock) eval_block(sc);
             __builtin_amdgcn_wave_barrier();
         }
     }
 #pragma unroll
     for (int sc = 0; sc < NSUB; ++sc) {
         if (tail[sc] > head[sc]) {   // the last partial block, padded with a far-away atom
-            if (lane < head[sc] + kClBlock - tail[sc]) {
+            if (lane < head[sc] + kBlock - tail[sc]) {
                 vec4_t<T> far;
                 far.x = far.y = far.z = T(1e18);
                 far.w = T(0);
@@ -775,15 +775,15 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
             __builtin_amdgcn_wave_barrier();
             eval_block(sc);
         }
-        fx[sc] = sum_slots(fx[sc]);
-        fy[sc] = sum_slots(fy[sc]);
-        fz[sc] = sum_slots(fz[sc]);
-        if (POT) u[sc] = sum_slots(u[sc]);
+        fx[sc] = sum_slots<CA>(fx[sc]);
+        fy[sc] = sum_slots<CA>(fy[sc]);
+        fz[sc] = sum_slots<CA>(fz[sc]);
+        if (POT) u[sc] = sum_slots<CA>(u[sc]);
         if (MD) {
-            lx[sc] = sum_slots(lx[sc]);
-            ly[sc] = sum_slots(ly[sc]);
-            lz[sc] = sum_slots(lz[sc]);
-            if (POT) le[sc] = sum_slots(le[sc]);
+            lx[sc] = sum_slots<CA>(lx[sc]);
+            ly[sc] = sum_slots<CA>(ly[sc]);
+            lz[sc] = sum_slots<CA>(lz[sc]);
+            if (POT) le[sc] = sum_slots<CA>(le[sc]);
         }
         if (slot == 0 && valid[sc]) {
             vec4_t<T> o;
@@ -804,25 +804,25 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
     }
 }
 
-template <typename T, int KIND, int NSUB>
+template <typename T, int KIND, int NSUB, int CA>
 static void pair_launch_cl(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot)
 {
-    hipLaunchKernelGGL((k_clusters<T>), dim3((unsigned)p.ngroups), dim3(kWave), 0, s, p, w.sxyzq, w.cluster);
-    const int64_t nclusters = p.ngroups * (kWave / kClAtoms);
+    hipLaunchKernelGGL((k_clusters<T, CA>), dim3((unsigned)p.ngroups), dim3(kWave), 0, s, p, w.sxyzq, w.cluster);
+    const int64_t nclusters = p.ngroups * (kWave / CA);
     const int64_t per_wg = (int64_t)kClWgWaves * NSUB;
     const dim3 grid((unsigned)((nclusters + per_wg - 1) / per_wg)), block(kClWgWaves * kWave);
     const vec4_t<T> *aux = (const vec4_t<T> *)w.saux;
     if (w.saux && pot)
-        hipLaunchKernelGGL((k_pair_cl<T, true, true, KIND, NSUB>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
+        hipLaunchKernelGGL((k_pair_cl<T, true, true, KIND, NSUB, CA>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
                            w.cluster, w.shrt, k, aux, w.shlj);
     else if (w.saux)
-        hipLaunchKernelGGL((k_pair_cl<T, true, false, KIND, NSUB>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
+        hipLaunchKernelGGL((k_pair_cl<T, true, false, KIND, NSUB, CA>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
                            w.cluster, w.shrt, k, aux, w.shlj);
     else if (pot)
-        hipLaunchKernelGGL((k_pair_cl<T, false, true, KIND, NSUB>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
+        hipLaunchKernelGGL((k_pair_cl<T, false, true, KIND, NSUB, CA>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
                            w.cluster, w.shrt, k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
     else
-        hipLaunchKernelGGL((k_pair_cl<T, false, false, KIND, NSUB>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
+        hipLaunchKernelGGL((k_pair_cl<T, false, false, KIND, NSUB, CA>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
                            w.cluster, w.shrt, k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
 }
 
@@ -867,22 +867,23 @@ static void pair_launch(hipStream_t s, const DevPlan &p, const Work<T> &w, const
 template <typename T, int NW>
 static void pair_launch_m(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot, int kind)
 {
-    if (NW == 2 || NW == 3) {   // cluster form: one cluster per wave, or two sharing a stream
-        constexpr int NS = NW == 2 ? 1 : 2;
-        if (kind == kWolf) pair_launch_cl<T, kWolf, NS>(s, p, w, k, pot);
-        else if (kind == kPolyHigh) pair_launch_cl<T, kPolyHigh, NS>(s, p, w, k, pot);
-        else pair_launch_cl<T, kPoly, NS>(s, p, w, k, pot);
-        return;
-    }
-    if (NW == 1) {   // sub-group form
+    if constexpr (NW == 2 || NW == 3 || NW == 5 || NW == 6) {
+        // cluster form: one 8-atom cluster per wave, or two sharing a stream;
+        // one 16-atom or one 32-atom cluster per wave
+        constexpr int NS = NW == 3 ? 2 : 1;
+        constexpr int CA = NW == 5 ? 16 : (NW == 6 ? 32 : 8);
+        if (kind == kWolf) pair_launch_cl<T, kWolf, NS, CA>(s, p, w, k, pot);
+        else if (kind == kPolyHigh) pair_launch_cl<T, kPolyHigh, NS, CA>(s, p, w, k, pot);
+        else pair_launch_cl<T, kPoly, NS, CA>(s, p, w, k, pot);
+    } else if constexpr (NW == 1) {   // sub-group form
         if (kind == kWolf) pair_launch_sub<T, kWolf>(s, p, w, k, pot);
         else if (kind == kPolyHigh) pair_launch_sub<T, kPolyHigh>(s, p, w, k, pot);
         else pair_launch_sub<T, kPoly>(s, p, w, k, pot);
-        return;
+    } else {
+        if (kind == kWolf) pair_launch<T, kWolf, NW>(s, p, w, k, pot);
+        else if (kind == kPolyHigh) pair_launch<T, kPolyHigh, NW>(s, p, w, k, pot);
+        else pair_launch<T, kPoly, NW>(s, p, w, k, pot);
     }
-    if (kind == kWolf) pair_launch<T, kWolf, NW>(s, p, w, k, pot);
-    else if (kind == kPolyHigh) pair_launch<T, kPolyHigh, NW>(s, p, w, k, pot);
-    else pair_launch<T, kPoly, NW>(s, p, w, k, pot);
 }
 
 }  // namespace
@@ -925,6 +926,8 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, co
     case 2: pair_launch_m<T, 2>(s, p, w, k, pot, kind); break;
     case 3: pair_launch_m<T, 3>(s, p, w, k, pot, kind); break;
     case 4: pair_launch_m<T, 4>(s, p, w, k, pot, kind); break;
+    case 5: pair_launch_m<T, 5>(s, p, w, k, pot, kind); break;
+    case 6: pair_launch_m<T, 6>(s, p, w, k, pot, kind); break;
     case 8: pair_launch_m<T, 8>(s, p, w, k, pot, kind); break;
     case 16: pair_launch_m<T, 16>(s, p, w, k, pot, kind); break;
     default: return hipErrorInvalidValue;

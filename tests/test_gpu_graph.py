@@ -79,9 +79,9 @@ def test_autotune_and_tunings_agree():
     x = torch.tensor(w.xyzq(np.float32), device="cuda")
     ref = [t.clone() for t in ctx.energy_forces(x)]
     chosen = ctx.autotune(x, reps=3)
-    assert chosen["pair_waves"] in (1, 2, 3, 4, 8, 16) and chosen["stencil_threads"] in (256, 1024)
+    assert chosen["pair_waves"] in (1, 2, 3, 4, 5, 6, 8, 16) and chosen["stencil_threads"] in (256, 1024)
     assert ctx.tuning() == chosen
-    for pw in (1, 2, 3, 4, 8, 16):
+    for pw in (1, 2, 3, 4, 5, 6, 8, 16):
         for st in (256, 1024):
             ctx.set_tuning(pw, st)
             e, f, p = ctx.energy_forces(x)
@@ -92,7 +92,7 @@ def test_autotune_and_tunings_agree():
             assert rel < 1e-5, (pw, st, rel)
             assert e.item() == pytest.approx(ref[0].item(), rel=1e-6)
     with pytest.raises(msmx.MsmError):
-        ctx.set_tuning(5, 256)
+        ctx.set_tuning(7, 256)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
@@ -109,7 +109,7 @@ def test_concurrent_stages_change_no_bit(precision):
     conc = msmx.MsmContext(w.a, w.h, w.lo, w.hi, precision=precision, max_atoms=w.n)
     seq.set_tuning(concurrent=0)
     assert conc.tuning()["concurrent"] == 1
-    for pw in (1, 2, 3, 4, 8):
+    for pw in (1, 2, 3, 4, 5, 6, 8):
         seq.set_tuning(pair_waves=pw)
         conc.set_tuning(pair_waves=pw)
         ref = seq.energy_forces(x)

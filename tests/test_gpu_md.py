@@ -62,17 +62,19 @@ def test_model_forces_match_oracle(precision):
     if precision == "fp32":
         w = w.as_dtype(np.float32)
     ctx = make_ctx(w, 1.0, 0.25, precision, mass, molid, lj, tri)
-    e, f, _ = ctx.energy_forces(torch.tensor(w.xyzq(dt), device="cuda"))
-    torch.cuda.synchronize()
-    assert ctx.status() == 0
     p = oracle.OracleParams(1.0, 0.25, tuple(w.lo), tuple(w.hi), 0, KE)
     eo, fo = oracle.md_forces(p, oracle.OracleModel(mass, molid, lj, True, tri), w.xyz, w.q)
     tol = 1e-11 if precision == "fp64" else 1e-4
-    assert rel_rms(f.double().cpu().numpy(), fo) < tol
     # the excluded intramolecular terms nearly cancel the full Coulomb energy,
     # so the energy is compared on the scale of the terms that cancel
     scale = abs(oracle.msm(p, w.xyz, w.q)[0])
-    assert abs(e.item() - eo) < tol * scale
+    for pw in (2, 3, 5, 6, 8):   # cluster forms of 8, 16 and 32 atoms; the broadcast form
+        ctx.set_tuning(pair_waves=pw)
+        e, f, _ = ctx.energy_forces(torch.tensor(w.xyzq(dt), device="cuda"))
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        assert rel_rms(f.double().cpu().numpy(), fo) < tol, pw
+        assert abs(e.item() - eo) < tol * scale, pw
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])

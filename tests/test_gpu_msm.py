@@ -221,6 +221,31 @@ def test_water_small_matches_oracle(precision):
     assert e == pytest.approx(eo, rel=tol)
 
 
+@pytest.mark.parametrize("pw", [2, 3, 5, 6])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_cluster_pair_forms_match_oracle(pw, precision):
+    """Each cluster form of the short-range sum (8-atom clusters, one or two
+    per wave; 16- and 32-atom clusters) against the oracle, on a water box
+    whose last 64-atom group is partly empty (999 atoms) and on uniform
+    charges with the coarse cells of h = 0.5."""
+    m = _lib()
+    dt = np.float32 if precision == "fp32" else np.float64
+    tol = 1e-11 if precision == "fp64" else 1e-4
+    for w in (water_box(1001 // 3, (7, 7, 7), (3.3, 3.3, 3.3), seed=31),
+              uniform_pm(777, 3.4, seed=32, a=0.8, h=0.5)):
+        if precision == "fp32":
+            w = w.as_dtype(np.float32)
+        ctx = m.MsmContext(w.a, w.h, w.lo, w.hi, levels=w.levels, precision=precision, max_atoms=w.n)
+        ctx.set_tuning(pair_waves=pw)
+        e, f, p = ctx.energy_forces(torch.tensor(w.xyzq(dt), device="cuda"))
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        eo, fo, po = run_oracle(w)
+        assert rel_rms(f.double().cpu().numpy(), fo) < tol, w.n
+        assert rel_rms(p.double().cpu().numpy(), po) < tol, w.n
+        assert float(e[0].item()) == pytest.approx(eo, rel=tol)
+
+
 @pytest.mark.parametrize("a,h,levels", [(0.8, 0.5, 0), (1.2, 0.25, 1), (1.2, 0.25, 2), (0.6, 0.2, 0),
                                         (1.0, 0.35, 0), (0.3, 0.25, 0), (1.3, 0.25, 0), (1.4, 0.25, 0)])
 def test_fp64_parameter_variants(a, h, levels):
