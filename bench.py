@@ -132,7 +132,7 @@ def traffic_record(kernel_file, kernel_name, workload, form):
     return None if got is None else got.get("bytes_per_launch")
 
 
-def bench_batched(torch, msmx, w32, steps, warmup, slices, single_value):
+def bench_batched(torch, msmx, w32, steps, warmup, slices, single_value, autotune=True):
     """One evaluation of `slices` systems of the water box at once (the fine
     propagator's batch in parareal), and an uneven batch of 8 water boxes of
     9,999 .. 200,001 atoms against evaluating them one by one."""
@@ -154,6 +154,9 @@ def bench_batched(torch, msmx, w32, steps, warmup, slices, single_value):
            torch.empty((slices * n, 3), dtype=torch.float32, device=dev),
            torch.empty(slices * n, dtype=torch.float32, device=dev))
 
+    # the launch configuration is tuned on the batch itself
+    tuning = ctx.autotune(xyzq, offs, reps=3) if autotune else ctx.tuning()
+
     def run():
         ctx.energy_forces(xyzq, offs, energy=out[0], forces=out[1], potentials=out[2])
 
@@ -171,10 +174,11 @@ def bench_batched(torch, msmx, w32, steps, warmup, slices, single_value):
     ms = e0.elapsed_time(e1) / k
     # slice 0 of the batch against the single-system context: identical bits
     one = msmx.MsmContext(w32.a, w32.h, w32.lo, w32.hi, precision="fp32", max_atoms=n)
+    one.set_tuning(**tuning)
     e_1, f_1, _ = one.energy_forces(xyzq[:n].contiguous())
     torch.cuda.synchronize()
     same = bool(torch.equal(f_1, out[1][:n]) and torch.equal(e_1, out[0][:1]))
-    batched = {"systems": slices, "atoms": slices * n, "ms_per_step": ms,
+    batched = {"systems": slices, "atoms": slices * n, "ms_per_step": ms, "tuning": tuning,
                "value": slices * n / (ms * 1e-3), "unit": "atom-steps/s",
                "speedup_vs_single_system": slices * n / (ms * 1e-3) / single_value,
                "slice0_bitwise_equal_to_single": same}
@@ -619,7 +623,8 @@ def main():
     log(f"single system done: fp32 {ms32:.4f} ms per step")
     batched = uneven = par = large = orders = mts = window = None
     if not args.no_batched:
-        batched, uneven = bench_batched(torch, msmx, w32, args.steps, args.warmup, args.slices, value)
+        batched, uneven = bench_batched(torch, msmx, w32, args.steps, args.warmup, args.slices, value,
+                                        autotune=not args.no_autotune)
         log("batched done")
     if not args.no_parareal:
         par = bench_parareal(torch, msmx, args.slices)
