@@ -155,7 +155,7 @@ def bench_batched(torch, msmx, w32, steps, warmup, slices, single_value, autotun
            torch.empty(slices * n, dtype=torch.float32, device=dev))
 
     # the launch configuration is tuned on the batch itself
-    tuning = ctx.autotune(xyzq, offs, reps=3) if autotune else ctx.tuning()
+    tuning = ctx.autotune(xyzq, offs, reps=5) if autotune else ctx.tuning()
 
     def run():
         ctx.energy_forces(xyzq, offs, energy=out[0], forces=out[1], potentials=out[2])
