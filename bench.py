@@ -463,6 +463,7 @@ def bench_large(torch, msmx, steps=100, dt=0.002):
     x = torch.tensor(w.xyzq(np.float32), device=dev)
     out = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float32, device=dev),
            torch.empty(n, dtype=torch.float32, device=dev))
+    tuning = ctx.autotune(x, reps=2)
     ctx.set_graphs(True)
     ms = timed_steps(torch, ctx, x, out, 10, 2)
     ctx.check()
@@ -487,7 +488,7 @@ def bench_large(torch, msmx, steps=100, dt=0.002):
     md.check()
     e0, e1 = ep0.item() + ek0.item(), ep1.item() + ek1.item()
     return {"workload": f"{n} atoms, 30x65x65 nm rigid water, a 1.2 nm, h 0.25 nm, {len(md.grid_shape())} grids, FP32 forces, FP64 state",
-            "eval_ms": ms, "eval_atom_steps_per_s": n / (ms * 1e-3),
+            "eval_ms": ms, "eval_atom_steps_per_s": n / (ms * 1e-3), "eval_tuning": tuning,
             "vv_steps": steps, "dt_ps": dt, "vv_seconds": secs, "vv_atom_steps_per_s": n * steps / secs,
             "energy_start_kj_mol": e0, "energy_end_kj_mol": e1,
             "drift_kj_mol_per_ps": (e1 - e0) / (steps * dt),
