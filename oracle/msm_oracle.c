@@ -27,6 +27,7 @@
 
 #include <math.h>
 #include <omp.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -380,6 +381,21 @@ static void level_potential(const orc_params *p, const plan_t *pl, int k, const 
     long reach = top ? (long)(dm[0] > dm[1] ? (dm[0] > dm[2] ? dm[0] : dm[2]) : (dm[1] > dm[2] ? dm[1] : dm[2]))
                      : (long)ceil(2.0 * p->a / p->h);
     double rcut = ldexp(2.0 * p->a, k);
+    /* g^k at every node offset the sum visits, evaluated once (the values and
+     * the order of the terms are those of evaluating g^k per node pair); an
+     * offset at or beyond 2^{k+1} a below the top level is not a term */
+    const long side = 2 * reach + 1;
+    double *gt = malloc(sizeof(double) * side * side * side);
+    unsigned char *term = malloc((size_t)(side * side * side));
+    for (long dz = -reach; dz <= reach; dz++)
+        for (long dy = -reach; dy <= reach; dy++)
+            for (long dx = -reach; dx <= reach; dx++) {
+                const long t = ((dz + reach) * side + (dy + reach)) * side + (dx + reach);
+                double rx = dx * hk, ry = dy * hk, rz = dz * hk;
+                double r = sqrt(rx * rx + ry * ry + rz * rz);
+                term[t] = top || r < rcut;
+                gt[t] = term[t] ? orc_glevel_m(r, p->a, k, pl->l, smooth_of(p)) : 0.0;
+            }
 #pragma omp parallel for collapse(2) schedule(dynamic)
     for (long z = 0; z < dm[2]; z++)
         for (long y = 0; y < dm[1]; y++)
@@ -391,13 +407,14 @@ static void level_potential(const orc_params *p, const plan_t *pl, int k, const 
                         for (long nx = mx - reach; nx <= mx + reach; nx++) {
                             int64_t g = gidx(pl, k, nx, ny, nz);
                             if (g < 0 || qk[g] == 0.0) continue;
-                            double dx = (nx - mx) * hk, dy = (ny - my) * hk, dz = (nz - mz) * hk;
-                            double r = sqrt(dx * dx + dy * dy + dz * dz);
-                            if (!top && !(r < rcut)) continue;
-                            kadd(&acc, orc_glevel_m(r, p->a, k, pl->l, smooth_of(p)) * qk[g]);
+                            const long t = ((nz - mz + reach) * side + (ny - my + reach)) * side + (nx - mx + reach);
+                            if (!term[t]) continue;
+                            kadd(&acc, gt[t] * qk[g]);
                         }
                 uk[(z * dm[1] + y) * dm[0] + x] = acc.s + acc.c;
             }
+    free(gt);
+    free(term);
 }
 
 /* ---- Section 3, prolongation: u^k_mu = u^{k,cutoff}_mu + sum_nu phi^{k+1}_nu(r^k_mu) u^{k+1}_nu,
@@ -481,14 +498,21 @@ int orc_msm(const orc_params *p, int64_t n, const double *xyz, const double *q,
         ug[k] = malloc(sizeof(double) * pl.size[k]);
     }
 
+    /* ORC_PROGRESS set: a line on stderr after each step of a long evaluation */
+    const int progress = getenv("ORC_PROGRESS") != NULL;
     /* step 1: short-range part */
     short_range(p, n, xyz, q, us, fs);
+    if (progress) fprintf(stderr, "oracle: short-range part of %lld atoms done\n", (long long)n);
     /* step 2: anterpolation */
     anterpolate(p, &pl, n, xyz, q, qg[0]);
+    if (progress) fprintf(stderr, "oracle: anterpolation done\n");
     /* steps 3-4: restriction and lattice cutoff on levels 0 .. l-2 */
     for (int k = 0; k + 1 < l; k++) restrict_level(&pl, k, qg[k], qg[k + 1]);
     /* steps 3-5: lattice cutoff on every level, the top level over all pairs */
-    for (int k = 0; k < l; k++) level_potential(p, &pl, k, qg[k], ug[k]);
+    for (int k = 0; k < l; k++) {
+        level_potential(p, &pl, k, qg[k], ug[k]);
+        if (progress) fprintf(stderr, "oracle: level %d of %d done\n", k, l);
+    }
     if (st)
         for (int k = 0; k < l; k++) {
             if (st->q_grid[k]) memcpy(st->q_grid[k], qg[k], sizeof(double) * pl.size[k]);
