@@ -146,6 +146,35 @@ def _check(code: int, what: str):
     return code
 
 
+def _require(t, name, dtype, device, shape):
+    """Raise ValueError unless ``t`` is a contiguous tensor of ``dtype`` on
+    ``device`` with exactly ``shape`` (the C side cannot check buffer sizes)."""
+    if t is None:
+        return
+    if t.dtype != dtype or t.device != device or not t.is_contiguous() or tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape {tuple(shape)} on {device}; "
+                         f"got {t.dtype} {tuple(t.shape)} on {t.device}"
+                         f"{'' if t.is_contiguous() else ' (not contiguous)'}")
+
+
+def _offsets(offsets, n):
+    """Validated int64 system offsets: start at 0, non-decreasing, end at n."""
+    offs = np.ascontiguousarray(np.asarray([0, n] if offsets is None else offsets, dtype=np.int64))
+    if offs.ndim != 1 or len(offs) < 2 or offs[0] != 0 or offs[-1] != n or np.any(np.diff(offs) < 0):
+        raise ValueError(f"offsets must rise from 0 to the number of atoms ({n})")
+    return offs
+
+
+def _domains(domains, nsys):
+    if domains is None:
+        return None, None
+    dom = np.ascontiguousarray(np.asarray(domains, dtype=np.float64))
+    if dom.size != nsys * 6:
+        raise ValueError(f"domains must hold {nsys} x 6 values")
+    dom = dom.reshape(nsys, 6)
+    return dom, dom.ctypes.data_as(C.POINTER(C.c_double))
+
+
 def _stream_handle(stream):
     import torch
     if stream is None:
@@ -235,13 +264,11 @@ class MsmContext:
 
     def autotune(self, xyzq, offsets=None, domains=None, reps=5):
         """Pick the fastest launch configuration on this batch (msm_autotune)."""
+        self._check_xyzq(xyzq)
         n = xyzq.shape[0]
-        offs = np.ascontiguousarray(np.asarray([0, n] if offsets is None else offsets, dtype=np.int64))
+        offs = _offsets(offsets, n)
         nsys = len(offs) - 1
-        dom_p = None
-        if domains is not None:
-            dom = np.ascontiguousarray(np.asarray(domains, dtype=np.float64).reshape(nsys, 6))
-            dom_p = dom.ctypes.data_as(C.POINTER(C.c_double))
+        dom, dom_p = _domains(domains, nsys)
         t = _Tuning()
         _check(lib().msm_autotune(self._h, nsys, offs.ctypes.data_as(C.POINTER(C.c_int64)), dom_p,
                                   C.c_void_p(xyzq.data_ptr()), int(reps), C.byref(t)), "msm_autotune")
@@ -271,39 +298,41 @@ class MsmContext:
         return [(tuple(org[3 * k:3 * k + 3]), tuple(dim[3 * k:3 * k + 3])) for k in range(n)]
 
     # ------------------------------------------------------------------
+    def _check_xyzq(self, xyzq):
+        if xyzq.dtype != self.dtype or not xyzq.is_cuda or not xyzq.is_contiguous() or xyzq.dim() != 2 \
+                or xyzq.shape[1] != 4:
+            raise ValueError("xyzq must be a contiguous (N, 4) device tensor of the context's precision")
+
     def energy_forces(self, xyzq, offsets=None, domains=None, *, energy=None, forces=None, potentials=None,
                       want=("energy", "forces", "potentials")):
         """Evaluate nsys systems packed in ``xyzq`` (N x 4, contiguous, on the
         context's GPU, in its precision). ``offsets`` (nsys+1 ints) splits the
         atoms into systems (default: one system); ``domains`` (nsys x 6) gives
-        per-system domains. Output tensors are allocated unless passed in.
+        per-system domains. Output tensors are allocated unless passed in;
+        passed-in ones must be contiguous, on xyzq's device, of shape (nsys,)
+        float64, (N, 3) and (N,) in the context's precision.
         Returns (energy[nsys] float64, forces[N,3], potentials[N])."""
         import torch
-        if xyzq.dtype != self.dtype or not xyzq.is_cuda or not xyzq.is_contiguous() or xyzq.dim() != 2 \
-                or xyzq.shape[1] != 4:
-            raise ValueError("xyzq must be a contiguous (N, 4) device tensor of the context's precision")
+        self._check_xyzq(xyzq)
         n = xyzq.shape[0]
-        if offsets is None:
-            offsets = [0, n]
-        offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        offs = _offsets(offsets, n)
         nsys = len(offs) - 1
-        if offs[-1] != n:
-            raise ValueError("offsets must end at the number of atoms")
         dev = xyzq.device
+        _require(energy, "energy", torch.float64, dev, (nsys,))
+        _require(forces, "forces", self.dtype, dev, (n, 3))
+        _require(potentials, "potentials", self.dtype, dev, (n,))
         if energy is None and "energy" in want:
             energy = torch.empty(nsys, dtype=torch.float64, device=dev)
         if forces is None and "forces" in want:
             forces = torch.empty((n, 3), dtype=self.dtype, device=dev)
         if potentials is None and "potentials" in want:
             potentials = torch.empty(n, dtype=self.dtype, device=dev)
-        dom_p = None
-        if domains is not None:
-            dom = np.ascontiguousarray(np.asarray(domains, dtype=np.float64).reshape(nsys, 6))
-            dom_p = dom.ctypes.data_as(C.POINTER(C.c_double))
+        dom, dom_p = _domains(domains, nsys)
         ptr = lambda t: None if t is None else C.c_void_p(t.data_ptr())  # noqa: E731
         rc = lib().msm_energy_forces(self._h, nsys, offs.ctypes.data_as(C.POINTER(C.c_int64)), dom_p,
                                      ptr(xyzq), ptr(energy), ptr(forces), ptr(potentials))
         _check(rc, "msm_energy_forces")
+        self._last_offsets = offs.copy()
         return energy, forces, potentials
 
     def debug_stages(self, sys=0, domain=None):
@@ -325,7 +354,15 @@ class MsmContext:
         return out, ptrs
 
     def stages(self, n_sys_atoms, sys=0, domain=None):
+        """Intermediate results (msm_debug_stages) of system ``sys`` of the
+        last energy_forces call; ``n_sys_atoms`` must be that system's size."""
         import torch
+        last = getattr(self, "_last_offsets", None)
+        if last is None or not 0 <= sys < len(last) - 1:
+            raise ValueError("stages: no evaluation of that system yet")
+        if int(n_sys_atoms) != int(last[sys + 1] - last[sys]):
+            raise ValueError(f"stages: system {sys} has {int(last[sys + 1] - last[sys])} atoms, "
+                             f"not {n_sys_atoms}")
         out, ptrs = self.debug_stages(sys, domain)
         dev = out["q_grid"][0].device
         us = torch.zeros(n_sys_atoms, dtype=torch.float64, device=dev)
@@ -337,13 +374,21 @@ class MsmContext:
         out["f_short"] = fs
         return out
 
-
     # ------------------------------------------------------------------
     # dynamics
     # ------------------------------------------------------------------
     def bind_model(self, period, molid=None, lj=None, rigid=False, tri=(0.0, 0.0, 0.0), tol=0.0):
         """Bind a molecular model (see msm_md_model): ``molid`` int32 and ``lj``
         float64 (period, 2) device tensors, or None."""
+        import torch
+        if molid is not None:
+            _require(molid, "molid", torch.int32, molid.device, (int(period),))
+            if not molid.is_cuda:
+                raise ValueError("molid must be a device tensor")
+        if lj is not None:
+            _require(lj, "lj", torch.float64, lj.device, (int(period), 2))
+            if not lj.is_cuda:
+                raise ValueError("lj must be a device tensor")
         m = _Model()
         m.period = int(period)
         m.molid_dev = None if molid is None else molid.data_ptr()
@@ -365,16 +410,11 @@ class MsmContext:
                     or t.shape[1] != 4:
                 raise ValueError("vv_run expects contiguous float64 (N, 4) device tensors")
         n = xyzq.shape[0]
-        if vel.shape[0] != n:
-            raise ValueError("xyzq and vel differ in length")
-        if offsets is None:
-            offsets = [0, n]
-        offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        if vel.shape[0] != n or vel.device != xyzq.device:
+            raise ValueError("xyzq and vel differ in length or device")
+        offs = _offsets(offsets, n)
         nsys = len(offs) - 1
-        dom_p = None
-        if domains is not None:
-            dom = np.ascontiguousarray(np.asarray(domains, dtype=np.float64).reshape(nsys, 6))
-            dom_p = dom.ctypes.data_as(C.POINTER(C.c_double))
+        dom, dom_p = _domains(domains, nsys)
         ep = ek = None
         if energies:
             ep = torch.empty(nsys, dtype=torch.float64, device=xyzq.device)
@@ -394,14 +434,11 @@ class MsmContext:
                     or t.shape[1] != 4:
                 raise ValueError("vv_mts_run expects contiguous float64 (N, 4) device tensors")
         n = xyzq.shape[0]
-        if offsets is None:
-            offsets = [0, n]
-        offs = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+        if vel.shape[0] != n or vel.device != xyzq.device:
+            raise ValueError("xyzq and vel differ in length or device")
+        offs = _offsets(offsets, n)
         nsys = len(offs) - 1
-        dom_p = None
-        if domains is not None:
-            dom = np.ascontiguousarray(np.asarray(domains, dtype=np.float64).reshape(nsys, 6))
-            dom_p = dom.ctypes.data_as(C.POINTER(C.c_double))
+        dom, dom_p = _domains(domains, nsys)
         ep = ek = None
         if energies:
             ep = torch.empty(nsys, dtype=torch.float64, device=xyzq.device)
@@ -420,8 +457,13 @@ def parareal(fine, coarse, charges, invmass, state0, *, nslices, kmax, tol, step
     tensors. Returns (lambda[(nslices+1), natoms, 6], report dict, return code)."""
     import torch
     n = state0.shape[0]
+    dev = state0.device
+    _require(state0, "state0", torch.float64, dev, (n, 6))
+    _require(charges, "charges", torch.float64, dev, (n,))
+    _require(invmass, "invmass", torch.float64, dev, (n,))
     if lam is None:
-        lam = torch.empty((nslices + 1, n, 6), dtype=torch.float64, device=state0.device)
+        lam = torch.empty((nslices + 1, n, 6), dtype=torch.float64, device=dev)
+    _require(lam, "lam", torch.float64, dev, (nslices + 1, n, 6))
     pp = _PararealParams()
     pp.nslices, pp.kmax, pp.tol = int(nslices), int(kmax), float(tol)
     pp.steps_f, pp.dt_f, pp.steps_g, pp.dt_g = int(steps_f), float(dt_f), int(steps_g), float(dt_g)
@@ -442,12 +484,13 @@ def parareal_window(fine, coarse, charges, invmass, lam, ring, state, *, width, 
     (width, natoms, 6) and ``state`` (a WindowState). ``charges`` and
     ``invmass`` are (natoms,) float64 device tensors. Returns the return code:
     MSM_OK (0) when every slice is final, 1 when stopped after max_iters."""
-    for t in (charges, invmass, lam, ring):
-        if t.dtype != _torch_f64() or not t.is_contiguous():
-            raise ValueError("parareal_window: float64 contiguous device tensors expected")
-    n = lam.shape[1]
-    if lam.shape[2] != 6 or tuple(ring.shape) != (width, n, 6) or charges.numel() != n or invmass.numel() != n:
-        raise ValueError("parareal_window: shapes do not match")
+    if lam.dim() != 3 or lam.shape[2] != 6:
+        raise ValueError("parareal_window: lam must be (nslices + 1, natoms, 6)")
+    n, dev, f64 = lam.shape[1], lam.device, _torch_f64()
+    _require(lam, "lam", f64, dev, tuple(lam.shape))
+    _require(ring, "ring", f64, dev, (width, n, 6))
+    _require(charges, "charges", f64, dev, (n,))
+    _require(invmass, "invmass", f64, dev, (n,))
     pp = _WindowParams()
     pp.nslices, pp.width, pp.max_iters = lam.shape[0] - 1, int(width), int(max_iters)
     pp.pipeline, pp.chunk, pp.tol = int(bool(pipeline)), int(chunk), float(tol)

@@ -118,3 +118,33 @@ def test_window_run_validates_arguments_before_touching_a_device():
     st = binding.WindowState()
     L = binding.lib()
     assert L.parareal_window_run(None, None, C.byref(pp), 3, None, None, None, None, C.byref(st)) == -1
+
+
+def test_binding_validates_tensors_and_offsets():
+    """The C side cannot check buffer sizes, so the binding rejects tensors
+    of the wrong dtype, shape, device or layout and offsets that do not
+    partition the atoms, before any library call."""
+    import numpy as np
+    import torch
+    from paper_1309_1889_amd import binding
+    cpu = torch.device("cpu")
+    binding._require(None, "x", torch.float32, cpu, (3,))
+    binding._require(torch.zeros(3), "x", torch.float32, cpu, (3,))
+    with pytest.raises(ValueError):
+        binding._require(torch.zeros(3, dtype=torch.float64), "x", torch.float32, cpu, (3,))
+    with pytest.raises(ValueError):
+        binding._require(torch.zeros(4), "x", torch.float32, cpu, (3,))
+    with pytest.raises(ValueError):
+        binding._require(torch.zeros(3, 2).t(), "x", torch.float32, cpu, (2, 3))
+    if torch.cuda.is_available():
+        with pytest.raises(ValueError):
+            binding._require(torch.zeros(3), "x", torch.float32, torch.device("cuda", 0), (3,))
+    assert list(binding._offsets(None, 5)) == [0, 5]
+    assert list(binding._offsets([0, 2, 5], 5)) == [0, 2, 5]
+    for bad in ([1, 5], [0, 4], [0, 3, 2, 5], [0]):
+        with pytest.raises(ValueError):
+            binding._offsets(bad, 5)
+    dom, ptr = binding._domains(np.zeros(12), 2)
+    assert dom.shape == (2, 6) and ptr is not None
+    with pytest.raises(ValueError):
+        binding._domains(np.zeros(6), 2)
