@@ -133,6 +133,37 @@ int msm_energy_forces(msm_ctx *ctx, int nsys, const int64_t *offsets_host,
                       const double *domains_host, const void *xyzq_dev,
                       double *energy_dev, void *forces_dev, void *potentials_dev);
 
+/* Allocation-free evaluation, for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc): msm_energy_forces for one system of natoms atoms on the
+ * current device, without a context. Every work array (cells, sorted atoms,
+ * all grids, the stencil and plan tables) lives in one static device array
+ * of MSM_NOALLOC_SCRATCH_MIB MiB per device, which the library holds from
+ * the first call on that device until the process ends; the call allocates
+ * no device or pinned memory (the first call on a device looks the array up
+ * and reserves the host bookkeeping once).
+ *  params     as for msm_setup; max_atoms and max_systems are ignored.
+ *             At most MSM_NOALLOC_MAX_LEVELS grids.
+ *  stream     hipStream_t the work is enqueued on (NULL: the null stream).
+ *  xyzq_dev, energy_dev (1 double), forces_dev, potentials_dev: as for
+ *             msm_energy_forces with one system; outputs may be NULL.
+ *  status_dev NULL or one int32 that receives, when the work has run,
+ *             MSM_OK, MSM_ERR_DOMAIN or MSM_ERR_NONFINITE (msm_get_status's
+ *             codes for this evaluation).
+ * Returns MSM_ERR_CAPACITY when the system's work arrays and tables do not
+ * fit the array (a 99,999-atom water box at h = 0.25 nm fits in both
+ * precisions), MSM_ERR_ARG/UNSUPPORTED as msm_setup, MSM_ERR_HIP.
+ * Results equal msm_energy_forces with the default launch configuration.
+ * Every call on a device uses the same array and clears it first: calls that
+ * overlap on one device (on different streams, or from different host
+ * threads before the earlier work has run) race and give undefined results;
+ * the host side of concurrent calls is serialised. */
+#define MSM_NOALLOC_SCRATCH_MIB 64
+#define MSM_NOALLOC_MAX_LEVELS 8
+int msm_energy_forces_noalloc(const msm_params *params, void *stream, int64_t natoms,
+                              const void *xyzq_dev, double *energy_dev, void *forces_dev,
+                              void *potentials_dev, int32_t *status_dev);
+
 /* Launch configuration of the two heaviest kernels, and of the stream use of
  * an evaluation. Every configuration is deterministic, but pair_waves and
  * stencil_threads add the same terms in different orders, so results of

@@ -12,6 +12,7 @@ from .binding import (  # noqa: F401
     MSM_FP64,
     MsmError,
     MsmContext,
+    energy_forces_noalloc,
     lib,
     lib_path,
     parareal,

@@ -123,6 +123,8 @@ def lib():
         L.msm_vv_mts_run.argtypes = [vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_double), vp, vp, C.c_int,
                                      C.c_int, C.c_double, vp, vp]
         L.msm_vv_mts_run.restype = C.c_int
+        L.msm_energy_forces_noalloc.argtypes = [C.POINTER(_Params), vp, C.c_int64, vp, vp, vp, vp, vp]
+        L.msm_energy_forces_noalloc.restype = C.c_int
         L.parareal_run.argtypes = [vp, vp, C.POINTER(_PararealParams), C.c_int64, vp, vp, vp, vp,
                                    C.POINTER(_PararealReport)]
         L.parareal_run.restype = C.c_int
@@ -448,6 +450,61 @@ class MsmContext:
                                     ptr(vel), int(nouter), int(ninner), float(dt), ptr(ep), ptr(ek)),
                "msm_vv_mts_run")
         return ep, ek
+
+
+def _params(a, h, lo, hi, levels, precision, ke, max_atoms, max_systems, method, smoothing, basis, alpha):
+    if method not in METHODS:
+        raise ValueError(f"method must be one of {sorted(METHODS)}")
+    if precision not in ("fp32", "fp64"):
+        raise ValueError("precision must be 'fp32' or 'fp64'")
+    p = _Params()
+    p.a, p.h, p.levels = float(a), float(h), int(levels)
+    p.precision = MSM_FP32 if precision == "fp32" else MSM_FP64
+    for d in range(3):
+        p.lo[d] = float(lo[d])
+        p.hi[d] = float(hi[d])
+    p.coulomb_k = float(ke)
+    p.max_atoms = int(max_atoms)
+    p.max_systems = int(max_systems)
+    p.method = METHODS[method]
+    p.smoothing = int(smoothing)
+    p.basis = int(basis)
+    p.alpha = float(alpha)
+    return p
+
+
+def energy_forces_noalloc(xyzq, a, h, lo, hi, *, levels=0, precision="fp32", ke=138.935458, method="msm",
+                          smoothing=2, basis=3, alpha=0.0, energy=None, forces=None, potentials=None,
+                          status=None, stream=None):
+    """One evaluation of one system without a context and without device
+    allocation in the library (msm_energy_forces_noalloc). Output tensors are
+    allocated here unless passed in; ``status`` (one int32 on the device)
+    receives the status code of the evaluation. Returns (energy[1], forces,
+    potentials, status)."""
+    import torch
+    dtype = torch.float32 if precision == "fp32" else torch.float64
+    if xyzq.dtype != dtype or not xyzq.is_cuda or not xyzq.is_contiguous() or xyzq.dim() != 2 \
+            or xyzq.shape[1] != 4:
+        raise ValueError("xyzq must be a contiguous (N, 4) device tensor of the given precision")
+    n, dev = xyzq.shape[0], xyzq.device
+    _require(energy, "energy", torch.float64, dev, (1,))
+    _require(forces, "forces", dtype, dev, (n, 3))
+    _require(potentials, "potentials", dtype, dev, (n,))
+    _require(status, "status", torch.int32, dev, (1,))
+    if energy is None:
+        energy = torch.empty(1, dtype=torch.float64, device=dev)
+    if forces is None:
+        forces = torch.empty((n, 3), dtype=dtype, device=dev)
+    if potentials is None:
+        potentials = torch.empty(n, dtype=dtype, device=dev)
+    if status is None:
+        status = torch.empty(1, dtype=torch.int32, device=dev)
+    p = _params(a, h, lo, hi, levels, precision, ke, n, 1, method, smoothing, basis, alpha)
+    ptr = lambda t: C.c_void_p(t.data_ptr())  # noqa: E731
+    _check(lib().msm_energy_forces_noalloc(C.byref(p), _stream_handle(stream), n, ptr(xyzq), ptr(energy),
+                                           ptr(forces), ptr(potentials), ptr(status)),
+           "msm_energy_forces_noalloc")
+    return energy, forces, potentials, status
 
 
 def parareal(fine, coarse, charges, invmass, state0, *, nslices, kmax, tol, steps_f, dt_f, steps_g, dt_g,

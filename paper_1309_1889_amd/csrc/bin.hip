@@ -10,6 +10,7 @@
 // arrival order of the histogram atomics, so every evaluation is bitwise
 // reproducible.
 #include <algorithm>
+#include <cstring>
 
 #include "launch.h"
 
@@ -22,6 +23,16 @@ __global__ void k_fill_i32(int *p, int64_t n, int v)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
+}
+
+// put_bytes: one launch writes up to kPutWords words carried in its arguments
+constexpr int kPutWords = 512;
+struct PutChunk {
+    uint32_t w[kPutWords];
+};
+__global__ __launch_bounds__(kPutWords) void k_put(uint32_t *__restrict__ dst, PutChunk c, int n)
+{
+    if ((int)threadIdx.x < n) dst[threadIdx.x] = c.w[threadIdx.x];
 }
 
 template <typename T> __global__ void k_fill_t(T *p, int64_t n, T v)
@@ -264,6 +275,19 @@ hipError_t fill_i32(hipStream_t s, int *p, int64_t n, int v)
 {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_i32, dim3(nblocks(n, 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t put_bytes(hipStream_t s, void *dst, const void *src_host, size_t bytes)
+{
+    const uint32_t *src = (const uint32_t *)src_host;
+    const size_t nw = bytes / 4;
+    for (size_t o = 0; o < nw; o += kPutWords) {
+        PutChunk c;
+        const int n = (int)std::min<size_t>(kPutWords, nw - o);
+        std::memcpy(c.w, src + o, sizeof(uint32_t) * n);
+        hipLaunchKernelGGL(k_put, dim3(1), dim3(kPutWords), 0, s, (uint32_t *)dst + o, c, n);
+    }
     return hipGetLastError();
 }
 

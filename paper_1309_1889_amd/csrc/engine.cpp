@@ -170,14 +170,20 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
         if (offsets[s + 1] < offsets[s]) return MSM_ERR_ARG;
     if (offsets[nsys] > c->prm.max_atoms) return MSM_ERR_CAPACITY;
 
-    std::vector<SysPlan> sys(nsys);
+    // host tables in the context's own vectors: their capacity persists, so
+    // a batch shape seen before allocates no host memory
+    PlanScratch &ps = c->ps;
+    std::vector<SysPlan> &sys = ps.sys;
+    sys.resize(nsys);
     const int W = nsys + 1;
-    std::vector<int64_t> atom_p(W), group_p(W), cell_p(W), iblk_p(W), top_p(W), ant_p(W);
-    std::vector<int64_t> node_p((size_t)kMaxLevels * W);
+    std::vector<int64_t> &atom_p = ps.atom_p, &group_p = ps.group_p, &cell_p = ps.cell_p, &iblk_p = ps.iblk_p,
+                         &top_p = ps.top_p, &ant_p = ps.ant_p, &node_p = ps.node_p, &rxy_p = ps.rxy_p,
+                         &pxy_p = ps.pxy_p, &tile_p = ps.tile_p;
+    for (auto *v : {&atom_p, &group_p, &cell_p, &iblk_p, &top_p, &ant_p, &rxy_p, &pxy_p}) v->assign(W, 0);
+    node_p.assign((size_t)kMaxLevels * W, 0);
     int64_t cells = 0, q = 0, u = 0, groups = 0, iblk = 0, top = 0, ant = 0;
     int64_t tsz = 0, wsz = 0, rxy = 0, pxy = 0;
     bool composite = true;
-    std::vector<int64_t> rxy_p(W), pxy_p(W);
     int64_t nodes[kMaxLevels] = {0};
     int maxlev = 1, top_d2 = 0;
     for (int s = 0; s < nsys; s++) {
@@ -255,20 +261,22 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     // |m| <= s_k with s_1 = 2S-1 and s_{k+1} = s_k + 2^k s_1 (exact dyadic
     // rationals: products and sums of the half-integer basis values)
     const int S = (basis_degree(c->prm) + 1) / 2, s1 = 2 * S - 1;
-    std::vector<double> phi_tab;
+    std::vector<double> &phi_tab = ps.phi_tab;
+    phi_tab.clear();
     int phi_off[kMaxLevels] = {0}, phi_s[kMaxLevels] = {0};
-    {
-        std::vector<double> p1(2 * s1 + 1);
+    if (composite) {   // only the composite transfers read the filters
+        std::vector<double> &p1 = ps.p1, &cur = ps.cur, &nxt = ps.nxt;
+        p1.assign(2 * s1 + 1, 0.0);
         for (int m = -s1; m <= s1; m++)
             p1[m + s1] = m == 0 ? 1.0 : ((m & 1) ? (S == 3 ? basis5(0.5 * m) : basis(0.5 * m)) : 0.0);
-        std::vector<double> cur = p1;
+        cur = p1;
         int sk = s1;
         for (int k = 1; k < maxlev && k < kMaxLevels; k++) {
             phi_off[k] = (int)phi_tab.size();
             phi_s[k] = sk;
             phi_tab.insert(phi_tab.end(), cur.begin(), cur.end());
             const int sn = sk + (1 << k) * s1;
-            std::vector<double> nxt(2 * sn + 1, 0.0);
+            nxt.assign(2 * sn + 1, 0.0);
             for (int m = -sn; m <= sn; m++) {
                 double acc = 0;
                 for (int j = -s1; j <= s1; j++) {
@@ -292,7 +300,7 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     const int esz = c->prm.precision == MSM_FP32 ? 4 : 8;
     const int txy = stencil_tile_xy(esz, c->mc.reach), tz = stencil_tile_z(esz, c->mc.reach);
     const int nseg = (maxlev - 1) * nsys;
-    std::vector<int64_t> tile_p((size_t)nseg + 1);
+    tile_p.assign((size_t)nseg + 1, 0);
     int64_t tiles = 0;
     for (int k = 0; k + 1 < maxlev; k++)
         for (int s = 0; s < nsys; s++) {
@@ -320,7 +328,15 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     const size_t o_node = place(sizeof(int64_t) * kMaxLevels * W), o_tile = place(sizeof(int64_t) * (nseg + 1));
     const size_t o_rxy = place(sizeof(int64_t) * W), o_pxy = place(sizeof(int64_t) * W);
     const size_t o_phi = place(sizeof(double) * std::max<size_t>(phi_tab.size(), 1));
-    if (off > c->plan_cap) {
+    char *h = nullptr;
+    int slot = -1;
+    if (c->fixed_plan) {
+        // allocation-free contexts: the tables go to a fixed device region
+        // through kernel arguments, from the context's host image
+        if (off > c->fixed_plan_cap) return MSM_ERR_CAPACITY;
+        if (ps.blob.size() < off) ps.blob.resize(off);
+        h = ps.blob.data();
+    } else if (off > c->plan_cap) {
         // the current tables may still be read by queued work
         if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
         if (c->plan_dev) (void)hipFree(c->plan_dev);
@@ -334,13 +350,15 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
         c->plan_cap = off;
         for (bool &l : c->plan_ev_live) l = false;
     }
-    const int slot = c->plan_slot;
-    c->plan_slot = (slot + 1) % msm_ctx::kPlanStage;
-    if (!c->plan_ev[slot] && hipEventCreateWithFlags(&c->plan_ev[slot], hipEventDisableTiming) != hipSuccess)
-        return MSM_ERR_HIP;
-    // the slot's previous copy must have run before it is overwritten
-    if (c->plan_ev_live[slot] && hipEventSynchronize(c->plan_ev[slot]) != hipSuccess) return MSM_ERR_HIP;
-    char *h = c->plan_host + (size_t)slot * c->plan_cap;
+    if (!c->fixed_plan) {
+        slot = c->plan_slot;
+        c->plan_slot = (slot + 1) % msm_ctx::kPlanStage;
+        if (!c->plan_ev[slot] && hipEventCreateWithFlags(&c->plan_ev[slot], hipEventDisableTiming) != hipSuccess)
+            return MSM_ERR_HIP;
+        // the slot's previous copy must have run before it is overwritten
+        if (c->plan_ev_live[slot] && hipEventSynchronize(c->plan_ev[slot]) != hipSuccess) return MSM_ERR_HIP;
+        h = c->plan_host + (size_t)slot * c->plan_cap;
+    }
     std::memcpy(h + o_sys, sys.data(), sizeof(SysPlan) * nsys);
     std::memcpy(h + o_atom, atom_p.data(), sizeof(int64_t) * W);
     std::memcpy(h + o_group, group_p.data(), sizeof(int64_t) * W);
@@ -353,12 +371,16 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     std::memcpy(h + o_rxy, rxy_p.data(), sizeof(int64_t) * W);
     std::memcpy(h + o_pxy, pxy_p.data(), sizeof(int64_t) * W);
     if (!phi_tab.empty()) std::memcpy(h + o_phi, phi_tab.data(), sizeof(double) * phi_tab.size());
-    if (hipMemcpyAsync(c->plan_dev, h, off, hipMemcpyHostToDevice, c->stream) != hipSuccess) return MSM_ERR_HIP;
-    if (hipEventRecord(c->plan_ev[slot], c->stream) != hipSuccess) return MSM_ERR_HIP;
-    c->plan_ev_live[slot] = true;
+    if (c->fixed_plan) {
+        if (put_bytes(c->stream, c->fixed_plan, h, off) != hipSuccess) return MSM_ERR_HIP;
+    } else {
+        if (hipMemcpyAsync(c->plan_dev, h, off, hipMemcpyHostToDevice, c->stream) != hipSuccess) return MSM_ERR_HIP;
+        if (hipEventRecord(c->plan_ev[slot], c->stream) != hipSuccess) return MSM_ERR_HIP;
+        c->plan_ev_live[slot] = true;
+    }
 
     DevPlan &dp = c->dp;
-    char *d = c->plan_dev;
+    char *d = c->fixed_plan ? c->fixed_plan : c->plan_dev;
     dp.sys = (const SysPlan *)(d + o_sys);
     dp.nsys = nsys;
     dp.atom_prefix = (const int64_t *)(d + o_atom);
@@ -575,21 +597,112 @@ void stencil_tables(double a, double h, int R, int d2max, const Smooth &g, std::
         }
 }
 
+template <typename T> std::vector<T> &weights_image(msm_ctx *c);
+template <> std::vector<float> &weights_image<float>(msm_ctx *c) { return c->ps.wf; }
+template <> std::vector<double> &weights_image<double>(msm_ctx *c) { return c->ps.wd; }
+
+template <typename T> void stencil_image_t(msm_ctx *c, size_t *col_bytes, size_t *w_bytes)
+{
+    std::vector<T> &w = weights_image<T>(c);
+    stencil_tables<T>(c->prm.a, c->prm.h, c->mc.reach, c->d2max, c->mc.g, c->ps.cols, w);
+    c->ncols = (int)c->ps.cols.size();
+    *col_bytes = c->ps.cols.size() * sizeof(int2);
+    *w_bytes = w.size() * sizeof(T);
+}
+
 template <typename T> int upload_stencil(msm_ctx *c)
 {
-    std::vector<int2> cols;
-    std::vector<T> w;
-    stencil_tables<T>(c->prm.a, c->prm.h, c->mc.reach, c->d2max, c->mc.g, cols, w);
-    c->ncols = (int)cols.size();
-    if (hipMalloc(&c->weights, w.size() * sizeof(T)) != hipSuccess) return MSM_ERR_HIP;
-    if (hipMalloc((void **)&c->wcols, cols.size() * sizeof(int2)) != hipSuccess) return MSM_ERR_HIP;
-    if (hipMemcpy(c->weights, w.data(), w.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess) return MSM_ERR_HIP;
-    if (hipMemcpy(c->wcols, cols.data(), cols.size() * sizeof(int2), hipMemcpyHostToDevice) != hipSuccess)
+    size_t cb = 0, wb = 0;
+    stencil_image_t<T>(c, &cb, &wb);
+    if (hipMalloc(&c->weights, wb) != hipSuccess) return MSM_ERR_HIP;
+    if (hipMalloc((void **)&c->wcols, cb) != hipSuccess) return MSM_ERR_HIP;
+    if (hipMemcpy(c->weights, weights_image<T>(c).data(), wb, hipMemcpyHostToDevice) != hipSuccess)
         return MSM_ERR_HIP;
+    if (hipMemcpy(c->wcols, c->ps.cols.data(), cb, hipMemcpyHostToDevice) != hipSuccess) return MSM_ERR_HIP;
     return MSM_OK;
 }
 
 }  // namespace
+
+int msmx::init_context(msm_ctx *c, const msm_params *prm)
+{
+    if (!prm) return MSM_ERR_ARG;
+    if (!(prm->a > 0) || !(prm->h > 0) || !std::isfinite(prm->a) || !std::isfinite(prm->h)) return MSM_ERR_ARG;
+    if (prm->precision != MSM_FP32 && prm->precision != MSM_FP64) return MSM_ERR_ARG;
+    if (prm->max_atoms < 0 || prm->max_atoms >= ((int64_t)1 << 31) || prm->max_systems < 1) return MSM_ERR_ARG;
+    if (prm->levels < 0 || prm->levels > kMaxLevels) return MSM_ERR_ARG;
+    if (!std::isfinite(prm->coulomb_k)) return MSM_ERR_ARG;
+    if (prm->method != MSM_METHOD_MSM && prm->method != MSM_METHOD_CUTOFF && prm->method != MSM_METHOD_WOLF)
+        return MSM_ERR_ARG;
+    if (prm->method == MSM_METHOD_WOLF && !(prm->alpha >= 0 && std::isfinite(prm->alpha))) return MSM_ERR_ARG;
+    const int smoothing = prm->smoothing ? prm->smoothing : 2;
+    if (smoothing < 1 || smoothing > kMaxSmooth) return MSM_ERR_UNSUPPORTED;
+    if (prm->basis != 0 && prm->basis != 3 && prm->basis != 5) return MSM_ERR_UNSUPPORTED;
+    const bool cutoff = prm->method != MSM_METHOD_MSM;   // no grids
+    const double ratio = 2.0 * prm->a / prm->h;
+    const int reach = (int)std::ceil(ratio) - 1;       // largest integer below 2a/h
+    if (!cutoff && (reach < 1 || reach > kMaxReach - 1)) return MSM_ERR_UNSUPPORTED;
+
+    c->prm = *prm;
+    c->mc = MethodConst{};
+    c->mc.a = prm->a;
+    c->mc.h = prm->h;
+    c->mc.ke = prm->coulomb_k;
+    c->mc.method = prm->method;
+    c->mc.cutoff = cutoff ? 1 : 0;
+    c->mc.alpha = prm->method == MSM_METHOD_WOLF ? prm->alpha : 0.0;
+    c->mc.g = make_smooth(smoothing);
+    c->mc.p = basis_degree(*prm);
+    c->mc.reach = cutoff ? 0 : reach;
+    c->mc.pair_waves = 2;
+    c->mc.stencil_threads = 1024;
+    c->d2max = (int)std::ceil(ratio * ratio) - 1;      // largest integer below (2a/h)^2
+    int rc = geometry(*prm, prm->lo, prm->hi, c->ctx_geom);
+    if (rc) return rc;
+    const Sizes sz = sizes_of(c->ctx_geom);
+    const int64_t ns = prm->max_systems;
+    c->cap_cells = sz.cells * ns;
+    c->cap_q = sz.q * ns;
+    c->cap_u = sz.u * ns;
+    c->cap_t = sz.t * ns;
+    c->cap_w = sz.w * ns;
+    c->cap_iblk = (prm->max_atoms + 255) / 256 + ns;
+    if (c->cap_cells >= ((int64_t)1 << 31)) return MSM_ERR_CAPACITY;
+    return MSM_OK;
+}
+
+size_t msmx::workspace_bytes(msm_ctx *c)
+{
+    size_t bytes = 0;
+    if (c->prm.precision == MSM_FP32) carve<float>(c, c->wf, nullptr, &bytes, false);
+    else carve<double>(c, c->wd, nullptr, &bytes, false);
+    return bytes;
+}
+
+void msmx::carve_workspace(msm_ctx *c, char *base)
+{
+    size_t bytes = 0;
+    if (c->prm.precision == MSM_FP32) carve<float>(c, c->wf, base, &bytes, true);
+    else carve<double>(c, c->wd, base, &bytes, true);
+}
+
+void msmx::stencil_image(msm_ctx *c, size_t *col_bytes, size_t *w_bytes)
+{
+    if (c->prm.precision == MSM_FP32) stencil_image_t<float>(c, col_bytes, w_bytes);
+    else stencil_image_t<double>(c, col_bytes, w_bytes);
+}
+
+int msmx::put_stencil(msm_ctx *c, void *cols_dev, void *w_dev)
+{
+    const void *w = c->prm.precision == MSM_FP32 ? (const void *)c->ps.wf.data() : (const void *)c->ps.wd.data();
+    const size_t wb = c->prm.precision == MSM_FP32 ? c->ps.wf.size() * 4 : c->ps.wd.size() * 8;
+    if (put_bytes(c->stream, cols_dev, c->ps.cols.data(), c->ps.cols.size() * sizeof(int2)) != hipSuccess ||
+        put_bytes(c->stream, w_dev, w, wb) != hipSuccess)
+        return MSM_ERR_HIP;
+    c->wcols = (int2 *)cols_dev;
+    c->weights = w_dev;
+    return MSM_OK;
+}
 
 
 extern "C" {
@@ -613,76 +726,32 @@ int msm_setup(const msm_params *prm, void *stream, msm_ctx **out)
 {
     if (!prm || !out) return MSM_ERR_ARG;
     *out = nullptr;
-    if (!(prm->a > 0) || !(prm->h > 0) || !std::isfinite(prm->a) || !std::isfinite(prm->h)) return MSM_ERR_ARG;
-    if (prm->precision != MSM_FP32 && prm->precision != MSM_FP64) return MSM_ERR_ARG;
-    if (prm->max_atoms < 0 || prm->max_atoms >= ((int64_t)1 << 31) || prm->max_systems < 1) return MSM_ERR_ARG;
-    if (prm->levels < 0 || prm->levels > kMaxLevels) return MSM_ERR_ARG;
-    if (!std::isfinite(prm->coulomb_k)) return MSM_ERR_ARG;
-    if (prm->method != MSM_METHOD_MSM && prm->method != MSM_METHOD_CUTOFF && prm->method != MSM_METHOD_WOLF)
-        return MSM_ERR_ARG;
-    if (prm->method == MSM_METHOD_WOLF && !(prm->alpha >= 0 && std::isfinite(prm->alpha))) return MSM_ERR_ARG;
-    const int smoothing = prm->smoothing ? prm->smoothing : 2;
-    if (smoothing < 1 || smoothing > kMaxSmooth) return MSM_ERR_UNSUPPORTED;
-    if (prm->basis != 0 && prm->basis != 3 && prm->basis != 5) return MSM_ERR_UNSUPPORTED;
-    const bool cutoff = prm->method != MSM_METHOD_MSM;   // no grids
-    const double ratio = 2.0 * prm->a / prm->h;
-    const int reach = (int)std::ceil(ratio) - 1;       // largest integer below 2a/h
-    if (!cutoff && (reach < 1 || reach > kMaxReach - 1)) return MSM_ERR_UNSUPPORTED;
-
     msm_ctx *c = new (std::nothrow) msm_ctx();
     if (!c) return MSM_ERR_ARG;
-    c->prm = *prm;
+    int rc = init_context(c, prm);
+    if (rc) {
+        delete c;
+        return rc;
+    }
     c->stream = (hipStream_t)stream;
     if (hipGetDevice(&c->device) != hipSuccess) {
         delete c;
         return MSM_ERR_HIP;
     }
-    c->mc.a = prm->a;
-    c->mc.h = prm->h;
-    c->mc.ke = prm->coulomb_k;
-    c->mc.method = prm->method;
-    c->mc.cutoff = cutoff ? 1 : 0;
-    c->mc.alpha = prm->method == MSM_METHOD_WOLF ? prm->alpha : 0.0;
-    c->mc.g = make_smooth(smoothing);
-    c->mc.p = basis_degree(*prm);
-    c->mc.reach = cutoff ? 0 : reach;
-    c->mc.pair_waves = 2;
-    c->mc.stencil_threads = 1024;
-    c->d2max = (int)std::ceil(ratio * ratio) - 1;      // largest integer below (2a/h)^2
-    int rc = geometry(*prm, prm->lo, prm->hi, c->ctx_geom);
-    if (rc) {
-        delete c;
-        return rc;
-    }
-    const Sizes sz = sizes_of(c->ctx_geom);
-    const int64_t ns = prm->max_systems;
-    c->cap_cells = sz.cells * ns;
-    c->cap_q = sz.q * ns;
-    c->cap_u = sz.u * ns;
-    c->cap_t = sz.t * ns;
-    c->cap_w = sz.w * ns;
-    c->cap_iblk = (prm->max_atoms + 255) / 256 + ns;
-    if (c->cap_cells >= ((int64_t)1 << 31)) {
-        delete c;
-        return MSM_ERR_CAPACITY;
-    }
-    size_t bytes = 0;
-    if (prm->precision == MSM_FP32) carve<float>(c, c->wf, nullptr, &bytes, false);
-    else carve<double>(c, c->wd, nullptr, &bytes, false);
+    size_t bytes = workspace_bytes(c);
     if (hipMalloc((void **)&c->wbuf, bytes) != hipSuccess) {
         delete c;
         return MSM_ERR_HIP;
     }
     c->wbytes = bytes;
-    if (prm->precision == MSM_FP32) carve<float>(c, c->wf, c->wbuf, &bytes, true);
-    else carve<double>(c, c->wd, c->wbuf, &bytes, true);
+    carve_workspace(c, c->wbuf);
 
     // zero everything once: the halos of the charge grids are never written
     if (hipMemsetAsync(c->wbuf, 0, c->wbytes, c->stream) != hipSuccess) {
         msm_destroy(c);
         return MSM_ERR_HIP;
     }
-    if (!cutoff) rc = prm->precision == MSM_FP32 ? upload_stencil<float>(c) : upload_stencil<double>(c);
+    if (!c->mc.cutoff) rc = prm->precision == MSM_FP32 ? upload_stencil<float>(c) : upload_stencil<double>(c);
     if (rc) {
         msm_destroy(c);
         return rc;

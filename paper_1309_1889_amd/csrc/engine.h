@@ -19,6 +19,18 @@ struct Geometry {
     int gdim[kMaxLevels][3];
 };
 
+// Host vectors of a plan build, kept by the context so that their capacity
+// is reused from one build to the next.
+struct PlanScratch {
+    std::vector<SysPlan> sys;
+    std::vector<int64_t> atom_p, group_p, cell_p, iblk_p, top_p, ant_p, node_p, rxy_p, pxy_p, tile_p;
+    std::vector<double> phi_tab, p1, cur, nxt;
+    std::vector<char> blob;            // image of the tables for a fixed device region
+    std::vector<int2> cols;            // stencil columns and weights before upload
+    std::vector<float> wf;
+    std::vector<double> wd;
+};
+
 }  // namespace msmx
 
 struct msm_ctx {
@@ -47,6 +59,11 @@ struct msm_ctx {
     bool plan_ev_live[kPlanStage] = {};
     int plan_slot = 0;
     msmx::DevPlan dp{};
+    // allocation-free contexts: the tables are written to this fixed device
+    // region (at most fixed_plan_cap bytes) instead of plan_dev
+    char *fixed_plan = nullptr;
+    size_t fixed_plan_cap = 0;
+    msmx::PlanScratch ps;
     bool plan_valid = false;
     std::vector<int64_t> last_offsets;
     std::vector<double> last_domains;
@@ -96,6 +113,19 @@ struct msm_ctx {
 
 
 namespace msmx {
+
+// Validate the parameters and fill the context's method constants, geometry
+// and capacities (everything msm_setup does before allocating).
+int init_context(msm_ctx *c, const msm_params *prm);
+// Bytes of the workspace the context's capacities need.
+size_t workspace_bytes(msm_ctx *c);
+// Point the context's workspace arrays into base (workspace_bytes long).
+void carve_workspace(msm_ctx *c, char *base);
+// Host image of the stencil columns and weights of the context (in c->ps),
+// their byte sizes, and the upload of that image to device memory at cols_dev
+// and w_dev through kernel arguments.
+void stencil_image(msm_ctx *c, size_t *col_bytes, size_t *w_bytes);
+int put_stencil(msm_ctx *c, void *cols_dev, void *w_dev);
 
 // Build (or reuse) the device tables of a batch.
 int build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double *domains);

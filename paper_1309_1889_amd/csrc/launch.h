@@ -129,6 +129,10 @@ template <typename T> struct Launch {
 };
 
 hipError_t fill_i32(hipStream_t s, int *p, int64_t n, int v);
+// Copy bytes of host memory to device memory through kernel arguments
+// (2 KiB per launch), so that the copy allocates nothing and the source may
+// be reused as soon as the call returns. dst and bytes: multiples of 4.
+hipError_t put_bytes(hipStream_t s, void *dst, const void *src_host, size_t bytes);
 template <typename T> hipError_t fill_t(hipStream_t s, T *p, int64_t n, T v);
 
 }  // namespace msmx
