@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import oracle
-from workloads import named, uniform_pm, water_box
+from workloads import named, uniform_pm, uniform_pm_box, water_box
 
 pytestmark = pytest.mark.gpu
 
@@ -92,6 +92,86 @@ def test_anterpolation_forms_match_oracle_per_stage(h, two_pass):
         nc = int(np.floor((w.hi[d] - w.lo[d]) / h)) + 1
         ncells *= (nc + 3) // 4 * 4
     assert (w.n > 2 * ncells) == two_pass
+    eo, fo, po, st = run_oracle(w, stages=True)
+    assert e == pytest.approx(eo, rel=1e-12)
+    assert max_rel(f, fo) < 1e-11
+    assert max_rel(p, po) < 1e-11
+    g = ctx.stages(w.n)
+    for k in range(len(st["q_grid"])):
+        assert max_rel(g["q_grid"][k].cpu().numpy(), st["q_grid"][k]) < 1e-12, k
+
+
+@pytest.mark.parametrize("box", ["water_2400", "water_99999"])
+def test_fp32_grid_charges_match_oracle(box):
+    """The single-precision anterpolation (one-axis weights staged with each
+    atom) against the oracle's scatter on every level's grid charges, to
+    single-precision rounding relative to the largest grid charge: a node
+    adds about a hundred products of three weights and a charge of either
+    sign, so rounding reaches a few 1e-6 of the largest value; a wrong weight
+    or node would be off by 1e-2 or more."""
+    w = (water_box(800, (10, 10, 10), (3.1, 3.1, 3.1), seed=29) if box == "water_2400"
+         else named("water_99999")).as_dtype(np.float32)
+    ctx, e, f, p = run_gpu(w, "fp32")
+    eo, fo, po, st = run_oracle(w, stages=True)
+    g = ctx.stages(w.n)
+    for k in range(len(st["q_grid"])):
+        assert max_rel(g["q_grid"][k].cpu().numpy(), st["q_grid"][k]) < 1e-5, k
+    assert rel_rms(f, fo) < 1e-5
+    assert rel_rms(p, po) < 1e-5
+
+
+# the composite transfers hold a level-0 xy plane of at most this many nodes in
+# LDS; larger planes restrict and prolong one level at a time
+PLANE_CAP = 6144
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_per_level_transfers_match_oracle_per_stage(precision):
+    """A flat 22 x 22 x 1.5 nm domain: its level-0 xy plane (92 x 92 nodes)
+    exceeds the composite transfers' LDS plane, so restriction and
+    prolongation run one level at a time (the path of every large box). FP64:
+    every q^k, u^{k,cutoff} and u^k of the six grids and the outputs against
+    the oracle at rounding level; FP32: the outputs at the single-precision
+    bound."""
+    w = uniform_pm_box(2000, (22.0, 22.0, 1.5), seed=31)
+    if precision == "fp32":
+        w = w.as_dtype(np.float32)
+    ctx, e, f, p = run_gpu(w, precision)
+    shapes = ctx.grid_shape()
+    org, dim = shapes[0]
+    assert dim[0] * dim[1] > PLANE_CAP and len(shapes) == 6
+    if precision == "fp32":
+        eo, fo, po = run_oracle(w)
+        assert rel_rms(f, fo) < 1e-4
+        assert rel_rms(p, po) < 1e-4
+        assert e == pytest.approx(eo, rel=1e-4)
+        return
+    eo, fo, po, st = run_oracle(w, stages=True)
+    assert e == pytest.approx(eo, rel=1e-12)
+    assert max_rel(f, fo) < 1e-11
+    assert max_rel(p, po) < 1e-11
+    g = ctx.stages(w.n)
+    assert len(st["q_grid"]) == len(shapes)
+    for k in range(len(shapes)):
+        assert tuple(g["q_grid"][k].shape) == st["q_grid"][k].shape, k
+        assert max_rel(g["q_grid"][k].cpu().numpy(), st["q_grid"][k]) < 1e-12, k
+        assert max_rel(g["ucut_grid"][k].cpu().numpy(), st["ucut_grid"][k]) < 1e-12, k
+        assert max_rel(g["u_grid"][k].cpu().numpy(), st["u_grid"][k]) < 1e-12, k
+
+
+def test_anterpolation_global_gather_matches_oracle():
+    """A sparse 6 nm box with 2,500 of its 3,000 charges in one 1 nm cube: the
+    tile whose 11 x 11 x 7-cell region holds the dense spot has more atoms than
+    its LDS stages (2,048), so its nodes gather from global memory, while the
+    box as a whole stays below 2 atoms per cell (the tiled form). q^k and the
+    outputs against the oracle's scatter at rounding level."""
+    w = uniform_pm_box(3000, (6.0, 6.0, 6.0), seed=32, cluster=(2500, (2.5, 2.5, 2.5), 1.0))
+    ncells = 1
+    for d in range(3):
+        nc = int(np.floor((w.hi[d] - w.lo[d]) / w.h)) + 1
+        ncells *= (nc + 3) // 4 * 4
+    assert w.n <= 2 * ncells   # the tiled form, not the two-pass cell form
+    ctx, e, f, p = run_gpu(w, "fp64")
     eo, fo, po, st = run_oracle(w, stages=True)
     assert e == pytest.approx(eo, rel=1e-12)
     assert max_rel(f, fo) < 1e-11

@@ -12,6 +12,7 @@ geometry) on a jittered lattice at about 100 atoms per nm^3.
 from .water import (  # noqa: F401
     Workload,
     uniform_pm,
+    uniform_pm_box,
     water_box,
     water_box_dims,
     maxwell_velocities,

@@ -67,6 +67,22 @@ def uniform_pm(n: int = 2000, side: float = 4.0, seed: int = 1,
                     a=a, h=h, levels=levels)
 
 
+def uniform_pm_box(n: int, dims, seed: int, a: float = 1.2, h: float = 0.25, levels: int = 0,
+                   cluster: tuple | None = None) -> Workload:
+    """``n`` points uniform in the box [0, dims) with charges +1, -1, ...; the
+    domain is the box. ``cluster = (m, corner, side)`` puts the first ``m``
+    points uniformly in the cube of edge ``side`` at ``corner`` instead (a
+    dense spot in a sparse box)."""
+    rng = np.random.default_rng(seed)
+    dims = np.asarray(dims, dtype=np.float64)
+    xyz = rng.uniform(0.0, 1.0, size=(n, 3)) * dims
+    if cluster is not None:
+        m, corner, side = cluster
+        xyz[:m] = np.asarray(corner, dtype=np.float64) + rng.uniform(0.0, side, size=(m, 3))
+    q = np.where(np.arange(n) % 2 == 0, 1.0, -1.0)
+    return Workload(f"charges_{n}_box", xyz, q, np.zeros(3), dims.copy(), a=a, h=h, levels=levels)
+
+
 def _random_rotations(rng, m):
     """Uniform random rotation matrices from normalised Gaussian quaternions."""
     quat = rng.standard_normal((m, 4))
