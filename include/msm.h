@@ -47,7 +47,9 @@ enum {
     MSM_ERR_NONFINITE = -3,     /* a position or charge is NaN or infinite */
     MSM_ERR_CAPACITY = -4,      /* more atoms/systems or a larger domain than set up for */
     MSM_ERR_HIP = -5,           /* a HIP runtime call failed */
-    MSM_ERR_UNSUPPORTED = -6    /* parameters outside what the kernels are built for */
+    MSM_ERR_UNSUPPORTED = -6,   /* parameters outside what the kernels are built for */
+    MSM_ERR_CONSTRAINT = -7     /* the constraint iteration of a rigid molecule stopped at its
+                                   cap (500 sweeps) without meeting the tolerance */
 };
 
 enum { MSM_FP64 = 0, MSM_FP32 = 1 };
@@ -185,6 +187,9 @@ typedef struct {
     int concurrent;        /* 1: the short-range sum runs on a second stream of the context,
                               concurrently with the grid stages (forked after binning,
                               joined before interpolation; HIP graphs capture both branches);
+                              2: as 1, but forked after anterpolation, which first runs
+                              alone (its LDS-heavy tiles are not starved by the pair
+                              workgroups; better for large systems);
                               0: every stage on the context stream in turn. Stage timing
                               always runs the stages in turn. */
 } msm_tuning;
@@ -192,8 +197,8 @@ typedef struct {
 int msm_get_tuning(const msm_ctx *ctx, msm_tuning *out);
 int msm_set_tuning(msm_ctx *ctx, const msm_tuning *tuning);
 
-/* Autotuner: time whole evaluations (launched eagerly, with the context's
- * concurrent setting) for every pair_waves and stencil_threads candidate,
+/* Autotuner: time whole evaluations (launched eagerly; with concurrent stages
+ * on, for both fork points 1 and 2) for every pair_waves and stencil_threads candidate,
  * reps evaluations each, on the caller's own batch (arguments as for
  * msm_energy_forces; no outputs are written), keep the fastest pair and
  * report it in *chosen (may be NULL). Synchronous. */
@@ -209,7 +214,11 @@ int msm_autotune(msm_ctx *ctx, int nsys, const int64_t *offsets_host, const doub
 int msm_set_graphs(msm_ctx *ctx, int enable);
 
 /* Synchronise the stream, return and clear the device status word:
- * MSM_OK, MSM_ERR_DOMAIN or MSM_ERR_NONFINITE (the first seen), or MSM_ERR_HIP. */
+ * MSM_OK, or the first applicable of the conditions seen since the last
+ * call: MSM_ERR_DOMAIN (an atom left its domain; what follows from it is not
+ * reported separately), MSM_ERR_NONFINITE (a non-finite position or charge,
+ * or a constraint iteration that met a non-finite value and stopped there),
+ * MSM_ERR_CONSTRAINT; or MSM_ERR_HIP. */
 int msm_get_status(msm_ctx *ctx);
 
 /* Text for a status code. */

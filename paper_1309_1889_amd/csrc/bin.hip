@@ -64,7 +64,10 @@ __global__ void k_bin_count(DevPlan p, const vec4_t<T> *__restrict__ xyzq, int *
         c[d] = ci;
     }
     if (!isfinite(a.w)) bad |= kStatusNonFinite;
-    if (bad) atomicOr(status, bad);
+    if (bad) {
+        atomicOr(status, bad);
+        atomicOr(status + 1, 1);   // this evaluation's failure flag
+    }
     const int cell = (int)(P.cell0 + cell_rank(P, c[0], c[1], c[2]));
     cell_of[i] = cell;
     slot_of[i] = atomicAdd(&counts[cell], 1);
@@ -220,11 +223,13 @@ __device__ inline void sort_range(int *a, int n)
 template <typename T>
 __global__ void k_cell_sort_thread(int64_t ncells, const int *__restrict__ start, int *__restrict__ order,
                                    const vec4_t<T> *__restrict__ xyzq, vec4_t<T> *__restrict__ sxyzq,
-                                   const vec4_t<T> *__restrict__ maux, vec4_t<T> *__restrict__ saux, int64_t period)
+                                   const vec4_t<T> *__restrict__ maux, vec4_t<T> *__restrict__ saux, int64_t period,
+                                   const int *__restrict__ evflag)
 {
     int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= ncells) return;
     int b = start[c], e = start[c + 1];
+    if (e - b > 64 && *evflag) return;   // a cell of clamped atoms of a failed evaluation
     sort_range(order + b, e - b);
     for (int i = b; i < e; i++) sxyzq[i] = xyzq[order[i]];
     if (maux)
@@ -240,7 +245,8 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_cell_sort(int64_t ncells, const int *__restrict__ start,
                                                    int *__restrict__ order, const vec4_t<T> *__restrict__ xyzq,
                                                    vec4_t<T> *__restrict__ sxyzq, const vec4_t<T> *__restrict__ maux,
-                                                   vec4_t<T> *__restrict__ saux, int64_t period)
+                                                   vec4_t<T> *__restrict__ saux, int64_t period,
+                                                   const int *__restrict__ evflag)
 {
     const int64_t c = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
     if (c >= ncells) return;
@@ -249,7 +255,7 @@ __global__ __launch_bounds__(256) void k_cell_sort(int64_t ncells, const int *__
     const int n = __builtin_amdgcn_readfirstlane(start[c + 1]) - b;
     if (n == 0) return;
     if (n > 64) {
-        if (lane == 0) {
+        if (lane == 0 && !*evflag) {   // a cell of clamped atoms of a failed evaluation is left
             sort_range(order + b, n);
             for (int i = b; i < b + n; i++) sxyzq[i] = xyzq[order[i]];
             if (maux)
@@ -332,10 +338,12 @@ hipError_t Launch<T>::bin(hipStream_t s, const DevPlan &p, const Work<T> &w, con
                            w.slot_of, w.cell_start, w.order);
         if (p.natoms > 2 * p.ncells)
             hipLaunchKernelGGL(k_cell_sort<T>, dim3(nblocks(p.ncells, 4)), dim3(256), 0, s, p.ncells,
-                               w.cell_start, w.order, xyzq, w.sxyzq, (const vec4_t<T> *)w.maux, w.saux, w.period);
+                               w.cell_start, w.order, xyzq, w.sxyzq, (const vec4_t<T> *)w.maux, w.saux, w.period,
+                               (const int *)p.evflag);
         else
             hipLaunchKernelGGL(k_cell_sort_thread<T>, dim3(nblocks(p.ncells, 256)), dim3(256), 0, s, p.ncells,
-                               w.cell_start, w.order, xyzq, w.sxyzq, (const vec4_t<T> *)w.maux, w.saux, w.period);
+                               w.cell_start, w.order, xyzq, w.sxyzq, (const vec4_t<T> *)w.maux, w.saux, w.period,
+                               (const int *)p.evflag);
     }
     return hipGetLastError();
 }

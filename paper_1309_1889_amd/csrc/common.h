@@ -24,7 +24,7 @@ constexpr int kMaxReach = 12;        // stencil reach R (largest integer below 2
 constexpr int kGridPad = kMaxReach;  // zero halo below every charge grid (and above, plus a tile)
 constexpr int kStencilTile = 8;      // stencil output tile edge (nodes per axis)
 
-enum StatusBits : int { kStatusDomain = 1, kStatusNonFinite = 2 };
+enum StatusBits : int { kStatusDomain = 1, kStatusNonFinite = 2, kStatusConstraint = 4 };
 
 template <typename T> struct Vec4;
 template <> struct Vec4<float> { using type = float4; };

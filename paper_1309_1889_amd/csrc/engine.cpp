@@ -412,6 +412,7 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     dp.npxy = pxy;
     dp.nrz = 0;
     for (int k = 1; k < kMaxLevels; k++) dp.nrz += nodes[k];
+    dp.evflag = (c->prm.precision == MSM_FP32 ? c->wf.status : c->wd.status) + 1;
     c->host_sys = sys;
     c->last_offsets.assign(offsets, offsets + nsys + 1);
     if (domains) c->last_domains.assign(domains, domains + nsys * 6);
@@ -448,6 +449,13 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     // concurrency on, the pair kernel runs on the side stream from here until
     // the join before interpolation
     const bool fork = do_short && do_long && c->concurrent && !c->timing && p.nnodes[0] > 0;
+    // mode 2: anterpolation first, alone (its large LDS tiles are starved by
+    // long-lived pair workgroups when both start together), then the fork
+    const bool ant_first = fork && c->concurrent == 2;
+    if (ant_first) {
+        mark(MSM_STAGE_ANTERP);
+        if ((e = L::anterp(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
+    }
     hipStream_t ps = s;
     if (fork) {
         if (!c->side_stream && hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking) != hipSuccess)
@@ -461,8 +469,10 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
         ps = c->side_stream;
     }
     if (do_short && (e = L::pair(ps, p, w, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
-    mark(MSM_STAGE_ANTERP);
-    if (do_long && (e = L::anterp(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
+    if (!ant_first) {
+        mark(MSM_STAGE_ANTERP);
+        if (do_long && (e = L::anterp(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;
+    }
     mark(MSM_STAGE_RESTRICT);
     // every level from level 0 by composite filters (two launches), or one
     // launch per level; each launch serves all systems of the batch
@@ -601,24 +611,46 @@ template <typename T> std::vector<T> &weights_image(msm_ctx *c);
 template <> std::vector<float> &weights_image<float>(msm_ctx *c) { return c->ps.wf; }
 template <> std::vector<double> &weights_image<double>(msm_ctx *c) { return c->ps.wd; }
 
+// The context's constant device table: the lattice-cutoff columns and
+// weights (MSM), or the single-precision Wolf pair table (Wolf summation in
+// FP32, in the weights slot); nothing otherwise.
 template <typename T> void stencil_image_t(msm_ctx *c, size_t *col_bytes, size_t *w_bytes)
 {
     std::vector<T> &w = weights_image<T>(c);
-    stencil_tables<T>(c->prm.a, c->prm.h, c->mc.reach, c->d2max, c->mc.g, c->ps.cols, w);
+    c->ps.cols.clear();
+    w.clear();
+    if (c->mc.method == MSM_METHOD_MSM) {
+        stencil_tables<T>(c->prm.a, c->prm.h, c->mc.reach, c->d2max, c->mc.g, c->ps.cols, w);
+    } else if (c->mc.method == MSM_METHOD_WOLF && sizeof(T) == 4) {
+        w.resize(8 * kWolfPieces);
+        wolf_table(c->prm.a, c->mc.alpha, (float *)w.data());
+    }
     c->ncols = (int)c->ps.cols.size();
     *col_bytes = c->ps.cols.size() * sizeof(int2);
     *w_bytes = w.size() * sizeof(T);
+}
+
+bool has_table(const msm_ctx *c)
+{
+    return c->mc.method == MSM_METHOD_MSM || (c->mc.method == MSM_METHOD_WOLF && c->prm.precision == MSM_FP32);
+}
+
+// after the table is in device memory
+void bind_table(msm_ctx *c)
+{
+    c->mc.wolf_tab = c->mc.method == MSM_METHOD_WOLF ? (const float4 *)c->weights : nullptr;
 }
 
 template <typename T> int upload_stencil(msm_ctx *c)
 {
     size_t cb = 0, wb = 0;
     stencil_image_t<T>(c, &cb, &wb);
-    if (hipMalloc(&c->weights, wb) != hipSuccess) return MSM_ERR_HIP;
-    if (hipMalloc((void **)&c->wcols, cb) != hipSuccess) return MSM_ERR_HIP;
-    if (hipMemcpy(c->weights, weights_image<T>(c).data(), wb, hipMemcpyHostToDevice) != hipSuccess)
+    if (wb && hipMalloc(&c->weights, wb) != hipSuccess) return MSM_ERR_HIP;
+    if (cb && hipMalloc((void **)&c->wcols, cb) != hipSuccess) return MSM_ERR_HIP;
+    if (wb && hipMemcpy(c->weights, weights_image<T>(c).data(), wb, hipMemcpyHostToDevice) != hipSuccess)
         return MSM_ERR_HIP;
-    if (hipMemcpy(c->wcols, c->ps.cols.data(), cb, hipMemcpyHostToDevice) != hipSuccess) return MSM_ERR_HIP;
+    if (cb && hipMemcpy(c->wcols, c->ps.cols.data(), cb, hipMemcpyHostToDevice) != hipSuccess) return MSM_ERR_HIP;
+    bind_table(c);
     return MSM_OK;
 }
 
@@ -688,6 +720,8 @@ void msmx::carve_workspace(msm_ctx *c, char *base)
 
 void msmx::stencil_image(msm_ctx *c, size_t *col_bytes, size_t *w_bytes)
 {
+    *col_bytes = *w_bytes = 0;
+    if (!has_table(c)) return;
     if (c->prm.precision == MSM_FP32) stencil_image_t<float>(c, col_bytes, w_bytes);
     else stencil_image_t<double>(c, col_bytes, w_bytes);
 }
@@ -701,6 +735,7 @@ int msmx::put_stencil(msm_ctx *c, void *cols_dev, void *w_dev)
         return MSM_ERR_HIP;
     c->wcols = (int2 *)cols_dev;
     c->weights = w_dev;
+    bind_table(c);
     return MSM_OK;
 }
 
@@ -718,6 +753,7 @@ const char *msm_status_string(int code)
     case MSM_ERR_CAPACITY: return "capacity of the context exceeded";
     case MSM_ERR_HIP: return "HIP runtime error";
     case MSM_ERR_UNSUPPORTED: return "parameters outside the supported range";
+    case MSM_ERR_CONSTRAINT: return "a rigid molecule's constraint iteration did not converge";
     default: return "unknown status";
     }
 }
@@ -751,7 +787,7 @@ int msm_setup(const msm_params *prm, void *stream, msm_ctx **out)
         msm_destroy(c);
         return MSM_ERR_HIP;
     }
-    if (!c->mc.cutoff) rc = prm->precision == MSM_FP32 ? upload_stencil<float>(c) : upload_stencil<double>(c);
+    if (has_table(c)) rc = prm->precision == MSM_FP32 ? upload_stencil<float>(c) : upload_stencil<double>(c);
     if (rc) {
         msm_destroy(c);
         return rc;
@@ -813,7 +849,7 @@ int msm_get_tuning(const msm_ctx *c, msm_tuning *t)
     if (!c || !t) return MSM_ERR_ARG;
     t->pair_waves = c->mc.pair_waves;
     t->stencil_threads = c->mc.stencil_threads;
-    t->concurrent = c->concurrent ? 1 : 0;
+    t->concurrent = c->concurrent;
     return MSM_OK;
 }
 
@@ -824,12 +860,12 @@ int msm_set_tuning(msm_ctx *c, const msm_tuning *t)
         t->pair_waves != 6 && t->pair_waves != 8 && t->pair_waves != 16)
         return MSM_ERR_ARG;
     if (t->stencil_threads != 256 && t->stencil_threads != 1024) return MSM_ERR_ARG;
-    if (t->concurrent != 0 && t->concurrent != 1) return MSM_ERR_ARG;
+    if (t->concurrent < 0 || t->concurrent > 2) return MSM_ERR_ARG;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
     for (auto &g : c->graphs) drop_graph(g);     // captured launches use the old kernels
     c->mc.pair_waves = t->pair_waves;
     c->mc.stencil_threads = t->stencil_threads;
-    c->concurrent = t->concurrent != 0;
+    c->concurrent = t->concurrent;
     return MSM_OK;
 }
 
@@ -840,7 +876,7 @@ int msm_autotune(msm_ctx *c, int nsys, const int64_t *offsets, const double *dom
     if (nsys > c->prm.max_systems) return MSM_ERR_CAPACITY;
     int rc = build_plan(c, nsys, offsets, domains);
     if (rc) return rc;
-    const msm_tuning start{c->mc.pair_waves, c->mc.stencil_threads, c->concurrent ? 1 : 0};
+    const msm_tuning start{c->mc.pair_waves, c->mc.stencil_threads, c->concurrent};
     // whole evaluations, launched eagerly with the context's stream use: with
     // concurrent stages the pair kernel that fits best beside the grid stages
     // is not the fastest one alone
@@ -865,19 +901,25 @@ int msm_autotune(msm_ctx *c, int nsys, const int64_t *offsets, const double *dom
     };
     msm_tuning best = start;
     double best_ms = 1e300;
-    for (int pw : {1, 2, 3, 4, 5, 6, 8, 16})
-        for (int st : {256, 1024}) {
-            if (rc) break;
-            c->mc.pair_waves = pw;
-            c->mc.stencil_threads = st;
-            double ms = 0;
-            if ((rc = eval_time(&ms))) break;
-            if (ms < best_ms) {
-                best_ms = ms;
-                best.pair_waves = pw;
-                best.stencil_threads = st;
+    // with concurrent stages, both fork points: after binning, or after anterpolation
+    const int modes[2] = {1, 2};
+    const int nmodes = start.concurrent ? 2 : 1;
+    for (int mi = 0; mi < nmodes; mi++)
+        for (int pw : {1, 2, 3, 4, 5, 6, 8, 16})
+            for (int st : {256, 1024}) {
+                if (rc) break;
+                c->mc.pair_waves = pw;
+                c->mc.stencil_threads = st;
+                c->concurrent = start.concurrent ? modes[mi] : 0;
+                double ms = 0;
+                if ((rc = eval_time(&ms))) break;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best.pair_waves = pw;
+                    best.stencil_threads = st;
+                    best.concurrent = c->concurrent;
+                }
             }
-        }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     c->timing = was_timing;
@@ -885,6 +927,7 @@ int msm_autotune(msm_ctx *c, int nsys, const int64_t *offsets, const double *dom
     c->tuning_pass = false;
     c->mc.pair_waves = start.pair_waves;
     c->mc.stencil_threads = start.stencil_threads;
+    c->concurrent = start.concurrent;
     if (rc) return rc;
     int r2 = msm_set_tuning(c, &best);
     if (r2) return r2;
@@ -913,8 +956,11 @@ int msm_get_status(msm_ctx *c)
         if (fill_i32(c->stream, st, 1, 0) != hipSuccess) return MSM_ERR_HIP;
         if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
     }
-    if (v & kStatusNonFinite) return MSM_ERR_NONFINITE;
+    // an atom that left its domain is the first cause of what follows from
+    // it (forces and constraint iterations that turn non-finite)
     if (v & kStatusDomain) return MSM_ERR_DOMAIN;
+    if (v & kStatusNonFinite) return MSM_ERR_NONFINITE;
+    if (v & kStatusConstraint) return MSM_ERR_CONSTRAINT;
     return MSM_OK;
 }
 

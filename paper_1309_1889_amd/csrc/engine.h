@@ -76,8 +76,10 @@ struct msm_ctx {
     hipEvent_t ev[MSM_NSTAGES + 1] = {};
     double stage_ms[MSM_NSTAGES] = {};
     int64_t timed_evals = 0;
-    // concurrent stages: the short-range sum on side_stream between the two events
-    bool concurrent = true;
+    // concurrent stages: the short-range sum on side_stream between the two
+    // events; 1: forked after binning, 2: forked after anterpolation (which
+    // then runs alone on the whole chip), 0: every stage in turn
+    int concurrent = 1;
     hipStream_t side_stream = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     // captured evaluations (msm_set_graphs)

@@ -35,7 +35,15 @@ struct DevPlan {
     const int64_t *rxy_prefix;   // nsys+1: level-0 z-planes x levels >= 1 (restriction xy blocks)
     const int64_t *pxy_prefix;   // nsys+1: z-planes of levels >= 1 (prolongation xy blocks)
     int64_t nrxy, npxy, nrz;     // those block counts, and the nodes of levels >= 1
+    // set by binning when this evaluation has an atom outside its domain or a
+    // non-finite value (its results are undefined), cleared by interpolation
+    int *evflag;
 };
+
+// The evaluation's results are undefined (see DevPlan::evflag): the stages
+// whose cost grows with the atoms piled into one cell skip their work, so a
+// diverging trajectory fails at the cost of an ordinary step.
+__device__ inline bool eval_failed(const DevPlan &p) { return p.evflag && *p.evflag; }
 
 // Scratch arrays owned by the context.
 template <typename T> struct Work {
@@ -55,7 +63,7 @@ template <typename T> struct Work {
     T *tscr;             // composite restriction: per level, level-0 z-planes x level-k (y, x)
     T *wscr;             // composite prolongation: per level, level-k z-planes x level-0 (y, x)
     double *eparts;      // per interpolation block: sum q_i phi_i
-    int *status;         // device status word
+    int *status;         // device status word; status[1]: the current evaluation's failure flag
     // dynamics model (null when no model is bound)
     vec4_t<T> *maux;     // per model atom: (molecule id bits, sigma/2, sqrt(eps), 0)
     vec4_t<T> *saux;     // sorted copy of maux
@@ -85,12 +93,24 @@ struct MethodConst {
     Smooth g;                  // smoothing function gamma of order g.m
     int p;                     // degree of the nodal basis Phi: 3 or 5
     int reach;                 // stencil reach R: largest integer with R < 2a/h
+    // Wolf summation in single precision: kWolfPieces cubic pieces on [0, a)
+    // of E(r) = erfc(alpha r) and D(r) = E(r) + (2 alpha r / sqrt(pi)) exp(-alpha^2 r^2),
+    // two float4 per piece (E, then D), in device memory
+    const float4 *wolf_tab;
     int pair_waves;            // waves per 64-atom group in the pair kernel: 4, 8 or 16; 1: 16-atom sub-groups;
                                // 2: 8-atom clusters with bounding-box candidate filtering;
                                // 3: two such clusters per wave sharing one candidate stream;
                                // 5, 6: one 16-atom (5) or 32-atom (6) cluster per wave
     int stencil_threads;       // threads per stencil tile: 256 or 1024
 };
+
+// Pieces of the single-precision Wolf pair table (see MethodConst::wolf_tab).
+constexpr int kWolfPieces = 128;
+// Coefficients c0..c3 of each piece in its local coordinate u in [0, 1):
+// f(r_k + u a / kWolfPieces) = c0 + u (c1 + u (c2 + u c3)), from the values
+// and derivatives of f at the piece ends (cubic Hermite); out holds
+// 8 * kWolfPieces floats.
+void wolf_table(double a, double alpha, float *out);
 
 int anterp_tiles(int dx, int dy, int dz);
 // composite transfers: LDS capacity (elements) of a level-0 xy plane and of

@@ -10,6 +10,8 @@ struct TriModel {
     double len[3];
     double tol;        // relative tolerance on the squared bond length / bond velocity
     int max_iter;
+    int *status;       // the context's status word: kStatusConstraint when an iteration
+                       // stops at max_iter, kStatusNonFinite when it meets a non-finite value
 };
 
 // T is the precision of the forces (the context's); the state is FP64.

@@ -101,6 +101,7 @@ template <typename T> int bind(msm_ctx *c, const msm_md_model *m)
     for (int d = 0; d < 3; d++) c->tri.len[d] = m->tri_len[d];
     c->tri.tol = m->constraint_tol > 0 ? m->constraint_tol : 1e-10;   // the state is FP64 either way
     c->tri.max_iter = 500;
+    c->tri.status = c->prm.precision == MSM_FP32 ? c->wf.status : c->wd.status;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
     c->md_bound = true;
     return MSM_OK;

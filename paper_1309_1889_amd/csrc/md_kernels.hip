@@ -37,9 +37,18 @@ __device__ inline bool bond_within(const V3<double> r[3], int c, const TriModel 
     return fabs(diff) <= 2.0 * tm.tol * d2;
 }
 
+// Outcome of a constraint iteration: 0 (every bond within the tolerance),
+// kStatusNonFinite (it met a non-finite value and stopped there) or
+// kStatusConstraint (max_iter sweeps without meeting the tolerance); a
+// non-zero outcome is or-ed into the status word.
+__device__ inline void report_constraint(const TriModel &tm, int outcome)
+{
+    if (outcome && tm.status) atomicOr(tm.status, outcome);
+}
+
 // RATTLE's velocity stage: remove the relative velocity along every bond.
-__device__ inline void constrain_velocities(const V3<double> r[3], V3<double> vel[3], const double im[3],
-                                            const TriModel &tm)
+__device__ inline int constrain_velocities(const V3<double> r[3], V3<double> vel[3], const double im[3],
+                                           const TriModel &tm)
 {
     for (int it = 0; it < tm.max_iter; it++) {
         bool done = true;
@@ -49,6 +58,7 @@ __device__ inline void constrain_velocities(const V3<double> r[3], V3<double> ve
             const V3<double> rr = sub(r[a], r[b]);
             const V3<double> w = sub(vel[a], vel[b]);
             const double rw = dot(rr, w);
+            if (!isfinite(rw)) return kStatusNonFinite;
             if (fabs(rw) <= tm.tol * d2) continue;
             done = false;
             const double kk = rw / ((im[a] + im[b]) * d2);
@@ -56,8 +66,9 @@ __device__ inline void constrain_velocities(const V3<double> r[3], V3<double> ve
             vel[a] = {vel[a].x - ka * rr.x, vel[a].y - ka * rr.y, vel[a].z - ka * rr.z};
             vel[b] = {vel[b].x + kb * rr.x, vel[b].y + kb * rr.y, vel[b].z + kb * rr.z};
         }
-        if (done) break;
+        if (done) return 0;
     }
+    return kStatusConstraint;
 }
 
 // Half kick and drift of one atom (no constraints). The state is FP64; the
@@ -112,7 +123,8 @@ __global__ void k_kick_drift_rattle(int64_t ntri, double4 *__restrict__ x, doubl
         r[a] = {old[a].x + dt * vel[a].x, old[a].y + dt * vel[a].y, old[a].z + dt * vel[a].z};
     }
     const double inv_dt = 1.0 / dt;
-    for (int it = 0; it < tm.max_iter; it++) {
+    int outcome = kStatusConstraint;
+    for (int it = 0; it < tm.max_iter && outcome == kStatusConstraint; it++) {
         bool done = true;
         for (int c = 0; c < 3; c++) {
             const int a = kTriA[c], b = kTriB[c];
@@ -122,14 +134,19 @@ __global__ void k_kick_drift_rattle(int64_t ntri, double4 *__restrict__ x, doubl
             const V3<double> ro = sub(old[a], old[b]);
             done = false;
             const double g = diff / (2.0 * dot(s, ro) * (im[a] + im[b]));
+            if (!isfinite(g)) {
+                outcome = kStatusNonFinite;
+                break;
+            }
             const double ga = g * im[a], gb = g * im[b];
             r[a] = {r[a].x + ga * ro.x, r[a].y + ga * ro.y, r[a].z + ga * ro.z};
             r[b] = {r[b].x - gb * ro.x, r[b].y - gb * ro.y, r[b].z - gb * ro.z};
             vel[a] = {vel[a].x + ga * inv_dt * ro.x, vel[a].y + ga * inv_dt * ro.y, vel[a].z + ga * inv_dt * ro.z};
             vel[b] = {vel[b].x - gb * inv_dt * ro.x, vel[b].y - gb * inv_dt * ro.y, vel[b].z - gb * inv_dt * ro.z};
         }
-        if (done) break;
+        if (done && outcome == kStatusConstraint) outcome = 0;
     }
+    report_constraint(tm, outcome);
     for (int a = 0; a < 3; a++) {
         const int64_t i = 3 * t + a;
         x[i] = make_double4(r[a].x, r[a].y, r[a].z, q[a]);
@@ -176,7 +193,7 @@ __global__ void k_kick_rattle(int64_t ntri, const double4 *__restrict__ x, doubl
         vel[a] = {vi.x + h * (double)f[3 * i], vi.y + h * (double)f[3 * i + 1], vi.z + h * (double)f[3 * i + 2]};
         r[a] = {xi.x, xi.y, xi.z};
     }
-    constrain_velocities(r, vel, im, tm);
+    report_constraint(tm, constrain_velocities(r, vel, im, tm));
     for (int a = 0; a < 3; a++) v[3 * t + a] = make_double4(vel[a].x, vel[a].y, vel[a].z, im[a]);
 }
 
@@ -295,7 +312,8 @@ __global__ __launch_bounds__(256) void k_correct_rigid(int64_t ntri, double *__r
             vel[a] = {nv[3], nv[4], nv[5]};
             im[a] = invm[3 * t + a];
         }
-        for (int it = 0; it < tm.max_iter; it++) {
+        int outcome = kStatusConstraint;
+        for (int it = 0; it < tm.max_iter && outcome == kStatusConstraint; it++) {
             bool done = true;
             for (int c = 0; c < 3; c++) {
                 const int a = kTriA[c], b = kTriB[c];
@@ -304,13 +322,18 @@ __global__ __launch_bounds__(256) void k_correct_rigid(int64_t ntri, double *__r
                 if (bond_within(r, c, tm, s, diff)) continue;
                 done = false;
                 const double g = diff / (2.0 * dot(s, s) * (im[a] + im[b]));
+                if (!isfinite(g)) {
+                    outcome = kStatusNonFinite;
+                    break;
+                }
                 const double ga = g * im[a], gb = g * im[b];
                 r[a] = {r[a].x + ga * s.x, r[a].y + ga * s.y, r[a].z + ga * s.z};
                 r[b] = {r[b].x - gb * s.x, r[b].y - gb * s.y, r[b].z - gb * s.z};
             }
-            if (done) break;
+            if (done && outcome == kStatusConstraint) outcome = 0;
         }
-        constrain_velocities(r, vel, im, tm);
+        report_constraint(tm, outcome);
+        if (!outcome) report_constraint(tm, constrain_velocities(r, vel, im, tm));
         for (int a = 0; a < 3; a++) {
             double *l = lam + 6 * (3 * t + a);
             const double rv[3] = {r[a].x, r[a].y, r[a].z}, vv[3] = {vel[a].x, vel[a].y, vel[a].z};

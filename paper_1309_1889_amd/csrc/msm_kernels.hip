@@ -94,6 +94,7 @@ __global__ __launch_bounds__(ant_threads<PD>()) void k_anterp(DevPlan p, const v
     __shared__ int start[A::Cells + 1];   // staged position of each region cell's first atom
     __shared__ int gfirst[A::Cells];      // its sorted index
     __shared__ int wsum[NT / kWave];
+    if (eval_failed(p)) return;
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
     const int s = find_segment(p.ant_prefix, p.nsys, blk);
     const SysPlan &P = p.sys[s];
@@ -224,7 +225,7 @@ __global__ __launch_bounds__(256) void k_anterp_cells(DevPlan p, const vec4_t<T>
     using B = Basis<PD>;
     constexpr int S = B::S, W = 2 * S, NP = W * W * W;   // partials per cell
     constexpr int CPB = ant_cells_per_block<PD>();
-    if ((int)threadIdx.x >= CPB * NP) return;
+    if ((int)threadIdx.x >= CPB * NP || eval_failed(p)) return;
     // the cell index is uniform over each wave (NP is a multiple of 64 or CPB is 1)
     const int64_t c = (int64_t)blockIdx.x * CPB + uni((int)(threadIdx.x / NP));   // batch cell
     if (c >= p.ncells) return;
@@ -878,6 +879,9 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4
 {
     __shared__ double wpart[kInterpThreads / kWave];
     const int64_t blk = blockIdx.x;
+    // every stage that reads the failure flag has run (the pair sum joins
+    // before interpolation): clear it for the next evaluation
+    if (blk == 0 && threadIdx.x == 0 && p.evflag) *p.evflag = 0;
     const int s = find_segment(p.iblk_prefix, p.nsys, blk);
     const SysPlan &P = p.sys[s];
     const int64_t pos = P.atom0 + (blk - p.iblk_prefix[s]) * kInterpThreads + threadIdx.x;

@@ -104,7 +104,7 @@ extern "C" int msm_energy_forces_noalloc(const msm_params *params, void *stream,
     if (c->ctx_geom.nlev > MSM_NOALLOC_MAX_LEVELS) return MSM_ERR_CAPACITY;
     c->stream = (hipStream_t)stream;
     c->device = dev;
-    c->concurrent = false;
+    c->concurrent = 0;
     c->use_graphs = false;
     c->timing = false;
     c->tuning_pass = false;
@@ -113,7 +113,7 @@ extern "C" int msm_energy_forces_noalloc(const msm_params *params, void *stream,
     // scratch layout: work arrays | stencil columns | stencil weights | plan tables
     const size_t wbytes = up256(workspace_bytes(c));
     size_t cb = 0, wb = 0;
-    if (!c->mc.cutoff) stencil_image(c, &cb, &wb);
+    stencil_image(c, &cb, &wb);   // the lattice-cutoff or Wolf table, if the method has one
     const size_t o_cols = wbytes, o_w = o_cols + up256(cb), o_plan = o_w + up256(wb);
     if (o_plan + kPlanBytes > kScratchBytes) return MSM_ERR_CAPACITY;
     carve_workspace(c, d.ptr);
@@ -125,7 +125,7 @@ extern "C" int msm_energy_forces_noalloc(const msm_params *params, void *stream,
     // the work arrays keep the last call's contents: clear them (the charge
     // grid halos, the cell histogram and the status word must start at zero)
     if (fill_i32(c->stream, (int *)d.ptr, (int64_t)(wbytes / 4), 0) != hipSuccess) return MSM_ERR_HIP;
-    if (!c->mc.cutoff && (rc = put_stencil(c, d.ptr + o_cols, d.ptr + o_w))) return rc;
+    if ((rc = put_stencil(c, d.ptr + o_cols, d.ptr + o_w))) return rc;
     const int64_t offsets[2] = {0, natoms};
     if ((rc = build_plan(c, 1, offsets, nullptr))) return rc;
     if ((rc = evaluate_any(c, xyzq, energy, forces, pots))) return rc;

@@ -33,6 +33,39 @@ template <typename T> struct PairK {
     T d0, d1, d2;       // -(d/dr)(gamma(r/a)/a) / r = d0 + d1 r^2 (+ d2 r^4 for m = 3)
     T alpha, alpha2;    // Wolf damping alpha and alpha^2
     T wshift, wexp;     // erfc(alpha a)/a and 2 alpha / sqrt(pi)
+    const float4 *wtab; // single precision: the Wolf table (kWolfPieces pieces of E and D)
+    float wscale;       // kWolfPieces / a
+};
+
+// Wolf summation in single precision: E(r) = erfc(alpha r) and the force
+// numerator D(r) = E(r) + (2 alpha r / sqrt(pi)) exp(-alpha^2 r^2) from the
+// cubic pieces staged in LDS, so that
+// erfc(alpha r)/r - erfc(alpha a)/a = E rinv - wshift and
+// -(d/dr)(erfc(alpha r)/r) / r = D rinv^3.
+__device__ inline void wolf_lookup(const float4 *__restrict__ tab, float r, float scale, float &E, float &D)
+{
+    const float x = r * scale;
+    const int k = min((int)x, kWolfPieces - 1);
+    const float u = x - float(k);
+    const float4 ce = tab[2 * k], cd = tab[2 * k + 1];
+    E = ce.x + u * (ce.y + u * (ce.z + u * ce.w));
+    D = cd.x + u * (cd.y + u * (cd.z + u * cd.w));
+}
+
+// The table of a workgroup in LDS (all threads take part; one barrier).
+template <typename T, int KIND> struct WolfLds {
+    float4 t[1];
+    __device__ void load(const PairK<T> &) {}
+    __device__ const float4 *ptr() const { return nullptr; }
+};
+template <> struct WolfLds<float, 2> {
+    float4 t[2 * kWolfPieces];
+    __device__ void load(const PairK<float> &k)
+    {
+        for (int e = threadIdx.x; e < 2 * kWolfPieces; e += blockDim.x) t[e] = k.wtab[e];
+        __syncthreads();
+    }
+    __device__ const float4 *ptr() const { return t; }
 };
 
 // Pair kernel forms: the smoothing polynomial of degree at most 4 (MSM with
@@ -62,7 +95,8 @@ template <typename T, bool MD> struct PairLds {
 // that are asked for neither. KIND: one of PairKind.
 template <typename T, bool MD, bool POT, int KIND>
 __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const vec4_t<T> &aj, const vec4_t<T> &xj,
-                                 const PairK<T> &k, T &fx, T &fy, T &fz, T &u, T &lx, T &ly, T &lz, T &le)
+                                 const PairK<T> &k, T &fx, T &fy, T &fz, T &u, T &lx, T &ly, T &lz, T &le,
+                                 const float4 *wtab = nullptr)
 {
     const T dx = ai.x - aj.x, dy = ai.y - aj.y, dz = ai.z - aj.z;
     const T r2 = dx * dx + dy * dy + dz * dz;
@@ -75,7 +109,16 @@ __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const
             rc = same ? T(0) : rinv;
         }
         T br;
-        if (KIND == kWolf) {
+        if (KIND == kWolf && sizeof(T) == 4) {
+            // single precision: the tabulated E and D (an excluded pair, rc = 0,
+            // contributes nothing)
+            const T r = r2 * rinv;
+            const T on = rc * r;   // 1, or 0 for an excluded pair
+            float E, D;
+            wolf_lookup(wtab, float(r), k.wscale, E, D);
+            br = on * T(D) * rinv * rinv * rinv;
+            if (POT) u += aj.w * on * (T(E) * rinv - k.wshift);
+        } else if (KIND == kWolf) {
             // erfc(alpha r)/r - erfc(alpha a)/a, and -(d/dr)(erfc(alpha r)/r)/r
             // = (erfc(alpha r)/r + 2 alpha/sqrt(pi) exp(-alpha^2 r^2)) / r^2;
             // an excluded pair (rc = 0) contributes nothing
@@ -141,6 +184,10 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
     __shared__ PairLds<T, MD> lds[kPairWaves];
     __shared__ vec4_t<T> red[kPairWaves][kWave];
     __shared__ vec4_t<T> redlj[MD ? kPairWaves : 1][kWave];
+    __shared__ WolfLds<T, KIND> wl;
+    if (eval_failed(p)) return;
+    wl.load(k);
+    const float4 *wtab = wl.ptr();
     const int64_t g = blockIdx.x;
     const int s = find_segment(p.group_prefix, p.nsys, g);
     const SysPlan &P = p.sys[s];
@@ -255,12 +302,12 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
                 }
 #pragma unroll
                 for (int v = 0; v < kPairUnroll; ++v)
-                    pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le);
+                    pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le, wtab);
             }
             for (; t < cnt; ++t) {
                 const vec4_t<T> aj = L.atom[t];
                 const vec4_t<T> xj = MD ? L.aux[t] : aj;
-                pair_term<T, MD, POT, KIND>(ai, xi, aj, xj, k, fx, fy, fz, u, lx, ly, lz, le);
+                pair_term<T, MD, POT, KIND>(ai, xi, aj, xj, k, fx, fy, fz, u, lx, ly, lz, le, wtab);
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -330,6 +377,10 @@ __global__ __launch_bounds__(kSubLanes * kWave) void k_pair_sub(DevPlan p, const
                                                                 vec4_t<T> *__restrict__ ljout)
 {
     __shared__ PairLds<T, MD> lds[kWave / kSub];
+    __shared__ WolfLds<T, KIND> wl;
+    if (eval_failed(p)) return;
+    wl.load(k);
+    const float4 *wtab = wl.ptr();
     const int64_t g = blockIdx.x;
     const int s = find_segment(p.group_prefix, p.nsys, g);
     const SysPlan &P = p.sys[s];
@@ -437,14 +488,14 @@ __global__ __launch_bounds__(kSubLanes * kWave) void k_pair_sub(DevPlan p, const
                 }
 #pragma unroll
                 for (int v = 0; v < kSubUnroll; ++v)
-                    pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le);
+                    pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le, wtab);
             }
             for (; t < cnt; t += kSubLanes) {
                 const int tj = t + slot;
                 if (tj < cnt) {
                     const vec4_t<T> aj = L.atom[tj];
                     const vec4_t<T> xj = MD ? L.aux[tj] : aj;
-                    pair_term<T, MD, POT, KIND>(ai, xi, aj, xj, k, fx, fy, fz, u, lx, ly, lz, le);
+                    pair_term<T, MD, POT, KIND>(ai, xi, aj, xj, k, fx, fy, fz, u, lx, ly, lz, le, wtab);
                 }
             }
         }
@@ -559,6 +610,7 @@ __global__ __launch_bounds__(kWave) void k_clusters(DevPlan p, const vec4_t<T> *
                                                     int *__restrict__ cluster)
 {
     __shared__ vec4_t<T> grp[kWave];
+    if (eval_failed(p)) return;
     const int64_t g = blockIdx.x;
     const int s = find_segment(p.group_prefix, p.nsys, g);
     const SysPlan &P = p.sys[s];
@@ -596,6 +648,10 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
     constexpr int kSlots = kWave / CA;          // candidates per step
     constexpr int kBlock = kSlots * kClUnroll;  // candidates per evaluated block
     __shared__ ClLds<T, MD, NSUB> L;
+    __shared__ WolfLds<T, KIND> wl;
+    if (eval_failed(p)) return;
+    wl.load(k);   // before any wave of the workgroup can leave
+    const float4 *wtab = wl.ptr();
     const int lane = threadIdx.x % kWave;
     const int wv = uni((int)(threadIdx.x / kWave));
     // clusters of neighbouring groups share candidates: keep them on one XCD's L2
@@ -671,7 +727,7 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
 #pragma unroll
         for (int v = 0; v < kClUnroll; ++v)
             pair_term<T, MD, POT, KIND>(ai[sc], xi[sc], aj[v], xj[v], k, fx[sc], fy[sc], fz[sc], u[sc], lx[sc],
-                                        ly[sc], lz[sc], le[sc]);
+                                        ly[sc], lz[sc], le[sc], wtab);
         head[sc] += kBlock;
     };
     for (int ib = 0; ib < nitems; ib += kWave) {
@@ -888,6 +944,26 @@ static void pair_launch_m(hipStream_t s, const DevPlan &p, const Work<T> &w, con
 
 }  // namespace
 
+void wolf_table(double a, double alpha, float *out)
+{
+    const double c = 2.0 * alpha / std::sqrt(std::acos(-1.0)), dr = a / kWolfPieces;
+    auto E = [&](double r) { return std::erfc(alpha * r); };
+    auto dE = [&](double r) { return -c * std::exp(-alpha * alpha * r * r); };
+    auto D = [&](double r) { return std::erfc(alpha * r) + c * r * std::exp(-alpha * alpha * r * r); };
+    auto dD = [&](double r) { return -2.0 * alpha * alpha * c * r * r * std::exp(-alpha * alpha * r * r); };
+    auto piece = [&](double f0, double f1, double m0, double m1, float *o) {
+        o[0] = float(f0);
+        o[1] = float(m0);
+        o[2] = float(3.0 * (f1 - f0) - 2.0 * m0 - m1);
+        o[3] = float(2.0 * (f0 - f1) + m0 + m1);
+    };
+    for (int k = 0; k < kWolfPieces; k++) {
+        const double r0 = k * dr, r1 = (k + 1) * dr;
+        piece(E(r0), E(r1), dE(r0) * dr, dE(r1) * dr, out + 8 * k);
+        piece(D(r0), D(r1), dD(r0) * dr, dD(r1) * dr, out + 8 * k + 4);
+    }
+}
+
 template <typename T>
 hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m, bool pot)
 {
@@ -920,6 +996,9 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, co
     k.alpha2 = T(m.alpha * m.alpha);
     k.wshift = T(std::erfc(m.alpha * a) / a);
     k.wexp = T(2.0 * m.alpha / std::sqrt(std::acos(-1.0)));
+    k.wtab = m.wolf_tab;
+    k.wscale = float(kWolfPieces / a);
+    if (m.method == MSM_METHOD_WOLF && sizeof(T) == 4 && !k.wtab) return hipErrorInvalidValue;
     const int kind = m.method == MSM_METHOD_WOLF ? kWolf : (m.method == MSM_METHOD_MSM && m.g.m == 3 ? kPolyHigh : kPoly);
     switch (m.pair_waves) {
     case 1: pair_launch_m<T, 1>(s, p, w, k, pot, kind); break;

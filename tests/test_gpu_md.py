@@ -270,3 +270,31 @@ def test_mts_is_for_msm_contexts_only():
     with pytest.raises(msmx().MsmError) as ei:
         c.vv_mts_run(x, vv, 1, 2, 0.002)
     assert ei.value.code == -6
+
+
+def test_constraint_failure_is_a_status_not_a_hang():
+    """A tolerance below FP64 resolution cannot be met: every RATTLE loop
+    stops at its cap and the step reports MSM_ERR_CONSTRAINT (-7) through the
+    status word. A non-finite position stops the loops at once and reports
+    MSM_ERR_NONFINITE (-3). Both are ordinary status checks."""
+    m = msmx()
+    w, mass, molid, lj, tri, v = small_water(60, 1.6, seed=17)
+    ctx = m.MsmContext(1.0, 0.25, w.lo, w.hi, precision="fp64", ke=KE, max_atoms=w.n)
+    ctx.bind_model(len(mass), torch.tensor(molid, dtype=torch.int32, device="cuda"),
+                   torch.tensor(lj, dtype=torch.float64, device="cuda"), rigid=True, tri=tri, tol=1e-30)
+    x, vv = state_tensors(w.xyz, v, w.q, mass)
+    ctx.vv_run(x, vv, 1, 0.002, energies=False)
+    torch.cuda.synchronize()
+    assert ctx.status() == -7
+    assert ctx.status() == 0          # cleared after reading
+    ok = m.MsmContext(1.0, 0.25, w.lo, w.hi, precision="fp64", ke=KE, max_atoms=w.n)
+    ok.bind_model(len(mass), torch.tensor(molid, dtype=torch.int32, device="cuda"),
+                  torch.tensor(lj, dtype=torch.float64, device="cuda"), rigid=True, tri=tri)
+    x, vv = state_tensors(w.xyz, v, w.q, mass)
+    ok.vv_run(x, vv, 2, 0.002, energies=False)
+    torch.cuda.synchronize()
+    assert ok.status() == 0
+    vv[4, 0] = float("nan")
+    ok.vv_run(x, vv, 1, 0.002, energies=False)
+    torch.cuda.synchronize()
+    assert ok.status() == -3
