@@ -3,15 +3,19 @@
 A step is one complete evaluation of the method on one batch: binning,
 short-range pairs, anterpolation, restriction, lattice cutoff on every level,
 top level, prolongation, interpolation, combination and the FP64 energy
-reduction. The default workload is a water-like box of 99,999 atoms (33,333
-rigid 3-site molecules, TIP3P charges and geometry, random orientations, about
-100 atoms/nm^3 in a 10 nm cube; cutoff a = 1.2 nm, finest spacing
-h = 0.25 nm), with positions and charges already resident in HBM.
+reduction. The headline workload is the paper's 30 x 65 x 65 nm box of
+12,675,000 water-like atoms (4,225,000 rigid 3-site molecules, TIP3P charges
+and geometry, random orientations, about 100 atoms/nm^3; cutoff a = 1.2 nm,
+finest spacing h = 0.25 nm, 8 grids), with positions and charges already
+resident in HBM.
 
 Prints one JSON line: atom-steps/s of the single-precision path (value), the
 double-precision path beside it, the accuracy of both against the FP64 CPU
-oracle, a roofline record of the dominant kernel timed live with HIP events
-on the evaluation stream, and the oracle's own rate on the host cores.
+oracle on the same box, a roofline record of the dominant kernel timed live
+with HIP events on the evaluation stream, the oracle's own rate on the host
+cores, and secondary records (the 99,999-atom box, batches of parareal slice
+states, parareal, dynamics of the large box with energy drift, orders,
+multiple time steps, the sliding window).
 """
 from __future__ import annotations
 
@@ -44,9 +48,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--workload", default="water_99999")
+    ap.add_argument("--workload", default="water_12675000")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="bound on the oracle's CPU-baseline sample")
+                    help="bound on the oracle's single-thread CPU-baseline sample")
+    ap.add_argument("--no-small", action="store_true", help="skip the secondary 99,999-atom record")
+    ap.add_argument("--equilibrate-ps", type=float, default=1.0,
+                    help="velocity-rescaled equilibration before the energy-drift runs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
@@ -55,6 +62,9 @@ def parse():
     ap.add_argument("--slices", type=int, default=32)
     ap.add_argument("--no-graphs", action="store_true", help="time eager launches only")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
+    ap.add_argument("--tuning", default=None,
+                    help="pair_waves,stencil_threads,concurrent for the headline workload instead of autotuning "
+                         "(for profiler runs)")
     ap.add_argument("--no-orders", action="store_true", help="skip the smoothing-order / basis-degree study")
     ap.add_argument("--no-mts", action="store_true", help="skip the multiple-time-step dynamics")
     ap.add_argument("--no-window", action="store_true", help="skip the sliding-window parareal runs")
@@ -67,16 +77,29 @@ def parse():
     args = ap.parse_args()
     if args.only_fp32:
         args.no_fp64 = args.no_accuracy = args.no_cpu_baseline = args.no_batched = args.no_parareal = True
-        args.no_large = args.no_orders = args.no_mts = args.no_window = True
+        args.no_large = args.no_orders = args.no_mts = args.no_window = args.no_small = True
     return args
 
 
-def unique_pairs(xyz, a):
-    """Unique atom pairs closer than a (counted exactly on the input)."""
+def unique_pairs(xyz, a, chunk=1 << 20):
+    """Unique atom pairs closer than a, counted exactly on the input (a k-d
+    tree, every host thread)."""
     from scipy.spatial import cKDTree
     t = cKDTree(xyz)
-    ordered = t.count_neighbors(t, a)
-    return int((ordered - xyz.shape[0]) // 2)
+    total = 0
+    for c0 in range(0, xyz.shape[0], chunk):
+        total += int(t.query_ball_point(xyz[c0:c0 + chunk], a, return_length=True, workers=-1).sum())
+    return (total - xyz.shape[0]) // 2
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def timed_steps(torch, ctx, xyzq, out, steps, warmup):
@@ -132,24 +155,20 @@ def traffic_record(kernel_file, kernel_name, workload, form):
     return None if got is None else got.get("bytes_per_launch")
 
 
-def bench_batched(torch, msmx, w32, steps, warmup, slices, single_value, autotune=True):
-    """One evaluation of `slices` systems of the water box at once (the fine
-    propagator's batch in parareal), and an uneven batch of 8 water boxes of
-    9,999 .. 200,001 atoms against evaluating them one by one."""
+def bench_batched(torch, msmx, states, q, lo, hi, steps, warmup, autotune=True):
+    """One evaluation of all parareal slice states at once (the fine
+    propagator's batch: the serial-fine states at the start of every slice of
+    the parareal workload, each a different configuration), against one of
+    them alone; and an uneven batch of 8 water boxes of 9,999 .. 200,001 atoms
+    against evaluating them one by one."""
     from workloads import uneven_batch_sizes, water_box, water_box_dims
     dev = torch.device("cuda", 0)
-    n = w32.n
-    rng = np.random.default_rng(44)
-    base = w32.xyzq(np.float32)
-    xs = []
-    for s in range(slices):   # each slice jittered by up to 5 pm, all inside the domain
-        x = base.copy()
-        x[:, :3] += rng.uniform(-0.005, 0.005, size=(n, 3)).astype(np.float32)
-        xs.append(x)
-    xyzq = torch.tensor(np.concatenate(xs), device=dev)
+    slices, n = states.shape[0], states.shape[1]
+    xyzq = torch.empty((slices * n, 4), dtype=torch.float32, device=dev)
+    xyzq.view(slices, n, 4)[:, :, :3] = states.float()
+    xyzq.view(slices, n, 4)[:, :, 3] = q.float()[None, :]
     offs = np.arange(slices + 1, dtype=np.int64) * n
-    ctx = msmx.MsmContext(w32.a, w32.h, w32.lo, w32.hi, precision="fp32", max_atoms=slices * n,
-                          max_systems=slices)
+    ctx = msmx.MsmContext(1.2, 0.25, lo, hi, precision="fp32", max_atoms=slices * n, max_systems=slices)
     out = (torch.empty(slices, dtype=torch.float64, device=dev),
            torch.empty((slices * n, 3), dtype=torch.float32, device=dev),
            torch.empty(slices * n, dtype=torch.float32, device=dev))
@@ -172,15 +191,25 @@ def bench_batched(torch, msmx, w32, steps, warmup, slices, single_value, autotun
     torch.cuda.synchronize()
     ctx.check()
     ms = e0.elapsed_time(e1) / k
-    # slice 0 of the batch against the single-system context: identical bits
-    one = msmx.MsmContext(w32.a, w32.h, w32.lo, w32.hi, precision="fp32", max_atoms=n)
+    # slice 0 of the batch against a single-system context with the same
+    # launch configuration: identical bits; and its time per atom
+    one = msmx.MsmContext(1.2, 0.25, lo, hi, precision="fp32", max_atoms=n)
     one.set_tuning(**tuning)
-    e_1, f_1, _ = one.energy_forces(xyzq[:n].contiguous())
+    x0 = xyzq[:n].contiguous()
+    e_1, f_1, _ = one.energy_forces(x0)
     torch.cuda.synchronize()
     same = bool(torch.equal(f_1, out[1][:n]) and torch.equal(e_1, out[0][:1]))
-    batched = {"systems": slices, "atoms": slices * n, "ms_per_step": ms, "tuning": tuning,
+    o1 = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float32, device=dev),
+          torch.empty(n, dtype=torch.float32, device=dev))
+    ms1 = timed_steps(torch, one, x0, o1, max(steps, 10), warmup)
+    one.check()
+    spread = float((states - states[:1]).abs().amax(dim=(1, 2)).max().item())
+    batched = {"workload": f"{slices} parareal slice states x {n} atoms (serial fine, 20 fs apart), one call",
+               "systems": slices, "atoms": slices * n, "ms_per_step": ms, "tuning": tuning,
                "value": slices * n / (ms * 1e-3), "unit": "atom-steps/s",
-               "speedup_vs_single_system": slices * n / (ms * 1e-3) / single_value,
+               "single_system_ms": ms1,
+               "speedup_vs_single_system": (slices * n / (ms * 1e-3)) / (n / (ms1 * 1e-3)),
+               "largest_position_change_between_states_nm": spread,
                "slice0_bitwise_equal_to_single": same}
 
     # uneven batch
@@ -263,6 +292,15 @@ def bench_parareal(torch, msmx, slices, n_atoms=99999):
     torch.cuda.synchronize()
     serial_s = time.perf_counter() - t0
     serial.check()
+    # the state at the start of every slice (for the batched evaluation leg)
+    states = torch.empty((slices, w.n, 3), dtype=torch.float64, device=dev)
+    xs, vs = torch.cat([s0[:, :3], q[:, None]], 1).contiguous(), vv.clone()
+    vs.copy_(torch.cat([s0[:, 3:], invm[:, None]], 1))
+    for k in range(slices):
+        states[k] = xs[:, :3]
+        serial.vv_run(xs, vs, 10, 0.002, energies=False)
+    torch.cuda.synchronize()
+    assert torch.equal(xs, x)   # the same serial trajectory
     out = {"workload": f"{slices} slices x {w.n} atoms, rigid water at 300 K, fine 10 x 2 fs (a 1.2, h 0.25)",
            "serial_fine_seconds": serial_s}
     # coarse propagators: the configured one (MSM, one 20 fs step), a stable MSM
@@ -299,7 +337,7 @@ def bench_parareal(torch, msmx, slices, n_atoms=99999):
         out[name] = rec
         del coarse
     out["fine_step_ms"] = serial_s / (slices * 10) * 1e3
-    return out
+    return out, (states, q, w.lo, w.hi)
 
 
 def exact_coulomb_rows(xyz, q, sel, ke=138.935458, chunk=64):
@@ -415,7 +453,98 @@ def bench_window(torch, msmx, slices=50, width=5, tol=1e-4, n_atoms=99999):
     return out
 
 
-def bench_mts(torch, msmx, inner_steps=100, dt_inner=0.002):
+KB = 8.314462618e-3   # kJ/(mol K)
+
+
+def rigid_dof(n_atoms):
+    """Degrees of freedom of rigid 3-site molecules with the total momentum removed."""
+    return 6 * (n_atoms // 3) - 3
+
+
+def equilibrate(torch, ctx, x, vel, ps, dt=0.002, temperature=300.0, every=10):
+    """Velocity Verlet with the velocities rescaled to `temperature` every
+    `every` steps (uniform scaling keeps the rigid constraints), for `ps`
+    picoseconds. Returns the temperatures seen before each rescaling."""
+    dof = rigid_dof(x.shape[0])
+    temps = []
+    for _ in range(max(int(round(ps / (dt * every))), 0)):
+        _, ek = ctx.vv_run(x, vel, every, dt)
+        t = 2.0 * ek.item() / (dof * KB)
+        temps.append(t)
+        vel[:, :3] *= float(np.sqrt(temperature / t))
+    torch.cuda.synchronize()
+    return temps
+
+
+def nve_series(torch, ctx, x, vel, nsteps, dt, chunk):
+    """Total energy after every `chunk` steps of plain velocity Verlet."""
+    ep, ek = ctx.vv_run(x, vel, 0, dt)
+    es, ks = [ep.item() + ek.item()], [ek.item()]
+    for _ in range(nsteps // chunk):
+        ep, ek = ctx.vv_run(x, vel, chunk, dt)
+        es.append(ep.item() + ek.item())
+        ks.append(ek.item())
+    return np.array(es), np.array(ks)
+
+
+def drift_record(es, ks, dt, chunk, n_atoms):
+    """Drift (slope of a least-squares line through E(t)) per ps and per
+    degree of freedom, the RMS fluctuation about that line, and the start and
+    end temperatures."""
+    dof = rigid_dof(n_atoms)
+    t = np.arange(len(es)) * chunk * dt
+    slope, icept = np.polyfit(t, es, 1)
+    resid = es - (slope * t + icept)
+    return {"dt_fs": dt * 1000, "steps": int((len(es) - 1) * chunk), "ps": float(t[-1]),
+            "drift_kj_mol_per_ps_per_dof": float(slope / dof),
+            "drift_relative_to_kinetic_per_ps": float(slope / ks.mean()),
+            "energy_change_relative_to_kinetic": float((es[-1] - es[0]) / ks.mean()),
+            "rms_fluctuation_kj_mol_per_dof": float(np.sqrt((resid ** 2).mean()) / dof),
+            "temperature_start_k": float(2 * ks[0] / (dof * KB)), "temperature_end_k": float(2 * ks[-1] / (dof * KB))}
+
+
+def dt_halving(torch, ctx, x, vel, ps, dt, chunk_ps=0.02):
+    """The same NVE stretch from the same equilibrated state with dt and
+    dt/2: velocity Verlet is second order, so the energy fluctuation (and a
+    drift that the integrator causes) should shrink about 4 times."""
+    rec = {}
+    for name, d in (("dt", dt), ("dt_half", dt / 2)):
+        xs, vs = x.clone(), vel.clone()
+        steps = int(round(ps / d))
+        chunk = max(int(round(chunk_ps / d)), 1)
+        es, ks = nve_series(torch, ctx, xs, vs, steps, d, chunk)
+        rec[name] = drift_record(es, ks, d, chunk, x.shape[0])
+        del xs, vs
+    rec["fluctuation_ratio"] = rec["dt"]["rms_fluctuation_kj_mol_per_dof"] / rec["dt_half"]["rms_fluctuation_kj_mol_per_dof"]
+    rec["drift_ratio"] = rec["dt"]["drift_kj_mol_per_ps_per_dof"] / rec["dt_half"]["drift_kj_mol_per_ps_per_dof"]
+    return rec
+
+
+def bench_dt_halving(torch, msmx, equilibrate_ps=1.0, ps=0.4):
+    """Second order of velocity Verlet on the GPU path: a 2,997-atom rigid
+    water box in FP64 (so that the integrator's error, not the rounding of
+    single-precision forces, sets the energy fluctuation), equilibrated at
+    300 K, then the same NVE stretch with dt = 2 fs and 1 fs."""
+    from workloads import rigid_water_velocities, water_box, water_model_arrays
+    dev = torch.device("cuda", 0)
+    w = water_box(999, (10, 10, 10), (3.1, 3.1, 3.1), seed=61, margin=1.5)
+    mass, molid, lj, tri = water_model_arrays(w.n)
+    v = rigid_water_velocities(w.xyz, 300.0, seed=62)
+    c = msmx.MsmContext(1.0, 0.25, w.lo, w.hi, precision="fp64", max_atoms=w.n)
+    c.bind_model(w.n, torch.tensor(molid, dtype=torch.int32, device=dev), torch.tensor(lj, device=dev), rigid=True,
+                 tri=tri)
+    c.set_graphs(True)
+    x = torch.tensor(np.concatenate([w.xyz, w.q[:, None]], 1), device=dev).contiguous()
+    vel = torch.tensor(np.concatenate([v, 1.0 / mass[:, None]], 1), device=dev).contiguous()
+    temps = equilibrate(torch, c, x, vel, equilibrate_ps, 0.002)
+    rec = dt_halving(torch, c, x, vel, ps, 0.002, chunk_ps=0.01)
+    c.check()
+    return {"workload": f"{w.n} atoms, rigid water, a 1.0 nm, h 0.25 nm, FP64; {ps:g} ps NVE after "
+                        f"{equilibrate_ps:g} ps rescaled to 300 K", "equilibration_temperature_k":
+            [round(t, 1) for t in temps[::10]], **rec}
+
+
+def bench_mts(torch, msmx, inner_steps=100, dt_inner=0.002, equilibrate_ps=1.0):
     """Multiple time steps on the 99,999-atom water box (rigid water at 300 K,
     FP32 forces): the grid part every 1 (plain velocity Verlet), 2 and 4
     inner steps of 2 fs; time per inner step and total-energy drift."""
@@ -429,10 +558,13 @@ def bench_mts(torch, msmx, inner_steps=100, dt_inner=0.002):
     c.bind_model(w.n, torch.tensor(molid, dtype=torch.int32, device=dev), torch.tensor(lj, device=dev), rigid=True,
                  tri=tri)
     c.set_graphs(True)
+    # start every variant from one state equilibrated at 300 K
+    x0 = torch.tensor(np.concatenate([w.xyz, w.q[:, None]], 1), device=dev).contiguous()
+    v0 = torch.tensor(np.concatenate([v, 1.0 / mass[:, None]], 1), device=dev).contiguous()
+    temps = equilibrate(torch, c, x0, v0, equilibrate_ps, dt_inner)
     rec = []
     for ninner in (1, 2, 4):
-        x = torch.tensor(np.concatenate([w.xyz, w.q[:, None]], 1), device=dev).contiguous()
-        vv = torch.tensor(np.concatenate([v, 1.0 / mass[:, None]], 1), device=dev).contiguous()
+        x, vv = x0.clone(), v0.clone()
         dt = dt_inner * ninner
         c.vv_mts_run(x.clone(), vv.clone(), 2, ninner, dt, energies=False)   # warm-up, graphs captured
         ep0, ek0 = c.vv_mts_run(x, vv, 0, ninner, dt)
@@ -443,62 +575,183 @@ def bench_mts(torch, msmx, inner_steps=100, dt_inner=0.002):
         secs = time.perf_counter() - t0
         c.check()
         e0, e1 = ep0.item() + ek0.item(), ep1.item() + ek1.item()
+        dof = rigid_dof(w.n)
+        ps = inner_steps * dt_inner
         rec.append({"grid_every_inner_steps": ninner, "dt_outer_fs": dt * 1000, "inner_steps": inner_steps,
                     "ms_per_inner_step": secs / inner_steps * 1e3,
-                    "drift_relative_to_kinetic": (e1 - e0) / ek0.item()})
-    return {"workload": f"{w.n} atoms, rigid water at 300 K, a 1.2 nm, h 0.25 nm, FP32 forces, inner step "
-                        f"{dt_inner * 1000:g} fs", "variants": rec}
+                    "drift_kj_mol_per_ps_per_dof": (e1 - e0) / ps / dof,
+                    "drift_relative_to_kinetic": (e1 - e0) / ek0.item(),
+                    "temperature_start_k": 2 * ek0.item() / (dof * KB),
+                    "temperature_end_k": 2 * ek1.item() / (dof * KB)})
+    return {"workload": f"{w.n} atoms, rigid water, a 1.2 nm, h 0.25 nm, FP32 forces, inner step "
+                        f"{dt_inner * 1000:g} fs; every variant starts from one state after "
+                        f"{equilibrate_ps:g} ps of velocity Verlet rescaled to 300 K",
+            "equilibration_temperature_k": [round(t, 1) for t in temps[::10]], "variants": rec}
 
 
-def bench_large(torch, msmx, steps=100, dt=0.002):
-    """The paper's 30 x 65 x 65 nm box with 12,675,000 water-like atoms: one
-    FP32 evaluation timed, then `steps` velocity-Verlet steps of the rigid
-    water model with the total-energy drift."""
-    from workloads import named, rigid_water_velocities, water_model_arrays
+def bench_large(torch, msmx, w64, steps=100, dt=0.002, equilibrate_ps=1.0):
+    """Dynamics of the paper's 30 x 65 x 65 nm box (12,675,000 water-like
+    atoms, rigid water model, FP32 forces, FP64 state): velocity-Verlet step
+    rate, then the energy drift over `steps` steps of dt from a state
+    equilibrated at 300 K, and the same stretch at dt/2."""
+    from workloads import rigid_water_velocities, water_model_arrays
     dev = torch.device("cuda", 0)
-    w64 = named("water_12675000", margin=1.0)
     w = w64.as_dtype(np.float32)
     n = w.n
-    ctx = msmx.MsmContext(w.a, w.h, w.lo, w.hi, precision="fp32", max_atoms=n)
-    x = torch.tensor(w.xyzq(np.float32), device=dev)
-    out = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float32, device=dev),
-           torch.empty(n, dtype=torch.float32, device=dev))
-    tuning = ctx.autotune(x, reps=2)
-    ctx.set_graphs(True)
-    ms = timed_steps(torch, ctx, x, out, 10, 2)
-    ctx.check()
-    del ctx, out
     mass, molid, lj, tri = water_model_arrays(n)
     v = rigid_water_velocities(w64.xyz, 300.0, seed=105)
     md = msmx.MsmContext(w.a, w.h, w.lo, w.hi, precision="fp32", max_atoms=n)
     md.bind_model(n, torch.tensor(molid, dtype=torch.int32, device=dev), torch.tensor(lj, device=dev), rigid=True,
                   tri=tri)
     md.set_graphs(True)
-    # FP64 integrator state, FP32 force evaluation
-    del x
     x = torch.tensor(np.concatenate([w64.xyz, w64.q[:, None]], 1), device=dev).contiguous()
     vel = torch.tensor(np.concatenate([v, 1.0 / mass[:, None]], 1), device=dev).contiguous()
-    del w64, v
-    ep0, ek0 = md.vv_run(x, vel, 0, dt)
+    del v
+    temps = equilibrate(torch, md, x, vel, equilibrate_ps, dt)
+    md.check()
+    # step rate (graphs captured in the equilibration)
+    xs, vs = x.clone(), vel.clone()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    ep1, ek1 = md.vv_run(x, vel, steps, dt)
+    md.vv_run(xs, vs, steps, dt, energies=False)
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
     md.check()
-    e0, e1 = ep0.item() + ek0.item(), ep1.item() + ek1.item()
-    return {"workload": f"{n} atoms, 30x65x65 nm rigid water, a 1.2 nm, h 0.25 nm, {len(md.grid_shape())} grids, FP32 forces, FP64 state",
-            "eval_ms": ms, "eval_atom_steps_per_s": n / (ms * 1e-3), "eval_tuning": tuning,
-            "vv_steps": steps, "dt_ps": dt, "vv_seconds": secs, "vv_atom_steps_per_s": n * steps / secs,
-            "energy_start_kj_mol": e0, "energy_end_kj_mol": e1,
-            "drift_kj_mol_per_ps": (e1 - e0) / (steps * dt),
-            "drift_relative_to_kinetic": (e1 - e0) / ek0.item(),
-            "kinetic_start": ek0.item(), "kinetic_end": ek1.item()}
+    del xs, vs
+    halving = dt_halving(torch, md, x, vel, steps * dt, dt)
+    md.check()
+    return {"workload": f"{n} atoms, 30x65x65 nm rigid water, a 1.2 nm, h 0.25 nm, {len(md.grid_shape())} grids, "
+                        f"FP32 forces, FP64 state; drift from a state after {equilibrate_ps:g} ps of velocity "
+                        f"Verlet rescaled to 300 K",
+            "vv_steps": steps, "dt_ps": dt, "vv_seconds": secs, "vv_ms_per_step": secs / steps * 1e3,
+            "vv_atom_steps_per_s": n * steps / secs,
+            "equilibration_temperature_k": [round(t, 1) for t in temps[::5]],
+            "drift": halving["dt"], "drift_dt_half": halving["dt_half"],
+            "fluctuation_ratio_dt_vs_half": halving["fluctuation_ratio"],
+            "drift_ratio_dt_vs_half": halving["drift_ratio"]}
 
 
 def log(msg):
     """Progress of the legs on stderr (the JSON line alone goes to stdout)."""
     print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def big_workload(w):
+    return w.n > 2_000_000
+
+
+def single_fp32(torch, msmx, w32, args, reps):
+    """The single-system FP32 path: default launch configuration, then the
+    autotuned one eagerly and as a graph replay; stage times in turn."""
+    dev = torch.device("cuda", 0)
+    n = w32.n
+    ctx = msmx.MsmContext(w32.a, w32.h, w32.lo, w32.hi, precision="fp32", max_atoms=n)
+    x32 = torch.tensor(w32.xyzq(np.float32), device=dev)
+    out = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float32, device=dev),
+           torch.empty(n, dtype=torch.float32, device=dev))
+    eager_default_ms = timed_steps(torch, ctx, x32, out, args.steps, args.warmup)
+    if args.tuning and big_workload(w32):
+        pw, st, cc = (int(v) for v in args.tuning.split(","))
+        ctx.set_tuning(pair_waves=pw, stencil_threads=st, concurrent=cc)
+        tuning = ctx.tuning()
+    else:
+        tuning = ctx.autotune(x32, reps=reps) if not args.no_autotune else ctx.tuning()
+    graph_ms = None
+    if not args.no_graphs:
+        ctx.set_graphs(True)
+        graph_ms = timed_steps(torch, ctx, x32, out, args.steps, args.warmup)
+        ctx.check()
+        ctx.set_graphs(False)
+    eager_tuned_ms = timed_steps(torch, ctx, x32, out, args.steps, args.warmup)
+    stages = stage_profile(torch, ctx, x32, out, max(args.steps // 2, 3))
+    ctx.check()
+    # the headline uses the faster of the two launch modes; both are reported
+    mode = "graph" if graph_ms is not None and graph_ms < eager_tuned_ms else "eager"
+    ms = graph_ms if mode == "graph" else eager_tuned_ms
+    launch = {"mode": mode, "tuning": tuning, "graph_ms_per_step": graph_ms,
+              "eager_default_ms_per_step": eager_default_ms, "eager_tuned_ms_per_step": eager_tuned_ms}
+    return ms, stages, launch, ctx, x32, out
+
+
+def single_fp64(torch, msmx, w32, args, reps):
+    dev = torch.device("cuda", 0)
+    n = w32.n
+    ctx64 = msmx.MsmContext(w32.a, w32.h, w32.lo, w32.hi, precision="fp64", max_atoms=n)
+    x64 = torch.tensor(w32.xyzq(np.float64), device=dev)
+    out64 = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float64, device=dev),
+             torch.empty(n, dtype=torch.float64, device=dev))
+    tuning64 = ctx64.autotune(x64, reps=reps) if not args.no_autotune else ctx64.tuning()
+    k = max(args.steps // 4, 3)
+    ms64 = timed_steps(torch, ctx64, x64, out64, k, max(args.warmup // 2, 1))
+    if not args.no_graphs:
+        ctx64.set_graphs(True)
+        ms64 = min(ms64, timed_steps(torch, ctx64, x64, out64, k, max(args.warmup // 2, 1)))
+        ctx64.check()
+        ctx64.set_graphs(False)
+    stages64 = stage_profile(torch, ctx64, x64, out64, k)
+    ctx64.check()
+    rec = {"value": n / (ms64 * 1e-3), "ms_per_step": ms64, "tuning": tuning64,
+           "stage_ms": {k_: round(v, 5) for k_, v in stages64.items()}}
+    del ctx64, x64
+    return rec, out64
+
+
+def roofline_of(stages, pairs, shapes, taps, form, workload):
+    """Per-stage records and the roofline of the dominant kernel (algorithmic
+    flops over the stage's HIP-event time)."""
+    work = {"short": FLOPS_PER_PAIR * pairs, "cutoff": stencil_flops(shapes, taps)}
+    dominant = max(stages, key=stages.get)
+    kernels = {}
+    for st, ms in stages.items():
+        rec = {"ms": round(ms, 5)}
+        if st in work:
+            rec["tflops"] = round(work[st] / (ms * 1e-3) / 1e12, 3)
+            rec["frac_fp32_valu"] = round(work[st] / (ms * 1e-3) / 1e12 / PEAK_FP32_VALU, 4)
+        kernels[st] = rec
+    if dominant in work:
+        achieved = work[dominant] / (stages[dominant] * 1e-3) / 1e12
+        kname = {"short": "pair_short", "cutoff": "stencil"}[dominant]
+        roofline = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU,
+                    "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU, 4),
+                    "traffic": traffic_record("pair.hip", kname, workload, form) if dominant == "short" else None,
+                    "algorithmic_flops_per_launch": float(work[dominant]), "kernel_ms": round(stages[dominant], 5),
+                    "unique_pairs": int(pairs), "flops_per_pair": FLOPS_PER_PAIR, "stencil_taps": taps}
+    else:
+        roofline = {"bound": "hbm", "kernel": dominant, "achieved": None, "peak": PEAK_HBM, "unit": "GB/s",
+                    "frac": None, "traffic": None}
+    return roofline, kernels
+
+
+def rel_rms(x, ref):
+    return float(np.sqrt(((x - ref) ** 2).sum() / (ref ** 2).sum()))
+
+
+def small_box_record(torch, msmx, args):
+    """The 99,999-atom water box (10 nm cube, 5 grids): FP32 and FP64 single
+    evaluations, the pair kernel's roofline there, and the accuracy against
+    the oracle."""
+    from workloads import named
+    w32 = named("water_99999").as_dtype(np.float32)
+    ms32, stages32, launch, ctx, x32, out32 = single_fp32(torch, msmx, w32, args, 5)
+    pairs = unique_pairs(w32.xyz, w32.a)
+    roofline, kernels = roofline_of(stages32, pairs, ctx.grid_shape(), sphere_taps(w32.a, w32.h),
+                                    ctx.tuning()["pair_waves"], "water_99999")
+    rec = {"workload": f"water_99999: {w32.n} atoms, 10 nm cube, a 1.2 nm, h 0.25 nm, 5 grids",
+           "fp32_ms_per_step": ms32, "fp32_value": w32.n / (ms32 * 1e-3), "launch": launch,
+           "roofline": roofline, "stage_ms": kernels}
+    fp64, out64 = (None, None) if args.no_fp64 else single_fp64(torch, msmx, w32, args, 5)
+    rec["fp64_plain"] = fp64
+    if fp64:
+        rec["speedup_fp32_vs_fp64_plain"] = rec["fp32_value"] / fp64["value"]
+    if not args.no_accuracy:
+        import oracle
+        eo, fo, po = oracle.msm(oracle.OracleParams.of(w32), w32.xyz, w32.q)
+        rec["accuracy"] = {"fp32_force_rel_rms": rel_rms(out32[1].double().cpu().numpy(), fo),
+                           "fp32_energy_rel": abs(out32[0].item() - eo) / abs(eo)}
+        if out64 is not None:
+            rec["accuracy"]["fp64_force_rel_rms"] = rel_rms(out64[1].cpu().numpy(), fo)
+            rec["accuracy"]["fp64_energy_rel"] = abs(out64[0].item() - eo) / abs(eo)
+    return rec
 
 
 def main():
@@ -512,137 +765,111 @@ def main():
     import paper_1309_1889_amd as msmx
     from workloads import named
 
-    w32 = named(args.workload).as_dtype(np.float32)
+    w64 = named(args.workload)
+    w32 = w64.as_dtype(np.float32)
     n = w32.n
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
+    big = big_workload(w32)
+    log(f"{args.workload}: {n} atoms")
 
     result = {"metric": METRIC}
     # ---- single-precision path (the headline) ----
-    ctx = msmx.MsmContext(w32.a, w32.h, w32.lo, w32.hi, precision="fp32", max_atoms=n)
-    x32 = torch.tensor(w32.xyzq(np.float32), device=dev)
-    out32 = (torch.empty(1, dtype=torch.float64, device=dev), torch.empty((n, 3), dtype=torch.float32, device=dev),
-             torch.empty(n, dtype=torch.float32, device=dev))
-    eager_default_ms = timed_steps(torch, ctx, x32, out32, args.steps, args.warmup)
-    tuning32 = ctx.autotune(x32, reps=5) if not args.no_autotune else ctx.tuning()
-    graph_ms = None
-    if not args.no_graphs:
-        ctx.set_graphs(True)
-        graph_ms = timed_steps(torch, ctx, x32, out32, args.steps, args.warmup)
-        ctx.check()
-        ctx.set_graphs(False)
-    eager_tuned_ms = timed_steps(torch, ctx, x32, out32, args.steps, args.warmup)
-    stages32 = stage_profile(torch, ctx, x32, out32, args.steps)
-    # the headline uses the faster of the two launch modes; both are reported
-    launch_mode = "graph" if graph_ms is not None and graph_ms < eager_tuned_ms else "eager"
-    ms32 = graph_ms if launch_mode == "graph" else eager_tuned_ms
+    ms32, stages32, launch, ctx, x32, out32 = single_fp32(torch, msmx, w32, args, 2 if big else 5)
     value = n / (ms32 * 1e-3)
+    shapes = ctx.grid_shape()
+    form = ctx.tuning()["pair_waves"]
     if args.copy_calibration_mib > 0:
         src = torch.ones(args.copy_calibration_mib * (1 << 18), dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         for _ in range(5):
             dst.copy_(src)
         torch.cuda.synchronize()
+        del src, dst
+    del ctx, x32
+    log(f"fp32 {ms32:.4f} ms per evaluation")
 
-    # ---- double-precision plain path ----
-    fp64 = None
-    out64 = None
-    if not args.no_fp64:
-        ctx64 = msmx.MsmContext(w32.a, w32.h, w32.lo, w32.hi, precision="fp64", max_atoms=n)
-        x64 = torch.tensor(w32.xyzq(np.float64), device=dev)
-        out64 = (torch.empty(1, dtype=torch.float64, device=dev),
-                 torch.empty((n, 3), dtype=torch.float64, device=dev),
-                 torch.empty(n, dtype=torch.float64, device=dev))
-        tuning64 = ctx64.autotune(x64, reps=5) if not args.no_autotune else ctx64.tuning()
-        ms64 = timed_steps(torch, ctx64, x64, out64, max(args.steps // 2, 1), args.warmup)
-        if not args.no_graphs:
-            ctx64.set_graphs(True)
-            ms64 = min(ms64, timed_steps(torch, ctx64, x64, out64, max(args.steps // 2, 1), args.warmup))
-            ctx64.check()
-            ctx64.set_graphs(False)
-        stages64 = stage_profile(torch, ctx64, x64, out64, max(args.steps // 2, 1))
-        fp64 = {"value": n / (ms64 * 1e-3), "ms_per_step": ms64, "tuning": tuning64,
-                "stage_ms": {k: round(v, 5) for k, v in stages64.items()}}
+    # ---- double-precision plain path on the same box ----
+    fp64, out64 = (None, None) if args.no_fp64 else single_fp64(torch, msmx, w32, args, 2 if big else 5)
+    if fp64:
+        log(f"fp64 {fp64['ms_per_step']:.4f} ms per evaluation")
 
     # ---- roofline of the dominant kernel (timed live, HIP events on the context stream) ----
     pairs = unique_pairs(w32.xyz, w32.a)
-    shapes = ctx.grid_shape()
-    taps = sphere_taps(w32.a, w32.h)
-    work = {
-        "short": FLOPS_PER_PAIR * pairs,
-        "cutoff": stencil_flops(shapes, taps),
-    }
-    dominant = max(stages32, key=stages32.get)
-    kernels = {}
-    for st, ms in stages32.items():
-        rec = {"ms": round(ms, 5)}
-        if st in work:
-            rec["tflops"] = round(work[st] / (ms * 1e-3) / 1e12, 3)
-            rec["frac_fp32_valu"] = round(work[st] / (ms * 1e-3) / 1e12 / PEAK_FP32_VALU, 4)
-        kernels[st] = rec
-    if dominant in work:
-        achieved = work[dominant] / (stages32[dominant] * 1e-3) / 1e12
-        kfile = "pair.hip"
-        kname = {"short": "pair_short", "cutoff": "stencil"}[dominant]
-        roofline = {"bound": "alu", "kernel": kname, "achieved": round(achieved, 3), "peak": PEAK_FP32_VALU,
-                    "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_VALU, 4),
-                    "traffic": traffic_record(kfile, kname, args.workload, ctx.tuning()["pair_waves"])
-                    if dominant == "short" else None,
-                    "algorithmic_flops_per_launch": float(work[dominant]),
-                    "unique_pairs": pairs, "flops_per_pair": FLOPS_PER_PAIR, "stencil_taps": taps}
-    else:
-        roofline = {"bound": "hbm", "kernel": dominant, "achieved": None, "peak": PEAK_HBM, "unit": "GB/s",
-                    "frac": None, "traffic": None}
+    roofline, kernels = roofline_of(stages32, pairs, shapes, sphere_taps(w32.a, w32.h), form, args.workload)
+    log(f"{pairs} unique pairs inside the cutoff")
 
-    # ---- accuracy against the FP64 oracle, and the oracle as the CPU baseline ----
+    # ---- accuracy against the FP64 oracle; the oracle as the CPU baseline ----
     accuracy = None
     cpu = None
     if not (args.no_accuracy and args.no_cpu_baseline):
         import oracle
-        p = oracle.OracleParams.of(w32)
+        threads = oracle.threads()
         t0 = time.perf_counter()
-        eo, fo, po = oracle.msm(p, w32.xyz, w32.q)
-        evals = 1
-        if not args.no_cpu_baseline:
-            while time.perf_counter() - t0 < args.cpu_seconds:
-                oracle.msm(p, w32.xyz, w32.q)
-                evals += 1
-        dt = time.perf_counter() - t0
-        if not args.no_cpu_baseline:
-            cpu = {"value": n * evals / dt, "unit": "atom-steps/s", "cores": oracle.threads(), "kind": "oracle",
-                   "sample": f"{evals} full FP64 oracle evaluation(s) of the same {n}-atom workload, {dt:.1f} s"}
+        eo, fo, po = oracle.msm(oracle.OracleParams.of(w32), w32.xyz, w32.q)
+        t_all = time.perf_counter() - t0
+        log(f"oracle on {threads} threads: {t_all:.1f} s")
         if not args.no_accuracy:
-            def rel_rms(x, ref):
-                return float(np.sqrt(((x - ref) ** 2).sum() / (ref ** 2).sum()))
             accuracy = {"fp32_force_rel_rms": rel_rms(out32[1].double().cpu().numpy(), fo),
-                        "fp32_energy_rel": abs(out32[0].item() - eo) / abs(eo),
-                        "oracle_energy": eo}
+                        "fp32_potential_rel_rms": rel_rms(out32[2].double().cpu().numpy(), po),
+                        "fp32_energy_rel": abs(out32[0].item() - eo) / abs(eo), "oracle_energy": eo}
             if out64 is not None:
                 accuracy["fp64_force_rel_rms"] = rel_rms(out64[1].cpu().numpy(), fo)
+                accuracy["fp64_potential_rel_rms"] = rel_rms(out64[2].cpu().numpy(), po)
                 accuracy["fp64_energy_rel"] = abs(out64[0].item() - eo) / abs(eo)
+        del fo, po
+        if not args.no_cpu_baseline:
+            # one thread on a 10 nm cube cut from the same box (about as many
+            # atoms as the 99,999-atom workload), repeated up to the bound
+            sel = np.all((w32.xyz >= 0.0) & (w32.xyz < 10.0), axis=1)
+            sub = w32.xyz[sel]
+            p1 = oracle.OracleParams(w32.a, w32.h, (0.0, 0.0, 0.0), (10.0, 10.0, 10.0), 0, 138.935458)
+            oracle.set_threads(1)
+            t1 = time.perf_counter()
+            ev = 0
+            while ev == 0 or time.perf_counter() - t1 < args.cpu_seconds:
+                oracle.msm(p1, sub, w32.q[sel])
+                ev += 1
+            t_one = time.perf_counter() - t1
+            oracle.set_threads(threads)
+            cpu = {"value": n / t_all, "unit": "atom-steps/s", "cores": threads, "kind": "oracle",
+                   "sample": f"one full FP64 oracle evaluation of the same {n}-atom box on {threads} threads "
+                             f"({t_all:.1f} s; it is also the accuracy reference)",
+                   "single_thread": {"value": int(sel.sum()) * ev / t_one, "unit": "atom-steps/s", "cores": 1,
+                                     "sample": f"{ev} oracle evaluation(s) of the {int(sel.sum())} atoms of a "
+                                               f"10 nm cube cut from the same box, {t_one:.1f} s"},
+                   "cpu_model": cpu_model()}
+    del out32, out64
 
-    log(f"single system done: fp32 {ms32:.4f} ms per step")
-    batched = uneven = par = large = orders = mts = window = None
-    if not args.no_batched:
-        batched, uneven = bench_batched(torch, msmx, w32, args.steps, args.warmup, args.slices, value,
-                                        autotune=not args.no_autotune)
-        log("batched done")
+    small = batched = uneven = par = large = orders = mts = window = None
+    if not args.no_small:
+        small = small_box_record(torch, msmx, args)
+        log("99,999-atom record done")
+    states = None
     if not args.no_parareal:
-        par = bench_parareal(torch, msmx, args.slices)
+        par, states = bench_parareal(torch, msmx, args.slices)
         log("parareal done")
+    if not args.no_batched and states is not None:
+        batched, uneven = bench_batched(torch, msmx, *states, args.steps, args.warmup, autotune=not args.no_autotune)
+        log("batched done")
+    del states
     if not args.no_large:
-        large = bench_large(torch, msmx)
-        log("large box done")
+        large = bench_large(torch, msmx, named("water_12675000", margin=1.0), equilibrate_ps=args.equilibrate_ps)
+        log("large box dynamics done")
     if not args.no_orders:
-        orders = bench_orders(torch, msmx, w32)
+        orders = bench_orders(torch, msmx, named("water_99999").as_dtype(np.float32))
         log("orders done")
+    dt_half = None
     if not args.no_mts:
-        mts = bench_mts(torch, msmx)
+        mts = bench_mts(torch, msmx, equilibrate_ps=args.equilibrate_ps)
         log("multiple time steps done")
+        dt_half = bench_dt_halving(torch, msmx, equilibrate_ps=args.equilibrate_ps)
+        log("dt halving done")
     if not args.no_window:
         window = bench_window(torch, msmx)
         log("window done")
 
+    dims = "x".join(f"{d:g}" for d in np.round(w32.hi - w32.lo, 2))
     result.update({
         "value": value,
         "unit": "atom-steps/s",
@@ -655,8 +882,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {n} atoms, rigid 3-site water, 10 nm cube, a=1.2 nm, "
-                               f"h=0.25 nm, {len(shapes)} grids, FP32 bulk + FP64 energy reduction",
+        "config": {"workload": f"{args.workload}: {n} atoms, rigid 3-site water, {dims} nm domain, a={w32.a} nm, "
+                               f"h={w32.h} nm, {len(shapes)} grids, one energy+force+potential evaluation, "
+                               f"FP32 bulk + FP64 energy reduction",
                    "atoms": n, "levels": len(shapes), "a_nm": w32.a, "h_nm": w32.h},
         "roofline": roofline,
         "cpu_baseline": cpu,
@@ -667,11 +895,12 @@ def main():
         "uneven_batch": uneven,
         "parareal": par,
         "large_box": large,
+        "box_99999": small,
         "orders": orders,
         "mts": mts,
+        "dt_halving_fp64": dt_half,
         "window": window,
-        "launch": {"mode": launch_mode, "tuning": tuning32, "graph_ms_per_step": graph_ms,
-                   "eager_default_ms_per_step": eager_default_ms, "eager_tuned_ms_per_step": eager_tuned_ms},
+        "launch": launch,
         "accuracy": accuracy,
         "stage_ms": kernels,
     })

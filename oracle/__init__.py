@@ -31,6 +31,7 @@ from .loader import (  # noqa: F401
     wolf,
     short_subset,
     threads,
+    set_threads,
     OracleModel,
     md_forces,
     md_forces_split,

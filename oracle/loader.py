@@ -96,6 +96,8 @@ def lib():
             L.orc_coulomb.restype = C.c_int
             L.orc_threads.restype = C.c_int
             L.orc_threads.argtypes = []
+            L.orc_set_threads.restype = None
+            L.orc_set_threads.argtypes = [C.c_int]
             L.orc_coulomb.argtypes = [C.c_int64, _dp, _dp, C.c_double, _dp, _dp, _dp]
             L.orc_cutoff.restype = C.c_int
             L.orc_cutoff.argtypes = [C.c_int64, _dp, _dp, C.POINTER(C.c_int32), C.c_double, C.c_double, _dp, _dp,
@@ -149,6 +151,11 @@ def glevel(r, a, k, l, m: int = 2):
 def threads() -> int:
     """OpenMP threads the oracle's parallel loops use."""
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """Use n OpenMP threads in the oracle's parallel loops from now on."""
+    lib().orc_set_threads(int(n))
 
 
 def levels(p: OracleParams) -> int:

@@ -33,6 +33,7 @@
 
 /* Threads the OpenMP loops of this library use. */
 int orc_threads(void) { return omp_get_max_threads(); }
+void orc_set_threads(int n) { if (n > 0) omp_set_num_threads(n); }
 
 /* ---- Section 3, smoothing function gamma of degree 2m: for rho < 1 the
  *      Taylor polynomial of (rho^2)^(-1/2) about rho^2 = 1 up to the

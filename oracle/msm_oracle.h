@@ -49,6 +49,8 @@ typedef struct {
 } orc_stages;
 
 int orc_threads(void);
+/* OpenMP threads of the parallel loops that follow (n > 0). */
+void orc_set_threads(int n);
 /* gamma of order m (degree 2m) and its derivative; the unsuffixed forms are m = 2 */
 double orc_gamma_m(double rho, int m);
 double orc_dgamma_m(double rho, int m);
