@@ -182,7 +182,11 @@ typedef struct {
                               takes two clusters and lays out one candidate stream for both
                               (same terms in the same order as 2, so the same bits); 5 and 6:
                               as 2 with 16-atom clusters, four lanes per atom (5), or 32-atom
-                              clusters, two lanes per atom (6) */
+                              clusters, two lanes per atom (6); 7 and 9: as 2, but the 8
+                              clusters of a 64-atom group (7; one workgroup of 8 waves) or the
+                              4 of half a group (9) share one candidate stream, built and
+                              loaded once by the workgroup (same terms in the same order as
+                              2, so the same bits) */
     int stencil_threads;   /* threads per lattice-cutoff tile: 256 or 1024 */
     int concurrent;        /* 1: the short-range sum runs on a second stream of the context,
                               concurrently with the grid stages (forked after binning,

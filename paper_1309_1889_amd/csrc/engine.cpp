@@ -857,7 +857,7 @@ int msm_set_tuning(msm_ctx *c, const msm_tuning *t)
 {
     if (!c || !t) return MSM_ERR_ARG;
     if (t->pair_waves != 1 && t->pair_waves != 2 && t->pair_waves != 3 && t->pair_waves != 4 && t->pair_waves != 5 &&
-        t->pair_waves != 6 && t->pair_waves != 8 && t->pair_waves != 16)
+        t->pair_waves != 6 && t->pair_waves != 7 && t->pair_waves != 8 && t->pair_waves != 9 && t->pair_waves != 16)
         return MSM_ERR_ARG;
     if (t->stencil_threads != 256 && t->stencil_threads != 1024) return MSM_ERR_ARG;
     if (t->concurrent < 0 || t->concurrent > 2) return MSM_ERR_ARG;
@@ -905,7 +905,7 @@ int msm_autotune(msm_ctx *c, int nsys, const int64_t *offsets, const double *dom
     const int modes[2] = {1, 2};
     const int nmodes = start.concurrent ? 2 : 1;
     for (int mi = 0; mi < nmodes; mi++)
-        for (int pw : {1, 2, 3, 4, 5, 6, 8, 16})
+        for (int pw : {1, 2, 3, 4, 5, 6, 7, 8, 9, 16})
             for (int st : {256, 1024}) {
                 if (rc) break;
                 c->mc.pair_waves = pw;

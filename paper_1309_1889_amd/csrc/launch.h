@@ -100,7 +100,9 @@ struct MethodConst {
     int pair_waves;            // waves per 64-atom group in the pair kernel: 4, 8 or 16; 1: 16-atom sub-groups;
                                // 2: 8-atom clusters with bounding-box candidate filtering;
                                // 3: two such clusters per wave sharing one candidate stream;
-                               // 5, 6: one 16-atom (5) or 32-atom (6) cluster per wave
+                               // 5, 6: one 16-atom (5) or 32-atom (6) cluster per wave;
+                               // 7, 9: as 2, the clusters of a group (7) or half group (9)
+                               // sharing one stream built and loaded by the workgroup
     int stencil_threads;       // threads per stencil tile: 256 or 1024
 };
 

@@ -554,6 +554,10 @@ constexpr int kClUnroll = 4;                   // steps per evaluated block
 constexpr int kClRing = 128;                   // ring capacity (a multiple of kBlock, power of two)
 constexpr int kClMap = 512;                    // stream positions with a table entry
 constexpr int kClWgWaves = 4;                  // waves per workgroup (independent)
+#ifndef MSMX_CL_PREFETCH
+#define MSMX_CL_PREFETCH 1
+#endif
+constexpr int kClPrefetch = MSMX_CL_PREFETCH;  // stream chunks in flight ahead of the one in use
 
 template <int CA, typename T> __device__ inline T sum_slots(T v)
 {
@@ -778,22 +782,30 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
             }
             return fst[lo_] + (pos - pre[lo_]);
         };
-        vec4_t<T> pa, px;
-        if (lane < total) {
-            const int j = atom_at(lane);
-            pa = sx[j];
-            if (MD) px = saux[j];
-        }
+        // chunks c0 + kWave * d (d < kClPrefetch) are in flight
+        vec4_t<T> pa[kClPrefetch], px[kClPrefetch];
+#pragma unroll
+        for (int d = 0; d < kClPrefetch; ++d)
+            if (kWave * d + lane < total) {
+                const int j = atom_at(kWave * d + lane);
+                pa[d] = sx[j];
+                if (MD) px[d] = saux[j];
+            }
         for (int c0 = 0; c0 < total; c0 += kWave) {
             const bool have = c0 + lane < total;
-            const vec4_t<T> ca = pa;
+            const vec4_t<T> ca = pa[0];
             vec4_t<T> cx;
-            if (MD) cx = px;
-            const int nxt = c0 + kWave + lane;   // the next chunk
+            if (MD) cx = px[0];
+#pragma unroll
+            for (int d = 0; d + 1 < kClPrefetch; ++d) {
+                pa[d] = pa[d + 1];
+                if (MD) px[d] = px[d + 1];
+            }
+            const int nxt = c0 + kWave * kClPrefetch + lane;   // the chunk that joins the pipeline
             if (nxt < total) {
                 const int j = atom_at(nxt);
-                pa = sx[j];
-                if (MD) px = saux[j];
+                pa[kClPrefetch - 1] = sx[j];
+                if (MD) px[kClPrefetch - 1] = saux[j];
             }
 #pragma unroll
             for (int sc = 0; sc < NSUB; ++sc) {
@@ -860,6 +872,289 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
     }
 }
 
+// k_pair_grp: the 8-atom clusters of one 64-atom group (GW = 8 waves in one
+// workgroup) or of half a group (GW = 4) share one candidate stream: the
+// cell-row pieces that reach the box around all of them. The waves build the
+// piece table together (64 pieces each per batch), load the stream together
+// (64 candidates each per round, the next round in flight while the current
+// one is used) into a double buffer in LDS, and then each wave keeps, from
+// every candidate of the round, those within the cutoff of its own cluster's
+// box and evaluates them as k_pair_cl does with 8-atom clusters. The pieces
+// are clipped to the common box, so each of them holds the pieces of the
+// single-cluster stream as sub-runs, in the same order: every cluster keeps
+// the same candidates in the same order as in k_pair_cl, and the results are
+// the same bits. Building and loading the stream is paid once per workgroup
+// instead of once per cluster.
+template <int GW> constexpr int grp_map() { return GW * 256; }   // positions with a table entry
+
+template <typename T, bool MD, int GW> struct GrpLds {
+    vec4_t<T> cand[2][GW * kWave];   // one round of the stream, double buffered
+    vec4_t<T> caux[MD ? 2 : 1][MD ? GW * kWave : 1];
+    vec4_t<T> ring[GW][kClRing];
+    vec4_t<T> raux[MD ? GW : 1][MD ? kClRing : 1];
+    int map[grp_map<GW>()];          // stream position -> sorted atom
+    int pre[GW * kWave + 1];         // piece stream offsets of the batch
+    int first[GW * kWave];           // first atom of each piece
+    int wtot[GW];                    // stream length of each wave's pieces
+    T box[GW][6];                    // cluster boxes; an absent cluster's is empty (lo > hi)
+};
+
+template <typename T, bool MD, bool POT, int KIND, int GW>
+__global__ __launch_bounds__(GW * kWave) void k_pair_grp(DevPlan p, const vec4_t<T> *__restrict__ sx,
+                                                          const int *__restrict__ cstart,
+                                                          const int *__restrict__ cluster,
+                                                          vec4_t<T> *__restrict__ out, PairK<T> k,
+                                                          const vec4_t<T> *__restrict__ saux,
+                                                          vec4_t<T> *__restrict__ ljout)
+{
+    constexpr int CA = 8, kSlots = kWave / CA, kBlock = kSlots * kClUnroll, NR = GW * kWave;
+    constexpr int kMap = grp_map<GW>();
+    __shared__ GrpLds<T, MD, GW> L;
+    __shared__ WolfLds<T, KIND> wl;
+    if (eval_failed(p)) return;   // the same for every workgroup
+    wl.load(k);
+    const float4 *wtab = wl.ptr();
+    const int lane = threadIdx.x % kWave;
+    const int wv = uni((int)(threadIdx.x / kWave));
+    const int64_t c = xcd_remap(blockIdx.x, gridDim.x) * GW + wv;   // this wave's cluster
+    const int64_t g = c / (kWave / CA);
+    const int s = find_segment(p.group_prefix, p.nsys, g);
+    const SysPlan &P = p.sys[s];
+    const int me = lane % CA, slot = lane / CA;
+    const int cfirst = uni(cluster[c * CA]);
+    const bool on = cfirst >= 0;   // uniform
+    const int mi = cluster[c * CA + me];
+    const bool valid = mi >= 0;
+    // lanes of absent atoms evaluate a stand-in (a real atom) and write nothing
+    const int64_t i = valid ? (int64_t)mi : (on ? (int64_t)cfirst : P.atom0 + (g - p.group_prefix[s]) * kWave);
+    const vec4_t<T> ai = sx[i];
+    vec4_t<T> xi;
+    if (MD) xi = saux[i];
+    const T bx_lo = uni(seg_min(ai.x, CA)), bx_hi = uni(seg_max(ai.x, CA));
+    const T by_lo = uni(seg_min(ai.y, CA)), by_hi = uni(seg_max(ai.y, CA));
+    const T bz_lo = uni(seg_min(ai.z, CA)), bz_hi = uni(seg_max(ai.z, CA));
+    if (lane == 0) {
+        const T inf = T(1e30);
+        L.box[wv][0] = on ? bx_lo : inf;
+        L.box[wv][1] = on ? by_lo : inf;
+        L.box[wv][2] = on ? bz_lo : inf;
+        L.box[wv][3] = on ? bx_hi : -inf;
+        L.box[wv][4] = on ? by_hi : -inf;
+        L.box[wv][5] = on ? bz_hi : -inf;
+    }
+    __syncthreads();
+    // the box around the workgroup's clusters (the same in every wave)
+    T bminx = L.box[0][0], bminy = L.box[0][1], bminz = L.box[0][2];
+    T bmaxx = L.box[0][3], bmaxy = L.box[0][4], bmaxz = L.box[0][5];
+#pragma unroll
+    for (int w = 1; w < GW; ++w) {
+        bminx = fmin(bminx, L.box[w][0]), bminy = fmin(bminy, L.box[w][1]), bminz = fmin(bminz, L.box[w][2]);
+        bmaxx = fmax(bmaxx, L.box[w][3]), bmaxy = fmax(bmaxy, L.box[w][4]), bmaxz = fmax(bmaxz, L.box[w][5]);
+    }
+    if (!(bminx <= bmaxx)) return;   // no cluster here: the whole workgroup leaves
+    const T lox = T(P.lo[0]), loy = T(P.lo[1]), loz = T(P.lo[2]);
+    const T inv_h = T(P.inv_h), h = T(1.0 / P.inv_h);
+    const int ncx = P.nc[0], ncy = P.nc[1], ncz = P.nc[2];
+    const T reach = k.reach, reach2 = k.reach * k.reach;
+    const int cy0 = clampi((int)floor((bminy - loy - reach) * inv_h), 0, ncy - 1);
+    const int cy1 = clampi((int)floor((bmaxy - loy + reach) * inv_h), 0, ncy - 1);
+    const int cz0 = clampi((int)floor((bminz - loz - reach) * inv_h), 0, ncz - 1);
+    const int cz1 = clampi((int)floor((bmaxz - loz + reach) * inv_h), 0, ncz - 1);
+    const int bx0 = clampi((int)floor((bminx - lox - reach) * inv_h), 0, ncx - 1) / kBrick;
+    const int bx1 = clampi((int)floor((bmaxx - lox + reach) * inv_h), 0, ncx - 1) / kBrick;
+    const int nbx = bx1 - bx0 + 1, ny = cy1 - cy0 + 1;
+    const int nitems = nbx * ny * (cz1 - cz0 + 1);
+
+    if (KIND == kPolyHigh)
+        asm volatile("" : "+v"(k.c2), "+v"(k.d1));
+    else if (KIND == kPoly)
+        asm volatile("" : "+v"(k.c1), "+v"(k.d0));
+    T fx = 0, fy = 0, fz = 0, u = 0, lx = 0, ly = 0, lz = 0, le = 0;
+    int head = 0, tail = 0;   // ring positions (uniform; taken modulo the capacity)
+    vec4_t<T> *ring = L.ring[wv];
+    vec4_t<T> *raux = L.raux[MD ? wv : 0];
+    auto eval_block = [&]() {
+        // a block starts at a multiple of its size, so it does not wrap
+        const int e0 = (head & (kClRing - 1)) + slot;
+        vec4_t<T> aj[kClUnroll], xj[kClUnroll];
+#pragma unroll
+        for (int v = 0; v < kClUnroll; ++v) {
+            aj[v] = ring[e0 + kSlots * v];
+            xj[v] = MD ? raux[MD ? e0 + kSlots * v : 0] : aj[v];
+        }
+#pragma unroll
+        for (int v = 0; v < kClUnroll; ++v)
+            pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le, wtab);
+        head += kBlock;
+    };
+    int *map = L.map, *pre = L.pre, *fst = L.first;
+    for (int ib = 0; ib < nitems; ib += NR) {
+        // this wave's 64 pieces of the batch
+        const int q = ib + wv * kWave + lane;
+        int len = 0, jb = 0;
+        if (q < nitems) {
+            const int bx = bx0 + q % nbx, row = q / nbx;
+            const int cy = cy0 + row % ny, cz = cz0 + row / ny;
+            const T z0 = loz + T(cz) * h, y0 = loy + T(cy) * h;
+            const T dz = fmax(T(0), fmax(z0 - bmaxz, bminz - (z0 + h)));
+            const T dy = fmax(T(0), fmax(y0 - bmaxy, bminy - (y0 + h)));
+            const T rem = reach2 - dy * dy - dz * dz;
+            if (rem > T(0)) {
+                const T wdt = sqrt(rem);
+                const int cx0 = clampi((int)floor((bminx - lox - wdt) * inv_h), 0, ncx - 1);
+                const int cx1 = clampi((int)floor((bmaxx - lox + wdt) * inv_h), 0, ncx - 1);
+                const int ca = max(cx0, bx * kBrick), cb = min(cx1, bx * kBrick + kBrick - 1);
+                if (ca <= cb) {
+                    const int64_t r0 = P.cell0 + cell_rank(P, ca, cy, cz);
+                    jb = cstart[r0];
+                    len = cstart[r0 + (cb - ca) + 1] - jb;
+                }
+            }
+        }
+        int incl = len;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int v = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += v;
+        }
+        if (lane == kWave - 1) L.wtot[wv] = incl;
+        __syncthreads();   // the previous batch's tables are no longer read
+        int base = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < GW; ++w) {
+            const int t = L.wtot[w];
+            base += w < wv ? t : 0;
+            total += t;
+        }
+        const int start = base + incl - len;
+        pre[wv * kWave + lane] = start;
+        fst[wv * kWave + lane] = jb;
+        if (wv == GW - 1 && lane == kWave - 1) pre[NR] = total;
+        int maxlen = len;
+        for (int off = 32; off > 0; off >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, off, kWave));
+        maxlen = uni(maxlen);
+        for (int t = 0; t < maxlen; ++t)
+            if (t < len && start + t < kMap) map[start + t] = jb + t;
+        __syncthreads();   // the batch's tables are complete
+        auto atom_at = [&](int pos) -> int {
+            if (pos < kMap) return map[pos];
+            int lo_ = 0, hi_ = NR;   // pre[lo_] <= pos < pre[hi_]
+            while (hi_ - lo_ > 1) {
+                const int mid = (lo_ + hi_) >> 1;
+                if (pre[mid] <= pos) lo_ = mid; else hi_ = mid;
+            }
+            return fst[lo_] + (pos - pre[lo_]);
+        };
+        // the first round
+        const int own = wv * kWave + lane;   // this thread's place in a round
+        if (own < total) {
+            const int j = atom_at(own);
+            L.cand[0][own] = sx[j];
+            if (MD) L.caux[0][MD ? own : 0] = saux[j];
+        }
+        __syncthreads();
+        int buf = 0;
+        for (int r0 = 0; r0 < total; r0 += NR) {
+            // the next round, in flight while this one is used
+            const int nx = r0 + NR + own;
+            vec4_t<T> pa, px;
+            if (nx < total) {
+                const int j = atom_at(nx);
+                pa = sx[j];
+                if (MD) px = saux[j];
+            }
+            if (on) {
+#pragma unroll 1
+                for (int kk = 0; kk < GW; ++kk) {
+                    const int c0 = r0 + kk * kWave;
+                    if (c0 >= total) break;   // uniform
+                    const bool have = c0 + lane < total;
+                    const vec4_t<T> ca = L.cand[buf][kk * kWave + lane];
+                    const T ddx = fmax(T(0), fmax(bx_lo - ca.x, ca.x - bx_hi));
+                    const T ddy = fmax(T(0), fmax(by_lo - ca.y, ca.y - by_hi));
+                    const T ddz = fmax(T(0), fmax(bz_lo - ca.z, ca.z - bz_hi));
+                    const bool keep = have && ddx * ddx + ddy * ddy + ddz * ddz < reach2;
+                    const uint64_t m = __ballot(keep);
+                    if (keep) {
+                        const int e = (tail + (int)__builtin_amdgcn_mbcnt_hi(
+                                                  (unsigned)(m >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u))) &
+                                      (kClRing - 1);
+                        ring[e] = ca;
+                        if (MD) raux[MD ? e : 0] = L.caux[MD ? buf : 0][MD ? kk * kWave + lane : 0];
+                    }
+                    tail += __popcll(m);
+                    __builtin_amdgcn_wave_barrier();
+                    while (tail - head >= kBlock) eval_block();
+                    __builtin_amdgcn_wave_barrier();
+                }
+            }
+            if (nx < total) {
+                L.cand[buf ^ 1][own] = pa;
+                if (MD) L.caux[MD ? buf ^ 1 : 0][MD ? own : 0] = px;
+            }
+            __syncthreads();   // the next round is in place; this one is no longer read
+            buf ^= 1;
+        }
+    }
+    if (!on) return;
+    if (tail > head) {   // the last partial block, padded with a far-away atom
+        if (lane < head + kBlock - tail) {
+            vec4_t<T> far;
+            far.x = far.y = far.z = T(1e18);
+            far.w = T(0);
+            ring[(tail + lane) & (kClRing - 1)] = far;
+            if (MD) raux[MD ? (tail + lane) & (kClRing - 1) : 0] = far;
+        }
+        __builtin_amdgcn_wave_barrier();
+        eval_block();
+    }
+    fx = sum_slots<CA>(fx);
+    fy = sum_slots<CA>(fy);
+    fz = sum_slots<CA>(fz);
+    if (POT) u = sum_slots<CA>(u);
+    if (MD) {
+        lx = sum_slots<CA>(lx);
+        ly = sum_slots<CA>(ly);
+        lz = sum_slots<CA>(lz);
+        if (POT) le = sum_slots<CA>(le);
+    }
+    if (slot == 0 && valid) {
+        vec4_t<T> o;
+        o.x = fx;
+        o.y = fy;
+        o.z = fz;
+        o.w = u;
+        out[i] = o;
+        if (MD) {
+            vec4_t<T> ol;
+            ol.x = lx;
+            ol.y = ly;
+            ol.z = lz;
+            ol.w = le;
+            ljout[i] = ol;
+        }
+    }
+}
+
+template <typename T, int KIND, int GW>
+static void pair_launch_grp(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot)
+{
+    hipLaunchKernelGGL((k_clusters<T, 8>), dim3((unsigned)p.ngroups), dim3(kWave), 0, s, p, w.sxyzq, w.cluster);
+    const dim3 grid((unsigned)(p.ngroups * (8 / GW))), block(GW * kWave);
+    const vec4_t<T> *aux = (const vec4_t<T> *)w.saux;
+    if (w.saux && pot)
+        hipLaunchKernelGGL((k_pair_grp<T, true, true, KIND, GW>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
+                           w.cluster, w.shrt, k, aux, w.shlj);
+    else if (w.saux)
+        hipLaunchKernelGGL((k_pair_grp<T, true, false, KIND, GW>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
+                           w.cluster, w.shrt, k, aux, w.shlj);
+    else if (pot)
+        hipLaunchKernelGGL((k_pair_grp<T, false, true, KIND, GW>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
+                           w.cluster, w.shrt, k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+    else
+        hipLaunchKernelGGL((k_pair_grp<T, false, false, KIND, GW>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
+                           w.cluster, w.shrt, k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+}
+
 template <typename T, int KIND, int NSUB, int CA>
 static void pair_launch_cl(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot)
 {
@@ -923,7 +1218,13 @@ static void pair_launch(hipStream_t s, const DevPlan &p, const Work<T> &w, const
 template <typename T, int NW>
 static void pair_launch_m(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot, int kind)
 {
-    if constexpr (NW == 2 || NW == 3 || NW == 5 || NW == 6) {
+    if constexpr (NW == 7 || NW == 9) {
+        // 8-atom clusters sharing one stream per group (7) or half group (9)
+        constexpr int GW = NW == 7 ? 8 : 4;
+        if (kind == kWolf) pair_launch_grp<T, kWolf, GW>(s, p, w, k, pot);
+        else if (kind == kPolyHigh) pair_launch_grp<T, kPolyHigh, GW>(s, p, w, k, pot);
+        else pair_launch_grp<T, kPoly, GW>(s, p, w, k, pot);
+    } else if constexpr (NW == 2 || NW == 3 || NW == 5 || NW == 6) {
         // cluster form: one 8-atom cluster per wave, or two sharing a stream;
         // one 16-atom or one 32-atom cluster per wave
         constexpr int NS = NW == 3 ? 2 : 1;
@@ -1007,6 +1308,8 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, co
     case 4: pair_launch_m<T, 4>(s, p, w, k, pot, kind); break;
     case 5: pair_launch_m<T, 5>(s, p, w, k, pot, kind); break;
     case 6: pair_launch_m<T, 6>(s, p, w, k, pot, kind); break;
+    case 7: pair_launch_m<T, 7>(s, p, w, k, pot, kind); break;
+    case 9: pair_launch_m<T, 9>(s, p, w, k, pot, kind); break;
     case 8: pair_launch_m<T, 8>(s, p, w, k, pot, kind); break;
     case 16: pair_launch_m<T, 16>(s, p, w, k, pot, kind); break;
     default: return hipErrorInvalidValue;

@@ -79,7 +79,7 @@ def test_autotune_and_tunings_agree():
     x = torch.tensor(w.xyzq(np.float32), device="cuda")
     ref = [t.clone() for t in ctx.energy_forces(x)]
     chosen = ctx.autotune(x, reps=3)
-    assert chosen["pair_waves"] in (1, 2, 3, 4, 5, 6, 8, 16) and chosen["stencil_threads"] in (256, 1024)
+    assert chosen["pair_waves"] in (1, 2, 3, 4, 5, 6, 7, 8, 9, 16) and chosen["stencil_threads"] in (256, 1024)
     assert ctx.tuning() == chosen
     for pw in (1, 2, 3, 4, 5, 6, 8, 16):
         for st in (256, 1024):
@@ -109,7 +109,7 @@ def test_concurrent_stages_change_no_bit(precision):
     conc = msmx.MsmContext(w.a, w.h, w.lo, w.hi, precision=precision, max_atoms=w.n)
     seq.set_tuning(concurrent=0)
     assert conc.tuning()["concurrent"] == 1
-    for pw in (1, 2, 3, 4, 5, 6, 8):
+    for pw in (1, 2, 3, 4, 5, 6, 7, 8, 9):
         seq.set_tuning(pair_waves=pw)
         conc.set_tuning(pair_waves=pw)
         ref = seq.energy_forces(x)
@@ -127,10 +127,11 @@ def test_concurrent_stages_change_no_bit(precision):
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
 def test_two_clusters_per_wave_same_bits(precision):
-    """Two clusters sharing one candidate stream keep, for each cluster, the
-    candidates of its own box in the same order, so the sums are the one-
-    cluster form's bit for bit; systems whose last group is partly empty
-    included."""
+    """Two clusters sharing one candidate stream in a wave, and the clusters
+    of a group or half group sharing one stream in a workgroup, keep, for
+    each cluster, the candidates of its own box in the same order, so the
+    sums are the one-cluster form's bit for bit; systems whose last group is
+    partly empty included."""
     import paper_1309_1889_amd as msmx
     dt = np.float32 if precision == "fp32" else np.float64
     parts = [water_box(n, (p,) * 3, (s,) * 3, seed=20 + n) for n, p, s in ((1000, 10, 3.2), (733, 10, 3.0))]
@@ -140,10 +141,32 @@ def test_two_clusters_per_wave_same_bits(precision):
     doms = [list(p.lo) + list(p.hi) for p in parts]
     ctx = msmx.MsmContext(w.a, w.h, w.lo, w.hi, precision=precision, max_atoms=offs[-1], max_systems=2)
     got = {}
-    for pw in (2, 3):
+    for pw in (2, 3, 7, 9):
         ctx.set_tuning(pair_waves=pw)
         got[pw] = [t.clone() for t in ctx.energy_forces(x, offs, doms)]
     torch.cuda.synchronize()
     assert ctx.status() == 0
-    for a, b in zip(got[2], got[3]):
-        assert torch.equal(a, b)
+    for pw in (3, 7, 9):
+        for a, b in zip(got[2], got[pw]):
+            assert torch.equal(a, b), pw
+
+
+def test_shared_stream_forms_same_bits_large():
+    """The workgroup-shared candidate streams at 99,999 atoms, where a batch
+    of pieces spans more stream positions than the position table holds (so
+    the search path of the table runs) and the stream takes several batches
+    and rounds: the sums are the one-cluster form's bit for bit."""
+    import paper_1309_1889_amd as msmx
+    from workloads import named
+    w = named("water_99999").as_dtype(np.float32)
+    x = torch.tensor(w.xyzq(np.float32), device="cuda")
+    ctx = msmx.MsmContext(w.a, w.h, w.lo, w.hi, precision="fp32", max_atoms=w.n)
+    got = {}
+    for pw in (2, 7, 9):
+        ctx.set_tuning(pair_waves=pw)
+        got[pw] = [t.clone() for t in ctx.energy_forces(x)]
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    for pw in (7, 9):
+        for a, b in zip(got[2], got[pw]):
+            assert torch.equal(a, b), pw

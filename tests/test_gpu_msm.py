@@ -301,11 +301,12 @@ def test_water_small_matches_oracle(precision):
     assert e == pytest.approx(eo, rel=tol)
 
 
-@pytest.mark.parametrize("pw", [2, 3, 5, 6])
+@pytest.mark.parametrize("pw", [2, 3, 5, 6, 7, 9])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_cluster_pair_forms_match_oracle(pw, precision):
     """Each cluster form of the short-range sum (8-atom clusters, one or two
-    per wave; 16- and 32-atom clusters) against the oracle, on a water box
+    per wave, or sharing a workgroup's stream; 16- and 32-atom clusters)
+    against the oracle, on a water box
     whose last 64-atom group is partly empty (999 atoms) and on uniform
     charges with the coarse cells of h = 0.5."""
     m = _lib()
