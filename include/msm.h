@@ -237,7 +237,8 @@ int msm_grid_shape(const msm_ctx *ctx, const double *domain_host, int *org, int 
 /* Copy intermediate results of the last msm_energy_forces call for system
  * `sys` into caller device buffers (any may be NULL), converted to double:
  * u_short (N_s), f_short (N_s x 3, the bracket of the short-range force
- * before the factor k q_i), per-level grids q^k and u^k (prolongated; the
+ * before the factor k q_i; with a molecular model bound, the short-range
+ * force itself, Coulomb and Lennard-Jones), per-level grids q^k and u^k (prolongated; the
  * lattice-cutoff part for `ucut`) in x-fastest order of msm_grid_shape.
  * Grid pointers are arrays of `levels` device pointers in host memory.
  * Atom arrays are in the caller's order. u_short is zero when that call asked

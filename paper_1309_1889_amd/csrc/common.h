@@ -214,7 +214,14 @@ template <int P, typename T> __device__ inline T phi_piece(T t, int j)
 template <int P, typename T> __device__ inline T phi_inside(T t)
 {
     const T x = fabs(t);
-    if (P == 3) return x <= T(1) ? phi_piece<3>(t, 0) : phi_piece<3>(t, 1);
+    if (P == 3) {
+        // both pieces, then a select (the same expressions as phi_piece)
+        const T u = T(2) - x;
+        const T inner = T(1) + x * x * (T(-2.5) + T(1.5) * x);
+        const T outer = T(-0.5) * (x - T(1)) * u * u;
+        const T v = x <= T(1) ? inner : outer;
+        return x < T(2) ? v : T(0);
+    }
     return x < T(1) ? phi_piece<5>(t, 0) : (x < T(2) ? phi_piece<5>(t, 1) : phi_piece<5>(t, 2));
 }
 

@@ -54,7 +54,8 @@ template <typename T> struct Work {
     int *scan_blocks;    // block sums of the scan
     int *order;          // sorted position -> input atom
     vec4_t<T> *sxyzq;    // atoms in sorted order
-    vec4_t<T> *shrt;     // sorted order: (bracket of F^short, u^short)
+    vec4_t<T> *shrt;     // sorted order: (bracket of F^short, u^short); with a molecular model
+                         // bound, .xyz is the short-range force in final units (Coulomb and LJ)
     int *cluster;        // per 64-atom pair group: its atoms in k-d cluster order (sorted index, -1 absent)
     T *apart;            // ncells x 64: each cell's partial charges on its 4x4x4 support nodes
     T *qgrid;            // padded charge grids, all levels and systems
@@ -67,7 +68,7 @@ template <typename T> struct Work {
     // dynamics model (null when no model is bound)
     vec4_t<T> *maux;     // per model atom: (molecule id bits, sigma/2, sqrt(eps), 0)
     vec4_t<T> *saux;     // sorted copy of maux
-    vec4_t<T> *shlj;     // sorted order: Lennard-Jones force and energy
+    vec4_t<T> *shlj;     // sorted order: Lennard-Jones energy in .w (the force joins shrt)
     int64_t period;      // batch atom i uses model entry i % period
 };
 

@@ -933,16 +933,23 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4
         const T phi = ke * (sr.w + ul - a.w * self);
         const int64_t o = order[pos];
         if (potentials) potentials[o] = phi;
-        vec4_t<T> lj;
-        lj.x = lj.y = lj.z = lj.w = T(0);
-        if (SHORT && ljin) lj = ljin[pos];
+        // with a molecular model bound, the pair kernel leaves the short-range
+        // force in final units (coulomb_k q_i times the Coulomb bracket, plus
+        // Lennard-Jones) and the Lennard-Jones energy in ljin[pos].w
+        const bool md = SHORT && ljin;
         if (forces) {
             const T kq = ke * a.w;
-            forces[3 * o + 0] = kq * (sr.x - gx) + lj.x;
-            forces[3 * o + 1] = kq * (sr.y - gy) + lj.y;
-            forces[3 * o + 2] = kq * (sr.z - gz) + lj.z;
+            if (md) {
+                forces[3 * o + 0] = sr.x - kq * gx;
+                forces[3 * o + 1] = sr.y - kq * gy;
+                forces[3 * o + 2] = sr.z - kq * gz;
+            } else {
+                forces[3 * o + 0] = kq * (sr.x - gx);
+                forces[3 * o + 1] = kq * (sr.y - gy);
+                forces[3 * o + 2] = kq * (sr.z - gz);
+            }
         }
-        e = (double)a.w * (double)phi + (double)lj.w;
+        e = (double)a.w * (double)phi + (md ? (double)ljin[pos].w : 0.0);
     }
     e = block_sum<kInterpThreads>(e, wpart);
     if (threadIdx.x == 0) eparts[blk] = e;

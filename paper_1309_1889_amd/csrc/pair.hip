@@ -35,6 +35,7 @@ template <typename T> struct PairK {
     T wshift, wexp;     // erfc(alpha a)/a and 2 alpha / sqrt(pi)
     const float4 *wtab; // single precision: the Wolf table (kWolfPieces pieces of E and D)
     float wscale;       // kWolfPieces / a
+    T ke;               // Coulomb constant (dynamics forms: forces leave in final units)
 };
 
 // Wolf summation in single precision: E(r) = erfc(alpha r) and the force
@@ -82,6 +83,18 @@ constexpr int kPairUnroll = MSMX_PAIR_UNROLL;   // staged candidates read per st
 __device__ inline int mol_of(const float4 &v) { return __float_as_int(v.x); }
 __device__ inline int mol_of(const double4 &v) { return (int)__double_as_longlong(v.x); }
 
+// the three used components of an aux record (molecule id, s/2, sqrt(eps))
+// read from LDS, the fourth known to be zero, so no register holds it
+template <typename T> __device__ inline vec4_t<T> aux3(const vec4_t<T> &r)
+{
+    vec4_t<T> v;
+    v.x = r.x;
+    v.y = r.y;
+    v.z = r.z;
+    v.w = T(0);
+    return v;
+}
+
 // Per-wave LDS: the flattened candidate stream of the wave's 64 current work
 // items and the staged chunk of 64 candidate atoms.
 template <typename T, bool MD> struct PairLds {
@@ -95,7 +108,7 @@ template <typename T, bool MD> struct PairLds {
 // that are asked for neither. KIND: one of PairKind.
 template <typename T, bool MD, bool POT, int KIND>
 __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const vec4_t<T> &aj, const vec4_t<T> &xj,
-                                 const PairK<T> &k, T &fx, T &fy, T &fz, T &u, T &lx, T &ly, T &lz, T &le,
+                                 const PairK<T> &k, T kq, T &fx, T &fy, T &fz, T &u, T &le,
                                  const float4 *wtab = nullptr)
 {
     const T dx = ai.x - aj.x, dy = ai.y - aj.y, dz = ai.z - aj.z;
@@ -134,26 +147,24 @@ __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const
             br = rc * rinv * rinv - (k.d0 + k.d1 * r2);
             if (POT) u += aj.w * (rc - (k.c0 + r2 * (k.c1 + r2 * k.c2)));
         }
-        const T t = aj.w * br;
+        T t = aj.w * br;
+        if (MD) {
+            // Lennard-Jones (zero for eps = 0, an excluded pair included);
+            // the force on i in final units: coulomb_k q_i q_j br + f_LJ
+            const T eps = same ? T(0) : xi.z * xj.z;
+            const T sg = xi.y + xj.y;
+            const T s2 = sg * sg, ir2 = rinv * rinv;
+            const T sr2 = s2 * ir2, sr6 = sr2 * sr2 * sr2;
+            if (POT) {
+                const T sc2 = s2 * k.inv_a2, sc6 = sc2 * sc2 * sc2;
+                le += T(4) * eps * ((sr6 * sr6 - sr6) - (sc6 * sc6 - sc6));
+            }
+            const T fl = T(24) * eps * (T(2) * sr6 * sr6 - sr6) * ir2;
+            t = kq * t + fl;
+        }
         fx += t * dx;
         fy += t * dy;
         fz += t * dz;
-        if (MD) {
-            const T eps = same ? T(0) : xi.z * xj.z;
-            if (eps != T(0)) {
-                const T sg = xi.y + xj.y;
-                const T s2 = sg * sg;
-                const T sr2 = s2 * rinv * rinv, sr6 = sr2 * sr2 * sr2;
-                if (POT) {
-                    const T sc2 = s2 * k.inv_a2, sc6 = sc2 * sc2 * sc2;
-                    le += T(4) * eps * ((sr6 * sr6 - sr6) - (sc6 * sc6 - sc6));
-                }
-                const T fl = T(24) * eps * (T(2) * sr6 * sr6 - sr6) * rinv * rinv;
-                lx += fl * dx;
-                ly += fl * dy;
-                lz += fl * dz;
-            }
-        }
     }
 }
 
@@ -227,7 +238,8 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
     else if (KIND == kPoly)
         asm volatile("" : "+v"(k.c1), "+v"(k.d0));
     T fx = 0, fy = 0, fz = 0, u = 0;
-    T lx = 0, ly = 0, lz = 0, le = 0;
+    T le = 0;
+    const T kq = MD ? k.ke * ai.w : T(0);   // coulomb_k q_i (dynamics forms)
     // items wv, wv + W, wv + 2W, ..., 64 per batch
     for (int ib = wv; ib < nitems; ib += kPairWaves * kWave) {
         const int q = ib + kPairWaves * lane;            // this lane's item
@@ -298,16 +310,16 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
 #pragma unroll
                 for (int v = 0; v < kPairUnroll; ++v) {
                     aj[v] = L.atom[t + v];
-                    xj[v] = MD ? L.aux[t + v] : aj[v];
+                    xj[v] = MD ? aux3<T>(L.aux[t + v]) : aj[v];
                 }
 #pragma unroll
                 for (int v = 0; v < kPairUnroll; ++v)
-                    pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le, wtab);
+                    pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, kq, fx, fy, fz, u, le, wtab);
             }
             for (; t < cnt; ++t) {
                 const vec4_t<T> aj = L.atom[t];
-                const vec4_t<T> xj = MD ? L.aux[t] : aj;
-                pair_term<T, MD, POT, KIND>(ai, xi, aj, xj, k, fx, fy, fz, u, lx, ly, lz, le, wtab);
+                const vec4_t<T> xj = MD ? aux3<T>(L.aux[t]) : aj;
+                pair_term<T, MD, POT, KIND>(ai, xi, aj, xj, k, kq, fx, fy, fz, u, le, wtab);
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -320,9 +332,7 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
     red[wv][lane] = o;
     if (MD) {
         vec4_t<T> ol;
-        ol.x = lx;
-        ol.y = ly;
-        ol.z = lz;
+        ol.x = ol.y = ol.z = T(0);
         ol.w = le;
         redlj[MD ? wv : 0][lane] = ol;
     }
@@ -418,7 +428,8 @@ __global__ __launch_bounds__(kSubLanes * kWave) void k_pair_sub(DevPlan p, const
     else if (KIND == kPoly)
         asm volatile("" : "+v"(k.c1), "+v"(k.d0));
     T fx = 0, fy = 0, fz = 0, u = 0;
-    T lx = 0, ly = 0, lz = 0, le = 0;
+    T le = 0;
+    const T kq = MD ? k.ke * ai.w : T(0);   // coulomb_k q_i (dynamics forms)
     for (int ib = 0; ib < nitems; ib += kWave) {
         const int q = ib + lane;   // this lane's item
         int len = 0, jb = 0;
@@ -484,18 +495,18 @@ __global__ __launch_bounds__(kSubLanes * kWave) void k_pair_sub(DevPlan p, const
 #pragma unroll
                 for (int v = 0; v < kSubUnroll; ++v) {
                     aj[v] = L.atom[t + kSubLanes * v + slot];
-                    xj[v] = MD ? L.aux[t + kSubLanes * v + slot] : aj[v];
+                    xj[v] = MD ? aux3<T>(L.aux[t + kSubLanes * v + slot]) : aj[v];
                 }
 #pragma unroll
                 for (int v = 0; v < kSubUnroll; ++v)
-                    pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le, wtab);
+                    pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, kq, fx, fy, fz, u, le, wtab);
             }
             for (; t < cnt; t += kSubLanes) {
                 const int tj = t + slot;
                 if (tj < cnt) {
                     const vec4_t<T> aj = L.atom[tj];
-                    const vec4_t<T> xj = MD ? L.aux[tj] : aj;
-                    pair_term<T, MD, POT, KIND>(ai, xi, aj, xj, k, fx, fy, fz, u, lx, ly, lz, le, wtab);
+                    const vec4_t<T> xj = MD ? aux3<T>(L.aux[tj]) : aj;
+                    pair_term<T, MD, POT, KIND>(ai, xi, aj, xj, k, kq, fx, fy, fz, u, le, wtab);
                 }
             }
         }
@@ -506,9 +517,6 @@ __global__ __launch_bounds__(kSubLanes * kWave) void k_pair_sub(DevPlan p, const
     fz = sum_lanes(fz);
     if (POT) u = sum_lanes(u);
     if (MD) {
-        lx = sum_lanes(lx);
-        ly = sum_lanes(ly);
-        lz = sum_lanes(lz);
         if (POT) le = sum_lanes(le);
     }
     if (slot == 0 && valid) {
@@ -520,9 +528,7 @@ __global__ __launch_bounds__(kSubLanes * kWave) void k_pair_sub(DevPlan p, const
         out[i] = o;
         if (MD) {
             vec4_t<T> ol;
-            ol.x = lx;
-            ol.y = ly;
-            ol.z = lz;
+            ol.x = ol.y = ol.z = T(0);
             ol.w = le;
             ljout[i] = ol;
         }
@@ -551,6 +557,11 @@ __global__ __launch_bounds__(kSubLanes * kWave) void k_pair_sub(DevPlan p, const
 // cost of building the stream among more atoms. The waves share nothing. The
 // partial sums of an atom are added across its lanes in a fixed order.
 constexpr int kClUnroll = 4;                   // steps per evaluated block
+#ifndef MSMX_CL_UNROLL_MD
+#define MSMX_CL_UNROLL_MD 4
+#endif
+// steps per evaluated block of the dynamics forms (their pair term holds more registers)
+template <bool MD> constexpr int cl_unroll() { return MD ? MSMX_CL_UNROLL_MD : kClUnroll; }
 constexpr int kClRing = 128;                   // ring capacity (a multiple of kBlock, power of two)
 constexpr int kClMap = 512;                    // stream positions with a table entry
 constexpr int kClWgWaves = 4;                  // waves per workgroup (independent)
@@ -650,7 +661,7 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
                                                                 vec4_t<T> *__restrict__ ljout)
 {
     constexpr int kSlots = kWave / CA;          // candidates per step
-    constexpr int kBlock = kSlots * kClUnroll;  // candidates per evaluated block
+    constexpr int kU = cl_unroll<MD>(), kBlock = kSlots * kU;  // candidates per evaluated block
     __shared__ ClLds<T, MD, NSUB> L;
     __shared__ WolfLds<T, KIND> wl;
     if (eval_failed(p)) return;
@@ -710,9 +721,9 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
         asm volatile("" : "+v"(k.c2), "+v"(k.d1));
     else if (KIND == kPoly)
         asm volatile("" : "+v"(k.c1), "+v"(k.d0));
-    T fx[NSUB], fy[NSUB], fz[NSUB], u[NSUB], lx[NSUB], ly[NSUB], lz[NSUB], le[NSUB];
+    T fx[NSUB], fy[NSUB], fz[NSUB], u[NSUB], le[NSUB];
 #pragma unroll
-    for (int sc = 0; sc < NSUB; ++sc) fx[sc] = fy[sc] = fz[sc] = u[sc] = lx[sc] = ly[sc] = lz[sc] = le[sc] = T(0);
+    for (int sc = 0; sc < NSUB; ++sc) fx[sc] = fy[sc] = fz[sc] = u[sc] = le[sc] = T(0);
     int *map = L.map[wv], *pre = L.pre[wv], *fst = L.first[wv];
     int head[NSUB], tail[NSUB];   // ring positions (uniform; taken modulo the capacity)
 #pragma unroll
@@ -722,16 +733,16 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
         const vec4_t<T> *ring = L.ring[wv][sc];
         const vec4_t<T> *raux = L.raux[MD ? wv : 0][MD ? sc : 0];
         const int e0 = (head[sc] & (kClRing - 1)) + slot;
-        vec4_t<T> aj[kClUnroll], xj[kClUnroll];
+        vec4_t<T> aj[kU], xj[kU];
 #pragma unroll
-        for (int v = 0; v < kClUnroll; ++v) {
+        for (int v = 0; v < kU; ++v) {
             aj[v] = ring[e0 + kSlots * v];
-            xj[v] = MD ? raux[MD ? e0 + kSlots * v : 0] : aj[v];
+            xj[v] = MD ? aux3<T>(raux[MD ? e0 + kSlots * v : 0]) : aj[v];
         }
 #pragma unroll
-        for (int v = 0; v < kClUnroll; ++v)
-            pair_term<T, MD, POT, KIND>(ai[sc], xi[sc], aj[v], xj[v], k, fx[sc], fy[sc], fz[sc], u[sc], lx[sc],
-                                        ly[sc], lz[sc], le[sc], wtab);
+        for (int v = 0; v < kU; ++v)
+            pair_term<T, MD, POT, KIND>(ai[sc], xi[sc], aj[v], xj[v], k, k.ke * ai[sc].w, fx[sc], fy[sc], fz[sc],
+                                        u[sc], le[sc], wtab);
         head[sc] += kBlock;
     };
     for (int ib = 0; ib < nitems; ib += kWave) {
@@ -848,9 +859,6 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
         fz[sc] = sum_slots<CA>(fz[sc]);
         if (POT) u[sc] = sum_slots<CA>(u[sc]);
         if (MD) {
-            lx[sc] = sum_slots<CA>(lx[sc]);
-            ly[sc] = sum_slots<CA>(ly[sc]);
-            lz[sc] = sum_slots<CA>(lz[sc]);
             if (POT) le[sc] = sum_slots<CA>(le[sc]);
         }
         if (slot == 0 && valid[sc]) {
@@ -862,9 +870,7 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
             out[i[sc]] = o;
             if (MD) {
                 vec4_t<T> ol;
-                ol.x = lx[sc];
-                ol.y = ly[sc];
-                ol.z = lz[sc];
+                ol.x = ol.y = ol.z = T(0);
                 ol.w = le[sc];
                 ljout[i[sc]] = ol;
             }
@@ -907,7 +913,7 @@ __global__ __launch_bounds__(GW * kWave) void k_pair_grp(DevPlan p, const vec4_t
                                                           const vec4_t<T> *__restrict__ saux,
                                                           vec4_t<T> *__restrict__ ljout)
 {
-    constexpr int CA = 8, kSlots = kWave / CA, kBlock = kSlots * kClUnroll, NR = GW * kWave;
+    constexpr int CA = 8, kSlots = kWave / CA, kU = cl_unroll<MD>(), kBlock = kSlots * kU, NR = GW * kWave;
     constexpr int kMap = grp_map<GW>();
     __shared__ GrpLds<T, MD, GW> L;
     __shared__ WolfLds<T, KIND> wl;
@@ -969,22 +975,23 @@ __global__ __launch_bounds__(GW * kWave) void k_pair_grp(DevPlan p, const vec4_t
         asm volatile("" : "+v"(k.c2), "+v"(k.d1));
     else if (KIND == kPoly)
         asm volatile("" : "+v"(k.c1), "+v"(k.d0));
-    T fx = 0, fy = 0, fz = 0, u = 0, lx = 0, ly = 0, lz = 0, le = 0;
+    T fx = 0, fy = 0, fz = 0, u = 0, le = 0;
+    const T kq = MD ? k.ke * ai.w : T(0);   // coulomb_k q_i (dynamics forms)
     int head = 0, tail = 0;   // ring positions (uniform; taken modulo the capacity)
     vec4_t<T> *ring = L.ring[wv];
     vec4_t<T> *raux = L.raux[MD ? wv : 0];
     auto eval_block = [&]() {
         // a block starts at a multiple of its size, so it does not wrap
         const int e0 = (head & (kClRing - 1)) + slot;
-        vec4_t<T> aj[kClUnroll], xj[kClUnroll];
+        vec4_t<T> aj[kU], xj[kU];
 #pragma unroll
-        for (int v = 0; v < kClUnroll; ++v) {
+        for (int v = 0; v < kU; ++v) {
             aj[v] = ring[e0 + kSlots * v];
-            xj[v] = MD ? raux[MD ? e0 + kSlots * v : 0] : aj[v];
+            xj[v] = MD ? aux3<T>(raux[MD ? e0 + kSlots * v : 0]) : aj[v];
         }
 #pragma unroll
-        for (int v = 0; v < kClUnroll; ++v)
-            pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, lx, ly, lz, le, wtab);
+        for (int v = 0; v < kU; ++v)
+            pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, kq, fx, fy, fz, u, le, wtab);
         head += kBlock;
     };
     int *map = L.map, *pre = L.pre, *fst = L.first;
@@ -1112,9 +1119,6 @@ __global__ __launch_bounds__(GW * kWave) void k_pair_grp(DevPlan p, const vec4_t
     fz = sum_slots<CA>(fz);
     if (POT) u = sum_slots<CA>(u);
     if (MD) {
-        lx = sum_slots<CA>(lx);
-        ly = sum_slots<CA>(ly);
-        lz = sum_slots<CA>(lz);
         if (POT) le = sum_slots<CA>(le);
     }
     if (slot == 0 && valid) {
@@ -1126,9 +1130,7 @@ __global__ __launch_bounds__(GW * kWave) void k_pair_grp(DevPlan p, const vec4_t
         out[i] = o;
         if (MD) {
             vec4_t<T> ol;
-            ol.x = lx;
-            ol.y = ly;
-            ol.z = lz;
+            ol.x = ol.y = ol.z = T(0);
             ol.w = le;
             ljout[i] = ol;
         }
@@ -1297,6 +1299,7 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, co
     k.alpha2 = T(m.alpha * m.alpha);
     k.wshift = T(std::erfc(m.alpha * a) / a);
     k.wexp = T(2.0 * m.alpha / std::sqrt(std::acos(-1.0)));
+    k.ke = T(m.ke);
     k.wtab = m.wolf_tab;
     k.wscale = float(kWolfPieces / a);
     if (m.method == MSM_METHOD_WOLF && sizeof(T) == 4 && !k.wtab) return hipErrorInvalidValue;
