@@ -237,8 +237,8 @@ int msm_grid_shape(const msm_ctx *ctx, const double *domain_host, int *org, int 
 /* Copy intermediate results of the last msm_energy_forces call for system
  * `sys` into caller device buffers (any may be NULL), converted to double:
  * u_short (N_s), f_short (N_s x 3, the bracket of the short-range force
- * before the factor k q_i; with a molecular model bound, the short-range
- * force itself, Coulomb and Lennard-Jones), per-level grids q^k and u^k (prolongated; the
+ * before the factor k q_i; with a molecular model bound, with the excluded
+ * pairs taken out and without Lennard-Jones), per-level grids q^k and u^k (prolongated; the
  * lattice-cutoff part for `ucut`) in x-fastest order of msm_grid_shape.
  * Grid pointers are arrays of `levels` device pointers in host memory.
  * Atom arrays are in the caller's order. u_short is zero when that call asked
@@ -257,7 +257,8 @@ typedef struct {
     int64_t period;              /* entries of the per-atom arrays; batch atom i uses
                                     entry i % period (period = atoms of one system) */
     const int32_t *molid_dev;    /* period molecule ids, or NULL (no exclusions); the atoms of a
-                                    molecule lie within one system and closer than a */
+                                    molecule lie within one system and closer than a, at most
+                                    1024 atoms per molecule (MSM_ERR_ARG otherwise) */
     const double *lj_dev;        /* period x 2 (sigma nm, epsilon kJ/mol), or NULL */
     int rigid_triples;           /* 1: atoms 3m, 3m+1, 3m+2 of every system are rigid; system
                                     offsets must then be multiples of 3 */
@@ -269,7 +270,10 @@ typedef struct {
 /* Copy a molecular model into the context and allocate the dynamics
  * workspace (forces, propagator state and parareal arrays for max_atoms
  * atoms). Must precede msm_vv_run and parareal_run; a later call replaces the
- * model. With a model bound, msm_energy_forces also applies it. */
+ * model. With a model bound, msm_energy_forces also applies it: the pair sum
+ * runs as without a model, a per-atom pass takes each molecule's excluded
+ * pairs out of it, and Lennard-Jones runs over the atoms with epsilon > 0
+ * only. */
 int msm_md_bind(msm_ctx *ctx, const msm_md_model *model);
 
 /* nsteps velocity-Verlet steps of dt ps (Section 2), in place, on nsys

@@ -313,6 +313,31 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     tile_p[nseg] = tiles;
     if (cells > c->cap_cells || q > c->cap_q || u > c->cap_u || iblk > c->cap_iblk) return MSM_ERR_CAPACITY;
     if (cells >= (int64_t)1 << 31) return MSM_ERR_CAPACITY;
+    // the atoms that carry Lennard-Jones (a bound model): per system their
+    // count from the model's prefix (batch atom i is model atom i % period),
+    // the same systems and cells, their own 64-atom groups
+    const bool lj = c->md_bound && !c->lj_prefix.empty();
+    std::vector<SysPlan> &lj_sys = ps.lj_sys;
+    std::vector<int64_t> &lj_group_p = ps.lj_group_p;
+    int64_t lj_atoms = 0, lj_groups = 0;
+    if (lj) {
+        const int64_t period = (int64_t)c->lj_prefix.size() - 1, per = c->lj_prefix[period];
+        auto before = [&](int64_t i) { return (i / period) * per + c->lj_prefix[i % period]; };
+        lj_sys = sys;
+        lj_group_p.assign(W, 0);
+        for (int s = 0; s < nsys; s++) {
+            SysPlan &P = lj_sys[s];
+            const int64_t n = before(offsets[s + 1]) - before(offsets[s]);
+            P.atom0 = lj_atoms;
+            P.natoms = n;
+            P.group0 = lj_groups;
+            P.ngroups = (n + kWave - 1) / kWave;
+            lj_group_p[s] = lj_groups;
+            lj_atoms += n;
+            lj_groups += P.ngroups;
+        }
+        lj_group_p[nsys] = lj_groups;
+    }
 
     // pack the tables into one blob
     size_t off = 0;
@@ -328,6 +353,7 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     const size_t o_node = place(sizeof(int64_t) * kMaxLevels * W), o_tile = place(sizeof(int64_t) * (nseg + 1));
     const size_t o_rxy = place(sizeof(int64_t) * W), o_pxy = place(sizeof(int64_t) * W);
     const size_t o_phi = place(sizeof(double) * std::max<size_t>(phi_tab.size(), 1));
+    const size_t o_ljsys = lj ? place(sizeof(SysPlan) * nsys) : 0, o_ljgroup = lj ? place(sizeof(int64_t) * W) : 0;
     char *h = nullptr;
     int slot = -1;
     if (c->fixed_plan) {
@@ -371,6 +397,10 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     std::memcpy(h + o_rxy, rxy_p.data(), sizeof(int64_t) * W);
     std::memcpy(h + o_pxy, pxy_p.data(), sizeof(int64_t) * W);
     if (!phi_tab.empty()) std::memcpy(h + o_phi, phi_tab.data(), sizeof(double) * phi_tab.size());
+    if (lj) {
+        std::memcpy(h + o_ljsys, lj_sys.data(), sizeof(SysPlan) * nsys);
+        std::memcpy(h + o_ljgroup, lj_group_p.data(), sizeof(int64_t) * W);
+    }
     if (c->fixed_plan) {
         if (put_bytes(c->stream, c->fixed_plan, h, off) != hipSuccess) return MSM_ERR_HIP;
     } else {
@@ -413,6 +443,17 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     dp.nrz = 0;
     for (int k = 1; k < kMaxLevels; k++) dp.nrz += nodes[k];
     dp.evflag = (c->prm.precision == MSM_FP32 ? c->wf.status : c->wd.status) + 1;
+    // the subset plan: the same cells and tables, its own atoms and groups
+    c->dps = dp;
+    if (lj) {
+        c->dps.sys = (const SysPlan *)(d + o_ljsys);
+        c->dps.group_prefix = (const int64_t *)(d + o_ljgroup);
+        c->dps.natoms = lj_atoms;
+        c->dps.ngroups = lj_groups;
+    } else {
+        c->dps.natoms = 0;
+        c->dps.ngroups = 0;
+    }
     c->host_sys = sys;
     c->last_offsets.assign(offsets, offsets + nsys + 1);
     if (domains) c->last_domains.assign(domains, domains + nsys * 6);
@@ -469,6 +510,10 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
         ps = c->side_stream;
     }
     if (do_short && (e = L::pair(ps, p, w, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
+    if (do_short && c->md_bound) {
+        if ((e = L::exclusions(ps, p, w, (const vec4_t<T> *)xyzq, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
+        if ((e = L::lj(ps, p, c->dps, w, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
+    }
     if (!ant_first) {
         mark(MSM_STAGE_ANTERP);
         if (do_long && (e = L::anterp(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;

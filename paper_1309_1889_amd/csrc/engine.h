@@ -24,6 +24,8 @@ struct Geometry {
 struct PlanScratch {
     std::vector<SysPlan> sys;
     std::vector<int64_t> atom_p, group_p, cell_p, iblk_p, top_p, ant_p, node_p, rxy_p, pxy_p, tile_p;
+    std::vector<SysPlan> lj_sys;      // the Lennard-Jones subset's system plans
+    std::vector<int64_t> lj_group_p;  // and its 64-atom groups
     std::vector<double> phi_tab, p1, cur, nxt;
     std::vector<char> blob;            // image of the tables for a fixed device region
     std::vector<int2> cols;            // stencil columns and weights before upload
@@ -59,6 +61,7 @@ struct msm_ctx {
     bool plan_ev_live[kPlanStage] = {};
     int plan_slot = 0;
     msmx::DevPlan dp{};
+    msmx::DevPlan dps{};         // the plan of the atoms that carry Lennard-Jones (dynamics model)
     // allocation-free contexts: the tables are written to this fixed device
     // region (at most fixed_plan_cap bytes) instead of plan_dev
     char *fixed_plan = nullptr;
@@ -100,6 +103,9 @@ struct msm_ctx {
     uint64_t graph_clock = 0;
     // dynamics (msm_md_bind)
     bool md_bound = false;
+    // model atoms that carry Lennard-Jones: lj_prefix[m] counts those before
+    // model atom m (period + 1 entries); empty when none does
+    std::vector<int64_t> lj_prefix;
     bool rigid = false;
     msmx::TriModel tri{};
     char *mdbuf = nullptr;       // model, forces and parareal scratch

@@ -54,8 +54,7 @@ template <typename T> struct Work {
     int *scan_blocks;    // block sums of the scan
     int *order;          // sorted position -> input atom
     vec4_t<T> *sxyzq;    // atoms in sorted order
-    vec4_t<T> *shrt;     // sorted order: (bracket of F^short, u^short); with a molecular model
-                         // bound, .xyz is the short-range force in final units (Coulomb and LJ)
+    vec4_t<T> *shrt;     // sorted order: (bracket of F^short, u^short)
     int *cluster;        // per 64-atom pair group: its atoms in k-d cluster order (sorted index, -1 absent)
     T *apart;            // ncells x 64: each cell's partial charges on its 4x4x4 support nodes
     T *qgrid;            // padded charge grids, all levels and systems
@@ -68,8 +67,18 @@ template <typename T> struct Work {
     // dynamics model (null when no model is bound)
     vec4_t<T> *maux;     // per model atom: (molecule id bits, sigma/2, sqrt(eps), 0)
     vec4_t<T> *saux;     // sorted copy of maux
-    vec4_t<T> *shlj;     // sorted order: Lennard-Jones energy in .w (the force joins shrt)
     int64_t period;      // batch atom i uses model entry i % period
+    int *xstart, *xidx;  // excluded partners of model atom m: xidx[xstart[m] .. xstart[m+1]) (model
+                         // indices, ascending); null without molecule ids
+    // the atoms that carry Lennard-Jones (null when none does), in sorted order
+    int *lj_cnt;         // ncells + 1: per-cell count (the scan clears it)
+    int *lj_start;       // ncells + 1: their cell starts
+    int *lj_blocks;      // block sums of that scan
+    int *lj_of;          // sorted position -> subset index, or -1
+    int *lj_cluster;     // the subset's k-d clusters
+    vec4_t<T> *lj_x;     // subset positions and charges
+    vec4_t<T> *lj_aux;   // subset aux records
+    vec4_t<T> *lj_out;   // subset: Lennard-Jones force and energy (counted from both sides)
 };
 
 // Quarter-disc stencil columns (ox >= 0, oy >= 0 inside the sphere) and their
@@ -133,6 +142,14 @@ template <typename T> struct Launch {
     static hipError_t bin(hipStream_t s, const DevPlan &p, const Work<T> &w, const vec4_t<T> *xyzq);
     // pot = false: forces only, the short-range potentials are left at zero
     static hipError_t pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m, bool pot);
+    // after pair, with a molecular model bound: take the excluded pairs of each
+    // molecule out of the short-range sums (xyzq: the evaluation's input), and
+    // the Lennard-Jones forces and energies of the atoms that carry them (sub:
+    // the plan of that subset)
+    static hipError_t exclusions(hipStream_t s, const DevPlan &p, const Work<T> &w, const vec4_t<T> *xyzq,
+                                 const MethodConst &m, bool pot);
+    static hipError_t lj(hipStream_t s, const DevPlan &p, const DevPlan &sub, const Work<T> &w, const MethodConst &m,
+                         bool pot);
     static hipError_t anterp(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m);
     static hipError_t restrict_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k, const MethodConst &m);
     // the lattice cutoff of every level below the top and the top level

@@ -5,6 +5,9 @@
 
 namespace msmx {
 
+// Largest molecule of a bound model (its excluded pairs are listed per atom).
+constexpr int kMaxMoleculeAtoms = 1024;
+
 // Rigid triples: atoms 3m, 3m+1, 3m+2 at distances len[0] (0-1), len[1] (0-2), len[2] (1-2).
 struct TriModel {
     double len[3];

@@ -31,16 +31,81 @@ template <typename T> int bind(msm_ctx *c, const msm_md_model *m)
         (void)hipFree(c->mdbuf);
         c->mdbuf = nullptr;
     }
+    c->md_bound = false;
+    c->lj_prefix.clear();
+    c->plan_valid = false;   // the plan of the Lennard-Jones atoms depends on the model
     const bool aux = m->molid_dev || m->lj_dev;
+    // the model on the host: molecule ids (every atom its own molecule
+    // without them) and (sigma, epsilon)
+    std::vector<int32_t> mol(aux ? period : 0, -1);
+    std::vector<double> lj(aux ? 2 * period : 0, 0.0);
+    if (m->molid_dev &&
+        hipMemcpy(mol.data(), m->molid_dev, sizeof(int32_t) * period, hipMemcpyDeviceToHost) != hipSuccess)
+        return MSM_ERR_HIP;
+    if (aux && !m->molid_dev)
+        for (int64_t i = 0; i < period; i++) mol[i] = -1 - (int32_t)i;
+    if (m->lj_dev && hipMemcpy(lj.data(), m->lj_dev, sizeof(double) * 2 * period, hipMemcpyDeviceToHost) != hipSuccess)
+        return MSM_ERR_HIP;
+    for (int64_t i = 0; aux && i < period; i++)
+        if (lj[2 * i] < 0 || lj[2 * i + 1] < 0 || !std::isfinite(lj[2 * i]) || !std::isfinite(lj[2 * i + 1]))
+            return MSM_ERR_ARG;
+    // excluded partners: the other atoms of each molecule, ascending
+    std::vector<int32_t> xstart, xidx;
+    if (m->molid_dev) {
+        std::vector<std::pair<int32_t, int32_t>> by(period);
+        for (int64_t i = 0; i < period; i++) by[i] = {mol[i], (int32_t)i};
+        std::sort(by.begin(), by.end());
+        std::vector<int32_t> cnt(period, 0);
+        for (int64_t b = 0; b < period;) {
+            int64_t e = b;
+            while (e < period && by[e].first == by[b].first) e++;
+            if (e - b > kMaxMoleculeAtoms) return MSM_ERR_ARG;
+            for (int64_t k = b; k < e; k++) cnt[by[k].second] = (int32_t)(e - b - 1);
+            b = e;
+        }
+        xstart.assign(period + 1, 0);
+        for (int64_t i = 0; i < period; i++) xstart[i + 1] = xstart[i] + cnt[i];
+        xidx.assign(std::max<int32_t>(xstart[period], 1), 0);
+        std::vector<int32_t> fill(xstart.begin(), xstart.end() - 1);
+        for (int64_t b = 0; b < period;) {
+            int64_t e = b;
+            while (e < period && by[e].first == by[b].first) e++;
+            for (int64_t k = b; k < e; k++)
+                for (int64_t q = b; q < e; q++)
+                    if (q != k) xidx[fill[by[k].second]++] = by[q].second;
+            b = e;
+        }
+        if (xstart[period] == 0) xstart.clear();   // no molecule of two atoms or more
+    }
+    // the atoms that carry Lennard-Jones, as the kernels see them (a nonzero
+    // sqrt(epsilon) in the context's precision)
+    int64_t nlj = 0;
+    if (aux) {
+        c->lj_prefix.assign(period + 1, 0);
+        for (int64_t i = 0; i < period; i++) {
+            c->lj_prefix[i + 1] = c->lj_prefix[i] + (T(std::sqrt(lj[2 * i + 1])) != T(0) ? 1 : 0);
+        }
+        nlj = c->lj_prefix[period];
+        if (nlj == 0) c->lj_prefix.clear();
+    }
     size_t off = 0;
     auto take = [&](size_t b) {
         size_t o = off;
         off += up256(b);
         return o;
     };
+    const bool excl = !xstart.empty(), ljs = nlj > 0;
+    const int64_t cells1 = c->cap_cells + 1;
     const size_t o_maux = aux ? take(sizeof(vec4_t<T>) * period) : 0;
     const size_t o_saux = aux ? take(sizeof(vec4_t<T>) * (na + 64)) : 0;
-    const size_t o_shlj = aux ? take(sizeof(vec4_t<T>) * na) : 0;
+    const size_t o_xs = excl ? take(sizeof(int32_t) * xstart.size()) : 0;
+    const size_t o_xi = excl ? take(sizeof(int32_t) * xidx.size()) : 0;
+    const size_t o_lcnt = ljs ? take(sizeof(int) * cells1) : 0, o_lstart = ljs ? take(sizeof(int) * cells1) : 0;
+    const size_t o_lblk = ljs ? take(sizeof(int) * std::max<int64_t>(kScanFewBlocks, cells1 / 4096 + 2)) : 0;
+    const size_t o_lof = ljs ? take(sizeof(int) * na) : 0;
+    const size_t o_lcl = ljs ? take(sizeof(int) * (na + (int64_t)kWave * c->prm.max_systems)) : 0;
+    const size_t o_lx = ljs ? take(sizeof(vec4_t<T>) * (na + 64)) : 0, o_laux = ljs ? take(sizeof(vec4_t<T>) * (na + 64)) : 0;
+    const size_t o_lout = ljs ? take(sizeof(vec4_t<T>) * na) : 0;
     const size_t o_f = take(sizeof(T) * 3 * na), o_fs = take(sizeof(T) * 3 * na);
     const size_t o_parts = take(sizeof(double) * c->cap_iblk);
     const size_t o_scal = take(sizeof(double) * (64 + std::max(c->prm.max_systems, 1)));
@@ -54,8 +119,17 @@ template <typename T> int bind(msm_ctx *c, const msm_md_model *m)
     Work<T> &w = work_of<T>(c);
     w.maux = aux ? (vec4_t<T> *)(b + o_maux) : nullptr;
     w.saux = aux ? (vec4_t<T> *)(b + o_saux) : nullptr;
-    w.shlj = aux ? (vec4_t<T> *)(b + o_shlj) : nullptr;
     w.period = period;
+    w.xstart = excl ? (int *)(b + o_xs) : nullptr;
+    w.xidx = excl ? (int *)(b + o_xi) : nullptr;
+    w.lj_cnt = ljs ? (int *)(b + o_lcnt) : nullptr;
+    w.lj_start = ljs ? (int *)(b + o_lstart) : nullptr;
+    w.lj_blocks = ljs ? (int *)(b + o_lblk) : nullptr;
+    w.lj_of = ljs ? (int *)(b + o_lof) : nullptr;
+    w.lj_cluster = ljs ? (int *)(b + o_lcl) : nullptr;
+    w.lj_x = ljs ? (vec4_t<T> *)(b + o_lx) : nullptr;
+    w.lj_aux = ljs ? (vec4_t<T> *)(b + o_laux) : nullptr;
+    w.lj_out = ljs ? (vec4_t<T> *)(b + o_lout) : nullptr;
     c->md_forces = b + o_f;
     c->md_forces_slow = b + o_fs;
     c->md_parts = (double *)(b + o_parts);
@@ -68,19 +142,8 @@ template <typename T> int bind(msm_ctx *c, const msm_md_model *m)
     c->gnew = (double *)(b + o_gnew);
     if (aux) {
         // per model atom: (molecule id bits, sigma/2, sqrt(epsilon), 0)
-        std::vector<int32_t> mol(period, -1);
-        std::vector<double> lj(2 * period, 0.0);
-        if (m->molid_dev &&
-            hipMemcpy(mol.data(), m->molid_dev, sizeof(int32_t) * period, hipMemcpyDeviceToHost) != hipSuccess)
-            return MSM_ERR_HIP;
-        if (!m->molid_dev)
-            for (int64_t i = 0; i < period; i++) mol[i] = -1 - (int32_t)i;   // every atom its own molecule
-        if (m->lj_dev && hipMemcpy(lj.data(), m->lj_dev, sizeof(double) * 2 * period, hipMemcpyDeviceToHost) != hipSuccess)
-            return MSM_ERR_HIP;
         std::vector<vec4_t<T>> h(period);
         for (int64_t i = 0; i < period; i++) {
-            if (lj[2 * i] < 0 || lj[2 * i + 1] < 0 || !std::isfinite(lj[2 * i]) || !std::isfinite(lj[2 * i + 1]))
-                return MSM_ERR_ARG;
             vec4_t<T> r;
             if (sizeof(T) == 4) {
                 int32_t bits = mol[i];
@@ -94,7 +157,17 @@ template <typename T> int bind(msm_ctx *c, const msm_md_model *m)
             r.w = T(0);
             h[i] = r;
         }
-        if (hipMemcpy(w.maux, h.data(), sizeof(vec4_t<T>) * period, hipMemcpyHostToDevice) != hipSuccess)
+        if (hipMemcpyAsync(w.maux, h.data(), sizeof(vec4_t<T>) * period, hipMemcpyHostToDevice, c->stream) !=
+            hipSuccess)
+            return MSM_ERR_HIP;
+        if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
+    }
+    if (excl) {
+        if (hipMemcpyAsync(w.xstart, xstart.data(), sizeof(int32_t) * xstart.size(), hipMemcpyHostToDevice,
+                           c->stream) != hipSuccess ||
+            hipMemcpyAsync(w.xidx, xidx.data(), sizeof(int32_t) * xidx.size(), hipMemcpyHostToDevice, c->stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess)
             return MSM_ERR_HIP;
     }
     c->rigid = m->rigid_triples != 0;

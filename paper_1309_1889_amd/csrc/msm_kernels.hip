@@ -867,15 +867,18 @@ __global__ __launch_bounds__(kZThreads) void k_prolong_z(DevPlan p, const T *__r
 // ---------------------------------------------------------------------------
 constexpr int kInterpThreads = 256;
 
-// GRID: add the grid part; SHORT: add the short-range pair part (and the
-// model's Lennard-Jones) that the pair kernel left in shrt / ljin.
+// GRID: add the grid part; SHORT: add the short-range pair part that the
+// pair kernel left in shrt, and, with a molecular model bound, the
+// Lennard-Jones force and energy of the atoms that carry it (ljof: sorted
+// position -> index into ljout, or -1; null without a model).
 template <typename T, bool GRID, bool SHORT, int PD>
 __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                            const vec4_t<T> *__restrict__ shrt,
                                                            const int *__restrict__ order,
                                                            const T *__restrict__ ugrid, T *__restrict__ forces,
                                                            T *__restrict__ potentials, double *__restrict__ eparts,
-                                                           T ke, T self, const vec4_t<T> *__restrict__ ljin)
+                                                           T ke, T self, const int *__restrict__ ljof,
+                                                           const vec4_t<T> *__restrict__ ljout)
 {
     __shared__ double wpart[kInterpThreads / kWave];
     const int64_t blk = blockIdx.x;
@@ -933,23 +936,19 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4
         const T phi = ke * (sr.w + ul - a.w * self);
         const int64_t o = order[pos];
         if (potentials) potentials[o] = phi;
-        // with a molecular model bound, the pair kernel leaves the short-range
-        // force in final units (coulomb_k q_i times the Coulomb bracket, plus
-        // Lennard-Jones) and the Lennard-Jones energy in ljin[pos].w
-        const bool md = SHORT && ljin;
+        vec4_t<T> lj;
+        lj.x = lj.y = lj.z = lj.w = T(0);
+        if (SHORT && ljof && !eval_failed(p)) {
+            const int li = ljof[pos];
+            if (li >= 0) lj = ljout[li];
+        }
         if (forces) {
             const T kq = ke * a.w;
-            if (md) {
-                forces[3 * o + 0] = sr.x - kq * gx;
-                forces[3 * o + 1] = sr.y - kq * gy;
-                forces[3 * o + 2] = sr.z - kq * gz;
-            } else {
-                forces[3 * o + 0] = kq * (sr.x - gx);
-                forces[3 * o + 1] = kq * (sr.y - gy);
-                forces[3 * o + 2] = kq * (sr.z - gz);
-            }
+            forces[3 * o + 0] = kq * (sr.x - gx) + lj.x;
+            forces[3 * o + 1] = kq * (sr.y - gy) + lj.y;
+            forces[3 * o + 2] = kq * (sr.z - gz) + lj.z;
         }
-        e = (double)a.w * (double)phi + (md ? (double)ljin[pos].w : 0.0);
+        e = (double)a.w * (double)phi + (double)lj.w;
     }
     e = block_sum<kInterpThreads>(e, wpart);
     if (threadIdx.x == 0) eparts[blk] = e;
@@ -1135,7 +1134,8 @@ hipError_t Launch<T>::interp(hipStream_t s, const DevPlan &p, const Work<T> &w, 
                              T *potentials, int part)
 {
     if (p.niblk == 0) return hipSuccess;
-    const vec4_t<T> *lj = (const vec4_t<T> *)(w.saux ? w.shlj : nullptr);
+    const int *ljof = w.lj_x ? w.lj_of : nullptr;
+    const vec4_t<T> *ljout = w.lj_out;
     const dim3 grid((unsigned)p.niblk), block(kInterpThreads);
     if (m.cutoff) {
         // no grid potential; the simple cutoff has no self term, Wolf's is
@@ -1143,7 +1143,7 @@ hipError_t Launch<T>::interp(hipStream_t s, const DevPlan &p, const Work<T> &w, 
         const double c_wolf = std::erfc(m.alpha * m.a) / (2.0 * m.a) + m.alpha / std::sqrt(std::acos(-1.0));
         const T self_nogrid = m.method == MSM_METHOD_WOLF ? T(2.0 * c_wolf) : T(0);
         hipLaunchKernelGGL((k_interp<T, false, true, 3>), grid, block, 0, s, p, w.sxyzq, w.shrt, w.order,
-                           (const T *)nullptr, forces, potentials, w.eparts, T(m.ke), self_nogrid, lj);
+                           (const T *)nullptr, forces, potentials, w.eparts, T(m.ke), self_nogrid, ljof, ljout);
         return hipGetLastError();
     }
     // the smooth self term gamma(0)/a goes with the grid part
@@ -1152,7 +1152,7 @@ hipError_t Launch<T>::interp(hipStream_t s, const DevPlan &p, const Work<T> &w, 
     const T ke = T(m.ke);
 #define MSMX_INTERP(G, S, P)                                                                                        \
     hipLaunchKernelGGL((k_interp<T, G, S, P>), grid, block, 0, s, p, w.sxyzq, w.shrt, w.order, ug, forces,          \
-                       potentials, w.eparts, ke, self, lj)
+                       potentials, w.eparts, ke, self, ljof, ljout)
     if (part == 1)
         MSMX_INTERP(false, true, 3);
     else if (part == 2 && m.p == 5)

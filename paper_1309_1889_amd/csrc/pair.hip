@@ -71,8 +71,9 @@ template <> struct WolfLds<float, 2> {
 
 // Pair kernel forms: the smoothing polynomial of degree at most 4 (MSM with
 // m <= 2, and the simple cutoff method with a zero polynomial), of degree 6
-// (m = 3), and Wolf's damped, shifted Coulomb (Section 5).
-enum PairKind { kPoly = 0, kPolyHigh = 1, kWolf = 2 };
+// (m = 3), Wolf's damped, shifted Coulomb (Section 5), and the dynamics
+// model's Lennard-Jones term, which runs over the atoms that carry one.
+enum PairKind { kPoly = 0, kPolyHigh = 1, kWolf = 2, kLJ = 3 };
 
 #ifndef MSMX_PAIR_UNROLL
 #define MSMX_PAIR_UNROLL 8
@@ -105,62 +106,55 @@ template <typename T, bool MD> struct PairLds {
 };
 
 // POT = false: forces only (no potential or energy sums), for evaluations
-// that are asked for neither. KIND: one of PairKind.
+// that are asked for neither. KIND: one of PairKind. MD: the candidates carry
+// aux records (molecule id bits, s/2, sqrt(eps), 0), which the Lennard-Jones
+// kind reads: 4 eps ((s/r)^12 - (s/r)^6), shifted to zero at r = a, between
+// atoms of different molecules, with s = s_i/2 + s_j/2 and
+// eps = sqrt(eps_i) sqrt(eps_j); u then sums the pair energies of atom i.
 template <typename T, bool MD, bool POT, int KIND>
 __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const vec4_t<T> &aj, const vec4_t<T> &xj,
-                                 const PairK<T> &k, T kq, T &fx, T &fy, T &fz, T &u, T &le,
-                                 const float4 *wtab = nullptr)
+                                 const PairK<T> &k, T &fx, T &fy, T &fz, T &u, const float4 *wtab = nullptr)
 {
     const T dx = ai.x - aj.x, dy = ai.y - aj.y, dz = ai.z - aj.z;
     const T r2 = dx * dx + dy * dy + dz * dz;
     if (r2 < k.a2 && r2 > T(0)) {
         const T rinv = rsqrt_t(r2);
-        T rc = rinv;
-        bool same = false;
-        if (MD) {
-            same = mol_of(xi) == mol_of(xj);
-            rc = same ? T(0) : rinv;
-        }
-        T br;
-        if (KIND == kWolf && sizeof(T) == 4) {
-            // single precision: the tabulated E and D (an excluded pair, rc = 0,
-            // contributes nothing)
-            const T r = r2 * rinv;
-            const T on = rc * r;   // 1, or 0 for an excluded pair
-            float E, D;
-            wolf_lookup(wtab, float(r), k.wscale, E, D);
-            br = on * T(D) * rinv * rinv * rinv;
-            if (POT) u += aj.w * on * (T(E) * rinv - k.wshift);
-        } else if (KIND == kWolf) {
-            // erfc(alpha r)/r - erfc(alpha a)/a, and -(d/dr)(erfc(alpha r)/r)/r
-            // = (erfc(alpha r)/r + 2 alpha/sqrt(pi) exp(-alpha^2 r^2)) / r^2;
-            // an excluded pair (rc = 0) contributes nothing
-            const T r = r2 * rinv;
-            const T er = erfc(k.alpha * r);
-            const T on = rc * r;   // 1, or 0 for an excluded pair
-            br = on * (er * rinv + k.wexp * exp(-k.alpha2 * r2)) * rinv * rinv;
-            if (POT) u += aj.w * on * (er * rinv - k.wshift);
-        } else if (KIND == kPolyHigh) {
-            br = rc * rinv * rinv - (k.d0 + r2 * (k.d1 + r2 * k.d2));
-            if (POT) u += aj.w * (rc - (k.c0 + r2 * (k.c1 + r2 * (k.c2 + r2 * k.c3))));
-        } else {
-            br = rc * rinv * rinv - (k.d0 + k.d1 * r2);
-            if (POT) u += aj.w * (rc - (k.c0 + r2 * (k.c1 + r2 * k.c2)));
-        }
-        T t = aj.w * br;
-        if (MD) {
-            // Lennard-Jones (zero for eps = 0, an excluded pair included);
-            // the force on i in final units: coulomb_k q_i q_j br + f_LJ
-            const T eps = same ? T(0) : xi.z * xj.z;
+        T t;
+        if constexpr (KIND == kLJ) {
+            static_assert(MD, "the Lennard-Jones kind reads the aux records");
+            const T eps = mol_of(xi) == mol_of(xj) ? T(0) : xi.z * xj.z;
             const T sg = xi.y + xj.y;
             const T s2 = sg * sg, ir2 = rinv * rinv;
             const T sr2 = s2 * ir2, sr6 = sr2 * sr2 * sr2;
             if (POT) {
                 const T sc2 = s2 * k.inv_a2, sc6 = sc2 * sc2 * sc2;
-                le += T(4) * eps * ((sr6 * sr6 - sr6) - (sc6 * sc6 - sc6));
+                u += T(4) * eps * ((sr6 * sr6 - sr6) - (sc6 * sc6 - sc6));
             }
-            const T fl = T(24) * eps * (T(2) * sr6 * sr6 - sr6) * ir2;
-            t = kq * t + fl;
+            t = T(24) * eps * (T(2) * sr6 * sr6 - sr6) * ir2;
+        } else {
+            T br;
+            if (KIND == kWolf && sizeof(T) == 4) {
+                // single precision: the tabulated E and D
+                const T r = r2 * rinv;
+                float E, D;
+                wolf_lookup(wtab, float(r), k.wscale, E, D);
+                br = T(D) * rinv * rinv * rinv;
+                if (POT) u += aj.w * (T(E) * rinv - k.wshift);
+            } else if (KIND == kWolf) {
+                // erfc(alpha r)/r - erfc(alpha a)/a, and -(d/dr)(erfc(alpha r)/r)/r
+                // = (erfc(alpha r)/r + 2 alpha/sqrt(pi) exp(-alpha^2 r^2)) / r^2
+                const T r = r2 * rinv;
+                const T er = erfc(k.alpha * r);
+                br = (er * rinv + k.wexp * exp(-k.alpha2 * r2)) * rinv * rinv;
+                if (POT) u += aj.w * (er * rinv - k.wshift);
+            } else if (KIND == kPolyHigh) {
+                br = rinv * rinv * rinv - (k.d0 + r2 * (k.d1 + r2 * k.d2));
+                if (POT) u += aj.w * (rinv - (k.c0 + r2 * (k.c1 + r2 * (k.c2 + r2 * k.c3))));
+            } else {
+                br = rinv * rinv * rinv - (k.d0 + k.d1 * r2);
+                if (POT) u += aj.w * (rinv - (k.c0 + r2 * (k.c1 + r2 * k.c2)));
+            }
+            t = aj.w * br;
         }
         fx += t * dx;
         fy += t * dy;
@@ -168,13 +162,6 @@ __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const
     }
 }
 
-// Dynamics variant (MD = true): pairs inside one molecule are excluded from
-// Coulomb's law, so instead of g* they contribute -gamma(r/a)/a, which cancels
-// the smooth part the grids carry for them; and a Lennard-Jones term
-// 4 eps ((s/r)^12 - (s/r)^6), shifted to zero at r = a, acts between atoms of
-// different molecules, with s = s_i/2 + s_j/2 and eps = sqrt(eps_i) sqrt(eps_j)
-// stored per atom in aux = (molecule id bits, s/2, sqrt(eps), 0).
-//
 // Work layout: a workgroup of kPairWaves waves owns one group of 64
 // consecutive sorted atoms (one per lane). The work items are the pieces of
 // cell rows (cy, cz) inside one brick column that can reach the group's
@@ -189,12 +176,10 @@ template <typename T, bool MD, bool POT, int KIND, int kPairWaves>
 __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                               const int *__restrict__ cstart,
                                                               vec4_t<T> *__restrict__ out, PairK<T> k,
-                                                              const vec4_t<T> *__restrict__ saux,
-                                                              vec4_t<T> *__restrict__ ljout)
+                                                              const vec4_t<T> *__restrict__ saux)
 {
     __shared__ PairLds<T, MD> lds[kPairWaves];
     __shared__ vec4_t<T> red[kPairWaves][kWave];
-    __shared__ vec4_t<T> redlj[MD ? kPairWaves : 1][kWave];
     __shared__ WolfLds<T, KIND> wl;
     if (eval_failed(p)) return;
     wl.load(k);
@@ -238,8 +223,6 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
     else if (KIND == kPoly)
         asm volatile("" : "+v"(k.c1), "+v"(k.d0));
     T fx = 0, fy = 0, fz = 0, u = 0;
-    T le = 0;
-    const T kq = MD ? k.ke * ai.w : T(0);   // coulomb_k q_i (dynamics forms)
     // items wv, wv + W, wv + 2W, ..., 64 per batch
     for (int ib = wv; ib < nitems; ib += kPairWaves * kWave) {
         const int q = ib + kPairWaves * lane;            // this lane's item
@@ -314,12 +297,12 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
                 }
 #pragma unroll
                 for (int v = 0; v < kPairUnroll; ++v)
-                    pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, kq, fx, fy, fz, u, le, wtab);
+                    pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, wtab);
             }
             for (; t < cnt; ++t) {
                 const vec4_t<T> aj = L.atom[t];
                 const vec4_t<T> xj = MD ? aux3<T>(L.aux[t]) : aj;
-                pair_term<T, MD, POT, KIND>(ai, xi, aj, xj, k, kq, fx, fy, fz, u, le, wtab);
+                pair_term<T, MD, POT, KIND>(ai, xi, aj, xj, k, fx, fy, fz, u, wtab);
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -330,12 +313,6 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
     o.z = fz;
     o.w = u;
     red[wv][lane] = o;
-    if (MD) {
-        vec4_t<T> ol;
-        ol.x = ol.y = ol.z = T(0);
-        ol.w = le;
-        redlj[MD ? wv : 0][lane] = ol;
-    }
     __syncthreads();
     if (wv == 0 && valid) {
         vec4_t<T> acc = red[0][lane];
@@ -347,17 +324,6 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
             acc.w += v.w;
         }
         out[i] = acc;
-        if (MD) {
-            vec4_t<T> al = redlj[0][lane];
-            for (int w = 1; w < kPairWaves; ++w) {
-                const vec4_t<T> v = redlj[MD ? w : 0][lane];
-                al.x += v.x;
-                al.y += v.y;
-                al.z += v.z;
-                al.w += v.w;
-            }
-            ljout[i] = al;
-        }
     }
 }
 
@@ -383,8 +349,7 @@ template <typename T, bool MD, bool POT, int KIND>
 __global__ __launch_bounds__(kSubLanes * kWave) void k_pair_sub(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                                 const int *__restrict__ cstart,
                                                                 vec4_t<T> *__restrict__ out, PairK<T> k,
-                                                                const vec4_t<T> *__restrict__ saux,
-                                                                vec4_t<T> *__restrict__ ljout)
+                                                                const vec4_t<T> *__restrict__ saux)
 {
     __shared__ PairLds<T, MD> lds[kWave / kSub];
     __shared__ WolfLds<T, KIND> wl;
@@ -428,8 +393,6 @@ __global__ __launch_bounds__(kSubLanes * kWave) void k_pair_sub(DevPlan p, const
     else if (KIND == kPoly)
         asm volatile("" : "+v"(k.c1), "+v"(k.d0));
     T fx = 0, fy = 0, fz = 0, u = 0;
-    T le = 0;
-    const T kq = MD ? k.ke * ai.w : T(0);   // coulomb_k q_i (dynamics forms)
     for (int ib = 0; ib < nitems; ib += kWave) {
         const int q = ib + lane;   // this lane's item
         int len = 0, jb = 0;
@@ -499,14 +462,14 @@ __global__ __launch_bounds__(kSubLanes * kWave) void k_pair_sub(DevPlan p, const
                 }
 #pragma unroll
                 for (int v = 0; v < kSubUnroll; ++v)
-                    pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, kq, fx, fy, fz, u, le, wtab);
+                    pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, wtab);
             }
             for (; t < cnt; t += kSubLanes) {
                 const int tj = t + slot;
                 if (tj < cnt) {
                     const vec4_t<T> aj = L.atom[tj];
                     const vec4_t<T> xj = MD ? aux3<T>(L.aux[tj]) : aj;
-                    pair_term<T, MD, POT, KIND>(ai, xi, aj, xj, k, kq, fx, fy, fz, u, le, wtab);
+                    pair_term<T, MD, POT, KIND>(ai, xi, aj, xj, k, fx, fy, fz, u, wtab);
                 }
             }
         }
@@ -516,9 +479,6 @@ __global__ __launch_bounds__(kSubLanes * kWave) void k_pair_sub(DevPlan p, const
     fy = sum_lanes(fy);
     fz = sum_lanes(fz);
     if (POT) u = sum_lanes(u);
-    if (MD) {
-        if (POT) le = sum_lanes(le);
-    }
     if (slot == 0 && valid) {
         vec4_t<T> o;
         o.x = fx;
@@ -526,12 +486,6 @@ __global__ __launch_bounds__(kSubLanes * kWave) void k_pair_sub(DevPlan p, const
         o.z = fz;
         o.w = u;
         out[i] = o;
-        if (MD) {
-            vec4_t<T> ol;
-            ol.x = ol.y = ol.z = T(0);
-            ol.w = le;
-            ljout[i] = ol;
-        }
     }
 }
 
@@ -657,8 +611,7 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
                                                                 const int *__restrict__ cstart,
                                                                 const int *__restrict__ cluster,
                                                                 vec4_t<T> *__restrict__ out, PairK<T> k,
-                                                                const vec4_t<T> *__restrict__ saux,
-                                                                vec4_t<T> *__restrict__ ljout)
+                                                                const vec4_t<T> *__restrict__ saux)
 {
     constexpr int kSlots = kWave / CA;          // candidates per step
     constexpr int kU = cl_unroll<MD>(), kBlock = kSlots * kU;  // candidates per evaluated block
@@ -721,9 +674,9 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
         asm volatile("" : "+v"(k.c2), "+v"(k.d1));
     else if (KIND == kPoly)
         asm volatile("" : "+v"(k.c1), "+v"(k.d0));
-    T fx[NSUB], fy[NSUB], fz[NSUB], u[NSUB], le[NSUB];
+    T fx[NSUB], fy[NSUB], fz[NSUB], u[NSUB];
 #pragma unroll
-    for (int sc = 0; sc < NSUB; ++sc) fx[sc] = fy[sc] = fz[sc] = u[sc] = le[sc] = T(0);
+    for (int sc = 0; sc < NSUB; ++sc) fx[sc] = fy[sc] = fz[sc] = u[sc] = T(0);
     int *map = L.map[wv], *pre = L.pre[wv], *fst = L.first[wv];
     int head[NSUB], tail[NSUB];   // ring positions (uniform; taken modulo the capacity)
 #pragma unroll
@@ -741,8 +694,7 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
         }
 #pragma unroll
         for (int v = 0; v < kU; ++v)
-            pair_term<T, MD, POT, KIND>(ai[sc], xi[sc], aj[v], xj[v], k, k.ke * ai[sc].w, fx[sc], fy[sc], fz[sc],
-                                        u[sc], le[sc], wtab);
+            pair_term<T, MD, POT, KIND>(ai[sc], xi[sc], aj[v], xj[v], k, fx[sc], fy[sc], fz[sc], u[sc], wtab);
         head[sc] += kBlock;
     };
     for (int ib = 0; ib < nitems; ib += kWave) {
@@ -858,9 +810,6 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
         fy[sc] = sum_slots<CA>(fy[sc]);
         fz[sc] = sum_slots<CA>(fz[sc]);
         if (POT) u[sc] = sum_slots<CA>(u[sc]);
-        if (MD) {
-            if (POT) le[sc] = sum_slots<CA>(le[sc]);
-        }
         if (slot == 0 && valid[sc]) {
             vec4_t<T> o;
             o.x = fx[sc];
@@ -868,12 +817,6 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
             o.z = fz[sc];
             o.w = u[sc];
             out[i[sc]] = o;
-            if (MD) {
-                vec4_t<T> ol;
-                ol.x = ol.y = ol.z = T(0);
-                ol.w = le[sc];
-                ljout[i[sc]] = ol;
-            }
         }
     }
 }
@@ -910,8 +853,7 @@ __global__ __launch_bounds__(GW * kWave) void k_pair_grp(DevPlan p, const vec4_t
                                                           const int *__restrict__ cstart,
                                                           const int *__restrict__ cluster,
                                                           vec4_t<T> *__restrict__ out, PairK<T> k,
-                                                          const vec4_t<T> *__restrict__ saux,
-                                                          vec4_t<T> *__restrict__ ljout)
+                                                          const vec4_t<T> *__restrict__ saux)
 {
     constexpr int CA = 8, kSlots = kWave / CA, kU = cl_unroll<MD>(), kBlock = kSlots * kU, NR = GW * kWave;
     constexpr int kMap = grp_map<GW>();
@@ -975,8 +917,7 @@ __global__ __launch_bounds__(GW * kWave) void k_pair_grp(DevPlan p, const vec4_t
         asm volatile("" : "+v"(k.c2), "+v"(k.d1));
     else if (KIND == kPoly)
         asm volatile("" : "+v"(k.c1), "+v"(k.d0));
-    T fx = 0, fy = 0, fz = 0, u = 0, le = 0;
-    const T kq = MD ? k.ke * ai.w : T(0);   // coulomb_k q_i (dynamics forms)
+    T fx = 0, fy = 0, fz = 0, u = 0;
     int head = 0, tail = 0;   // ring positions (uniform; taken modulo the capacity)
     vec4_t<T> *ring = L.ring[wv];
     vec4_t<T> *raux = L.raux[MD ? wv : 0];
@@ -991,7 +932,7 @@ __global__ __launch_bounds__(GW * kWave) void k_pair_grp(DevPlan p, const vec4_t
         }
 #pragma unroll
         for (int v = 0; v < kU; ++v)
-            pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, kq, fx, fy, fz, u, le, wtab);
+            pair_term<T, MD, POT, KIND>(ai, xi, aj[v], xj[v], k, fx, fy, fz, u, wtab);
         head += kBlock;
     };
     int *map = L.map, *pre = L.pre, *fst = L.first;
@@ -1118,9 +1059,6 @@ __global__ __launch_bounds__(GW * kWave) void k_pair_grp(DevPlan p, const vec4_t
     fy = sum_slots<CA>(fy);
     fz = sum_slots<CA>(fz);
     if (POT) u = sum_slots<CA>(u);
-    if (MD) {
-        if (POT) le = sum_slots<CA>(le);
-    }
     if (slot == 0 && valid) {
         vec4_t<T> o;
         o.x = fx;
@@ -1128,11 +1066,107 @@ __global__ __launch_bounds__(GW * kWave) void k_pair_grp(DevPlan p, const vec4_t
         o.z = fz;
         o.w = u;
         out[i] = o;
-        if (MD) {
-            vec4_t<T> ol;
-            ol.x = ol.y = ol.z = T(0);
-            ol.w = le;
-            ljout[i] = ol;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The dynamics model (Section 2). The pair kernels sum the method's pair term
+// for every pair inside the cutoff, the pairs inside one molecule included.
+// Such a pair must leave only -gamma(r/a)/a in MSM (the negative of the smooth
+// part the grids carry for it) and nothing in the simple cutoff method and
+// Wolf summation, which have no grids: k_exclude takes away, for each partner
+// within the cutoff, 1/r (MSM and the simple cutoff) or the Wolf pair term,
+// with its force bracket. One thread per sorted atom, partners in a fixed
+// order (the model's list, built from the molecule ids when it is bound).
+template <typename T, int KIND, bool POT>
+__global__ __launch_bounds__(256) void k_exclude(DevPlan p, const vec4_t<T> *__restrict__ sx,
+                                                 const int *__restrict__ order, const vec4_t<T> *__restrict__ xin,
+                                                 const int *__restrict__ xstart, const int *__restrict__ xidx,
+                                                 int64_t period, vec4_t<T> *__restrict__ out, PairK<T> k)
+{
+    if (eval_failed(p)) return;
+    const int64_t pos = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (pos >= p.natoms) return;
+    const int64_t o = order[pos];
+    const int64_t mdl = o % period, base = o - mdl;
+    const int e0 = xstart[mdl], e1 = xstart[mdl + 1];
+    if (e0 == e1) return;
+    const vec4_t<T> ai = sx[pos];
+    T fx = 0, fy = 0, fz = 0, u = 0;
+    for (int e = e0; e < e1; ++e) {
+        const int64_t j = base + xidx[e];
+        if (j >= p.natoms) continue;   // a model that does not fit the batch
+        const vec4_t<T> aj = xin[j];
+        const T dx = ai.x - aj.x, dy = ai.y - aj.y, dz = ai.z - aj.z;
+        const T r2 = dx * dx + dy * dy + dz * dz;
+        if (r2 < k.a2 && r2 > T(0)) {
+            const T rinv = rsqrt_t(r2);
+            T br, pu;
+            if (KIND == kWolf && sizeof(T) == 4) {
+                const T r = r2 * rinv;
+                float E, D;
+                wolf_lookup(k.wtab, float(r), k.wscale, E, D);
+                br = T(D) * rinv * rinv * rinv;
+                pu = T(E) * rinv - k.wshift;
+            } else if (KIND == kWolf) {
+                const T r = r2 * rinv;
+                const T er = erfc(k.alpha * r);
+                br = (er * rinv + k.wexp * exp(-k.alpha2 * r2)) * rinv * rinv;
+                pu = er * rinv - k.wshift;
+            } else {
+                br = rinv * rinv * rinv;
+                pu = rinv;
+            }
+            const T t = aj.w * br;
+            fx += t * dx;
+            fy += t * dy;
+            fz += t * dz;
+            if (POT) u += aj.w * pu;
+        }
+    }
+    vec4_t<T> v = out[pos];
+    v.x -= fx;
+    v.y -= fy;
+    v.z -= fz;
+    if (POT) v.w -= u;
+    out[pos] = v;
+}
+
+// Lennard-Jones runs over the atoms that carry it (eps > 0; in water only the
+// oxygens, a third of the atoms and a ninth of the pairs): k_lj_count counts
+// them per cell (every cell written), a scan places the cells, and k_lj_fill
+// copies them, in sorted order, with their aux records into a cell-sorted
+// subset that the cluster pair kernel then runs over as over the full set
+// (lj_of: sorted position -> subset index, or -1).
+template <typename T>
+__global__ __launch_bounds__(256) void k_lj_count(DevPlan p, const int *__restrict__ cstart,
+                                                  const vec4_t<T> *__restrict__ saux, int *__restrict__ cnt)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= p.ncells) return;
+    int n = 0;
+    if (!eval_failed(p))   // a failed evaluation may pile every atom into one cell
+        for (int pos = cstart[c]; pos < cstart[c + 1]; ++pos) n += saux[pos].z != T(0);
+    cnt[c] = n;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_lj_fill(DevPlan p, const int *__restrict__ cstart,
+                                                 const vec4_t<T> *__restrict__ sx, const vec4_t<T> *__restrict__ saux,
+                                                 const int *__restrict__ sstart, vec4_t<T> *__restrict__ lx,
+                                                 vec4_t<T> *__restrict__ laux, int *__restrict__ lof)
+{
+    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (c >= p.ncells || eval_failed(p)) return;
+    int r = sstart[c];
+    for (int pos = cstart[c]; pos < cstart[c + 1]; ++pos) {
+        const vec4_t<T> a = saux[pos];
+        if (a.z != T(0)) {
+            lx[r] = sx[pos];
+            laux[r] = a;
+            lof[pos] = r++;
+        } else {
+            lof[pos] = -1;
         }
     }
 }
@@ -1142,19 +1176,13 @@ static void pair_launch_grp(hipStream_t s, const DevPlan &p, const Work<T> &w, c
 {
     hipLaunchKernelGGL((k_clusters<T, 8>), dim3((unsigned)p.ngroups), dim3(kWave), 0, s, p, w.sxyzq, w.cluster);
     const dim3 grid((unsigned)(p.ngroups * (8 / GW))), block(GW * kWave);
-    const vec4_t<T> *aux = (const vec4_t<T> *)w.saux;
-    if (w.saux && pot)
-        hipLaunchKernelGGL((k_pair_grp<T, true, true, KIND, GW>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
-                           w.cluster, w.shrt, k, aux, w.shlj);
-    else if (w.saux)
-        hipLaunchKernelGGL((k_pair_grp<T, true, false, KIND, GW>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
-                           w.cluster, w.shrt, k, aux, w.shlj);
-    else if (pot)
+    const vec4_t<T> *none = nullptr;
+    if (pot)
         hipLaunchKernelGGL((k_pair_grp<T, false, true, KIND, GW>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
-                           w.cluster, w.shrt, k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+                           w.cluster, w.shrt, k, none);
     else
         hipLaunchKernelGGL((k_pair_grp<T, false, false, KIND, GW>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
-                           w.cluster, w.shrt, k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+                           w.cluster, w.shrt, k, none);
 }
 
 template <typename T, int KIND, int NSUB, int CA>
@@ -1164,57 +1192,39 @@ static void pair_launch_cl(hipStream_t s, const DevPlan &p, const Work<T> &w, co
     const int64_t nclusters = p.ngroups * (kWave / CA);
     const int64_t per_wg = (int64_t)kClWgWaves * NSUB;
     const dim3 grid((unsigned)((nclusters + per_wg - 1) / per_wg)), block(kClWgWaves * kWave);
-    const vec4_t<T> *aux = (const vec4_t<T> *)w.saux;
-    if (w.saux && pot)
-        hipLaunchKernelGGL((k_pair_cl<T, true, true, KIND, NSUB, CA>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
-                           w.cluster, w.shrt, k, aux, w.shlj);
-    else if (w.saux)
-        hipLaunchKernelGGL((k_pair_cl<T, true, false, KIND, NSUB, CA>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
-                           w.cluster, w.shrt, k, aux, w.shlj);
-    else if (pot)
+    const vec4_t<T> *none = nullptr;
+    if (pot)
         hipLaunchKernelGGL((k_pair_cl<T, false, true, KIND, NSUB, CA>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
-                           w.cluster, w.shrt, k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+                           w.cluster, w.shrt, k, none);
     else
         hipLaunchKernelGGL((k_pair_cl<T, false, false, KIND, NSUB, CA>), grid, block, 0, s, p, w.sxyzq, w.cell_start,
-                           w.cluster, w.shrt, k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+                           w.cluster, w.shrt, k, none);
 }
 
 template <typename T, int KIND>
 static void pair_launch_sub(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot)
 {
     const dim3 grid((unsigned)p.ngroups), block(kSubLanes * kWave);
-    const vec4_t<T> *aux = (const vec4_t<T> *)w.saux;
-    if (w.saux && pot)
-        hipLaunchKernelGGL((k_pair_sub<T, true, true, KIND>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
-                           aux, w.shlj);
-    else if (w.saux)
-        hipLaunchKernelGGL((k_pair_sub<T, true, false, KIND>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt,
-                           k, aux, w.shlj);
-    else if (pot)
+    const vec4_t<T> *none = nullptr;
+    if (pot)
         hipLaunchKernelGGL((k_pair_sub<T, false, true, KIND>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt,
-                           k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+                           k, none);
     else
         hipLaunchKernelGGL((k_pair_sub<T, false, false, KIND>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt,
-                           k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+                           k, none);
 }
 
 template <typename T, int KIND, int NW>
 static void pair_launch(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot)
 {
     const dim3 grid((unsigned)p.ngroups), block(NW * kWave);
-    const vec4_t<T> *aux = (const vec4_t<T> *)w.saux;
-    if (w.saux && pot)
-        hipLaunchKernelGGL((k_pair<T, true, true, KIND, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
-                           aux, w.shlj);
-    else if (w.saux)
-        hipLaunchKernelGGL((k_pair<T, true, false, KIND, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
-                           aux, w.shlj);
-    else if (pot)
+    const vec4_t<T> *none = nullptr;
+    if (pot)
         hipLaunchKernelGGL((k_pair<T, false, true, KIND, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt, k,
-                           (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+                           none);
     else
         hipLaunchKernelGGL((k_pair<T, false, false, KIND, NW>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.shrt,
-                           k, (const vec4_t<T> *)nullptr, (vec4_t<T> *)nullptr);
+                           k, none);
 }
 
 template <typename T, int NW>
@@ -1267,10 +1277,9 @@ void wolf_table(double a, double alpha, float *out)
     }
 }
 
-template <typename T>
-hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m, bool pot)
+// The pair constants of the method (all kernels of this file use them).
+template <typename T> static PairK<T> pair_constants(const MethodConst &m)
 {
-    if (p.ngroups == 0) return hipSuccess;
     PairK<T> k{};
     const double a = m.a;
     k.a2 = T(a * a);
@@ -1299,11 +1308,23 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, co
     k.alpha2 = T(m.alpha * m.alpha);
     k.wshift = T(std::erfc(m.alpha * a) / a);
     k.wexp = T(2.0 * m.alpha / std::sqrt(std::acos(-1.0)));
-    k.ke = T(m.ke);
     k.wtab = m.wolf_tab;
     k.wscale = float(kWolfPieces / a);
+    return k;
+}
+
+static int pair_kind(const MethodConst &m)
+{
+    return m.method == MSM_METHOD_WOLF ? kWolf : (m.method == MSM_METHOD_MSM && m.g.m == 3 ? kPolyHigh : kPoly);
+}
+
+template <typename T>
+hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m, bool pot)
+{
+    if (p.ngroups == 0) return hipSuccess;
+    const PairK<T> k = pair_constants<T>(m);
     if (m.method == MSM_METHOD_WOLF && sizeof(T) == 4 && !k.wtab) return hipErrorInvalidValue;
-    const int kind = m.method == MSM_METHOD_WOLF ? kWolf : (m.method == MSM_METHOD_MSM && m.g.m == 3 ? kPolyHigh : kPoly);
+    const int kind = pair_kind(m);
     switch (m.pair_waves) {
     case 1: pair_launch_m<T, 1>(s, p, w, k, pot, kind); break;
     case 2: pair_launch_m<T, 2>(s, p, w, k, pot, kind); break;
@@ -1320,7 +1341,60 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, co
     return hipGetLastError();
 }
 
-template hipError_t Launch<float>::pair(hipStream_t, const DevPlan &, const Work<float> &, const MethodConst &, bool);
-template hipError_t Launch<double>::pair(hipStream_t, const DevPlan &, const Work<double> &, const MethodConst &, bool);
+template <typename T>
+hipError_t Launch<T>::exclusions(hipStream_t s, const DevPlan &p, const Work<T> &w, const vec4_t<T> *xyzq,
+                                 const MethodConst &m, bool pot)
+{
+    if (p.natoms == 0 || !w.xstart) return hipSuccess;
+    const PairK<T> k = pair_constants<T>(m);
+    const dim3 grid((unsigned)((p.natoms + 255) / 256)), block(256);
+#define MSMX_EXCL(KIND, POT)                                                                                         \
+    hipLaunchKernelGGL((k_exclude<T, KIND, POT>), grid, block, 0, s, p, w.sxyzq, w.order, xyzq, w.xstart, w.xidx, \
+                       w.period, w.shrt, k)
+    if (m.method == MSM_METHOD_WOLF) {
+        if (pot) MSMX_EXCL(kWolf, true);
+        else MSMX_EXCL(kWolf, false);
+    } else {
+        if (pot) MSMX_EXCL(kPoly, true);
+        else MSMX_EXCL(kPoly, false);
+    }
+#undef MSMX_EXCL
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t Launch<T>::lj(hipStream_t s, const DevPlan &p, const DevPlan &sub, const Work<T> &w, const MethodConst &m,
+                         bool pot)
+{
+    if (!w.lj_x || p.ncells == 0) return hipSuccess;
+    const dim3 cgrid((unsigned)((p.ncells + 255) / 256)), block(256);
+    hipLaunchKernelGGL(k_lj_count<T>, cgrid, block, 0, s, p, w.cell_start, (const vec4_t<T> *)w.saux, w.lj_cnt);
+    scan_cells(s, w.lj_cnt, w.lj_start, p.ncells + 1, w.lj_blocks);
+    hipLaunchKernelGGL(k_lj_fill<T>, cgrid, block, 0, s, p, w.cell_start, w.sxyzq, (const vec4_t<T> *)w.saux,
+                       w.lj_start, w.lj_x, w.lj_aux, w.lj_of);
+    if (sub.ngroups == 0) return hipGetLastError();
+    const PairK<T> k = pair_constants<T>(m);
+    hipLaunchKernelGGL((k_clusters<T, 8>), dim3((unsigned)sub.ngroups), dim3(kWave), 0, s, sub, w.lj_x, w.lj_cluster);
+    const int64_t nclusters = sub.ngroups * (kWave / 8);
+    const dim3 grid((unsigned)((nclusters + kClWgWaves - 1) / kClWgWaves)), pblock(kClWgWaves * kWave);
+    const vec4_t<T> *aux = w.lj_aux;
+    if (pot)
+        hipLaunchKernelGGL((k_pair_cl<T, true, true, kLJ, 1, 8>), grid, pblock, 0, s, sub, w.lj_x, w.lj_start,
+                           w.lj_cluster, w.lj_out, k, aux);
+    else
+        hipLaunchKernelGGL((k_pair_cl<T, true, false, kLJ, 1, 8>), grid, pblock, 0, s, sub, w.lj_x, w.lj_start,
+                           w.lj_cluster, w.lj_out, k, aux);
+    return hipGetLastError();
+}
+
+#define MSMX_PAIR_INST(T)                                                                                            \
+    template hipError_t Launch<T>::pair(hipStream_t, const DevPlan &, const Work<T> &, const MethodConst &, bool);   \
+    template hipError_t Launch<T>::exclusions(hipStream_t, const DevPlan &, const Work<T> &, const vec4_t<T> *,      \
+                                              const MethodConst &, bool);                                            \
+    template hipError_t Launch<T>::lj(hipStream_t, const DevPlan &, const DevPlan &, const Work<T> &,                \
+                                      const MethodConst &, bool);
+MSMX_PAIR_INST(float)
+MSMX_PAIR_INST(double)
+#undef MSMX_PAIR_INST
 
 }  // namespace msmx
