@@ -73,6 +73,47 @@ __global__ void k_bin_count(DevPlan p, const vec4_t<T> *__restrict__ xyzq, int *
     slot_of[i] = atomicAdd(&counts[cell], 1);
 }
 
+// The atoms that carry Lennard-Jones (a bound model's atoms with a nonzero
+// sqrt(eps)) in cells of their own (edge and cell layout from the subset
+// plan pl, one system plan per system of the batch plan p): the histogram of
+// k_bin_count for those atoms only (the others get cell -1). Positions were
+// checked by the batch's own binning; here they are only clamped.
+template <typename T>
+__global__ void k_lj_bin_count(DevPlan p, const SysPlan *__restrict__ lsys, const vec4_t<T> *__restrict__ xyzq,
+                               const vec4_t<T> *__restrict__ maux, int64_t period, int *__restrict__ cell_of,
+                               int *__restrict__ slot_of, int *__restrict__ counts)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= p.natoms) return;
+    if (maux[i % period].z == T(0)) {
+        cell_of[i] = -1;
+        return;
+    }
+    const SysPlan &P = lsys[find_segment(p.atom_prefix, p.nsys, i)];
+    const vec4_t<T> a = xyzq[i];
+    const T pos[3] = {a.x, a.y, a.z};
+    int c[3];
+    for (int d = 0; d < 3; d++) {
+        const T t = (pos[d] - T(P.lo[d])) * T(P.inv_h);
+        int ci = (t >= T(0)) ? (int)floor(t) : 0;   // also 0 for a non-finite t
+        if (ci > P.nc[d] - 1) ci = P.nc[d] - 1;
+        c[d] = ci;
+    }
+    const int cell = (int)(P.cell0 + cell_rank(P, c[0], c[1], c[2]));
+    cell_of[i] = cell;
+    slot_of[i] = atomicAdd(&counts[cell], 1);
+}
+
+__global__ void k_lj_scatter(int64_t n, const int *__restrict__ cell_of, const int *__restrict__ slot_of,
+                             const int *__restrict__ start, int *__restrict__ order, int *__restrict__ pos_of)
+{
+    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int cell = cell_of[i];
+    if (cell < 0) pos_of[i] = -1;
+    else order[start[cell] + slot_of[i]] = (int)i;
+}
+
 // Exclusive scan of int counts: per-block sums, then each block adds the
 // sums of the blocks before it to its own scan. A thread takes IPT
 // consecutive counts (16-byte loads), waves scan with lane shuffles, and one
@@ -224,7 +265,7 @@ template <typename T>
 __global__ void k_cell_sort_thread(int64_t ncells, const int *__restrict__ start, int *__restrict__ order,
                                    const vec4_t<T> *__restrict__ xyzq, vec4_t<T> *__restrict__ sxyzq,
                                    const vec4_t<T> *__restrict__ maux, vec4_t<T> *__restrict__ saux, int64_t period,
-                                   const int *__restrict__ evflag)
+                                   const int *__restrict__ evflag, int *__restrict__ pos_of)
 {
     int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (c >= ncells) return;
@@ -234,6 +275,8 @@ __global__ void k_cell_sort_thread(int64_t ncells, const int *__restrict__ start
     for (int i = b; i < e; i++) sxyzq[i] = xyzq[order[i]];
     if (maux)
         for (int i = b; i < e; i++) saux[i] = maux[order[i] % period];
+    if (pos_of)
+        for (int i = b; i < e; i++) pos_of[order[i]] = i;
 }
 
 // One wave per cell, for crowded cells (coarse h): lane l holds the cell's l-th
@@ -246,7 +289,7 @@ __global__ __launch_bounds__(256) void k_cell_sort(int64_t ncells, const int *__
                                                    int *__restrict__ order, const vec4_t<T> *__restrict__ xyzq,
                                                    vec4_t<T> *__restrict__ sxyzq, const vec4_t<T> *__restrict__ maux,
                                                    vec4_t<T> *__restrict__ saux, int64_t period,
-                                                   const int *__restrict__ evflag)
+                                                   const int *__restrict__ evflag, int *__restrict__ pos_of)
 {
     const int64_t c = (int64_t)blockIdx.x * 4 + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / 64));
     if (c >= ncells) return;
@@ -260,6 +303,8 @@ __global__ __launch_bounds__(256) void k_cell_sort(int64_t ncells, const int *__
             for (int i = b; i < b + n; i++) sxyzq[i] = xyzq[order[i]];
             if (maux)
                 for (int i = b; i < b + n; i++) saux[i] = maux[order[i] % period];
+            if (pos_of)
+                for (int i = b; i < b + n; i++) pos_of[order[i]] = i;
         }
         return;
     }
@@ -270,6 +315,7 @@ __global__ __launch_bounds__(256) void k_cell_sort(int64_t ncells, const int *__
         order[b + rank] = v;
         sxyzq[b + rank] = xyzq[v];
         if (maux) saux[b + rank] = maux[v % period];
+        if (pos_of) pos_of[v] = b + rank;
     }
 }
 
@@ -339,14 +385,41 @@ hipError_t Launch<T>::bin(hipStream_t s, const DevPlan &p, const Work<T> &w, con
         if (p.natoms > 2 * p.ncells)
             hipLaunchKernelGGL(k_cell_sort<T>, dim3(nblocks(p.ncells, 4)), dim3(256), 0, s, p.ncells,
                                w.cell_start, w.order, xyzq, w.sxyzq, (const vec4_t<T> *)w.maux, w.saux, w.period,
-                               (const int *)p.evflag);
+                               (const int *)p.evflag, (int *)nullptr);
         else
             hipLaunchKernelGGL(k_cell_sort_thread<T>, dim3(nblocks(p.ncells, 256)), dim3(256), 0, s, p.ncells,
                                w.cell_start, w.order, xyzq, w.sxyzq, (const vec4_t<T> *)w.maux, w.saux, w.period,
-                               (const int *)p.evflag);
+                               (const int *)p.evflag, (int *)nullptr);
     }
     return hipGetLastError();
 }
+
+template <typename T>
+hipError_t bin_lj(hipStream_t s, const DevPlan &p, const DevPlan &pl, const Work<T> &w, const vec4_t<T> *xyzq)
+{
+    if (p.natoms == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_lj_bin_count<T>, dim3(nblocks(p.natoms, 256)), dim3(256), 0, s, p, pl.sys, xyzq,
+                       (const vec4_t<T> *)w.maux, w.period, w.lj_cell_of, w.lj_slot_of, w.lj_cnt);
+    scan_cells(s, w.lj_cnt, w.lj_start, pl.ncells + 1, w.lj_blocks);
+    hipLaunchKernelGGL(k_lj_scatter, dim3(nblocks(p.natoms, 256)), dim3(256), 0, s, p.natoms, w.lj_cell_of,
+                       w.lj_slot_of, w.lj_start, w.lj_order, w.lj_of);
+    // per-cell order by input index, the atoms and their records gathered,
+    // and each atom's place recorded (a period beyond any index: the records
+    // are the model's, indexed by input atom modulo the period)
+    if (pl.natoms > 2 * pl.ncells)
+        hipLaunchKernelGGL(k_cell_sort<T>, dim3(nblocks(pl.ncells, 4)), dim3(256), 0, s, pl.ncells, w.lj_start,
+                           w.lj_order, xyzq, w.lj_x, (const vec4_t<T> *)w.maux, w.lj_aux, w.period,
+                           (const int *)p.evflag, w.lj_of);
+    else
+        hipLaunchKernelGGL(k_cell_sort_thread<T>, dim3(nblocks(pl.ncells, 256)), dim3(256), 0, s, pl.ncells,
+                           w.lj_start, w.lj_order, xyzq, w.lj_x, (const vec4_t<T> *)w.maux, w.lj_aux, w.period,
+                           (const int *)p.evflag, w.lj_of);
+    return hipGetLastError();
+}
+template hipError_t bin_lj<float>(hipStream_t, const DevPlan &, const DevPlan &, const Work<float> &,
+                                  const vec4_t<float> *);
+template hipError_t bin_lj<double>(hipStream_t, const DevPlan &, const DevPlan &, const Work<double> &,
+                                   const vec4_t<double> *);
 
 template hipError_t Launch<float>::bin(hipStream_t, const DevPlan &, const Work<float> &, const vec4_t<float> *);
 template hipError_t Launch<double>::bin(hipStream_t, const DevPlan &, const Work<double> &, const vec4_t<double> *);

@@ -320,6 +320,7 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     std::vector<SysPlan> &lj_sys = ps.lj_sys;
     std::vector<int64_t> &lj_group_p = ps.lj_group_p;
     int64_t lj_atoms = 0, lj_groups = 0;
+    int64_t lj_cells = 0;
     if (lj) {
         const int64_t period = (int64_t)c->lj_prefix.size() - 1, per = c->lj_prefix[period];
         auto before = [&](int64_t i) { return (i / period) * per + c->lj_prefix[i % period]; };
@@ -328,6 +329,21 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
         for (int s = 0; s < nsys; s++) {
             SysPlan &P = lj_sys[s];
             const int64_t n = before(offsets[s + 1]) - before(offsets[s]);
+            // cells of their own: an edge that holds about kLjCellAtoms of them
+            // at their mean density, no finer than h (the cell capacity) and
+            // no coarser than a
+            double vol = 1.0;
+            for (int d = 0; d < 3; d++) vol *= std::max(sys[s].tmax[d] * c->prm.h, c->prm.h);
+            const double edge = std::min(c->prm.a, std::max(c->prm.h, std::cbrt(kLjCellAtoms * vol / std::max<int64_t>(n, 1))));
+            P.inv_h = 1.0 / edge;
+            for (int d = 0; d < 3; d++) {
+                P.tmax[d] = sys[s].tmax[d] * c->prm.h / edge;
+                P.nc[d] = (int)std::floor(P.tmax[d]) + 1;
+                P.nb[d] = (P.nc[d] + kBrick - 1) / kBrick;
+            }
+            P.cell0 = lj_cells;
+            P.ncells = (int64_t)P.nb[0] * P.nb[1] * P.nb[2] * kBrickCells;
+            lj_cells += P.ncells;
             P.atom0 = lj_atoms;
             P.natoms = n;
             P.group0 = lj_groups;
@@ -337,6 +353,7 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
             lj_groups += P.ngroups;
         }
         lj_group_p[nsys] = lj_groups;
+        if (lj_cells > c->cap_cells) return MSM_ERR_CAPACITY;
     }
 
     // pack the tables into one blob
@@ -450,9 +467,11 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
         c->dps.group_prefix = (const int64_t *)(d + o_ljgroup);
         c->dps.natoms = lj_atoms;
         c->dps.ngroups = lj_groups;
+        c->dps.ncells = lj_cells;
     } else {
         c->dps.natoms = 0;
         c->dps.ngroups = 0;
+        c->dps.ncells = 0;
     }
     c->host_sys = sys;
     c->last_offsets.assign(offsets, offsets + nsys + 1);
@@ -512,7 +531,7 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     if (do_short && (e = L::pair(ps, p, w, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
     if (do_short && c->md_bound) {
         if ((e = L::exclusions(ps, p, w, (const vec4_t<T> *)xyzq, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
-        if ((e = L::lj(ps, p, c->dps, w, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
+        if ((e = L::lj(ps, p, c->dps, w, (const vec4_t<T> *)xyzq, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
     }
     if (!ant_first) {
         mark(MSM_STAGE_ANTERP);

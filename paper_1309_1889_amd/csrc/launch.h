@@ -70,14 +70,18 @@ template <typename T> struct Work {
     int64_t period;      // batch atom i uses model entry i % period
     int *xstart, *xidx;  // excluded partners of model atom m: xidx[xstart[m] .. xstart[m+1]) (model
                          // indices, ascending); null without molecule ids
-    // the atoms that carry Lennard-Jones (null when none does), in sorted order
-    int *lj_cnt;         // ncells + 1: per-cell count (the scan clears it)
-    int *lj_start;       // ncells + 1: their cell starts
+    // the atoms that carry Lennard-Jones (null when none does), binned into
+    // cells of their own (the subset plan's)
+    int *lj_cell_of;     // per input atom: its subset cell, or -1
+    int *lj_slot_of;     // per input atom: arrival slot within that cell
+    int *lj_cnt;         // subset cells + 1: histogram, zero between evaluations
+    int *lj_start;       // subset cells + 1: cell starts
     int *lj_blocks;      // block sums of that scan
-    int *lj_of;          // sorted position -> subset index, or -1
+    int *lj_order;       // subset sorted position -> input atom
+    int *lj_of;          // input atom -> subset sorted position, or -1
     int *lj_cluster;     // the subset's k-d clusters
-    vec4_t<T> *lj_x;     // subset positions and charges
-    vec4_t<T> *lj_aux;   // subset aux records
+    vec4_t<T> *lj_x;     // subset positions and charges, sorted
+    vec4_t<T> *lj_aux;   // subset aux records, sorted
     vec4_t<T> *lj_out;   // subset: Lennard-Jones force and energy (counted from both sides)
 };
 
@@ -144,12 +148,12 @@ template <typename T> struct Launch {
     static hipError_t pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m, bool pot);
     // after pair, with a molecular model bound: take the excluded pairs of each
     // molecule out of the short-range sums (xyzq: the evaluation's input), and
-    // the Lennard-Jones forces and energies of the atoms that carry them (sub:
-    // the plan of that subset)
+    // the Lennard-Jones forces and energies of the atoms that carry them,
+    // binned into the cells of their own plan sub
     static hipError_t exclusions(hipStream_t s, const DevPlan &p, const Work<T> &w, const vec4_t<T> *xyzq,
                                  const MethodConst &m, bool pot);
-    static hipError_t lj(hipStream_t s, const DevPlan &p, const DevPlan &sub, const Work<T> &w, const MethodConst &m,
-                         bool pot);
+    static hipError_t lj(hipStream_t s, const DevPlan &p, const DevPlan &sub, const Work<T> &w,
+                         const vec4_t<T> *xyzq, const MethodConst &m, bool pot);
     static hipError_t anterp(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m);
     static hipError_t restrict_level(hipStream_t s, const DevPlan &p, const Work<T> &w, int k, const MethodConst &m);
     // the lattice cutoff of every level below the top and the top level
@@ -169,6 +173,16 @@ template <typename T> struct Launch {
 };
 
 hipError_t fill_i32(hipStream_t s, int *p, int64_t n, int v);
+// Lennard-Jones subset cells: an edge that holds about this many of its atoms
+// at their mean density (clamped to [h, a])
+#ifndef MSMX_LJ_CELL_ATOMS
+#define MSMX_LJ_CELL_ATOMS 2.0
+#endif
+constexpr double kLjCellAtoms = MSMX_LJ_CELL_ATOMS;
+// Bin the atoms of the batch plan p that carry Lennard-Jones into the cells of
+// the subset plan pl (the Work's lj_* arrays).
+template <typename T>
+hipError_t bin_lj(hipStream_t s, const DevPlan &p, const DevPlan &pl, const Work<T> &w, const vec4_t<T> *xyzq);
 // Copy bytes of host memory to device memory through kernel arguments
 // (2 KiB per launch), so that the copy allocates nothing and the source may
 // be reused as soon as the call returns. dst and bytes: multiples of 4.

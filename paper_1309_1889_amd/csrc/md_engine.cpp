@@ -102,7 +102,8 @@ template <typename T> int bind(msm_ctx *c, const msm_md_model *m)
     const size_t o_xi = excl ? take(sizeof(int32_t) * xidx.size()) : 0;
     const size_t o_lcnt = ljs ? take(sizeof(int) * cells1) : 0, o_lstart = ljs ? take(sizeof(int) * cells1) : 0;
     const size_t o_lblk = ljs ? take(sizeof(int) * std::max<int64_t>(kScanFewBlocks, cells1 / 4096 + 2)) : 0;
-    const size_t o_lof = ljs ? take(sizeof(int) * na) : 0;
+    const size_t o_lof = ljs ? take(sizeof(int) * na) : 0, o_lord = ljs ? take(sizeof(int) * na) : 0;
+    const size_t o_lcell = ljs ? take(sizeof(int) * na) : 0, o_lslot = ljs ? take(sizeof(int) * na) : 0;
     const size_t o_lcl = ljs ? take(sizeof(int) * (na + (int64_t)kWave * c->prm.max_systems)) : 0;
     const size_t o_lx = ljs ? take(sizeof(vec4_t<T>) * (na + 64)) : 0, o_laux = ljs ? take(sizeof(vec4_t<T>) * (na + 64)) : 0;
     const size_t o_lout = ljs ? take(sizeof(vec4_t<T>) * na) : 0;
@@ -126,6 +127,9 @@ template <typename T> int bind(msm_ctx *c, const msm_md_model *m)
     w.lj_start = ljs ? (int *)(b + o_lstart) : nullptr;
     w.lj_blocks = ljs ? (int *)(b + o_lblk) : nullptr;
     w.lj_of = ljs ? (int *)(b + o_lof) : nullptr;
+    w.lj_order = ljs ? (int *)(b + o_lord) : nullptr;
+    w.lj_cell_of = ljs ? (int *)(b + o_lcell) : nullptr;
+    w.lj_slot_of = ljs ? (int *)(b + o_lslot) : nullptr;
     w.lj_cluster = ljs ? (int *)(b + o_lcl) : nullptr;
     w.lj_x = ljs ? (vec4_t<T> *)(b + o_lx) : nullptr;
     w.lj_aux = ljs ? (vec4_t<T> *)(b + o_laux) : nullptr;

@@ -869,8 +869,8 @@ constexpr int kInterpThreads = 256;
 
 // GRID: add the grid part; SHORT: add the short-range pair part that the
 // pair kernel left in shrt, and, with a molecular model bound, the
-// Lennard-Jones force and energy of the atoms that carry it (ljof: sorted
-// position -> index into ljout, or -1; null without a model).
+// Lennard-Jones force and energy of the atoms that carry it (ljof: input
+// atom -> index into ljout, or -1; null without a model).
 template <typename T, bool GRID, bool SHORT, int PD>
 __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                            const vec4_t<T> *__restrict__ shrt,
@@ -939,7 +939,7 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4
         vec4_t<T> lj;
         lj.x = lj.y = lj.z = lj.w = T(0);
         if (SHORT && ljof && !eval_failed(p)) {
-            const int li = ljof[pos];
+            const int li = ljof[o];
             if (li >= 0) lj = ljout[li];
         }
         if (forces) {

@@ -1132,45 +1132,6 @@ __global__ __launch_bounds__(256) void k_exclude(DevPlan p, const vec4_t<T> *__r
     out[pos] = v;
 }
 
-// Lennard-Jones runs over the atoms that carry it (eps > 0; in water only the
-// oxygens, a third of the atoms and a ninth of the pairs): k_lj_count counts
-// them per cell (every cell written), a scan places the cells, and k_lj_fill
-// copies them, in sorted order, with their aux records into a cell-sorted
-// subset that the cluster pair kernel then runs over as over the full set
-// (lj_of: sorted position -> subset index, or -1).
-template <typename T>
-__global__ __launch_bounds__(256) void k_lj_count(DevPlan p, const int *__restrict__ cstart,
-                                                  const vec4_t<T> *__restrict__ saux, int *__restrict__ cnt)
-{
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= p.ncells) return;
-    int n = 0;
-    if (!eval_failed(p))   // a failed evaluation may pile every atom into one cell
-        for (int pos = cstart[c]; pos < cstart[c + 1]; ++pos) n += saux[pos].z != T(0);
-    cnt[c] = n;
-}
-
-template <typename T>
-__global__ __launch_bounds__(256) void k_lj_fill(DevPlan p, const int *__restrict__ cstart,
-                                                 const vec4_t<T> *__restrict__ sx, const vec4_t<T> *__restrict__ saux,
-                                                 const int *__restrict__ sstart, vec4_t<T> *__restrict__ lx,
-                                                 vec4_t<T> *__restrict__ laux, int *__restrict__ lof)
-{
-    const int64_t c = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (c >= p.ncells || eval_failed(p)) return;
-    int r = sstart[c];
-    for (int pos = cstart[c]; pos < cstart[c + 1]; ++pos) {
-        const vec4_t<T> a = saux[pos];
-        if (a.z != T(0)) {
-            lx[r] = sx[pos];
-            laux[r] = a;
-            lof[pos] = r++;
-        } else {
-            lof[pos] = -1;
-        }
-    }
-}
-
 template <typename T, int KIND, int GW>
 static void pair_launch_grp(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot)
 {
@@ -1362,27 +1323,30 @@ hipError_t Launch<T>::exclusions(hipStream_t s, const DevPlan &p, const Work<T> 
     return hipGetLastError();
 }
 
+// cluster size of the Lennard-Jones subset's pair kernel
+#ifndef MSMX_LJ_CLUSTER
+#define MSMX_LJ_CLUSTER 8
+#endif
+constexpr int kLjCluster = MSMX_LJ_CLUSTER;
+
 template <typename T>
-hipError_t Launch<T>::lj(hipStream_t s, const DevPlan &p, const DevPlan &sub, const Work<T> &w, const MethodConst &m,
-                         bool pot)
+hipError_t Launch<T>::lj(hipStream_t s, const DevPlan &p, const DevPlan &sub, const Work<T> &w, const vec4_t<T> *xyzq,
+                         const MethodConst &m, bool pot)
 {
-    if (!w.lj_x || p.ncells == 0) return hipSuccess;
-    const dim3 cgrid((unsigned)((p.ncells + 255) / 256)), block(256);
-    hipLaunchKernelGGL(k_lj_count<T>, cgrid, block, 0, s, p, w.cell_start, (const vec4_t<T> *)w.saux, w.lj_cnt);
-    scan_cells(s, w.lj_cnt, w.lj_start, p.ncells + 1, w.lj_blocks);
-    hipLaunchKernelGGL(k_lj_fill<T>, cgrid, block, 0, s, p, w.cell_start, w.sxyzq, (const vec4_t<T> *)w.saux,
-                       w.lj_start, w.lj_x, w.lj_aux, w.lj_of);
-    if (sub.ngroups == 0) return hipGetLastError();
+    if (!w.lj_x || p.natoms == 0) return hipSuccess;
+    hipError_t e = bin_lj<T>(s, p, sub, w, xyzq);
+    if (e != hipSuccess || sub.ngroups == 0) return e;
     const PairK<T> k = pair_constants<T>(m);
-    hipLaunchKernelGGL((k_clusters<T, 8>), dim3((unsigned)sub.ngroups), dim3(kWave), 0, s, sub, w.lj_x, w.lj_cluster);
-    const int64_t nclusters = sub.ngroups * (kWave / 8);
+    constexpr int CA = kLjCluster;
+    hipLaunchKernelGGL((k_clusters<T, CA>), dim3((unsigned)sub.ngroups), dim3(kWave), 0, s, sub, w.lj_x, w.lj_cluster);
+    const int64_t nclusters = sub.ngroups * (kWave / CA);
     const dim3 grid((unsigned)((nclusters + kClWgWaves - 1) / kClWgWaves)), pblock(kClWgWaves * kWave);
     const vec4_t<T> *aux = w.lj_aux;
     if (pot)
-        hipLaunchKernelGGL((k_pair_cl<T, true, true, kLJ, 1, 8>), grid, pblock, 0, s, sub, w.lj_x, w.lj_start,
+        hipLaunchKernelGGL((k_pair_cl<T, true, true, kLJ, 1, CA>), grid, pblock, 0, s, sub, w.lj_x, w.lj_start,
                            w.lj_cluster, w.lj_out, k, aux);
     else
-        hipLaunchKernelGGL((k_pair_cl<T, true, false, kLJ, 1, 8>), grid, pblock, 0, s, sub, w.lj_x, w.lj_start,
+        hipLaunchKernelGGL((k_pair_cl<T, true, false, kLJ, 1, CA>), grid, pblock, 0, s, sub, w.lj_x, w.lj_start,
                            w.lj_cluster, w.lj_out, k, aux);
     return hipGetLastError();
 }
@@ -1392,7 +1356,7 @@ hipError_t Launch<T>::lj(hipStream_t s, const DevPlan &p, const DevPlan &sub, co
     template hipError_t Launch<T>::exclusions(hipStream_t, const DevPlan &, const Work<T> &, const vec4_t<T> *,      \
                                               const MethodConst &, bool);                                            \
     template hipError_t Launch<T>::lj(hipStream_t, const DevPlan &, const DevPlan &, const Work<T> &,                \
-                                      const MethodConst &, bool);
+                                      const vec4_t<T> *, const MethodConst &, bool);
 MSMX_PAIR_INST(float)
 MSMX_PAIR_INST(double)
 #undef MSMX_PAIR_INST
