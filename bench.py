@@ -63,7 +63,7 @@ def parse():
     ap.add_argument("--no-graphs", action="store_true", help="time eager launches only")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default launch configuration")
     ap.add_argument("--tuning", default=None,
-                    help="pair_waves,stencil_threads,concurrent for the headline workload instead of autotuning "
+                    help="pair_waves,stencil_threads,concurrent[,pair_cell] for the headline workload instead of autotuning "
                          "(for profiler runs)")
     ap.add_argument("--no-orders", action="store_true", help="skip the smoothing-order / basis-degree study")
     ap.add_argument("--no-mts", action="store_true", help="skip the multiple-time-step dynamics")
@@ -651,8 +651,9 @@ def single_fp32(torch, msmx, w32, args, reps):
            torch.empty(n, dtype=torch.float32, device=dev))
     eager_default_ms = timed_steps(torch, ctx, x32, out, args.steps, args.warmup)
     if args.tuning and big_workload(w32):
-        pw, st, cc = (int(v) for v in args.tuning.split(","))
-        ctx.set_tuning(pair_waves=pw, stencil_threads=st, concurrent=cc)
+        vals = [int(v) for v in args.tuning.split(",")]
+        pw, st, cc = vals[:3]
+        ctx.set_tuning(pair_waves=pw, stencil_threads=st, concurrent=cc, pair_cell=vals[3] if len(vals) > 3 else 1)
         tuning = ctx.tuning()
     else:
         tuning = ctx.autotune(x32, reps=reps) if not args.no_autotune else ctx.tuning()

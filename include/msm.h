@@ -172,7 +172,7 @@ int msm_energy_forces_noalloc(const msm_params *params, void *stream, int64_t na
  * different values agree to rounding, not bitwise (contexts that must agree
  * bitwise, e.g. a parareal pair and its serial reference, should share one
  * configuration); concurrent changes no result bit. Defaults: the cluster form (2), 1024
- * threads, concurrent. */
+ * threads, concurrent, the grid cells (pair_cell 1). */
 typedef struct {
     int pair_waves;        /* short-range sum: 4, 8 or 16 waves share one 64-atom group, one
                               lane per atom; 1: each wave owns 16 atoms, four lanes per atom;
@@ -196,6 +196,13 @@ typedef struct {
                               workgroups; better for large systems);
                               0: every stage on the context stream in turn. Stage timing
                               always runs the stages in turn. */
+    int pair_cell;         /* cells of the short-range pair search: 1, the cells of edge h
+                              that anterpolation walks; 2 or 3, cells of edge h/2 or h/3,
+                              into which the atoms are binned a second time (for a coarse
+                              h, whose cells hold many atoms outside the cutoff of a
+                              cluster). Setting 2 or 3 allocates those cells' arrays
+                              (MSM_ERR_CAPACITY beyond 2^31 cells; MSM_ERR_UNSUPPORTED for
+                              msm_energy_forces_noalloc) */
 } msm_tuning;
 
 int msm_get_tuning(const msm_ctx *ctx, msm_tuning *out);
@@ -204,8 +211,9 @@ int msm_set_tuning(msm_ctx *ctx, const msm_tuning *tuning);
 /* Autotuner: time whole evaluations (launched eagerly; with concurrent stages
  * on, for both fork points 1 and 2) for every pair_waves and stencil_threads candidate,
  * reps evaluations each, on the caller's own batch (arguments as for
- * msm_energy_forces; no outputs are written), keep the fastest pair and
- * report it in *chosen (may be NULL). Synchronous. */
+ * msm_energy_forces; no outputs are written), then the chosen ones with
+ * pair_cell 2 and 3; keep the fastest and report it in *chosen (may be
+ * NULL). Synchronous; may allocate the pair cells' arrays. */
 int msm_autotune(msm_ctx *ctx, int nsys, const int64_t *offsets_host, const double *domains_host,
                  const void *xyzq_dev, int reps, msm_tuning *chosen);
 

@@ -58,7 +58,13 @@ class _PararealReport(C.Structure):
 
 
 class _Tuning(C.Structure):
-    _fields_ = [("pair_waves", C.c_int), ("stencil_threads", C.c_int), ("concurrent", C.c_int)]
+    _fields_ = [("pair_waves", C.c_int), ("stencil_threads", C.c_int), ("concurrent", C.c_int),
+                ("pair_cell", C.c_int)]
+
+
+def _tuning_dict(t):
+    return {"pair_waves": t.pair_waves, "stencil_threads": t.stencil_threads, "concurrent": t.concurrent,
+            "pair_cell": t.pair_cell}
 
 
 METHODS = {"msm": 0, "cutoff": 1, "wolf": 2}
@@ -254,14 +260,15 @@ class MsmContext:
     def tuning(self):
         t = _Tuning()
         _check(lib().msm_get_tuning(self._h, C.byref(t)), "msm_get_tuning")
-        return {"pair_waves": t.pair_waves, "stencil_threads": t.stencil_threads, "concurrent": t.concurrent}
+        return _tuning_dict(t)
 
-    def set_tuning(self, pair_waves=None, stencil_threads=None, concurrent=None):
+    def set_tuning(self, pair_waves=None, stencil_threads=None, concurrent=None, pair_cell=None):
         """Set the launch configuration (msm_set_tuning); None keeps a field."""
         cur = self.tuning()
         t = _Tuning(int(cur["pair_waves"] if pair_waves is None else pair_waves),
                     int(cur["stencil_threads"] if stencil_threads is None else stencil_threads),
-                    int(cur["concurrent"] if concurrent is None else concurrent))
+                    int(cur["concurrent"] if concurrent is None else concurrent),
+                    int(cur["pair_cell"] if pair_cell is None else pair_cell))
         _check(lib().msm_set_tuning(self._h, C.byref(t)), "msm_set_tuning")
 
     def autotune(self, xyzq, offsets=None, domains=None, reps=5):
@@ -274,7 +281,7 @@ class MsmContext:
         t = _Tuning()
         _check(lib().msm_autotune(self._h, nsys, offs.ctypes.data_as(C.POINTER(C.c_int64)), dom_p,
                                   C.c_void_p(xyzq.data_ptr()), int(reps), C.byref(t)), "msm_autotune")
-        return {"pair_waves": t.pair_waves, "stencil_threads": t.stencil_threads, "concurrent": t.concurrent}
+        return _tuning_dict(t)
 
     def set_graphs(self, enable=True):
         """Replay captured HIP graphs for repeated evaluations (msm_set_graphs)."""

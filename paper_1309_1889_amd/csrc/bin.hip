@@ -73,19 +73,20 @@ __global__ void k_bin_count(DevPlan p, const vec4_t<T> *__restrict__ xyzq, int *
     slot_of[i] = atomicAdd(&counts[cell], 1);
 }
 
-// The atoms that carry Lennard-Jones (a bound model's atoms with a nonzero
-// sqrt(eps)) in cells of their own (edge and cell layout from the subset
-// plan pl, one system plan per system of the batch plan p): the histogram of
-// k_bin_count for those atoms only (the others get cell -1). Positions were
-// checked by the batch's own binning; here they are only clamped.
+// A second binning of the batch's atoms into cells of another edge (cell
+// layout from the subset plan pl, one system plan per system of the batch
+// plan p): all atoms (maux null: the pair search in cells finer than h), or
+// the atoms that carry Lennard-Jones (a nonzero sqrt(eps) in their model
+// record; the others get cell -1). The histogram of k_bin_count; positions
+// were checked by the batch's own binning, here they are only clamped.
 template <typename T>
-__global__ void k_lj_bin_count(DevPlan p, const SysPlan *__restrict__ lsys, const vec4_t<T> *__restrict__ xyzq,
-                               const vec4_t<T> *__restrict__ maux, int64_t period, int *__restrict__ cell_of,
-                               int *__restrict__ slot_of, int *__restrict__ counts)
+__global__ void k_sub_bin_count(DevPlan p, const SysPlan *__restrict__ lsys, const vec4_t<T> *__restrict__ xyzq,
+                                const vec4_t<T> *__restrict__ maux, int64_t period, int *__restrict__ cell_of,
+                                int *__restrict__ slot_of, int *__restrict__ counts)
 {
     const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (i >= p.natoms) return;
-    if (maux[i % period].z == T(0)) {
+    if (maux && maux[i % period].z == T(0)) {
         cell_of[i] = -1;
         return;
     }
@@ -104,7 +105,7 @@ __global__ void k_lj_bin_count(DevPlan p, const SysPlan *__restrict__ lsys, cons
     slot_of[i] = atomicAdd(&counts[cell], 1);
 }
 
-__global__ void k_lj_scatter(int64_t n, const int *__restrict__ cell_of, const int *__restrict__ slot_of,
+__global__ void k_sub_scatter(int64_t n, const int *__restrict__ cell_of, const int *__restrict__ slot_of,
                              const int *__restrict__ start, int *__restrict__ order, int *__restrict__ pos_of)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
@@ -395,31 +396,30 @@ hipError_t Launch<T>::bin(hipStream_t s, const DevPlan &p, const Work<T> &w, con
 }
 
 template <typename T>
-hipError_t bin_lj(hipStream_t s, const DevPlan &p, const DevPlan &pl, const Work<T> &w, const vec4_t<T> *xyzq)
+hipError_t bin_sub(hipStream_t s, const DevPlan &p, const DevPlan &pl, const SubBins<T> &b, const vec4_t<T> *xyzq,
+                   const vec4_t<T> *maux, int64_t period)
 {
     if (p.natoms == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_lj_bin_count<T>, dim3(nblocks(p.natoms, 256)), dim3(256), 0, s, p, pl.sys, xyzq,
-                       (const vec4_t<T> *)w.maux, w.period, w.lj_cell_of, w.lj_slot_of, w.lj_cnt);
-    scan_cells(s, w.lj_cnt, w.lj_start, pl.ncells + 1, w.lj_blocks);
-    hipLaunchKernelGGL(k_lj_scatter, dim3(nblocks(p.natoms, 256)), dim3(256), 0, s, p.natoms, w.lj_cell_of,
-                       w.lj_slot_of, w.lj_start, w.lj_order, w.lj_of);
-    // per-cell order by input index, the atoms and their records gathered,
-    // and each atom's place recorded (a period beyond any index: the records
-    // are the model's, indexed by input atom modulo the period)
+    hipLaunchKernelGGL(k_sub_bin_count<T>, dim3(nblocks(p.natoms, 256)), dim3(256), 0, s, p, pl.sys, xyzq, maux,
+                       period, b.cell_of, b.slot_of, b.cnt);
+    scan_cells(s, b.cnt, b.start, pl.ncells + 1, b.blocks);
+    hipLaunchKernelGGL(k_sub_scatter, dim3(nblocks(p.natoms, 256)), dim3(256), 0, s, p.natoms, b.cell_of, b.slot_of,
+                       b.start, b.order, b.pos_of);
+    // per-cell order by input index, the atoms (and their model records, for
+    // the Lennard-Jones subset) gathered, and each atom's place recorded
+    const vec4_t<T> *ma = b.aux ? maux : nullptr;
     if (pl.natoms > 2 * pl.ncells)
-        hipLaunchKernelGGL(k_cell_sort<T>, dim3(nblocks(pl.ncells, 4)), dim3(256), 0, s, pl.ncells, w.lj_start,
-                           w.lj_order, xyzq, w.lj_x, (const vec4_t<T> *)w.maux, w.lj_aux, w.period,
-                           (const int *)p.evflag, w.lj_of);
+        hipLaunchKernelGGL(k_cell_sort<T>, dim3(nblocks(pl.ncells, 4)), dim3(256), 0, s, pl.ncells, b.start, b.order,
+                           xyzq, b.x, ma, b.aux, period, (const int *)p.evflag, b.pos_of);
     else
-        hipLaunchKernelGGL(k_cell_sort_thread<T>, dim3(nblocks(pl.ncells, 256)), dim3(256), 0, s, pl.ncells,
-                           w.lj_start, w.lj_order, xyzq, w.lj_x, (const vec4_t<T> *)w.maux, w.lj_aux, w.period,
-                           (const int *)p.evflag, w.lj_of);
+        hipLaunchKernelGGL(k_cell_sort_thread<T>, dim3(nblocks(pl.ncells, 256)), dim3(256), 0, s, pl.ncells, b.start,
+                           b.order, xyzq, b.x, ma, b.aux, period, (const int *)p.evflag, b.pos_of);
     return hipGetLastError();
 }
-template hipError_t bin_lj<float>(hipStream_t, const DevPlan &, const DevPlan &, const Work<float> &,
-                                  const vec4_t<float> *);
-template hipError_t bin_lj<double>(hipStream_t, const DevPlan &, const DevPlan &, const Work<double> &,
-                                   const vec4_t<double> *);
+template hipError_t bin_sub<float>(hipStream_t, const DevPlan &, const DevPlan &, const SubBins<float> &,
+                                   const vec4_t<float> *, const vec4_t<float> *, int64_t);
+template hipError_t bin_sub<double>(hipStream_t, const DevPlan &, const DevPlan &, const SubBins<double> &,
+                                    const vec4_t<double> *, const vec4_t<double> *, int64_t);
 
 template hipError_t Launch<float>::bin(hipStream_t, const DevPlan &, const Work<float> &, const vec4_t<float> *);
 template hipError_t Launch<double>::bin(hipStream_t, const DevPlan &, const Work<double> &, const vec4_t<double> *);

@@ -320,6 +320,26 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     std::vector<SysPlan> &lj_sys = ps.lj_sys;
     std::vector<int64_t> &lj_group_p = ps.lj_group_p;
     int64_t lj_atoms = 0, lj_groups = 0;
+    // the pair search's own cells: edge h / pair_cell, the same atoms and groups
+    const int pcm = c->mc.pair_cell;
+    std::vector<SysPlan> &pc_sys = ps.pc_sys;
+    int64_t pc_cells = 0;
+    if (pcm > 1) {
+        pc_sys = sys;
+        for (int s = 0; s < nsys; s++) {
+            SysPlan &P = pc_sys[s];
+            P.inv_h = pcm / c->prm.h;
+            for (int d = 0; d < 3; d++) {
+                P.tmax[d] = sys[s].tmax[d] * pcm;
+                P.nc[d] = (int)std::floor(P.tmax[d]) + 1;
+                P.nb[d] = (P.nc[d] + kBrick - 1) / kBrick;
+            }
+            P.cell0 = pc_cells;
+            P.ncells = (int64_t)P.nb[0] * P.nb[1] * P.nb[2] * kBrickCells;
+            pc_cells += P.ncells;
+        }
+        if (pc_cells > c->pc_cap) return MSM_ERR_CAPACITY;
+    }
     int64_t lj_cells = 0;
     if (lj) {
         const int64_t period = (int64_t)c->lj_prefix.size() - 1, per = c->lj_prefix[period];
@@ -371,6 +391,7 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     const size_t o_rxy = place(sizeof(int64_t) * W), o_pxy = place(sizeof(int64_t) * W);
     const size_t o_phi = place(sizeof(double) * std::max<size_t>(phi_tab.size(), 1));
     const size_t o_ljsys = lj ? place(sizeof(SysPlan) * nsys) : 0, o_ljgroup = lj ? place(sizeof(int64_t) * W) : 0;
+    const size_t o_pcsys = pcm > 1 ? place(sizeof(SysPlan) * nsys) : 0;
     char *h = nullptr;
     int slot = -1;
     if (c->fixed_plan) {
@@ -414,6 +435,7 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     std::memcpy(h + o_rxy, rxy_p.data(), sizeof(int64_t) * W);
     std::memcpy(h + o_pxy, pxy_p.data(), sizeof(int64_t) * W);
     if (!phi_tab.empty()) std::memcpy(h + o_phi, phi_tab.data(), sizeof(double) * phi_tab.size());
+    if (pcm > 1) std::memcpy(h + o_pcsys, pc_sys.data(), sizeof(SysPlan) * nsys);
     if (lj) {
         std::memcpy(h + o_ljsys, lj_sys.data(), sizeof(SysPlan) * nsys);
         std::memcpy(h + o_ljgroup, lj_group_p.data(), sizeof(int64_t) * W);
@@ -460,7 +482,13 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     dp.nrz = 0;
     for (int k = 1; k < kMaxLevels; k++) dp.nrz += nodes[k];
     dp.evflag = (c->prm.precision == MSM_FP32 ? c->wf.status : c->wd.status) + 1;
-    // the subset plan: the same cells and tables, its own atoms and groups
+    // the pair search's own cells
+    c->dpp = dp;
+    if (pcm > 1) {
+        c->dpp.sys = (const SysPlan *)(d + o_pcsys);
+        c->dpp.ncells = pc_cells;
+    }
+    // the subset plan: its own cells, atoms and groups
     c->dps = dp;
     if (lj) {
         c->dps.sys = (const SysPlan *)(d + o_ljsys);
@@ -528,7 +556,8 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
             return MSM_ERR_HIP;
         ps = c->side_stream;
     }
-    if (do_short && (e = L::pair(ps, p, w, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
+    const DevPlan *pp = c->mc.pair_cell > 1 ? &c->dpp : nullptr;
+    if (do_short && (e = L::pair(ps, p, pp, w, (const vec4_t<T> *)xyzq, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
     if (do_short && c->md_bound) {
         if ((e = L::exclusions(ps, p, w, (const vec4_t<T> *)xyzq, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
         if ((e = L::lj(ps, p, c->dps, w, (const vec4_t<T> *)xyzq, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
@@ -752,6 +781,7 @@ int msmx::init_context(msm_ctx *c, const msm_params *prm)
     c->mc.reach = cutoff ? 0 : reach;
     c->mc.pair_waves = 2;
     c->mc.stencil_threads = 1024;
+    c->mc.pair_cell = 1;
     c->d2max = (int)std::ceil(ratio * ratio) - 1;      // largest integer below (2a/h)^2
     int rc = geometry(*prm, prm->lo, prm->hi, c->ctx_geom);
     if (rc) return rc;
@@ -886,6 +916,7 @@ void msm_destroy(msm_ctx *c)
     if (c->plan_dev) (void)hipFree(c->plan_dev);
     if (c->plan_host) (void)hipHostFree(c->plan_host);
     if (c->mdbuf) (void)hipFree(c->mdbuf);
+    if (c->pcbuf) (void)hipFree(c->pcbuf);
     delete c;
 }
 
@@ -914,6 +945,60 @@ int msm_get_tuning(const msm_ctx *c, msm_tuning *t)
     t->pair_waves = c->mc.pair_waves;
     t->stencil_threads = c->mc.stencil_threads;
     t->concurrent = c->concurrent;
+    t->pair_cell = c->mc.pair_cell;
+    return MSM_OK;
+}
+
+// Arrays of the pair search's own cells for edge h / m (grown, never shrunk).
+static int ensure_pair_cells(msm_ctx *c, int m)
+{
+    if (m <= 1) return MSM_OK;
+    Geometry g{};
+    msm_params fine = c->prm;
+    fine.h = c->prm.h / m;
+    fine.method = MSM_METHOD_CUTOFF;   // cells only
+    int rc = geometry(fine, c->prm.lo, c->prm.hi, g);
+    if (rc) return rc;
+    int64_t nb = 1;
+    for (int d = 0; d < 3; d++) nb *= (g.nc[d] + kBrick - 1) / kBrick;
+    const int64_t cells = nb * kBrickCells * c->prm.max_systems;
+    if (cells >= ((int64_t)1 << 31)) return MSM_ERR_CAPACITY;
+    if (c->pcbuf && cells <= c->pc_cap) return MSM_OK;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
+    if (c->pcbuf) (void)hipFree(c->pcbuf);
+    c->pcbuf = nullptr;
+    c->pc_cap = 0;
+    const int64_t na = std::max<int64_t>(c->prm.max_atoms, 1);
+    const size_t vb = c->prm.precision == MSM_FP32 ? sizeof(float4) : sizeof(double4);
+    size_t off = 0;
+    auto take = [&](size_t b) {
+        size_t o = off;
+        off += (b + 255) / 256 * 256;
+        return o;
+    };
+    const size_t o_cell = take(4 * na), o_slot = take(4 * na), o_cnt = take(4 * (cells + 1)),
+                 o_start = take(4 * (cells + 1)), o_blk = take(4 * std::max<int64_t>(kScanFewBlocks, (cells + 1) / 4096 + 2)),
+                 o_ord = take(4 * na), o_pos = take(4 * na), o_x = take(vb * (na + 64)), o_out = take(vb * na);
+    if (hipMalloc((void **)&c->pcbuf, off) != hipSuccess) return MSM_ERR_HIP;
+    if (hipMemsetAsync(c->pcbuf, 0, off, c->stream) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
+        return MSM_ERR_HIP;
+    char *b = c->pcbuf;
+    auto fill = [&](auto &w) {
+        using V = std::remove_pointer_t<decltype(w.pc.x)>;
+        w.pc.cell_of = (int *)(b + o_cell);
+        w.pc.slot_of = (int *)(b + o_slot);
+        w.pc.cnt = (int *)(b + o_cnt);
+        w.pc.start = (int *)(b + o_start);
+        w.pc.blocks = (int *)(b + o_blk);
+        w.pc.order = (int *)(b + o_ord);
+        w.pc.pos_of = (int *)(b + o_pos);
+        w.pc.x = (V *)(b + o_x);
+        w.pc.aux = nullptr;
+        w.pc_out = (V *)(b + o_out);
+    };
+    if (c->prm.precision == MSM_FP32) fill(c->wf);
+    else fill(c->wd);
+    c->pc_cap = cells;
     return MSM_OK;
 }
 
@@ -925,11 +1010,17 @@ int msm_set_tuning(msm_ctx *c, const msm_tuning *t)
         return MSM_ERR_ARG;
     if (t->stencil_threads != 256 && t->stencil_threads != 1024) return MSM_ERR_ARG;
     if (t->concurrent < 0 || t->concurrent > 2) return MSM_ERR_ARG;
+    if (t->pair_cell < 1 || t->pair_cell > 3) return MSM_ERR_ARG;
+    if (c->fixed_plan && t->pair_cell != 1) return MSM_ERR_UNSUPPORTED;
     if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
+    int rc = ensure_pair_cells(c, t->pair_cell);
+    if (rc) return rc;
     for (auto &g : c->graphs) drop_graph(g);     // captured launches use the old kernels
+    if (t->pair_cell != c->mc.pair_cell) c->plan_valid = false;   // the plan holds the cells
     c->mc.pair_waves = t->pair_waves;
     c->mc.stencil_threads = t->stencil_threads;
     c->concurrent = t->concurrent;
+    c->mc.pair_cell = t->pair_cell;
     return MSM_OK;
 }
 
@@ -938,9 +1029,15 @@ int msm_autotune(msm_ctx *c, int nsys, const int64_t *offsets, const double *dom
 {
     if (!c || nsys < 1 || !offsets || reps < 1) return MSM_ERR_ARG;
     if (nsys > c->prm.max_systems) return MSM_ERR_CAPACITY;
+    const msm_tuning start{c->mc.pair_waves, c->mc.stencil_threads, c->concurrent, c->mc.pair_cell};
+    // first the kernels with the grid cells, then the pair search's own cells
+    if (c->mc.pair_cell != 1) c->plan_valid = false;
+    c->mc.pair_cell = 1;
     int rc = build_plan(c, nsys, offsets, domains);
-    if (rc) return rc;
-    const msm_tuning start{c->mc.pair_waves, c->mc.stencil_threads, c->concurrent};
+    if (rc) {
+        c->mc.pair_cell = start.pair_cell;
+        return rc;
+    }
     // whole evaluations, launched eagerly with the context's stream use: with
     // concurrent stages the pair kernel that fits best beside the grid stages
     // is not the fastest one alone
@@ -982,8 +1079,28 @@ int msm_autotune(msm_ctx *c, int nsys, const int64_t *offsets, const double *dom
                     best.pair_waves = pw;
                     best.stencil_threads = st;
                     best.concurrent = c->concurrent;
+                    best.pair_cell = 1;
                 }
             }
+    // cells of edge h/2 and h/3 for the pair search, with the chosen kernels
+    // (skipped where their arrays would not fit)
+    for (int m = 2; m <= 3 && !rc && !c->fixed_plan; m++) {
+        if (ensure_pair_cells(c, m) != MSM_OK) break;
+        c->mc.pair_waves = best.pair_waves;
+        c->mc.stencil_threads = best.stencil_threads;
+        c->concurrent = best.concurrent;
+        c->mc.pair_cell = m;
+        c->plan_valid = false;
+        if ((rc = build_plan(c, nsys, offsets, domains))) break;
+        double ms = 0;
+        if ((rc = eval_time(&ms))) break;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best.pair_cell = m;
+        }
+    }
+    if (c->mc.pair_cell != start.pair_cell) c->plan_valid = false;
+    c->mc.pair_cell = start.pair_cell;
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
     c->timing = was_timing;

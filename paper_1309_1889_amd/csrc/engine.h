@@ -26,6 +26,7 @@ struct PlanScratch {
     std::vector<int64_t> atom_p, group_p, cell_p, iblk_p, top_p, ant_p, node_p, rxy_p, pxy_p, tile_p;
     std::vector<SysPlan> lj_sys;      // the Lennard-Jones subset's system plans
     std::vector<int64_t> lj_group_p;  // and its 64-atom groups
+    std::vector<SysPlan> pc_sys;      // the system plans of the pair search's own cells
     std::vector<double> phi_tab, p1, cur, nxt;
     std::vector<char> blob;            // image of the tables for a fixed device region
     std::vector<int2> cols;            // stencil columns and weights before upload
@@ -109,6 +110,11 @@ struct msm_ctx {
     bool rigid = false;
     msmx::TriModel tri{};
     char *mdbuf = nullptr;       // model, forces and parareal scratch
+    // the pair search's own cells (tuning pair_cell > 1): their arrays, sized
+    // for pc_cap cells and max_atoms atoms, and the plan of those cells
+    char *pcbuf = nullptr;
+    int64_t pc_cap = 0;
+    msmx::DevPlan dpp{};
     void *md_forces = nullptr;                  // max_atoms x 3, precision T
     void *md_forces_slow = nullptr;             // multiple time steps: the grid part, max_atoms x 3
     double *md_parts = nullptr;  // per-block partial sums (kinetic energy)

@@ -45,6 +45,20 @@ struct DevPlan {
 // diverging trajectory fails at the cost of an ordinary step.
 __device__ inline bool eval_failed(const DevPlan &p) { return p.evflag && *p.evflag; }
 
+// A second binning of the atoms of the batch plan p into the cells of plan pl:
+// every atom (maux null) or those whose model record carries Lennard-Jones.
+template <typename T> struct SubBins {
+    int *cell_of;     // per input atom: its cell, or -1
+    int *slot_of;     // per input atom: arrival slot within that cell
+    int *cnt;         // cells + 1: histogram, zero between evaluations
+    int *start;       // cells + 1: cell starts
+    int *blocks;      // block sums of that scan
+    int *order;       // sorted position -> input atom
+    int *pos_of;      // input atom -> sorted position, or -1
+    vec4_t<T> *x;     // sorted positions and charges
+    vec4_t<T> *aux;   // sorted model records (null: not gathered)
+};
+
 // Scratch arrays owned by the context.
 template <typename T> struct Work {
     int *cell_of;        // per input atom: brick-major cell (batch-global)
@@ -70,19 +84,15 @@ template <typename T> struct Work {
     int64_t period;      // batch atom i uses model entry i % period
     int *xstart, *xidx;  // excluded partners of model atom m: xidx[xstart[m] .. xstart[m+1]) (model
                          // indices, ascending); null without molecule ids
-    // the atoms that carry Lennard-Jones (null when none does), binned into
-    // cells of their own (the subset plan's)
-    int *lj_cell_of;     // per input atom: its subset cell, or -1
-    int *lj_slot_of;     // per input atom: arrival slot within that cell
-    int *lj_cnt;         // subset cells + 1: histogram, zero between evaluations
-    int *lj_start;       // subset cells + 1: cell starts
-    int *lj_blocks;      // block sums of that scan
-    int *lj_order;       // subset sorted position -> input atom
-    int *lj_of;          // input atom -> subset sorted position, or -1
+    // the atoms that carry Lennard-Jones, binned into cells of their own (the
+    // subset plan's); lj.x null when no atom carries it
+    SubBins<T> lj;
     int *lj_cluster;     // the subset's k-d clusters
-    vec4_t<T> *lj_x;     // subset positions and charges, sorted
-    vec4_t<T> *lj_aux;   // subset aux records, sorted
     vec4_t<T> *lj_out;   // subset: Lennard-Jones force and energy (counted from both sides)
+    // pair search in cells finer than h (null unless tuned so): every atom binned
+    // a second time, the pair sums in that order, then permuted into shrt
+    SubBins<T> pc;
+    vec4_t<T> *pc_out;
 };
 
 // Quarter-disc stencil columns (ox >= 0, oy >= 0 inside the sphere) and their
@@ -118,6 +128,7 @@ struct MethodConst {
                                // 7, 9: as 2, the clusters of a group (7) or half group (9)
                                // sharing one stream built and loaded by the workgroup
     int stencil_threads;       // threads per stencil tile: 256 or 1024
+    int pair_cell;             // the pair search's cells: edge h / pair_cell (1: the grid cells)
 };
 
 // Pieces of the single-precision Wolf pair table (see MethodConst::wolf_tab).
@@ -144,8 +155,10 @@ int scan_cells(hipStream_t s, int *counts, int *start, int64_t n, int *block_sum
 
 template <typename T> struct Launch {
     static hipError_t bin(hipStream_t s, const DevPlan &p, const Work<T> &w, const vec4_t<T> *xyzq);
-    // pot = false: forces only, the short-range potentials are left at zero
-    static hipError_t pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m, bool pot);
+    // pot = false: forces only, the short-range potentials are left at zero;
+    // pp: the plan of the pair search's own cells (null: the batch cells)
+    static hipError_t pair(hipStream_t s, const DevPlan &p, const DevPlan *pp, const Work<T> &w,
+                           const vec4_t<T> *xyzq, const MethodConst &m, bool pot);
     // after pair, with a molecular model bound: take the excluded pairs of each
     // molecule out of the short-range sums (xyzq: the evaluation's input), and
     // the Lennard-Jones forces and energies of the atoms that carry them,
@@ -179,10 +192,9 @@ hipError_t fill_i32(hipStream_t s, int *p, int64_t n, int v);
 #define MSMX_LJ_CELL_ATOMS 2.0
 #endif
 constexpr double kLjCellAtoms = MSMX_LJ_CELL_ATOMS;
-// Bin the atoms of the batch plan p that carry Lennard-Jones into the cells of
-// the subset plan pl (the Work's lj_* arrays).
 template <typename T>
-hipError_t bin_lj(hipStream_t s, const DevPlan &p, const DevPlan &pl, const Work<T> &w, const vec4_t<T> *xyzq);
+hipError_t bin_sub(hipStream_t s, const DevPlan &p, const DevPlan &pl, const SubBins<T> &b, const vec4_t<T> *xyzq,
+                   const vec4_t<T> *maux, int64_t period);
 // Copy bytes of host memory to device memory through kernel arguments
 // (2 KiB per launch), so that the copy allocates nothing and the source may
 // be reused as soon as the call returns. dst and bytes: multiples of 4.

@@ -123,16 +123,19 @@ template <typename T> int bind(msm_ctx *c, const msm_md_model *m)
     w.period = period;
     w.xstart = excl ? (int *)(b + o_xs) : nullptr;
     w.xidx = excl ? (int *)(b + o_xi) : nullptr;
-    w.lj_cnt = ljs ? (int *)(b + o_lcnt) : nullptr;
-    w.lj_start = ljs ? (int *)(b + o_lstart) : nullptr;
-    w.lj_blocks = ljs ? (int *)(b + o_lblk) : nullptr;
-    w.lj_of = ljs ? (int *)(b + o_lof) : nullptr;
-    w.lj_order = ljs ? (int *)(b + o_lord) : nullptr;
-    w.lj_cell_of = ljs ? (int *)(b + o_lcell) : nullptr;
-    w.lj_slot_of = ljs ? (int *)(b + o_lslot) : nullptr;
+    w.lj = SubBins<T>{};
+    if (ljs) {
+        w.lj.cell_of = (int *)(b + o_lcell);
+        w.lj.slot_of = (int *)(b + o_lslot);
+        w.lj.cnt = (int *)(b + o_lcnt);
+        w.lj.start = (int *)(b + o_lstart);
+        w.lj.blocks = (int *)(b + o_lblk);
+        w.lj.order = (int *)(b + o_lord);
+        w.lj.pos_of = (int *)(b + o_lof);
+        w.lj.x = (vec4_t<T> *)(b + o_lx);
+        w.lj.aux = (vec4_t<T> *)(b + o_laux);
+    }
     w.lj_cluster = ljs ? (int *)(b + o_lcl) : nullptr;
-    w.lj_x = ljs ? (vec4_t<T> *)(b + o_lx) : nullptr;
-    w.lj_aux = ljs ? (vec4_t<T> *)(b + o_laux) : nullptr;
     w.lj_out = ljs ? (vec4_t<T> *)(b + o_lout) : nullptr;
     c->md_forces = b + o_f;
     c->md_forces_slow = b + o_fs;

@@ -1134,7 +1134,7 @@ hipError_t Launch<T>::interp(hipStream_t s, const DevPlan &p, const Work<T> &w, 
                              T *potentials, int part)
 {
     if (p.niblk == 0) return hipSuccess;
-    const int *ljof = w.lj_x ? w.lj_of : nullptr;
+    const int *ljof = w.lj.x ? w.lj.pos_of : nullptr;
     const vec4_t<T> *ljout = w.lj_out;
     const dim3 grid((unsigned)p.niblk), block(kInterpThreads);
     if (m.cutoff) {

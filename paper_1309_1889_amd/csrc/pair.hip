@@ -1279,26 +1279,53 @@ static int pair_kind(const MethodConst &m)
     return m.method == MSM_METHOD_WOLF ? kWolf : (m.method == MSM_METHOD_MSM && m.g.m == 3 ? kPolyHigh : kPoly);
 }
 
+// The pair sums from the pair search's own cells, in the batch's sorted order.
 template <typename T>
-hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const Work<T> &w, const MethodConst &m, bool pot)
+__global__ __launch_bounds__(256) void k_pair_permute(int64_t n, const int *__restrict__ order,
+                                                      const int *__restrict__ pos_of, const vec4_t<T> *__restrict__ in,
+                                                      vec4_t<T> *__restrict__ out)
+{
+    const int64_t pos = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (pos < n) out[pos] = in[pos_of[order[pos]]];
+}
+
+template <typename T>
+hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const DevPlan *pp, const Work<T> &w0,
+                           const vec4_t<T> *xyzq, const MethodConst &m, bool pot)
 {
     if (p.ngroups == 0) return hipSuccess;
     const PairK<T> k = pair_constants<T>(m);
     if (m.method == MSM_METHOD_WOLF && sizeof(T) == 4 && !k.wtab) return hipErrorInvalidValue;
     const int kind = pair_kind(m);
+    // with cells of its own, the search runs over a second binning of the
+    // atoms (same systems and 64-atom groups, other cells) and its sums are
+    // permuted back into the batch order afterwards
+    Work<T> w = w0;
+    if (pp) {
+        if (!w0.pc.x) return hipErrorInvalidValue;
+        hipError_t e = bin_sub<T>(s, p, *pp, w0.pc, xyzq, nullptr, 1);
+        if (e != hipSuccess) return e;
+        w.sxyzq = w0.pc.x;
+        w.cell_start = w0.pc.start;
+        w.shrt = w0.pc_out;
+    }
+    const DevPlan &q = pp ? *pp : p;
     switch (m.pair_waves) {
-    case 1: pair_launch_m<T, 1>(s, p, w, k, pot, kind); break;
-    case 2: pair_launch_m<T, 2>(s, p, w, k, pot, kind); break;
-    case 3: pair_launch_m<T, 3>(s, p, w, k, pot, kind); break;
-    case 4: pair_launch_m<T, 4>(s, p, w, k, pot, kind); break;
-    case 5: pair_launch_m<T, 5>(s, p, w, k, pot, kind); break;
-    case 6: pair_launch_m<T, 6>(s, p, w, k, pot, kind); break;
-    case 7: pair_launch_m<T, 7>(s, p, w, k, pot, kind); break;
-    case 9: pair_launch_m<T, 9>(s, p, w, k, pot, kind); break;
-    case 8: pair_launch_m<T, 8>(s, p, w, k, pot, kind); break;
-    case 16: pair_launch_m<T, 16>(s, p, w, k, pot, kind); break;
+    case 1: pair_launch_m<T, 1>(s, q, w, k, pot, kind); break;
+    case 2: pair_launch_m<T, 2>(s, q, w, k, pot, kind); break;
+    case 3: pair_launch_m<T, 3>(s, q, w, k, pot, kind); break;
+    case 4: pair_launch_m<T, 4>(s, q, w, k, pot, kind); break;
+    case 5: pair_launch_m<T, 5>(s, q, w, k, pot, kind); break;
+    case 6: pair_launch_m<T, 6>(s, q, w, k, pot, kind); break;
+    case 7: pair_launch_m<T, 7>(s, q, w, k, pot, kind); break;
+    case 9: pair_launch_m<T, 9>(s, q, w, k, pot, kind); break;
+    case 8: pair_launch_m<T, 8>(s, q, w, k, pot, kind); break;
+    case 16: pair_launch_m<T, 16>(s, q, w, k, pot, kind); break;
     default: return hipErrorInvalidValue;
     }
+    if (pp)
+        hipLaunchKernelGGL(k_pair_permute<T>, dim3((unsigned)((p.natoms + 255) / 256)), dim3(256), 0, s, p.natoms,
+                           w0.order, w0.pc.pos_of, w0.pc_out, w0.shrt);
     return hipGetLastError();
 }
 
@@ -1333,26 +1360,27 @@ template <typename T>
 hipError_t Launch<T>::lj(hipStream_t s, const DevPlan &p, const DevPlan &sub, const Work<T> &w, const vec4_t<T> *xyzq,
                          const MethodConst &m, bool pot)
 {
-    if (!w.lj_x || p.natoms == 0) return hipSuccess;
-    hipError_t e = bin_lj<T>(s, p, sub, w, xyzq);
+    if (!w.lj.x || p.natoms == 0) return hipSuccess;
+    hipError_t e = bin_sub<T>(s, p, sub, w.lj, xyzq, (const vec4_t<T> *)w.maux, w.period);
     if (e != hipSuccess || sub.ngroups == 0) return e;
     const PairK<T> k = pair_constants<T>(m);
     constexpr int CA = kLjCluster;
-    hipLaunchKernelGGL((k_clusters<T, CA>), dim3((unsigned)sub.ngroups), dim3(kWave), 0, s, sub, w.lj_x, w.lj_cluster);
+    hipLaunchKernelGGL((k_clusters<T, CA>), dim3((unsigned)sub.ngroups), dim3(kWave), 0, s, sub, w.lj.x, w.lj_cluster);
     const int64_t nclusters = sub.ngroups * (kWave / CA);
     const dim3 grid((unsigned)((nclusters + kClWgWaves - 1) / kClWgWaves)), pblock(kClWgWaves * kWave);
-    const vec4_t<T> *aux = w.lj_aux;
+    const vec4_t<T> *aux = w.lj.aux;
     if (pot)
-        hipLaunchKernelGGL((k_pair_cl<T, true, true, kLJ, 1, CA>), grid, pblock, 0, s, sub, w.lj_x, w.lj_start,
+        hipLaunchKernelGGL((k_pair_cl<T, true, true, kLJ, 1, CA>), grid, pblock, 0, s, sub, w.lj.x, w.lj.start,
                            w.lj_cluster, w.lj_out, k, aux);
     else
-        hipLaunchKernelGGL((k_pair_cl<T, true, false, kLJ, 1, CA>), grid, pblock, 0, s, sub, w.lj_x, w.lj_start,
+        hipLaunchKernelGGL((k_pair_cl<T, true, false, kLJ, 1, CA>), grid, pblock, 0, s, sub, w.lj.x, w.lj.start,
                            w.lj_cluster, w.lj_out, k, aux);
     return hipGetLastError();
 }
 
 #define MSMX_PAIR_INST(T)                                                                                            \
-    template hipError_t Launch<T>::pair(hipStream_t, const DevPlan &, const Work<T> &, const MethodConst &, bool);   \
+    template hipError_t Launch<T>::pair(hipStream_t, const DevPlan &, const DevPlan *, const Work<T> &,              \
+                                        const vec4_t<T> *, const MethodConst &, bool);                               \
     template hipError_t Launch<T>::exclusions(hipStream_t, const DevPlan &, const Work<T> &, const vec4_t<T> *,      \
                                               const MethodConst &, bool);                                            \
     template hipError_t Launch<T>::lj(hipStream_t, const DevPlan &, const DevPlan &, const Work<T> &,                \

@@ -80,10 +80,11 @@ def test_autotune_and_tunings_agree():
     ref = [t.clone() for t in ctx.energy_forces(x)]
     chosen = ctx.autotune(x, reps=3)
     assert chosen["pair_waves"] in (1, 2, 3, 4, 5, 6, 7, 8, 9, 16) and chosen["stencil_threads"] in (256, 1024)
+    assert chosen["pair_cell"] in (1, 2, 3)
     assert ctx.tuning() == chosen
-    for pw in (1, 2, 3, 4, 5, 6, 8, 16):
+    for pw in (1, 2, 3, 4, 5, 6, 7, 8, 9, 16):
         for st in (256, 1024):
-            ctx.set_tuning(pw, st)
+            ctx.set_tuning(pw, st, pair_cell=1 if pw != 2 else 2)
             e, f, p = ctx.energy_forces(x)
             e2, f2, p2 = ctx.energy_forces(x)
             torch.cuda.synchronize()
@@ -92,7 +93,9 @@ def test_autotune_and_tunings_agree():
             assert rel < 1e-5, (pw, st, rel)
             assert e.item() == pytest.approx(ref[0].item(), rel=1e-6)
     with pytest.raises(msmx.MsmError):
-        ctx.set_tuning(7, 256)
+        ctx.set_tuning(10, 256)
+    with pytest.raises(msmx.MsmError):
+        ctx.set_tuning(pair_cell=0)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "fp64"])
@@ -109,9 +112,9 @@ def test_concurrent_stages_change_no_bit(precision):
     conc = msmx.MsmContext(w.a, w.h, w.lo, w.hi, precision=precision, max_atoms=w.n)
     seq.set_tuning(concurrent=0)
     assert conc.tuning()["concurrent"] == 1
-    for pw in (1, 2, 3, 4, 5, 6, 7, 8, 9):
-        seq.set_tuning(pair_waves=pw)
-        conc.set_tuning(pair_waves=pw)
+    for pw, pc in ((1, 1), (2, 1), (3, 1), (4, 1), (5, 1), (6, 1), (7, 1), (8, 1), (9, 1), (2, 2), (5, 2)):
+        seq.set_tuning(pair_waves=pw, pair_cell=pc)
+        conc.set_tuning(pair_waves=pw, pair_cell=pc)
         ref = seq.energy_forces(x)
         for graphs in (False, True):
             conc.set_graphs(graphs)
@@ -120,7 +123,7 @@ def test_concurrent_stages_change_no_bit(precision):
                 again = seq.energy_forces(x)       # eager work between replays
                 torch.cuda.synchronize()
                 for a, b, c in zip(got, ref, again):
-                    assert torch.equal(a, b) and torch.equal(b, c), (pw, graphs, rep)
+                    assert torch.equal(a, b) and torch.equal(b, c), (pw, pc, graphs, rep)
         conc.set_graphs(False)
     assert seq.status() == 0 and conc.status() == 0
 

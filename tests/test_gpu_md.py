@@ -68,13 +68,15 @@ def test_model_forces_match_oracle(precision):
     # the excluded intramolecular terms nearly cancel the full Coulomb energy,
     # so the energy is compared on the scale of the terms that cancel
     scale = abs(oracle.msm(p, w.xyz, w.q)[0])
-    for pw in (2, 3, 5, 6, 7, 9, 8):   # cluster forms of 8, 16 and 32 atoms; the broadcast form
-        ctx.set_tuning(pair_waves=pw)
+    # cluster forms of 8, 16 and 32 atoms, shared streams; the broadcast form;
+    # the pair search in cells of edge h/2
+    for pw, pc in ((2, 1), (3, 1), (5, 1), (6, 1), (7, 1), (9, 1), (8, 1), (2, 2), (5, 2)):
+        ctx.set_tuning(pair_waves=pw, pair_cell=pc)
         e, f, _ = ctx.energy_forces(torch.tensor(w.xyzq(dt), device="cuda"))
         torch.cuda.synchronize()
         assert ctx.status() == 0
-        assert rel_rms(f.double().cpu().numpy(), fo) < tol, pw
-        assert abs(e.item() - eo) < tol * scale, pw
+        assert rel_rms(f.double().cpu().numpy(), fo) < tol, (pw, pc)
+        assert abs(e.item() - eo) < tol * scale, (pw, pc)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])

@@ -327,6 +327,51 @@ def test_cluster_pair_forms_match_oracle(pw, precision):
         assert float(e[0].item()) == pytest.approx(eo, rel=tol)
 
 
+@pytest.mark.parametrize("pc", [2, 3])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_pair_cells_finer_than_h_match_oracle(pc, precision):
+    """The pair search in cells of edge h/2 and h/3 (a second binning of the
+    atoms, the sums permuted back) against the oracle, with the 8- and
+    16-atom cluster forms, on a water box and on uniform charges at the
+    coarse h = 0.5 with a = 0.8 (the coarse propagator's grid); the model
+    exclusions and Lennard-Jones applied on top; and a batch of two systems
+    equal to the systems alone, bitwise."""
+    m = _lib()
+    dt = np.float32 if precision == "fp32" else np.float64
+    tol = 1e-11 if precision == "fp64" else 1e-4
+    for w in (water_box(1001 // 3, (7, 7, 7), (3.3, 3.3, 3.3), seed=31),
+              uniform_pm(777, 3.4, seed=32, a=0.8, h=0.5)):
+        if precision == "fp32":
+            w = w.as_dtype(np.float32)
+        ctx = m.MsmContext(w.a, w.h, w.lo, w.hi, levels=w.levels, precision=precision, max_atoms=w.n)
+        eo, fo, po = run_oracle(w)
+        for pw in (2, 5):
+            ctx.set_tuning(pair_waves=pw, pair_cell=pc)
+            assert ctx.tuning()["pair_cell"] == pc
+            e, f, p = ctx.energy_forces(torch.tensor(w.xyzq(dt), device="cuda"))
+            torch.cuda.synchronize()
+            assert ctx.status() == 0
+            assert rel_rms(f.double().cpu().numpy(), fo) < tol, (w.n, pw)
+            assert rel_rms(p.double().cpu().numpy(), po) < tol, (w.n, pw)
+            assert float(e[0].item()) == pytest.approx(eo, rel=tol)
+    parts = [water_box(n, (p_,) * 3, (s_,) * 3, seed=40 + n) for n, p_, s_ in ((700, 9, 3.0), (433, 8, 2.6))]
+    offs = [0, 3 * 700, 3 * 700 + 3 * 433]
+    doms = [list(q.lo) + list(q.hi) for q in parts]
+    big = m.MsmContext(1.2, 0.25, parts[0].lo, parts[0].hi, precision=precision, max_atoms=offs[-1], max_systems=2)
+    big.set_tuning(pair_cell=pc)
+    x = torch.tensor(np.concatenate([q.xyzq(dt) for q in parts]), device="cuda")
+    eb, fb, pb = big.energy_forces(x, offs, doms)
+    for s_, q in enumerate(parts):
+        one = m.MsmContext(1.2, 0.25, q.lo, q.hi, precision=precision, max_atoms=q.n)
+        one.set_tuning(pair_cell=pc)
+        e1, f1, p1 = one.energy_forces(torch.tensor(q.xyzq(dt), device="cuda"))
+        torch.cuda.synchronize()
+        assert torch.equal(eb[s_:s_ + 1], e1) and torch.equal(fb[offs[s_]:offs[s_ + 1]], f1)
+        assert torch.equal(pb[offs[s_]:offs[s_ + 1]], p1)
+    with pytest.raises(m.MsmError):
+        big.set_tuning(pair_cell=4)
+
+
 @pytest.mark.parametrize("a,h,levels", [(0.8, 0.5, 0), (1.2, 0.25, 1), (1.2, 0.25, 2), (0.6, 0.2, 0),
                                         (1.0, 0.35, 0), (0.3, 0.25, 0), (1.3, 0.25, 0), (1.4, 0.25, 0)])
 def test_fp64_parameter_variants(a, h, levels):
