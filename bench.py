@@ -703,6 +703,34 @@ def single_fp64(torch, msmx, w32, args, reps):
     return rec, out64
 
 
+def composite_roofline(n, pairs, shapes, taps, ms_eval, elem=4):
+    """The whole evaluation against its roofline: t_roof = sum over the stages
+    of max(algorithmic flops / FP32 VALU peak, algorithmic bytes / HBM peak),
+    over the measured evaluation time. Flops: 38 per unique pair; 2 per
+    stencil tap and node plus the top level's all pairs; anterpolation 2 per
+    node-atom pair plus 12 evaluations of the cubic basis (7 flops each) per
+    atom; interpolation 8 per node-atom pair (value and gradient) plus 24 basis
+    and derivative evaluations. Bytes: atoms in and out of each stage, every
+    grid node read and written once per transfer."""
+    m = [d[0] * d[1] * d[2] for _, d in shapes]
+    m0, mk = m[0], sum(m[1:])
+    peak_f, peak_b = PEAK_FP32_VALU * 1e12, PEAK_HBM * 1e9
+    terms = {
+        "bin": (0.0, n * (16 + 16 + 12) + 8.0 * m0),
+        "short": (FLOPS_PER_PAIR * pairs, n * 32.0),
+        "anterp": (n * (2 * 64 + 12 * 7.0), n * 16.0 + m0 * elem),
+        "restrict": (0.0, 2.0 * mk * elem + m0 * elem),
+        "cutoff": (stencil_flops(shapes, taps), 2.0 * sum(m) * elem),
+        "prolong": (0.0, 2.0 * mk * elem + m0 * elem),
+        "interp": (n * (8 * 64 + 24 * 7.0), n * 16.0 + m0 * elem + n * 16.0),
+    }
+    t = {k: max(f / peak_f, b / peak_b) * 1e3 for k, (f, b) in terms.items()}
+    t_roof = sum(t.values())
+    return {"t_roof_ms": round(t_roof, 5), "t_measured_ms": round(ms_eval, 5), "frac": round(t_roof / ms_eval, 4),
+            "peaks": {"fp32_valu_tflops": PEAK_FP32_VALU, "hbm_gbs": PEAK_HBM},
+            "terms_ms": {k: round(v, 5) for k, v in t.items()}}
+
+
 def roofline_of(stages, pairs, shapes, taps, form, workload):
     """Per-stage records and the roofline of the dominant kernel (algorithmic
     flops over the stage's HIP-event time)."""
@@ -745,7 +773,8 @@ def small_box_record(torch, msmx, args):
                                     ctx.tuning()["pair_waves"], "water_99999")
     rec = {"workload": f"water_99999: {w32.n} atoms, 10 nm cube, a 1.2 nm, h 0.25 nm, 5 grids",
            "fp32_ms_per_step": ms32, "fp32_value": w32.n / (ms32 * 1e-3), "launch": launch,
-           "roofline": roofline, "stage_ms": kernels}
+           "roofline": roofline, "stage_ms": kernels,
+           "composite_roofline": composite_roofline(w32.n, pairs, ctx.grid_shape(), sphere_taps(w32.a, w32.h), ms32)}
     fp64, out64 = (None, None) if args.no_fp64 else single_fp64(torch, msmx, w32, args, 5)
     rec["fp64_plain"] = fp64
     if fp64:
@@ -894,6 +923,7 @@ def main():
                                f"FP32 bulk + FP64 energy reduction",
                    "atoms": n, "levels": len(shapes), "a_nm": w32.a, "h_nm": w32.h},
         "roofline": roofline,
+        "composite_roofline": composite_roofline(n, pairs, shapes, sphere_taps(w32.a, w32.h), ms32),
         "cpu_baseline": cpu,
         "fp64_plain": fp64,
         "speedup_fp32_vs_fp64_plain": (value / fp64["value"]) if fp64 else None,

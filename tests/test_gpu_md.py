@@ -300,3 +300,42 @@ def test_constraint_failure_is_a_status_not_a_hang():
     ok.vv_run(x, vv, 1, 0.002, energies=False)
     torch.cuda.synchronize()
     assert ok.status() == -3
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp64"])
+def test_binding_after_an_evaluation_rebuilds_the_model_plan(precision):
+    """A context that has evaluated without a model and is then bound (and
+    rebound with the Lennard-Jones parameters of the hydrogens switched on)
+    gives the bits of a fresh context bound the same way: the plan of the
+    Lennard-Jones atoms follows the model."""
+    m = msmx()
+    w, mass, molid, lj, tri, v = small_water(300, 3.0, seed=21)
+    dt = np.float32 if precision == "fp32" else np.float64
+    x = torch.tensor(w.xyzq(dt), device="cuda")
+    ctx = m.MsmContext(1.0, 0.25, w.lo, w.hi, precision=precision, ke=KE, max_atoms=w.n)
+    ctx.energy_forces(x)
+    lj_all = lj.copy()
+    lj_all[1::3] = lj_all[2::3] = (0.1, 0.2)   # hydrogens with Lennard-Jones too
+    for table in (lj, lj_all):
+        ctx.bind_model(len(mass), torch.tensor(molid, dtype=torch.int32, device="cuda"),
+                       torch.tensor(table, dtype=torch.float64, device="cuda"), rigid=True, tri=tri)
+        got = ctx.energy_forces(x)
+        fresh = make_ctx(w, 1.0, 0.25, precision, mass, molid, table, tri)
+        ref = fresh.energy_forces(x)
+        torch.cuda.synchronize()
+        assert ctx.status() == 0 and fresh.status() == 0
+        for a, b in zip(got, ref):
+            assert torch.equal(a, b)
+
+
+def test_molecule_size_limit():
+    """Molecules of more than 1024 atoms are refused at binding."""
+    m = msmx()
+    n = 2048
+    ctx = m.MsmContext(1.0, 0.25, np.zeros(3), np.full(3, 4.0), precision="fp32", ke=KE, max_atoms=n)
+    molid = torch.zeros(n, dtype=torch.int32, device="cuda")
+    molid[1025:] = 1
+    with pytest.raises(m.MsmError):
+        ctx.bind_model(n, molid, None)
+    molid[1024:] = 1
+    ctx.bind_model(n, molid, None)   # two molecules of 1024 atoms
