@@ -80,6 +80,25 @@ enum PairKind { kPoly = 0, kPolyHigh = 1, kWolf = 2, kLJ = 3 };
 #endif
 constexpr int kPairUnroll = MSMX_PAIR_UNROLL;   // staged candidates read per step
 
+// Half-width of the chord a row of cells leaves inside the cutoff sphere
+// around a box. The search reach carries a relative margin of 1e-5, far above
+// the error of the hardware square root, so the chord still covers every
+// candidate within the cutoff (a candidate it might lose lies beyond a and
+// contributes nothing).
+__device__ inline float chord_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline double chord_sqrt(double x) { return sqrt(x); }
+
+// cell_rank in 32-bit arithmetic (a batch holds fewer than 2^31 cells)
+static_assert(kBrick == 4 && kBrickCells == 64, "cell_rank32 assumes 4x4x4 bricks");
+__device__ inline int cell_rank32(const SysPlan &p, int cx, int cy, int cz)
+{
+    const int bx = cx >> 2, by = cy >> 2, bz = cz >> 2;
+    const int nb0 = p.nb[0], nb1 = p.nb[1];
+    const int row = bz * nb1 + ((bz & 1) ? nb1 - 1 - by : by);
+    const int xb = (row & 1) ? nb0 - 1 - bx : bx;
+    return ((row * nb0 + xb) << 6) + ((cz & 3) << 4) + ((cy & 3) << 2) + (cx & 3);
+}
+
 // molecule id stored in the first component of an aux record
 __device__ inline int mol_of(const float4 &v) { return __float_as_int(v.x); }
 __device__ inline int mol_of(const double4 &v) { return (int)__double_as_longlong(v.x); }
@@ -235,12 +254,12 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
             const T dy = fmax(T(0), fmax(y0 - bmaxy, bminy - (y0 + h)));
             const T rem = reach2 - dy * dy - dz * dz;
             if (rem > T(0)) {
-                const T wdt = sqrt(rem);
+                const T wdt = chord_sqrt(rem);
                 const int cx0 = clampi((int)floor((bminx - lox - wdt) * inv_h), 0, ncx - 1);
                 const int cx1 = clampi((int)floor((bmaxx - lox + wdt) * inv_h), 0, ncx - 1);
                 const int ca = max(cx0, bx * kBrick), cb = min(cx1, bx * kBrick + kBrick - 1);
                 if (ca <= cb) {
-                    const int64_t r0 = P.cell0 + cell_rank(P, ca, cy, cz);
+                    const int r0 = (int)P.cell0 + cell_rank32(P, ca, cy, cz);
                     jb = cstart[r0];
                     len = cstart[r0 + (cb - ca) + 1] - jb;
                 }
@@ -404,12 +423,12 @@ __global__ __launch_bounds__(kSubLanes * kWave) void k_pair_sub(DevPlan p, const
             const T dy = fmax(T(0), fmax(y0 - bmaxy, bminy - (y0 + h)));
             const T rem = reach2 - dy * dy - dz * dz;
             if (rem > T(0)) {
-                const T wdt = sqrt(rem);
+                const T wdt = chord_sqrt(rem);
                 const int cx0 = clampi((int)floor((bminx - lox - wdt) * inv_h), 0, ncx - 1);
                 const int cx1 = clampi((int)floor((bmaxx - lox + wdt) * inv_h), 0, ncx - 1);
                 const int ca = max(cx0, bx * kBrick), cb = min(cx1, bx * kBrick + kBrick - 1);
                 if (ca <= cb) {
-                    const int64_t r0 = P.cell0 + cell_rank(P, ca, cy, cz);
+                    const int r0 = (int)P.cell0 + cell_rank32(P, ca, cy, cz);
                     jb = cstart[r0];
                     len = cstart[r0 + (cb - ca) + 1] - jb;
                 }
@@ -708,12 +727,12 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
             const T dy = fmax(T(0), fmax(y0 - bmaxy, bminy - (y0 + h)));
             const T rem = reach2 - dy * dy - dz * dz;
             if (rem > T(0)) {
-                const T wdt = sqrt(rem);
+                const T wdt = chord_sqrt(rem);
                 const int cx0 = clampi((int)floor((bminx - lox - wdt) * inv_h), 0, ncx - 1);
                 const int cx1 = clampi((int)floor((bmaxx - lox + wdt) * inv_h), 0, ncx - 1);
                 const int ca = max(cx0, bx * kBrick), cb = min(cx1, bx * kBrick + kBrick - 1);
                 if (ca <= cb) {
-                    const int64_t r0 = P.cell0 + cell_rank(P, ca, cy, cz);
+                    const int r0 = (int)P.cell0 + cell_rank32(P, ca, cy, cz);
                     jb = cstart[r0];
                     len = cstart[r0 + (cb - ca) + 1] - jb;
                 }
@@ -948,12 +967,12 @@ __global__ __launch_bounds__(GW * kWave) void k_pair_grp(DevPlan p, const vec4_t
             const T dy = fmax(T(0), fmax(y0 - bmaxy, bminy - (y0 + h)));
             const T rem = reach2 - dy * dy - dz * dz;
             if (rem > T(0)) {
-                const T wdt = sqrt(rem);
+                const T wdt = chord_sqrt(rem);
                 const int cx0 = clampi((int)floor((bminx - lox - wdt) * inv_h), 0, ncx - 1);
                 const int cx1 = clampi((int)floor((bmaxx - lox + wdt) * inv_h), 0, ncx - 1);
                 const int ca = max(cx0, bx * kBrick), cb = min(cx1, bx * kBrick + kBrick - 1);
                 if (ca <= cb) {
-                    const int64_t r0 = P.cell0 + cell_rank(P, ca, cy, cz);
+                    const int r0 = (int)P.cell0 + cell_rank32(P, ca, cy, cz);
                     jb = cstart[r0];
                     len = cstart[r0 + (cb - ca) + 1] - jb;
                 }
