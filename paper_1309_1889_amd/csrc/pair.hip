@@ -749,11 +749,9 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
         const int total = uni(__shfl(incl, kWave - 1, kWave));
         if (lane == 0) pre[kWave] = total;
         // table of the first kClMap stream positions
-        int maxlen = len;
-        for (int off = 32; off > 0; off >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, off, kWave));
-        maxlen = uni(maxlen);
-        for (int t = 0; t < maxlen; ++t)
-            if (t < len && start + t < kClMap) map[start + t] = jb + t;
+        // (a per-lane loop: a wave-wide bound would hold cross-lane
+        // addresses in registers the kernel cannot spare)
+        for (int t = 0; t < len && start + t < kClMap; ++t) map[start + t] = jb + t;
         __builtin_amdgcn_wave_barrier();
         auto atom_at = [&](int pos) -> int {
             if (pos < kClMap) return map[pos];
@@ -996,11 +994,7 @@ __global__ __launch_bounds__(GW * kWave) void k_pair_grp(DevPlan p, const vec4_t
         pre[wv * kWave + lane] = start;
         fst[wv * kWave + lane] = jb;
         if (wv == GW - 1 && lane == kWave - 1) pre[NR] = total;
-        int maxlen = len;
-        for (int off = 32; off > 0; off >>= 1) maxlen = max(maxlen, __shfl_xor(maxlen, off, kWave));
-        maxlen = uni(maxlen);
-        for (int t = 0; t < maxlen; ++t)
-            if (t < len && start + t < kMap) map[start + t] = jb + t;
+        for (int t = 0; t < len && start + t < kMap; ++t) map[start + t] = jb + t;
         __syncthreads();   // the batch's tables are complete
         auto atom_at = [&](int pos) -> int {
             if (pos < kMap) return map[pos];
