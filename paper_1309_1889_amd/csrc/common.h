@@ -57,17 +57,41 @@ struct SysPlan {
 __host__ __device__ inline int padded_x(int d) { return d + 2 * kGridPad + kStencilTile; }
 __host__ __device__ inline int padded_z(int d) { return d + 2 * kGridPad + kStencilTile; }
 
+// Brick rows (the bricks of one (by, bz) pair, along x) are taken in strips
+// of kRowStrip rows along y: all rows of a strip, z after y, before the next
+// strip. The pair sum reads every atom within the cutoff of the atoms it is
+// working on, about two bricks in each direction; with rows ordered z after y
+// over the whole domain, the rows one brick away in z are a whole plane of
+// rows away in the order, and at 65 x 65 rows of bricks the band a pass over
+// the order touches is larger than an XCD's L2. Inside a strip it is
+// kRowStrip rows wide. A domain at most kRowStrip bricks wide in y is one
+// strip. Strips and the y runs inside them alternate direction, so
+// consecutive rows share a face.
+#ifndef MSMX_ROW_STRIP
+#define MSMX_ROW_STRIP 8
+#endif
+constexpr int kRowStrip = MSMX_ROW_STRIP;
+
+__host__ __device__ inline int64_t brick_row(const SysPlan &p, int by, int bz)
+{
+    const int nb1 = p.nb[1], nb2 = p.nb[2];
+    const int s = by / kRowStrip, yl = by - s * kRowStrip;
+    const int ws = nb1 - s * kRowStrip < kRowStrip ? nb1 - s * kRowStrip : kRowStrip;
+    const int zz = (s & 1) ? nb2 - 1 - bz : bz;
+    const int yy = (zz & 1) ? ws - 1 - yl : yl;
+    return (int64_t)s * kRowStrip * nb2 + (int64_t)zz * ws + yy;
+}
+
 // Rank of cell (cx, cy, cz) within its system. Bricks of 4x4x4 cells are
-// visited in a snake order (x runs alternate direction from row to row and
-// rows alternate from plane to plane), so consecutive bricks always share a
-// face and any run of consecutive sorted atoms stays spatially compact;
-// cells inside a brick are x-fastest, so a brick row of up to 4 cells along x
-// is one contiguous range.
+// visited row by row (brick_row), x alternating direction from row to row,
+// so consecutive bricks always share a face and any run of consecutive
+// sorted atoms stays spatially compact; cells inside a brick are x-fastest,
+// so a brick row of up to 4 cells along x is one contiguous range.
 __host__ __device__ inline int64_t cell_rank(const SysPlan &p, int cx, int cy, int cz)
 {
     int bx = cx / kBrick, by = cy / kBrick, bz = cz / kBrick;
     int ix = cx % kBrick, iy = cy % kBrick, iz = cz % kBrick;
-    int64_t row = (int64_t)bz * p.nb[1] + ((bz & 1) ? p.nb[1] - 1 - by : by);
+    int64_t row = brick_row(p, by, bz);
     int xb = (row & 1) ? p.nb[0] - 1 - bx : bx;
     int64_t brick = row * p.nb[0] + xb;
     return brick * kBrickCells + (iz * kBrick + iy) * kBrick + ix;
@@ -81,8 +105,13 @@ __host__ __device__ inline void cell_coords(const SysPlan &p, int64_t r, int c[3
     const int64_t row = brick / p.nb[0];
     const int xb = (int)(brick % p.nb[0]);
     const int bx = (row & 1) ? p.nb[0] - 1 - xb : xb;
-    const int bz = (int)(row / p.nb[1]), yr = (int)(row % p.nb[1]);
-    const int by = (bz & 1) ? p.nb[1] - 1 - yr : yr;
+    const int nb1 = p.nb[1], nb2 = p.nb[2];
+    const int s = (int)(row / ((int64_t)kRowStrip * nb2));
+    const int rem = (int)(row - (int64_t)s * kRowStrip * nb2);
+    const int ws = nb1 - s * kRowStrip < kRowStrip ? nb1 - s * kRowStrip : kRowStrip;
+    const int zz = rem / ws, yy = rem % ws;
+    const int bz = (s & 1) ? nb2 - 1 - zz : zz;
+    const int by = s * kRowStrip + ((zz & 1) ? ws - 1 - yy : yy);
     c[0] = bx * kBrick + in % kBrick;
     c[1] = by * kBrick + (in / kBrick) % kBrick;
     c[2] = bz * kBrick + in / (kBrick * kBrick);
