@@ -261,6 +261,10 @@ template <int P> struct Basis {
     template <typename T> __device__ static T dphi(T t) { return P == 5 ? dbasis5(t) : dbasis(t); }
 };
 
+// Reciprocal: the hardware estimate for float (1 ulp), a division for double.
+__device__ inline float rcp_t(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double rcp_t(double x) { return 1.0 / x; }
+
 // Reciprocal square root: the hardware estimate for float; for double the
 // estimate refined by two Newton-Raphson steps y <- y (3 - x y^2) / 2.
 __device__ inline float rsqrt_t(float x) { return __builtin_amdgcn_rsqf(x); }

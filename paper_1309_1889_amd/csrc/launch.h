@@ -87,6 +87,8 @@ template <typename T> struct Work {
     // the atoms that carry Lennard-Jones, binned into cells of their own (the
     // subset plan's); lj.x null when no atom carries it
     SubBins<T> lj;
+    int lj_one;          // one Lennard-Jones type (lj_sigma, lj_eps) and at most one such atom per molecule
+    double lj_sigma, lj_eps;
     int *lj_cluster;     // the subset's k-d clusters
     vec4_t<T> *lj_out;   // subset: Lennard-Jones force and energy (counted from both sides)
     // pair search in cells finer than h (null unless tuned so): every atom binned

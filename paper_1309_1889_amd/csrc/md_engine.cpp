@@ -88,6 +88,25 @@ template <typename T> int bind(msm_ctx *c, const msm_md_model *m)
         nlj = c->lj_prefix[period];
         if (nlj == 0) c->lj_prefix.clear();
     }
+    // one Lennard-Jones type and at most one such atom per molecule: the
+    // pair kernel then takes the parameters as constants and reads no records
+    bool lj_one = nlj > 0;
+    double lj_sigma = 0, lj_eps = 0;
+    if (lj_one) {
+        std::vector<int32_t> ljmol;
+        for (int64_t i = 0; i < period; i++) {
+            if (T(std::sqrt(lj[2 * i + 1])) == T(0)) continue;
+            if (ljmol.empty()) {
+                lj_sigma = lj[2 * i];
+                lj_eps = lj[2 * i + 1];
+            } else if (lj[2 * i] != lj_sigma || lj[2 * i + 1] != lj_eps) {
+                lj_one = false;
+            }
+            ljmol.push_back(mol[i]);
+        }
+        std::sort(ljmol.begin(), ljmol.end());
+        if (std::adjacent_find(ljmol.begin(), ljmol.end()) != ljmol.end()) lj_one = false;
+    }
     size_t off = 0;
     auto take = [&](size_t b) {
         size_t o = off;
@@ -124,6 +143,9 @@ template <typename T> int bind(msm_ctx *c, const msm_md_model *m)
     w.xstart = excl ? (int *)(b + o_xs) : nullptr;
     w.xidx = excl ? (int *)(b + o_xi) : nullptr;
     w.lj = SubBins<T>{};
+    w.lj_one = ljs && lj_one;
+    w.lj_sigma = lj_sigma;
+    w.lj_eps = lj_eps;
     if (ljs) {
         w.lj.cell_of = (int *)(b + o_lcell);
         w.lj.slot_of = (int *)(b + o_lslot);

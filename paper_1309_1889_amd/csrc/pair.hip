@@ -36,6 +36,8 @@ template <typename T> struct PairK {
     const float4 *wtab; // single precision: the Wolf table (kWolfPieces pieces of E and D)
     float wscale;       // kWolfPieces / a
     T ke;               // Coulomb constant (dynamics forms: forces leave in final units)
+    // kLJ1: s^2, 4 eps, 24 eps, 48 eps and the energy at r = a, 4 eps ((s/a)^12 - (s/a)^6)
+    T lj_s2, lj_e4, lj_e24, lj_e48, lj_shift;
 };
 
 // Wolf summation in single precision: E(r) = erfc(alpha r) and the force
@@ -72,8 +74,11 @@ template <> struct WolfLds<float, 2> {
 // Pair kernel forms: the smoothing polynomial of degree at most 4 (MSM with
 // m <= 2, and the simple cutoff method with a zero polynomial), of degree 6
 // (m = 3), Wolf's damped, shifted Coulomb (Section 5), and the dynamics
-// model's Lennard-Jones term, which runs over the atoms that carry one.
-enum PairKind { kPoly = 0, kPolyHigh = 1, kWolf = 2, kLJ = 3 };
+// model's Lennard-Jones term, which runs over the atoms that carry one: in
+// general (kLJ, per-atom parameters and molecules read from the aux records)
+// or for a model with one Lennard-Jones type and at most one such atom per
+// molecule (kLJ1, the parameters constant, no record read).
+enum PairKind { kPoly = 0, kPolyHigh = 1, kWolf = 2, kLJ = 3, kLJ1 = 4 };
 
 #ifndef MSMX_PAIR_UNROLL
 #define MSMX_PAIR_UNROLL 8
@@ -134,6 +139,9 @@ template <typename T, bool MD> struct PairLds {
 // kind reads: 4 eps ((s/r)^12 - (s/r)^6), shifted to zero at r = a, between
 // atoms of different molecules, with s = s_i/2 + s_j/2 and
 // eps = sqrt(eps_i) sqrt(eps_j); u then sums the pair energies of atom i.
+// The one-type kind kLJ1 takes s and eps from the constants; with at most
+// one Lennard-Jones atom per molecule the only pair inside a molecule is an
+// atom with itself, which r^2 > 0 leaves out.
 template <typename T, bool MD, bool POT, int KIND>
 __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const vec4_t<T> &aj, const vec4_t<T> &xj,
                                  const PairK<T> &k, T &fx, T &fy, T &fz, T &u, const float4 *wtab = nullptr)
@@ -141,9 +149,14 @@ __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const
     const T dx = ai.x - aj.x, dy = ai.y - aj.y, dz = ai.z - aj.z;
     const T r2 = dx * dx + dy * dy + dz * dz;
     if (r2 < k.a2 && r2 > T(0)) {
-        const T rinv = rsqrt_t(r2);
         T t;
-        if constexpr (KIND == kLJ) {
+        if constexpr (KIND == kLJ1) {
+            const T ir2 = rcp_t(r2);
+            const T sr2 = k.lj_s2 * ir2, sr6 = sr2 * sr2 * sr2;
+            if (POT) u += k.lj_e4 * (sr6 * sr6 - sr6) - k.lj_shift;
+            t = sr6 * (k.lj_e48 * sr6 - k.lj_e24) * ir2;
+        } else if constexpr (KIND == kLJ) {
+            const T rinv = rsqrt_t(r2);
             static_assert(MD, "the Lennard-Jones kind reads the aux records");
             const T eps = mol_of(xi) == mol_of(xj) ? T(0) : xi.z * xj.z;
             const T sg = xi.y + xj.y;
@@ -155,6 +168,7 @@ __device__ inline void pair_term(const vec4_t<T> &ai, const vec4_t<T> &xi, const
             }
             t = T(24) * eps * (T(2) * sr6 * sr6 - sr6) * ir2;
         } else {
+            const T rinv = rsqrt_t(r2);
             T br;
             if (KIND == kWolf && sizeof(T) == 4) {
                 // single precision: the tabulated E and D
@@ -1380,13 +1394,26 @@ hipError_t Launch<T>::lj(hipStream_t s, const DevPlan &p, const DevPlan &sub, co
     if (!w.lj.x || p.natoms == 0) return hipSuccess;
     hipError_t e = bin_sub<T>(s, p, sub, w.lj, xyzq, (const vec4_t<T> *)w.maux, w.period);
     if (e != hipSuccess || sub.ngroups == 0) return e;
-    const PairK<T> k = pair_constants<T>(m);
+    PairK<T> k = pair_constants<T>(m);
     constexpr int CA = kLjCluster;
     hipLaunchKernelGGL((k_clusters<T, CA>), dim3((unsigned)sub.ngroups), dim3(kWave), 0, s, sub, w.lj.x, w.lj_cluster);
     const int64_t nclusters = sub.ngroups * (kWave / CA);
     const dim3 grid((unsigned)((nclusters + kClWgWaves - 1) / kClWgWaves)), pblock(kClWgWaves * kWave);
     const vec4_t<T> *aux = w.lj.aux;
-    if (pot)
+    if (w.lj_one) {
+        const double s2 = w.lj_sigma * w.lj_sigma, e = w.lj_eps, c6 = std::pow(s2 / m.a / m.a, 3);
+        k.lj_s2 = T(s2);
+        k.lj_e4 = T(4 * e);
+        k.lj_e24 = T(24 * e);
+        k.lj_e48 = T(48 * e);
+        k.lj_shift = T(4 * e * (c6 * c6 - c6));
+        if (pot)
+            hipLaunchKernelGGL((k_pair_cl<T, false, true, kLJ1, 1, CA>), grid, pblock, 0, s, sub, w.lj.x, w.lj.start,
+                               w.lj_cluster, w.lj_out, k, nullptr);
+        else
+            hipLaunchKernelGGL((k_pair_cl<T, false, false, kLJ1, 1, CA>), grid, pblock, 0, s, sub, w.lj.x,
+                               w.lj.start, w.lj_cluster, w.lj_out, k, nullptr);
+    } else if (pot)
         hipLaunchKernelGGL((k_pair_cl<T, true, true, kLJ, 1, CA>), grid, pblock, 0, s, sub, w.lj.x, w.lj.start,
                            w.lj_cluster, w.lj_out, k, aux);
     else

@@ -80,6 +80,38 @@ def test_model_forces_match_oracle(precision):
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("variant", ["hydrogen_sites", "two_oxygen_types"])
+def test_model_forces_general_lennard_jones_match_oracle(precision, variant):
+    """Lennard-Jones parameters that the one-type pair kernel cannot take:
+    sites on the hydrogens too (three per molecule, two types), or two oxygen
+    types (one site per molecule). The general kernel reads each atom's
+    parameters and molecule; both against the oracle."""
+    w, mass, molid, lj, tri, v = small_water(300, 3.0, seed=14)
+    lj = lj.copy()
+    if variant == "hydrogen_sites":
+        lj[1::3] = (0.12, 0.06)
+        lj[2::3] = (0.12, 0.06)
+    else:
+        lj[0::6, 0] *= 1.08
+        lj[0::6, 1] *= 0.7
+    dt = np.float32 if precision == "fp32" else np.float64
+    if precision == "fp32":
+        w = w.as_dtype(np.float32)
+    ctx = make_ctx(w, 1.0, 0.25, precision, mass, molid, lj, tri)
+    p = oracle.OracleParams(1.0, 0.25, tuple(w.lo), tuple(w.hi), 0, KE)
+    eo, fo = oracle.md_forces(p, oracle.OracleModel(mass, molid, lj, True, tri), w.xyz, w.q)
+    tol = 1e-11 if precision == "fp64" else 1e-4
+    scale = abs(oracle.msm(p, w.xyz, w.q)[0])
+    for pw in (2, 5):
+        ctx.set_tuning(pair_waves=pw)
+        e, f, _ = ctx.energy_forces(torch.tensor(w.xyzq(dt), device="cuda"))
+        torch.cuda.synchronize()
+        assert ctx.status() == 0
+        assert rel_rms(f.double().cpu().numpy(), fo) < tol, pw
+        assert abs(e.item() - eo) < tol * scale, pw
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_velocity_verlet_matches_oracle(precision):
     w, mass, molid, lj, tri, v = small_water(216, 1.86, seed=3)
     xyz, vel = w.xyz, v
