@@ -46,29 +46,47 @@ __device__ inline void report_constraint(const TriModel &tm, int outcome)
     if (outcome && tm.status) atomicOr(tm.status, outcome);
 }
 
-// RATTLE's velocity stage: remove the relative velocity along every bond.
+// RATTLE's velocity stage: velocities with no relative component along any
+// bond. A triple whose bonds are all within the tolerance is left unchanged.
+// Otherwise the three conditions, linear in the bond multipliers mu_c
+// (v_x -= im_x sum_c mu_c sgn(c, x) r_c, r_c = r_a(c) - r_b(c), sgn +1 for
+// a(c), -1 for b(c)), are solved at once: M mu = w with
+// w_c = r_c . (v_a(c) - v_b(c)) and M_cd = (r_c . r_d) K_cd, K the inverse-mass
+// coupling of the bonds (symmetric), by Cramer's rule. This is the point the
+// iteration of the velocity stage converges to, reached to rounding.
 __device__ inline int constrain_velocities(const V3<double> r[3], V3<double> vel[3], const double im[3],
                                            const TriModel &tm)
 {
-    for (int it = 0; it < tm.max_iter; it++) {
-        bool done = true;
-        for (int c = 0; c < 3; c++) {
-            const int a = kTriA[c], b = kTriB[c];
-            const double d2 = tm.len[c] * tm.len[c];
-            const V3<double> rr = sub(r[a], r[b]);
-            const V3<double> w = sub(vel[a], vel[b]);
-            const double rw = dot(rr, w);
-            if (!isfinite(rw)) return kStatusNonFinite;
-            if (fabs(rw) <= tm.tol * d2) continue;
-            done = false;
-            const double kk = rw / ((im[a] + im[b]) * d2);
-            const double ka = kk * im[a], kb = kk * im[b];
-            vel[a] = {vel[a].x - ka * rr.x, vel[a].y - ka * rr.y, vel[a].z - ka * rr.z};
-            vel[b] = {vel[b].x + kb * rr.x, vel[b].y + kb * rr.y, vel[b].z + kb * rr.z};
-        }
-        if (done) return 0;
+    V3<double> rr[3];
+    double w[3];
+    bool done = true;
+    for (int c = 0; c < 3; c++) {
+        const int a = kTriA[c], b = kTriB[c];
+        rr[c] = sub(r[a], r[b]);
+        w[c] = dot(rr[c], sub(vel[a], vel[b]));
+        if (!isfinite(w[c])) return kStatusNonFinite;
+        if (fabs(w[c]) > tm.tol * tm.len[c] * tm.len[c]) done = false;
     }
-    return kStatusConstraint;
+    if (done) return 0;
+    // bonds 0 = (0, 1), 1 = (0, 2), 2 = (1, 2)
+    const double m00 = dot(rr[0], rr[0]) * (im[0] + im[1]), m11 = dot(rr[1], rr[1]) * (im[0] + im[2]);
+    const double m22 = dot(rr[2], rr[2]) * (im[1] + im[2]);
+    const double m01 = dot(rr[0], rr[1]) * im[0], m02 = -dot(rr[0], rr[2]) * im[1], m12 = dot(rr[1], rr[2]) * im[2];
+    const double a00 = m11 * m22 - m12 * m12, a01 = m02 * m12 - m01 * m22, a02 = m01 * m12 - m02 * m11;
+    const double a11 = m00 * m22 - m02 * m02, a12 = m01 * m02 - m00 * m12, a22 = m00 * m11 - m01 * m01;
+    const double idet = 1.0 / (m00 * a00 + m01 * a01 + m02 * a02);
+    const double mu0 = (a00 * w[0] + a01 * w[1] + a02 * w[2]) * idet;
+    const double mu1 = (a01 * w[0] + a11 * w[1] + a12 * w[2]) * idet;
+    const double mu2 = (a02 * w[0] + a12 * w[1] + a22 * w[2]) * idet;
+    if (!isfinite(mu0) || !isfinite(mu1) || !isfinite(mu2)) return kStatusNonFinite;
+    const double k0 = im[0], k1 = im[1], k2 = im[2];
+    vel[0] = {vel[0].x - k0 * (mu0 * rr[0].x + mu1 * rr[1].x), vel[0].y - k0 * (mu0 * rr[0].y + mu1 * rr[1].y),
+              vel[0].z - k0 * (mu0 * rr[0].z + mu1 * rr[1].z)};
+    vel[1] = {vel[1].x - k1 * (mu2 * rr[2].x - mu0 * rr[0].x), vel[1].y - k1 * (mu2 * rr[2].y - mu0 * rr[0].y),
+              vel[1].z - k1 * (mu2 * rr[2].z - mu0 * rr[0].z)};
+    vel[2] = {vel[2].x + k2 * (mu1 * rr[1].x + mu2 * rr[2].x), vel[2].y + k2 * (mu1 * rr[1].y + mu2 * rr[2].y),
+              vel[2].z + k2 * (mu1 * rr[1].z + mu2 * rr[2].z)};
+    return 0;
 }
 
 // Half kick and drift of one atom (no constraints). The state is FP64; the
@@ -100,16 +118,46 @@ __global__ void k_kick_drift(int64_t n, double4 *__restrict__ x, double4 *__rest
     }
 }
 
-// Half kick, drift, then RATTLE's position stage for one rigid triple: each
-// bond is brought back to its length along the bond vector before the drift,
-// and the same displacement over dt is added to the velocities.
+// Molecules per workgroup of k_kick_rattle. A thread owns one triple (96
+// bytes of positions and 96 of velocities); the workgroup moves its atoms
+// between HBM and LDS as contiguous runs, so every global access is
+// coalesced, and each thread reads and writes its own triple in LDS.
+constexpr int kTriWg = 128;
+
+template <typename T> struct TriLds {
+    double4 x[3 * kTriWg];
+    double4 v[3 * kTriWg];
+    T f[9 * kTriWg];
+};
+
+// Load the workgroup's atoms (positions, velocities) and their forces.
+template <typename T>
+__device__ inline void tri_stage_in(TriLds<T> &L, int64_t a0, int na, const double4 *__restrict__ x,
+                                    const double4 *__restrict__ v, const T *__restrict__ f)
+{
+    for (int k = threadIdx.x; k < na; k += kTriWg) {
+        L.x[k] = x[a0 + k];
+        L.v[k] = v[a0 + k];
+    }
+    for (int k = threadIdx.x; k < 3 * na; k += kTriWg) L.f[k] = f[3 * a0 + k];
+    __syncthreads();
+}
+
+// Half kick, drift, then RATTLE's position stage for one rigid triple: the
+// drifted atoms are moved along the old bond vectors ro_d, atom x by
+// im_x sum_d lambda_d sgn(d, x) ro_d, until every bond has its length, and
+// the same displacement over dt is added to the velocities. The multipliers
+// come from Newton's method on the three conditions |s_c|^2 = len_c^2 (the
+// Jacobian is J_cd = 2 K_cd (s_c . ro_d) with K the inverse-mass coupling of
+// the bonds), solved by Cramer's rule: three or four steps to the tolerance,
+// where a sweep bond by bond (the same solution) takes several dozen.
 template <typename T>
 __global__ void k_kick_drift_rattle(int64_t ntri, double4 *__restrict__ x, double4 *__restrict__ v,
                                     const T *__restrict__ f, double dt, TriModel tm, vec4_t<T> *__restrict__ xe)
 {
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= ntri) return;
-    V3<double> r[3], old[3], vel[3];
+    V3<double> r[3], vel[3], ro[3];
     double im[3], q[3];
     for (int a = 0; a < 3; a++) {
         const int64_t i = 3 * t + a;
@@ -119,32 +167,52 @@ __global__ void k_kick_drift_rattle(int64_t ntri, double4 *__restrict__ x, doubl
         im[a] = vi.w;
         const double h = 0.5 * dt * vi.w;
         vel[a] = {vi.x + h * (double)f[3 * i], vi.y + h * (double)f[3 * i + 1], vi.z + h * (double)f[3 * i + 2]};
-        old[a] = {xs.x, xs.y, xs.z};
-        r[a] = {old[a].x + dt * vel[a].x, old[a].y + dt * vel[a].y, old[a].z + dt * vel[a].z};
+        r[a] = {xs.x, xs.y, xs.z};
     }
+    for (int c = 0; c < 3; c++) ro[c] = sub(r[kTriA[c]], r[kTriB[c]]);
+    for (int a = 0; a < 3; a++) r[a] = {r[a].x + dt * vel[a].x, r[a].y + dt * vel[a].y, r[a].z + dt * vel[a].z};
+    // bonds 0 = (0, 1), 1 = (0, 2), 2 = (1, 2)
+    const double k00 = im[0] + im[1], k11 = im[0] + im[2], k22 = im[1] + im[2];
+    const double k01 = im[0], k02 = -im[1], k12 = im[2];
     const double inv_dt = 1.0 / dt;
     int outcome = kStatusConstraint;
-    for (int it = 0; it < tm.max_iter && outcome == kStatusConstraint; it++) {
+    for (int it = 0; it < tm.max_iter; it++) {
+        V3<double> sb[3];
+        double d[3];
         bool done = true;
-        for (int c = 0; c < 3; c++) {
-            const int a = kTriA[c], b = kTriB[c];
-            V3<double> s;
-            double diff;
-            if (bond_within(r, c, tm, s, diff)) continue;
-            const V3<double> ro = sub(old[a], old[b]);
-            done = false;
-            const double g = diff / (2.0 * dot(s, ro) * (im[a] + im[b]));
-            if (!isfinite(g)) {
-                outcome = kStatusNonFinite;
-                break;
-            }
-            const double ga = g * im[a], gb = g * im[b];
-            r[a] = {r[a].x + ga * ro.x, r[a].y + ga * ro.y, r[a].z + ga * ro.z};
-            r[b] = {r[b].x - gb * ro.x, r[b].y - gb * ro.y, r[b].z - gb * ro.z};
-            vel[a] = {vel[a].x + ga * inv_dt * ro.x, vel[a].y + ga * inv_dt * ro.y, vel[a].z + ga * inv_dt * ro.z};
-            vel[b] = {vel[b].x - gb * inv_dt * ro.x, vel[b].y - gb * inv_dt * ro.y, vel[b].z - gb * inv_dt * ro.z};
+        for (int c = 0; c < 3; c++)
+            if (!bond_within(r, c, tm, sb[c], d[c])) done = false;
+        if (done) {
+            outcome = 0;
+            break;
         }
-        if (done && outcome == kStatusConstraint) outcome = 0;
+        const double j00 = 2.0 * k00 * dot(sb[0], ro[0]), j01 = 2.0 * k01 * dot(sb[0], ro[1]);
+        const double j02 = 2.0 * k02 * dot(sb[0], ro[2]), j10 = 2.0 * k01 * dot(sb[1], ro[0]);
+        const double j11 = 2.0 * k11 * dot(sb[1], ro[1]), j12 = 2.0 * k12 * dot(sb[1], ro[2]);
+        const double j20 = 2.0 * k02 * dot(sb[2], ro[0]), j21 = 2.0 * k12 * dot(sb[2], ro[1]);
+        const double j22 = 2.0 * k22 * dot(sb[2], ro[2]);
+        const double c00 = j11 * j22 - j12 * j21, c01 = j12 * j20 - j10 * j22, c02 = j10 * j21 - j11 * j20;
+        const double c10 = j02 * j21 - j01 * j22, c11 = j00 * j22 - j02 * j20, c12 = j01 * j20 - j00 * j21;
+        const double c20 = j01 * j12 - j02 * j11, c21 = j02 * j10 - j00 * j12, c22 = j00 * j11 - j01 * j10;
+        const double idet = 1.0 / (j00 * c00 + j01 * c01 + j02 * c02);
+        const double l0 = (c00 * d[0] + c10 * d[1] + c20 * d[2]) * idet;
+        const double l1 = (c01 * d[0] + c11 * d[1] + c21 * d[2]) * idet;
+        const double l2 = (c02 * d[0] + c12 * d[1] + c22 * d[2]) * idet;
+        if (!isfinite(l0) || !isfinite(l1) || !isfinite(l2)) {
+            outcome = kStatusNonFinite;
+            break;
+        }
+        const V3<double> dr[3] = {
+            {im[0] * (l0 * ro[0].x + l1 * ro[1].x), im[0] * (l0 * ro[0].y + l1 * ro[1].y),
+             im[0] * (l0 * ro[0].z + l1 * ro[1].z)},
+            {im[1] * (l2 * ro[2].x - l0 * ro[0].x), im[1] * (l2 * ro[2].y - l0 * ro[0].y),
+             im[1] * (l2 * ro[2].z - l0 * ro[0].z)},
+            {-im[2] * (l1 * ro[1].x + l2 * ro[2].x), -im[2] * (l1 * ro[1].y + l2 * ro[2].y),
+             -im[2] * (l1 * ro[1].z + l2 * ro[2].z)}};
+        for (int a = 0; a < 3; a++) {
+            r[a] = {r[a].x + dr[a].x, r[a].y + dr[a].y, r[a].z + dr[a].z};
+            vel[a] = {vel[a].x + inv_dt * dr[a].x, vel[a].y + inv_dt * dr[a].y, vel[a].z + inv_dt * dr[a].z};
+        }
     }
     report_constraint(tm, outcome);
     for (int a = 0; a < 3; a++) {
@@ -175,26 +243,34 @@ __global__ void k_kick(int64_t n, double4 *__restrict__ v, const T *__restrict__
     v[i] = vi;
 }
 
-// Second half kick, then RATTLE's velocity stage: remove the relative
-// velocity along every bond of the triple.
+// Second half kick, then RATTLE's velocity stage.
 template <typename T>
-__global__ void k_kick_rattle(int64_t ntri, const double4 *__restrict__ x, double4 *__restrict__ v,
-                              const T *__restrict__ f, double dt, TriModel tm)
+__global__ __launch_bounds__(kTriWg) void k_kick_rattle(int64_t ntri, const double4 *__restrict__ x,
+                                                        double4 *__restrict__ v, const T *__restrict__ f, double dt,
+                                                        TriModel tm)
 {
-    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (t >= ntri) return;
-    V3<double> r[3], vel[3];
-    double im[3];
-    for (int a = 0; a < 3; a++) {
-        const int64_t i = 3 * t + a;
-        const double4 xi = x[i], vi = v[i];
-        im[a] = vi.w;
-        const double h = 0.5 * dt * vi.w;
-        vel[a] = {vi.x + h * (double)f[3 * i], vi.y + h * (double)f[3 * i + 1], vi.z + h * (double)f[3 * i + 2]};
-        r[a] = {xi.x, xi.y, xi.z};
+    __shared__ TriLds<T> L;
+    const int64_t t0 = blockIdx.x * (int64_t)kTriWg, a0 = 3 * t0;
+    const int na = 3 * (int)min((int64_t)kTriWg, ntri - t0);
+    tri_stage_in(L, a0, na, x, v, f);
+    const int tl = threadIdx.x;
+    if (3 * tl < na) {
+        V3<double> r[3], vel[3];
+        double im[3];
+        for (int a = 0; a < 3; a++) {
+            const int i = 3 * tl + a;
+            const double4 xi = L.x[i], vi = L.v[i];
+            im[a] = vi.w;
+            const double h = 0.5 * dt * vi.w;
+            vel[a] = {vi.x + h * (double)L.f[3 * i], vi.y + h * (double)L.f[3 * i + 1],
+                      vi.z + h * (double)L.f[3 * i + 2]};
+            r[a] = {xi.x, xi.y, xi.z};
+        }
+        report_constraint(tm, constrain_velocities(r, vel, im, tm));
+        for (int a = 0; a < 3; a++) L.v[3 * tl + a] = make_double4(vel[a].x, vel[a].y, vel[a].z, im[a]);
     }
-    report_constraint(tm, constrain_velocities(r, vel, im, tm));
-    for (int a = 0; a < 3; a++) v[3 * t + a] = make_double4(vel[a].x, vel[a].y, vel[a].z, im[a]);
+    __syncthreads();
+    for (int k = threadIdx.x; k < na; k += kTriWg) v[a0 + k] = L.v[k];
 }
 
 // Positions and charges in the evaluation precision.
@@ -383,7 +459,8 @@ hipError_t MdLaunch<T>::kick(hipStream_t s, int64_t n, const double4 *x, double4
 {
     if (n == 0) return hipSuccess;
     if (tm)
-        hipLaunchKernelGGL(k_kick_rattle<T>, dim3(nblocks(n / 3, 128)), dim3(128), 0, s, n / 3, x, v, f, dt, *tm);
+        hipLaunchKernelGGL(k_kick_rattle<T>, dim3(nblocks(n / 3, kTriWg)), dim3(kTriWg), 0, s, n / 3, x, v, f, dt,
+                           *tm);
     else
         hipLaunchKernelGGL(k_kick<T>, dim3(nblocks(n, 256)), dim3(256), 0, s, n, v, f, dt);
     return hipGetLastError();
