@@ -558,10 +558,18 @@ int evaluate(msm_ctx *c, const void *xyzq, double *energy, void *forces, void *p
     }
     const DevPlan *pp = c->mc.pair_cell > 1 ? &c->dpp : nullptr;
     if (do_short && (e = L::pair(ps, p, pp, w, (const vec4_t<T> *)xyzq, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
+    // Lennard-Jones needs only the input positions: with the fork it runs on
+    // the first stream ahead of the grid stages, beside the pair kernel, which
+    // a small system does not fill (after the grid stages it measured slower:
+    // the join then waits for it)
+    const bool lj_beside = fork;
     if (do_short && c->md_bound) {
         if ((e = L::exclusions(ps, p, w, (const vec4_t<T> *)xyzq, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
-        if ((e = L::lj(ps, p, c->dps, w, (const vec4_t<T> *)xyzq, c->mc, pot)) != hipSuccess) return MSM_ERR_HIP;
+        if (!lj_beside && (e = L::lj(ps, p, c->dps, w, (const vec4_t<T> *)xyzq, c->mc, pot)) != hipSuccess)
+            return MSM_ERR_HIP;
     }
+    if (lj_beside && c->md_bound && (e = L::lj(s, p, c->dps, w, (const vec4_t<T> *)xyzq, c->mc, pot)) != hipSuccess)
+        return MSM_ERR_HIP;
     if (!ant_first) {
         mark(MSM_STAGE_ANTERP);
         if (do_long && (e = L::anterp(s, p, w, c->mc)) != hipSuccess) return MSM_ERR_HIP;

@@ -1392,7 +1392,10 @@ hipError_t Launch<T>::lj(hipStream_t s, const DevPlan &p, const DevPlan &sub, co
                          const MethodConst &m, bool pot)
 {
     if (!w.lj.x || p.natoms == 0) return hipSuccess;
-    hipError_t e = bin_sub<T>(s, p, sub, w.lj, xyzq, (const vec4_t<T> *)w.maux, w.period);
+    // the one-type kernel reads no model records: they are not gathered
+    SubBins<T> lb = w.lj;
+    if (w.lj_one) lb.aux = nullptr;
+    hipError_t e = bin_sub<T>(s, p, sub, lb, xyzq, (const vec4_t<T> *)w.maux, w.period);
     if (e != hipSuccess || sub.ngroups == 0) return e;
     PairK<T> k = pair_constants<T>(m);
     constexpr int CA = kLjCluster;
