@@ -590,12 +590,18 @@ __device__ inline void prolong_node(const SysPlan &P, const T *__restrict__ ucut
     }
     const int cdx = P.gdim[k + 1][0], cdy = P.gdim[k + 1][1];
     const T *uc = ugrid + P.uoff[k + 1];
+    // an even fine index along y or z takes one coarse row or plane (the
+    // others weigh exactly 0); the lanes of a wave share their y and z, so
+    // the skipped rows cost nothing
+    const bool ey = !((r[1] + P.gorg[k][1]) & 1), ez = !((r[2] + P.gorg[k][2]) & 1);
     T acc = 0;
 #pragma unroll
     for (int c = 0; c < W; ++c) {
+        if (ez && c != S - 1) continue;
         T accy = 0;
 #pragma unroll
         for (int b = 0; b < W; ++b) {
+            if (ey && b != S - 1) continue;
             const T *row = uc + ((int64_t)cn[2][c] * cdy + cn[1][b]) * cdx;
             T accx = 0;
 #pragma unroll
