@@ -37,6 +37,7 @@ namespace {
 //     (2S)^3 cells whose support covers it, in a fixed order.
 // ---------------------------------------------------------------------------
 constexpr int kAntX = 8, kAntY = 8, kAntZ = 4;
+constexpr int kAntLoads = 4;   // atoms of a cell a staging thread loads at once
 // atoms a tile stages in LDS: the cubic's 11x11x7-cell region holds about
 // 1,300 water atoms, the quintic's 13x13x9 about 2,400 (FP64: 3,072 x 32 bytes)
 template <typename T, int PD> constexpr int ant_atoms()
@@ -92,7 +93,6 @@ __global__ __launch_bounds__(ant_threads<PD>()) void k_anterp(DevPlan p, const v
     constexpr int NT = ant_threads<PD>(), NODES = kAntX * kAntY * kAntZ, CPT = ant_layers_per_thread<PD>();
     __shared__ vec4_t<T> atoms[ant_atoms<T, PD>()];
     __shared__ int start[A::Cells + 1];   // staged position of each region cell's first atom
-    __shared__ int gfirst[A::Cells];      // its sorted index
     __shared__ int wsum[NT / kWave];
     if (eval_failed(p)) return;
     const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -111,7 +111,7 @@ __global__ __launch_bounds__(ant_threads<PD>()) void k_anterp(DevPlan p, const v
     // outside the grid: each thread counts a contiguous run of cells, a
     // workgroup scan places the runs
     constexpr int per = (A::Cells + NT - 1) / NT;
-    int cnt[per];
+    int cnt[per], fst[per], sst[per];
     int sum = 0;
 #pragma unroll
     for (int j = 0; j < per; ++j) {
@@ -125,9 +125,9 @@ __global__ __launch_bounds__(ant_threads<PD>()) void k_anterp(DevPlan p, const v
                 f = cstart[r];
                 n = cstart[r + 1] - f;
             }
-            gfirst[c] = f;
         }
         cnt[j] = n;
+        fst[j] = f;
         sum += n;
     }
     int incl = sum;
@@ -143,6 +143,7 @@ __global__ __launch_bounds__(ant_threads<PD>()) void k_anterp(DevPlan p, const v
     for (int j = 0; j < per; ++j) {
         const int c = tid * per + j;
         if (c < A::Cells) start[c] = run;
+        sst[j] = run;
         run += cnt[j];
     }
     if (tid == NT - 1) start[A::Cells] = run;
@@ -150,21 +151,28 @@ __global__ __launch_bounds__(ant_threads<PD>()) void k_anterp(DevPlan p, const v
     const int total = start[A::Cells];
     const bool staged = total <= ant_atoms<T, PD>();
     if (staged) {
-        // one staged atom per thread and step: its cell by binary search
+        // each thread stages the atoms of the cells it counted, the first
+        // kAntLoads of a cell loaded together
         const T lox = T(P.lo[0]), loy = T(P.lo[1]), loz = T(P.lo[2]), inv_h = T(P.inv_h);
-        for (int pos = tid; pos < total; pos += NT) {
-            int lo_ = 0, hi_ = A::Cells;   // start[lo_] <= pos < start[hi_]
-            while (hi_ - lo_ > 1) {
-                const int mid = (lo_ + hi_) >> 1;
-                if (start[mid] <= pos) lo_ = mid; else hi_ = mid;
-            }
-            const vec4_t<T> a = sx[gfirst[lo_] + (pos - start[lo_])];
+        auto put = [&](int pos, const vec4_t<T> &a) {
             vec4_t<T> o;
             o.x = (a.x - lox) * inv_h;
             o.y = (a.y - loy) * inv_h;
             o.z = (a.z - loz) * inv_h;
             o.w = a.w;
             atoms[pos] = o;
+        };
+#pragma unroll
+        for (int j = 0; j < per; ++j) {
+            const int n = cnt[j], f = fst[j], s0 = sst[j];
+            vec4_t<T> v[kAntLoads];
+#pragma unroll
+            for (int k = 0; k < kAntLoads; ++k)
+                if (k < n) v[k] = sx[f + k];
+#pragma unroll
+            for (int k = 0; k < kAntLoads; ++k)
+                if (k < n) put(s0 + k, v[k]);
+            for (int k = kAntLoads; k < n; ++k) put(s0 + k, sx[f + k]);
         }
     }
     __syncthreads();
