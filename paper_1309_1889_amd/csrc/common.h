@@ -64,17 +64,22 @@ __host__ __device__ inline int padded_z(int d) { return d + 2 * kGridPad + kSten
 // over the whole domain, the rows one brick away in z are a whole plane of
 // rows away in the order, and at 65 x 65 rows of bricks the band a pass over
 // the order touches is larger than an XCD's L2. Inside a strip it is
-// kRowStrip rows wide. A domain at most kRowStrip bricks wide in y is one
-// strip. Strips and the y runs inside them alternate direction, so
-// consecutive rows share a face.
+// kRowStrip rows wide. Strips and the y runs inside them alternate
+// direction, so consecutive rows share a face. A domain narrower than
+// kRowStripMin bricks in y is one strip (rows z after y): its band fits the
+// L2 anyway, and on such domains with empty rows around the atoms (a
+// dynamics box with room to move) strips measured 1.5-2.5x slower pair
+// kernels.
 #ifndef MSMX_ROW_STRIP
 #define MSMX_ROW_STRIP 8
 #endif
 constexpr int kRowStrip = MSMX_ROW_STRIP;
+constexpr int kRowStripMin = 32;
 
 __host__ __device__ inline int64_t brick_row(const SysPlan &p, int by, int bz)
 {
     const int nb1 = p.nb[1], nb2 = p.nb[2];
+    if (nb1 < kRowStripMin) return (int64_t)bz * nb1 + ((bz & 1) ? nb1 - 1 - by : by);
     const int s = by / kRowStrip, yl = by - s * kRowStrip;
     const int ws = nb1 - s * kRowStrip < kRowStrip ? nb1 - s * kRowStrip : kRowStrip;
     const int zz = (s & 1) ? nb2 - 1 - bz : bz;
@@ -106,6 +111,13 @@ __host__ __device__ inline void cell_coords(const SysPlan &p, int64_t r, int c[3
     const int xb = (int)(brick % p.nb[0]);
     const int bx = (row & 1) ? p.nb[0] - 1 - xb : xb;
     const int nb1 = p.nb[1], nb2 = p.nb[2];
+    if (nb1 < kRowStripMin) {
+        const int bz = (int)(row / nb1), yr = (int)(row % nb1);
+        c[0] = bx * kBrick + in % kBrick;
+        c[1] = ((bz & 1) ? nb1 - 1 - yr : yr) * kBrick + (in / kBrick) % kBrick;
+        c[2] = bz * kBrick + in / (kBrick * kBrick);
+        return;
+    }
     const int s = (int)(row / ((int64_t)kRowStrip * nb2));
     const int rem = (int)(row - (int64_t)s * kRowStrip * nb2);
     const int ws = nb1 - s * kRowStrip < kRowStrip ? nb1 - s * kRowStrip : kRowStrip;

@@ -100,10 +100,15 @@ __device__ inline int cell_rank32(const SysPlan &p, int cx, int cy, int cz)
     static_assert((kRowStrip & (kRowStrip - 1)) == 0, "the strip width is a power of two");
     const int bx = cx >> 2, by = cy >> 2, bz = cz >> 2;
     const int nb0 = p.nb[0], nb1 = p.nb[1], nb2 = p.nb[2];
-    const int s = by / kRowStrip, yl = by & (kRowStrip - 1);
-    const int ws = min(nb1 - s * kRowStrip, kRowStrip);
-    const int zz = (s & 1) ? nb2 - 1 - bz : bz;
-    const int row = s * kRowStrip * nb2 + zz * ws + ((zz & 1) ? ws - 1 - yl : yl);
+    int row;
+    if (nb1 < kRowStripMin) {
+        row = bz * nb1 + ((bz & 1) ? nb1 - 1 - by : by);
+    } else {
+        const int s = by / kRowStrip, yl = by & (kRowStrip - 1);
+        const int ws = min(nb1 - s * kRowStrip, kRowStrip);
+        const int zz = (s & 1) ? nb2 - 1 - bz : bz;
+        row = s * kRowStrip * nb2 + zz * ws + ((zz & 1) ? ws - 1 - yl : yl);
+    }
     const int xb = (row & 1) ? nb0 - 1 - bx : bx;
     return ((row * nb0 + xb) << 6) + ((cz & 3) << 4) + ((cy & 3) << 2) + (cx & 3);
 }
