@@ -45,6 +45,17 @@ template <typename T, int PD> constexpr int ant_atoms()
     return Basis<PD>::S == 2 ? 2048 : (sizeof(T) == 4 ? 4096 : 3072);
 }
 
+// A fixed piece of the cubic along y or z in the tiled gather: the atom's
+// row lies within the support (|t| <= 2, up to the rounding of an atom
+// clamped into an edge cell), so unlike phi_piece no range test follows.
+template <typename T> __device__ inline T cubic_row_piece(T t, int j)
+{
+    const T x = fabs(t);
+    if (j == 0) return T(1) + x * x * (T(-2.5) + T(1.5) * x);
+    const T u = T(2) - x;
+    return T(-0.5) * (x - T(1)) * u * u;
+}
+
 template <int S> struct AntTile {
     static constexpr int CX = kAntX + 2 * S - 1, CY = kAntY + 2 * S - 1, CZ = kAntZ + 2 * S - 1;   // cells reached
     static constexpr int Rows = CY * CZ;
@@ -200,7 +211,12 @@ __global__ __launch_bounds__(ant_threads<PD>()) void k_anterp(DevPlan p, const v
                 const int jb = start[row * A::CX + lx], je = start[row * A::CX + lx + 2 * S];
                 for (int j = jb; j < je; ++j) {
                     const vec4_t<T> a = atoms[j];
-                    acc += phi_inside<PD>(a.x - fx) * phi_piece<PD>(a.y - fy, py) * phi_piece<PD>(a.z - fz, pz) * a.w;
+                    if constexpr (PD == 3)
+                        acc += phi_inside<PD>(a.x - fx) * cubic_row_piece(a.y - fy, py) * cubic_row_piece(a.z - fz, pz) *
+                               a.w;
+                    else
+                        acc += phi_inside<PD>(a.x - fx) * phi_piece<PD>(a.y - fy, py) * phi_piece<PD>(a.z - fz, pz) *
+                               a.w;
                 }
             }
         }
