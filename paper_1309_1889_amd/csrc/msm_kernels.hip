@@ -56,6 +56,17 @@ template <typename T> __device__ inline T cubic_row_piece(T t, int j)
     return T(-0.5) * (x - T(1)) * u * u;
 }
 
+// The cubic along x in the tiled gather: the run of a node's cells holds
+// only atoms within the support, so the piece is chosen without a range test.
+template <typename T> __device__ inline T cubic_run(T t)
+{
+    const T x = fabs(t);
+    const T u = T(2) - x;
+    const T inner = T(1) + x * x * (T(-2.5) + T(1.5) * x);
+    const T outer = T(-0.5) * (x - T(1)) * u * u;
+    return x <= T(1) ? inner : outer;
+}
+
 template <int S> struct AntTile {
     static constexpr int CX = kAntX + 2 * S - 1, CY = kAntY + 2 * S - 1, CZ = kAntZ + 2 * S - 1;   // cells reached
     static constexpr int Rows = CY * CZ;
@@ -212,8 +223,7 @@ __global__ __launch_bounds__(ant_threads<PD>()) void k_anterp(DevPlan p, const v
                 for (int j = jb; j < je; ++j) {
                     const vec4_t<T> a = atoms[j];
                     if constexpr (PD == 3)
-                        acc += phi_inside<PD>(a.x - fx) * cubic_row_piece(a.y - fy, py) * cubic_row_piece(a.z - fz, pz) *
-                               a.w;
+                        acc += cubic_run(a.x - fx) * cubic_row_piece(a.y - fy, py) * cubic_row_piece(a.z - fz, pz) * a.w;
                     else
                         acc += phi_inside<PD>(a.x - fx) * phi_piece<PD>(a.y - fy, py) * phi_piece<PD>(a.z - fz, pz) *
                                a.w;
@@ -935,8 +945,26 @@ __global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4
 #pragma unroll
                 for (int m = 0; m < W; ++m) {
                     const T o = t[d] - T(base[d] + m);
-                    w[d][m] = B::phi(o);
-                    dw[d][m] = B::dphi(o) * inv_h;
+                    if constexpr (PD == 3) {
+                        // node m of the four lies at |o| in [1, 2] (m = 0, 3) or
+                        // [0, 1] (m = 1, 2) from the atom, o < 0 for m = 2, 3:
+                        // a fixed piece of the cubic and of its derivative
+                        const T x = m < 2 ? o : -o;
+                        T v, dv;
+                        if (m == 1 || m == 2) {
+                            v = T(1) + x * x * (T(-2.5) + T(1.5) * x);
+                            dv = x * (T(-5) + T(4.5) * x);
+                        } else {
+                            const T u = T(2) - x;
+                            v = T(-0.5) * (x - T(1)) * u * u;
+                            dv = T(-0.5) * u * (T(4) - T(3) * x);
+                        }
+                        w[d][m] = v;
+                        dw[d][m] = (m < 2 ? dv : -dv) * inv_h;
+                    } else {
+                        w[d][m] = B::phi(o);
+                        dw[d][m] = B::dphi(o) * inv_h;
+                    }
                 }
             }
             const int dx = P.gdim[0][0], dy = P.gdim[0][1];
