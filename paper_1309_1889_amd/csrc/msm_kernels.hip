@@ -473,9 +473,10 @@ struct TopArgs {
 // the tile grown by the reach R in LDS. Each thread owns one (x, y) output
 // column of TZ nodes and one share of the stencil's columns (ox, oy). The
 // weights depend on |o| only, so the (up to) four mirrored columns
-// (+-ox, +-oy) are added first and share one pass of the 2R+1 weights along z:
-// the quarter-disc of columns carries the whole sphere. The shares are summed
-// in a fixed order at the end.
+// (+-ox, +-oy) are added first and share one pass of the 2R+1 weights along z,
+// in which the charges at +-oz are paired too: the quarter-disc of columns
+// and half of each carry the whole sphere. The shares are summed in a fixed
+// order at the end.
 // ---------------------------------------------------------------------------
 template <typename T, int R, int NT> struct StencilGeom {
     static constexpr int TZ = (sizeof(T) == 8 && R >= 10) ? 4 : kStencilTile;
@@ -561,12 +562,23 @@ __global__ __launch_bounds__(NT) void k_stencil(DevPlan p, const T *__restrict__
             column(cx + o.x, cy - o.y, S);
             if (o.x) column(cx - o.x, cy - o.y, S);
         }
+        // the weights along z are even in oz as well: the pair of charges at
+        // +-oz is added first and shares one multiply
         const T *w = qw + (int64_t)c * D;
+        {
+            const T wv = w[R];
 #pragma unroll
-        for (int oz = 0; oz < D; ++oz) {
-            const T wv = w[oz];
+            for (int z = 0; z < G::TZ; ++z) acc[z] += wv * S[z + R];
+        }
+        // beyond the sphere (|o| >= 2a/h) the weights of a column are zero
+        // from some d on: the column's remaining pairs are skipped (the
+        // weights are the same for the whole wave)
 #pragma unroll
-            for (int z = 0; z < G::TZ; ++z) acc[z] += wv * S[z + oz];
+        for (int d = 1; d <= R; ++d) {
+            const T wv = w[R + d];
+            if (wv == T(0)) break;
+#pragma unroll
+            for (int z = 0; z < G::TZ; ++z) acc[z] += wv * (S[z + R + d] + S[z + R - d]);
         }
     }
     __syncthreads();
