@@ -805,7 +805,7 @@ def small_box_record(torch, msmx, args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the multi-GPU "
+        print(json.dumps({"error": "bench.py runs on one GPU; --gpus must be 1 (the multi-GPU "
                                    "sharding is a design in the documentation, not code)"}))
         sys.exit(2)
 
