@@ -129,6 +129,27 @@ __host__ __device__ inline void cell_coords(const SysPlan &p, int64_t r, int c[3
     c[2] = bz * kBrick + in / (kBrick * kBrick);
 }
 
+// cell_rank in 32-bit arithmetic (a batch holds fewer than 2^31 cells), for
+// the pair search's inner loops
+static_assert(kBrick == 4 && kBrickCells == 64, "cell_rank32 assumes 4x4x4 bricks");
+__host__ __device__ inline int cell_rank32(const SysPlan &p, int cx, int cy, int cz)
+{
+    static_assert((kRowStrip & (kRowStrip - 1)) == 0, "the strip width is a power of two");
+    const int bx = cx >> 2, by = cy >> 2, bz = cz >> 2;
+    const int nb0 = p.nb[0], nb1 = p.nb[1], nb2 = p.nb[2];
+    int row;
+    if (nb1 < kRowStripMin) {
+        row = bz * nb1 + ((bz & 1) ? nb1 - 1 - by : by);
+    } else {
+        const int s = by / kRowStrip, yl = by & (kRowStrip - 1);
+        const int ws = nb1 - s * kRowStrip < kRowStrip ? nb1 - s * kRowStrip : kRowStrip;
+        const int zz = (s & 1) ? nb2 - 1 - bz : bz;
+        row = s * kRowStrip * nb2 + zz * ws + ((zz & 1) ? ws - 1 - yl : yl);
+    }
+    const int xb = (row & 1) ? nb0 - 1 - bx : bx;
+    return ((row * nb0 + xb) << 6) + ((cz & 3) << 4) + ((cy & 3) << 2) + (cx & 3);
+}
+
 // Find s with prefix[s] <= g < prefix[s+1]; prefix has n+1 increasing entries.
 __device__ inline int find_segment(const int64_t *prefix, int n, int64_t g)
 {

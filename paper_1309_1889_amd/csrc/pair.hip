@@ -93,26 +93,6 @@ constexpr int kPairUnroll = MSMX_PAIR_UNROLL;   // staged candidates read per st
 __device__ inline float chord_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ inline double chord_sqrt(double x) { return sqrt(x); }
 
-// cell_rank in 32-bit arithmetic (a batch holds fewer than 2^31 cells)
-static_assert(kBrick == 4 && kBrickCells == 64, "cell_rank32 assumes 4x4x4 bricks");
-__device__ inline int cell_rank32(const SysPlan &p, int cx, int cy, int cz)
-{
-    static_assert((kRowStrip & (kRowStrip - 1)) == 0, "the strip width is a power of two");
-    const int bx = cx >> 2, by = cy >> 2, bz = cz >> 2;
-    const int nb0 = p.nb[0], nb1 = p.nb[1], nb2 = p.nb[2];
-    int row;
-    if (nb1 < kRowStripMin) {
-        row = bz * nb1 + ((bz & 1) ? nb1 - 1 - by : by);
-    } else {
-        const int s = by / kRowStrip, yl = by & (kRowStrip - 1);
-        const int ws = min(nb1 - s * kRowStrip, kRowStrip);
-        const int zz = (s & 1) ? nb2 - 1 - bz : bz;
-        row = s * kRowStrip * nb2 + zz * ws + ((zz & 1) ? ws - 1 - yl : yl);
-    }
-    const int xb = (row & 1) ? nb0 - 1 - bx : bx;
-    return ((row * nb0 + xb) << 6) + ((cz & 3) << 4) + ((cy & 3) << 2) + (cx & 3);
-}
-
 // molecule id stored in the first component of an aux record
 __device__ inline int mol_of(const float4 &v) { return __float_as_int(v.x); }
 __device__ inline int mol_of(const double4 &v) { return (int)__double_as_longlong(v.x); }
