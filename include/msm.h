@@ -49,7 +49,7 @@ enum {
     MSM_ERR_HIP = -5,           /* a HIP runtime call failed */
     MSM_ERR_UNSUPPORTED = -6,   /* parameters outside what the kernels are built for */
     MSM_ERR_CONSTRAINT = -7     /* the constraint iteration of a rigid molecule stopped at its
-                                   cap (500 sweeps) without meeting the tolerance */
+                                   cap (500 steps) without meeting the tolerance */
 };
 
 enum { MSM_FP64 = 0, MSM_FP32 = 1 };
@@ -271,8 +271,11 @@ typedef struct {
     int rigid_triples;           /* 1: atoms 3m, 3m+1, 3m+2 of every system are rigid; system
                                     offsets must then be multiples of 3 */
     double tri_len[3];           /* distances 0-1, 0-2, 1-2 of each rigid triple (nm) */
-    double constraint_tol;       /* relative tolerance of the constraint iteration (0: 1e-10);
-                                    the iteration runs in FP64 */
+    double constraint_tol;       /* relative tolerance of the constraints (0: 1e-10), in FP64:
+                                    RATTLE's position stage takes Newton steps on a triple's
+                                    three bond conditions until each is within it, the velocity
+                                    stage solves its three linear conditions directly, and a
+                                    triple already within it is left unchanged by both */
 } msm_md_model;
 
 /* Copy a molecular model into the context and allocate the dynamics
