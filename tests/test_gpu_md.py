@@ -139,6 +139,15 @@ def test_velocity_verlet_matches_oracle(precision):
     lim = 1e-9
     for (a, b), L in zip([(0, 1), (0, 2), (1, 2)], tri):
         assert np.abs(np.linalg.norm(d[:, a] - d[:, b], axis=1) - L).max() < lim
+    # RATTLE's velocity stage solves its three linear conditions exactly: no
+    # relative velocity along any bond beyond rounding (the tolerance would
+    # allow 1e-10 of the bond length squared per ps)
+    vgm = vg.reshape(-1, 3, 3)
+    for a, b in [(0, 1), (0, 2), (1, 2)]:
+        r = d[:, a] - d[:, b]
+        w = vgm[:, a] - vgm[:, b]
+        along = np.abs((r * w).sum(1)) / (np.linalg.norm(r, axis=1) * np.linalg.norm(w, axis=1) + 1e-300)
+        assert along.max() < 1e-11, (a, b, along.max())
 
 
 def test_uneven_batch_vv_equals_separate_bitwise():
