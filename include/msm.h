@@ -186,7 +186,15 @@ typedef struct {
                               clusters of a 64-atom group (7; one workgroup of 8 waves) or the
                               4 of half a group (9) share one candidate stream, built and
                               loaded once by the workgroup (same terms in the same order as
-                              2, so the same bits) */
+                              2, so the same bits); 10 (single precision only, not for
+                              msm_energy_forces_noalloc): as 2, but each pair inside the
+                              cutoff is evaluated once (Newton's third law, Section 3's
+                              short-range sum) and the candidate's share is added to 64-bit
+                              fixed-point accumulators (unit 2^-32 of the force bracket and
+                              potential, |share| < 2^31 per block of candidates); setting it
+                              allocates those accumulators (32 bytes per atom of max_atoms).
+                              Integer sums are exact, so this form too gives the same bits
+                              in every run, but other bits than 2 */
     int stencil_threads;   /* threads per lattice-cutoff tile: 256 or 1024 */
     int concurrent;        /* 1: the short-range sum runs on a second stream of the context,
                               concurrently with the grid stages (forked after binning,
@@ -209,7 +217,8 @@ int msm_get_tuning(const msm_ctx *ctx, msm_tuning *out);
 int msm_set_tuning(msm_ctx *ctx, const msm_tuning *tuning);
 
 /* Autotuner: time whole evaluations (launched eagerly; with concurrent stages
- * on, for both fork points 1 and 2) for every pair_waves and stencil_threads candidate,
+ * on, for both fork points 1 and 2) for every pair_waves (10 in single
+ * precision only) and stencil_threads candidate,
  * reps evaluations each, on the caller's own batch (arguments as for
  * msm_energy_forces; no outputs are written), then the chosen ones with
  * pair_cell 2 and 3; keep the fastest and report it in *chosen (may be

@@ -925,6 +925,7 @@ void msm_destroy(msm_ctx *c)
     if (c->plan_host) (void)hipHostFree(c->plan_host);
     if (c->mdbuf) (void)hipFree(c->mdbuf);
     if (c->pcbuf) (void)hipFree(c->pcbuf);
+    if (c->n3buf) (void)hipFree(c->n3buf);
     delete c;
 }
 
@@ -1010,11 +1011,35 @@ static int ensure_pair_cells(msm_ctx *c, int m)
     return MSM_OK;
 }
 
+// The accumulators of the Newton's third law pair form, zero (single
+// precision contexts that own their memory only).
+static int ensure_newton(msm_ctx *c)
+{
+    if (c->prm.precision != MSM_FP32 || c->fixed_plan) return MSM_ERR_UNSUPPORTED;
+    const int64_t na = std::max<int64_t>(c->prm.max_atoms, 1);
+    if (c->n3buf && na <= c->n3_cap) return MSM_OK;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
+    if (c->n3buf) (void)hipFree(c->n3buf);
+    c->n3buf = nullptr;
+    c->n3_cap = 0;
+    c->wf.nacc = nullptr;
+    c->wf.nacc_stride = 0;
+    const size_t bytes = sizeof(unsigned long long) * 4 * (size_t)na;
+    if (hipMalloc(&c->n3buf, bytes) != hipSuccess) return MSM_ERR_HIP;
+    if (hipMemsetAsync(c->n3buf, 0, bytes, c->stream) != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess)
+        return MSM_ERR_HIP;
+    c->n3_cap = na;
+    c->wf.nacc = (unsigned long long *)c->n3buf;
+    c->wf.nacc_stride = na;
+    return MSM_OK;
+}
+
 int msm_set_tuning(msm_ctx *c, const msm_tuning *t)
 {
     if (!c || !t) return MSM_ERR_ARG;
     if (t->pair_waves != 1 && t->pair_waves != 2 && t->pair_waves != 3 && t->pair_waves != 4 && t->pair_waves != 5 &&
-        t->pair_waves != 6 && t->pair_waves != 7 && t->pair_waves != 8 && t->pair_waves != 9 && t->pair_waves != 16)
+        t->pair_waves != 6 && t->pair_waves != 7 && t->pair_waves != 8 && t->pair_waves != 9 && t->pair_waves != 10 &&
+        t->pair_waves != 16)
         return MSM_ERR_ARG;
     if (t->stencil_threads != 256 && t->stencil_threads != 1024) return MSM_ERR_ARG;
     if (t->concurrent < 0 || t->concurrent > 2) return MSM_ERR_ARG;
@@ -1023,6 +1048,7 @@ int msm_set_tuning(msm_ctx *c, const msm_tuning *t)
     if (hipStreamSynchronize(c->stream) != hipSuccess) return MSM_ERR_HIP;
     int rc = ensure_pair_cells(c, t->pair_cell);
     if (rc) return rc;
+    if (t->pair_waves == 10 && (rc = ensure_newton(c))) return rc;
     for (auto &g : c->graphs) drop_graph(g);     // captured launches use the old kernels
     if (t->pair_cell != c->mc.pair_cell) c->plan_valid = false;   // the plan holds the cells
     c->mc.pair_waves = t->pair_waves;
@@ -1074,9 +1100,10 @@ int msm_autotune(msm_ctx *c, int nsys, const int64_t *offsets, const double *dom
     const int modes[2] = {1, 2};
     const int nmodes = start.concurrent ? 2 : 1;
     for (int mi = 0; mi < nmodes; mi++)
-        for (int pw : {1, 2, 3, 4, 5, 6, 7, 8, 9, 16})
+        for (int pw : {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 16})
             for (int st : {256, 1024}) {
                 if (rc) break;
+                if (pw == 10 && ensure_newton(c) != MSM_OK) continue;   // single precision only
                 c->mc.pair_waves = pw;
                 c->mc.stencil_threads = st;
                 c->concurrent = start.concurrent ? modes[mi] : 0;

@@ -114,6 +114,10 @@ struct msm_ctx {
     // for pc_cap cells and max_atoms atoms, and the plan of those cells
     char *pcbuf = nullptr;
     int64_t pc_cap = 0;
+    // accumulators of the Newton's third law pair form (tuning pair_waves 10),
+    // 4 x n3_cap 64-bit words
+    void *n3buf = nullptr;
+    int64_t n3_cap = 0;
     msmx::DevPlan dpp{};
     void *md_forces = nullptr;                  // max_atoms x 3, precision T
     void *md_forces_slow = nullptr;             // multiple time steps: the grid part, max_atoms x 3

@@ -95,6 +95,12 @@ template <typename T> struct Work {
     // a second time, the pair sums in that order, then permuted into shrt
     SubBins<T> pc;
     vec4_t<T> *pc_out;
+    // the Newton's third law pair form (single precision): per sorted atom the
+    // fixed-point sums (unit 2^-32) of the contributions it received as a
+    // candidate, components x, y, z, u at nacc[c * nacc_stride + atom]; zero
+    // between evaluations (null until that form is chosen)
+    unsigned long long *nacc;
+    int64_t nacc_stride;
 };
 
 // Quarter-disc stencil columns (ox >= 0, oy >= 0 inside the sphere) and their
@@ -128,7 +134,8 @@ struct MethodConst {
                                // 3: two such clusters per wave sharing one candidate stream;
                                // 5, 6: one 16-atom (5) or 32-atom (6) cluster per wave;
                                // 7, 9: as 2, the clusters of a group (7) or half group (9)
-                               // sharing one stream built and loaded by the workgroup
+                               // sharing one stream built and loaded by the workgroup;
+                               // 10: as 2, each pair evaluated once (Newton's third law), single precision
     int stencil_threads;       // threads per stencil tile: 256 or 1024
     int pair_cell;             // the pair search's cells: edge h / pair_cell (1: the grid cells)
 };

@@ -841,6 +841,327 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
     }
 }
 
+// ---------------------------------------------------------------------------
+// Newton's third law form (pair_waves 10, single precision): each pair inside
+// the cutoff is evaluated once. The wave of an 8-atom cluster of group G
+// takes from its candidate stream only the atoms sorted after G (the clusters
+// of a later group would otherwise meet the pair again), and from G itself the
+// atoms of its own and of later clusters in the group's k-d order (inside its
+// own cluster the later ones). A lane holds one candidate j; the wave walks the
+// cluster's 8 atoms i, wave-uniform, and the lane adds q_j b (r_i - r_j) and
+// q_j g to its partial sums of atom i, and q_i b (r_j - r_i) and q_i g to
+// those of its candidate (b: the force bracket, g: the pair potential, both
+// of r_ij). After a block of 64 candidates each lane adds its candidate's sums
+// to the candidate's 64-bit accumulators in fixed point (unit 2^-32): integer
+// addition is associative, so the totals do not depend on the order in which
+// waves reach them, and the results are the same bits in every run. The
+// partial sums of the cluster's atoms are added across the lanes at the end
+// (a fixed butterfly) and stored; k_n3_combine then adds each atom's
+// accumulators to its stored sums and clears them for the next evaluation.
+// Every term is the one the full-list forms compute for the pair, from its
+// either side; only the grouping of the sums differs.
+// ---------------------------------------------------------------------------
+constexpr double kFixScale = 4294967296.0;   // 2^32
+constexpr double kFixUnit = 1.0 / kFixScale;
+
+__device__ inline unsigned long long to_fixed(float v)
+{
+    return (unsigned long long)(long long)((double)v * kFixScale);
+}
+
+__device__ inline void acc_add(unsigned long long *a, unsigned long long v)
+{
+    __hip_atomic_fetch_add(a, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// the force bracket b and (POT) the potential g of a pair at r^2 (the terms of pair_term)
+template <bool POT, int KIND>
+__device__ inline void pair_bg(float r2, const PairK<float> &k, const float4 *wtab, float &br, float &g)
+{
+    const float rinv = rsqrt_t(r2);
+    if constexpr (KIND == kWolf) {
+        const float r = r2 * rinv;
+        float E, D;
+        wolf_lookup(wtab, r, k.wscale, E, D);
+        br = D * rinv * rinv * rinv;
+        if (POT) g = E * rinv - k.wshift;
+    } else if constexpr (KIND == kPolyHigh) {
+        br = rinv * rinv * rinv - (k.d0 + r2 * (k.d1 + r2 * k.d2));
+        if (POT) g = rinv - (k.c0 + r2 * (k.c1 + r2 * (k.c2 + r2 * k.c3)));
+    } else {
+        br = rinv * rinv * rinv - (k.d0 + k.d1 * r2);
+        if (POT) g = rinv - (k.c0 + r2 * (k.c1 + r2 * k.c2));
+    }
+}
+
+constexpr int kN3Cl = 8;   // atoms per cluster
+
+// One exchange of the lane sums: of the values v[0, 2N) a lane keeps the
+// lower half (bit OFF of its lane clear) or the upper half, adds its partner's
+// copy of that half and leaves it in v[0, N).
+template <int N, int OFF> __device__ inline void halve(float (&v)[32], int lane)
+{
+    const bool up = (lane & OFF) != 0;
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
+        const float send = up ? v[t] : v[t + N];
+        const float keep = up ? v[t + N] : v[t];
+        v[t] = keep + __shfl_xor(send, OFF, kWave);
+    }
+}
+
+struct N3Lds {
+    float4 ring[kClWgWaves][kClRing];   // kept candidates
+    int ridx[kClWgWaves][kClRing];      // their sorted indices
+    int map[kClWgWaves][kClMap];        // stream position -> sorted atom
+    int pre[kClWgWaves][kWave + 1];
+    int first[kClWgWaves][kWave];
+};
+
+template <bool POT, int KIND>
+__global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_n3(DevPlan p, const float4 *__restrict__ sx,
+                                                                const int *__restrict__ cstart,
+                                                                const int *__restrict__ cluster,
+                                                                float4 *__restrict__ out,
+                                                                unsigned long long *__restrict__ acc,
+                                                                int64_t stride, PairK<float> k)
+{
+    constexpr int CA = kN3Cl;
+    __shared__ N3Lds L;
+    __shared__ WolfLds<float, KIND> wl;
+    if (eval_failed(p)) return;
+    wl.load(k);   // before any wave of the workgroup can leave
+    const float4 *wtab = wl.ptr();
+    const int lane = threadIdx.x % kWave;
+    const int wv = uni((int)(threadIdx.x / kWave));
+    const int64_t c = xcd_remap(blockIdx.x, gridDim.x) * kClWgWaves + wv;
+    if (c >= p.ngroups * (kWave / CA)) return;
+    const int m0 = uni(cluster[c * CA]);
+    if (m0 < 0) return;   // a cluster of absent atoms (the last group of a system)
+    const int64_t g = c / (kWave / CA);
+    const int base = (int)(c % (kWave / CA)) * CA;   // the cluster's first place in the group's k-d order
+    const int s = find_segment(p.group_prefix, p.nsys, g);
+    const SysPlan &P = p.sys[s];
+    const int gend = (int)min(P.atom0 + (g - p.group_prefix[s] + 1) * kWave, P.atom0 + P.natoms);
+    const int me = lane % CA;
+    const int mi = cluster[c * CA + me];
+    const float4 ai = sx[mi >= 0 ? mi : m0];
+    const float bx_lo = uni(seg_min(ai.x, CA)), bx_hi = uni(seg_max(ai.x, CA));
+    const float by_lo = uni(seg_min(ai.y, CA)), by_hi = uni(seg_max(ai.y, CA));
+    const float bz_lo = uni(seg_min(ai.z, CA)), bz_hi = uni(seg_max(ai.z, CA));
+    // the cluster's atoms, wave-uniform (an absent one carries no charge)
+    const float qme = mi >= 0 ? ai.w : 0.f;
+    float xi[CA], yi[CA], zi[CA], qi[CA];
+#pragma unroll
+    for (int ia = 0; ia < CA; ++ia) {
+        xi[ia] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ai.x), ia));
+        yi[ia] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ai.y), ia));
+        zi[ia] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ai.z), ia));
+        qi[ia] = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(qme), ia));
+    }
+    float fx[CA], fy[CA], fz[CA], u[CA];
+#pragma unroll
+    for (int ia = 0; ia < CA; ++ia) fx[ia] = fy[ia] = fz[ia] = u[ia] = 0.f;
+
+    // one candidate per lane (jj < 0: none); INTRA: only places after the pair's atom i
+    auto eval64 = [&](const float4 aj, const int jj, const bool intra) {
+        float gx = 0.f, gy = 0.f, gz = 0.f, gu = 0.f;
+#pragma unroll
+        for (int ia = 0; ia < CA; ++ia) {
+            const float dx = xi[ia] - aj.x, dy = yi[ia] - aj.y, dz = zi[ia] - aj.z;
+            const float r2 = dx * dx + dy * dy + dz * dz;
+            bool in = r2 < k.a2 && r2 > 0.f;
+            if (intra) in = in && lane > base + ia;
+            if (in) {
+                float br, pg;
+                pair_bg<POT, KIND>(r2, k, wtab, br, pg);
+                const float ti = aj.w * br, tj = qi[ia] * br;
+                fx[ia] += ti * dx;
+                fy[ia] += ti * dy;
+                fz[ia] += ti * dz;
+                gx -= tj * dx;
+                gy -= tj * dy;
+                gz -= tj * dz;
+                if (POT) {
+                    u[ia] += aj.w * pg;
+                    gu += qi[ia] * pg;
+                }
+            }
+        }
+        if (jj >= 0) {
+            acc_add(acc + jj, to_fixed(gx));
+            acc_add(acc + stride + jj, to_fixed(gy));
+            acc_add(acc + 2 * stride + jj, to_fixed(gz));
+            if (POT) acc_add(acc + 3 * stride + jj, to_fixed(gu));
+        }
+    };
+
+    // pairs inside the group: the places from the cluster's own on
+    {
+        const int jj0 = cluster[g * kWave + lane];
+        const int jj = lane > base ? jj0 : -1;
+        float4 aj;
+        if (jj >= 0) aj = sx[jj];
+        else aj.x = aj.y = aj.z = 1e18f, aj.w = 0.f;
+        eval64(aj, jj, true);
+    }
+
+    // candidates sorted after the group
+    const float lox = float(P.lo[0]), loy = float(P.lo[1]), loz = float(P.lo[2]);
+    const float inv_h = float(P.inv_h), h = float(1.0 / P.inv_h);
+    const int ncx = P.nc[0], ncy = P.nc[1], ncz = P.nc[2];
+    const float reach = k.reach, reach2 = k.reach * k.reach;
+    const int cy0 = clampi((int)floorf((by_lo - loy - reach) * inv_h), 0, ncy - 1);
+    const int cy1 = clampi((int)floorf((by_hi - loy + reach) * inv_h), 0, ncy - 1);
+    const int cz0 = clampi((int)floorf((bz_lo - loz - reach) * inv_h), 0, ncz - 1);
+    const int cz1 = clampi((int)floorf((bz_hi - loz + reach) * inv_h), 0, ncz - 1);
+    const int bx0 = clampi((int)floorf((bx_lo - lox - reach) * inv_h), 0, ncx - 1) / kBrick;
+    const int bx1 = clampi((int)floorf((bx_hi - lox + reach) * inv_h), 0, ncx - 1) / kBrick;
+    const int nbx = bx1 - bx0 + 1, ny = cy1 - cy0 + 1;
+    const int nitems = nbx * ny * (cz1 - cz0 + 1);
+    int *map = L.map[wv], *pre = L.pre[wv], *fst = L.first[wv];
+    float4 *ring = L.ring[wv];
+    int *ridx = L.ridx[wv];
+    int head = 0, tail = 0;   // ring positions (uniform; taken modulo the capacity)
+    auto eval_block = [&]() {
+        const int e = (head + lane) & (kClRing - 1);
+        eval64(ring[e], ridx[e], false);
+        head += kWave;
+    };
+    for (int ib = 0; ib < nitems; ib += kWave) {
+        const int q = ib + lane;   // this lane's item
+        int len = 0, jb = 0;
+        if (q < nitems) {
+            const int bx = bx0 + q % nbx, row = q / nbx;
+            const int cy = cy0 + row % ny, cz = cz0 + row / ny;
+            const float z0 = loz + float(cz) * h, y0 = loy + float(cy) * h;
+            const float dz = fmaxf(0.f, fmaxf(z0 - bz_hi, bz_lo - (z0 + h)));
+            const float dy = fmaxf(0.f, fmaxf(y0 - by_hi, by_lo - (y0 + h)));
+            const float rem = reach2 - dy * dy - dz * dz;
+            if (rem > 0.f) {
+                const float wdt = chord_sqrt(rem);
+                const int cx0 = clampi((int)floorf((bx_lo - lox - wdt) * inv_h), 0, ncx - 1);
+                const int cx1 = clampi((int)floorf((bx_hi - lox + wdt) * inv_h), 0, ncx - 1);
+                const int ca = max(cx0, bx * kBrick), cb = min(cx1, bx * kBrick + kBrick - 1);
+                if (ca <= cb) {
+                    const int r0 = (int)P.cell0 + cell_rank32(P, ca, cy, cz);
+                    const int e = cstart[r0 + (cb - ca) + 1];
+                    jb = max(cstart[r0], gend);
+                    len = max(0, e - jb);
+                }
+            }
+        }
+        int incl = len;
+        for (int off = 1; off < kWave; off <<= 1) {
+            const int v = __shfl_up(incl, off, kWave);
+            if (lane >= off) incl += v;
+        }
+        const int start = incl - len;
+        pre[lane] = start;
+        fst[lane] = jb;
+        const int total = uni(__shfl(incl, kWave - 1, kWave));
+        if (lane == 0) pre[kWave] = total;
+        for (int t = 0; t < len && start + t < kClMap; ++t) map[start + t] = jb + t;
+        __builtin_amdgcn_wave_barrier();
+        auto atom_at = [&](int pos) -> int {
+            if (pos < kClMap) return map[pos];
+            int lo_ = 0, hi_ = kWave;   // pre[lo_] <= pos < pre[hi_]
+            while (hi_ - lo_ > 1) {
+                const int mid = (lo_ + hi_) >> 1;
+                if (pre[mid] <= pos) lo_ = mid; else hi_ = mid;
+            }
+            return fst[lo_] + (pos - pre[lo_]);
+        };
+        int pj = -1;
+        float4 pa;
+        if (lane < total) {
+            pj = atom_at(lane);
+            pa = sx[pj];
+        }
+        for (int c0 = 0; c0 < total; c0 += kWave) {
+            const bool have = c0 + lane < total;
+            const float4 ca = pa;
+            const int cj = pj;
+            const int nxt = c0 + kWave + lane;   // the next chunk, in flight while this one is used
+            if (nxt < total) {
+                pj = atom_at(nxt);
+                pa = sx[pj];
+            }
+            const float ddx = fmaxf(0.f, fmaxf(bx_lo - ca.x, ca.x - bx_hi));
+            const float ddy = fmaxf(0.f, fmaxf(by_lo - ca.y, ca.y - by_hi));
+            const float ddz = fmaxf(0.f, fmaxf(bz_lo - ca.z, ca.z - bz_hi));
+            const bool keep = have && ddx * ddx + ddy * ddy + ddz * ddz < reach2;
+            const uint64_t m = __ballot(keep);
+            if (keep) {
+                const int e = (tail + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(m >> 32),
+                                                                     __builtin_amdgcn_mbcnt_lo((unsigned)m, 0u))) &
+                              (kClRing - 1);
+                ring[e] = ca;
+                ridx[e] = cj;
+            }
+            tail += __popcll(m);
+            __builtin_amdgcn_wave_barrier();
+            if (tail - head >= kWave) eval_block();
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+    if (tail > head) {   // the last partial block, padded with far-away atoms of no index
+        if (lane >= tail - head) {
+            const int e = (head + lane) & (kClRing - 1);
+            float4 far;
+            far.x = far.y = far.z = 1e18f;
+            far.w = 0.f;
+            ring[e] = far;
+            ridx[e] = -1;
+        }
+        __builtin_amdgcn_wave_barrier();
+        eval_block();
+    }
+
+    // the cluster's sums across the 64 lanes: each exchange halves the values a
+    // lane holds (the upper lane of a pair keeps the upper half), then the two
+    // lanes left for each value add; lane 2v holds value v = 4 ia + component
+    float v[4 * CA];
+#pragma unroll
+    for (int ia = 0; ia < CA; ++ia) {
+        v[4 * ia] = fx[ia];
+        v[4 * ia + 1] = fy[ia];
+        v[4 * ia + 2] = fz[ia];
+        v[4 * ia + 3] = u[ia];
+    }
+    halve<16, 32>(v, lane);
+    halve<8, 16>(v, lane);
+    halve<4, 8>(v, lane);
+    halve<2, 4>(v, lane);
+    halve<1, 2>(v, lane);
+    v[0] += __shfl_xor(v[0], 1, kWave);
+    const int vi = lane >> 1, ia = vi >> 2, comp = vi & 3;
+    const int iat = __shfl(mi, ia, kWave);
+    if ((lane & 1) == 0 && iat >= 0) reinterpret_cast<float *>(out)[4 * (int64_t)iat + comp] = v[0];
+}
+
+// Adds each atom's fixed-point accumulators to the stored sums and clears them.
+__global__ __launch_bounds__(256) void k_n3_combine(int64_t n, float4 *__restrict__ out,
+                                                    unsigned long long *__restrict__ acc, int64_t stride, int pot)
+{
+    const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float4 o = out[i];
+    const long long ax = (long long)acc[i], ay = (long long)acc[stride + i], az = (long long)acc[2 * stride + i];
+    o.x = (float)((double)o.x + (double)ax * kFixUnit);
+    o.y = (float)((double)o.y + (double)ay * kFixUnit);
+    o.z = (float)((double)o.z + (double)az * kFixUnit);
+    acc[i] = 0;
+    acc[stride + i] = 0;
+    acc[2 * stride + i] = 0;
+    if (pot) {
+        const long long au = (long long)acc[3 * stride + i];
+        o.w = (float)((double)o.w + (double)au * kFixUnit);
+        acc[3 * stride + i] = 0;
+    }
+    out[i] = o;
+}
+
 // k_pair_grp: the 8-atom clusters of one 64-atom group (GW = 8 waves in one
 // workgroup) or of half a group (GW = 4) share one candidate stream: the
 // cell-row pieces that reach the box around all of them. The waves build the
@@ -1178,6 +1499,25 @@ static void pair_launch_cl(hipStream_t s, const DevPlan &p, const Work<T> &w, co
                            w.cluster, w.shrt, k, none);
 }
 
+// Newton's third law form: clusters, the pair kernel, then the accumulators
+// added to the sums (single precision only; the caller checks)
+template <int KIND>
+static void pair_launch_n3(hipStream_t s, const DevPlan &p, const Work<float> &w, const PairK<float> &k, bool pot)
+{
+    hipLaunchKernelGGL((k_clusters<float, kN3Cl>), dim3((unsigned)p.ngroups), dim3(kWave), 0, s, p, w.sxyzq,
+                       w.cluster);
+    const int64_t nclusters = p.ngroups * (kWave / kN3Cl);
+    const dim3 grid((unsigned)((nclusters + kClWgWaves - 1) / kClWgWaves)), block(kClWgWaves * kWave);
+    if (pot)
+        hipLaunchKernelGGL((k_pair_n3<true, KIND>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.cluster, w.shrt,
+                           w.nacc, w.nacc_stride, k);
+    else
+        hipLaunchKernelGGL((k_pair_n3<false, KIND>), grid, block, 0, s, p, w.sxyzq, w.cell_start, w.cluster, w.shrt,
+                           w.nacc, w.nacc_stride, k);
+    hipLaunchKernelGGL(k_n3_combine, dim3((unsigned)((p.natoms + 255) / 256)), dim3(256), 0, s, p.natoms, w.shrt,
+                       w.nacc, w.nacc_stride, pot ? 1 : 0);
+}
+
 template <typename T, int KIND>
 static void pair_launch_sub(hipStream_t s, const DevPlan &p, const Work<T> &w, const PairK<T> &k, bool pot)
 {
@@ -1337,6 +1677,16 @@ hipError_t Launch<T>::pair(hipStream_t s, const DevPlan &p, const DevPlan *pp, c
     case 9: pair_launch_m<T, 9>(s, q, w, k, pot, kind); break;
     case 8: pair_launch_m<T, 8>(s, q, w, k, pot, kind); break;
     case 16: pair_launch_m<T, 16>(s, q, w, k, pot, kind); break;
+    case 10:
+        if constexpr (sizeof(T) == 4) {
+            if (!w.nacc || q.natoms > w.nacc_stride) return hipErrorInvalidValue;
+            if (kind == kWolf) pair_launch_n3<kWolf>(s, q, w, k, pot);
+            else if (kind == kPolyHigh) pair_launch_n3<kPolyHigh>(s, q, w, k, pot);
+            else pair_launch_n3<kPoly>(s, q, w, k, pot);
+            break;
+        } else {
+            return hipErrorInvalidValue;
+        }
     default: return hipErrorInvalidValue;
     }
     if (pp)

@@ -79,10 +79,10 @@ def test_autotune_and_tunings_agree():
     x = torch.tensor(w.xyzq(np.float32), device="cuda")
     ref = [t.clone() for t in ctx.energy_forces(x)]
     chosen = ctx.autotune(x, reps=3)
-    assert chosen["pair_waves"] in (1, 2, 3, 4, 5, 6, 7, 8, 9, 16) and chosen["stencil_threads"] in (256, 1024)
+    assert chosen["pair_waves"] in (1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 16) and chosen["stencil_threads"] in (256, 1024)
     assert chosen["pair_cell"] in (1, 2, 3)
     assert ctx.tuning() == chosen
-    for pw in (1, 2, 3, 4, 5, 6, 7, 8, 9, 16):
+    for pw in (1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 16):
         for st in (256, 1024):
             ctx.set_tuning(pw, st, pair_cell=1 if pw != 2 else 2)
             e, f, p = ctx.energy_forces(x)
@@ -93,7 +93,7 @@ def test_autotune_and_tunings_agree():
             assert rel < 1e-5, (pw, st, rel)
             assert e.item() == pytest.approx(ref[0].item(), rel=1e-6)
     with pytest.raises(msmx.MsmError):
-        ctx.set_tuning(10, 256)
+        ctx.set_tuning(11, 256)
     with pytest.raises(msmx.MsmError):
         ctx.set_tuning(pair_cell=0)
 
@@ -112,7 +112,10 @@ def test_concurrent_stages_change_no_bit(precision):
     conc = msmx.MsmContext(w.a, w.h, w.lo, w.hi, precision=precision, max_atoms=w.n)
     seq.set_tuning(concurrent=0)
     assert conc.tuning()["concurrent"] == 1
-    for pw, pc in ((1, 1), (2, 1), (3, 1), (4, 1), (5, 1), (6, 1), (7, 1), (8, 1), (9, 1), (2, 2), (5, 2)):
+    forms = ((1, 1), (2, 1), (3, 1), (4, 1), (5, 1), (6, 1), (7, 1), (8, 1), (9, 1), (2, 2), (5, 2))
+    if precision == "fp32":
+        forms += ((10, 1), (10, 2))
+    for pw, pc in forms:
         seq.set_tuning(pair_waves=pw, pair_cell=pc)
         conc.set_tuning(pair_waves=pw, pair_cell=pc)
         ref = seq.energy_forces(x)

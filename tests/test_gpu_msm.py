@@ -301,14 +301,15 @@ def test_water_small_matches_oracle(precision):
     assert e == pytest.approx(eo, rel=tol)
 
 
-@pytest.mark.parametrize("pw", [2, 3, 5, 6, 7, 9])
+@pytest.mark.parametrize("pw", [2, 3, 5, 6, 7, 9, 10])
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_cluster_pair_forms_match_oracle(pw, precision):
     """Each cluster form of the short-range sum (8-atom clusters, one or two
-    per wave, or sharing a workgroup's stream; 16- and 32-atom clusters)
-    against the oracle, on a water box
-    whose last 64-atom group is partly empty (999 atoms) and on uniform
-    charges with the coarse cells of h = 0.5."""
+    per wave, or sharing a workgroup's stream, or each pair once with
+    Newton's third law; 16- and 32-atom clusters) against the oracle, on a
+    water box whose last 64-atom group is partly empty (999 atoms) and on
+    uniform charges with the coarse cells of h = 0.5. The Newton form is
+    single precision only: a double precision context refuses it."""
     m = _lib()
     dt = np.float32 if precision == "fp32" else np.float64
     tol = 1e-11 if precision == "fp64" else 1e-4
@@ -317,6 +318,10 @@ def test_cluster_pair_forms_match_oracle(pw, precision):
         if precision == "fp32":
             w = w.as_dtype(np.float32)
         ctx = m.MsmContext(w.a, w.h, w.lo, w.hi, levels=w.levels, precision=precision, max_atoms=w.n)
+        if pw == 10 and precision == "fp64":
+            with pytest.raises(m.MsmError):
+                ctx.set_tuning(pair_waves=pw)
+            continue
         ctx.set_tuning(pair_waves=pw)
         e, f, p = ctx.energy_forces(torch.tensor(w.xyzq(dt), device="cuda"))
         torch.cuda.synchronize()
@@ -441,8 +446,11 @@ def test_single_atom_and_pair():
         np.testing.assert_allclose(f, fo, rtol=1e-11, atol=1e-11 * max(1.0, np.abs(fo).max()))
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_batched_equals_separate_bitwise(precision):
+@pytest.mark.parametrize("precision,pw", [("fp64", 2), ("fp32", 2), ("fp32", 10)])
+def test_batched_equals_separate_bitwise(precision, pw):
+    """A batch of systems (one of them empty) gives each system the bits it
+    gets alone, with the default pair form and with the Newton form, whose
+    fixed-point sums do not depend on the order of their terms."""
     m = _lib()
     dt = np.float32 if precision == "fp32" else np.float64
     systems = [water_box(300, (10, 10, 10), (3.0, 3.0, 3.0), seed=31),
@@ -453,6 +461,7 @@ def test_batched_equals_separate_bitwise(precision):
     lo0 = np.zeros(3)
     ntot = sum(s.n for s in systems)
     ctx = m.MsmContext(1.2, 0.25, lo0, lo0 + big, precision=precision, max_atoms=ntot, max_systems=4)
+    ctx.set_tuning(pair_waves=pw)
     offs = np.cumsum([0] + [s.n for s in systems])
     doms = np.array([np.concatenate([s.lo, s.hi]) for s in systems])
     xyzq = torch.tensor(np.concatenate([s.xyzq(dt) for s in systems]), device="cuda")
@@ -464,6 +473,7 @@ def test_batched_equals_separate_bitwise(precision):
             assert e[s].item() == 0.0
             continue
         one = m.MsmContext(1.2, 0.25, sysw.lo, sysw.hi, precision=precision, max_atoms=sysw.n)
+        one.set_tuning(pair_waves=pw)
         x1 = torch.tensor(sysw.xyzq(dt), device="cuda")
         e1, f1, p1 = one.energy_forces(x1)
         torch.cuda.synchronize()
@@ -502,8 +512,13 @@ def test_forces_only_evaluation_gives_the_same_forces(precision):
     w = water_box(2000, (19, 19, 19), (5.8, 5.8, 5.8), seed=43)
     dt = np.float32 if precision == "fp32" else np.float64
     x = torch.tensor(w.xyzq(dt), device="cuda")
-    for model in (False, True):
+    cases = [(False, None), (True, None)]
+    if precision == "fp32":
+        cases += [(False, 10), (True, 10)]   # and each pair once (Newton's third law)
+    for model, pw in cases:
         ctx = m.MsmContext(w.a, w.h, w.lo, w.hi, precision=precision, max_atoms=w.n)
+        if pw is not None:
+            ctx.set_tuning(pair_waves=pw)
         if model:
             from workloads import water_model_arrays
             mass, molid, lj, tri = water_model_arrays(w.n)
@@ -513,7 +528,7 @@ def test_forces_only_evaluation_gives_the_same_forces(precision):
         _, f_only, _ = ctx.energy_forces(x, want=("forces",))
         torch.cuda.synchronize()
         assert ctx.status() == 0
-        assert torch.equal(f_full, f_only), model
+        assert torch.equal(f_full, f_only), (model, pw)
 
 
 def test_status_reports_domain_and_nonfinite():
@@ -542,6 +557,30 @@ def test_water_99999_fp32_matches_oracle():
     assert rel_rms(f, fo) < 1e-4
     assert rel_rms(p, po) < 1e-4
     assert e == pytest.approx(eo, rel=1e-5)
+
+
+def test_newton_form_water_99999_matches_oracle():
+    """The pair form that evaluates each pair once (Newton's third law, its
+    candidate's share in fixed point) on the benchmark workload: every atom
+    against the oracle, within single precision rounding of the form that
+    evaluates each pair from both sides, and the same bits when repeated."""
+    m = _lib()
+    w = named("water_99999").as_dtype(np.float32)
+    x = torch.tensor(w.xyzq(np.float32), device="cuda")
+    ctx = m.MsmContext(w.a, w.h, w.lo, w.hi, levels=w.levels, precision="fp32", max_atoms=w.n)
+    e2, f2, p2 = [t.clone() for t in ctx.energy_forces(x)]
+    ctx.set_tuning(pair_waves=10)
+    e, f, p = [t.clone() for t in ctx.energy_forces(x)]
+    er, fr, pr = ctx.energy_forces(x)
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    assert torch.equal(e, er) and torch.equal(f, fr) and torch.equal(p, pr)
+    assert rel_rms(f.double().cpu().numpy(), f2.double().cpu().numpy()) < 1e-6
+    assert rel_rms(p.double().cpu().numpy(), p2.double().cpu().numpy()) < 1e-6
+    eo, fo, po = run_oracle(w)
+    assert rel_rms(f.double().cpu().numpy(), fo) < 1e-4
+    assert rel_rms(p.double().cpu().numpy(), po) < 1e-4
+    assert float(e[0].item()) == pytest.approx(eo, rel=1e-5)
 
 
 def test_water_99999_fp64_matches_oracle():
