@@ -93,13 +93,22 @@ def unique_pairs(xyz, a, chunk=1 << 20):
 
 
 def cpu_model():
+    """The host CPU as /proc/cpuinfo names it: model name, family, model and
+    stepping numbers, and the logical CPUs it lists."""
+    fields, ncpu = {}, 0
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            key = line.split(":", 1)[0].strip()
+            if key == "processor":
+                ncpu += 1
+            elif key in ("model name", "cpu family", "model", "stepping") and key not in fields:
+                fields[key] = line.split(":", 1)[1].strip()
     except OSError:
-        pass
-    return None
+        return None
+    if "model name" not in fields:
+        return None
+    return (f"{fields['model name']} (family {fields.get('cpu family', '?')}, model {fields.get('model', '?')}, "
+            f"stepping {fields.get('stepping', '?')}; {ncpu} logical CPUs listed)")
 
 
 def timed_steps(torch, ctx, xyzq, out, steps, warmup):
@@ -194,6 +203,15 @@ def bench_batched(torch, msmx, states, q, lo, hi, steps, warmup, autotune=True):
     torch.cuda.synchronize()
     ctx.check()
     ms = e0.elapsed_time(e1) / k
+    # the stages in turn (HIP events on the library's stream, eager launches)
+    ctx.stage_timing(reset=True)
+    ctx.enable_stage_timing(True)
+    for _ in range(3):
+        run()
+    ctx.enable_stage_timing(False)
+    torch.cuda.synchronize()
+    sms, sn = ctx.stage_timing(reset=True)
+    stage_ms = {key: round(v / max(sn, 1), 5) for key, v in sms.items()}
     # slice 0 of the batch against a single-system context with the same
     # launch configuration: identical bits; and its time per atom
     one = msmx.MsmContext(1.2, 0.25, lo, hi, precision="fp32", max_atoms=n)
@@ -214,7 +232,8 @@ def bench_batched(torch, msmx, states, q, lo, hi, steps, warmup, autotune=True):
                "single_system_ms": ms1,
                "speedup_vs_single_system": (slices * n / (ms * 1e-3)) / (n / (ms1 * 1e-3)),
                "largest_position_change_between_states_nm": spread, "launch": "graph replay",
-               "slice0_bitwise_equal_to_single": same}
+               "slice0_bitwise_equal_to_single": same, "stage_ms": stage_ms,
+               "evaluation_over_short_stage": ms / stage_ms["short"] if stage_ms.get("short") else None}
 
     # uneven batch
     sizes = uneven_batch_sizes()
