@@ -22,6 +22,29 @@ __device__ inline double uni(double v)
     return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
 }
 
+// Lane l receives v from lane l ^ m, m a power of two below 64: the values
+// of __shfl_xor(v, m, 64), moved by a DPP quad permutation (m = 1, 2) or a
+// row rotation (m = 8) inside the VALU, by a swizzle within each half wave
+// (m = 4, 16), and by a permute for m = 32.
+__device__ inline int xor_lane(int v, int m)
+{
+    switch (m) {
+    case 1: return __builtin_amdgcn_update_dpp(v, v, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+    case 2: return __builtin_amdgcn_update_dpp(v, v, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+    case 8: return __builtin_amdgcn_update_dpp(v, v, 0x128, 0xF, 0xF, false);  // row_ror:8
+    case 4: return __builtin_amdgcn_ds_swizzle(v, 0x1F | (4 << 10));
+    case 16: return __builtin_amdgcn_ds_swizzle(v, 0x1F | (16 << 10));
+    default: return __shfl_xor(v, m, 64);
+    }
+}
+__device__ inline float xor_lane(float v, int m) { return __int_as_float(xor_lane(__float_as_int(v), m)); }
+__device__ inline double xor_lane(double v, int m)
+{
+    const int64_t b = __double_as_longlong(v);
+    const int lo = xor_lane((int)(b & 0xffffffff), m), hi = xor_lane((int)(b >> 32), m);
+    return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
+}
+
 template <typename T> __device__ inline T wave_min(T v)
 {
     for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));

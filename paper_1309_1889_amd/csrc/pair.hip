@@ -549,19 +549,21 @@ constexpr int kClPrefetch = MSMX_CL_PREFETCH;  // stream chunks in flight ahead 
 template <int CA, typename T> __device__ inline T sum_slots(T v)
 {
 #pragma unroll
-    for (int off = CA; off < kWave; off <<= 1) v += __shfl_xor(v, off, kWave);
+    for (int off = CA; off < kWave; off <<= 1) v += xor_lane(v, off);
     return v;
 }
 
 // min / max over aligned segments of n lanes
 template <typename T> __device__ inline T seg_min(T v, int n)
 {
-    for (int off = 1; off < n; off <<= 1) v = fmin(v, __shfl_xor(v, off, kWave));
+#pragma unroll
+    for (int off = 1; off < n; off <<= 1) v = fmin(v, xor_lane(v, off));
     return v;
 }
 template <typename T> __device__ inline T seg_max(T v, int n)
 {
-    for (int off = 1; off < n; off <<= 1) v = fmax(v, __shfl_xor(v, off, kWave));
+#pragma unroll
+    for (int off = 1; off < n; off <<= 1) v = fmax(v, xor_lane(v, off));
     return v;
 }
 
@@ -581,10 +583,12 @@ __device__ inline int kd_cut(const vec4_t<T> *grp, int pos, int natoms, int n, i
     const int axis = (ex >= ey && ex >= ez) ? 0 : (ey >= ez ? 1 : 2);
     T key = real ? (axis == 0 ? a.x : (axis == 1 ? a.y : a.z)) : inf;
     int p = pos;
+#pragma unroll
     for (int kk = 2; kk <= n; kk <<= 1)
+#pragma unroll
         for (int j = kk >> 1; j > 0; j >>= 1) {
-            const T ok = __shfl_xor(key, j, kWave);
-            const int op = __shfl_xor(p, j, kWave);
+            const T ok = xor_lane(key, j);
+            const int op = xor_lane(p, j);
             const bool up = kk == n || (lane & kk) == 0;   // every segment ascending
             const bool lower = (lane & j) == 0;
             const bool less = ok < key || (ok == key && op < p);   // the partner comes first
@@ -611,6 +615,7 @@ __global__ __launch_bounds__(kWave) void k_clusters(DevPlan p, const vec4_t<T> *
     grp[lane] = sx[first + min(lane, natoms - 1)];
     __syncthreads();
     int pos = lane;
+#pragma unroll
     for (int n = kWave; n > CA; n >>= 1) pos = kd_cut<T>(grp, pos, natoms, n, lane);
     cluster[g * kWave + lane] = pos < natoms ? (int)(first + pos) : -1;
 }
