@@ -12,6 +12,7 @@
 #include <algorithm>
 #include <cstring>
 
+#include "device_util.h"
 #include "launch.h"
 
 namespace msmx {
@@ -178,11 +179,7 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int *__restrict__ c
     int before = 0;
     for (int b = threadIdx.x; b < (int)blockIdx.x; b += kScanThreads) before += bsum[b];
     before = wave_sum_i(before);
-    int incl = acc;   // inclusive scan over the wave's threads
-    for (int off = 1; off < kWave; off <<= 1) {
-        const int t = __shfl_up(incl, off, kWave);
-        if (lane >= off) incl += t;
-    }
+    const int incl = wave_incl_scan(acc);   // inclusive scan over the wave's threads
     if (lane == kWave - 1) wsum[wv] = incl;
     if (lane == 0) wbefore[wv] = before;
     __syncthreads();
@@ -319,8 +316,6 @@ __global__ __launch_bounds__(256) void k_cell_sort(int64_t ncells, const int *__
         if (pos_of) pos_of[v] = b + rank;
     }
 }
-
-inline unsigned nblocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
 

@@ -45,6 +45,21 @@ __device__ inline double xor_lane(double v, int m)
     return __longlong_as_double(((int64_t)hi << 32) | (uint32_t)lo);
 }
 
+// Inclusive prefix sum over the 64 lanes of a wave, by DPP: shifts within
+// each row of 16 lanes, then each row's total carried into the rows after it
+// by the row broadcasts (lanes 15 and 31). Integer sums, so the values of the
+// shuffle-based scan.
+__device__ inline int wave_incl_scan(int x)
+{
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, true);    // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, true);    // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, true);    // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, true);    // row_shr:8
+    x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);   // row_bcast:15 into rows 1 and 3
+    x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);   // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
 template <typename T> __device__ inline T wave_min(T v)
 {
     for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, 64));

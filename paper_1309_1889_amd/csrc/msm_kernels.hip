@@ -152,11 +152,7 @@ __global__ __launch_bounds__(ant_threads<PD>()) void k_anterp(DevPlan p, const v
         fst[j] = f;
         sum += n;
     }
-    int incl = sum;
-    for (int off = 1; off < kWave; off <<= 1) {
-        const int v = __shfl_up(incl, off, kWave);
-        if (lane >= off) incl += v;
-    }
+    const int incl = wave_incl_scan(sum);
     if (lane == kWave - 1) wsum[wv] = incl;
     __syncthreads();
     int run = incl - sum;

@@ -269,14 +269,10 @@ __global__ __launch_bounds__(kPairWaves * kWave) void k_pair(DevPlan p, const ve
             }
         }
         // exclusive prefix of the item lengths across the wave
-        int incl = len;
-        for (int off = 1; off < kWave; off <<= 1) {
-            const int v = __shfl_up(incl, off, kWave);
-            if (lane >= off) incl += v;
-        }
+        const int incl = wave_incl_scan(len);
         L.pre[lane] = incl - len;
         L.first[lane] = jb;
-        const int total = uni(__shfl(incl, kWave - 1, kWave));
+        const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
         if (lane == 0) L.pre[kWave] = total;
         // the wave's own LDS writes are seen by its later reads (one wave, in
         // order); the barrier only keeps the compiler from moving them
@@ -437,14 +433,10 @@ __global__ __launch_bounds__(kSubLanes * kWave) void k_pair_sub(DevPlan p, const
                 }
             }
         }
-        int incl = len;
-        for (int off = 1; off < kWave; off <<= 1) {
-            const int v = __shfl_up(incl, off, kWave);
-            if (lane >= off) incl += v;
-        }
+        const int incl = wave_incl_scan(len);
         L.pre[lane] = incl - len;
         L.first[lane] = jb;
-        const int total = uni(__shfl(incl, kWave - 1, kWave));
+        const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
         if (lane == 0) L.pre[kWave] = total;
         __builtin_amdgcn_wave_barrier();
         auto locate = [&](int pos) -> int {
@@ -746,15 +738,11 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_cl(DevPlan p, const
                 }
             }
         }
-        int incl = len;
-        for (int off = 1; off < kWave; off <<= 1) {
-            const int v = __shfl_up(incl, off, kWave);
-            if (lane >= off) incl += v;
-        }
+        const int incl = wave_incl_scan(len);
         const int start = incl - len;
         pre[lane] = start;
         fst[lane] = jb;
-        const int total = uni(__shfl(incl, kWave - 1, kWave));
+        const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
         if (lane == 0) pre[kWave] = total;
         // table of the first kClMap stream positions
         // (a per-lane loop: a wave-wide bound would hold cross-lane
@@ -1056,15 +1044,11 @@ __global__ __launch_bounds__(kClWgWaves * kWave) void k_pair_n3(DevPlan p, const
                 }
             }
         }
-        int incl = len;
-        for (int off = 1; off < kWave; off <<= 1) {
-            const int v = __shfl_up(incl, off, kWave);
-            if (lane >= off) incl += v;
-        }
+        const int incl = wave_incl_scan(len);
         const int start = incl - len;
         pre[lane] = start;
         fst[lane] = jb;
-        const int total = uni(__shfl(incl, kWave - 1, kWave));
+        const int total = __builtin_amdgcn_readlane(incl, kWave - 1);
         if (lane == 0) pre[kWave] = total;
         for (int t = 0; t < len && start + t < kClMap; ++t) map[start + t] = jb + t;
         __builtin_amdgcn_wave_barrier();
@@ -1305,11 +1289,7 @@ __global__ __launch_bounds__(GW * kWave) void k_pair_grp(DevPlan p, const vec4_t
                 }
             }
         }
-        int incl = len;
-        for (int off = 1; off < kWave; off <<= 1) {
-            const int v = __shfl_up(incl, off, kWave);
-            if (lane >= off) incl += v;
-        }
+        const int incl = wave_incl_scan(len);
         if (lane == kWave - 1) L.wtot[wv] = incl;
         __syncthreads();   // the previous batch's tables are no longer read
         int base = 0, total = 0;
