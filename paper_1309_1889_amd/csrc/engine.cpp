@@ -177,11 +177,11 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     sys.resize(nsys);
     const int W = nsys + 1;
     std::vector<int64_t> &atom_p = ps.atom_p, &group_p = ps.group_p, &cell_p = ps.cell_p, &iblk_p = ps.iblk_p,
-                         &top_p = ps.top_p, &ant_p = ps.ant_p, &node_p = ps.node_p, &rxy_p = ps.rxy_p,
+                         &top_p = ps.top_p, &ant_p = ps.ant_p, &ant_p8 = ps.ant_p8, &node_p = ps.node_p, &rxy_p = ps.rxy_p,
                          &pxy_p = ps.pxy_p, &tile_p = ps.tile_p;
-    for (auto *v : {&atom_p, &group_p, &cell_p, &iblk_p, &top_p, &ant_p, &rxy_p, &pxy_p}) v->assign(W, 0);
+    for (auto *v : {&atom_p, &group_p, &cell_p, &iblk_p, &top_p, &ant_p, &ant_p8, &rxy_p, &pxy_p}) v->assign(W, 0);
     node_p.assign((size_t)kMaxLevels * W, 0);
-    int64_t cells = 0, q = 0, u = 0, groups = 0, iblk = 0, top = 0, ant = 0;
+    int64_t cells = 0, q = 0, u = 0, groups = 0, iblk = 0, top = 0, ant = 0, ant8 = 0;
     int64_t tsz = 0, wsz = 0, rxy = 0, pxy = 0;
     bool composite = true;
     int64_t nodes[kMaxLevels] = {0};
@@ -220,7 +220,11 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
         iblk_p[s] = iblk;
         top_p[s] = top;
         ant_p[s] = ant;
-        if (g.nlev > 0) ant += anterp_tiles(g.gdim[0][0], g.gdim[0][1], g.gdim[0][2]);
+        ant_p8[s] = ant8;
+        if (g.nlev > 0) {
+            ant += anterp_tiles(g.gdim[0][0], g.gdim[0][1], g.gdim[0][2], 4);
+            ant8 += anterp_tiles(g.gdim[0][0], g.gdim[0][1], g.gdim[0][2], 8);
+        }
         for (int k = 0; k < kMaxLevels; k++) node_p[(size_t)k * W + s] = nodes[k];
         for (int k = 0; k < g.nlev; k++) {
             P.qoff[k] = q;
@@ -295,6 +299,15 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     iblk_p[nsys] = iblk;
     top_p[nsys] = top;
     ant_p[nsys] = ant;
+    ant_p8[nsys] = ant8;
+    // deeper anterpolation tiles (single precision, cubic basis) where there
+    // are enough of them to fill the chip: fewer staged halo atoms per node
+    int ant_depth = 4;
+    if (c->prm.precision == MSM_FP32 && basis_degree(c->prm) == 3 && ant8 >= kAntDeep) {
+        ant_depth = 8;
+        ant = ant8;
+        ant_p.swap(ant_p8);
+    }
     for (int k = 0; k < kMaxLevels; k++) node_p[(size_t)k * W + nsys] = nodes[k];
     // stencil tiles of every level below each system's top, segment k*nsys + s
     const int esz = c->prm.precision == MSM_FP32 ? 4 : 8;
@@ -469,6 +482,7 @@ int msmx::build_plan(msm_ctx *c, int nsys, const int64_t *offsets, const double 
     dp.niblk = iblk;
     dp.ntop = top;
     dp.nant = ant;
+    dp.ant_depth = ant_depth;
     for (int k = 0; k < kMaxLevels; k++) dp.nnodes[k] = nodes[k];
     dp.maxlev = maxlev;
     dp.composite = composite ? 1 : 0;

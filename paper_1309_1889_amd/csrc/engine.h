@@ -23,7 +23,7 @@ struct Geometry {
 // is reused from one build to the next.
 struct PlanScratch {
     std::vector<SysPlan> sys;
-    std::vector<int64_t> atom_p, group_p, cell_p, iblk_p, top_p, ant_p, node_p, rxy_p, pxy_p, tile_p;
+    std::vector<int64_t> atom_p, group_p, cell_p, iblk_p, top_p, ant_p, ant_p8, node_p, rxy_p, pxy_p, tile_p;
     std::vector<SysPlan> lj_sys;      // the Lennard-Jones subset's system plans
     std::vector<int64_t> lj_group_p;  // and its 64-atom groups
     std::vector<SysPlan> pc_sys;      // the system plans of the pair search's own cells

@@ -23,6 +23,7 @@ struct DevPlan {
     const int64_t *tile_prefix;  // ntile_seg+1: stencil tiles of segment k*nsys + s (levels below the top)
     const int64_t *top_prefix;   // nsys+1: top-level workgroups per system
     const int64_t *ant_prefix;   // nsys+1: anterpolation tiles per system
+    int ant_depth;               // node layers along z per anterpolation tile: 4 or 8
     int ntile_seg;               // (maxlev - 1) * nsys
     int top_d2;                  // largest squared index distance on any top grid
     int64_t natoms, ngroups, ncells, niblk, ntop, ntiles, nant;
@@ -148,7 +149,11 @@ constexpr int kWolfPieces = 128;
 // 8 * kWolfPieces floats.
 void wolf_table(double a, double alpha, float *out);
 
-int anterp_tiles(int dx, int dy, int dz);
+// anterpolation tiles of a level-0 grid, 8 x 8 x depth nodes each (depth 4,
+// or 8 for the single precision cubic basis on grids of at least kAntDeep
+// tiles of that depth over the batch)
+int anterp_tiles(int dx, int dy, int dz, int depth);
+constexpr int64_t kAntDeep = 1024;
 // composite transfers: LDS capacity (elements) of a level-0 xy plane and of
 // the one-axis partial sums
 constexpr int kPlaneCap = 6144;

@@ -36,13 +36,16 @@ namespace {
 //  2. k_anterp_nodes: one thread per level-0 node adds the partials of the
 //     (2S)^3 cells whose support covers it, in a fixed order.
 // ---------------------------------------------------------------------------
-constexpr int kAntX = 8, kAntY = 8, kAntZ = 4;
+// tiles of kAntX x kAntY x AZ nodes: AZ = 4, or 8 for the single precision
+// cubic on grids with enough tiles to fill the chip (kAntDeep)
+constexpr int kAntX = 8, kAntY = 8;
 constexpr int kAntLoads = 4;   // atoms of a cell a staging thread loads at once
 // atoms a tile stages in LDS: the cubic's 11x11x7-cell region holds about
-// 1,300 water atoms, the quintic's 13x13x9 about 2,400 (FP64: 3,072 x 32 bytes)
-template <typename T, int PD> constexpr int ant_atoms()
+// 1,300 water atoms (11x11x11 for AZ = 8: about 2,000), the quintic's 13x13x9
+// about 2,400 (FP64: 3,072 x 32 bytes)
+template <typename T, int PD, int AZ> constexpr int ant_atoms()
 {
-    return Basis<PD>::S == 2 ? 2048 : (sizeof(T) == 4 ? 4096 : 3072);
+    return Basis<PD>::S == 2 ? (AZ == 8 ? 4096 : 2048) : (sizeof(T) == 4 ? 4096 : 3072);
 }
 
 // A fixed piece of the cubic along y or z in the tiled gather: the atom's
@@ -67,8 +70,8 @@ template <typename T> __device__ inline T cubic_run(T t)
     return x <= T(1) ? inner : outer;
 }
 
-template <int S> struct AntTile {
-    static constexpr int CX = kAntX + 2 * S - 1, CY = kAntY + 2 * S - 1, CZ = kAntZ + 2 * S - 1;   // cells reached
+template <int S, int AZ> struct AntTile {
+    static constexpr int CX = kAntX + 2 * S - 1, CY = kAntY + 2 * S - 1, CZ = AZ + 2 * S - 1;   // cells reached
     static constexpr int Rows = CY * CZ;
     static constexpr int Cells = Rows * CX;
 };
@@ -97,23 +100,25 @@ __device__ inline T gather_global(const SysPlan &P, const vec4_t<T> *__restrict_
     return acc;
 }
 
-// threads per node in the tiled form: one per cell layer along z (two for the
-// quintic, whose six layers would need 1536 threads)
-template <int PD> constexpr int ant_layers_per_thread() { return Basis<PD>::S == 2 ? 1 : 2; }
-template <int PD> constexpr int ant_threads()
+// cell layers along z per thread in the tiled form: one (a thread per layer),
+// or two where one per layer would need more than 1024 threads (the quintic's
+// six layers, the cubic's four with AZ = 8)
+template <int PD, int AZ> constexpr int ant_layers_per_thread() { return Basis<PD>::S == 2 && AZ == 4 ? 1 : 2; }
+template <int PD, int AZ> constexpr int ant_threads()
 {
-    return kAntX * kAntY * kAntZ * (2 * Basis<PD>::S / ant_layers_per_thread<PD>());
+    return kAntX * kAntY * AZ * (2 * Basis<PD>::S / ant_layers_per_thread<PD, AZ>());
 }
 
-template <typename T, int PD>
-__global__ __launch_bounds__(ant_threads<PD>()) void k_anterp(DevPlan p, const vec4_t<T> *__restrict__ sx,
-                                                              const int *__restrict__ cstart, T *__restrict__ qgrid)
+template <typename T, int PD, int AZ>
+__global__ __launch_bounds__((ant_threads<PD, AZ>())) void k_anterp(DevPlan p, const vec4_t<T> *__restrict__ sx,
+                                                                  const int *__restrict__ cstart, T *__restrict__ qgrid)
 {
     using B = Basis<PD>;
     constexpr int S = B::S;
-    using A = AntTile<S>;
-    constexpr int NT = ant_threads<PD>(), NODES = kAntX * kAntY * kAntZ, CPT = ant_layers_per_thread<PD>();
-    __shared__ vec4_t<T> atoms[ant_atoms<T, PD>()];
+    using A = AntTile<S, AZ>;
+    constexpr int NT = ant_threads<PD, AZ>(), NODES = kAntX * kAntY * AZ, CPT = ant_layers_per_thread<PD, AZ>();
+    static_assert(NODES * 2 * S * sizeof(T) <= ant_atoms<T, PD, AZ>() * sizeof(vec4_t<T>), "layer sums fit the atom buffer");
+    __shared__ vec4_t<T> atoms[ant_atoms<T, PD, AZ>()];
     __shared__ int start[A::Cells + 1];   // staged position of each region cell's first atom
     __shared__ int wsum[NT / kWave];
     if (eval_failed(p)) return;
@@ -126,7 +131,7 @@ __global__ __launch_bounds__(ant_threads<PD>()) void k_anterp(DevPlan p, const v
     // tile origin in absolute node indices
     const int x0 = (int)(t % ntx) * kAntX + P.gorg[0][0];
     const int y0 = (int)((t / ntx) % nty) * kAntY + P.gorg[0][1];
-    const int z0 = (int)(t / ((int64_t)ntx * nty)) * kAntZ + P.gorg[0][2];
+    const int z0 = (int)(t / ((int64_t)ntx * nty)) * AZ + P.gorg[0][2];
     const int tid = threadIdx.x, lane = tid % kWave, wv = tid / kWave;
 
     // cells of the reachable region (cells x0-S .. x0+kAntX+S-2, ...), 0 atoms
@@ -167,7 +172,7 @@ __global__ __launch_bounds__(ant_threads<PD>()) void k_anterp(DevPlan p, const v
     if (tid == NT - 1) start[A::Cells] = run;
     __syncthreads();
     const int total = start[A::Cells];
-    const bool staged = total <= ant_atoms<T, PD>();
+    const bool staged = total <= ant_atoms<T, PD, AZ>();
     if (staged) {
         // each thread stages the atoms of the cells it counted, the first
         // kAntLoads of a cell loaded together
@@ -200,7 +205,9 @@ __global__ __launch_bounds__(ant_threads<PD>()) void k_anterp(DevPlan p, const v
     const int ix = x0 + lx, iy = y0 + ly, iz = z0 + lz;
     const int rx = ix - P.gorg[0][0], ry = iy - P.gorg[0][1], rz = iz - P.gorg[0][2];
     const bool inside = rx < dx && ry < dy && rz < dz;
-    T acc = 0;
+    T acc[CPT];   // one sum per cell layer, so the order of the additions does not depend on CPT
+#pragma unroll
+    for (int cc = 0; cc < CPT; ++cc) acc[cc] = 0;
     if (inside && staged) {
         const T fx = T(ix), fy = T(iy), fz = T(iz);
         // the node's cells ix-S .. ix+S-1 are region columns lx .. lx+2S-1;
@@ -219,24 +226,25 @@ __global__ __launch_bounds__(ant_threads<PD>()) void k_anterp(DevPlan p, const v
                 for (int j = jb; j < je; ++j) {
                     const vec4_t<T> a = atoms[j];
                     if constexpr (PD == 3)
-                        acc += cubic_run(a.x - fx) * cubic_row_piece(a.y - fy, py) * cubic_row_piece(a.z - fz, pz) * a.w;
+                        acc[cc] += cubic_run(a.x - fx) * cubic_row_piece(a.y - fy, py) * cubic_row_piece(a.z - fz, pz) * a.w;
                     else
-                        acc += phi_inside<PD>(a.x - fx) * phi_piece<PD>(a.y - fy, py) * phi_piece<PD>(a.z - fz, pz) *
-                               a.w;
+                        acc[cc] += phi_inside<PD>(a.x - fx) * phi_piece<PD>(a.y - fy, py) * phi_piece<PD>(a.z - fz, pz) *
+                                   a.w;
                 }
             }
         }
     } else if (inside && q == 0) {
-        acc = gather_global<T, PD>(P, sx, cstart, ix, iy, iz);
+        acc[0] = gather_global<T, PD>(P, sx, cstart, ix, iy, iz);
     }
-    // the layers' partial sums, added in a fixed order
+    // the layers' partial sums, added in layer order
     __syncthreads();
     T *part = reinterpret_cast<T *>(atoms);
-    part[tid] = acc;
+#pragma unroll
+    for (int cc = 0; cc < CPT; ++cc) part[(q * CPT + cc) * NODES + node] = acc[cc];
     __syncthreads();
     if (q != 0 || !inside) return;
     T v = part[node];
-    for (int r = 1; r < NT / NODES; ++r) v += part[r * NODES + node];
+    for (int c = 1; c < 2 * S; ++c) v += part[c * NODES + node];
     const int PX = padded_x(dx), PY = padded_x(dy);
     qgrid[P.qoff[0] + ((int64_t)(rz + kGridPad) * PY + (ry + kGridPad)) * PX + (rx + kGridPad)] = v;
 }
@@ -1072,9 +1080,9 @@ __global__ void k_stage_grid(const SysPlan *sys, int s, int k, const T *__restri
 
 }  // namespace
 
-int anterp_tiles(int dx, int dy, int dz)
+int anterp_tiles(int dx, int dy, int dz, int depth)
 {
-    return ((dx + kAntX - 1) / kAntX) * ((dy + kAntY - 1) / kAntY) * ((dz + kAntZ - 1) / kAntZ);
+    return ((dx + kAntX - 1) / kAntX) * ((dy + kAntY - 1) / kAntY) * ((dz + depth - 1) / depth);
 }
 
 // The tiles stage at least twice as many atoms as their region has cells
@@ -1086,9 +1094,18 @@ bool anterp_two_pass(const DevPlan &p) { return p.natoms > 2 * p.ncells; }
 template <typename T, int PD> static hipError_t anterp_p(hipStream_t s, const DevPlan &p, const Work<T> &w)
 {
     if (!anterp_two_pass(p)) {
-        hipLaunchKernelGGL((k_anterp<T, PD>), dim3((unsigned)p.nant), dim3(ant_threads<PD>()), 0, s, p, w.sxyzq,
-                           w.cell_start,
-                           w.qgrid);
+        if constexpr (sizeof(T) == 4 && PD == 3) {
+            if (p.ant_depth == 8) {
+                hipLaunchKernelGGL((k_anterp<T, PD, 8>), dim3((unsigned)p.nant), dim3(ant_threads<PD, 8>()), 0, s, p,
+                                   w.sxyzq, w.cell_start, w.qgrid);
+                return hipGetLastError();
+            }
+        }
+        if (p.ant_depth == 4)
+            hipLaunchKernelGGL((k_anterp<T, PD, 4>), dim3((unsigned)p.nant), dim3(ant_threads<PD, 4>()), 0, s, p,
+                               w.sxyzq, w.cell_start, w.qgrid);
+        else
+            return hipErrorInvalidValue;   // a plan whose tiles no kernel form has
         return hipGetLastError();
     }
     constexpr int cpb = ant_cells_per_block<PD>();

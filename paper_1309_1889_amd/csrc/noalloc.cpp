@@ -49,7 +49,7 @@ int setup_slot(DeviceSlot &d)
     if (!c) return MSM_ERR_HIP;
     PlanScratch &ps = c->ps;
     ps.sys.reserve(1);
-    for (auto *v : {&ps.atom_p, &ps.group_p, &ps.cell_p, &ps.iblk_p, &ps.top_p, &ps.ant_p, &ps.rxy_p, &ps.pxy_p})
+    for (auto *v : {&ps.atom_p, &ps.group_p, &ps.cell_p, &ps.iblk_p, &ps.top_p, &ps.ant_p, &ps.ant_p8, &ps.rxy_p, &ps.pxy_p})
         v->reserve(2);
     ps.node_p.reserve((size_t)kMaxLevels * 2);
     ps.tile_p.reserve(kMaxLevels + 1);

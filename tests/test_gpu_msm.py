@@ -485,6 +485,40 @@ def test_batched_equals_separate_bitwise(precision, pw):
             assert e1.item() == pytest.approx(eo, rel=1e-12)
 
 
+def test_deep_anterpolation_tiles_same_bits():
+    """Single precision batches whose level-0 grids hold enough tiles use
+    anterpolation tiles 8 node layers deep instead of 4 (fewer staged halo
+    atoms per node); each node's sum is kept per cell layer and added in layer
+    order, so both depths give the same bits. Eight water boxes in 12 nm
+    domains (343 deep tiles each, 2,744 together) go through one batched call
+    (deep tiles) and one call each (a single grid of 343 deep tiles keeps the
+    shallow ones); the outputs must agree bitwise, and one system matches the
+    oracle."""
+    m = _lib()
+    parts = [water_box(200 + 40 * i, (10, 10, 10), (3.0, 3.0, 3.0), seed=70 + i, margin=4.5).as_dtype(np.float32)
+             for i in range(8)]
+    big = np.max([q.hi - q.lo for q in parts], axis=0)
+    offs = np.cumsum([0] + [q.n for q in parts])
+    doms = np.array([np.concatenate([q.lo, q.hi]) for q in parts])
+    ctx = m.MsmContext(1.2, 0.25, np.zeros(3), big, precision="fp32", max_atoms=int(offs[-1]), max_systems=8)
+    x = torch.tensor(np.concatenate([q.xyzq(np.float32) for q in parts]), device="cuda")
+    eb, fb, pb = [t.clone() for t in ctx.energy_forces(x, offs, doms)]
+    torch.cuda.synchronize()
+    assert ctx.status() == 0
+    for s_, q in enumerate(parts):
+        one = m.MsmContext(1.2, 0.25, q.lo, q.hi, precision="fp32", max_atoms=q.n)
+        e1, f1, p1 = one.energy_forces(torch.tensor(q.xyzq(np.float32), device="cuda"))
+        torch.cuda.synchronize()
+        assert torch.equal(eb[s_:s_ + 1], e1), s_
+        assert torch.equal(fb[offs[s_]:offs[s_ + 1]], f1), s_
+        assert torch.equal(pb[offs[s_]:offs[s_ + 1]], p1), s_
+        if s_ == 0:
+            eo, fo, po = run_oracle(q)
+            assert rel_rms(f1.double().cpu().numpy(), fo) < 1e-4
+            assert rel_rms(p1.double().cpu().numpy(), po) < 1e-4
+            assert float(e1.item()) == pytest.approx(eo, rel=1e-5)
+
+
 def test_repeat_is_bitwise_deterministic():
     m = _lib()
     w = water_box(2000, (19, 19, 19), (5.8, 5.8, 5.8), seed=41)
