@@ -927,8 +927,14 @@ constexpr int kInterpThreads = 256;
 // pair kernel left in shrt, and, with a molecular model bound, the
 // Lennard-Jones force and energy of the atoms that carry it (ljof: input
 // atom -> index into ljout, or -1; null without a model).
+// least waves per SIMD the compiler fits the interpolation kernel to: the
+// single precision cubic form in 128 registers (4 waves instead of 3, its 16
+// row loads still issued together); the others as they come (fewer registers
+// would spill)
+template <typename T, int PD> constexpr int interp_waves() { return sizeof(T) == 4 && PD == 3 ? 4 : 1; }
+
 template <typename T, bool GRID, bool SHORT, int PD>
-__global__ __launch_bounds__(kInterpThreads) void k_interp(DevPlan p, const vec4_t<T> *__restrict__ sx,
+__global__ __launch_bounds__(kInterpThreads) __attribute__((amdgpu_waves_per_eu(interp_waves<T, PD>()))) void k_interp(DevPlan p, const vec4_t<T> *__restrict__ sx,
                                                            const vec4_t<T> *__restrict__ shrt,
                                                            const int *__restrict__ order,
                                                            const T *__restrict__ ugrid, T *__restrict__ forces,
